@@ -1,0 +1,179 @@
+/* ETALE dynamic graph index on one AMD Instinct MI355X (gfx950): C ABI.
+ *
+ * The index is a degree-bounded directed proximity graph over a fixed id
+ * space (paper Section 3.2, Definition 1). Each id owns one 64-bit reference
+ * word <deletion flag, degree, slab id>; its neighbor list lives in an
+ * immutable slab of R (neighbor id, distance) entries drawn from a pool, and
+ * every list change is a copy-on-write publication that swaps the reference
+ * with one 64-bit compare-and-swap (Section 3.3, Algorithm 1).
+ *
+ * Calls and what they follow in the paper:
+ *   etale_insert_batch   Insert, Algorithm 2 (Section 3.4.1), over a batch
+ *   etale_delete_batch   Delete with connectivity repair, Algorithm 3 (3.4.2)
+ *   etale_reclaim        Reclaim, Algorithm 4 (3.4.3)
+ *   etale_search_batch   the query side of the problem statement (3.1): a
+ *                        greedy beam search whose output admits only nodes
+ *                        whose reference has deletion flag 0 (3.4.2)
+ *
+ * Round semantics. Every mutating call is one round: its phases run in a
+ * fixed order and each phase reads the state the previous one left. The
+ * searches of an insert call all see the graph as it was when the call
+ * started, so members of one batch do not see each other; writes aimed at the
+ * same node within a phase are applied in ascending source-id order and
+ * published once. Retired slabs return to the free pool only at the end of a
+ * call (the epoch separation of Lemma 1). All orders are lexicographic on
+ * (distance, id).
+ *
+ * Memory. The library owns every piece of index state (vectors, references,
+ * slab pool, scratch) in device memory allocated by etale_create and freed by
+ * etale_destroy. Arguments named *_dev are device pointers owned by the
+ * caller, valid for the duration of the call's stream work; *_host arguments
+ * are host pointers. Calls are ordered on the stream given in the config
+ * (NULL = the default stream) and may return before the device work ends,
+ * except create, destroy, get_stats, export and reclaim, which synchronize.
+ * Calls that must check the slab pool (insert, delete, reclaim) synchronize
+ * the stream once before mutating anything.
+ *
+ * Errors. No call aborts or throws. Argument errors return ETALE_EINVAL and
+ * change nothing. A call that cannot be covered by the free slab pool returns
+ * ETALE_EPOOL, or by the id space ETALE_ECAPACITY, before any change; the
+ * caller may reclaim and retry. A HIP failure returns ETALE_EDEVICE and
+ * poisons the handle: later calls return ETALE_ESTATE. etale_last_error
+ * describes the last failure.
+ *
+ * Vectors: ETALE_METRIC_L2_U8 stores dim uint8 per vector (dim a power of two,
+ * 16..1024) and uses the exact squared L2 distance in 32-bit integers.
+ */
+#ifndef ETALE_H
+#define ETALE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct etale_index* etale_t;
+typedef int32_t etale_status;
+
+enum {
+  ETALE_OK = 0,
+  ETALE_EINVAL = -1,
+  ETALE_ENOMEM = -2,
+  ETALE_EPOOL = -3,
+  ETALE_ECAPACITY = -4,
+  ETALE_EDEVICE = -5,
+  ETALE_ESTATE = -6
+};
+
+enum { ETALE_METRIC_L2_U8 = 0 };
+
+/* per-id outcome of etale_delete_batch */
+enum { ETALE_DEL_OK = 0, ETALE_DEL_NOT_LIVE = 1, ETALE_DEL_OUT_OF_RANGE = 2, ETALE_DEL_DUPLICATE = 3 };
+
+typedef struct {
+  uint32_t dim;              /* vector length */
+  uint32_t R;                /* slab capacity = maximum out-degree, 1..64 */
+  uint32_t L_build;          /* candidate-list length of insert searches */
+  uint32_t alpha_num;        /* RobustPrune slack alpha = alpha_num / alpha_den, */
+  uint32_t alpha_den;        /*   applied to squared distances as alpha^2 */
+  uint32_t visit_mult;       /* a search expands at most visit_mult * L nodes */
+  uint32_t prune_cap;        /* RobustPrune keeps at most this many nearest candidates */
+  uint32_t n_entry;          /* entry set = the n_entry smallest live ids */
+  uint32_t refine;           /* 1: run the same-batch refine pass of inserts */
+  uint32_t tombstone_only;   /* 1: delete only flags; no repair, no reclaim */
+  uint32_t publish_attempts; /* CAS attempt budget of one publication */
+  uint32_t max_batch;        /* largest insert / delete batch of one call */
+  uint32_t vt_slots;         /* visited-table slots per search (power of two) */
+  uint32_t waves_per_block;  /* search wavefronts per workgroup */
+  int32_t metric;            /* ETALE_METRIC_* */
+  int32_t reserved;
+  uint64_t id_capacity;      /* size of the id space */
+  uint64_t slab_capacity;    /* slabs in the pool */
+  void* hip_stream;          /* hipStream_t, or NULL */
+} etale_config;
+
+typedef struct {
+  uint64_t next_id;          /* ids handed out so far */
+  uint64_t live;             /* ids with deletion flag 0 */
+  uint64_t tombstones;       /* flagged ids that still hold a slab */
+  uint64_t slab_capacity;
+  uint64_t free_slabs;
+  uint64_t resident_slabs;   /* slabs named by some reference */
+  uint64_t n_entries;
+  uint64_t pub_forward, pub_repair, pub_reverse, pub_refine, pub_compact;
+  uint64_t freed;            /* tombstone slabs retired by reclaim */
+  uint64_t dirty_last;       /* live nodes republished by the last compaction */
+  uint64_t dead_edges_last;  /* edges into tombstones found by the last compaction */
+  uint64_t search_expansions, search_distances; /* totals over search calls */
+  uint64_t cas_failures, publish_dropped;
+  uint64_t device_bytes;     /* device memory held by the index */
+  uint64_t error_bits;
+} etale_stats;
+
+/* Create an index on the current HIP device. On success *out receives the
+ * handle. Errors: EINVAL (bad config), ENOMEM, EDEVICE. */
+etale_status etale_create(const etale_config* cfg, etale_t* out);
+
+/* Release every device allocation of the index. NULL is accepted. */
+etale_status etale_destroy(etale_t ix);
+
+/* Make later calls run on stream (hipStream_t, NULL = default). */
+etale_status etale_set_stream(etale_t ix, void* stream);
+
+/* Insert n vectors (vecs_dev: n x dim elements, row-major). Ids are handed
+ * out in input order, starting at the current next id, and written to
+ * ids_out_dev (n uint32, may be NULL). Worst-case slab demand n * (R + 2)
+ * must be free, else ETALE_EPOOL; next id + n must fit the id space, else
+ * ETALE_ECAPACITY. n must not exceed max_batch. */
+etale_status etale_insert_batch(etale_t ix, const void* vecs_dev, uint64_t n, uint32_t* ids_out_dev);
+
+/* Delete the ids in ids_dev (n uint32). status_out_dev (n bytes, may be
+ * NULL) receives ETALE_DEL_* per position: repeats of an id in one call are
+ * DUPLICATE (the first occurrence wins), ids never handed out are
+ * OUT_OF_RANGE, already deleted ids are NOT_LIVE. Worst-case slab demand
+ * (OK count) * R must be free, else ETALE_EPOOL with nothing changed. */
+etale_status etale_delete_batch(etale_t ix, const uint32_t* ids_dev, uint64_t n, uint8_t* status_out_dev);
+
+/* Search nq query rows (q_dev: nq x dim) with candidate-list length L,
+ * 1 <= k <= L <= 256. Writes the k best live results per query in (distance,
+ * id) order: ids_out_dev (nq x k uint32) and dists_out_dev (nq x k int32),
+ * padded with id 0xFFFFFFFF and distance INT32_MAX. counts_out_dev (nq x 2
+ * uint32, may be NULL) receives the expansions and distance evaluations. */
+etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
+                                uint32_t* ids_out_dev, void* dists_out_dev, uint32_t* counts_out_dev);
+
+/* Compaction, then release of every tombstone's slab (Algorithm 4). The
+ * number of dirty nodes must be covered by free slabs, else ETALE_EPOOL with
+ * nothing changed. A no-op in tombstone-only mode. */
+etale_status etale_reclaim(etale_t ix);
+
+/* Exact k nearest live nodes of each query by (distance, id), 1 <= k <= 16:
+ * the plain definition used to measure recall. */
+etale_status etale_bruteforce(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t* ids_out_dev,
+                              void* dists_out_dev);
+
+/* Counters and pool state (synchronizes). */
+etale_status etale_get_stats(etale_t ix, etale_stats* out_host);
+
+/* Dump ids [0, n_ids) (n_ids <= next id): R neighbor ids and R distances per
+ * id (unused entries 0xFFFFFFFF / 0), degree, deletion flag and slab
+ * presence, into host buffers (synchronizes). Any pointer may be NULL. */
+etale_status etale_export(etale_t ix, uint64_t n_ids, uint32_t* nbr_host, void* dist_host, uint8_t* deg_host,
+                          uint8_t* del_host, uint8_t* has_slab_host);
+
+/* Entry-set members in ascending id order (up to cap ids); returns the
+ * count through *n_out (synchronizes). */
+etale_status etale_get_entries(etale_t ix, uint32_t* ids_host, uint64_t cap, uint64_t* n_out);
+
+/* Wait for the index's stream. */
+etale_status etale_sync(etale_t ix);
+
+/* Text of the last failure on this handle (owned by the library). */
+const char* etale_last_error(etale_t ix);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ETALE_H */

@@ -1,0 +1,462 @@
+// C-ABI of the ETALE index: argument checks, device memory, and the order of
+// the phase launches of each call. Every numeric step runs in the kernels of
+// etale_kernels.hip; this file only moves sizes, pointers and counters.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include <string>
+#include <vector>
+
+#include "etale.h"
+#include "etale_dev.h"
+#include "etale_launch.h"
+
+using namespace etale;
+
+struct etale_index {
+  etale_config cfg;
+  hipStream_t stream = nullptr;
+  Index dev{};
+  uint8_t* x = nullptr;
+  unsigned long long* refs = nullptr;
+  uint32_t* slabs = nullptr;
+  uint32_t* free_stack = nullptr;
+  uint32_t* retired_stack = nullptr;
+  unsigned long long* ctr = nullptr;
+  uint32_t* entries = nullptr;
+  // call scratch
+  uint64_t* vis_keys = nullptr;
+  uint32_t* vis_cnt = nullptr;
+  uint32_t* F = nullptr;
+  uint64_t* pairs_a = nullptr;
+  uint64_t* pairs_b = nullptr;
+  uint32_t* dlist = nullptr;
+  uint32_t* dirty = nullptr;
+  uint64_t* bitmap = nullptr;
+  void* sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  uint64_t next_id = 0;
+  uint32_t vcap_build = 0;
+  uint64_t bytes = 0;
+  bool poisoned = false;
+  std::string err;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+etale_status fail(etale_index* ix, etale_status code, const std::string& what) {
+  if (ix) {
+    ix->err = what;
+    if (code == ETALE_EDEVICE) ix->poisoned = true;
+  }
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(ix, ETALE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool pow2(uint64_t v) { return v && !(v & (v - 1)); }
+
+uint32_t pow2_ge64(uint32_t n) {
+  uint32_t p = 64;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+template <class T>
+hipError_t dalloc(etale_index* ix, T** p, size_t bytes) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+  if (e != hipSuccess) return e;
+  ix->allocs.push_back(q);
+  ix->bytes += bytes;
+  *p = reinterpret_cast<T*>(q);
+  return hipSuccess;
+}
+
+etale_status read_counters(etale_index* ix, unsigned long long* h) {
+  HIP_TRY(hipMemcpyAsync(h, ix->ctr, C_NCOUNTERS * sizeof(unsigned long long), hipMemcpyDeviceToHost, ix->stream));
+  HIP_TRY(hipStreamSynchronize(ix->stream));
+  if (h[C_ERROR]) {
+    ix->poisoned = true;
+    return fail(ix, ETALE_ESTATE, "device invariant violated, error bits " + std::to_string(h[C_ERROR]));
+  }
+  return ETALE_OK;
+}
+
+etale_status set_counter(etale_index* ix, Counter c, unsigned long long v) {
+  HIP_TRY(hipMemcpyAsync(ix->ctr + c, &v, sizeof(v), hipMemcpyHostToDevice, ix->stream));
+  HIP_TRY(hipStreamSynchronize(ix->stream));
+  return ETALE_OK;
+}
+
+etale_status sort_keys(etale_index* ix, uint64_t* in, uint64_t* out, size_t n) {
+  if (n == 0) return ETALE_OK;
+  size_t bytes = 0;
+  HIP_TRY(rocprim::radix_sort_keys(nullptr, bytes, in, out, n, 0, 64, ix->stream));
+  if (bytes > ix->sort_tmp_bytes) return fail(ix, ETALE_EDEVICE, "sort scratch too small");
+  bytes = ix->sort_tmp_bytes;
+  HIP_TRY(rocprim::radix_sort_keys(ix->sort_tmp, bytes, in, out, n, 0, 64, ix->stream));
+  return ETALE_OK;
+}
+
+MaintArgs maint_args(const etale_index* ix, uint32_t nmax) {
+  MaintArgs a{};
+  a.vcap = ix->vcap_build;
+  a.nmax = nmax;
+  a.nsort = pow2_ge64(nmax);
+  a.prune_cap = std::min(ix->cfg.prune_cap, nmax);
+  a.vstride = ix->cfg.dim + 16;
+  a.lds_per_wave = maint_lds_per_wave(a, ix->cfg.R);
+  return a;
+}
+
+uint32_t maint_waves_per_block(const MaintArgs& a) {
+  uint32_t w = 65536u / a.lds_per_wave;
+  return w >= 4 ? 4 : (w >= 2 ? 2 : 1);
+}
+
+#define CHECK_HANDLE()                                       \
+  do {                                                       \
+    if (!ix) return ETALE_EINVAL;                            \
+    if (ix->poisoned) return fail(ix, ETALE_ESTATE, "index poisoned by an earlier device error: " + ix->err); \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+etale_status etale_create(const etale_config* cfg, etale_t* out) {
+  if (!cfg || !out) return ETALE_EINVAL;
+  const etale_config& c = *cfg;
+  if (c.metric != ETALE_METRIC_L2_U8) return ETALE_EINVAL;
+  if (!pow2(c.dim) || c.dim < 16 || c.dim > 1024) return ETALE_EINVAL;
+  if (c.R < 1 || c.R > 64 || c.L_build < 1 || c.L_build > 256) return ETALE_EINVAL;
+  if (c.alpha_num == 0 || c.alpha_den == 0 || c.alpha_num > 1000 || c.alpha_den > 1000) return ETALE_EINVAL;
+  if (c.visit_mult < 1 || c.visit_mult * c.L_build > 4096) return ETALE_EINVAL;
+  if (c.prune_cap < c.R || c.prune_cap > 2048) return ETALE_EINVAL;
+  if (c.n_entry < 1 || c.n_entry > (1u << 20)) return ETALE_EINVAL;
+  if (c.publish_attempts < 1 || c.max_batch < 1) return ETALE_EINVAL;
+  if (!pow2(c.vt_slots) || c.vt_slots < 64 || c.vt_slots > 16384) return ETALE_EINVAL;
+  if (c.waves_per_block != 1 && c.waves_per_block != 2 && c.waves_per_block != 4) return ETALE_EINVAL;
+  if (c.id_capacity < 1 || c.id_capacity >= 0xFFFFFFFFull || c.slab_capacity < 1 || c.slab_capacity >= 0xFFFFFFFFull)
+    return ETALE_EINVAL;
+  if ((uint64_t)c.max_batch > c.id_capacity) return ETALE_EINVAL;
+  {
+    // every kernel's LDS must fit one 64 KiB workgroup allocation
+    etale_index probe;
+    probe.cfg = c;
+    probe.vcap_build = c.visit_mult * c.L_build;
+    const uint32_t worst_nmax[] = {probe.vcap_build, c.R + 1, 2 * c.R, c.R + c.R * c.R};
+    for (uint32_t nm : worst_nmax)
+      if (maint_args(&probe, nm).lds_per_wave > 65536u) return ETALE_EINVAL;
+    if (search_lds_per_wave(std::max(256u, probe.vcap_build), c.vt_slots) > 65536u) return ETALE_EINVAL;
+  }
+
+  etale_index* ix = new etale_index();
+  ix->cfg = c;
+  ix->stream = reinterpret_cast<hipStream_t>(c.hip_stream);
+  ix->vcap_build = c.visit_mult * c.L_build;
+  const uint64_t C = c.id_capacity, P = c.slab_capacity, B = c.max_batch, R = c.R;
+  auto cleanup = [&](etale_status st, const std::string& why) {
+    for (void* p : ix->allocs) (void)hipFree(p);
+    delete ix;
+    (void)why;
+    return st;
+  };
+#define ALLOC(ptr, bytes)                                          \
+  if (dalloc(ix, &(ptr), (bytes)) != hipSuccess) return cleanup(ETALE_ENOMEM, "hipMalloc");
+  ALLOC(ix->x, C * c.dim);
+  ALLOC(ix->refs, C * 8);
+  ALLOC(ix->slabs, P * 2 * R * 4);
+  ALLOC(ix->free_stack, P * 4);
+  ALLOC(ix->retired_stack, P * 4);
+  ALLOC(ix->ctr, C_NCOUNTERS * 8);
+  ALLOC(ix->entries, (uint64_t)c.n_entry * 4);
+  ALLOC(ix->vis_keys, B * ix->vcap_build * 8);
+  ALLOC(ix->vis_cnt, B * 4);
+  ALLOC(ix->F, B * R * 4);
+  ALLOC(ix->pairs_a, B * R * 8);
+  ALLOC(ix->pairs_b, B * R * 8);
+  ALLOC(ix->dlist, B * 4);
+  ALLOC(ix->dirty, C * 4);
+  ALLOC(ix->bitmap, ((C + 63) / 64) * 8);
+  {
+    size_t bytes = 0;
+    if (rocprim::radix_sort_keys(nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr, (size_t)(B * R), 0, 64,
+                                 ix->stream) != hipSuccess)
+      return cleanup(ETALE_EDEVICE, "sort size");
+    ix->sort_tmp_bytes = bytes;
+    ALLOC(ix->sort_tmp, bytes);
+  }
+#undef ALLOC
+  Index& d = ix->dev;
+  d.dim = c.dim;
+  d.R = c.R;
+  d.a2 = c.alpha_num * c.alpha_num;
+  d.b2 = c.alpha_den * c.alpha_den;
+  d.publish_attempts = c.publish_attempts;
+  d.prune_cap = c.prune_cap;
+  d.cap = C;
+  d.P = P;
+  d.x = ix->x;
+  d.refs = ix->refs;
+  d.slabs = ix->slabs;
+  d.free_stack = ix->free_stack;
+  d.retired_stack = ix->retired_stack;
+  d.ctr = ix->ctr;
+  d.entries = ix->entries;
+  if (launch_init(d, ix->stream) != hipSuccess || hipStreamSynchronize(ix->stream) != hipSuccess)
+    return cleanup(ETALE_EDEVICE, "init");
+  *out = ix;
+  return ETALE_OK;
+}
+
+etale_status etale_destroy(etale_t ix) {
+  if (!ix) return ETALE_OK;
+  (void)hipStreamSynchronize(ix->stream);
+  for (void* p : ix->allocs) (void)hipFree(p);
+  delete ix;
+  return ETALE_OK;
+}
+
+etale_status etale_set_stream(etale_t ix, void* stream) {
+  if (!ix) return ETALE_EINVAL;
+  ix->stream = reinterpret_cast<hipStream_t>(stream);
+  return ETALE_OK;
+}
+
+etale_status etale_insert_batch(etale_t ix, const void* vecs_dev, uint64_t n, uint32_t* ids_out_dev) {
+  CHECK_HANDLE();
+  if (n == 0) return ETALE_OK;
+  if (!vecs_dev || n > ix->cfg.max_batch) return fail(ix, ETALE_EINVAL, "insert: null vectors or n > max_batch");
+  if (ix->next_id + n > ix->cfg.id_capacity) return fail(ix, ETALE_ECAPACITY, "insert: id space exhausted");
+  unsigned long long h[C_NCOUNTERS];
+  if (etale_status st = read_counters(ix, h)) return st;
+  const uint32_t R = ix->cfg.R;
+  if (h[C_FREE_TOP] < n * (uint64_t)(R + 2)) return fail(ix, ETALE_EPOOL, "insert: slab pool cannot cover n*(R+2)");
+  const uint32_t first = (uint32_t)ix->next_id;
+  const Index& d = ix->dev;
+  HIP_TRY(hipMemcpyAsync(ix->x + (size_t)first * ix->cfg.dim, vecs_dev, n * ix->cfg.dim, hipMemcpyDeviceToDevice,
+                         ix->stream));
+  if (ids_out_dev) HIP_TRY(launch_write_ids(ids_out_dev, first, n, ix->stream));
+  const bool bootstrap = h[C_N_ENTRIES] == 0;
+  const uint32_t vcap = ix->vcap_build;
+
+  // searches on the graph as it was at the call's start (or the bootstrap)
+  SearchArgs sa{};
+  sa.mode = bootstrap ? MODE_BOOT : MODE_INSERT;
+  sa.first = first;
+  sa.nq = (uint32_t)n;
+  sa.L = bootstrap ? vcap : ix->cfg.L_build;
+  sa.vcap = vcap;
+  sa.vt_mask = ix->cfg.vt_slots - 1;
+  sa.lds_per_wave = search_lds_per_wave(sa.L, ix->cfg.vt_slots);
+  sa.vis_keys = ix->vis_keys;
+  sa.vis_cnt = ix->vis_cnt;
+  const uint32_t swpb = sa.lds_per_wave * ix->cfg.waves_per_block <= 65536u ? ix->cfg.waves_per_block : 1u;
+  HIP_TRY(launch_search(d, sa, swpb, ix->stream));
+
+  // forward neighbors and the node's own slab
+  MaintArgs fa = maint_args(ix, vcap);
+  fa.first = first;
+  fa.n = (uint32_t)n;
+  fa.vis_keys = ix->vis_keys;
+  fa.vis_cnt = ix->vis_cnt;
+  fa.F = ix->F;
+  HIP_TRY(launch_maint(MK_FORWARD, d, fa, (uint32_t)n, maint_waves_per_block(fa), ix->stream));
+
+  // reverse edges, grouped by target in (target, source) order
+  {
+    fa.pairs = ix->pairs_a;
+    HIP_TRY(launch_reverse_pairs(d, fa, ix->stream));
+    if (etale_status st = sort_keys(ix, ix->pairs_a, ix->pairs_b, n * R)) return st;
+    MaintArgs ra = maint_args(ix, R + 1);
+    ra.first = first;
+    ra.n = (uint32_t)n;
+    ra.pairs = ix->pairs_b;
+    ra.npairs = (uint32_t)(n * R);
+    HIP_TRY(launch_maint(MK_REVERSE, d, ra, ra.npairs, maint_waves_per_block(ra), ix->stream));
+  }
+  if (ix->cfg.refine && !bootstrap) {
+    MaintArgs ga = maint_args(ix, R + R * R);
+    ga.first = first;
+    ga.n = (uint32_t)n;
+    HIP_TRY(launch_maint(MK_REFINE, d, ga, (uint32_t)n, maint_waves_per_block(ga), ix->stream));
+  }
+  HIP_TRY(launch_refresh_entries(d, first + (uint32_t)n, ix->cfg.n_entry, ix->stream));
+  HIP_TRY(launch_recycle(d, ix->stream));
+  ix->next_id += n;
+  return ETALE_OK;
+}
+
+etale_status etale_delete_batch(etale_t ix, const uint32_t* ids_dev, uint64_t n, uint8_t* status_out_dev) {
+  CHECK_HANDLE();
+  if (n == 0) return ETALE_OK;
+  if (!ids_dev || n > ix->cfg.max_batch) return fail(ix, ETALE_EINVAL, "delete: null ids or n > max_batch");
+  const Index& d = ix->dev;
+  const uint32_t R = ix->cfg.R;
+  if (etale_status st = set_counter(ix, C_DEL_OK, 0)) return st;
+  HIP_TRY(launch_del_keys(ids_dev, n, ix->pairs_a, ix->stream));
+  if (etale_status st = sort_keys(ix, ix->pairs_a, ix->pairs_b, n)) return st;
+  HIP_TRY(launch_del_classify(d, ix->pairs_b, n, ix->next_id, status_out_dev, ix->dlist, ix->stream));
+  unsigned long long h[C_NCOUNTERS];
+  if (etale_status st = read_counters(ix, h)) return st;
+  const uint64_t dok = h[C_DEL_OK];
+  if (!ix->cfg.tombstone_only && h[C_FREE_TOP] < dok * R)
+    return fail(ix, ETALE_EPOOL, "delete: slab pool cannot cover the repairs");
+  HIP_TRY(launch_tombstone(d, ix->dlist, dok, ix->stream));
+  HIP_TRY(launch_refresh_entries(d, (uint32_t)ix->next_id, ix->cfg.n_entry, ix->stream));
+  if (!ix->cfg.tombstone_only && dok) {
+    MaintArgs pa = maint_args(ix, 2 * R);
+    pa.n = (uint32_t)dok;
+    pa.dlist = ix->dlist;
+    pa.pairs = ix->pairs_a;
+    HIP_TRY(launch_repair_pairs(d, pa, ix->stream));
+    if (etale_status st = sort_keys(ix, ix->pairs_a, ix->pairs_b, dok * R)) return st;
+    pa.pairs = ix->pairs_b;
+    pa.npairs = (uint32_t)(dok * R);
+    HIP_TRY(launch_maint(MK_REPAIR, d, pa, pa.npairs, maint_waves_per_block(pa), ix->stream));
+  }
+  HIP_TRY(launch_recycle(d, ix->stream));
+  return ETALE_OK;
+}
+
+etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
+                                uint32_t* ids_out_dev, void* dists_out_dev, uint32_t* counts_out_dev) {
+  CHECK_HANDLE();
+  if (k < 1 || k > L || L > 256) return fail(ix, ETALE_EINVAL, "search: need 1 <= k <= L <= 256");
+  if (nq == 0) return ETALE_OK;
+  if (!q_dev || !ids_out_dev || !dists_out_dev || nq > 0xFFFFFFFFull)
+    return fail(ix, ETALE_EINVAL, "search: null buffer");
+  SearchArgs sa{};
+  sa.mode = MODE_QUERY;
+  sa.q = reinterpret_cast<const uint8_t*>(q_dev);
+  sa.nq = (uint32_t)nq;
+  sa.L = L;
+  sa.k = k;
+  sa.vcap = ix->cfg.visit_mult * L;
+  sa.vt_mask = ix->cfg.vt_slots - 1;
+  sa.lds_per_wave = search_lds_per_wave(L, ix->cfg.vt_slots);
+  sa.out_ids = ids_out_dev;
+  sa.out_d = reinterpret_cast<int32_t*>(dists_out_dev);
+  sa.counts = counts_out_dev;
+  const uint32_t wpb = sa.lds_per_wave * ix->cfg.waves_per_block <= 65536u ? ix->cfg.waves_per_block : 1u;
+  HIP_TRY(launch_search(ix->dev, sa, wpb, ix->stream));
+  return ETALE_OK;
+}
+
+etale_status etale_reclaim(etale_t ix) {
+  CHECK_HANDLE();
+  if (ix->cfg.tombstone_only) return ETALE_OK;
+  const Index& d = ix->dev;
+  const uint64_t n_ids = ix->next_id;
+  if (etale_status st = set_counter(ix, C_DIRTY, 0)) return st;
+  if (etale_status st = set_counter(ix, C_DEAD, 0)) return st;
+  HIP_TRY(launch_del_bitmap(d, n_ids, ix->bitmap, ix->stream));
+  HIP_TRY(launch_dirty(d, n_ids, ix->bitmap, ix->dirty, ix->stream));
+  unsigned long long h[C_NCOUNTERS];
+  if (etale_status st = read_counters(ix, h)) return st;
+  const uint64_t nd = h[C_DIRTY];
+  if (h[C_FREE_TOP] < nd) return fail(ix, ETALE_EPOOL, "reclaim: slab pool cannot cover compaction");
+  HIP_TRY(launch_compact(d, ix->dirty, nd, ix->bitmap, ix->stream));
+  HIP_TRY(launch_free_tombstones(d, n_ids, ix->stream));
+  HIP_TRY(launch_recycle(d, ix->stream));
+  HIP_TRY(hipStreamSynchronize(ix->stream));
+  return ETALE_OK;
+}
+
+etale_status etale_bruteforce(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t* ids_out_dev,
+                              void* dists_out_dev) {
+  CHECK_HANDLE();
+  if (k < 1 || k > 16 || nq > 0xFFFFFFFFull) return fail(ix, ETALE_EINVAL, "bruteforce: need 1 <= k <= 16");
+  if (nq == 0) return ETALE_OK;
+  if (!q_dev || !ids_out_dev || !dists_out_dev) return fail(ix, ETALE_EINVAL, "bruteforce: null buffer");
+  HIP_TRY(launch_bruteforce(ix->dev, reinterpret_cast<const uint8_t*>(q_dev), (uint32_t)nq, ix->next_id, k,
+                            ids_out_dev, reinterpret_cast<int32_t*>(dists_out_dev), ix->stream));
+  return ETALE_OK;
+}
+
+etale_status etale_get_stats(etale_t ix, etale_stats* out) {
+  if (!ix || !out) return ETALE_EINVAL;
+  unsigned long long h[C_NCOUNTERS];
+  HIP_TRY(hipMemcpyAsync(h, ix->ctr, sizeof(h), hipMemcpyDeviceToHost, ix->stream));
+  HIP_TRY(hipStreamSynchronize(ix->stream));
+  etale_stats s{};
+  s.next_id = ix->next_id;
+  s.live = ix->next_id - h[C_TOMBSTONED];
+  s.tombstones = h[C_TOMBSTONED] - h[C_FREED];
+  s.slab_capacity = ix->cfg.slab_capacity;
+  s.free_slabs = h[C_FREE_TOP];
+  s.resident_slabs = ix->cfg.slab_capacity - h[C_FREE_TOP] - h[C_RETIRED_TOP];
+  s.n_entries = h[C_N_ENTRIES];
+  s.pub_forward = h[C_PUB_FORWARD];
+  s.pub_repair = h[C_PUB_REPAIR];
+  s.pub_reverse = h[C_PUB_REVERSE];
+  s.pub_refine = h[C_PUB_REFINE];
+  s.pub_compact = h[C_PUB_COMPACT];
+  s.freed = h[C_FREED];
+  s.dirty_last = h[C_DIRTY];
+  s.dead_edges_last = h[C_DEAD];
+  s.search_expansions = h[C_SEARCH_EXP];
+  s.search_distances = h[C_SEARCH_DIST];
+  s.cas_failures = h[C_CAS_FAIL];
+  s.publish_dropped = h[C_PUB_DROPPED];
+  s.device_bytes = ix->bytes;
+  s.error_bits = h[C_ERROR];
+  *out = s;
+  return ETALE_OK;
+}
+
+etale_status etale_export(etale_t ix, uint64_t n_ids, uint32_t* nbr_host, void* dist_host, uint8_t* deg_host,
+                          uint8_t* del_host, uint8_t* has_slab_host) {
+  CHECK_HANDLE();
+  if (n_ids > ix->next_id) return fail(ix, ETALE_EINVAL, "export: n_ids > next id");
+  if (n_ids == 0) return ETALE_OK;
+  const uint64_t R = ix->cfg.R;
+  uint32_t *nbr = nullptr, *rho = nullptr;
+  uint8_t* flags = nullptr;
+  HIP_TRY(hipMalloc(&nbr, n_ids * R * 4));
+  HIP_TRY(hipMalloc(&rho, n_ids * R * 4));
+  HIP_TRY(hipMalloc(&flags, n_ids * 3));
+  hipError_t e = launch_export(ix->dev, n_ids, nbr, rho, flags, flags + n_ids, flags + 2 * n_ids, ix->stream);
+  if (e == hipSuccess && nbr_host) e = hipMemcpyAsync(nbr_host, nbr, n_ids * R * 4, hipMemcpyDeviceToHost, ix->stream);
+  if (e == hipSuccess && dist_host) e = hipMemcpyAsync(dist_host, rho, n_ids * R * 4, hipMemcpyDeviceToHost, ix->stream);
+  if (e == hipSuccess && deg_host) e = hipMemcpyAsync(deg_host, flags, n_ids, hipMemcpyDeviceToHost, ix->stream);
+  if (e == hipSuccess && del_host) e = hipMemcpyAsync(del_host, flags + n_ids, n_ids, hipMemcpyDeviceToHost, ix->stream);
+  if (e == hipSuccess && has_slab_host)
+    e = hipMemcpyAsync(has_slab_host, flags + 2 * n_ids, n_ids, hipMemcpyDeviceToHost, ix->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ix->stream);
+  (void)hipFree(nbr);
+  (void)hipFree(rho);
+  (void)hipFree(flags);
+  HIP_TRY(e);
+  return ETALE_OK;
+}
+
+etale_status etale_get_entries(etale_t ix, uint32_t* ids_host, uint64_t cap, uint64_t* n_out) {
+  CHECK_HANDLE();
+  if (!ids_host || !n_out) return ETALE_EINVAL;
+  unsigned long long h[C_NCOUNTERS];
+  if (etale_status st = read_counters(ix, h)) return st;
+  const uint64_t n = std::min<uint64_t>(h[C_N_ENTRIES], cap);
+  if (n) {
+    HIP_TRY(hipMemcpyAsync(ids_host, ix->entries, n * 4, hipMemcpyDeviceToHost, ix->stream));
+    HIP_TRY(hipStreamSynchronize(ix->stream));
+  }
+  *n_out = h[C_N_ENTRIES];
+  return ETALE_OK;
+}
+
+etale_status etale_sync(etale_t ix) {
+  if (!ix) return ETALE_EINVAL;
+  HIP_TRY(hipStreamSynchronize(ix->stream));
+  return ETALE_OK;
+}
+
+const char* etale_last_error(etale_t ix) { return ix ? ix->err.c_str() : "null handle"; }
+
+}  // extern "C"

@@ -1,0 +1,475 @@
+// Device-side building blocks of the ETALE index for gfx950 (wave64).
+//
+// Layout in HBM (one index):
+//   x      : vectors, id-indexed, row = dim bytes (uint8) .
+//   refs   : one 64-bit reference word per id (Definition 1):
+//              bit 63 deletion flag, bits 62..56 degree, bits 31..0 slab id,
+//              slab id 0xFFFFFFFF = no slab. Unborn ids hold <0,0,none>.
+//   slabs  : pool of P slabs of 2R words each: R neighbor ids, then R
+//            distances (structure of arrays, so a search reads only the ids).
+//   free / retired stacks of slab ids with one counter each (Section 3.3).
+//   ctr    : 64-bit counters (stack tops, error bits, statistics).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace etale {
+
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr uint64_t KEY_NONE = ~0ull;
+constexpr uint64_t REF_UNBORN = 0x00000000FFFFFFFFull;
+
+__host__ __device__ inline uint64_t make_ref(uint32_t del, uint32_t deg, uint32_t slab) {
+  return ((uint64_t)(del & 1u) << 63) | ((uint64_t)(deg & 0x7Fu) << 56) | (uint64_t)slab;
+}
+__host__ __device__ inline uint32_t ref_del(uint64_t r) { return (uint32_t)(r >> 63); }
+__host__ __device__ inline uint32_t ref_deg(uint64_t r) { return (uint32_t)(r >> 56) & 0x7Fu; }
+__host__ __device__ inline uint32_t ref_slab(uint64_t r) { return (uint32_t)r; }
+
+// search / sort key: (distance, id) packed so that integer order is the
+// lexicographic order the method uses everywhere.
+__host__ __device__ inline uint64_t make_key(uint32_t d, uint32_t id) { return ((uint64_t)d << 32) | id; }
+__host__ __device__ inline uint32_t key_id(uint64_t k) { return (uint32_t)k; }
+__host__ __device__ inline uint32_t key_dist(uint64_t k) { return (uint32_t)(k >> 32); }
+
+enum Counter {
+  C_FREE_TOP = 0,
+  C_RETIRED_TOP,
+  C_ERROR,
+  C_N_ENTRIES,
+  C_PUB_FORWARD,
+  C_PUB_REPAIR,
+  C_PUB_REVERSE,
+  C_PUB_REFINE,
+  C_PUB_COMPACT,
+  C_FREED,
+  C_DIRTY,
+  C_DEAD,
+  C_SEARCH_EXP,
+  C_SEARCH_DIST,
+  C_CAS_FAIL,
+  C_PUB_DROPPED,
+  C_DEL_OK,
+  C_TOMBSTONED,
+  C_NCOUNTERS = 32
+};
+
+enum ErrorBits : uint64_t { ERR_POOL_EMPTY = 1, ERR_POOL_OVERFLOW = 2, ERR_BAD_LIST = 4 };
+
+struct Index {
+  uint32_t dim, R;
+  uint32_t a2, b2;  // alpha = a/b, applied squared: a^2 * D1 <= b^2 * D2
+  uint32_t publish_attempts;
+  uint32_t prune_cap;
+  uint64_t cap, P;
+  const uint8_t* x;
+  unsigned long long* refs;
+  uint32_t* slabs;
+  uint32_t* free_stack;
+  uint32_t* retired_stack;
+  unsigned long long* ctr;
+  uint32_t* entries;
+};
+
+// ---- wave primitives --------------------------------------------------------
+
+__device__ inline int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Order LDS traffic among the lanes of one wave (waves of a block run
+// independent loops, so block barriers are not usable).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of m below this lane
+__device__ inline uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ inline uint32_t bcast(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint64_t bcast64(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t load_ref(const Index& ix, uint32_t u) {
+  return __hip_atomic_load(&ix.refs[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- uint8 squared L2 via 4-wide byte dot products ----------------------------
+// |a-b|^2 = |a|^2 + |b|^2 - 2<a,b>, every term exact in 32-bit integers for
+// dim <= 1024 (1024 * 255^2 < 2^31).
+
+__device__ inline uint32_t dot16(uint4 a, uint4 b, uint32_t acc) {
+  acc = __builtin_amdgcn_udot4(a.x, b.x, acc, false);
+  acc = __builtin_amdgcn_udot4(a.y, b.y, acc, false);
+  acc = __builtin_amdgcn_udot4(a.z, b.z, acc, false);
+  acc = __builtin_amdgcn_udot4(a.w, b.w, acc, false);
+  return acc;
+}
+
+// sum over the G consecutive lanes of a group (G a power of two)
+template <int G>
+__device__ inline uint32_t group_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---- visited table: exact ids, open addressing, may forget -----------------------
+// A lookup that finds the id reports "seen"; a table too crowded to take the
+// id reports "unseen" without storing it. Forgetting only costs a repeated
+// distance evaluation: the list merge drops keys already listed, and a key
+// rejected or evicted earlier is rejected again (the list's worst key never
+// increases), so results do not depend on the table size.
+constexpr int VT_PROBES = 8;
+
+__device__ inline bool vt_insert(uint32_t* vt, uint32_t mask, uint32_t id) {
+  uint32_t h = (id * 2654435761u) & mask;
+#pragma unroll 1
+  for (int i = 0; i < VT_PROBES; ++i) {
+    uint32_t s = (h + (uint32_t)i) & mask;
+    uint32_t v = vt[s];
+    if (v == id) return false;
+    if (v == NONE) {
+      uint32_t prev = atomicCAS(&vt[s], NONE, id);
+      if (prev == NONE) return true;
+      if (prev == id) return false;
+    }
+  }
+  return true;
+}
+
+// ---- the candidate list (sorted keys + expanded flags, double-buffered) --------
+struct CandList {
+  uint64_t* k[2];
+  uint8_t* x[2];
+  int cur;
+  int n;
+  int L;
+  uint64_t* acck;  // [64] accepted keys of one merge
+  uint32_t* accp;  // [64] their insertion points
+};
+
+// Merge nc <= 64 candidate keys ck[0..nc) (distinct among themselves) into the
+// list, keeping the L smallest and dropping keys already present.
+__device__ inline void list_merge(CandList& cl, const uint64_t* ck, int nc) {
+  const int l = lane_id();
+  const uint64_t* lk = cl.k[cl.cur];
+  const uint8_t* lx = cl.x[cl.cur];
+  uint64_t* nk = cl.k[cl.cur ^ 1];
+  uint8_t* nx = cl.x[cl.cur ^ 1];
+  const int n = cl.n, L = cl.L;
+  bool ok = false;
+  uint64_t key = KEY_NONE;
+  uint32_t pos = 0;
+  if (l < nc) {
+    key = ck[l];
+    ok = key != KEY_NONE && (n < L || key < lk[n - 1]);
+    if (ok) {
+      uint32_t lo = 0, hi = (uint32_t)n;
+      while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (lk[mid] < key)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      pos = lo;
+      if (pos < (uint32_t)n && lk[pos] == key) ok = false;
+    }
+  }
+  const uint64_t m = ballot(ok);
+  const int na = __popcll(m);
+  if (na == 0) return;
+  if (ok) {
+    uint32_t idx = lanes_below(m);
+    cl.acck[idx] = key;
+    cl.accp[idx] = pos;
+  }
+  wave_sync();
+  uint32_t cpos = 0;
+  if (ok) {
+    uint32_t r = 0;
+    for (int t = 0; t < na; ++t) r += cl.acck[t] < key;
+    cpos = pos + r;
+  }
+  for (int i = l; i < n; i += 64) {
+    uint32_t s = 0;
+    for (int t = 0; t < na; ++t) s += cl.accp[t] <= (uint32_t)i;
+    uint32_t np = (uint32_t)i + s;
+    if (np < (uint32_t)L) {
+      nk[np] = lk[i];
+      nx[np] = lx[i];
+    }
+  }
+  if (ok && cpos < (uint32_t)L) {
+    nk[cpos] = key;
+    nx[cpos] = 0;
+  }
+  wave_sync();
+  cl.cur ^= 1;
+  cl.n = min(L, n + na);
+}
+
+// index of the first unexpanded entry, or -1
+__device__ inline int list_first_open(const CandList& cl) {
+  const int l = lane_id();
+  const uint8_t* lx = cl.x[cl.cur];
+  for (int base = 0; base < cl.n; base += 64) {
+    int i = base + l;
+    uint64_t m = ballot(i < cl.n && lx[i] == 0);
+    if (m) return base + (int)__builtin_ctzll(m);
+  }
+  return -1;
+}
+
+// ---- cooperative distance batch ----------------------------------------------
+// G lanes share one vector (16 bytes each); 64/G vectors per pass. qf is this
+// lane's 16-byte chunk of the query, qq the query's squared norm.
+// Writes ck[i] = (D, id) for ids[0..cnt).
+template <int G>
+__device__ inline void dist_batch_u8(const Index& ix, uint4 qf, uint32_t qq, const uint32_t* ids, int cnt,
+                                     uint64_t* ck) {
+  constexpr int VPP = 64 / G;
+  const int l = lane_id();
+  const int c = l % G, grp = l / G;
+  for (int base = 0; base < cnt; base += 4 * VPP) {
+    uint4 v[4];
+    uint32_t id[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int vi = base + u * VPP + grp;
+      id[u] = vi < cnt ? ids[vi] : NONE;
+      v[u] = make_uint4(0, 0, 0, 0);
+      if (id[u] != NONE) v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim)[c];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      uint32_t qx = group_sum<G>(dot16(qf, v[u], 0u));
+      uint32_t xx = group_sum<G>(dot16(v[u], v[u], 0u));
+      int vi = base + u * VPP + grp;
+      if (c == 0 && vi < cnt) ck[vi] = make_key(qq + xx - 2u * qx, id[u]);
+    }
+  }
+}
+
+template <int G>
+__device__ inline uint4 load_frag(const uint8_t* row) {
+  return reinterpret_cast<const uint4*>(row)[lane_id() % G];
+}
+
+// ---- pool and publication (Algorithm 1) ---------------------------------------
+
+__device__ inline uint32_t alloc_slab(const Index& ix) {
+  unsigned long long old = atomicAdd(&ix.ctr[C_FREE_TOP], ~0ull);  // pop
+  if (old == 0ull || old > ix.P) {
+    atomicAdd(&ix.ctr[C_FREE_TOP], 1ull);
+    atomicOr(&ix.ctr[C_ERROR], (unsigned long long)ERR_POOL_EMPTY);
+    return NONE;
+  }
+  return ix.free_stack[old - 1];
+}
+
+__device__ inline void retire_slab(const Index& ix, uint32_t s) {
+  unsigned long long idx = atomicAdd(&ix.ctr[C_RETIRED_TOP], 1ull);  // push
+  if (idx >= ix.P) {
+    atomicOr(&ix.ctr[C_ERROR], (unsigned long long)ERR_POOL_OVERFLOW);
+    return;
+  }
+  ix.retired_stack[idx] = s;
+}
+
+// Copy-on-write publication of list (ids, d)[0..n) for node u by the whole
+// wave: snapshot the reference, take a fresh slab, write it, fence, CAS the
+// reference from the snapshot to <flag of snapshot, n, fresh slab>; on
+// success retire the displaced slab, on failure retire the fresh one and
+// retry, up to the attempt budget. Returns true when installed.
+__device__ inline bool publish(const Index& ix, uint32_t u, const uint32_t* ids, const uint32_t* d, uint32_t n,
+                               Counter which) {
+  const int l = lane_id();
+  const uint32_t R = ix.R;
+  for (uint32_t attempt = 0; attempt < ix.publish_attempts; ++attempt) {
+    const uint64_t snap = bcast64(load_ref(ix, u));
+    uint32_t s = 0;
+    if (l == 0) s = alloc_slab(ix);
+    s = bcast(s);
+    if (s == NONE) return false;
+    uint32_t* slab = ix.slabs + (size_t)s * 2u * R;
+    for (uint32_t j = (uint32_t)l; j < R; j += 64) {
+      slab[j] = j < n ? ids[j] : NONE;
+      slab[R + j] = j < n ? d[j] : 0u;
+    }
+    __threadfence();  // slab contents before the reference that names them
+    uint32_t won = 0;
+    if (l == 0) {
+      const uint64_t want = make_ref(ref_del(snap), n, s);
+      const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)snap, (unsigned long long)want);
+      if (prev == snap) {
+        won = 1;
+        if (ref_slab(snap) != NONE) retire_slab(ix, ref_slab(snap));
+        atomicAdd(&ix.ctr[which], 1ull);
+      } else {
+        retire_slab(ix, s);
+        atomicAdd(&ix.ctr[C_CAS_FAIL], 1ull);
+      }
+    }
+    if (bcast(won)) return true;
+  }
+  if (l == 0) atomicAdd(&ix.ctr[C_PUB_DROPPED], 1ull);
+  return false;
+}
+
+// ---- RobustPrune (slack alpha), one wave -----------------------------------------
+struct PruneLds {
+  uint64_t* keys;   // [nsort]
+  uint64_t* keys2;  // [rows] survivors in order
+  uint8_t* vec;     // [prune_cap * vstride] staged candidate vectors
+  uint32_t* norm;   // [prune_cap]
+  uint32_t* out_ids;  // [R]
+  uint32_t* out_d;    // [R]
+  int nsort;
+  int rows;  // staging rows: keys2, vec and norm hold this many candidates
+  int vstride;
+};
+
+__device__ inline int next_pow2_ge64(int n) {
+  int p = 64;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// In-LDS bitonic sort of keys[0..np), np a power of two >= 64, by one wave.
+__device__ inline void wave_bitonic_sort(uint64_t* keys, int np) {
+  const int l = lane_id();
+  for (int k = 2; k <= np; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = l; i < np; i += 64) {
+        int p = i ^ j;
+        if (p > i) {
+          uint64_t a = keys[i], b = keys[p];
+          bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            keys[i] = b;
+            keys[p] = a;
+          }
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+// RobustPrune_alpha(p, cand[0..n), R): drop p, tombstones and duplicates, order
+// by (D(p,c), id), keep at most prune_cap, then select in order: keep c unless
+// an already kept c' has a^2 * D(c', c) <= b^2 * D(p, c). Result (ids, D) in
+// lds.out_ids / lds.out_d, in (D, id) order; returns its length.
+template <int G>
+__device__ inline int robust_prune_u8(const Index& ix, uint32_t p, const uint32_t* cand, int n, PruneLds& s) {
+  constexpr int VPP = 64 / G;
+  const int l = lane_id();
+  const int c = l % G, grp = l / G;
+  const uint8_t* prow = ix.x + (size_t)p * ix.dim;
+  const uint4 pf = load_frag<G>(prow);
+  const uint32_t pp = group_sum<G>(dot16(pf, pf, 0u));
+  const int np = next_pow2_ge64(n);
+  // 1. keys (D(p,c), c) for admissible candidates
+  for (int base = 0; base < np; base += 4 * VPP) {
+    uint4 v[4];
+    uint32_t id[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int vi = base + u * VPP + grp;
+      id[u] = vi < n ? cand[vi] : NONE;
+      if (id[u] == p) id[u] = NONE;
+      v[u] = make_uint4(0, 0, 0, 0);
+      if (id[u] != NONE) {
+        if (ref_del(load_ref(ix, id[u])))
+          id[u] = NONE;
+        else
+          v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim)[c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      uint32_t px = group_sum<G>(dot16(pf, v[u], 0u));
+      uint32_t xx = group_sum<G>(dot16(v[u], v[u], 0u));
+      int vi = base + u * VPP + grp;
+      if (c == 0 && vi < np) s.keys[vi] = id[u] == NONE ? KEY_NONE : make_key(pp + xx - 2u * px, id[u]);
+    }
+  }
+  wave_sync();
+  wave_bitonic_sort(s.keys, np);
+  // 2. drop duplicates (equal keys are adjacent) and compact
+  int m = 0;
+  for (int base = 0; base < np; base += 64) {
+    int i = base + l;
+    uint64_t k = s.keys[i];
+    bool keep = k != KEY_NONE && (i == 0 || s.keys[i - 1] != k);
+    uint64_t bm = ballot(keep);
+    const int at = m + (int)lanes_below(bm);
+    if (keep && at < s.rows) s.keys2[at] = k;
+    m += __popcll(bm);
+  }
+  wave_sync();
+  if (m > (int)ix.prune_cap) m = (int)ix.prune_cap;
+  if (m > s.rows) m = s.rows;
+  // 3. stage the survivors' vectors (and norms) in LDS
+  for (int base = 0; base < m; base += VPP) {
+    int vi = base + grp;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (vi < m) v = reinterpret_cast<const uint4*>(ix.x + (size_t)key_id(s.keys2[vi]) * ix.dim)[c];
+    uint32_t nn = group_sum<G>(dot16(v, v, 0u));
+    if (vi < m) {
+      *reinterpret_cast<uint4*>(s.vec + (size_t)vi * s.vstride + c * 16) = v;
+      if (c == 0) s.norm[vi] = nn;
+    }
+  }
+  wave_sync();
+  // 4. ordered selection; lane l owns candidates l, l+64, ...
+  const int T = (m + 63) >> 6;
+  uint32_t alive = 0;
+  for (int t = 0; t < T; ++t)
+    if (t * 64 + l < m) alive |= 1u << t;
+  int cnt = 0, from = 0;
+  const uint64_t a2 = ix.a2, b2 = ix.b2;
+  const int words = (int)ix.dim / 16;
+  while (cnt < (int)ix.R) {
+    int j = -1;
+    for (int t = from >> 6; t < T && j < 0; ++t) {
+      uint64_t bm = ballot(((alive >> t) & 1u) && (t * 64 + l) >= from);
+      if (bm) j = t * 64 + (int)__builtin_ctzll(bm);
+    }
+    if (j < 0) break;
+    const uint64_t kj = s.keys2[j];
+    if (l == 0) {
+      s.out_ids[cnt] = key_id(kj);
+      s.out_d[cnt] = key_dist(kj);
+    }
+    ++cnt;
+    from = j + 1;
+    if (cnt == (int)ix.R) break;
+    const uint4* vj = reinterpret_cast<const uint4*>(s.vec + (size_t)j * s.vstride);
+    const uint32_t nj = s.norm[j];
+    for (int t = from >> 6; t < T; ++t) {
+      int i = t * 64 + l;
+      if (!((alive >> t) & 1u) || i < from) continue;
+      const uint4* vi = reinterpret_cast<const uint4*>(s.vec + (size_t)i * s.vstride);
+      uint32_t dot = 0;
+      for (int w = 0; w < words; ++w) dot = dot16(vi[w], vj[w], dot);
+      const uint64_t dji = (uint64_t)(nj + s.norm[i] - 2u * dot);
+      const uint64_t dpi = (uint64_t)key_dist(s.keys2[i]);
+      if (a2 * dji <= b2 * dpi) alive &= ~(1u << t);
+    }
+  }
+  wave_sync();
+  return cnt;
+}
+
+}  // namespace etale

@@ -1,0 +1,797 @@
+// HIP kernels of the ETALE index for gfx950 (uint8 vectors, squared L2).
+//
+// Execution model (Definition 2): every kernel is one launch; the host
+// serializes them on one stream. Within a maintenance phase each target node
+// is owned by exactly one wavefront, so the reference CAS of a publication is
+// uncontended and the phase result does not depend on scheduling.
+#include "etale_dev.h"
+#include "etale_launch.h"
+
+namespace etale {
+
+__host__ __device__ inline uint64_t pair_key(uint32_t target, uint32_t source) {
+  return ((uint64_t)target << 32) | source;
+}
+
+// ---- pool / state initialisation ----------------------------------------------
+
+__global__ void k_init(Index ix) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ix.cap; i += stride)
+    ix.refs[i] = REF_UNBORN;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ix.P; i += stride)
+    ix.free_stack[i] = (uint32_t)(ix.P - 1 - i);
+  if (blockIdx.x == 0 && threadIdx.x < C_NCOUNTERS) ix.ctr[threadIdx.x] = threadIdx.x == C_FREE_TOP ? ix.P : 0ull;
+}
+
+// End of a launch epoch: the retired stack joins the free stack (Lemma 1).
+__global__ void k_recycle(Index ix) {
+  const uint64_t n = ix.ctr[C_RETIRED_TOP];
+  const uint64_t f = ix.ctr[C_FREE_TOP];
+  if (f + n > ix.P) {
+    if (threadIdx.x == 0) atomicOr(&ix.ctr[C_ERROR], (unsigned long long)ERR_POOL_OVERFLOW);
+    return;
+  }
+  for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) ix.free_stack[f + i] = ix.retired_stack[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ix.ctr[C_FREE_TOP] = f + n;
+    ix.ctr[C_RETIRED_TOP] = 0;
+  }
+}
+
+__global__ void k_write_ids(uint32_t* out, uint32_t first, uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = first + (uint32_t)i;
+}
+
+// ---- entry set: the S smallest live ids ---------------------------------------------
+// Old members stay unless deleted; the gap is filled with the next live ids
+// above the old largest member (every live id below it is already a member).
+__device__ inline uint32_t block_prefix(bool keep, uint32_t* wcnt, uint32_t* total) {
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint64_t m = ballot(keep);
+  if (lane_id() == 0) wcnt[w] = __popcll(m);
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    if (i < w) before += wcnt[i];
+    tot += wcnt[i];
+  }
+  *total = tot;
+  return before + lanes_below(m);
+}
+
+__global__ void __launch_bounds__(1024) k_refresh_entries(Index ix, uint32_t next_id, uint32_t S) {
+  __shared__ uint32_t wcnt[16];
+  const uint32_t m_old = (uint32_t)ix.ctr[C_N_ENTRIES];
+  const uint32_t start = m_old ? ix.entries[m_old - 1] + 1u : 0u;
+  uint32_t out = 0;
+  for (uint32_t base = 0; base < m_old; base += blockDim.x) {
+    const uint32_t t = base + threadIdx.x;
+    const uint32_t id = t < m_old ? ix.entries[t] : NONE;
+    const bool keep = id != NONE && !ref_del(load_ref(ix, id));
+    __syncthreads();
+    uint32_t tot;
+    const uint32_t pos = block_prefix(keep, wcnt, &tot);
+    if (keep) ix.entries[out + pos] = id;
+    out += tot;
+    __syncthreads();
+  }
+  for (uint32_t base = start; base < next_id && out < S; base += blockDim.x) {
+    const uint32_t id = base + threadIdx.x;
+    const bool keep = id < next_id && !ref_del(load_ref(ix, id));
+    uint32_t tot;
+    const uint32_t pos = block_prefix(keep, wcnt, &tot);
+    if (keep && out + pos < S) ix.entries[out + pos] = id;
+    out = min(S, out + tot);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ix.ctr[C_N_ENTRIES] = out;
+}
+
+// ---- greedy beam search (queries, insert searches, bootstrap) ----------------------
+// One wavefront per query. LDS per wave: the double-buffered candidate list,
+// one batch of candidate keys/ids, merge scratch and the visited table.
+template <int G>
+__global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  const int wv = (int)(threadIdx.x >> 6);
+  const int l = lane_id();
+  const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (uint32_t)wv;
+  if (qi >= a.nq) return;
+  char* base = smem + (size_t)wv * a.lds_per_wave;
+  CandList cl;
+  uint64_t* p64 = reinterpret_cast<uint64_t*>(base);
+  cl.k[0] = p64;
+  cl.k[1] = p64 + a.L;
+  uint64_t* ck = p64 + 2 * a.L;
+  cl.acck = ck + 64;
+  uint32_t* ci = reinterpret_cast<uint32_t*>(cl.acck + 64);
+  cl.accp = ci + 64;
+  uint32_t* vt = cl.accp + 64;
+  uint8_t* flags = reinterpret_cast<uint8_t*>(vt + a.vt_mask + 1);
+  cl.x[0] = flags;
+  cl.x[1] = flags + a.L;
+  cl.cur = 0;
+  cl.n = 0;
+  cl.L = (int)a.L;
+
+  const uint8_t* qrow = a.mode == MODE_QUERY ? a.q + (size_t)qi * ix.dim : ix.x + (size_t)(a.first + qi) * ix.dim;
+  const uint4 qf = load_frag<G>(qrow);
+  const uint32_t qq = group_sum<G>(dot16(qf, qf, 0u));
+  for (uint32_t i = (uint32_t)l; i <= a.vt_mask; i += 64) vt[i] = NONE;
+  wave_sync();
+
+  uint32_t ndist = 0;
+  if (a.mode == MODE_BOOT) {
+    // bootstrap: the start set is every other member of the batch
+    const uint32_t self = a.first + qi;
+    for (uint32_t b = 0; b < a.nq; b += 64) {
+      const uint32_t id = b + (uint32_t)l < a.nq ? a.first + b + (uint32_t)l : NONE;
+      const bool ok = id != NONE && id != self;
+      const uint64_t m = ballot(ok);
+      if (ok) ci[lanes_below(m)] = id;
+      const int cnt = __popcll(m);
+      wave_sync();
+      dist_batch_u8<G>(ix, qf, qq, ci, cnt, ck);
+      wave_sync();
+      list_merge(cl, ck, cnt);
+      ndist += (uint32_t)cnt;
+    }
+  } else {
+    // the L best members of the entry set
+    const uint32_t ne = bcast((uint32_t)ix.ctr[C_N_ENTRIES]);
+    for (uint32_t b = 0; b < ne; b += 64) {
+      const int cnt = (int)min(64u, ne - b);
+      if (l < cnt) {
+        const uint32_t id = ix.entries[b + (uint32_t)l];
+        ci[l] = id;
+        vt_insert(vt, a.vt_mask, id);
+      }
+      wave_sync();
+      dist_batch_u8<G>(ix, qf, qq, ci, cnt, ck);
+      wave_sync();
+      list_merge(cl, ck, cnt);
+      ndist += (uint32_t)cnt;
+    }
+  }
+
+  uint32_t nexp = 0;
+  if (a.mode != MODE_BOOT) {
+    const uint32_t R = ix.R;
+    while (nexp < a.vcap) {
+      const int j = list_first_open(cl);
+      if (j < 0) break;
+      const uint64_t key = cl.k[cl.cur][j];
+      const uint32_t p = key_id(key);
+      if (l == 0) {
+        cl.x[cl.cur][j] = 1;
+        if (a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp] = key;
+      }
+      ++nexp;
+      const uint64_t r = bcast64(load_ref(ix, p));
+      const uint32_t deg = ref_deg(r), s = ref_slab(r);
+      uint32_t nid = NONE;
+      if ((uint32_t)l < deg && s != NONE) nid = ix.slabs[(size_t)s * 2u * R + (uint32_t)l];
+      const bool fresh = nid != NONE && vt_insert(vt, a.vt_mask, nid);
+      const uint64_t m = ballot(fresh);
+      if (fresh) ci[lanes_below(m)] = nid;
+      const int cnt = __popcll(m);
+      wave_sync();
+      if (cnt) {
+        dist_batch_u8<G>(ix, qf, qq, ci, cnt, ck);
+        wave_sync();
+        list_merge(cl, ck, cnt);
+        ndist += (uint32_t)cnt;
+      }
+    }
+  }
+
+  const uint64_t* lk = cl.k[cl.cur];
+  if (a.mode == MODE_QUERY) {
+    // the first k listed nodes whose reference has flag 0
+    uint32_t got = 0;
+    for (int b = 0; b < cl.n && got < a.k; b += 64) {
+      const int i = b + l;
+      bool live = false;
+      uint64_t key = 0;
+      if (i < cl.n) {
+        key = lk[i];
+        live = !ref_del(load_ref(ix, key_id(key)));
+      }
+      const uint64_t m = ballot(live);
+      const uint32_t idx = got + lanes_below(m);
+      if (live && idx < a.k) {
+        a.out_ids[(size_t)qi * a.k + idx] = key_id(key);
+        a.out_d[(size_t)qi * a.k + idx] = (int32_t)key_dist(key);
+      }
+      got += (uint32_t)__popcll(m);
+    }
+    for (uint32_t i = min(got, a.k) + (uint32_t)l; i < a.k; i += 64) {
+      a.out_ids[(size_t)qi * a.k + i] = NONE;
+      a.out_d[(size_t)qi * a.k + i] = 0x7FFFFFFF;
+    }
+  } else {
+    if (a.mode == MODE_BOOT)
+      for (int i = l; i < cl.n; i += 64) a.vis_keys[(size_t)qi * a.vcap + i] = lk[i];
+    if (l == 0) a.vis_cnt[qi] = a.mode == MODE_BOOT ? (uint32_t)cl.n : nexp;
+  }
+  if (l == 0) {
+    if (a.mode == MODE_QUERY) {
+      atomicAdd(&ix.ctr[C_SEARCH_EXP], (unsigned long long)nexp);
+      atomicAdd(&ix.ctr[C_SEARCH_DIST], (unsigned long long)ndist);
+    }
+    if (a.counts) {
+      a.counts[2 * (size_t)qi] = nexp;
+      a.counts[2 * (size_t)qi + 1] = ndist;
+    }
+  }
+}
+
+// ---- LDS carving for the maintenance kernels ------------------------------------------
+struct MaintLds {
+  PruneLds pr;
+  uint32_t* cand;   // [nmax]
+  uint32_t* nl_id;  // [R + 1] current list of the target
+  uint32_t* nl_d;   // [R + 1]
+  uint32_t* tmp;    // [R + 1]
+};
+
+__device__ inline MaintLds carve(char* base, const MaintArgs& a, uint32_t R) {
+  MaintLds m;
+  char* p = base;
+  m.pr.nsort = a.nsort;
+  m.pr.rows = a.prune_cap;
+  m.pr.vstride = a.vstride;
+  m.pr.keys = reinterpret_cast<uint64_t*>(p);
+  p += (size_t)a.nsort * 8;
+  m.pr.keys2 = reinterpret_cast<uint64_t*>(p);
+  p += (size_t)a.prune_cap * 8;
+  m.pr.vec = reinterpret_cast<uint8_t*>(p);
+  p += (size_t)a.prune_cap * a.vstride;
+  m.pr.norm = reinterpret_cast<uint32_t*>(p);
+  p += (size_t)a.prune_cap * 4;
+  m.pr.out_ids = reinterpret_cast<uint32_t*>(p);
+  p += (size_t)(R + 1) * 4;
+  m.pr.out_d = reinterpret_cast<uint32_t*>(p);
+  p += (size_t)(R + 1) * 4;
+  m.cand = reinterpret_cast<uint32_t*>(p);
+  p += (size_t)a.nmax * 4;
+  m.nl_id = reinterpret_cast<uint32_t*>(p);
+  p += (size_t)(R + 1) * 4;
+  m.nl_d = reinterpret_cast<uint32_t*>(p);
+  p += (size_t)(R + 1) * 4;
+  m.tmp = reinterpret_cast<uint32_t*>(p);
+  return m;
+}
+
+__device__ inline uint32_t wave_index() { return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); }
+__device__ inline char* wave_lds(char* smem, const MaintArgs& a) {
+  return smem + (size_t)(threadIdx.x >> 6) * a.lds_per_wave;
+}
+
+// load node u's current list into (ids, d); returns its degree
+__device__ inline uint32_t load_list(const Index& ix, uint32_t u, uint32_t* ids, uint32_t* d) {
+  const uint64_t r = bcast64(load_ref(ix, u));
+  const uint32_t deg = ref_deg(r), s = ref_slab(r);
+  const int l = lane_id();
+  if ((uint32_t)l < deg && s != NONE) {
+    ids[l] = ix.slabs[(size_t)s * 2u * ix.R + (uint32_t)l];
+    d[l] = ix.slabs[(size_t)s * 2u * ix.R + ix.R + (uint32_t)l];
+  }
+  wave_sync();
+  return s == NONE ? 0u : deg;
+}
+
+__device__ inline void copy_out(const MaintLds& m, uint32_t n) {
+  const int l = lane_id();
+  if ((uint32_t)l < n) {
+    m.nl_id[l] = m.pr.out_ids[l];
+    m.nl_d[l] = m.pr.out_d[l];
+  }
+  wave_sync();
+}
+
+// ---- insert: forward prune + own publication (Algorithm 2, first lines) --------------
+template <int G>
+__global__ void __launch_bounds__(256) k_forward(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  const uint32_t qi = wave_index();
+  if (qi >= a.n) return;
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  const int l = lane_id();
+  const uint32_t v = a.first + qi;
+  const uint32_t nc = a.vis_cnt[qi];
+  for (uint32_t j = (uint32_t)l; j < nc; j += 64) m.cand[j] = key_id(a.vis_keys[(size_t)qi * a.vcap + j]);
+  wave_sync();
+  const int cnt = robust_prune_u8<G>(ix, v, m.cand, (int)nc, m.pr);
+  publish(ix, v, m.pr.out_ids, m.pr.out_d, (uint32_t)cnt, C_PUB_FORWARD);
+  for (uint32_t j = (uint32_t)l; j < ix.R; j += 64) a.F[(size_t)qi * ix.R + j] = j < (uint32_t)cnt ? m.pr.out_ids[j] : NONE;
+}
+
+__global__ void k_reverse_pairs(Index ix, MaintArgs a) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (uint64_t)a.n * ix.R) return;
+  const uint32_t w = a.F[t];
+  const uint32_t v = a.first + (uint32_t)(t / ix.R);
+  a.pairs[t] = w == NONE ? KEY_NONE : pair_key(w, v);
+}
+
+// first wave of each run of equal targets in the sorted pair list owns it
+__device__ inline bool owns_segment(const MaintArgs& a, uint32_t t, uint32_t* target) {
+  if (t >= a.npairs) return false;
+  const uint64_t k = a.pairs[t];
+  if (k == KEY_NONE) return false;
+  *target = (uint32_t)(k >> 32);
+  return t == 0 || (uint32_t)(a.pairs[t - 1] >> 32) != *target;
+}
+
+// ---- insert: reverse edges in (target, source) order, one publication per target ------
+template <int G>
+__global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  const uint32_t t = wave_index();
+  uint32_t w;
+  if (!owns_segment(a, t, &w)) return;
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  const int l = lane_id();
+  const uint32_t R = ix.R;
+  uint32_t n = load_list(ix, w, m.nl_id, m.nl_d);
+  const uint4 wf = load_frag<G>(ix.x + (size_t)w * ix.dim);
+  const uint32_t ww = group_sum<G>(dot16(wf, wf, 0u));
+  uint64_t* ck = m.pr.keys;  // scratch for one distance
+  for (uint32_t u = t; u < a.npairs && a.pairs[u] != KEY_NONE && (uint32_t)(a.pairs[u] >> 32) == w; ++u) {
+    const uint32_t v = (uint32_t)a.pairs[u];
+    const bool present = ballot((uint32_t)l < n && m.nl_id[l] == v) != 0ull;
+    if (present) continue;  // a set union: nothing to add
+    if (n < R) {
+      if (l == 0) m.tmp[0] = v;
+      wave_sync();
+      dist_batch_u8<G>(ix, wf, ww, m.tmp, 1, ck);
+      wave_sync();
+      const uint64_t kv = make_key(key_dist(ck[0]), v);
+      const bool before = (uint32_t)l < n && make_key(m.nl_d[l], m.nl_id[l]) < kv;
+      const uint32_t pos = (uint32_t)__popcll(ballot(before));
+      uint32_t id_l = 0, d_l = 0;
+      if ((uint32_t)l < n) {
+        id_l = m.nl_id[l];
+        d_l = m.nl_d[l];
+      }
+      wave_sync();
+      if ((uint32_t)l < n && (uint32_t)l >= pos) {
+        m.nl_id[l + 1] = id_l;
+        m.nl_d[l + 1] = d_l;
+      }
+      if (l == 0) {
+        m.nl_id[pos] = v;
+        m.nl_d[pos] = key_dist(kv);
+      }
+      wave_sync();
+      ++n;
+    } else {
+      if ((uint32_t)l < n) m.cand[l] = m.nl_id[l];
+      if (l == 0) m.cand[n] = v;
+      wave_sync();
+      n = (uint32_t)robust_prune_u8<G>(ix, w, m.cand, (int)n + 1, m.pr);
+      copy_out(m, n);
+    }
+  }
+  publish(ix, w, m.nl_id, m.nl_d, n, C_PUB_REVERSE);
+}
+
+// ---- insert: refine -- same-batch nodes two hops away are offered ----------------------
+template <int G>
+__global__ void __launch_bounds__(256) k_refine(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  const uint32_t qi = wave_index();
+  if (qi >= a.n) return;
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  const int l = lane_id();
+  const uint32_t v = a.first + qi;
+  const uint32_t end = a.first + a.n;
+  const uint32_t own = load_list(ix, v, m.nl_id, m.nl_d);
+  if ((uint32_t)l < own) m.cand[l] = m.nl_id[l];
+  uint32_t nc = own;
+  for (uint32_t j = 0; j < own; ++j) {
+    const uint32_t w = m.nl_id[j];
+    const uint64_t r = bcast64(load_ref(ix, w));
+    const uint32_t dw = ref_deg(r), s = ref_slab(r);
+    uint32_t b = NONE;
+    if ((uint32_t)l < dw && s != NONE) b = ix.slabs[(size_t)s * 2u * ix.R + (uint32_t)l];
+    const bool extra = b >= a.first && b < end && b != v;
+    const uint64_t bm = ballot(extra);
+    if (extra) m.cand[nc + lanes_below(bm)] = b;
+    nc += (uint32_t)__popcll(bm);
+  }
+  wave_sync();
+  if (nc == own) return;  // no same-batch node within two hops
+  const int cnt = robust_prune_u8<G>(ix, v, m.cand, (int)nc, m.pr);
+  const bool diff = (uint32_t)cnt != own || ballot((uint32_t)l < own && m.pr.out_ids[l] != m.nl_id[l]) != 0ull;
+  if (diff) publish(ix, v, m.pr.out_ids, m.pr.out_d, (uint32_t)cnt, C_PUB_REFINE);
+}
+
+// ---- delete: classify, tombstone, repair (Algorithm 3) ----------------------------------
+__global__ void k_del_keys(const uint32_t* ids, uint64_t n, uint64_t* keys) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) keys[t] = pair_key(ids[t], (uint32_t)t);
+}
+
+__global__ void k_del_classify(Index ix, const uint64_t* sorted, uint64_t n, uint64_t next_id, uint8_t* status,
+                               uint32_t* dlist) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const uint64_t k = sorted[t];
+  const uint32_t id = (uint32_t)(k >> 32), pos = (uint32_t)k;
+  const bool first = t == 0 || (uint32_t)(sorted[t - 1] >> 32) != id;
+  uint8_t st;
+  if (!first)
+    st = DEL_DUPLICATE;
+  else if ((uint64_t)id >= next_id)
+    st = DEL_OUT_OF_RANGE;
+  else if (ref_del(load_ref(ix, id)))
+    st = DEL_NOT_LIVE;
+  else
+    st = DEL_OK;
+  if (status) status[pos] = st;
+  if (st == DEL_OK) {
+    const unsigned long long i = atomicAdd(&ix.ctr[C_DEL_OK], 1ull);
+    dlist[i] = id;
+  }
+}
+
+// <0,d,s> -> <1,d,s>: the flag is set, degree and slab are kept
+__global__ void k_tombstone(Index ix, const uint32_t* dlist, uint64_t n) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const uint32_t u = dlist[t];
+  uint64_t r = load_ref(ix, u);
+  for (int attempt = 0; attempt < 1024 && !ref_del(r); ++attempt) {
+    const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)r, (unsigned long long)(r | (1ull << 63)));
+    if (prev == r) {
+      atomicAdd(&ix.ctr[C_TOMBSTONED], 1ull);
+      break;
+    }
+    r = prev;
+  }
+}
+
+__global__ void k_repair_pairs(Index ix, MaintArgs a) {
+  const uint32_t i = wave_index();
+  if (i >= a.n) return;
+  const int l = lane_id();
+  const uint32_t u = a.dlist[i];
+  const uint64_t r = bcast64(load_ref(ix, u));
+  const uint32_t deg = ref_deg(r), s = ref_slab(r);
+  if ((uint32_t)l >= ix.R) return;
+  uint64_t key = KEY_NONE;
+  if ((uint32_t)l < deg && s != NONE) {
+    const uint32_t an = ix.slabs[(size_t)s * 2u * ix.R + (uint32_t)l];
+    if (!ref_del(load_ref(ix, an))) key = pair_key(an, u);
+  }
+  a.pairs[(size_t)i * ix.R + (uint32_t)l] = key;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  const uint32_t t = wave_index();
+  uint32_t an;
+  if (!owns_segment(a, t, &an)) return;
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  const int l = lane_id();
+  const uint32_t R = ix.R;
+  uint32_t n = load_list(ix, an, m.nl_id, m.nl_d);
+  for (uint32_t q = t; q < a.npairs && a.pairs[q] != KEY_NONE && (uint32_t)(a.pairs[q] >> 32) == an; ++q) {
+    const uint32_t u = (uint32_t)a.pairs[q];
+    // K = RobustPrune(a, N(u) \ {a})
+    const uint64_t r = bcast64(load_ref(ix, u));
+    const uint32_t du = ref_deg(r), s = ref_slab(r);
+    uint32_t b = NONE;
+    if ((uint32_t)l < du && s != NONE) b = ix.slabs[(size_t)s * 2u * R + (uint32_t)l];
+    const bool ok = b != NONE && b != an;
+    const uint64_t bm = ballot(ok);
+    if (ok) m.cand[lanes_below(bm)] = b;
+    wave_sync();
+    const int kc = robust_prune_u8<G>(ix, an, m.cand, __popcll(bm), m.pr);
+    // N = RobustPrune(a, (N(a) \ {u}) U K)
+    const bool keep = (uint32_t)l < n && m.nl_id[l] != u;
+    const uint64_t km = ballot(keep);
+    const uint32_t nk = (uint32_t)__popcll(km);
+    uint32_t kid = (l < kc) ? m.pr.out_ids[l] : NONE;
+    wave_sync();
+    if (keep) m.cand[lanes_below(km)] = m.nl_id[l];
+    if (l < kc) m.cand[nk + (uint32_t)l] = kid;
+    wave_sync();
+    n = (uint32_t)robust_prune_u8<G>(ix, an, m.cand, (int)(nk + (uint32_t)kc), m.pr);
+    copy_out(m, n);
+  }
+  publish(ix, an, m.nl_id, m.nl_d, n, C_PUB_REPAIR);
+}
+
+// ---- reclaim (Algorithm 4) -------------------------------------------------------------
+__global__ void k_del_bitmap(Index ix, uint64_t n_ids, uint64_t* bitmap) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool d = t < n_ids && ref_del(load_ref(ix, (uint32_t)t));
+  const uint64_t m = ballot(d);
+  if (lane_id() == 0 && t < n_ids) bitmap[t >> 6] = m;
+}
+
+__device__ inline bool bit_set(const uint64_t* bm, uint32_t id) { return (bm[id >> 6] >> (id & 63u)) & 1ull; }
+
+// live nodes with an edge into a tombstone ("dirty"), and the count of such edges
+__global__ void k_dirty(Index ix, uint64_t n_ids, const uint64_t* bitmap, uint32_t* dirty) {
+  const uint32_t u = wave_index();
+  if (u >= n_ids) return;
+  const int l = lane_id();
+  const uint64_t r = bcast64(load_ref(ix, u));
+  if (ref_del(r) || ref_slab(r) == NONE) return;
+  const uint32_t deg = ref_deg(r), s = ref_slab(r);
+  bool dead = false;
+  if ((uint32_t)l < deg) dead = bit_set(bitmap, ix.slabs[(size_t)s * 2u * ix.R + (uint32_t)l]);
+  const uint64_t m = ballot(dead);
+  if (m && l == 0) {
+    const unsigned long long i = atomicAdd(&ix.ctr[C_DIRTY], 1ull);
+    dirty[i] = u;
+    atomicAdd(&ix.ctr[C_DEAD], (unsigned long long)__popcll(m));
+  }
+}
+
+// phase 1, compaction: republish each dirty node without its tombstoned entries
+__global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty, uint64_t n, const uint64_t* bitmap,
+                                                 uint32_t lds_per_wave) {
+  extern __shared__ __align__(16) char smem[];
+  const uint32_t i = wave_index();
+  if (i >= n) return;
+  const int l = lane_id();
+  uint32_t* ids = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * lds_per_wave);
+  uint32_t* d = ids + 64;
+  const uint32_t u = dirty[i];
+  const uint64_t r = bcast64(load_ref(ix, u));
+  const uint32_t deg = ref_deg(r), s = ref_slab(r);
+  uint32_t id = NONE, dd = 0;
+  if ((uint32_t)l < deg) {
+    id = ix.slabs[(size_t)s * 2u * ix.R + (uint32_t)l];
+    dd = ix.slabs[(size_t)s * 2u * ix.R + ix.R + (uint32_t)l];
+  }
+  const bool keep = id != NONE && !bit_set(bitmap, id);
+  const uint64_t m = ballot(keep);
+  if (keep) {
+    ids[lanes_below(m)] = id;
+    d[lanes_below(m)] = dd;
+  }
+  wave_sync();
+  publish(ix, u, ids, d, (uint32_t)__popcll(m), C_PUB_COMPACT);
+}
+
+// phase 2: <1,d,s> -> <1,0,none> and the slab is retired
+__global__ void k_free_tombstones(Index ix, uint64_t n_ids) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_ids) return;
+  const uint32_t u = (uint32_t)t;
+  uint64_t r = load_ref(ix, u);
+  for (int attempt = 0; attempt < 1024 && ref_del(r) && ref_slab(r) != NONE; ++attempt) {
+    const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)r, (unsigned long long)make_ref(1, 0, NONE));
+    if (prev == r) {
+      retire_slab(ix, ref_slab(r));
+      atomicAdd(&ix.ctr[C_FREED], 1ull);
+      break;
+    }
+    r = prev;
+  }
+}
+
+// ---- export -----------------------------------------------------------------------------
+__global__ void k_export(Index ix, uint64_t n_ids, uint32_t* nbr, uint32_t* rho, uint8_t* deg, uint8_t* del,
+                         uint8_t* has_slab) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_ids * ix.R) return;
+  const uint32_t u = (uint32_t)(t / ix.R), j = (uint32_t)(t % ix.R);
+  const uint64_t r = load_ref(ix, u);
+  const uint32_t dg = ref_deg(r), s = ref_slab(r);
+  const bool has = s != NONE && j < dg;
+  nbr[t] = has ? ix.slabs[(size_t)s * 2u * ix.R + j] : NONE;
+  rho[t] = has ? ix.slabs[(size_t)s * 2u * ix.R + ix.R + j] : 0u;
+  if (j == 0) {
+    deg[u] = s == NONE ? 0 : (uint8_t)dg;
+    del[u] = (uint8_t)ref_del(r);
+    has_slab[u] = s != NONE;
+  }
+}
+
+// ---- brute-force ground truth over the live set ---------------------------------------
+// One wave per query; each lane scans ids l, l+64, ... keeping its own K best,
+// then the 64 lane lists are merged by a sort in LDS.
+template <int K>
+__global__ void __launch_bounds__(64) k_bruteforce_u8(Index ix, const uint8_t* q, uint32_t nq, uint64_t n_ids,
+                                                       uint32_t k, uint32_t* out_ids, int32_t* out_d) {
+  __shared__ uint64_t all[64 * K];
+  const uint32_t qi = blockIdx.x;
+  if (qi >= nq) return;
+  const int l = lane_id();
+  const uint4* qv = reinterpret_cast<const uint4*>(q + (size_t)qi * ix.dim);
+  const int words = (int)ix.dim / 16;
+  uint32_t qq = 0;
+  for (int w = 0; w < words; ++w) qq = dot16(qv[w], qv[w], qq);
+  uint64_t best[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) best[i] = KEY_NONE;
+  for (uint64_t u = (uint64_t)l; u < n_ids; u += 64) {
+    if (ref_del(load_ref(ix, (uint32_t)u)) || ref_slab(load_ref(ix, (uint32_t)u)) == NONE) continue;
+    const uint4* xv = reinterpret_cast<const uint4*>(ix.x + u * ix.dim);
+    uint32_t qx = 0, xx = 0;
+    for (int w = 0; w < words; ++w) {
+      const uint4 v = xv[w];
+      qx = dot16(qv[w], v, qx);
+      xx = dot16(v, v, xx);
+    }
+    uint64_t key = make_key(qq + xx - 2u * qx, (uint32_t)u);
+    if (key < best[K - 1]) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const uint64_t lo = key < best[i] ? key : best[i];
+        const uint64_t hi = key < best[i] ? best[i] : key;
+        best[i] = lo;
+        key = hi;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) all[l * K + i] = best[i];
+  __syncthreads();
+  wave_bitonic_sort(all, 64 * K);
+  for (uint32_t i = (uint32_t)l; i < k; i += 64) {
+    const uint64_t kk = all[i];
+    out_ids[(size_t)qi * k + i] = kk == KEY_NONE ? NONE : key_id(kk);
+    out_d[(size_t)qi * k + i] = kk == KEY_NONE ? 0x7FFFFFFF : (int32_t)key_dist(kk);
+  }
+}
+
+// ---- host-side launchers ---------------------------------------------------------------------
+
+#define LAUNCH_G(KERNEL, G, grid, block, lds, stream, ...)                                        \
+  switch (G) {                                                                                   \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, grid, block, lds, stream, __VA_ARGS__); break;          \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, grid, block, lds, stream, __VA_ARGS__); break;          \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, grid, block, lds, stream, __VA_ARGS__); break;          \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, grid, block, lds, stream, __VA_ARGS__); break;          \
+    case 16: hipLaunchKernelGGL(KERNEL<16>, grid, block, lds, stream, __VA_ARGS__); break;        \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, grid, block, lds, stream, __VA_ARGS__); break;        \
+    case 64: hipLaunchKernelGGL(KERNEL<64>, grid, block, lds, stream, __VA_ARGS__); break;        \
+    default: return hipErrorInvalidValue;                                                       \
+  }
+
+static inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_init(const Index& ix, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(1024), dim3(256), 0, s, ix);
+  return hipGetLastError();
+}
+
+hipError_t launch_recycle(const Index& ix, hipStream_t s) {
+  hipLaunchKernelGGL(k_recycle, dim3(1), dim3(1024), 0, s, ix);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_ids(uint32_t* out, uint32_t first, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_write_ids, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, first, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_entries(const Index& ix, uint32_t next_id, uint32_t S, hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh_entries, dim3(1), dim3(1024), 0, s, ix, next_id, S);
+  return hipGetLastError();
+}
+
+uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots) {
+  return 16u * L + 1024u + 512u + 4u * vt_slots + ((2u * L + 15u) & ~15u);
+}
+
+hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s) {
+  if (a.nq == 0) return hipSuccess;
+  const int G = (int)ix.dim / 16;
+  const unsigned grid = blocks_for(a.nq, waves_per_block);
+  const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
+  LAUNCH_G(k_search, G, dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a);
+  return hipGetLastError();
+}
+
+uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R) {
+  size_t b = (size_t)a.nsort * 8 + (size_t)a.prune_cap * 8 + (size_t)a.prune_cap * a.vstride + (size_t)a.prune_cap * 4 +
+             (size_t)(R + 1) * 8 + (size_t)a.nmax * 4 + (size_t)(R + 1) * 12;
+  return (uint32_t)((b + 15) & ~(size_t)15);
+}
+
+hipError_t launch_maint(MaintKernel which, const Index& ix, const MaintArgs& a, uint32_t nwaves,
+                        uint32_t waves_per_block, hipStream_t s) {
+  if (nwaves == 0) return hipSuccess;
+  const int G = (int)ix.dim / 16;
+  const unsigned grid = blocks_for(nwaves, waves_per_block);
+  const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
+  const dim3 blk(64 * waves_per_block);
+  switch (which) {
+    case MK_FORWARD: LAUNCH_G(k_forward, G, dim3(grid), blk, lds, s, ix, a); break;
+    case MK_REVERSE: LAUNCH_G(k_reverse_apply, G, dim3(grid), blk, lds, s, ix, a); break;
+    case MK_REFINE: LAUNCH_G(k_refine, G, dim3(grid), blk, lds, s, ix, a); break;
+    case MK_REPAIR: LAUNCH_G(k_repair_apply, G, dim3(grid), blk, lds, s, ix, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reverse_pairs(const Index& ix, const MaintArgs& a, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.n * ix.R;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reverse_pairs, dim3(blocks_for(n, 256)), dim3(256), 0, s, ix, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_repair_pairs(const Index& ix, const MaintArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_repair_pairs, dim3(blocks_for(a.n, 4)), dim3(256), 0, s, ix, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_del_keys(const uint32_t* ids, uint64_t n, uint64_t* keys, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_del_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, ids, n, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_del_classify(const Index& ix, const uint64_t* sorted, uint64_t n, uint64_t next_id,
+                               uint8_t* status, uint32_t* dlist, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_del_classify, dim3(blocks_for(n, 256)), dim3(256), 0, s, ix, sorted, n, next_id, status,
+                     dlist);
+  return hipGetLastError();
+}
+
+hipError_t launch_tombstone(const Index& ix, const uint32_t* dlist, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tombstone, dim3(blocks_for(n, 256)), dim3(256), 0, s, ix, dlist, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_del_bitmap(const Index& ix, uint64_t n_ids, uint64_t* bitmap, hipStream_t s) {
+  if (n_ids == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_del_bitmap, dim3(blocks_for(n_ids, 256)), dim3(256), 0, s, ix, n_ids, bitmap);
+  return hipGetLastError();
+}
+
+hipError_t launch_dirty(const Index& ix, uint64_t n_ids, const uint64_t* bitmap, uint32_t* dirty, hipStream_t s) {
+  if (n_ids == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dirty, dim3(blocks_for(n_ids, 4)), dim3(256), 0, s, ix, n_ids, bitmap, dirty);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const Index& ix, const uint32_t* dirty, uint64_t n, const uint64_t* bitmap,
+                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t per_wave = 512;
+  hipLaunchKernelGGL(k_compact, dim3(blocks_for(n, 4)), dim3(256), 4 * per_wave, s, ix, dirty, n, bitmap, per_wave);
+  return hipGetLastError();
+}
+
+hipError_t launch_free_tombstones(const Index& ix, uint64_t n_ids, hipStream_t s) {
+  if (n_ids == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_free_tombstones, dim3(blocks_for(n_ids, 256)), dim3(256), 0, s, ix, n_ids);
+  return hipGetLastError();
+}
+
+hipError_t launch_export(const Index& ix, uint64_t n_ids, uint32_t* nbr, uint32_t* rho, uint8_t* deg, uint8_t* del,
+                         uint8_t* has_slab, hipStream_t s) {
+  if (n_ids == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_export, dim3(blocks_for(n_ids * ix.R, 256)), dim3(256), 0, s, ix, n_ids, nbr, rho, deg, del,
+                     has_slab);
+  return hipGetLastError();
+}
+
+hipError_t launch_bruteforce(const Index& ix, const uint8_t* q, uint32_t nq, uint64_t n_ids, uint32_t k,
+                             uint32_t* out_ids, int32_t* out_d, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  if (k > 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bruteforce_u8<16>, dim3(nq), dim3(64), 0, s, ix, q, nq, n_ids, k, out_ids, out_d);
+  return hipGetLastError();
+}
+
+}  // namespace etale

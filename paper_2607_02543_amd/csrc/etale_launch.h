@@ -1,0 +1,71 @@
+// Kernel argument blocks and host launchers shared by the kernels and the
+// C-ABI implementation (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace etale {
+
+struct Index;
+
+enum SearchMode { MODE_QUERY = 0, MODE_INSERT = 1, MODE_BOOT = 2 };
+enum DelStatus { DEL_OK = 0, DEL_NOT_LIVE = 1, DEL_OUT_OF_RANGE = 2, DEL_DUPLICATE = 3 };
+
+struct SearchArgs {
+  int mode;
+  const uint8_t* q;   // MODE_QUERY: [nq x dim] query rows
+  uint32_t first;     // MODE_INSERT / MODE_BOOT: query i is stored vector first + i
+  uint32_t nq, L, k, vcap, vt_mask;
+  uint32_t lds_per_wave;
+  uint32_t* out_ids;  // MODE_QUERY: [nq x k]
+  int32_t* out_d;     // MODE_QUERY: [nq x k]
+  uint64_t* vis_keys; // MODE_INSERT / MODE_BOOT: [nq x vcap] candidate keys
+  uint32_t* vis_cnt;  // [nq]
+  uint32_t* counts;   // optional [nq x 2]: expansions, distance evaluations
+};
+
+struct MaintArgs {
+  uint32_t first, n;       // new ids [first, first + n) / number of deleted ids
+  uint32_t vcap;
+  const uint64_t* vis_keys;
+  const uint32_t* vis_cnt;
+  uint32_t* F;             // [n x R] forward lists
+  uint64_t* pairs;         // (target, source) keys, sorted for the apply kernels
+  uint32_t npairs;
+  const uint32_t* dlist;   // deleted ids of the call
+  uint32_t nmax;           // largest candidate count one prune sees
+  uint32_t nsort;          // power of two >= nmax, >= 64
+  uint32_t prune_cap;      // LDS staging rows
+  uint32_t vstride;        // bytes per staged row
+  uint32_t lds_per_wave;
+};
+
+enum MaintKernel { MK_FORWARD = 0, MK_REVERSE = 1, MK_REFINE = 2, MK_REPAIR = 3 };
+
+hipError_t launch_init(const Index& ix, hipStream_t s);
+hipError_t launch_recycle(const Index& ix, hipStream_t s);
+hipError_t launch_write_ids(uint32_t* out, uint32_t first, uint64_t n, hipStream_t s);
+hipError_t launch_refresh_entries(const Index& ix, uint32_t next_id, uint32_t S, hipStream_t s);
+uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots);
+hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s);
+uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R);
+hipError_t launch_maint(MaintKernel which, const Index& ix, const MaintArgs& a, uint32_t nwaves,
+                        uint32_t waves_per_block, hipStream_t s);
+hipError_t launch_reverse_pairs(const Index& ix, const MaintArgs& a, hipStream_t s);
+hipError_t launch_repair_pairs(const Index& ix, const MaintArgs& a, hipStream_t s);
+hipError_t launch_del_keys(const uint32_t* ids, uint64_t n, uint64_t* keys, hipStream_t s);
+hipError_t launch_del_classify(const Index& ix, const uint64_t* sorted, uint64_t n, uint64_t next_id,
+                               uint8_t* status, uint32_t* dlist, hipStream_t s);
+hipError_t launch_tombstone(const Index& ix, const uint32_t* dlist, uint64_t n, hipStream_t s);
+hipError_t launch_del_bitmap(const Index& ix, uint64_t n_ids, uint64_t* bitmap, hipStream_t s);
+hipError_t launch_dirty(const Index& ix, uint64_t n_ids, const uint64_t* bitmap, uint32_t* dirty, hipStream_t s);
+hipError_t launch_compact(const Index& ix, const uint32_t* dirty, uint64_t n, const uint64_t* bitmap,
+                          hipStream_t s);
+hipError_t launch_free_tombstones(const Index& ix, uint64_t n_ids, hipStream_t s);
+hipError_t launch_export(const Index& ix, uint64_t n_ids, uint32_t* nbr, uint32_t* rho, uint8_t* deg, uint8_t* del,
+                         uint8_t* has_slab, hipStream_t s);
+hipError_t launch_bruteforce(const Index& ix, const uint8_t* q, uint32_t nq, uint64_t n_ids, uint32_t k,
+                             uint32_t* out_ids, int32_t* out_d, hipStream_t s);
+
+}  // namespace etale

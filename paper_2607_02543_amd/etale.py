@@ -1,0 +1,212 @@
+"""Python binding of the ETALE C ABI (include/etale.h).
+
+Argument marshalling only: every step of insert / delete / search / reclaim
+runs in the HIP kernels of libetale.so. torch supplies device memory and the
+current HIP stream. The binding refuses to run without the built library.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libetale.so")
+
+OK, EINVAL, ENOMEM, EPOOL, ECAPACITY, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+METRIC_L2_U8 = 0
+DEL_OK, DEL_NOT_LIVE, DEL_OUT_OF_RANGE, DEL_DUPLICATE = 0, 1, 2, 3
+NONE = 0xFFFFFFFF
+
+_ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EPOOL: "EPOOL", ECAPACITY: "ECAPACITY", EDEVICE: "EDEVICE",
+             ESTATE: "ESTATE"}
+
+
+class EtaleError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {_ERRNAMES.get(code, code)} ({msg})")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("dim", C.c_uint32), ("R", C.c_uint32), ("L_build", C.c_uint32),
+        ("alpha_num", C.c_uint32), ("alpha_den", C.c_uint32), ("visit_mult", C.c_uint32),
+        ("prune_cap", C.c_uint32), ("n_entry", C.c_uint32), ("refine", C.c_uint32),
+        ("tombstone_only", C.c_uint32), ("publish_attempts", C.c_uint32), ("max_batch", C.c_uint32),
+        ("vt_slots", C.c_uint32), ("waves_per_block", C.c_uint32), ("metric", C.c_int32),
+        ("reserved", C.c_int32), ("id_capacity", C.c_uint64), ("slab_capacity", C.c_uint64),
+        ("hip_stream", C.c_void_p),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "next_id", "live", "tombstones", "slab_capacity", "free_slabs", "resident_slabs", "n_entries",
+        "pub_forward", "pub_repair", "pub_reverse", "pub_refine", "pub_compact", "freed", "dirty_last",
+        "dead_edges_last", "search_expansions", "search_distances", "cas_failures", "publish_dropped",
+        "device_bytes", "error_bits")]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load() -> C.CDLL:
+    """Load libetale.so; raise if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_02543_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32
+    sigs = {
+        "etale_create": ([C.POINTER(Config), C.POINTER(vp)], i32),
+        "etale_destroy": ([vp], i32),
+        "etale_set_stream": ([vp, vp], i32),
+        "etale_insert_batch": ([vp, vp, u64, vp], i32),
+        "etale_delete_batch": ([vp, vp, u64, vp], i32),
+        "etale_search_batch": ([vp, vp, u64, u32, u32, vp, vp, vp], i32),
+        "etale_reclaim": ([vp], i32),
+        "etale_bruteforce": ([vp, vp, u64, u32, vp, vp], i32),
+        "etale_get_stats": ([vp, C.POINTER(Stats)], i32),
+        "etale_export": ([vp, u64, vp, vp, vp, vp, vp], i32),
+        "etale_get_entries": ([vp, vp, u64, C.POINTER(u64)], i32),
+        "etale_sync": ([vp], i32),
+        "etale_last_error": ([vp], C.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Index:
+    """One ETALE index on the current GPU."""
+
+    def __init__(self, dim: int, R: int = 32, L_build: int = 64, alpha=(6, 5), visit_mult: int = 4,
+                 prune_cap: Optional[int] = None, n_entry: int = 128, refine: bool = True,
+                 tombstone_only: bool = False, publish_attempts: int = 8, max_batch: int = 10000,
+                 vt_slots: int = 1024, waves_per_block: int = 4, id_capacity: int = 100000,
+                 slab_capacity: Optional[int] = None, metric: int = METRIC_L2_U8, stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load()
+        if prune_cap is None:
+            prune_cap = max(visit_mult * L_build, 2 * R + 2)
+        if slab_capacity is None:
+            slab_capacity = 2 * id_capacity + max_batch * (R + 2)
+        self.dim, self.R, self.metric = dim, R, metric
+        self.cfg = Config(dim, R, L_build, alpha[0], alpha[1], visit_mult, prune_cap, n_entry, int(refine),
+                          int(tombstone_only), publish_attempts, max_batch, vt_slots, waves_per_block, metric, 0,
+                          id_capacity, slab_capacity, None)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.cfg.hip_stream = s.cuda_stream
+        self.stream = s
+        h = C.c_void_p()
+        rc = self.lib.etale_create(C.byref(self.cfg), C.byref(h))
+        if rc != OK:
+            raise EtaleError(rc, "etale_create", "configuration rejected or allocation failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.etale_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, where: str):
+        if rc != OK:
+            msg = self.lib.etale_last_error(self.h)
+            raise EtaleError(rc, where, msg.decode() if msg else "")
+
+    def _dev(self, t, dtype):
+        torch = self.torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda):
+            raise TypeError("expected a CUDA (HIP) tensor")
+        return t.contiguous().to(dtype)
+
+    def insert(self, x):
+        torch = self.torch
+        x = self._dev(x, torch.uint8)
+        n = x.shape[0]
+        ids = torch.empty(n, dtype=torch.int32, device=x.device)
+        self._check(self.lib.etale_insert_batch(self.h, _ptr(x), n, _ptr(ids)), "insert_batch")
+        return ids
+
+    def delete(self, ids):
+        torch = self.torch
+        ids = self._dev(ids, torch.int32)
+        st = torch.empty(ids.numel(), dtype=torch.uint8, device=ids.device)
+        self._check(self.lib.etale_delete_batch(self.h, _ptr(ids), ids.numel(), _ptr(st)), "delete_batch")
+        return st
+
+    def search(self, q, k: int, L: int, counts: bool = False):
+        torch = self.torch
+        q = self._dev(q, torch.uint8)
+        nq = q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+        d = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+        cnt = torch.empty((nq, 2), dtype=torch.int32, device=q.device) if counts else None
+        self._check(self.lib.etale_search_batch(self.h, _ptr(q), nq, k, L, _ptr(ids), _ptr(d), _ptr(cnt)),
+                    "search_batch")
+        return (ids, d, cnt) if counts else (ids, d)
+
+    def reclaim(self):
+        self._check(self.lib.etale_reclaim(self.h), "reclaim")
+
+    def bruteforce(self, q, k: int):
+        torch = self.torch
+        q = self._dev(q, torch.uint8)
+        ids = torch.empty((q.shape[0], k), dtype=torch.int32, device=q.device)
+        d = torch.empty((q.shape[0], k), dtype=torch.int32, device=q.device)
+        self._check(self.lib.etale_bruteforce(self.h, _ptr(q), q.shape[0], k, _ptr(ids), _ptr(d)), "bruteforce")
+        return ids, d
+
+    def sync(self):
+        self._check(self.lib.etale_sync(self.h), "sync")
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.etale_get_stats(self.h, C.byref(s)), "get_stats")
+        return {name: int(getattr(s, name)) for name, _ in Stats._fields_}
+
+    def export(self, n_ids: Optional[int] = None) -> dict:
+        if n_ids is None:
+            n_ids = self.stats()["next_id"]
+        R = self.R
+        nbr = np.zeros((max(n_ids, 1), R), np.uint32)
+        rho = np.zeros((max(n_ids, 1), R), np.uint32)
+        deg = np.zeros(max(n_ids, 1), np.uint8)
+        de = np.zeros(max(n_ids, 1), np.uint8)
+        hs = np.zeros(max(n_ids, 1), np.uint8)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        self._check(self.lib.etale_export(self.h, n_ids, p(nbr), p(rho), p(deg), p(de), p(hs)), "export")
+        return dict(nbr=nbr[:n_ids], rho=rho[:n_ids].view(np.int32), deg=deg[:n_ids],
+                    deleted=de[:n_ids].astype(bool), has_slab=hs[:n_ids].astype(bool))
+
+    def entries(self) -> np.ndarray:
+        cap = int(self.cfg.n_entry)
+        out = np.zeros(cap, np.uint32)
+        n = C.c_uint64(0)
+        self._check(self.lib.etale_get_entries(self.h, out.ctypes.data_as(C.c_void_p), cap, C.byref(n)), "entries")
+        return out[:n.value].copy()

@@ -1,0 +1,93 @@
+"""GPU path vs the CPU oracle through the C ABI: bit-exact on the uint8 path.
+
+Every insert / delete / reclaim call is followed by a full comparison of the
+exported state (neighbor lists with their distances, degrees, deletion flags,
+slab presence, pool counts, publication counters, entry set), and every
+search by a comparison of ids and distances.
+"""
+
+import numpy as np
+import pytest
+
+from common import assert_same_state, index_params, make_gpu, make_oracle, small_workload
+from paper_2607_02543_amd import datagen as dg
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def run_parity(wl, n_entry=64, refine=True, tombstone_only=False, search_L=(64,), k=10, n_queries=200,
+               reclaim=True, **gpu_kw):
+    torch = _torch()
+    p = index_params(wl, n_entry=n_entry, refine=refine, tombstone_only=tombstone_only)
+    o = make_oracle(p)
+    g = make_gpu(p, **gpu_kw)
+    st = dg.Stream(wl)
+    dev = torch.device("cuda")
+    print(f"[parity] {wl.name} n={wl.n_base} rounds={wl.churn_rounds} n_entry={n_entry} refine={refine} "
+          f"tombstone_only={tombstone_only} gpu_kw={gpu_kw}", flush=True)
+    for bi, b in enumerate(wl.build_batches()):
+        x = st.base(b)
+        ido = o.insert(x)
+        idg = g.insert(torch.from_numpy(x).to(dev)).cpu().numpy().astype(np.uint32)
+        assert np.array_equal(ido, idg)
+        assert_same_state(o, g, f"build batch {bi}")
+    q = st.queries(n_queries)
+    qd = torch.from_numpy(q).to(dev)
+
+    def check_search(where):
+        for L in search_L:
+            io, do = o.search(q, k, L)
+            ig, dgpu = g.search(qd, k, L)
+            ig = ig.cpu().numpy().astype(np.uint32)
+            dgpu = dgpu.cpu().numpy()
+            assert np.array_equal(io, ig), f"{where} L={L}: result ids differ"
+            assert np.array_equal(do, dgpu), f"{where} L={L}: result distances differ"
+
+    check_search("after build")
+    for r in range(wl.churn_rounds):
+        live = np.nonzero(~o.export()["deleted"])[0].astype(np.uint32)
+        dl = st.deletes(live, wl.churn_count())
+        so = o.delete(dl)
+        sg = g.delete(torch.from_numpy(dl.astype(np.int32)).to(dev)).cpu().numpy()
+        assert np.array_equal(so, sg)
+        assert_same_state(o, g, f"round {r} delete")
+        x = st.inserts(wl.churn_count())
+        o.insert(x)
+        g.insert(torch.from_numpy(x).to(dev))
+        assert_same_state(o, g, f"round {r} insert")
+        if reclaim:
+            o.reclaim()
+            g.reclaim()
+            assert_same_state(o, g, f"round {r} reclaim")
+        check_search(f"round {r}")
+    g.close()
+
+
+def test_parity_small_default():
+    run_parity(small_workload())
+
+
+def test_parity_small_no_refine_two_L():
+    run_parity(small_workload(seed=2), refine=False, search_L=(16, 32, 100))
+
+
+def test_parity_tombstone_only():
+    run_parity(small_workload(seed=3), tombstone_only=True)
+
+
+def test_parity_ragged_batches():
+    # batch sizes that are not multiples of the wave width or of 4 waves
+    wl = small_workload(n_base=1237, seed=4, batch=301, rounds=2, churn=0.03)
+    run_parity(wl, n_entry=37, search_L=(10, 64))
+
+
+def test_parity_knob_invariance():
+    # visited-table size and waves per block must not change any result
+    wl = small_workload(seed=5, n_base=1500, rounds=1)
+    run_parity(wl, vt_slots=64, waves_per_block=1)
+    run_parity(wl, vt_slots=4096, waves_per_block=2)
