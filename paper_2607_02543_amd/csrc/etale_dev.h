@@ -148,23 +148,31 @@ __device__ inline bool vt_insert(uint32_t* vt, uint32_t mask, uint32_t id) {
 
 // ---- the candidate list (sorted keys + expanded flags, double-buffered) --------
 struct CandList {
-  uint64_t* k[2];
-  uint8_t* x[2];
+  uint64_t* k0;
+  uint64_t* k1;
+  uint8_t* x0;
+  uint8_t* x1;
   int cur;
   int n;
   int L;
   uint64_t* acck;  // [64] accepted keys of one merge
   uint32_t* accp;  // [64] their insertion points
+  // the live buffer and the spare one (selects, not indexed arrays, so the
+  // pointers stay in registers)
+  __device__ uint64_t* keys() const { return cur ? k1 : k0; }
+  __device__ uint8_t* flags() const { return cur ? x1 : x0; }
+  __device__ uint64_t* spare_keys() const { return cur ? k0 : k1; }
+  __device__ uint8_t* spare_flags() const { return cur ? x0 : x1; }
 };
 
 // Merge nc <= 64 candidate keys ck[0..nc) (distinct among themselves) into the
 // list, keeping the L smallest and dropping keys already present.
 __device__ inline void list_merge(CandList& cl, const uint64_t* ck, int nc) {
   const int l = lane_id();
-  const uint64_t* lk = cl.k[cl.cur];
-  const uint8_t* lx = cl.x[cl.cur];
-  uint64_t* nk = cl.k[cl.cur ^ 1];
-  uint8_t* nx = cl.x[cl.cur ^ 1];
+  const uint64_t* lk = cl.keys();
+  const uint8_t* lx = cl.flags();
+  uint64_t* nk = cl.spare_keys();
+  uint8_t* nx = cl.spare_flags();
   const int n = cl.n, L = cl.L;
   bool ok = false;
   uint64_t key = KEY_NONE;
@@ -221,7 +229,7 @@ __device__ inline void list_merge(CandList& cl, const uint64_t* ck, int nc) {
 // index of the first unexpanded entry, or -1
 __device__ inline int list_first_open(const CandList& cl) {
   const int l = lane_id();
-  const uint8_t* lx = cl.x[cl.cur];
+  const uint8_t* lx = cl.flags();
   for (int base = 0; base < cl.n; base += 64) {
     int i = base + l;
     uint64_t m = ballot(i < cl.n && lx[i] == 0);

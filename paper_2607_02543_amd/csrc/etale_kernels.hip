@@ -103,16 +103,16 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   char* base = smem + (size_t)wv * a.lds_per_wave;
   CandList cl;
   uint64_t* p64 = reinterpret_cast<uint64_t*>(base);
-  cl.k[0] = p64;
-  cl.k[1] = p64 + a.L;
+  cl.k0 = p64;
+  cl.k1 = p64 + a.L;
   uint64_t* ck = p64 + 2 * a.L;
   cl.acck = ck + 64;
   uint32_t* ci = reinterpret_cast<uint32_t*>(cl.acck + 64);
   cl.accp = ci + 64;
   uint32_t* vt = cl.accp + 64;
   uint8_t* flags = reinterpret_cast<uint8_t*>(vt + a.vt_mask + 1);
-  cl.x[0] = flags;
-  cl.x[1] = flags + a.L;
+  cl.x0 = flags;
+  cl.x1 = flags + a.L;
   cl.cur = 0;
   cl.n = 0;
   cl.L = (int)a.L;
@@ -163,10 +163,10 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
     while (nexp < a.vcap) {
       const int j = list_first_open(cl);
       if (j < 0) break;
-      const uint64_t key = cl.k[cl.cur][j];
+      const uint64_t key = cl.keys()[j];
       const uint32_t p = key_id(key);
       if (l == 0) {
-        cl.x[cl.cur][j] = 1;
+        cl.flags()[j] = 1;
         if (a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp] = key;
       }
       ++nexp;
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
     }
   }
 
-  const uint64_t* lk = cl.k[cl.cur];
+  const uint64_t* lk = cl.keys();
   if (a.mode == MODE_QUERY) {
     // the first k listed nodes whose reference has flag 0
     uint32_t got = 0;
