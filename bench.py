@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--n-base", type=int, default=1_000_000)
     ap.add_argument("--queries", type=int, default=10_000)
     ap.add_argument("--L", default="32,64,128")
-    ap.add_argument("--n-entry", type=int, default=4096)
+    ap.add_argument("--n-entry", type=int, default=8192)
     ap.add_argument("--recall-sample", type=int, default=1000)
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--vt-slots", type=int, default=1024)

@@ -32,6 +32,12 @@ struct etale_index {
   uint32_t* dlist = nullptr;
   uint32_t* dirty = nullptr;
   uint64_t* bitmap = nullptr;
+  uint64_t* scan_keys = nullptr;  // [scan_chunk x 256] initial lists
+  uint32_t* scan_n = nullptr;
+  uint32_t* scan_dist = nullptr;  // [dist_cap] query x start-set distances
+  uint64_t dist_cap = 0;
+  uint32_t scan_chunk = 0;
+  uint64_t live = 0;              // ids with deletion flag 0 (host mirror)
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
   uint64_t next_id = 0;
@@ -114,9 +120,95 @@ MaintArgs maint_args(const etale_index* ix, uint32_t nmax) {
   return a;
 }
 
+// waves per search workgroup: the configured count, halved until the
+// workgroup's LDS fits 64 KiB
+uint32_t search_waves_per_block(const etale_index* ix, uint32_t lds_per_wave) {
+  uint32_t w = ix->cfg.waves_per_block;
+  while (w > 1 && (uint64_t)lds_per_wave * w > 65536u) w >>= 1;
+  return w;
+}
+
+constexpr uint32_t SCAN_L_MAX = 256;
+
 uint32_t maint_waves_per_block(const MaintArgs& a) {
   uint32_t w = 65536u / a.lds_per_wave;
   return w >= 4 ? 4 : (w >= 2 ? 2 : 1);
+}
+
+uint32_t n_entries(const etale_index* ix) { return (uint32_t)std::min<uint64_t>(ix->cfg.n_entry, ix->live); }
+
+// queries per launch so that the distance matrix fits its scratch
+uint32_t scan_chunk_for(const etale_index* ix, uint32_t ns) {
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ix->scan_chunk, ix->dist_cap / std::max(1u, ns)));
+}
+
+// start-set scoring, then the beam search, over queries [0, nq) in chunks
+etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t first, uint64_t nq, uint32_t k,
+                          uint32_t L, uint32_t vcap, uint32_t* out_ids, int32_t* out_d, uint32_t* counts) {
+  const uint32_t ns = n_entries(ix);
+  const uint32_t chunk = scan_chunk_for(ix, ns);
+  for (uint64_t c = 0; c < nq; c += chunk) {
+    const uint32_t cn = (uint32_t)std::min<uint64_t>(chunk, nq - c);
+    ScanArgs sc{};
+    sc.mode = mode;
+    sc.q = mode == MODE_QUERY ? q + c * ix->cfg.dim : nullptr;
+    sc.first = first + (uint32_t)c;
+    sc.nq = cn;
+    sc.L = L;
+    sc.ns = ns;
+    sc.dist = ix->scan_dist;
+    sc.out_keys = ix->scan_keys;
+    sc.out_n = ix->scan_n;
+    sc.out_stride = L;
+    if (ns == 0) {
+      HIP_TRY(hipMemsetAsync(ix->scan_n, 0, (size_t)cn * 4, ix->stream));
+    } else {
+      HIP_TRY(launch_scan(ix->dev, sc, ix->stream));
+    }
+    SearchArgs sa{};
+    sa.mode = mode;
+    sa.q = sc.q;
+    sa.first = sc.first;
+    sa.nq = cn;
+    sa.L = L;
+    sa.k = k;
+    sa.vcap = vcap;
+    sa.vt_mask = ix->cfg.vt_slots - 1;
+    sa.lds_per_wave = search_lds_per_wave(L, ix->cfg.vt_slots);
+    sa.init_keys = ix->scan_keys;
+    sa.init_n = ix->scan_n;
+    sa.init_stride = L;
+    if (mode == MODE_QUERY) {
+      sa.out_ids = out_ids + c * k;
+      sa.out_d = out_d + c * k;
+      sa.counts = counts ? counts + 2 * c : nullptr;
+    } else {
+      sa.vis_keys = ix->vis_keys + c * vcap;
+      sa.vis_cnt = ix->vis_cnt + c;
+    }
+    HIP_TRY(launch_search(ix->dev, sa, search_waves_per_block(ix, sa.lds_per_wave), ix->stream));
+  }
+  return ETALE_OK;
+}
+
+// bootstrap: each new node's candidates are the vcap nearest other members
+etale_status run_bootstrap(etale_index* ix, uint32_t first, uint32_t n, uint32_t vcap) {
+  const uint32_t chunk = scan_chunk_for(ix, n);
+  for (uint32_t c = 0; c < n; c += chunk) {
+    ScanArgs sc{};
+    sc.mode = MODE_BOOT;
+    sc.first = first;  // the start set is the whole batch
+    sc.nq = std::min(chunk, n - c);
+    sc.L = vcap;
+    sc.ns = n;
+    sc.dist = ix->scan_dist;
+    sc.out_keys = ix->vis_keys + (size_t)c * vcap;
+    sc.out_n = ix->vis_cnt + c;
+    sc.out_stride = vcap;
+    sc.qoff = c;
+    HIP_TRY(launch_scan(ix->dev, sc, ix->stream));
+  }
+  return ETALE_OK;
 }
 
 #define CHECK_HANDLE()                                       \
@@ -138,7 +230,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   if (c.alpha_num == 0 || c.alpha_den == 0 || c.alpha_num > 1000 || c.alpha_den > 1000) return ETALE_EINVAL;
   if (c.visit_mult < 1 || c.visit_mult * c.L_build > 4096) return ETALE_EINVAL;
   if (c.prune_cap < c.R || c.prune_cap > 2048) return ETALE_EINVAL;
-  if (c.n_entry < 1 || c.n_entry > (1u << 20)) return ETALE_EINVAL;
+  if (c.n_entry < 1 || c.n_entry > 16384) return ETALE_EINVAL;  // a start set is scored in registers
   if (c.publish_attempts < 1 || c.max_batch < 1) return ETALE_EINVAL;
   if (!pow2(c.vt_slots) || c.vt_slots < 64 || c.vt_slots > 16384) return ETALE_EINVAL;
   if (c.waves_per_block != 1 && c.waves_per_block != 2 && c.waves_per_block != 4) return ETALE_EINVAL;
@@ -153,7 +245,8 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
     const uint32_t worst_nmax[] = {probe.vcap_build, c.R + 1, 2 * c.R, c.R + c.R * c.R};
     for (uint32_t nm : worst_nmax)
       if (maint_args(&probe, nm).lds_per_wave > 65536u) return ETALE_EINVAL;
-    if (search_lds_per_wave(std::max(256u, probe.vcap_build), c.vt_slots) > 65536u) return ETALE_EINVAL;
+    if (search_lds_per_wave(SCAN_L_MAX, c.vt_slots) > 65536u) return ETALE_EINVAL;
+    if (4 * scan_select_lds_per_wave(std::max(SCAN_L_MAX, probe.vcap_build)) > 65536u) return ETALE_EINVAL;
   }
 
   etale_index* ix = new etale_index();
@@ -184,6 +277,11 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   ALLOC(ix->dlist, B * 4);
   ALLOC(ix->dirty, C * 4);
   ALLOC(ix->bitmap, ((C + 63) / 64) * 8);
+  ix->scan_chunk = 16384;
+  ALLOC(ix->scan_keys, (uint64_t)ix->scan_chunk * SCAN_L_MAX * 8);
+  ALLOC(ix->scan_n, (uint64_t)ix->scan_chunk * 4);
+  ix->dist_cap = std::min<uint64_t>(1ull << 25, std::max<uint64_t>((uint64_t)ix->scan_chunk * c.n_entry, B * 4096));
+  ALLOC(ix->scan_dist, ix->dist_cap * 4);
   {
     size_t bytes = 0;
     if (rocprim::radix_sort_keys(nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr, (size_t)(B * R), 0, 64,
@@ -237,28 +335,28 @@ etale_status etale_insert_batch(etale_t ix, const void* vecs_dev, uint64_t n, ui
   unsigned long long h[C_NCOUNTERS];
   if (etale_status st = read_counters(ix, h)) return st;
   const uint32_t R = ix->cfg.R;
+  if (h[C_N_ENTRIES] != n_entries(ix)) {
+    ix->poisoned = true;
+    return fail(ix, ETALE_ESTATE, "entry-set size on the device disagrees with the live count");
+  }
   if (h[C_FREE_TOP] < n * (uint64_t)(R + 2)) return fail(ix, ETALE_EPOOL, "insert: slab pool cannot cover n*(R+2)");
   const uint32_t first = (uint32_t)ix->next_id;
   const Index& d = ix->dev;
   HIP_TRY(hipMemcpyAsync(ix->x + (size_t)first * ix->cfg.dim, vecs_dev, n * ix->cfg.dim, hipMemcpyDeviceToDevice,
                          ix->stream));
   if (ids_out_dev) HIP_TRY(launch_write_ids(ids_out_dev, first, n, ix->stream));
-  const bool bootstrap = h[C_N_ENTRIES] == 0;
+  const bool bootstrap = ix->live == 0;
   const uint32_t vcap = ix->vcap_build;
 
-  // searches on the graph as it was at the call's start (or the bootstrap)
-  SearchArgs sa{};
-  sa.mode = bootstrap ? MODE_BOOT : MODE_INSERT;
-  sa.first = first;
-  sa.nq = (uint32_t)n;
-  sa.L = bootstrap ? vcap : ix->cfg.L_build;
-  sa.vcap = vcap;
-  sa.vt_mask = ix->cfg.vt_slots - 1;
-  sa.lds_per_wave = search_lds_per_wave(sa.L, ix->cfg.vt_slots);
-  sa.vis_keys = ix->vis_keys;
-  sa.vis_cnt = ix->vis_cnt;
-  const uint32_t swpb = sa.lds_per_wave * ix->cfg.waves_per_block <= 65536u ? ix->cfg.waves_per_block : 1u;
-  HIP_TRY(launch_search(d, sa, swpb, ix->stream));
+  // searches on the graph as it was at the call's start, or the bootstrap:
+  // the visit_cap nearest other members of the batch
+  if (bootstrap) {
+    if (n > 16384) return fail(ix, ETALE_EINVAL, "insert: a bootstrap batch holds at most 16384 vectors");
+    if (etale_status st = run_bootstrap(ix, first, (uint32_t)n, vcap)) return st;
+  } else if (etale_status st = run_searches(ix, MODE_INSERT, nullptr, first, n, 0, ix->cfg.L_build, vcap, nullptr,
+                                            nullptr, nullptr)) {
+    return st;
+  }
 
   // forward neighbors and the node's own slab
   MaintArgs fa = maint_args(ix, vcap);
@@ -290,6 +388,7 @@ etale_status etale_insert_batch(etale_t ix, const void* vecs_dev, uint64_t n, ui
   HIP_TRY(launch_refresh_entries(d, first + (uint32_t)n, ix->cfg.n_entry, ix->stream));
   HIP_TRY(launch_recycle(d, ix->stream));
   ix->next_id += n;
+  ix->live += n;
   return ETALE_OK;
 }
 
@@ -309,6 +408,7 @@ etale_status etale_delete_batch(etale_t ix, const uint32_t* ids_dev, uint64_t n,
   if (!ix->cfg.tombstone_only && h[C_FREE_TOP] < dok * R)
     return fail(ix, ETALE_EPOOL, "delete: slab pool cannot cover the repairs");
   HIP_TRY(launch_tombstone(d, ix->dlist, dok, ix->stream));
+  ix->live -= dok;
   HIP_TRY(launch_refresh_entries(d, (uint32_t)ix->next_id, ix->cfg.n_entry, ix->stream));
   if (!ix->cfg.tombstone_only && dok) {
     MaintArgs pa = maint_args(ix, 2 * R);
@@ -332,20 +432,10 @@ etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint
   if (nq == 0) return ETALE_OK;
   if (!q_dev || !ids_out_dev || !dists_out_dev || nq > 0xFFFFFFFFull)
     return fail(ix, ETALE_EINVAL, "search: null buffer");
-  SearchArgs sa{};
-  sa.mode = MODE_QUERY;
-  sa.q = reinterpret_cast<const uint8_t*>(q_dev);
-  sa.nq = (uint32_t)nq;
-  sa.L = L;
-  sa.k = k;
-  sa.vcap = ix->cfg.visit_mult * L;
-  sa.vt_mask = ix->cfg.vt_slots - 1;
-  sa.lds_per_wave = search_lds_per_wave(L, ix->cfg.vt_slots);
-  sa.out_ids = ids_out_dev;
-  sa.out_d = reinterpret_cast<int32_t*>(dists_out_dev);
-  sa.counts = counts_out_dev;
-  const uint32_t wpb = sa.lds_per_wave * ix->cfg.waves_per_block <= 65536u ? ix->cfg.waves_per_block : 1u;
-  HIP_TRY(launch_search(ix->dev, sa, wpb, ix->stream));
+  if (etale_status st = run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(q_dev), 0, nq, k, L,
+                                     ix->cfg.visit_mult * L, ids_out_dev, reinterpret_cast<int32_t*>(dists_out_dev),
+                                     counts_out_dev))
+    return st;
   return ETALE_OK;
 }
 

@@ -147,35 +147,46 @@ __device__ inline bool vt_insert(uint32_t* vt, uint32_t mask, uint32_t id) {
 }
 
 // ---- the candidate list (sorted keys + expanded flags, double-buffered) --------
+// Each entry also carries the node's reference word, fetched together with
+// its vector when it was scored, so an expansion reads the slab directly and
+// the output filter needs no further load.
 struct CandList {
   uint64_t* k0;
   uint64_t* k1;
+  uint64_t* r0;
+  uint64_t* r1;
   uint8_t* x0;
   uint8_t* x1;
   int cur;
   int n;
   int L;
   uint64_t* acck;  // [64] accepted keys of one merge
+  uint64_t* accr;  // [64] their references
   uint32_t* accp;  // [64] their insertion points
   // the live buffer and the spare one (selects, not indexed arrays, so the
   // pointers stay in registers)
   __device__ uint64_t* keys() const { return cur ? k1 : k0; }
+  __device__ uint64_t* refs() const { return cur ? r1 : r0; }
   __device__ uint8_t* flags() const { return cur ? x1 : x0; }
   __device__ uint64_t* spare_keys() const { return cur ? k0 : k1; }
+  __device__ uint64_t* spare_refs() const { return cur ? r0 : r1; }
   __device__ uint8_t* spare_flags() const { return cur ? x0 : x1; }
 };
 
-// Merge nc <= 64 candidate keys ck[0..nc) (distinct among themselves) into the
-// list, keeping the L smallest and dropping keys already present.
-__device__ inline void list_merge(CandList& cl, const uint64_t* ck, int nc) {
+// Merge nc <= 64 candidates (keys ck, references cr; keys distinct among
+// themselves) into the list, keeping the L smallest keys and dropping keys
+// already present.
+__device__ inline void list_merge(CandList& cl, const uint64_t* ck, const uint64_t* cr, int nc) {
   const int l = lane_id();
   const uint64_t* lk = cl.keys();
+  const uint64_t* lr = cl.refs();
   const uint8_t* lx = cl.flags();
   uint64_t* nk = cl.spare_keys();
+  uint64_t* nr = cl.spare_refs();
   uint8_t* nx = cl.spare_flags();
   const int n = cl.n, L = cl.L;
   bool ok = false;
-  uint64_t key = KEY_NONE;
+  uint64_t key = KEY_NONE, ref = 0;
   uint32_t pos = 0;
   if (l < nc) {
     key = ck[l];
@@ -191,6 +202,7 @@ __device__ inline void list_merge(CandList& cl, const uint64_t* ck, int nc) {
       }
       pos = lo;
       if (pos < (uint32_t)n && lk[pos] == key) ok = false;
+      ref = cr[l];
     }
   }
   const uint64_t m = ballot(ok);
@@ -214,11 +226,13 @@ __device__ inline void list_merge(CandList& cl, const uint64_t* ck, int nc) {
     uint32_t np = (uint32_t)i + s;
     if (np < (uint32_t)L) {
       nk[np] = lk[i];
+      nr[np] = lr[i];
       nx[np] = lx[i];
     }
   }
   if (ok && cpos < (uint32_t)L) {
     nk[cpos] = key;
+    nr[cpos] = ref;
     nx[cpos] = 0;
   }
   wave_sync();
@@ -244,26 +258,34 @@ __device__ inline int list_first_open(const CandList& cl) {
 // Writes ck[i] = (D, id) for ids[0..cnt).
 template <int G>
 __device__ inline void dist_batch_u8(const Index& ix, uint4 qf, uint32_t qq, const uint32_t* ids, int cnt,
-                                     uint64_t* ck) {
+                                     uint64_t* ck, uint64_t* cr = nullptr) {
   constexpr int VPP = 64 / G;
   const int l = lane_id();
   const int c = l % G, grp = l / G;
   for (int base = 0; base < cnt; base += 4 * VPP) {
     uint4 v[4];
     uint32_t id[4];
+    uint64_t r[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       int vi = base + u * VPP + grp;
       id[u] = vi < cnt ? ids[vi] : NONE;
       v[u] = make_uint4(0, 0, 0, 0);
-      if (id[u] != NONE) v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim)[c];
+      r[u] = 0;
+      if (id[u] != NONE) {
+        v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim)[c];
+        if (cr && c == 0) r[u] = load_ref(ix, id[u]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       uint32_t qx = group_sum<G>(dot16(qf, v[u], 0u));
       uint32_t xx = group_sum<G>(dot16(v[u], v[u], 0u));
       int vi = base + u * VPP + grp;
-      if (c == 0 && vi < cnt) ck[vi] = make_key(qq + xx - 2u * qx, id[u]);
+      if (c == 0 && vi < cnt) {
+        ck[vi] = make_key(qq + xx - 2u * qx, id[u]);
+        if (cr) cr[vi] = r[u];
+      }
     }
   }
 }
@@ -347,7 +369,7 @@ struct PruneLds {
   int vstride;
 };
 
-__device__ inline int next_pow2_ge64(int n) {
+__host__ __device__ inline int next_pow2_ge64(int n) {
   int p = 64;
   while (p < n) p <<= 1;
   return p;

@@ -90,24 +90,223 @@ __global__ void __launch_bounds__(1024) k_refresh_entries(Index ix, uint32_t nex
   if (threadIdx.x == 0) ix.ctr[C_N_ENTRIES] = out;
 }
 
-// ---- greedy beam search (queries, insert searches, bootstrap) ----------------------
-// One wavefront per query. LDS per wave: the double-buffered candidate list,
-// one batch of candidate keys/ids, merge scratch and the visited table.
+// ---- start-set scoring: the L best start nodes of every query --------------------------
+// The start set (the entry set, or the batch itself for a bootstrap) is the
+// same for every query of a launch, so scoring it is one dense block of
+// distances: k_scan_dist tiles 64 queries x 256 start rows per workgroup
+// (8 x 8 distances per thread, the byte dimension staged through LDS in
+// 64-byte slices) and writes the distance matrix; k_scan_select then takes,
+// with one wave per query, the exact L smallest (distance, id) keys by a
+// radix select on the distances. Start rows are in ascending id order, so the
+// row index breaks distance ties exactly as the id does.
+constexpr int SD_Q = 64, SD_E = 256, SD_KW = 4, SD_STRIDE = SD_KW + 1;  // in 16-byte words
+constexpr uint32_t D_INVALID = 0xFFFFFFFFu;
+
+__device__ inline uint32_t start_id(const Index& ix, const ScanArgs& a, uint32_t e) {
+  return a.mode == MODE_BOOT ? a.first + e : ix.entries[e];
+}
+
+__global__ void __launch_bounds__(256) k_scan_dist(Index ix, ScanArgs a) {
+  __shared__ uint4 qt[SD_Q * SD_STRIDE];
+  __shared__ uint4 et[SD_E * SD_STRIDE];
+  __shared__ uint32_t qn_s[SD_Q], en_s[SD_E];
+  const int t = (int)threadIdx.x;
+  const uint32_t e0 = blockIdx.x * SD_E, q0 = blockIdx.y * SD_Q;
+  const uint32_t ns = a.ns, dim = ix.dim;
+  const int words = (int)dim / 16;
+  const int qg = t / 32, eg = t % 32;
+  uint32_t acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = 0;
+  uint32_t qn = 0, en = 0;  // norms of query row t (t < 64) and start row t
+  const uint32_t my_e = e0 + (uint32_t)t;
+  const uint32_t my_eid = my_e < ns ? start_id(ix, a, my_e) : NONE;
+  const uint32_t my_q = q0 + (uint32_t)(t & 63);
+  const uint8_t* qrow = nullptr;
+  if (my_q < a.nq)
+    qrow = a.mode == MODE_QUERY ? a.q + (size_t)my_q * dim : ix.x + (size_t)(a.first + a.qoff + my_q) * dim;
+  for (int kw = 0; kw < words; kw += SD_KW) {
+    __syncthreads();
+    // query slice: 64 rows x 4 words, one word per thread
+    {
+      const int r = t & 63, c = t >> 6;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (qrow && kw + c < words) v = reinterpret_cast<const uint4*>(qrow)[kw + c];
+      qt[r * SD_STRIDE + c] = v;
+    }
+    // start slice: 256 rows x 4 words, this thread's own row
+#pragma unroll
+    for (int c = 0; c < SD_KW; ++c) {
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (my_eid != NONE && kw + c < words) v = reinterpret_cast<const uint4*>(ix.x + (size_t)my_eid * dim)[kw + c];
+      et[t * SD_STRIDE + c] = v;
+      en = dot16(v, v, en);
+    }
+    __syncthreads();
+    if (t < 64)
+#pragma unroll
+      for (int c = 0; c < SD_KW; ++c) qn = dot16(qt[t * SD_STRIDE + c], qt[t * SD_STRIDE + c], qn);
+#pragma unroll
+    for (int c = 0; c < SD_KW; ++c) {
+      uint4 qv[8], ev[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) qv[i] = qt[(qg * 8 + i) * SD_STRIDE + c];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ev[j] = et[(eg + 32 * j) * SD_STRIDE + c];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = dot16(qv[i], ev[j], acc[i][j]);
+    }
+  }
+  if (t < 64) qn_s[t] = qn;
+  en_s[t] = en;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t qi = q0 + (uint32_t)(qg * 8 + i);
+    if (qi >= a.nq) continue;
+    const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;  // a bootstrap row never scores itself
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t e = e0 + (uint32_t)(eg + 32 * j);
+      if (e >= ns) continue;
+      const uint32_t d = qn_s[qg * 8 + i] + en_s[eg + 32 * j] - 2u * acc[i][j];
+      a.dist[(size_t)qi * ns + e] = e == self ? D_INVALID : d;
+    }
+  }
+}
+
+// One wave per query: the exact L smallest (distance, row) pairs of its
+// distance row, by a most-significant-digit radix select on the distance
+// (8-bit digits from the highest set bit), then the rows below the threshold
+// plus the first rows (in row order) equal to it, sorted. The row is held in
+// registers (VPL values per lane, row i in lane i % 64, slot i / 64).
+template <int VPL>
+__global__ void __launch_bounds__(256) k_scan_select(Index ix, ScanArgs a, uint32_t sel_cap) {
+  extern __shared__ __align__(16) char smem[];
+  const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (qi >= a.nq) return;
+  const int l = lane_id();
+  uint32_t* hist = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * (1024 + 8 * sel_cap));
+  uint64_t* sel = reinterpret_cast<uint64_t*>(hist + 256);
+  const uint32_t ns = a.ns;
+  const uint32_t* D = a.dist + (size_t)qi * ns;
+  uint32_t v[VPL];
+  uint32_t vmax = 0, nvalid = 0;
+#pragma unroll
+  for (int t = 0; t < VPL; ++t) {
+    const uint32_t i = (uint32_t)(t * 64 + l);
+    v[t] = i < ns ? D[i] : D_INVALID;
+    if (v[t] != D_INVALID) {
+      vmax = max(vmax, v[t]);
+      ++nvalid;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, o, 64));
+    nvalid += (uint32_t)__shfl_xor((int)nvalid, o, 64);
+  }
+  uint32_t need = min(a.L, nvalid);
+  uint32_t prefix = 0, pmask = 0;
+  if (need > 0) {
+    for (int hi = 31 - __clz((int)(vmax | 1u)); hi >= 0; hi -= 8) {
+      const int lo = max(0, hi - 7), width = hi - lo + 1;
+      const uint32_t dmask = (1u << width) - 1u;
+      for (int b = l; b < 256; b += 64) hist[b] = 0;
+      wave_sync();
+#pragma unroll
+      for (int t = 0; t < VPL; ++t)
+        if (v[t] != D_INVALID && (v[t] & pmask) == prefix) atomicAdd(&hist[(v[t] >> lo) & dmask], 1u);
+      wave_sync();
+      // the digit whose cumulative count first reaches `need`
+      uint32_t c0 = hist[4 * l], c1 = hist[4 * l + 1], c2 = hist[4 * l + 2], c3 = hist[4 * l + 3];
+      const uint32_t own = c0 + c1 + c2 + c3;
+      uint32_t incl = own;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (l >= o) incl += u;
+      }
+      const uint32_t excl = incl - own;
+      const bool here = excl < need && incl >= need;
+      uint32_t digit = 0, before = 0;
+      if (here) {
+        uint32_t run = excl;
+        if (run + c0 >= need) {
+          digit = 4 * l;
+        } else if ((run += c0) + c1 >= need) {
+          digit = 4 * l + 1;
+        } else if ((run += c1) + c2 >= need) {
+          digit = 4 * l + 2;
+        } else {
+          run += c2;
+          digit = 4 * l + 3;
+        }
+        before = run;
+      }
+      const uint64_t hm = ballot(here);
+      const int src = (int)__builtin_ctzll(hm);
+      digit = (uint32_t)__shfl((int)digit, src, 64);
+      before = (uint32_t)__shfl((int)before, src, 64);
+      need -= before;
+      prefix |= digit << lo;
+      pmask |= dmask << lo;
+      wave_sync();
+    }
+  }
+  // rows below the threshold, then the first `need` rows equal to it
+  const uint32_t tau = prefix;
+  uint32_t cnt = 0, eq_seen = 0;
+#pragma unroll
+  for (int t = 0; t < VPL; ++t) {
+    const uint32_t i = (uint32_t)(t * 64 + l);
+    const bool lt = v[t] != D_INVALID && v[t] < tau;
+    const bool eq = v[t] != D_INVALID && v[t] == tau;
+    const uint64_t meq = ballot(eq);
+    const bool take = lt || (eq && eq_seen + lanes_below(meq) < need);
+    const uint64_t mt = ballot(take);
+    if (take) sel[cnt + lanes_below(mt)] = make_key(v[t], start_id(ix, a, i));
+    cnt += (uint32_t)__popcll(mt);
+    eq_seen += (uint32_t)__popcll(meq);
+  }
+  const int np = next_pow2_ge64((int)cnt);
+  for (int i = (int)cnt + l; i < np; i += 64) sel[i] = KEY_NONE;
+  wave_sync();
+  wave_bitonic_sort(sel, np);
+  for (uint32_t i = (uint32_t)l; i < cnt; i += 64) a.out_keys[(size_t)qi * a.out_stride + i] = sel[i];
+  if (l == 0) a.out_n[qi] = cnt;
+}
+
+uint32_t scan_select_lds_per_wave(uint32_t L) { return 1024u + 8u * (uint32_t)next_pow2_ge64((int)L); }
+
+// ---- greedy beam search (queries and insert searches) ---------------------------------
+// One wavefront per query, starting from the initial list k_scan left (the L
+// best members of the entry set). Per-wave LDS: the double-buffered candidate
+// list (keys, reference words, expanded flags), one batch of candidates, the
+// merge scratch and the visited table.
 template <int G>
 __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   extern __shared__ __align__(16) char smem[];
   const int wv = (int)(threadIdx.x >> 6);
+  const int nw = (int)(blockDim.x >> 6);
   const int l = lane_id();
-  const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (uint32_t)wv;
+  const uint32_t qi = blockIdx.x * (uint32_t)nw + (uint32_t)wv;
   if (qi >= a.nq) return;
+  const uint32_t dim = ix.dim;
   char* base = smem + (size_t)wv * a.lds_per_wave;
   CandList cl;
   uint64_t* p64 = reinterpret_cast<uint64_t*>(base);
   cl.k0 = p64;
   cl.k1 = p64 + a.L;
-  uint64_t* ck = p64 + 2 * a.L;
-  cl.acck = ck + 64;
-  uint32_t* ci = reinterpret_cast<uint32_t*>(cl.acck + 64);
+  cl.r0 = p64 + 2 * a.L;
+  cl.r1 = p64 + 3 * a.L;
+  uint64_t* ck = p64 + 4 * a.L;
+  uint64_t* cr = ck + 64;
+  cl.acck = cr + 64;
+  cl.accr = cl.acck + 64;
+  uint32_t* ci = reinterpret_cast<uint32_t*>(cl.accr + 64);
   cl.accp = ci + 64;
   uint32_t* vt = cl.accp + 64;
   uint8_t* flags = reinterpret_cast<uint8_t*>(vt + a.vt_mask + 1);
@@ -116,61 +315,36 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   cl.cur = 0;
   cl.n = 0;
   cl.L = (int)a.L;
-
-  const uint8_t* qrow = a.mode == MODE_QUERY ? a.q + (size_t)qi * ix.dim : ix.x + (size_t)(a.first + qi) * ix.dim;
+  const uint8_t* qrow = a.mode == MODE_QUERY ? a.q + (size_t)qi * dim : ix.x + (size_t)(a.first + qi) * dim;
   const uint4 qf = load_frag<G>(qrow);
   const uint32_t qq = group_sum<G>(dot16(qf, qf, 0u));
   for (uint32_t i = (uint32_t)l; i <= a.vt_mask; i += 64) vt[i] = NONE;
-  wave_sync();
-
-  uint32_t ndist = 0;
-  if (a.mode == MODE_BOOT) {
-    // bootstrap: the start set is every other member of the batch
-    const uint32_t self = a.first + qi;
-    for (uint32_t b = 0; b < a.nq; b += 64) {
-      const uint32_t id = b + (uint32_t)l < a.nq ? a.first + b + (uint32_t)l : NONE;
-      const bool ok = id != NONE && id != self;
-      const uint64_t m = ballot(ok);
-      if (ok) ci[lanes_below(m)] = id;
-      const int cnt = __popcll(m);
-      wave_sync();
-      dist_batch_u8<G>(ix, qf, qq, ci, cnt, ck);
-      wave_sync();
-      list_merge(cl, ck, cnt);
-      ndist += (uint32_t)cnt;
-    }
-  } else {
-    // the L best members of the entry set
-    const uint32_t ne = bcast((uint32_t)ix.ctr[C_N_ENTRIES]);
-    for (uint32_t b = 0; b < ne; b += 64) {
-      const int cnt = (int)min(64u, ne - b);
-      if (l < cnt) {
-        const uint32_t id = ix.entries[b + (uint32_t)l];
-        ci[l] = id;
-        vt_insert(vt, a.vt_mask, id);
-      }
-      wave_sync();
-      dist_batch_u8<G>(ix, qf, qq, ci, cnt, ck);
-      wave_sync();
-      list_merge(cl, ck, cnt);
-      ndist += (uint32_t)cnt;
-    }
+  // the initial list: the L best start nodes, with their reference words
+  const uint32_t n0 = a.init_n[qi];
+  for (uint32_t i = (uint32_t)l; i < n0; i += 64) {
+    const uint64_t key = a.init_keys[(size_t)qi * a.init_stride + i];
+    cl.k0[i] = key;
+    cl.r0[i] = load_ref(ix, key_id(key));
+    cl.x0[i] = 0;
   }
-
+  cl.n = (int)n0;
+  wave_sync();
+  for (int i = l; i < cl.n; i += 64) vt_insert(vt, a.vt_mask, key_id(cl.k0[i]));
+  wave_sync();
+  uint32_t ndist = (uint32_t)ix.ctr[C_N_ENTRIES];  // scored by k_scan
   uint32_t nexp = 0;
-  if (a.mode != MODE_BOOT) {
+  {
     const uint32_t R = ix.R;
     while (nexp < a.vcap) {
       const int j = list_first_open(cl);
       if (j < 0) break;
       const uint64_t key = cl.keys()[j];
-      const uint32_t p = key_id(key);
+      const uint64_t r = cl.refs()[j];
       if (l == 0) {
         cl.flags()[j] = 1;
         if (a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp] = key;
       }
       ++nexp;
-      const uint64_t r = bcast64(load_ref(ix, p));
       const uint32_t deg = ref_deg(r), s = ref_slab(r);
       uint32_t nid = NONE;
       if ((uint32_t)l < deg && s != NONE) nid = ix.slabs[(size_t)s * 2u * R + (uint32_t)l];
@@ -180,15 +354,16 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
       const int cnt = __popcll(m);
       wave_sync();
       if (cnt) {
-        dist_batch_u8<G>(ix, qf, qq, ci, cnt, ck);
+        dist_batch_u8<G>(ix, qf, qq, ci, cnt, ck, cr);
         wave_sync();
-        list_merge(cl, ck, cnt);
+        list_merge(cl, ck, cr, cnt);
         ndist += (uint32_t)cnt;
       }
     }
   }
 
   const uint64_t* lk = cl.keys();
+  const uint64_t* lr = cl.refs();
   if (a.mode == MODE_QUERY) {
     // the first k listed nodes whose reference has flag 0
     uint32_t got = 0;
@@ -198,7 +373,7 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
       uint64_t key = 0;
       if (i < cl.n) {
         key = lk[i];
-        live = !ref_del(load_ref(ix, key_id(key)));
+        live = !ref_del(lr[i]);
       }
       const uint64_t m = ballot(live);
       const uint32_t idx = got + lanes_below(m);
@@ -212,10 +387,8 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
       a.out_ids[(size_t)qi * a.k + i] = NONE;
       a.out_d[(size_t)qi * a.k + i] = 0x7FFFFFFF;
     }
-  } else {
-    if (a.mode == MODE_BOOT)
-      for (int i = l; i < cl.n; i += 64) a.vis_keys[(size_t)qi * a.vcap + i] = lk[i];
-    if (l == 0) a.vis_cnt[qi] = a.mode == MODE_BOOT ? (uint32_t)cl.n : nexp;
+  } else if (l == 0) {
+    a.vis_cnt[qi] = nexp;
   }
   if (l == 0) {
     if (a.mode == MODE_QUERY) {
@@ -685,7 +858,31 @@ hipError_t launch_refresh_entries(const Index& ix, uint32_t next_id, uint32_t S,
 }
 
 uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots) {
-  return 16u * L + 1024u + 512u + 4u * vt_slots + ((2u * L + 15u) & ~15u);
+  // keys + refs (double-buffered), candidate keys/refs, merge scratch, ids,
+  // insertion points, visited table, expanded flags
+  return 32u * L + 4u * 512u + 2u * 256u + 4u * vt_slots + ((2u * L + 15u) & ~15u);
+}
+
+hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s) {
+  if (a.nq == 0 || a.ns == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scan_dist, dim3(blocks_for(a.ns, SD_E), blocks_for(a.nq, SD_Q)), dim3(256), 0, s, ix, a);
+  const uint32_t cap = (uint32_t)next_pow2_ge64((int)a.L);
+  const dim3 grid(blocks_for(a.nq, 4)), blk(256);
+  const size_t lds = 4 * scan_select_lds_per_wave(a.L);
+  const uint32_t vpl = (a.ns + 63) / 64;
+  if (vpl <= 16)
+    hipLaunchKernelGGL(k_scan_select<16>, grid, blk, lds, s, ix, a, cap);
+  else if (vpl <= 32)
+    hipLaunchKernelGGL(k_scan_select<32>, grid, blk, lds, s, ix, a, cap);
+  else if (vpl <= 64)
+    hipLaunchKernelGGL(k_scan_select<64>, grid, blk, lds, s, ix, a, cap);
+  else if (vpl <= 128)
+    hipLaunchKernelGGL(k_scan_select<128>, grid, blk, lds, s, ix, a, cap);
+  else if (vpl <= 256)
+    hipLaunchKernelGGL(k_scan_select<256>, grid, blk, lds, s, ix, a, cap);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s) {

@@ -13,16 +13,32 @@ enum SearchMode { MODE_QUERY = 0, MODE_INSERT = 1, MODE_BOOT = 2 };
 enum DelStatus { DEL_OK = 0, DEL_NOT_LIVE = 1, DEL_OUT_OF_RANGE = 2, DEL_DUPLICATE = 3 };
 
 struct SearchArgs {
-  int mode;
-  const uint8_t* q;   // MODE_QUERY: [nq x dim] query rows
-  uint32_t first;     // MODE_INSERT / MODE_BOOT: query i is stored vector first + i
+  int mode;            // MODE_QUERY or MODE_INSERT
+  const uint8_t* q;    // MODE_QUERY: [nq x dim] query rows
+  uint32_t first;      // MODE_INSERT: query i is stored vector first + i
   uint32_t nq, L, k, vcap, vt_mask;
   uint32_t lds_per_wave;
-  uint32_t* out_ids;  // MODE_QUERY: [nq x k]
-  int32_t* out_d;     // MODE_QUERY: [nq x k]
-  uint64_t* vis_keys; // MODE_INSERT / MODE_BOOT: [nq x vcap] candidate keys
-  uint32_t* vis_cnt;  // [nq]
-  uint32_t* counts;   // optional [nq x 2]: expansions, distance evaluations
+  const uint64_t* init_keys;  // [nq x init_stride] initial list from k_scan
+  const uint32_t* init_n;     // [nq]
+  uint32_t init_stride;
+  uint32_t* out_ids;   // MODE_QUERY: [nq x k]
+  int32_t* out_d;      // MODE_QUERY: [nq x k]
+  uint64_t* vis_keys;  // MODE_INSERT: [nq x vcap] expanded keys
+  uint32_t* vis_cnt;   // [nq]
+  uint32_t* counts;    // optional [nq x 2]: expansions, distance evaluations
+};
+
+// k_scan: the L best start nodes (entry set, or the batch for a bootstrap,
+// excluding the query itself) of every query, in (distance, id) order
+struct ScanArgs {
+  int mode;
+  const uint8_t* q;    // MODE_QUERY rows; otherwise query i is stored vector first + qoff + i
+  uint32_t first, qoff, nq, L;  // a bootstrap's start set is stored vectors [first, first + ns)
+  uint32_t ns;         // start-set size (entry count, or the batch size for a bootstrap)
+  uint32_t* dist;      // [nq x ns] scratch distance matrix
+  uint64_t* out_keys;  // [nq x out_stride]
+  uint32_t* out_n;     // [nq]
+  uint32_t out_stride;
 };
 
 struct MaintArgs {
@@ -48,6 +64,8 @@ hipError_t launch_recycle(const Index& ix, hipStream_t s);
 hipError_t launch_write_ids(uint32_t* out, uint32_t first, uint64_t n, hipStream_t s);
 hipError_t launch_refresh_entries(const Index& ix, uint32_t next_id, uint32_t S, hipStream_t s);
 uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots);
+uint32_t scan_select_lds_per_wave(uint32_t L);
+hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s);
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s);
 uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R);
 hipError_t launch_maint(MaintKernel which, const Index& ix, const MaintArgs& a, uint32_t nwaves,
