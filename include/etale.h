@@ -42,7 +42,12 @@
  * describes the last failure.
  *
  * Vectors: ETALE_METRIC_L2_U8 stores dim uint8 per vector (dim a power of two,
- * 16..1024) and uses the exact squared L2 distance in 32-bit integers.
+ * 16..1024) and uses the exact squared L2 distance in 32-bit integers; its
+ * distances are int32. ETALE_METRIC_IP_F32 stores dim FP32 per vector (dim
+ * 96, 192, 384 or 768), uses d = 1 - <a, b> (for unit vectors half the
+ * squared L2 distance), and its distances are float. Neighbor lists, their
+ * stored distances and RobustPrune always use the FP32 rows; only traversal
+ * reads the bf16 / FP8 copy.
  */
 #ifndef ETALE_H
 #define ETALE_H
@@ -66,7 +71,11 @@ enum {
   ETALE_ESTATE = -6
 };
 
-enum { ETALE_METRIC_L2_U8 = 0 };
+enum { ETALE_METRIC_L2_U8 = 0, ETALE_METRIC_IP_F32 = 1 };
+
+/* traversal copy of ETALE_METRIC_IP_F32 rows: FP32 itself, bf16, or FP8
+ * e4m3 with one FP32 scale per row; accumulation is FP32 in every case */
+enum { ETALE_TRAV_NATIVE = 0, ETALE_TRAV_BF16 = 1, ETALE_TRAV_FP8E4M3 = 2 };
 
 /* per-id outcome of etale_delete_batch */
 enum { ETALE_DEL_OK = 0, ETALE_DEL_NOT_LIVE = 1, ETALE_DEL_OUT_OF_RANGE = 2, ETALE_DEL_DUPLICATE = 3 };
@@ -87,7 +96,9 @@ typedef struct {
   uint32_t vt_slots;         /* visited-table slots per search (power of two) */
   uint32_t waves_per_block;  /* search wavefronts per workgroup */
   int32_t metric;            /* ETALE_METRIC_* */
-  int32_t reserved;
+  int32_t traversal;         /* ETALE_TRAV_* (float metric only) */
+  uint32_t rerank_mult;      /* bf16 / FP8 traversal: re-rank rerank_mult*k results in FP32 (k*mult <= 64) */
+  uint32_t reserved;
   uint64_t id_capacity;      /* size of the id space */
   uint64_t slab_capacity;    /* slabs in the pool */
   void* hip_stream;          /* hipStream_t, or NULL */
@@ -137,9 +148,11 @@ etale_status etale_delete_batch(etale_t ix, const uint32_t* ids_dev, uint64_t n,
 
 /* Search nq query rows (q_dev: nq x dim) with candidate-list length L,
  * 1 <= k <= L <= 256. Writes the k best live results per query in (distance,
- * id) order: ids_out_dev (nq x k uint32) and dists_out_dev (nq x k int32),
- * padded with id 0xFFFFFFFF and distance INT32_MAX. counts_out_dev (nq x 2
- * uint32, may be NULL) receives the expansions and distance evaluations. */
+ * id) order: ids_out_dev (nq x k uint32) and dists_out_dev (nq x k int32 or
+ * float), padded with id 0xFFFFFFFF and distance INT32_MAX / +inf. With a
+ * bf16 / FP8 traversal the first rerank_mult*k live candidates are re-scored
+ * from the FP32 rows and the best k returned. counts_out_dev (nq x 2 uint32,
+ * may be NULL) receives the expansions and distance evaluations. */
 etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
                                 uint32_t* ids_out_dev, void* dists_out_dev, uint32_t* counts_out_dev);
 
@@ -148,8 +161,8 @@ etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint
  * nothing changed. A no-op in tombstone-only mode. */
 etale_status etale_reclaim(etale_t ix);
 
-/* Exact k nearest live nodes of each query by (distance, id), 1 <= k <= 16:
- * the plain definition used to measure recall. */
+/* Exact k nearest live nodes of each query by (distance, id), 1 <= k <= 16,
+ * from the uint8 / FP32 rows: the plain definition used to measure recall. */
 etale_status etale_bruteforce(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t* ids_out_dev,
                               void* dists_out_dev);
 
@@ -165,6 +178,21 @@ etale_status etale_export(etale_t ix, uint64_t n_ids, uint32_t* nbr_host, void* 
 /* Entry-set members in ascending id order (up to cap ids); returns the
  * count through *n_out (synchronizes). */
 etale_status etale_get_entries(etale_t ix, uint32_t* ids_host, uint64_t cap, uint64_t* n_out);
+
+/* Install neighbor lists (import): for each of the n ids in ids_host, the
+ * first deg_host[i] (<= R) entries of row i of nbr_host (n x R uint32) become
+ * its list, with distances computed from the stored rows and ordered by
+ * (distance, id); each install is one copy-on-write publication. Every id
+ * must be live and every neighbor must be a handed-out id, else EINVAL with
+ * nothing changed. Synchronizes. */
+etale_status etale_set_lists(etale_t ix, uint64_t n, const uint32_t* ids_host, const uint32_t* nbr_host,
+                             const uint32_t* deg_host);
+
+/* Copy rows [first, first + n) of a stored copy into out_host: which = 0 the
+ * vectors as inserted (uint8 or FP32), 1 the bf16 copy (uint16), 2 the FP8
+ * e4m3 codes (uint8), 3 the FP8 scales (one float per row). EINVAL when that
+ * copy is not kept. Synchronizes. */
+etale_status etale_export_rows(etale_t ix, uint64_t first, uint64_t n, int32_t which, void* out_host);
 
 /* Wait for the index's stream. */
 etale_status etale_sync(etale_t ix);

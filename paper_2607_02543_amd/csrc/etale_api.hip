@@ -17,6 +17,10 @@ struct etale_index {
   hipStream_t stream = nullptr;
   Index dev{};
   uint8_t* x = nullptr;
+  float* xf = nullptr;
+  uint16_t* xb = nullptr;
+  uint8_t* x8 = nullptr;
+  float* xs = nullptr;
   unsigned long long* refs = nullptr;
   uint32_t* slabs = nullptr;
   uint32_t* free_stack = nullptr;
@@ -115,7 +119,7 @@ MaintArgs maint_args(const etale_index* ix, uint32_t nmax) {
   a.nmax = nmax;
   a.nsort = pow2_ge64(nmax);
   a.prune_cap = std::min(ix->cfg.prune_cap, nmax);
-  a.vstride = ix->cfg.dim + 16;
+  a.vstride = ix->cfg.metric == ETALE_METRIC_L2_U8 ? ix->cfg.dim + 16 : 0;  // uint8 rows are staged in LDS
   a.lds_per_wave = maint_lds_per_wave(a, ix->cfg.R);
   return a;
 }
@@ -144,14 +148,14 @@ uint32_t scan_chunk_for(const etale_index* ix, uint32_t ns) {
 
 // start-set scoring, then the beam search, over queries [0, nq) in chunks
 etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t first, uint64_t nq, uint32_t k,
-                          uint32_t L, uint32_t vcap, uint32_t* out_ids, int32_t* out_d, uint32_t* counts) {
+                          uint32_t L, uint32_t vcap, uint32_t* out_ids, uint32_t* out_d, uint32_t* counts) {
   const uint32_t ns = n_entries(ix);
   const uint32_t chunk = scan_chunk_for(ix, ns);
   for (uint64_t c = 0; c < nq; c += chunk) {
     const uint32_t cn = (uint32_t)std::min<uint64_t>(chunk, nq - c);
     ScanArgs sc{};
     sc.mode = mode;
-    sc.q = mode == MODE_QUERY ? q + c * ix->cfg.dim : nullptr;
+    sc.q = mode == MODE_QUERY ? q + c * ix->cfg.dim * (ix->cfg.metric == ETALE_METRIC_L2_U8 ? 1 : 4) : nullptr;
     sc.first = first + (uint32_t)c;
     sc.nq = cn;
     sc.L = L;
@@ -224,8 +228,15 @@ extern "C" {
 etale_status etale_create(const etale_config* cfg, etale_t* out) {
   if (!cfg || !out) return ETALE_EINVAL;
   const etale_config& c = *cfg;
-  if (c.metric != ETALE_METRIC_L2_U8) return ETALE_EINVAL;
-  if (!pow2(c.dim) || c.dim < 16 || c.dim > 1024) return ETALE_EINVAL;
+  if (c.metric == ETALE_METRIC_L2_U8) {
+    if (!pow2(c.dim) || c.dim < 16 || c.dim > 1024) return ETALE_EINVAL;
+  } else if (c.metric == ETALE_METRIC_IP_F32) {
+    if (c.dim != 96 && c.dim != 192 && c.dim != 384 && c.dim != 768) return ETALE_EINVAL;
+    if (c.traversal < ETALE_TRAV_NATIVE || c.traversal > ETALE_TRAV_FP8E4M3) return ETALE_EINVAL;
+    if (c.traversal != ETALE_TRAV_NATIVE && (c.rerank_mult < 1 || c.rerank_mult > 64)) return ETALE_EINVAL;
+  } else {
+    return ETALE_EINVAL;
+  }
   if (c.R < 1 || c.R > 64 || c.L_build < 1 || c.L_build > 256) return ETALE_EINVAL;
   if (c.alpha_num == 0 || c.alpha_den == 0 || c.alpha_num > 1000 || c.alpha_den > 1000) return ETALE_EINVAL;
   if (c.visit_mult < 1 || c.visit_mult * c.L_build > 4096) return ETALE_EINVAL;
@@ -262,7 +273,16 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   };
 #define ALLOC(ptr, bytes)                                          \
   if (dalloc(ix, &(ptr), (bytes)) != hipSuccess) return cleanup(ETALE_ENOMEM, "hipMalloc");
-  ALLOC(ix->x, C * c.dim);
+  if (c.metric == ETALE_METRIC_L2_U8) {
+    ALLOC(ix->x, C * c.dim);
+  } else {
+    ALLOC(ix->xf, C * c.dim * 4);
+    if (c.traversal == ETALE_TRAV_BF16) ALLOC(ix->xb, C * c.dim * 2);
+    if (c.traversal == ETALE_TRAV_FP8E4M3) {
+      ALLOC(ix->x8, C * c.dim);
+      ALLOC(ix->xs, C * 4);
+    }
+  }
   ALLOC(ix->refs, C * 8);
   ALLOC(ix->slabs, P * 2 * R * 4);
   ALLOC(ix->free_stack, P * 4);
@@ -298,9 +318,16 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   d.b2 = c.alpha_den * c.alpha_den;
   d.publish_attempts = c.publish_attempts;
   d.prune_cap = c.prune_cap;
+  d.metric = c.metric;
+  d.trav = c.metric == ETALE_METRIC_IP_F32 ? c.traversal : 0;
+  d.rerank = c.rerank_mult;
   d.cap = C;
   d.P = P;
   d.x = ix->x;
+  d.xf = ix->xf;
+  d.xb = ix->xb;
+  d.x8 = ix->x8;
+  d.xs = ix->xs;
   d.refs = ix->refs;
   d.slabs = ix->slabs;
   d.free_stack = ix->free_stack;
@@ -342,8 +369,14 @@ etale_status etale_insert_batch(etale_t ix, const void* vecs_dev, uint64_t n, ui
   if (h[C_FREE_TOP] < n * (uint64_t)(R + 2)) return fail(ix, ETALE_EPOOL, "insert: slab pool cannot cover n*(R+2)");
   const uint32_t first = (uint32_t)ix->next_id;
   const Index& d = ix->dev;
-  HIP_TRY(hipMemcpyAsync(ix->x + (size_t)first * ix->cfg.dim, vecs_dev, n * ix->cfg.dim, hipMemcpyDeviceToDevice,
-                         ix->stream));
+  if (ix->cfg.metric == ETALE_METRIC_L2_U8) {
+    HIP_TRY(hipMemcpyAsync(ix->x + (size_t)first * ix->cfg.dim, vecs_dev, n * ix->cfg.dim, hipMemcpyDeviceToDevice,
+                           ix->stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(ix->xf + (size_t)first * ix->cfg.dim, vecs_dev, n * ix->cfg.dim * 4,
+                           hipMemcpyDeviceToDevice, ix->stream));
+    HIP_TRY(launch_encode(d, first, (uint32_t)n, ix->xs, ix->xb, ix->x8, ix->stream));
+  }
   if (ids_out_dev) HIP_TRY(launch_write_ids(ids_out_dev, first, n, ix->stream));
   const bool bootstrap = ix->live == 0;
   const uint32_t vcap = ix->vcap_build;
@@ -432,8 +465,11 @@ etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint
   if (nq == 0) return ETALE_OK;
   if (!q_dev || !ids_out_dev || !dists_out_dev || nq > 0xFFFFFFFFull)
     return fail(ix, ETALE_EINVAL, "search: null buffer");
+  if (ix->cfg.metric == ETALE_METRIC_IP_F32 && ix->cfg.traversal != ETALE_TRAV_NATIVE &&
+      (uint64_t)ix->cfg.rerank_mult * k > 64)
+    return fail(ix, ETALE_EINVAL, "search: rerank_mult * k must not exceed 64");
   if (etale_status st = run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(q_dev), 0, nq, k, L,
-                                     ix->cfg.visit_mult * L, ids_out_dev, reinterpret_cast<int32_t*>(dists_out_dev),
+                                     ix->cfg.visit_mult * L, ids_out_dev, reinterpret_cast<uint32_t*>(dists_out_dev),
                                      counts_out_dev))
     return st;
   return ETALE_OK;
@@ -465,8 +501,8 @@ etale_status etale_bruteforce(etale_t ix, const void* q_dev, uint64_t nq, uint32
   if (k < 1 || k > 16 || nq > 0xFFFFFFFFull) return fail(ix, ETALE_EINVAL, "bruteforce: need 1 <= k <= 16");
   if (nq == 0) return ETALE_OK;
   if (!q_dev || !ids_out_dev || !dists_out_dev) return fail(ix, ETALE_EINVAL, "bruteforce: null buffer");
-  HIP_TRY(launch_bruteforce(ix->dev, reinterpret_cast<const uint8_t*>(q_dev), (uint32_t)nq, ix->next_id, k,
-                            ids_out_dev, reinterpret_cast<int32_t*>(dists_out_dev), ix->stream));
+  HIP_TRY(launch_bruteforce(ix->dev, q_dev, (uint32_t)nq, ix->next_id, k, ids_out_dev,
+                            reinterpret_cast<uint32_t*>(dists_out_dev), ix->stream));
   return ETALE_OK;
 }
 
@@ -538,6 +574,76 @@ etale_status etale_get_entries(etale_t ix, uint32_t* ids_host, uint64_t cap, uin
     HIP_TRY(hipStreamSynchronize(ix->stream));
   }
   *n_out = h[C_N_ENTRIES];
+  return ETALE_OK;
+}
+
+etale_status etale_set_lists(etale_t ix, uint64_t n, const uint32_t* ids_host, const uint32_t* nbr_host,
+                             const uint32_t* deg_host) {
+  CHECK_HANDLE();
+  if (n == 0) return ETALE_OK;
+  if (!ids_host || !nbr_host || !deg_host) return fail(ix, ETALE_EINVAL, "set_lists: null buffer");
+  const uint32_t R = ix->cfg.R;
+  std::vector<uint8_t> seen(ix->next_id, 0);
+  for (uint64_t i = 0; i < n; ++i) {
+    if (ids_host[i] >= ix->next_id || deg_host[i] > R || seen[ids_host[i]])
+      return fail(ix, ETALE_EINVAL, "set_lists: bad id, repeated id or degree");
+    seen[ids_host[i]] = 1;
+    for (uint32_t j = 0; j < deg_host[i]; ++j) {
+      const uint32_t v = nbr_host[i * R + j];
+      if (v >= ix->next_id || v == ids_host[i]) return fail(ix, ETALE_EINVAL, "set_lists: bad neighbor");
+      for (uint32_t t = 0; t < j; ++t)
+        if (nbr_host[i * R + t] == v) return fail(ix, ETALE_EINVAL, "set_lists: repeated neighbor");
+    }
+  }
+  unsigned long long h[C_NCOUNTERS];
+  if (etale_status st = read_counters(ix, h)) return st;
+  if (h[C_FREE_TOP] < n) return fail(ix, ETALE_EPOOL, "set_lists: slab pool cannot cover n publications");
+  // every listed id must be live
+  std::vector<unsigned long long> refs(ix->next_id);
+  HIP_TRY(hipMemcpyAsync(refs.data(), ix->refs, ix->next_id * 8, hipMemcpyDeviceToHost, ix->stream));
+  HIP_TRY(hipStreamSynchronize(ix->stream));
+  for (uint64_t i = 0; i < n; ++i)
+    if (ref_del(refs[ids_host[i]])) return fail(ix, ETALE_EINVAL, "set_lists: id not live");
+  uint32_t *d_ids = nullptr, *d_nbr = nullptr, *d_deg = nullptr;
+  HIP_TRY(hipMalloc(&d_ids, n * 4));
+  HIP_TRY(hipMalloc(&d_nbr, n * R * 4));
+  HIP_TRY(hipMalloc(&d_deg, n * 4));
+  hipError_t e = hipMemcpy(d_ids, ids_host, n * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_nbr, nbr_host, n * R * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_deg, deg_host, n * 4, hipMemcpyHostToDevice);
+  MaintArgs a = maint_args(ix, R + 1);
+  a.n = (uint32_t)n;
+  if (e == hipSuccess) e = launch_set_lists(ix->dev, a, d_ids, d_nbr, d_deg, ix->stream);
+  if (e == hipSuccess) e = launch_recycle(ix->dev, ix->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ix->stream);
+  (void)hipFree(d_ids);
+  (void)hipFree(d_nbr);
+  (void)hipFree(d_deg);
+  HIP_TRY(e);
+  return ETALE_OK;
+}
+
+etale_status etale_export_rows(etale_t ix, uint64_t first, uint64_t n, int32_t which, void* out_host) {
+  CHECK_HANDLE();
+  if (!out_host || first + n > ix->next_id) return fail(ix, ETALE_EINVAL, "export_rows: range");
+  const uint64_t dim = ix->cfg.dim;
+  const void* src = nullptr;
+  uint64_t row_bytes = 0;
+  switch (which) {
+    case 0:
+      src = ix->cfg.metric == ETALE_METRIC_L2_U8 ? (const void*)ix->x : (const void*)ix->xf;
+      row_bytes = ix->cfg.metric == ETALE_METRIC_L2_U8 ? dim : dim * 4;
+      break;
+    case 1: src = ix->xb; row_bytes = dim * 2; break;
+    case 2: src = ix->x8; row_bytes = dim; break;
+    case 3: src = ix->xs; row_bytes = 4; break;
+    default: break;
+  }
+  if (!src) return fail(ix, ETALE_EINVAL, "export_rows: copy not kept");
+  if (n == 0) return ETALE_OK;
+  HIP_TRY(hipMemcpyAsync(out_host, (const uint8_t*)src + first * row_bytes, n * row_bytes, hipMemcpyDeviceToHost,
+                         ix->stream));
+  HIP_TRY(hipStreamSynchronize(ix->stream));
   return ETALE_OK;
 }
 

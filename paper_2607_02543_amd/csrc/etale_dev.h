@@ -62,8 +62,15 @@ struct Index {
   uint32_t a2, b2;  // alpha = a/b, applied squared: a^2 * D1 <= b^2 * D2
   uint32_t publish_attempts;
   uint32_t prune_cap;
+  int32_t metric;   // 0: uint8 squared L2, 1: FP32 inner product (d = 1 - <a,b>)
+  int32_t trav;     // traversal copy for the float metric: 0 FP32, 1 bf16, 2 FP8 e4m3 + scale
+  uint32_t rerank;  // float metric, non-FP32 traversal: results re-ranked from rerank*k candidates
   uint64_t cap, P;
-  const uint8_t* x;
+  const uint8_t* x;     // uint8 rows
+  const float* xf;      // FP32 rows (float metric)
+  const uint16_t* xb;   // bf16 rows (bf16 traversal)
+  const uint8_t* x8;    // e4m3 rows (FP8 traversal)
+  const float* xs;      // per-row FP8 scale
   unsigned long long* refs;
   uint32_t* slabs;
   uint32_t* free_stack;
@@ -360,10 +367,12 @@ __device__ inline bool publish(const Index& ix, uint32_t u, const uint32_t* ids,
 struct PruneLds {
   uint64_t* keys;   // [nsort]
   uint64_t* keys2;  // [rows] survivors in order
-  uint8_t* vec;     // [prune_cap * vstride] staged candidate vectors
-  uint32_t* norm;   // [prune_cap]
+  uint8_t* vec;     // [rows * vstride] staged candidate vectors (uint8 rows)
+  uint32_t* norm;   // [rows]
+  uint32_t* idx;    // [rows] alive-candidate list (FP32 rows)
+  uint8_t* kill;    // [rows] per-candidate prune flags (FP32 rows)
   uint32_t* out_ids;  // [R]
-  uint32_t* out_d;    // [R]
+  uint32_t* out_d;    // [R] stored distances (uint32 for uint8 rows, FP32 bits for float)
   int nsort;
   int rows;  // staging rows: keys2, vec and norm hold this many candidates
   int vstride;

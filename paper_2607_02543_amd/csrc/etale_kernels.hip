@@ -5,6 +5,7 @@
 // is owned by exactly one wavefront, so the reference CAS of a publication is
 // uncontended and the phase result does not depend on scheduling.
 #include "etale_dev.h"
+#include "etale_float.h"
 #include "etale_launch.h"
 
 namespace etale {
@@ -126,7 +127,8 @@ __global__ void __launch_bounds__(256) k_scan_dist(Index ix, ScanArgs a) {
   const uint32_t my_q = q0 + (uint32_t)(t & 63);
   const uint8_t* qrow = nullptr;
   if (my_q < a.nq)
-    qrow = a.mode == MODE_QUERY ? a.q + (size_t)my_q * dim : ix.x + (size_t)(a.first + a.qoff + my_q) * dim;
+    qrow = a.mode == MODE_QUERY ? (const uint8_t*)a.q + (size_t)my_q * dim
+                                : ix.x + (size_t)(a.first + a.qoff + my_q) * dim;
   for (int kw = 0; kw < words; kw += SD_KW) {
     __syncthreads();
     // query slice: 64 rows x 4 words, one word per thread
@@ -175,6 +177,105 @@ __global__ void __launch_bounds__(256) k_scan_dist(Index ix, ScanArgs a) {
       if (e >= ns) continue;
       const uint32_t d = qn_s[qg * 8 + i] + en_s[eg + 32 * j] - 2u * acc[i][j];
       a.dist[(size_t)qi * ns + e] = e == self ? D_INVALID : d;
+    }
+  }
+}
+
+// Float rows: the same 64 x 256 tiling over 16-element slices, in FP32; start
+// rows come from the traversal copy (FP8 rows as value/256, their scale
+// applied once per pair at the end).
+template <int TRAV>
+__global__ void __launch_bounds__(256) k_scan_dist_f(Index ix, ScanArgs a) {
+  __shared__ float4 qt[SD_Q * SD_STRIDE];
+  __shared__ float4 et[SD_E * SD_STRIDE];
+  __shared__ float es[SD_E];
+  const int t = (int)threadIdx.x;
+  const uint32_t e0 = blockIdx.x * SD_E, q0 = blockIdx.y * SD_Q;
+  const uint32_t ns = a.ns, dim = ix.dim;
+  const int qg = t / 32, eg = t % 32;
+  float acc[8][8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[i][j] = 0.f;
+  const uint32_t my_e = e0 + (uint32_t)t;
+  const uint32_t my_eid = my_e < ns ? start_id(ix, a, my_e) : NONE;
+  es[t] = (TRAV == TRAV_FP8 && my_eid != NONE) ? ix.xs[my_eid] * 256.0f : 1.0f;
+  const uint32_t my_q = q0 + (uint32_t)(t & 63);
+  const float* qrow = nullptr;
+  if (my_q < a.nq)
+    qrow = a.mode == MODE_QUERY ? (const float*)a.q + (size_t)my_q * dim : ix.xf + (size_t)(a.first + a.qoff + my_q) * dim;
+  for (uint32_t k0 = 0; k0 < dim; k0 += 16) {
+    __syncthreads();
+    {
+      const int r = t & 63, c = t >> 6;
+      qt[r * SD_STRIDE + c] = qrow ? reinterpret_cast<const float4*>(qrow + k0)[c] : make_float4(0, 0, 0, 0);
+    }
+    float4 ev4[4] = {make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0), make_float4(0, 0, 0, 0),
+                     make_float4(0, 0, 0, 0)};
+    if (my_eid != NONE) {
+      if (TRAV == TRAV_NATIVE) {
+        const float4* rw = reinterpret_cast<const float4*>(ix.xf + (size_t)my_eid * dim + k0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ev4[c] = rw[c];
+      } else if (TRAV == TRAV_BF16) {
+        const uint4* rw = reinterpret_cast<const uint4*>(ix.xb + (size_t)my_eid * dim + k0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint4 w = rw[h];
+          const uint32_t wd[4] = {w.x, w.y, w.z, w.w};
+          float f[8];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            f[2 * e] = __builtin_bit_cast(float, wd[e] << 16);
+            f[2 * e + 1] = __builtin_bit_cast(float, wd[e] & 0xFFFF0000u);
+          }
+          ev4[2 * h] = make_float4(f[0], f[1], f[2], f[3]);
+          ev4[2 * h + 1] = make_float4(f[4], f[5], f[6], f[7]);
+        }
+      } else {
+        const uint4 w = *reinterpret_cast<const uint4*>(ix.x8 + (size_t)my_eid * dim + k0);
+        const uint32_t wd[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          ev4[e] = make_float4(e4m3_div256(wd[e] & 0xFFu), e4m3_div256((wd[e] >> 8) & 0xFFu),
+                               e4m3_div256((wd[e] >> 16) & 0xFFu), e4m3_div256(wd[e] >> 24));
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) et[t * SD_STRIDE + c] = ev4[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float4 qv[8], ev[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) qv[i] = qt[(qg * 8 + i) * SD_STRIDE + c];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ev[j] = et[(eg + 32 * j) * SD_STRIDE + c];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          float x = acc[i][j];
+          x = __builtin_fmaf(qv[i].x, ev[j].x, x);
+          x = __builtin_fmaf(qv[i].y, ev[j].y, x);
+          x = __builtin_fmaf(qv[i].z, ev[j].z, x);
+          acc[i][j] = __builtin_fmaf(qv[i].w, ev[j].w, x);
+        }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t qi = q0 + (uint32_t)(qg * 8 + i);
+    if (qi >= a.nq) continue;
+    const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t e = e0 + (uint32_t)(eg + 32 * j);
+      if (e >= ns) continue;
+      const float d = 1.0f - es[eg + 32 * j] * acc[i][j];
+      a.dist[(size_t)qi * ns + e] = e == self ? D_INVALID : fkey(d);
     }
   }
 }
@@ -281,12 +382,57 @@ __global__ void __launch_bounds__(256) k_scan_select(Index ix, ScanArgs a, uint3
 
 uint32_t scan_select_lds_per_wave(uint32_t L) { return 1024u + 8u * (uint32_t)next_pow2_ge64((int)L); }
 
-// ---- greedy beam search (queries and insert searches) ---------------------------------
-// One wavefront per query, starting from the initial list k_scan left (the L
-// best members of the entry set). Per-wave LDS: the double-buffered candidate
-// list (keys, reference words, expanded flags), one batch of candidates, the
-// merge scratch and the visited table.
+// ---- traversal policies ------------------------------------------------------------
+// uint8 rows: G = dim/16 lanes per row, one 16-byte chunk each
 template <int G>
+struct TravU8 {
+  static constexpr bool FLOAT = false;
+  struct Q {
+    uint4 f;
+    uint32_t qq;
+  };
+  __device__ static Q load_query(const void* row) {
+    Q q;
+    q.f = load_frag<G>(reinterpret_cast<const uint8_t*>(row));
+    q.qq = group_sum<G>(dot16(q.f, q.f, 0u));
+    return q;
+  }
+  __device__ static const void* stored_row(const Index& ix, uint32_t id) { return ix.x + (size_t)id * ix.dim; }
+  __device__ static size_t query_bytes(const Index& ix) { return ix.dim; }
+  __device__ static void dist_batch(const Index& ix, const Q& q, const uint32_t* ids, int cnt, uint64_t* ck,
+                                    uint64_t* cr) {
+    dist_batch_u8<G>(ix, q.f, q.qq, ids, cnt, ck, cr);
+  }
+  __device__ static uint32_t out_bits(uint32_t kd) { return kd; }            // int32 distance
+  __device__ static uint32_t pad_bits() { return 0x7FFFFFFFu; }              // INT32_MAX
+};
+
+// float rows: traversal copy TRAV, G lanes per row; FP32 re-rank for non-FP32 copies
+template <int G, int TRAV>
+struct TravFloat {
+  static constexpr bool FLOAT = true;
+  static constexpr int MODE = TRAV;
+  using T = TravF<G, TRAV>;
+  using Q = typename T::Q;
+  static constexpr int GF = G * T::EPC / 4;  // lanes per row of the FP32 copy
+  using Exact = TravF<GF, TRAV_NATIVE>;
+  __device__ static Q load_query(const void* row) { return T::load_query(reinterpret_cast<const float*>(row)); }
+  __device__ static const void* stored_row(const Index& ix, uint32_t id) { return ix.xf + (size_t)id * ix.dim; }
+  __device__ static size_t query_bytes(const Index& ix) { return (size_t)ix.dim * 4; }
+  __device__ static void dist_batch(const Index& ix, const Q& q, const uint32_t* ids, int cnt, uint64_t* ck,
+                                    uint64_t* cr) {
+    T::dist_batch(ix, q, ids, cnt, ck, cr);
+  }
+  __device__ static uint32_t out_bits(uint32_t kd) { return __builtin_bit_cast(uint32_t, fkey_inv(kd)); }
+  __device__ static uint32_t pad_bits() { return 0x7F800000u; }              // +inf
+};
+
+// ---- greedy beam search (queries and insert searches) ---------------------------------
+// One wavefront per query, starting from the initial list the start-set scan
+// left (the L best members of the entry set). Per-wave LDS: the
+// double-buffered candidate list (keys, reference words, expanded flags), one
+// batch of candidates, the merge scratch and the visited table.
+template <class TP>
 __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   extern __shared__ __align__(16) char smem[];
   const int wv = (int)(threadIdx.x >> 6);
@@ -294,7 +440,6 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   const int l = lane_id();
   const uint32_t qi = blockIdx.x * (uint32_t)nw + (uint32_t)wv;
   if (qi >= a.nq) return;
-  const uint32_t dim = ix.dim;
   char* base = smem + (size_t)wv * a.lds_per_wave;
   CandList cl;
   uint64_t* p64 = reinterpret_cast<uint64_t*>(base);
@@ -315,9 +460,9 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   cl.cur = 0;
   cl.n = 0;
   cl.L = (int)a.L;
-  const uint8_t* qrow = a.mode == MODE_QUERY ? a.q + (size_t)qi * dim : ix.x + (size_t)(a.first + qi) * dim;
-  const uint4 qf = load_frag<G>(qrow);
-  const uint32_t qq = group_sum<G>(dot16(qf, qf, 0u));
+  const void* qrow = a.mode == MODE_QUERY ? (const void*)((const uint8_t*)a.q + (size_t)qi * TP::query_bytes(ix))
+                                          : TP::stored_row(ix, a.first + qi);
+  const typename TP::Q qv = TP::load_query(qrow);
   for (uint32_t i = (uint32_t)l; i <= a.vt_mask; i += 64) vt[i] = NONE;
   // the initial list: the L best start nodes, with their reference words
   const uint32_t n0 = a.init_n[qi];
@@ -331,7 +476,7 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   wave_sync();
   for (int i = l; i < cl.n; i += 64) vt_insert(vt, a.vt_mask, key_id(cl.k0[i]));
   wave_sync();
-  uint32_t ndist = (uint32_t)ix.ctr[C_N_ENTRIES];  // scored by k_scan
+  uint32_t ndist = (uint32_t)ix.ctr[C_N_ENTRIES];  // scored by the start-set scan
   uint32_t nexp = 0;
   {
     const uint32_t R = ix.R;
@@ -354,7 +499,7 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
       const int cnt = __popcll(m);
       wave_sync();
       if (cnt) {
-        dist_batch_u8<G>(ix, qf, qq, ci, cnt, ck, cr);
+        TP::dist_batch(ix, qv, ci, cnt, ck, cr);
         wave_sync();
         list_merge(cl, ck, cr, cnt);
         ndist += (uint32_t)cnt;
@@ -365,9 +510,14 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   const uint64_t* lk = cl.keys();
   const uint64_t* lr = cl.refs();
   if (a.mode == MODE_QUERY) {
-    // the first k listed nodes whose reference has flag 0
+    // the first `want` listed nodes whose reference has flag 0: k of them, or
+    // rerank*k for a bf16 / FP8 traversal, which are then re-scored from the
+    // FP32 rows and cut to k
+    bool rerank = false;
+    if constexpr (TP::FLOAT) rerank = TP::MODE != TRAV_NATIVE;
+    const uint32_t want = rerank ? min(64u, ix.rerank * a.k) : a.k;
     uint32_t got = 0;
-    for (int b = 0; b < cl.n && got < a.k; b += 64) {
+    for (int b = 0; b < cl.n && got < want; b += 64) {
       const int i = b + l;
       bool live = false;
       uint64_t key = 0;
@@ -377,15 +527,35 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
       }
       const uint64_t m = ballot(live);
       const uint32_t idx = got + lanes_below(m);
-      if (live && idx < a.k) {
-        a.out_ids[(size_t)qi * a.k + idx] = key_id(key);
-        a.out_d[(size_t)qi * a.k + idx] = (int32_t)key_dist(key);
+      if (live && idx < want) {
+        if (rerank) {
+          ci[idx] = key_id(key);
+        } else {
+          a.out_ids[(size_t)qi * a.k + idx] = key_id(key);
+          a.out_d[(size_t)qi * a.k + idx] = TP::out_bits(key_dist(key));
+        }
       }
       got += (uint32_t)__popcll(m);
     }
-    for (uint32_t i = min(got, a.k) + (uint32_t)l; i < a.k; i += 64) {
+    got = min(got, want);
+    if constexpr (TP::FLOAT) {
+      if (rerank) {
+        wave_sync();
+        using E = typename TP::Exact;
+        E::dist_batch(ix, E::load_query(reinterpret_cast<const float*>(qrow)), ci, (int)got, ck, nullptr);
+        for (int i = (int)got + l; i < 64; i += 64) ck[i] = KEY_NONE;
+        wave_sync();
+        wave_bitonic_sort(ck, 64);
+        got = min(got, a.k);
+        for (uint32_t i = (uint32_t)l; i < got; i += 64) {
+          a.out_ids[(size_t)qi * a.k + i] = key_id(ck[i]);
+          a.out_d[(size_t)qi * a.k + i] = TP::out_bits(key_dist(ck[i]));
+        }
+      }
+    }
+    for (uint32_t i = got + (uint32_t)l; i < a.k; i += 64) {
       a.out_ids[(size_t)qi * a.k + i] = NONE;
-      a.out_d[(size_t)qi * a.k + i] = 0x7FFFFFFF;
+      a.out_d[(size_t)qi * a.k + i] = TP::pad_bits();
     }
   } else if (l == 0) {
     a.vis_cnt[qi] = nexp;
@@ -425,6 +595,8 @@ __device__ inline MaintLds carve(char* base, const MaintArgs& a, uint32_t R) {
   p += (size_t)a.prune_cap * a.vstride;
   m.pr.norm = reinterpret_cast<uint32_t*>(p);
   p += (size_t)a.prune_cap * 4;
+  m.pr.idx = reinterpret_cast<uint32_t*>(p);
+  p += (size_t)a.prune_cap * 4;
   m.pr.out_ids = reinterpret_cast<uint32_t*>(p);
   p += (size_t)(R + 1) * 4;
   m.pr.out_d = reinterpret_cast<uint32_t*>(p);
@@ -436,6 +608,8 @@ __device__ inline MaintLds carve(char* base, const MaintArgs& a, uint32_t R) {
   m.nl_d = reinterpret_cast<uint32_t*>(p);
   p += (size_t)(R + 1) * 4;
   m.tmp = reinterpret_cast<uint32_t*>(p);
+  p += (size_t)(R + 1) * 4;
+  m.pr.kill = reinterpret_cast<uint8_t*>(p);
   return m;
 }
 
@@ -466,8 +640,40 @@ __device__ inline void copy_out(const MaintLds& m, uint32_t n) {
   wave_sync();
 }
 
-// ---- insert: forward prune + own publication (Algorithm 2, first lines) --------------
+// ---- per-metric maintenance policy --------------------------------------------------------
+// prune: RobustPrune; dist1: the exact stored distance between two rows (the
+// bit pattern kept in a slab); kd: a stored distance as the distance half of a
+// (distance, id) key.
 template <int G>
+struct MaintU8 {
+  __device__ static int prune(const Index& ix, uint32_t p, const uint32_t* cand, int n, PruneLds& s) {
+    return robust_prune_u8<G>(ix, p, cand, n, s);
+  }
+  __device__ static uint32_t dist1(const Index& ix, uint32_t w, uint32_t v, uint32_t* tmp, uint64_t* ck) {
+    const uint4 wf = load_frag<G>(ix.x + (size_t)w * ix.dim);
+    const uint32_t ww = group_sum<G>(dot16(wf, wf, 0u));
+    if (lane_id() == 0) tmp[0] = v;
+    wave_sync();
+    dist_batch_u8<G>(ix, wf, ww, tmp, 1, ck);
+    wave_sync();
+    return key_dist(ck[0]);
+  }
+  __device__ static uint32_t kd(uint32_t rho) { return rho; }
+};
+
+template <int G>
+struct MaintF32 {
+  __device__ static int prune(const Index& ix, uint32_t p, const uint32_t* cand, int n, PruneLds& s) {
+    return robust_prune_f32<G>(ix, p, cand, n, s);
+  }
+  __device__ static uint32_t dist1(const Index& ix, uint32_t w, uint32_t v, uint32_t*, uint64_t*) {
+    return dist1_f32<G>(ix, w, v);
+  }
+  __device__ static uint32_t kd(uint32_t rho) { return fkey(__builtin_bit_cast(float, rho)); }
+};
+
+// ---- insert: forward prune + own publication (Algorithm 2, first lines) --------------
+template <class P>
 __global__ void __launch_bounds__(256) k_forward(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   const uint32_t qi = wave_index();
@@ -478,7 +684,7 @@ __global__ void __launch_bounds__(256) k_forward(Index ix, MaintArgs a) {
   const uint32_t nc = a.vis_cnt[qi];
   for (uint32_t j = (uint32_t)l; j < nc; j += 64) m.cand[j] = key_id(a.vis_keys[(size_t)qi * a.vcap + j]);
   wave_sync();
-  const int cnt = robust_prune_u8<G>(ix, v, m.cand, (int)nc, m.pr);
+  const int cnt = P::prune(ix, v, m.cand, (int)nc, m.pr);
   publish(ix, v, m.pr.out_ids, m.pr.out_d, (uint32_t)cnt, C_PUB_FORWARD);
   for (uint32_t j = (uint32_t)l; j < ix.R; j += 64) a.F[(size_t)qi * ix.R + j] = j < (uint32_t)cnt ? m.pr.out_ids[j] : NONE;
 }
@@ -501,7 +707,7 @@ __device__ inline bool owns_segment(const MaintArgs& a, uint32_t t, uint32_t* ta
 }
 
 // ---- insert: reverse edges in (target, source) order, one publication per target ------
-template <int G>
+template <class P>
 __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   const uint32_t t = wave_index();
@@ -511,20 +717,15 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
   const int l = lane_id();
   const uint32_t R = ix.R;
   uint32_t n = load_list(ix, w, m.nl_id, m.nl_d);
-  const uint4 wf = load_frag<G>(ix.x + (size_t)w * ix.dim);
-  const uint32_t ww = group_sum<G>(dot16(wf, wf, 0u));
   uint64_t* ck = m.pr.keys;  // scratch for one distance
   for (uint32_t u = t; u < a.npairs && a.pairs[u] != KEY_NONE && (uint32_t)(a.pairs[u] >> 32) == w; ++u) {
     const uint32_t v = (uint32_t)a.pairs[u];
     const bool present = ballot((uint32_t)l < n && m.nl_id[l] == v) != 0ull;
     if (present) continue;  // a set union: nothing to add
     if (n < R) {
-      if (l == 0) m.tmp[0] = v;
-      wave_sync();
-      dist_batch_u8<G>(ix, wf, ww, m.tmp, 1, ck);
-      wave_sync();
-      const uint64_t kv = make_key(key_dist(ck[0]), v);
-      const bool before = (uint32_t)l < n && make_key(m.nl_d[l], m.nl_id[l]) < kv;
+      const uint32_t rho = P::dist1(ix, w, v, m.tmp, ck);
+      const uint64_t kv = make_key(P::kd(rho), v);
+      const bool before = (uint32_t)l < n && make_key(P::kd(m.nl_d[l]), m.nl_id[l]) < kv;
       const uint32_t pos = (uint32_t)__popcll(ballot(before));
       uint32_t id_l = 0, d_l = 0;
       if ((uint32_t)l < n) {
@@ -538,7 +739,7 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
       }
       if (l == 0) {
         m.nl_id[pos] = v;
-        m.nl_d[pos] = key_dist(kv);
+        m.nl_d[pos] = rho;
       }
       wave_sync();
       ++n;
@@ -546,7 +747,7 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
       if ((uint32_t)l < n) m.cand[l] = m.nl_id[l];
       if (l == 0) m.cand[n] = v;
       wave_sync();
-      n = (uint32_t)robust_prune_u8<G>(ix, w, m.cand, (int)n + 1, m.pr);
+      n = (uint32_t)P::prune(ix, w, m.cand, (int)n + 1, m.pr);
       copy_out(m, n);
     }
   }
@@ -554,7 +755,7 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
 }
 
 // ---- insert: refine -- same-batch nodes two hops away are offered ----------------------
-template <int G>
+template <class P>
 __global__ void __launch_bounds__(256) k_refine(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   const uint32_t qi = wave_index();
@@ -579,9 +780,49 @@ __global__ void __launch_bounds__(256) k_refine(Index ix, MaintArgs a) {
   }
   wave_sync();
   if (nc == own) return;  // no same-batch node within two hops
-  const int cnt = robust_prune_u8<G>(ix, v, m.cand, (int)nc, m.pr);
+  const int cnt = P::prune(ix, v, m.cand, (int)nc, m.pr);
   const bool diff = (uint32_t)cnt != own || ballot((uint32_t)l < own && m.pr.out_ids[l] != m.nl_id[l]) != 0ull;
   if (diff) publish(ix, v, m.pr.out_ids, m.pr.out_d, (uint32_t)cnt, C_PUB_REFINE);
+}
+
+// ---- install given neighbor lists (import / test hook) -----------------------------------
+// One wave per listed node: its neighbors' stored distances are computed from
+// the rows, the list is ordered by (distance, id) and published.
+template <class P>
+__global__ void __launch_bounds__(256) k_set_lists(Index ix, MaintArgs a, const uint32_t* ids, const uint32_t* nbr,
+                                                   const uint32_t* deg) {
+  extern __shared__ __align__(16) char smem[];
+  const uint32_t i = wave_index();
+  if (i >= a.n) return;
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  const int l = lane_id();
+  const uint32_t u = ids[i];
+  const uint32_t d = min(deg[i], ix.R);
+  uint64_t* keys = m.pr.keys;  // nsort >= 64
+  for (uint32_t j = 0; j < d; ++j) {
+    const uint32_t v = nbr[(size_t)i * ix.R + j];
+    const uint32_t rho = P::dist1(ix, u, v, m.tmp, m.pr.keys2);
+    if (l == 0) {
+      keys[j] = make_key(P::kd(rho), v);
+      m.nl_d[j] = rho;  // temporary: rho by input position
+      m.nl_id[j] = v;
+    }
+  }
+  for (int j = (int)d + l; j < 64; j += 64) keys[j] = KEY_NONE;
+  wave_sync();
+  // order by key; carry rho by looking its input position back up
+  uint64_t myk = (uint32_t)l < d ? keys[l] : KEY_NONE;
+  uint32_t myrho = (uint32_t)l < d ? m.nl_d[l] : 0u;
+  wave_sync();
+  uint32_t rank = 0;
+  for (uint32_t j = 0; j < d; ++j) rank += keys[j] < myk;
+  wave_sync();
+  if ((uint32_t)l < d) {
+    m.pr.out_ids[rank] = key_id(myk);
+    m.pr.out_d[rank] = myrho;
+  }
+  wave_sync();
+  publish(ix, u, m.pr.out_ids, m.pr.out_d, d, C_PUB_FORWARD);
 }
 
 // ---- delete: classify, tombstone, repair (Algorithm 3) ----------------------------------
@@ -645,7 +886,7 @@ __global__ void k_repair_pairs(Index ix, MaintArgs a) {
   a.pairs[(size_t)i * ix.R + (uint32_t)l] = key;
 }
 
-template <int G>
+template <class P>
 __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   const uint32_t t = wave_index();
@@ -666,7 +907,7 @@ __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
     const uint64_t bm = ballot(ok);
     if (ok) m.cand[lanes_below(bm)] = b;
     wave_sync();
-    const int kc = robust_prune_u8<G>(ix, an, m.cand, __popcll(bm), m.pr);
+    const int kc = P::prune(ix, an, m.cand, __popcll(bm), m.pr);
     // N = RobustPrune(a, (N(a) \ {u}) U K)
     const bool keep = (uint32_t)l < n && m.nl_id[l] != u;
     const uint64_t km = ballot(keep);
@@ -676,7 +917,7 @@ __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
     if (keep) m.cand[lanes_below(km)] = m.nl_id[l];
     if (l < kc) m.cand[nk + (uint32_t)l] = kid;
     wave_sync();
-    n = (uint32_t)robust_prune_u8<G>(ix, an, m.cand, (int)(nk + (uint32_t)kc), m.pr);
+    n = (uint32_t)P::prune(ix, an, m.cand, (int)(nk + (uint32_t)kc), m.pr);
     copy_out(m, n);
   }
   publish(ix, an, m.nl_id, m.nl_d, n, C_PUB_REPAIR);
@@ -820,19 +1061,84 @@ __global__ void __launch_bounds__(64) k_bruteforce_u8(Index ix, const uint8_t* q
   }
 }
 
-// ---- host-side launchers ---------------------------------------------------------------------
-
-#define LAUNCH_G(KERNEL, G, grid, block, lds, stream, ...)                                        \
-  switch (G) {                                                                                   \
-    case 1: hipLaunchKernelGGL(KERNEL<1>, grid, block, lds, stream, __VA_ARGS__); break;          \
-    case 2: hipLaunchKernelGGL(KERNEL<2>, grid, block, lds, stream, __VA_ARGS__); break;          \
-    case 4: hipLaunchKernelGGL(KERNEL<4>, grid, block, lds, stream, __VA_ARGS__); break;          \
-    case 8: hipLaunchKernelGGL(KERNEL<8>, grid, block, lds, stream, __VA_ARGS__); break;          \
-    case 16: hipLaunchKernelGGL(KERNEL<16>, grid, block, lds, stream, __VA_ARGS__); break;        \
-    case 32: hipLaunchKernelGGL(KERNEL<32>, grid, block, lds, stream, __VA_ARGS__); break;        \
-    case 64: hipLaunchKernelGGL(KERNEL<64>, grid, block, lds, stream, __VA_ARGS__); break;        \
-    default: return hipErrorInvalidValue;                                                       \
+// ---- float rows: traversal copies written on insert ------------------------------------------
+// One wave per new row: bf16 copy (round to nearest even) and/or FP8 e4m3
+// copy of x / s with s = max|x_i| / 448 (s = 1 for an all-zero row).
+__global__ void __launch_bounds__(256) k_encode_f32(Index ix, uint32_t first, uint32_t n, float* xs, uint16_t* xb,
+                                                    uint8_t* x8) {
+  const uint32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int l = lane_id();
+  const uint32_t id = first + i;
+  const float* row = ix.xf + (size_t)id * ix.dim;
+  float amax = 0.f;
+  for (uint32_t j = (uint32_t)l; j < ix.dim; j += 64) amax = fmaxf(amax, fabsf(row[j]));
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if (xb)
+    for (uint32_t j = (uint32_t)l; j < ix.dim; j += 64) xb[(size_t)id * ix.dim + j] = to_bf16(row[j]);
+  if (x8) {
+    const float sc = amax > 0.f ? amax / 448.0f : 1.0f;
+    for (uint32_t j = (uint32_t)l; j < ix.dim; j += 64) x8[(size_t)id * ix.dim + j] = to_e4m3(row[j] / sc);
+    if (l == 0) xs[id] = sc;
   }
+}
+
+// exact FP32 k nearest live rows by (distance, id); one wave per query, G lanes
+// per row, 64 rows per step, each lane keeping its own K best
+template <int G>
+__global__ void __launch_bounds__(64) k_bruteforce_f32(Index ix, const float* q, uint32_t nq, uint64_t n_ids,
+                                                        uint32_t k, uint32_t* out_ids, uint32_t* out_d) {
+  constexpr int K = 16;
+  __shared__ uint64_t all[64 * K];
+  __shared__ uint64_t ck[64];
+  __shared__ uint32_t ids[64];
+  const uint32_t qi = blockIdx.x;
+  if (qi >= nq) return;
+  const int l = lane_id();
+  using E = TravF<G, TRAV_NATIVE>;
+  const typename E::Q qv = E::load_query(q + (size_t)qi * ix.dim);
+  uint64_t best[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) best[i] = KEY_NONE;
+  for (uint64_t b = 0; b < n_ids; b += 64) {
+    const uint64_t u = b + (uint64_t)l;
+    bool ok = false;
+    if (u < n_ids) {
+      const uint64_t r = load_ref(ix, (uint32_t)u);
+      ok = !ref_del(r) && ref_slab(r) != NONE;
+    }
+    const uint64_t m = ballot(ok);
+    if (ok) ids[lanes_below(m)] = (uint32_t)u;
+    const int cnt = __popcll(m);
+    __syncthreads();
+    E::dist_batch(ix, qv, ids, cnt, ck, nullptr);
+    __syncthreads();
+    if (l < cnt) {
+      uint64_t key = ck[l];
+      if (key < best[K - 1]) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const uint64_t lo = key < best[i] ? key : best[i];
+          const uint64_t hi = key < best[i] ? best[i] : key;
+          best[i] = lo;
+          key = hi;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) all[l * K + i] = best[i];
+  __syncthreads();
+  wave_bitonic_sort(all, 64 * K);
+  for (uint32_t i = (uint32_t)l; i < k; i += 64) {
+    const uint64_t kk = all[i];
+    out_ids[(size_t)qi * k + i] = kk == KEY_NONE ? NONE : key_id(kk);
+    out_d[(size_t)qi * k + i] = kk == KEY_NONE ? 0x7F800000u : __builtin_bit_cast(uint32_t, fkey_inv(key_dist(kk)));
+  }
+}
+
+// ---- host-side launchers ---------------------------------------------------------------------
 
 static inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
 
@@ -863,9 +1169,23 @@ uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots) {
   return 32u * L + 4u * 512u + 2u * 256u + 4u * vt_slots + ((2u * L + 15u) & ~15u);
 }
 
+// lanes per row of a float copy: 3 chunks of 16 bytes per lane
+static inline int float_lanes(uint32_t dim, int elem_bytes) { return (int)(dim * (uint32_t)elem_bytes / 16u / 3u); }
+
 hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s) {
   if (a.nq == 0 || a.ns == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scan_dist, dim3(blocks_for(a.ns, SD_E), blocks_for(a.nq, SD_Q)), dim3(256), 0, s, ix, a);
+  const dim3 dgrid(blocks_for(a.ns, SD_E), blocks_for(a.nq, SD_Q));
+  if (ix.metric == 0) {
+    hipLaunchKernelGGL(k_scan_dist, dgrid, dim3(256), 0, s, ix, a);
+  } else {
+    const int trav = a.mode == MODE_BOOT ? TRAV_NATIVE : ix.trav;
+    if (trav == TRAV_NATIVE)
+      hipLaunchKernelGGL(k_scan_dist_f<TRAV_NATIVE>, dgrid, dim3(256), 0, s, ix, a);
+    else if (trav == TRAV_BF16)
+      hipLaunchKernelGGL(k_scan_dist_f<TRAV_BF16>, dgrid, dim3(256), 0, s, ix, a);
+    else
+      hipLaunchKernelGGL(k_scan_dist_f<TRAV_FP8>, dgrid, dim3(256), 0, s, ix, a);
+  }
   const uint32_t cap = (uint32_t)next_pow2_ge64((int)a.L);
   const dim3 grid(blocks_for(a.nq, 4)), blk(256);
   const size_t lds = 4 * scan_select_lds_per_wave(a.L);
@@ -885,34 +1205,130 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+#define LS(TP) hipLaunchKernelGGL(k_search<TP>, dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a)
+
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s) {
   if (a.nq == 0) return hipSuccess;
-  const int G = (int)ix.dim / 16;
   const unsigned grid = blocks_for(a.nq, waves_per_block);
   const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
-  LAUNCH_G(k_search, G, dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a);
+  if (ix.metric == 0) {
+    switch (ix.dim / 16) {
+      case 1: { using TP = TravU8<1>; LS(TP); break; }
+      case 2: { using TP = TravU8<2>; LS(TP); break; }
+      case 4: { using TP = TravU8<4>; LS(TP); break; }
+      case 8: { using TP = TravU8<8>; LS(TP); break; }
+      case 16: { using TP = TravU8<16>; LS(TP); break; }
+      case 32: { using TP = TravU8<32>; LS(TP); break; }
+      case 64: { using TP = TravU8<64>; LS(TP); break; }
+      default: return hipErrorInvalidValue;
+    }
+  } else if (ix.trav == TRAV_NATIVE) {
+    switch (float_lanes(ix.dim, 4)) {
+      case 8: { using TP = TravFloat<8, TRAV_NATIVE>; LS(TP); break; }
+      case 16: { using TP = TravFloat<16, TRAV_NATIVE>; LS(TP); break; }
+      case 32: { using TP = TravFloat<32, TRAV_NATIVE>; LS(TP); break; }
+      case 64: { using TP = TravFloat<64, TRAV_NATIVE>; LS(TP); break; }
+      default: return hipErrorInvalidValue;
+    }
+  } else if (ix.trav == TRAV_BF16) {
+    switch (float_lanes(ix.dim, 2)) {
+      case 4: { using TP = TravFloat<4, TRAV_BF16>; LS(TP); break; }
+      case 8: { using TP = TravFloat<8, TRAV_BF16>; LS(TP); break; }
+      case 16: { using TP = TravFloat<16, TRAV_BF16>; LS(TP); break; }
+      case 32: { using TP = TravFloat<32, TRAV_BF16>; LS(TP); break; }
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (float_lanes(ix.dim, 1)) {
+      case 2: { using TP = TravFloat<2, TRAV_FP8>; LS(TP); break; }
+      case 4: { using TP = TravFloat<4, TRAV_FP8>; LS(TP); break; }
+      case 8: { using TP = TravFloat<8, TRAV_FP8>; LS(TP); break; }
+      case 16: { using TP = TravFloat<16, TRAV_FP8>; LS(TP); break; }
+      default: return hipErrorInvalidValue;
+    }
+  }
   return hipGetLastError();
 }
+#undef LS
 
 uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R) {
-  size_t b = (size_t)a.nsort * 8 + (size_t)a.prune_cap * 8 + (size_t)a.prune_cap * a.vstride + (size_t)a.prune_cap * 4 +
-             (size_t)(R + 1) * 8 + (size_t)a.nmax * 4 + (size_t)(R + 1) * 12;
+  size_t b = (size_t)a.nsort * 8 + (size_t)a.prune_cap * 8 + (size_t)a.prune_cap * a.vstride + (size_t)a.prune_cap * 8 +
+             (size_t)(R + 1) * 8 + (size_t)a.nmax * 4 + (size_t)(R + 1) * 12 + (size_t)a.prune_cap;
   return (uint32_t)((b + 15) & ~(size_t)15);
+}
+
+template <class P>
+static void launch_maint_p(MaintKernel which, const Index& ix, const MaintArgs& a, unsigned grid, dim3 blk,
+                           size_t lds, hipStream_t s) {
+  switch (which) {
+    case MK_FORWARD: hipLaunchKernelGGL(k_forward<P>, dim3(grid), blk, lds, s, ix, a); break;
+    case MK_REVERSE: hipLaunchKernelGGL(k_reverse_apply<P>, dim3(grid), blk, lds, s, ix, a); break;
+    case MK_REFINE: hipLaunchKernelGGL(k_refine<P>, dim3(grid), blk, lds, s, ix, a); break;
+    case MK_REPAIR: hipLaunchKernelGGL(k_repair_apply<P>, dim3(grid), blk, lds, s, ix, a); break;
+  }
 }
 
 hipError_t launch_maint(MaintKernel which, const Index& ix, const MaintArgs& a, uint32_t nwaves,
                         uint32_t waves_per_block, hipStream_t s) {
   if (nwaves == 0) return hipSuccess;
-  const int G = (int)ix.dim / 16;
   const unsigned grid = blocks_for(nwaves, waves_per_block);
   const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
   const dim3 blk(64 * waves_per_block);
-  switch (which) {
-    case MK_FORWARD: LAUNCH_G(k_forward, G, dim3(grid), blk, lds, s, ix, a); break;
-    case MK_REVERSE: LAUNCH_G(k_reverse_apply, G, dim3(grid), blk, lds, s, ix, a); break;
-    case MK_REFINE: LAUNCH_G(k_refine, G, dim3(grid), blk, lds, s, ix, a); break;
-    case MK_REPAIR: LAUNCH_G(k_repair_apply, G, dim3(grid), blk, lds, s, ix, a); break;
+  if (ix.metric == 0) {
+    switch (ix.dim / 16) {
+      case 1: launch_maint_p<MaintU8<1>>(which, ix, a, grid, blk, lds, s); break;
+      case 2: launch_maint_p<MaintU8<2>>(which, ix, a, grid, blk, lds, s); break;
+      case 4: launch_maint_p<MaintU8<4>>(which, ix, a, grid, blk, lds, s); break;
+      case 8: launch_maint_p<MaintU8<8>>(which, ix, a, grid, blk, lds, s); break;
+      case 16: launch_maint_p<MaintU8<16>>(which, ix, a, grid, blk, lds, s); break;
+      case 32: launch_maint_p<MaintU8<32>>(which, ix, a, grid, blk, lds, s); break;
+      case 64: launch_maint_p<MaintU8<64>>(which, ix, a, grid, blk, lds, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (float_lanes(ix.dim, 4)) {
+      case 8: launch_maint_p<MaintF32<8>>(which, ix, a, grid, blk, lds, s); break;
+      case 16: launch_maint_p<MaintF32<16>>(which, ix, a, grid, blk, lds, s); break;
+      case 32: launch_maint_p<MaintF32<32>>(which, ix, a, grid, blk, lds, s); break;
+      case 64: launch_maint_p<MaintF32<64>>(which, ix, a, grid, blk, lds, s); break;
+      default: return hipErrorInvalidValue;
+    }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_lists(const Index& ix, const MaintArgs& a, const uint32_t* ids, const uint32_t* nbr,
+                            const uint32_t* deg, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const dim3 grid(blocks_for(a.n, 1)), blk(64);
+  const size_t lds = a.lds_per_wave;
+  if (ix.metric == 0) {
+    switch (ix.dim / 16) {
+      case 1: hipLaunchKernelGGL(k_set_lists<MaintU8<1>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      case 2: hipLaunchKernelGGL(k_set_lists<MaintU8<2>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      case 4: hipLaunchKernelGGL(k_set_lists<MaintU8<4>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      case 8: hipLaunchKernelGGL(k_set_lists<MaintU8<8>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      case 16: hipLaunchKernelGGL(k_set_lists<MaintU8<16>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      case 32: hipLaunchKernelGGL(k_set_lists<MaintU8<32>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      case 64: hipLaunchKernelGGL(k_set_lists<MaintU8<64>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (float_lanes(ix.dim, 4)) {
+      case 8: hipLaunchKernelGGL(k_set_lists<MaintF32<8>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      case 16: hipLaunchKernelGGL(k_set_lists<MaintF32<16>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      case 32: hipLaunchKernelGGL(k_set_lists<MaintF32<32>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      case 64: hipLaunchKernelGGL(k_set_lists<MaintF32<64>>, grid, blk, lds, s, ix, a, ids, nbr, deg); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const Index& ix, uint32_t first, uint32_t n, float* xs, uint16_t* xb, uint8_t* x8,
+                         hipStream_t s) {
+  if (n == 0 || (!xb && !x8)) return hipSuccess;
+  hipLaunchKernelGGL(k_encode_f32, dim3(blocks_for(n, 4)), dim3(256), 0, s, ix, first, n, xs, xb, x8);
   return hipGetLastError();
 }
 
@@ -983,11 +1399,22 @@ hipError_t launch_export(const Index& ix, uint64_t n_ids, uint32_t* nbr, uint32_
   return hipGetLastError();
 }
 
-hipError_t launch_bruteforce(const Index& ix, const uint8_t* q, uint32_t nq, uint64_t n_ids, uint32_t k,
-                             uint32_t* out_ids, int32_t* out_d, hipStream_t s) {
+hipError_t launch_bruteforce(const Index& ix, const void* q, uint32_t nq, uint64_t n_ids, uint32_t k,
+                             uint32_t* out_ids, uint32_t* out_d, hipStream_t s) {
   if (nq == 0) return hipSuccess;
   if (k > 16) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_bruteforce_u8<16>, dim3(nq), dim3(64), 0, s, ix, q, nq, n_ids, k, out_ids, out_d);
+  if (ix.metric == 0) {
+    hipLaunchKernelGGL(k_bruteforce_u8<16>, dim3(nq), dim3(64), 0, s, ix, (const uint8_t*)q, nq, n_ids, k, out_ids,
+                       (int32_t*)out_d);
+  } else {
+    switch (float_lanes(ix.dim, 4)) {
+      case 8: hipLaunchKernelGGL(k_bruteforce_f32<8>, dim3(nq), dim3(64), 0, s, ix, (const float*)q, nq, n_ids, k, out_ids, out_d); break;
+      case 16: hipLaunchKernelGGL(k_bruteforce_f32<16>, dim3(nq), dim3(64), 0, s, ix, (const float*)q, nq, n_ids, k, out_ids, out_d); break;
+      case 32: hipLaunchKernelGGL(k_bruteforce_f32<32>, dim3(nq), dim3(64), 0, s, ix, (const float*)q, nq, n_ids, k, out_ids, out_d); break;
+      case 64: hipLaunchKernelGGL(k_bruteforce_f32<64>, dim3(nq), dim3(64), 0, s, ix, (const float*)q, nq, n_ids, k, out_ids, out_d); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
   return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ enum DelStatus { DEL_OK = 0, DEL_NOT_LIVE = 1, DEL_OUT_OF_RANGE = 2, DEL_DUPLICA
 
 struct SearchArgs {
   int mode;            // MODE_QUERY or MODE_INSERT
-  const uint8_t* q;    // MODE_QUERY: [nq x dim] query rows
+  const void* q;       // MODE_QUERY: [nq x dim] query rows (uint8 or FP32)
   uint32_t first;      // MODE_INSERT: query i is stored vector first + i
   uint32_t nq, L, k, vcap, vt_mask;
   uint32_t lds_per_wave;
@@ -22,7 +22,7 @@ struct SearchArgs {
   const uint32_t* init_n;     // [nq]
   uint32_t init_stride;
   uint32_t* out_ids;   // MODE_QUERY: [nq x k]
-  int32_t* out_d;      // MODE_QUERY: [nq x k]
+  uint32_t* out_d;     // MODE_QUERY: [nq x k] int32 (uint8 rows) or FP32 (float rows) bit patterns
   uint64_t* vis_keys;  // MODE_INSERT: [nq x vcap] expanded keys
   uint32_t* vis_cnt;   // [nq]
   uint32_t* counts;    // optional [nq x 2]: expansions, distance evaluations
@@ -32,7 +32,7 @@ struct SearchArgs {
 // excluding the query itself) of every query, in (distance, id) order
 struct ScanArgs {
   int mode;
-  const uint8_t* q;    // MODE_QUERY rows; otherwise query i is stored vector first + qoff + i
+  const void* q;       // MODE_QUERY rows; otherwise query i is stored vector first + qoff + i
   uint32_t first, qoff, nq, L;  // a bootstrap's start set is stored vectors [first, first + ns)
   uint32_t ns;         // start-set size (entry count, or the batch size for a bootstrap)
   uint32_t* dist;      // [nq x ns] scratch distance matrix
@@ -83,7 +83,11 @@ hipError_t launch_compact(const Index& ix, const uint32_t* dirty, uint64_t n, co
 hipError_t launch_free_tombstones(const Index& ix, uint64_t n_ids, hipStream_t s);
 hipError_t launch_export(const Index& ix, uint64_t n_ids, uint32_t* nbr, uint32_t* rho, uint8_t* deg, uint8_t* del,
                          uint8_t* has_slab, hipStream_t s);
-hipError_t launch_bruteforce(const Index& ix, const uint8_t* q, uint32_t nq, uint64_t n_ids, uint32_t k,
-                             uint32_t* out_ids, int32_t* out_d, hipStream_t s);
+hipError_t launch_bruteforce(const Index& ix, const void* q, uint32_t nq, uint64_t n_ids, uint32_t k,
+                             uint32_t* out_ids, uint32_t* out_d, hipStream_t s);
+hipError_t launch_encode(const Index& ix, uint32_t first, uint32_t n, float* xs, uint16_t* xb, uint8_t* x8,
+                         hipStream_t s);
+hipError_t launch_set_lists(const Index& ix, const MaintArgs& a, const uint32_t* ids, const uint32_t* nbr,
+                            const uint32_t* deg, hipStream_t s);
 
 }  // namespace etale

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libetale.so")
 
 OK, EINVAL, ENOMEM, EPOOL, ECAPACITY, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5, -6
-METRIC_L2_U8 = 0
+METRIC_L2_U8, METRIC_IP_F32 = 0, 1
+TRAV_NATIVE, TRAV_BF16, TRAV_FP8 = 0, 1, 2
 DEL_OK, DEL_NOT_LIVE, DEL_OUT_OF_RANGE, DEL_DUPLICATE = 0, 1, 2, 3
 NONE = 0xFFFFFFFF
 
@@ -38,7 +39,8 @@ class Config(C.Structure):
         ("prune_cap", C.c_uint32), ("n_entry", C.c_uint32), ("refine", C.c_uint32),
         ("tombstone_only", C.c_uint32), ("publish_attempts", C.c_uint32), ("max_batch", C.c_uint32),
         ("vt_slots", C.c_uint32), ("waves_per_block", C.c_uint32), ("metric", C.c_int32),
-        ("reserved", C.c_int32), ("id_capacity", C.c_uint64), ("slab_capacity", C.c_uint64),
+        ("traversal", C.c_int32), ("rerank_mult", C.c_uint32), ("reserved", C.c_uint32),
+        ("id_capacity", C.c_uint64), ("slab_capacity", C.c_uint64),
         ("hip_stream", C.c_void_p),
     ]
 
@@ -79,6 +81,8 @@ def load() -> C.CDLL:
         "etale_get_stats": ([vp, C.POINTER(Stats)], i32),
         "etale_export": ([vp, u64, vp, vp, vp, vp, vp], i32),
         "etale_get_entries": ([vp, vp, u64, C.POINTER(u64)], i32),
+        "etale_set_lists": ([vp, u64, vp, vp, vp], i32),
+        "etale_export_rows": ([vp, u64, u64, i32, vp], i32),
         "etale_sync": ([vp], i32),
         "etale_last_error": ([vp], C.c_char_p),
     }
@@ -101,7 +105,8 @@ class Index:
                  prune_cap: Optional[int] = None, n_entry: int = 128, refine: bool = True,
                  tombstone_only: bool = False, publish_attempts: int = 8, max_batch: int = 10000,
                  vt_slots: int = 1024, waves_per_block: int = 4, id_capacity: int = 100000,
-                 slab_capacity: Optional[int] = None, metric: int = METRIC_L2_U8, stream=None):
+                 slab_capacity: Optional[int] = None, metric: int = METRIC_L2_U8, traversal: int = TRAV_NATIVE,
+                 rerank_mult: int = 4, stream=None):
         import torch
 
         self.torch = torch
@@ -111,9 +116,10 @@ class Index:
         if slab_capacity is None:
             slab_capacity = 2 * id_capacity + max_batch * (R + 2)
         self.dim, self.R, self.metric = dim, R, metric
+        self.traversal = traversal
         self.cfg = Config(dim, R, L_build, alpha[0], alpha[1], visit_mult, prune_cap, n_entry, int(refine),
-                          int(tombstone_only), publish_attempts, max_batch, vt_slots, waves_per_block, metric, 0,
-                          id_capacity, slab_capacity, None)
+                          int(tombstone_only), publish_attempts, max_batch, vt_slots, waves_per_block, metric,
+                          traversal, rerank_mult, 0, id_capacity, slab_capacity, None)
         s = stream if stream is not None else torch.cuda.current_stream()
         self.cfg.hip_stream = s.cuda_stream
         self.stream = s
@@ -145,9 +151,17 @@ class Index:
             raise TypeError("expected a CUDA (HIP) tensor")
         return t.contiguous().to(dtype)
 
+    @property
+    def _vdtype(self):
+        return self.torch.uint8 if self.metric == METRIC_L2_U8 else self.torch.float32
+
+    @property
+    def _ddtype(self):
+        return self.torch.int32 if self.metric == METRIC_L2_U8 else self.torch.float32
+
     def insert(self, x):
         torch = self.torch
-        x = self._dev(x, torch.uint8)
+        x = self._dev(x, self._vdtype)
         n = x.shape[0]
         ids = torch.empty(n, dtype=torch.int32, device=x.device)
         self._check(self.lib.etale_insert_batch(self.h, _ptr(x), n, _ptr(ids)), "insert_batch")
@@ -162,10 +176,10 @@ class Index:
 
     def search(self, q, k: int, L: int, counts: bool = False):
         torch = self.torch
-        q = self._dev(q, torch.uint8)
+        q = self._dev(q, self._vdtype)
         nq = q.shape[0]
         ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
-        d = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+        d = torch.empty((nq, k), dtype=self._ddtype, device=q.device)
         cnt = torch.empty((nq, 2), dtype=torch.int32, device=q.device) if counts else None
         self._check(self.lib.etale_search_batch(self.h, _ptr(q), nq, k, L, _ptr(ids), _ptr(d), _ptr(cnt)),
                     "search_batch")
@@ -176,9 +190,9 @@ class Index:
 
     def bruteforce(self, q, k: int):
         torch = self.torch
-        q = self._dev(q, torch.uint8)
+        q = self._dev(q, self._vdtype)
         ids = torch.empty((q.shape[0], k), dtype=torch.int32, device=q.device)
-        d = torch.empty((q.shape[0], k), dtype=torch.int32, device=q.device)
+        d = torch.empty((q.shape[0], k), dtype=self._ddtype, device=q.device)
         self._check(self.lib.etale_bruteforce(self.h, _ptr(q), q.shape[0], k, _ptr(ids), _ptr(d)), "bruteforce")
         return ids, d
 
@@ -201,7 +215,8 @@ class Index:
         hs = np.zeros(max(n_ids, 1), np.uint8)
         p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
         self._check(self.lib.etale_export(self.h, n_ids, p(nbr), p(rho), p(deg), p(de), p(hs)), "export")
-        return dict(nbr=nbr[:n_ids], rho=rho[:n_ids].view(np.int32), deg=deg[:n_ids],
+        rv = rho[:n_ids].view(np.int32 if self.metric == METRIC_L2_U8 else np.float32)
+        return dict(nbr=nbr[:n_ids], rho=rv, deg=deg[:n_ids],
                     deleted=de[:n_ids].astype(bool), has_slab=hs[:n_ids].astype(bool))
 
     def entries(self) -> np.ndarray:
@@ -210,3 +225,24 @@ class Index:
         n = C.c_uint64(0)
         self._check(self.lib.etale_get_entries(self.h, out.ctypes.data_as(C.c_void_p), cap, C.byref(n)), "entries")
         return out[:n.value].copy()
+
+    def set_lists(self, ids, nbr, deg):
+        """Install neighbor lists (import): row i of nbr (R wide) holds deg[i] neighbors of ids[i]."""
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        nbr = np.ascontiguousarray(nbr, dtype=np.uint32).reshape(ids.size, self.R)
+        deg = np.ascontiguousarray(deg, dtype=np.uint32)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        self._check(self.lib.etale_set_lists(self.h, ids.size, p(ids), p(nbr), p(deg)), "set_lists")
+
+    def rows(self, first: int, n: int, which: int = 0) -> np.ndarray:
+        """Stored rows: 0 as inserted, 1 bf16 copy (uint16), 2 FP8 codes, 3 FP8 scales."""
+        if which == 0:
+            out = np.zeros((n, self.dim), np.uint8 if self.metric == METRIC_L2_U8 else np.float32)
+        elif which == 1:
+            out = np.zeros((n, self.dim), np.uint16)
+        elif which == 2:
+            out = np.zeros((n, self.dim), np.uint8)
+        else:
+            out = np.zeros(n, np.float32)
+        self._check(self.lib.etale_export_rows(self.h, first, n, which, out.ctypes.data_as(C.c_void_p)), "export_rows")
+        return out

@@ -57,3 +57,31 @@ def assert_same_state(o, g, where=""):
 def recall_at(ids, gt, k=10):
     ids, gt = np.asarray(ids), np.asarray(gt)
     return float(np.mean([len(set(ids[i, :k].tolist()) & set(gt[i, :k].tolist())) / k for i in range(ids.shape[0])]))
+
+
+def float_workload(n_base=1500, clusters=16, seed=1, batch=500, rounds=2, churn=0.03, dim=96, sigma=0.3):
+    return dg.Workload("small_f32", dg.Mixture(dim, clusters, sigma, dg.METRIC_IP_F32), n_base, 24, 48, 6, 5,
+                       rounds, churn, 200, 10, (48,), seed, batch, batch)
+
+
+def make_oracle_f(p, traversal=0, rerank_mult=4):
+    return oracle.Oracle(oracle.METRIC_IP_F32, p["dim"], p["R"], p["L_build"], p["id_capacity"], p["slab_capacity"],
+                         alpha=p["alpha"], n_entry=p["n_entry"], refine=p["refine"],
+                         tombstone_only=p["tombstone_only"], traversal=traversal, rerank_mult=rerank_mult)
+
+
+def make_gpu_f(p, traversal=0, rerank_mult=4, **kw):
+    from paper_2607_02543_amd import etale
+    return etale.Index(p["dim"], R=p["R"], L_build=p["L_build"], alpha=p["alpha"], n_entry=p["n_entry"],
+                       refine=p["refine"], tombstone_only=p["tombstone_only"], id_capacity=p["id_capacity"],
+                       slab_capacity=p["slab_capacity"], max_batch=p["max_batch"], metric=etale.METRIC_IP_F32,
+                       traversal=traversal, rerank_mult=rerank_mult, **kw)
+
+
+def exact_ip_dist(q, x, ids):
+    """FP64 d = 1 - <q, x_id> for rows of ids (NONE -> inf)."""
+    ids = np.asarray(ids, dtype=np.int64)
+    out = np.full(ids.shape, np.inf)
+    ok = ids != 0xFFFFFFFF
+    out[ok] = 1.0 - np.einsum("...d,...d->...", np.broadcast_to(q.astype(np.float64)[..., None, :], ids.shape + (q.shape[-1],))[ok], x.astype(np.float64)[ids[ok]])
+    return out
