@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=5000)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--workload", default="scale_u8_1m", choices=["scale_u8_1m", "precision_f32"])
+    ap.add_argument("--prune-cap", type=int, default=0)
     return ap.parse_args()
 
 
@@ -92,12 +94,127 @@ def cpu_baseline(wl, L, n_sample, n_q=300):
             "ms_per_churn_round_sample": t_round * 1e3}
 
 
+def run_precision(args):
+    """768-d float embeddings: one graph built with FP32 traversal; queries
+    traverse the FP32 rows, the bf16 copy or the FP8 e4m3 copy (+ per-row scale),
+    the latter two re-ranked in FP32 from their first 40 live candidates."""
+    import torch
+
+    from paper_2607_02543_amd import datagen as dg
+    from paper_2607_02543_amd import etale
+
+    dev = torch.device("cuda:0")
+    n_base = args.n_base
+    wl = dg.precision_f32(n_base=n_base, rounds=args.warmup + args.steps, n_queries=args.queries)
+    st = dg.Stream(wl)
+    churn = wl.churn_count()
+    cap = wl.n_base + (args.warmup + args.steps) * churn + 16
+    max_batch = max(wl.build_batch_max, churn)
+    L, k = 96, 10
+    prune_cap = args.prune_cap or 2 * wl.R + 2
+    n_entry = min(args.n_entry, 1024)
+    t0 = time.perf_counter()
+    ix = etale.Index(wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den), n_entry=n_entry,
+                     prune_cap=prune_cap, id_capacity=cap, slab_capacity=2 * cap + max_batch * (wl.R + 2),
+                     max_batch=max_batch, metric=etale.METRIC_IP_F32, traversal=etale.TRAV_NATIVE, copies=3,
+                     rerank_mult=4)
+    xs = np.zeros((cap, wl.dim), np.float32)
+    live = np.zeros(cap, bool)
+    done = 0
+    for b in wl.build_batches():
+        xb = st.base(b)
+        xs[done:done + b] = xb
+        ix.insert(torch.from_numpy(xb).to(dev))
+        live[done:done + b] = True
+        done += b
+        log(args, f"built {done}")
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    log(args, f"build {t_build:.1f}s")
+    q_host = st.queries(args.queries)
+    q = torch.from_numpy(q_host).to(dev)
+    next_id = done
+    modes = [("fp32", etale.TRAV_NATIVE), ("bf16", etale.TRAV_BF16), ("fp8_e4m3", etale.TRAV_FP8)]
+
+    def churn_inputs():
+        nonlocal next_id
+        lids = np.nonzero(live[:next_id])[0].astype(np.uint32)
+        dl = st.deletes(lids, churn)
+        xb = st.inserts(churn)
+        xs[next_id:next_id + churn] = xb
+        live[dl] = False
+        live[next_id:next_id + churn] = True
+        next_id += churn
+        return torch.from_numpy(dl.astype(np.int32)).to(dev), torch.from_numpy(xb).to(dev)
+
+    for _ in range(args.warmup):
+        dlt, xb = churn_inputs()
+        ix.delete(dlt)
+        ix.insert(xb)
+        ix.reclaim()
+    stream = torch.cuda.current_stream()
+    inputs = [churn_inputs() for _ in range(args.steps)]
+    maint, search = [], {m: [] for m, _ in modes}
+    torch.cuda.synchronize()
+    for s_ in range(args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2 + len(modes))]
+        e[0].record(stream)
+        ix.delete(inputs[s_][0])
+        ix.insert(inputs[s_][1])
+        ix.reclaim()
+        e[1].record(stream)
+        for j, (name, mode) in enumerate(modes):
+            ix.set_query_traversal(mode, 4)
+            ix.search(q, k, L)
+            e[2 + j].record(stream)
+        torch.cuda.synchronize()
+        maint.append(e[0].elapsed_time(e[1]))
+        for j, (name, _) in enumerate(modes):
+            search[name].append(e[1 + j].elapsed_time(e[2 + j]))
+    ns = min(args.recall_sample, args.queries)
+    gt, _ = ix.bruteforce(q[:ns], k)
+    gt = gt.cpu().numpy()
+    out_modes = {}
+    for name, mode in modes:
+        ix.set_query_traversal(mode, 4)
+        ids, d = ix.search(q[:ns], k, L)
+        r = recall(ids.cpu().numpy(), gt)
+        # raw traversal distances of the returned ids against FP64 (no re-rank)
+        ix.set_query_traversal(mode, 0)
+        ids0, d0 = ix.search(q[:200], k, L)
+        ids0, d0 = ids0.cpu().numpy().astype(np.int64), d0.cpu().numpy().astype(np.float64)
+        ok = ids0 >= 0
+        ex = 1.0 - np.einsum("qd,qkd->qk", q_host[:200].astype(np.float64), xs[np.where(ok, ids0, 0)].astype(np.float64))
+        rel = np.abs(d0 - ex)[ok] / np.abs(ex)[ok]
+        t = float(np.mean(search[name])) * 1e-3
+        out_modes[name] = {"recall_at_10": round(r, 4), "qps": round(args.queries / t, 1), "search_ms": round(t * 1e3, 3),
+                           "rel_err_max": float(f"{rel.max():.3e}"), "rel_err_mean": float(f"{rel.mean():.3e}")}
+        log(args, name, out_modes[name])
+    stats = ix.stats()
+    ix.close()
+    best = max(out_modes.values(), key=lambda v: v["qps"])
+    return {
+        "metric": "ms per churn round + QPS at Recall@10>=0.95; FP32 vs BF16/FP8 traversal, 1 GPU",
+        "value": best["qps"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_churn_round": round(float(np.mean(maint)), 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 / bf16 / fp8-e4m3 traversal, f32 accumulate", "data": "synthetic",
+        "config": {"workload": "precision_f32", "n_base": wl.n_base, "dim": wl.dim, "clusters": 2000,
+                   "noise_sigma": 0.35, "R": wl.R, "L": L, "k": k, "rerank": 40, "prune_cap": prune_cap,
+                   "n_entry": n_entry, "churn_per_round": churn, "queries": args.queries},
+        "modes": out_modes, "build_s": round(t_build, 1), "device_bytes": stats["device_bytes"],
+        "recall_target_met": any(v["recall_at_10"] >= args.target_recall for v in out_modes.values()),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
               f"(multi-GPU sharding is a design note, not an implemented path).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "precision_f32":
+        print(json.dumps(run_precision(args)), flush=True)
+        return
     import torch
 
     from paper_2607_02543_amd import datagen as dg

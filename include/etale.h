@@ -97,8 +97,9 @@ typedef struct {
   uint32_t waves_per_block;  /* search wavefronts per workgroup */
   int32_t metric;            /* ETALE_METRIC_* */
   int32_t traversal;         /* ETALE_TRAV_* (float metric only) */
-  uint32_t rerank_mult;      /* bf16 / FP8 traversal: re-rank rerank_mult*k results in FP32 (k*mult <= 64) */
-  uint32_t reserved;
+  uint32_t rerank_mult;      /* bf16 / FP8 traversal: re-rank rerank_mult*k results in FP32 (k*mult <= 64);
+                                0 returns the traversal distances themselves */
+  uint32_t copies;           /* extra traversal copies to keep (1: bf16, 2: FP8), for query-side switching */
   uint64_t id_capacity;      /* size of the id space */
   uint64_t slab_capacity;    /* slabs in the pool */
   void* hip_stream;          /* hipStream_t, or NULL */
@@ -178,6 +179,11 @@ etale_status etale_export(etale_t ix, uint64_t n_ids, uint32_t* nbr_host, void* 
 /* Entry-set members in ascending id order (up to cap ids); returns the
  * count through *n_out (synchronizes). */
 etale_status etale_get_entries(etale_t ix, uint32_t* ids_host, uint64_t cap, uint64_t* n_out);
+
+/* Queries from now on traverse the given copy (ETALE_TRAV_*; it must be the
+ * configured one or kept through `copies`) with the given re-rank multiplier;
+ * inserts keep using the configured traversal. */
+etale_status etale_set_query_traversal(etale_t ix, int32_t traversal, uint32_t rerank_mult);
 
 /* Install neighbor lists (import): for each of the n ids in ids_host, the
  * first deg_host[i] (<= R) entries of row i of nbr_host (n x R uint32) become

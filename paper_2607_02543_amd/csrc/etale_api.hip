@@ -42,6 +42,8 @@ struct etale_index {
   uint64_t dist_cap = 0;
   uint32_t scan_chunk = 0;
   uint64_t live = 0;              // ids with deletion flag 0 (host mirror)
+  int32_t qtrav = 0;              // query-side traversal copy
+  uint32_t qrerank = 0;
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
   uint64_t next_id = 0;
@@ -164,6 +166,7 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t 
     sc.out_keys = ix->scan_keys;
     sc.out_n = ix->scan_n;
     sc.out_stride = L;
+    sc.trav = mode == MODE_QUERY ? ix->qtrav : ix->dev.trav;
     if (ns == 0) {
       HIP_TRY(hipMemsetAsync(ix->scan_n, 0, (size_t)cn * 4, ix->stream));
     } else {
@@ -182,6 +185,8 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t 
     sa.init_keys = ix->scan_keys;
     sa.init_n = ix->scan_n;
     sa.init_stride = L;
+    sa.trav = sc.trav;
+    sa.rerank = mode == MODE_QUERY ? ix->qrerank : 0;
     if (mode == MODE_QUERY) {
       sa.out_ids = out_ids + c * k;
       sa.out_d = out_d + c * k;
@@ -233,7 +238,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   } else if (c.metric == ETALE_METRIC_IP_F32) {
     if (c.dim != 96 && c.dim != 192 && c.dim != 384 && c.dim != 768) return ETALE_EINVAL;
     if (c.traversal < ETALE_TRAV_NATIVE || c.traversal > ETALE_TRAV_FP8E4M3) return ETALE_EINVAL;
-    if (c.traversal != ETALE_TRAV_NATIVE && (c.rerank_mult < 1 || c.rerank_mult > 64)) return ETALE_EINVAL;
+    if (c.rerank_mult > 64 || c.copies > 3) return ETALE_EINVAL;
   } else {
     return ETALE_EINVAL;
   }
@@ -277,8 +282,8 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
     ALLOC(ix->x, C * c.dim);
   } else {
     ALLOC(ix->xf, C * c.dim * 4);
-    if (c.traversal == ETALE_TRAV_BF16) ALLOC(ix->xb, C * c.dim * 2);
-    if (c.traversal == ETALE_TRAV_FP8E4M3) {
+    if (c.traversal == ETALE_TRAV_BF16 || (c.copies & 1)) ALLOC(ix->xb, C * c.dim * 2);
+    if (c.traversal == ETALE_TRAV_FP8E4M3 || (c.copies & 2)) {
       ALLOC(ix->x8, C * c.dim);
       ALLOC(ix->xs, C * 4);
     }
@@ -321,6 +326,8 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   d.metric = c.metric;
   d.trav = c.metric == ETALE_METRIC_IP_F32 ? c.traversal : 0;
   d.rerank = c.rerank_mult;
+  ix->qtrav = d.trav;
+  ix->qrerank = c.rerank_mult;
   d.cap = C;
   d.P = P;
   d.x = ix->x;
@@ -465,8 +472,7 @@ etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint
   if (nq == 0) return ETALE_OK;
   if (!q_dev || !ids_out_dev || !dists_out_dev || nq > 0xFFFFFFFFull)
     return fail(ix, ETALE_EINVAL, "search: null buffer");
-  if (ix->cfg.metric == ETALE_METRIC_IP_F32 && ix->cfg.traversal != ETALE_TRAV_NATIVE &&
-      (uint64_t)ix->cfg.rerank_mult * k > 64)
+  if (ix->cfg.metric == ETALE_METRIC_IP_F32 && ix->qtrav != ETALE_TRAV_NATIVE && (uint64_t)ix->qrerank * k > 64)
     return fail(ix, ETALE_EINVAL, "search: rerank_mult * k must not exceed 64");
   if (etale_status st = run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(q_dev), 0, nq, k, L,
                                      ix->cfg.visit_mult * L, ids_out_dev, reinterpret_cast<uint32_t*>(dists_out_dev),
@@ -574,6 +580,17 @@ etale_status etale_get_entries(etale_t ix, uint32_t* ids_host, uint64_t cap, uin
     HIP_TRY(hipStreamSynchronize(ix->stream));
   }
   *n_out = h[C_N_ENTRIES];
+  return ETALE_OK;
+}
+
+etale_status etale_set_query_traversal(etale_t ix, int32_t traversal, uint32_t rerank_mult) {
+  CHECK_HANDLE();
+  if (ix->cfg.metric != ETALE_METRIC_IP_F32) return fail(ix, ETALE_EINVAL, "query traversal: float metric only");
+  const bool kept = traversal == ETALE_TRAV_NATIVE || (traversal == ETALE_TRAV_BF16 && ix->xb) ||
+                    (traversal == ETALE_TRAV_FP8E4M3 && ix->x8);
+  if (!kept || rerank_mult > 64) return fail(ix, ETALE_EINVAL, "query traversal: copy not kept or bad multiplier");
+  ix->qtrav = traversal;
+  ix->qrerank = rerank_mult;
   return ETALE_OK;
 }
 

@@ -515,7 +515,8 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
     // FP32 rows and cut to k
     bool rerank = false;
     if constexpr (TP::FLOAT) rerank = TP::MODE != TRAV_NATIVE;
-    const uint32_t want = rerank ? min(64u, ix.rerank * a.k) : a.k;
+    if (a.rerank == 0) rerank = false;
+    const uint32_t want = rerank ? min(64u, a.rerank * a.k) : a.k;
     uint32_t got = 0;
     for (int b = 0; b < cl.n && got < want; b += 64) {
       const int i = b + l;
@@ -1178,7 +1179,7 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s) {
   if (ix.metric == 0) {
     hipLaunchKernelGGL(k_scan_dist, dgrid, dim3(256), 0, s, ix, a);
   } else {
-    const int trav = a.mode == MODE_BOOT ? TRAV_NATIVE : ix.trav;
+    const int trav = a.mode == MODE_BOOT ? TRAV_NATIVE : a.trav;
     if (trav == TRAV_NATIVE)
       hipLaunchKernelGGL(k_scan_dist_f<TRAV_NATIVE>, dgrid, dim3(256), 0, s, ix, a);
     else if (trav == TRAV_BF16)
@@ -1222,7 +1223,7 @@ hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_pe
       case 64: { using TP = TravU8<64>; LS(TP); break; }
       default: return hipErrorInvalidValue;
     }
-  } else if (ix.trav == TRAV_NATIVE) {
+  } else if (a.trav == TRAV_NATIVE) {
     switch (float_lanes(ix.dim, 4)) {
       case 8: { using TP = TravFloat<8, TRAV_NATIVE>; LS(TP); break; }
       case 16: { using TP = TravFloat<16, TRAV_NATIVE>; LS(TP); break; }
@@ -1230,7 +1231,7 @@ hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_pe
       case 64: { using TP = TravFloat<64, TRAV_NATIVE>; LS(TP); break; }
       default: return hipErrorInvalidValue;
     }
-  } else if (ix.trav == TRAV_BF16) {
+  } else if (a.trav == TRAV_BF16) {
     switch (float_lanes(ix.dim, 2)) {
       case 4: { using TP = TravFloat<4, TRAV_BF16>; LS(TP); break; }
       case 8: { using TP = TravFloat<8, TRAV_BF16>; LS(TP); break; }

@@ -18,6 +18,8 @@ struct SearchArgs {
   uint32_t first;      // MODE_INSERT: query i is stored vector first + i
   uint32_t nq, L, k, vcap, vt_mask;
   uint32_t lds_per_wave;
+  int32_t trav;        // float rows: traversal copy of this launch
+  uint32_t rerank;     // float rows, bf16 / FP8 copy: re-rank rerank*k candidates (0: none)
   const uint64_t* init_keys;  // [nq x init_stride] initial list from k_scan
   const uint32_t* init_n;     // [nq]
   uint32_t init_stride;
@@ -34,6 +36,7 @@ struct ScanArgs {
   int mode;
   const void* q;       // MODE_QUERY rows; otherwise query i is stored vector first + qoff + i
   uint32_t first, qoff, nq, L;  // a bootstrap's start set is stored vectors [first, first + ns)
+  int32_t trav;        // float rows: traversal copy the start rows are read from
   uint32_t ns;         // start-set size (entry count, or the batch size for a bootstrap)
   uint32_t* dist;      // [nq x ns] scratch distance matrix
   uint64_t* out_keys;  // [nq x out_stride]

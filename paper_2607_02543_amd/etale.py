@@ -39,7 +39,7 @@ class Config(C.Structure):
         ("prune_cap", C.c_uint32), ("n_entry", C.c_uint32), ("refine", C.c_uint32),
         ("tombstone_only", C.c_uint32), ("publish_attempts", C.c_uint32), ("max_batch", C.c_uint32),
         ("vt_slots", C.c_uint32), ("waves_per_block", C.c_uint32), ("metric", C.c_int32),
-        ("traversal", C.c_int32), ("rerank_mult", C.c_uint32), ("reserved", C.c_uint32),
+        ("traversal", C.c_int32), ("rerank_mult", C.c_uint32), ("copies", C.c_uint32),
         ("id_capacity", C.c_uint64), ("slab_capacity", C.c_uint64),
         ("hip_stream", C.c_void_p),
     ]
@@ -82,6 +82,7 @@ def load() -> C.CDLL:
         "etale_export": ([vp, u64, vp, vp, vp, vp, vp], i32),
         "etale_get_entries": ([vp, vp, u64, C.POINTER(u64)], i32),
         "etale_set_lists": ([vp, u64, vp, vp, vp], i32),
+        "etale_set_query_traversal": ([vp, i32, u32], i32),
         "etale_export_rows": ([vp, u64, u64, i32, vp], i32),
         "etale_sync": ([vp], i32),
         "etale_last_error": ([vp], C.c_char_p),
@@ -106,7 +107,7 @@ class Index:
                  tombstone_only: bool = False, publish_attempts: int = 8, max_batch: int = 10000,
                  vt_slots: int = 1024, waves_per_block: int = 4, id_capacity: int = 100000,
                  slab_capacity: Optional[int] = None, metric: int = METRIC_L2_U8, traversal: int = TRAV_NATIVE,
-                 rerank_mult: int = 4, stream=None):
+                 rerank_mult: int = 4, copies: int = 0, stream=None):
         import torch
 
         self.torch = torch
@@ -119,7 +120,7 @@ class Index:
         self.traversal = traversal
         self.cfg = Config(dim, R, L_build, alpha[0], alpha[1], visit_mult, prune_cap, n_entry, int(refine),
                           int(tombstone_only), publish_attempts, max_batch, vt_slots, waves_per_block, metric,
-                          traversal, rerank_mult, 0, id_capacity, slab_capacity, None)
+                          traversal, rerank_mult, copies, id_capacity, slab_capacity, None)
         s = stream if stream is not None else torch.cuda.current_stream()
         self.cfg.hip_stream = s.cuda_stream
         self.stream = s
@@ -225,6 +226,9 @@ class Index:
         n = C.c_uint64(0)
         self._check(self.lib.etale_get_entries(self.h, out.ctypes.data_as(C.c_void_p), cap, C.byref(n)), "entries")
         return out[:n.value].copy()
+
+    def set_query_traversal(self, traversal: int, rerank_mult: int = 4):
+        self._check(self.lib.etale_set_query_traversal(self.h, traversal, rerank_mult), "set_query_traversal")
 
     def set_lists(self, ids, nbr, deg):
         """Install neighbor lists (import): row i of nbr (R wide) holds deg[i] neighbors of ids[i]."""
