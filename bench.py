@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--workload", default="scale_u8_1m", choices=["scale_u8_1m", "precision_f32"])
     ap.add_argument("--prune-cap", type=int, default=0)
+    ap.add_argument("--W", type=int, default=2, help="expansions per search iteration (1 or 2)")
     return ap.parse_args()
 
 
@@ -234,7 +235,7 @@ def main():
     t0 = time.perf_counter()
     ix = etale.Index(wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den),
                      n_entry=args.n_entry, id_capacity=cap, slab_capacity=slab_cap, max_batch=max_batch,
-                     vt_slots=args.vt_slots, waves_per_block=args.waves_per_block)
+                     vt_slots=args.vt_slots, waves_per_block=args.waves_per_block, W=args.W)
     live = np.zeros(cap, bool)
     done = 0
     for b in wl.build_batches():
@@ -339,7 +340,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "scale_u8_1m", "n_base": wl.n_base, "dim": wl.dim, "clusters": 1024,
                    "R": wl.R, "L_build": wl.L_build, "alpha": "6/5", "churn_per_round": churn,
-                   "queries": args.queries, "k": 10, "search_L": Ls, "n_entry": args.n_entry,
+                   "queries": args.queries, "k": 10, "search_L": Ls, "n_entry": args.n_entry, "W": args.W,
                    "parallelism": "single GPU"},
         "sweep": {str(k): v for k, v in sweep.items()},
         "build_s": round(t_build, 2),

@@ -181,6 +181,7 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t 
     sa.k = k;
     sa.vcap = vcap;
     sa.vt_mask = ix->cfg.vt_slots - 1;
+    sa.W = ix->cfg.W;
     sa.lds_per_wave = search_lds_per_wave(L, ix->cfg.vt_slots);
     sa.init_keys = ix->scan_keys;
     sa.init_n = ix->scan_n;
@@ -248,6 +249,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   if (c.prune_cap < c.R || c.prune_cap > 2048) return ETALE_EINVAL;
   if (c.n_entry < 1 || c.n_entry > 16384) return ETALE_EINVAL;  // a start set is scored in registers
   if (c.publish_attempts < 1 || c.max_batch < 1) return ETALE_EINVAL;
+  if (c.W < 1 || c.W > 2 || c.W * c.R > 64) return ETALE_EINVAL;
   if (!pow2(c.vt_slots) || c.vt_slots < 64 || c.vt_slots > 16384) return ETALE_EINVAL;
   if (c.waves_per_block != 1 && c.waves_per_block != 2 && c.waves_per_block != 4) return ETALE_EINVAL;
   if (c.id_capacity < 1 || c.id_capacity >= 0xFFFFFFFFull || c.slab_capacity < 1 || c.slab_capacity >= 0xFFFFFFFFull)
@@ -305,7 +307,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   ix->scan_chunk = 16384;
   ALLOC(ix->scan_keys, (uint64_t)ix->scan_chunk * SCAN_L_MAX * 8);
   ALLOC(ix->scan_n, (uint64_t)ix->scan_chunk * 4);
-  ix->dist_cap = std::min<uint64_t>(1ull << 25, std::max<uint64_t>((uint64_t)ix->scan_chunk * c.n_entry, B * 4096));
+  ix->dist_cap = std::min<uint64_t>(1ull << 27, std::max<uint64_t>((uint64_t)ix->scan_chunk * c.n_entry, B * 4096));
   ALLOC(ix->scan_dist, ix->dist_cap * 4);
   {
     size_t bytes = 0;

@@ -247,13 +247,13 @@ __device__ inline void list_merge(CandList& cl, const uint64_t* ck, const uint64
   cl.n = min(L, n + na);
 }
 
-// index of the first unexpanded entry, or -1
-__device__ inline int list_first_open(const CandList& cl) {
+// index of the first unexpanded entry at or after `from`, or -1
+__device__ inline int list_first_open(const CandList& cl, int from = 0) {
   const int l = lane_id();
   const uint8_t* lx = cl.flags();
-  for (int base = 0; base < cl.n; base += 64) {
+  for (int base = from & ~63; base < cl.n; base += 64) {
     int i = base + l;
-    uint64_t m = ballot(i < cl.n && lx[i] == 0);
+    uint64_t m = ballot(i >= from && i < cl.n && lx[i] == 0);
     if (m) return base + (int)__builtin_ctzll(m);
   }
   return -1;

@@ -481,18 +481,34 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   {
     const uint32_t R = ix.R;
     while (nexp < a.vcap) {
-      const int j = list_first_open(cl);
-      if (j < 0) break;
-      const uint64_t key = cl.keys()[j];
-      const uint64_t r = cl.refs()[j];
-      if (l == 0) {
-        cl.flags()[j] = 1;
-        if (a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp] = key;
+      // up to W best unexpanded entries, within the visit cap; their slabs are
+      // read side by side (lanes [w*R, (w+1)*R) read the w-th)
+      const int j0 = list_first_open(cl);
+      if (j0 < 0) break;
+      int j1 = -1;
+      if (a.W > 1 && nexp + 1 < a.vcap) j1 = list_first_open(cl, j0 + 1);
+      const uint64_t key0 = cl.keys()[j0];
+      const uint64_t r0 = cl.refs()[j0];
+      uint64_t key1 = 0, r1 = 0;
+      if (j1 >= 0) {
+        key1 = cl.keys()[j1];
+        r1 = cl.refs()[j1];
       }
-      ++nexp;
-      const uint32_t deg = ref_deg(r), s = ref_slab(r);
+      if (l == 0) {
+        cl.flags()[j0] = 1;
+        if (a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp] = key0;
+        if (j1 >= 0) {
+          cl.flags()[j1] = 1;
+          if (a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp + 1] = key1;
+        }
+      }
+      nexp += j1 >= 0 ? 2u : 1u;
+      const bool second = (uint32_t)l >= R;
+      const uint64_t r = second ? r1 : r0;
+      const uint32_t slot = second ? (uint32_t)l - R : (uint32_t)l;
+      const uint32_t deg = (second && j1 < 0) ? 0u : ref_deg(r), s = ref_slab(r);
       uint32_t nid = NONE;
-      if ((uint32_t)l < deg && s != NONE) nid = ix.slabs[(size_t)s * 2u * R + (uint32_t)l];
+      if (slot < deg && s != NONE) nid = ix.slabs[(size_t)s * 2u * R + slot];
       const bool fresh = nid != NONE && vt_insert(vt, a.vt_mask, nid);
       const uint64_t m = ballot(fresh);
       if (fresh) ci[lanes_below(m)] = nid;

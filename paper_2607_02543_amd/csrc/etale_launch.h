@@ -17,6 +17,7 @@ struct SearchArgs {
   const void* q;       // MODE_QUERY: [nq x dim] query rows (uint8 or FP32)
   uint32_t first;      // MODE_INSERT: query i is stored vector first + i
   uint32_t nq, L, k, vcap, vt_mask;
+  uint32_t W;          // expansions per iteration (1, or 2 when 2R <= 64)
   uint32_t lds_per_wave;
   int32_t trav;        // float rows: traversal copy of this launch
   uint32_t rerank;     // float rows, bf16 / FP8 copy: re-rank rerank*k candidates (0: none)

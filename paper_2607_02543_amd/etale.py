@@ -40,6 +40,7 @@ class Config(C.Structure):
         ("tombstone_only", C.c_uint32), ("publish_attempts", C.c_uint32), ("max_batch", C.c_uint32),
         ("vt_slots", C.c_uint32), ("waves_per_block", C.c_uint32), ("metric", C.c_int32),
         ("traversal", C.c_int32), ("rerank_mult", C.c_uint32), ("copies", C.c_uint32),
+        ("W", C.c_uint32), ("reserved", C.c_uint32),
         ("id_capacity", C.c_uint64), ("slab_capacity", C.c_uint64),
         ("hip_stream", C.c_void_p),
     ]
@@ -107,7 +108,7 @@ class Index:
                  tombstone_only: bool = False, publish_attempts: int = 8, max_batch: int = 10000,
                  vt_slots: int = 1024, waves_per_block: int = 4, id_capacity: int = 100000,
                  slab_capacity: Optional[int] = None, metric: int = METRIC_L2_U8, traversal: int = TRAV_NATIVE,
-                 rerank_mult: int = 4, copies: int = 0, stream=None):
+                 rerank_mult: int = 4, copies: int = 0, W: int = 1, stream=None):
         import torch
 
         self.torch = torch
@@ -120,7 +121,7 @@ class Index:
         self.traversal = traversal
         self.cfg = Config(dim, R, L_build, alpha[0], alpha[1], visit_mult, prune_cap, n_entry, int(refine),
                           int(tombstone_only), publish_attempts, max_batch, vt_slots, waves_per_block, metric,
-                          traversal, rerank_mult, copies, id_capacity, slab_capacity, None)
+                          traversal, rerank_mult, copies, W, 0, id_capacity, slab_capacity, None)
         s = stream if stream is not None else torch.cuda.current_stream()
         self.cfg.hip_stream = s.cuda_stream
         self.stream = s

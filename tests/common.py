@@ -11,25 +11,25 @@ def small_workload(n_base=2000, clusters=8, seed=1, batch=500, rounds=2, churn=0
                        rounds, churn, 200, 10, (64,), seed, batch, batch)
 
 
-def index_params(wl, n_entry=64, refine=True, tombstone_only=False, max_batch=None, slack=2):
+def index_params(wl, n_entry=64, refine=True, tombstone_only=False, max_batch=None, slack=2, W=1):
     cap = wl.id_capacity()
     mb = max_batch or max(wl.build_batch_max, wl.churn_count(), 1)
     return dict(dim=wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den), n_entry=n_entry,
                 refine=refine, tombstone_only=tombstone_only, id_capacity=cap,
-                slab_capacity=slack * cap + mb * (wl.R + 2), max_batch=mb)
+                slab_capacity=slack * cap + mb * (wl.R + 2), max_batch=mb, W=W)
 
 
 def make_oracle(p):
     return oracle.Oracle(oracle.METRIC_L2_U8, p["dim"], p["R"], p["L_build"], p["id_capacity"], p["slab_capacity"],
                          alpha=p["alpha"], n_entry=p["n_entry"], refine=p["refine"],
-                         tombstone_only=p["tombstone_only"])
+                         tombstone_only=p["tombstone_only"], W=p["W"])
 
 
 def make_gpu(p, **kw):
     from paper_2607_02543_amd import etale
     return etale.Index(p["dim"], R=p["R"], L_build=p["L_build"], alpha=p["alpha"], n_entry=p["n_entry"],
                        refine=p["refine"], tombstone_only=p["tombstone_only"], id_capacity=p["id_capacity"],
-                       slab_capacity=p["slab_capacity"], max_batch=p["max_batch"], **kw)
+                       slab_capacity=p["slab_capacity"], max_batch=p["max_batch"], W=p["W"], **kw)
 
 
 def assert_same_state(o, g, where=""):
@@ -67,7 +67,8 @@ def float_workload(n_base=1500, clusters=16, seed=1, batch=500, rounds=2, churn=
 def make_oracle_f(p, traversal=0, rerank_mult=4):
     return oracle.Oracle(oracle.METRIC_IP_F32, p["dim"], p["R"], p["L_build"], p["id_capacity"], p["slab_capacity"],
                          alpha=p["alpha"], n_entry=p["n_entry"], refine=p["refine"],
-                         tombstone_only=p["tombstone_only"], traversal=traversal, rerank_mult=rerank_mult)
+                         tombstone_only=p["tombstone_only"], traversal=traversal, rerank_mult=rerank_mult,
+                         W=p["W"])
 
 
 def make_gpu_f(p, traversal=0, rerank_mult=4, **kw):
@@ -75,7 +76,7 @@ def make_gpu_f(p, traversal=0, rerank_mult=4, **kw):
     return etale.Index(p["dim"], R=p["R"], L_build=p["L_build"], alpha=p["alpha"], n_entry=p["n_entry"],
                        refine=p["refine"], tombstone_only=p["tombstone_only"], id_capacity=p["id_capacity"],
                        slab_capacity=p["slab_capacity"], max_batch=p["max_batch"], metric=etale.METRIC_IP_F32,
-                       traversal=traversal, rerank_mult=rerank_mult, **kw)
+                       traversal=traversal, rerank_mult=rerank_mult, W=p["W"], **kw)
 
 
 def exact_ip_dist(q, x, ids):

@@ -67,12 +67,13 @@ def test_create_rejects_bad_configs_without_touching_a_device():
     lib = etale.load()
     good = dict(dim=128, R=32, L_build=64, alpha_num=6, alpha_den=5, visit_mult=4, prune_cap=256, n_entry=64,
                 refine=1, tombstone_only=0, publish_attempts=8, max_batch=100, vt_slots=1024, waves_per_block=4,
-                metric=0, traversal=0, rerank_mult=4, copies=0, id_capacity=1000, slab_capacity=5000,
+                metric=0, traversal=0, rerank_mult=4, copies=0, W=1, reserved=0, id_capacity=1000, slab_capacity=5000,
                 hip_stream=None)
     bad = [dict(dim=96), dict(R=0), dict(R=65), dict(L_build=0), dict(alpha_den=0), dict(prune_cap=8),
            dict(vt_slots=1000), dict(waves_per_block=3), dict(metric=7), dict(max_batch=5000), dict(n_entry=0),
            dict(id_capacity=0xFFFFFFFF), dict(metric=1, dim=128), dict(metric=1, dim=96, traversal=3),
-           dict(metric=1, dim=96, traversal=1, rerank_mult=65), dict(metric=1, dim=96, copies=4)]
+           dict(metric=1, dim=96, traversal=1, rerank_mult=65), dict(metric=1, dim=96, copies=4), dict(W=0),
+           dict(W=3), dict(W=2, R=48)]
     for change in bad:
         cfg = etale.Config(**{**good, **change})
         h = C.c_void_p()

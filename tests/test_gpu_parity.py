@@ -21,9 +21,9 @@ def _torch():
 
 
 def run_parity(wl, n_entry=64, refine=True, tombstone_only=False, search_L=(64,), k=10, n_queries=200,
-               reclaim=True, **gpu_kw):
+               reclaim=True, W=1, **gpu_kw):
     torch = _torch()
-    p = index_params(wl, n_entry=n_entry, refine=refine, tombstone_only=tombstone_only)
+    p = index_params(wl, n_entry=n_entry, refine=refine, tombstone_only=tombstone_only, W=W)
     o = make_oracle(p)
     g = make_gpu(p, **gpu_kw)
     st = dg.Stream(wl)
@@ -91,3 +91,8 @@ def test_parity_knob_invariance():
     wl = small_workload(seed=5, n_base=1500, rounds=1)
     run_parity(wl, vt_slots=64, waves_per_block=1)
     run_parity(wl, vt_slots=4096, waves_per_block=2)
+
+
+def test_parity_two_expansions_per_iteration():
+    # W = 2: two slabs read side by side by one wavefront
+    run_parity(small_workload(seed=6, rounds=2), W=2, search_L=(16, 64, 101))
