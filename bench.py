@@ -45,7 +45,36 @@ def parse():
     ap.add_argument("--workload", default="scale_u8_1m", choices=["scale_u8_1m", "precision_f32"])
     ap.add_argument("--prune-cap", type=int, default=0)
     ap.add_argument("--W", type=int, default=2, help="expansions per search iteration (1 or 2)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a known-size reference for DRAM counters)")
     return ap.parse_args()
+
+
+def measured_traffic(L, args):
+    """HBM bytes of one k_search launch from the committed DRAM-counter summary.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
+    counters read for a device copy of known size. Returns None unless the
+    summary was taken on these kernel sources, at this L and in this launch
+    configuration (its counters describe that kernel only).
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_search_traffic_scale_u8_1m.md")
+    if not os.path.exists(path) or args.n_base != 1_000_000 or args.queries != 10_000 \
+            or args.W != 2 or args.n_entry != 8192:
+        return None
+    kv = {}
+    for line in open(path):
+        line = line.strip()
+        if "=" in line and " " not in line:
+            k_, v = line.split("=", 1)
+            kv[k_] = v
+    src = b"".join(open(os.path.join(ROOT, "paper_2607_02543_amd", "csrc", f), "rb").read()
+                   for f in ("etale_kernels.hip", "etale_dev.h", "etale_float.h"))
+    if kv.get("kernel_sources_sha256") != hashlib.sha256(src).hexdigest() or int(kv.get("L", -1)) != L:
+        return None
+    return int((float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                float(kv["write_kib"]) * float(kv["write_scale"])) * 1024)
 
 
 def log(args, *a):
@@ -269,6 +298,12 @@ def main():
         ix.reclaim()
 
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy_mib:
+        src = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         apply_round(*churn_round())
         for L in Ls:
@@ -279,6 +314,9 @@ def main():
     inputs = [churn_round() for _ in range(args.steps)]
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 + len(Ls))] for _ in range(args.steps)]
     counts = {L: [] for L in Ls}
+    stage = {L: [] for L in Ls}
+    ix.set_search_timing(True)
+    ix.search_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s_ in range(args.steps):
@@ -291,6 +329,14 @@ def main():
             counts[L].append(cnt)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # per-stage kernel durations of every timed search launch (HIP events on the index's stream)
+    ix.set_search_timing(False)
+    tm = ix.search_timing()
+    assert tm.shape[0] == args.steps * len(Ls), "one launch per search call expected"
+    tm = tm.reshape(args.steps, len(Ls), 3)
+    for j, L in enumerate(Ls):
+        stage[L] = {"scan_ms": float(tm[:, j, 0].mean()), "select_ms": float(tm[:, j, 1].mean()),
+                    "search_ms": float(tm[:, j, 2].mean())}
     maint_ms = [ev[s_][0].elapsed_time(ev[s_][1]) for s_ in range(args.steps)]
     search_ms = {L: [ev[s_][1 + j].elapsed_time(ev[s_][2 + j]) for s_ in range(args.steps)] for j, L in enumerate(Ls)}
     stats = ix.stats()
@@ -305,18 +351,20 @@ def main():
         c = torch.stack(counts[L]).cpu().numpy().astype(np.int64)
         E, U = c[..., 0].sum(1).mean(), c[..., 1].sum(1).mean()
         t = float(np.mean(search_ms[L])) * 1e-3
-        # algorithmic bytes of one launch: per expansion the 8-byte reference and
-        # the slab's 4R-byte id half; per traversal distance one vector row; the
-        # entry set is one dense block every query of the launch scores, so its
-        # rows count once per launch; plus query rows and k results per query.
+        # k_search's algorithmic bytes per launch: per expansion the slab's 4R-byte
+        # id half; per traversal distance one vector row plus its 8-byte reference
+        # (fetched with the row); per query its row, its initial list (L keys in,
+        # L references gathered) and k results out.
         U_trav = U - S * args.queries
-        nbytes = E * (8 + 4 * wl.R) + U_trav * wl.dim + S * wl.dim + args.queries * (wl.dim + 8 * 10)
+        nbytes = E * 4 * wl.R + U_trav * (wl.dim + 8) + args.queries * (wl.dim + 16 * L + 8 * 10)
+        t_k = stage[L]["search_ms"] * 1e-3  # one k_search launch
         sweep[L] = {"recall_at_10": round(recall(ids_s.cpu().numpy(), gt), 4),
                     "qps": round(args.queries / t, 1), "search_ms": round(t * 1e3, 4),
+                    "stage_ms": {k_: round(v, 4) for k_, v in stage[L].items()},
                     "expansions_per_query": round(float(E) / args.queries, 2),
                     "traversal_distances_per_query": round(float(U_trav) / args.queries, 2),
-                    "entry_distances_per_query": S, "bytes_per_launch": int(nbytes),
-                    "achieved_GBps": round(nbytes / t / 1e9, 1)}
+                    "entry_distances_per_query": S, "k_search_bytes_per_launch": int(nbytes),
+                    "k_search_GBps": round(nbytes / t_k / 1e9, 1)}
         log(args, f"L={L}", sweep[L])
     ok = [L for L in Ls if sweep[L]["recall_at_10"] >= args.target_recall]
     L_star = min(ok) if ok else max(Ls)
@@ -347,9 +395,11 @@ def main():
         "slabs_resident": stats["resident_slabs"],
         "live": stats["live"],
         "device_bytes": stats["device_bytes"],
-        "roofline": {"bound": "hbm", "kernel": "k_search", "achieved": best["achieved_GBps"], "peak": 8000.0,
-                     "unit": "GB/s", "frac": round(best["achieved_GBps"] / 8000.0, 4), "traffic": None,
-                     "bytes_per_launch": best["bytes_per_launch"], "launch_ms": best["search_ms"]},
+        "roofline": {"bound": "hbm", "kernel": "k_search", "achieved": best["k_search_GBps"], "peak": 8000.0,
+                     "unit": "GB/s", "frac": round(best["k_search_GBps"] / 8000.0, 4),
+                     "traffic": measured_traffic(L_star, args),
+                     "bytes_per_launch": best["k_search_bytes_per_launch"],
+                     "launch_ms": best["stage_ms"]["search_ms"]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, L_star, args.cpu_sample)

@@ -202,6 +202,15 @@ etale_status etale_set_lists(etale_t ix, uint64_t n, const uint32_t* ids_host, c
  * copy is not kept. Synchronizes. */
 etale_status etale_export_rows(etale_t ix, uint64_t first, uint64_t n, int32_t which, void* out_host);
 
+/* Stage timing of search calls: when enabled, HIP events are recorded on the
+ * index's stream around each start-set block kernel, start-set select kernel
+ * and beam-search kernel of every search launch. etale_get_search_timing
+ * synchronizes, writes up to cap launches as (scan, select, search)
+ * millisecond triples in launch order into ms_host (cap x 3), the number of
+ * recorded launches into *launches, and forgets them. */
+etale_status etale_set_search_timing(etale_t ix, int32_t enable);
+etale_status etale_get_search_timing(etale_t ix, float* ms_host, uint64_t cap, uint64_t* launches);
+
 /* Wait for the index's stream. */
 etale_status etale_sync(etale_t ix);
 

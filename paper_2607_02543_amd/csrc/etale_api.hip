@@ -3,6 +3,7 @@
 // etale_kernels.hip; this file only moves sizes, pointers and counters.
 #include <rocprim/device/device_radix_sort.hpp>
 
+#include <array>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,10 @@ struct etale_index {
   uint64_t live = 0;              // ids with deletion flag 0 (host mirror)
   int32_t qtrav = 0;              // query-side traversal copy
   uint32_t qrerank = 0;
+  // opt-in stage timing of search calls: event quadruples per launch
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::array<hipEvent_t, 4>> ev_used;
   void* sort_tmp = nullptr;
   size_t sort_tmp_bytes = 0;
   uint64_t next_id = 0;
@@ -167,10 +172,30 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t 
     sc.out_n = ix->scan_n;
     sc.out_stride = L;
     sc.trav = mode == MODE_QUERY ? ix->qtrav : ix->dev.trav;
+    std::array<hipEvent_t, 4> ev{};
+    const bool timed = ix->timing && mode == MODE_QUERY;
+    if (timed) {
+      for (auto& e : ev) {
+        if (ix->ev_pool.empty()) {
+          hipEvent_t ne;
+          HIP_TRY(hipEventCreate(&ne));
+          ix->ev_pool.push_back(ne);
+        }
+        e = ix->ev_pool.back();
+        ix->ev_pool.pop_back();
+      }
+      ix->ev_used.push_back(ev);
+      HIP_TRY(hipEventRecord(ev[0], ix->stream));
+    }
     if (ns == 0) {
       HIP_TRY(hipMemsetAsync(ix->scan_n, 0, (size_t)cn * 4, ix->stream));
+      if (timed) {
+        HIP_TRY(hipEventRecord(ev[1], ix->stream));
+        HIP_TRY(hipEventRecord(ev[2], ix->stream));
+      }
     } else {
-      HIP_TRY(launch_scan(ix->dev, sc, ix->stream));
+      HIP_TRY(launch_scan(ix->dev, sc, ix->stream, timed ? ev[1] : nullptr));
+      if (timed) HIP_TRY(hipEventRecord(ev[2], ix->stream));
     }
     SearchArgs sa{};
     sa.mode = mode;
@@ -197,6 +222,7 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t 
       sa.vis_cnt = ix->vis_cnt + c;
     }
     HIP_TRY(launch_search(ix->dev, sa, search_waves_per_block(ix, sa.lds_per_wave), ix->stream));
+    if (timed) HIP_TRY(hipEventRecord(ev[3], ix->stream));
   }
   return ETALE_OK;
 }
@@ -352,6 +378,9 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
 etale_status etale_destroy(etale_t ix) {
   if (!ix) return ETALE_OK;
   (void)hipStreamSynchronize(ix->stream);
+  for (auto& q : ix->ev_used)
+    for (hipEvent_t e : q) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ix->ev_pool) (void)hipEventDestroy(e);
   for (void* p : ix->allocs) (void)hipFree(p);
   delete ix;
   return ETALE_OK;
@@ -663,6 +692,31 @@ etale_status etale_export_rows(etale_t ix, uint64_t first, uint64_t n, int32_t w
   HIP_TRY(hipMemcpyAsync(out_host, (const uint8_t*)src + first * row_bytes, n * row_bytes, hipMemcpyDeviceToHost,
                          ix->stream));
   HIP_TRY(hipStreamSynchronize(ix->stream));
+  return ETALE_OK;
+}
+
+etale_status etale_set_search_timing(etale_t ix, int32_t enable) {
+  CHECK_HANDLE();
+  ix->timing = enable != 0;
+  return ETALE_OK;
+}
+
+etale_status etale_get_search_timing(etale_t ix, float* ms_host, uint64_t cap, uint64_t* launches) {
+  CHECK_HANDLE();
+  if ((!ms_host && cap) || !launches) return ETALE_EINVAL;
+  HIP_TRY(hipStreamSynchronize(ix->stream));
+  uint64_t n = 0;
+  for (auto& q : ix->ev_used) {
+    for (int i = 0; i < 3 && n < cap; ++i) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, q[i], q[i + 1]));
+      ms_host[n * 3 + i] = ms;
+    }
+    ++n;
+    for (hipEvent_t e : q) ix->ev_pool.push_back(e);
+  }
+  *launches = ix->ev_used.size();
+  ix->ev_used.clear();
   return ETALE_OK;
 }
 

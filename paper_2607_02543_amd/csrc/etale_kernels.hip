@@ -1189,7 +1189,7 @@ uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots) {
 // lanes per row of a float copy: 3 chunks of 16 bytes per lane
 static inline int float_lanes(uint32_t dim, int elem_bytes) { return (int)(dim * (uint32_t)elem_bytes / 16u / 3u); }
 
-hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s) {
+hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEvent_t after_dist) {
   if (a.nq == 0 || a.ns == 0) return hipSuccess;
   const dim3 dgrid(blocks_for(a.ns, SD_E), blocks_for(a.nq, SD_Q));
   if (ix.metric == 0) {
@@ -1202,6 +1202,10 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(k_scan_dist_f<TRAV_BF16>, dgrid, dim3(256), 0, s, ix, a);
     else
       hipLaunchKernelGGL(k_scan_dist_f<TRAV_FP8>, dgrid, dim3(256), 0, s, ix, a);
+  }
+  if (after_dist) {
+    const hipError_t e = hipEventRecord(after_dist, s);
+    if (e != hipSuccess) return e;
   }
   const uint32_t cap = (uint32_t)next_pow2_ge64((int)a.L);
   const dim3 grid(blocks_for(a.nq, 4)), blk(256);

@@ -69,7 +69,7 @@ hipError_t launch_write_ids(uint32_t* out, uint32_t first, uint64_t n, hipStream
 hipError_t launch_refresh_entries(const Index& ix, uint32_t next_id, uint32_t S, hipStream_t s);
 uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots);
 uint32_t scan_select_lds_per_wave(uint32_t L);
-hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s);
+hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEvent_t after_dist = nullptr);
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s);
 uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R);
 hipError_t launch_maint(MaintKernel which, const Index& ix, const MaintArgs& a, uint32_t nwaves,

@@ -85,6 +85,8 @@ def load() -> C.CDLL:
         "etale_set_lists": ([vp, u64, vp, vp, vp], i32),
         "etale_set_query_traversal": ([vp, i32, u32], i32),
         "etale_export_rows": ([vp, u64, u64, i32, vp], i32),
+        "etale_set_search_timing": ([vp, i32], i32),
+        "etale_get_search_timing": ([vp, vp, u64, C.POINTER(u64)], i32),
         "etale_sync": ([vp], i32),
         "etale_last_error": ([vp], C.c_char_p),
     }
@@ -251,3 +253,14 @@ class Index:
             out = np.zeros(n, np.float32)
         self._check(self.lib.etale_export_rows(self.h, first, n, which, out.ctypes.data_as(C.c_void_p)), "export_rows")
         return out
+
+    def set_search_timing(self, enable: bool = True):
+        self._check(self.lib.etale_set_search_timing(self.h, int(enable)), "set_search_timing")
+
+    def search_timing(self, cap: int = 4096) -> np.ndarray:
+        """(scan, select, search) milliseconds of each timed search launch since the last read."""
+        ms = np.zeros((cap, 3), np.float32)
+        n = C.c_uint64(0)
+        self._check(self.lib.etale_get_search_timing(self.h, ms.ctypes.data_as(C.c_void_p), cap, C.byref(n)),
+                    "get_search_timing")
+        return ms[:min(n.value, cap)].copy()
