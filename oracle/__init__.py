@@ -53,6 +53,7 @@ def _load():
         lib.oracle_insert.argtypes = [vp, vp, u64, vp]
         lib.oracle_delete.argtypes = [vp, vp, u64, vp]
         lib.oracle_reclaim.argtypes = [vp]
+        lib.oracle_round.argtypes = [vp, vp, u64, vp, vp, u64, vp, vp, u64, u32, u32, vp, vp, i32]
         lib.oracle_search.argtypes = [vp, vp, u64, u32, u32, vp, vp, vp, vp]
         lib.oracle_beam_search.argtypes = [vp, vp, u32, u32, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_robust_prune.argtypes = [vp, u32, vp, u64, vp, vp, vp]
@@ -128,6 +129,25 @@ class Oracle:
         rc = self.lib.oracle_reclaim(self.h)
         if rc:
             raise OracleError(rc, "reclaim")
+
+    def round(self, del_ids=None, x: Optional[np.ndarray] = None, q: Optional[np.ndarray] = None, k: int = 10,
+              L: int = 64, reclaim: bool = False):
+        """One round: deletes, inserts and queries in one epoch (queries and
+        insert searches see the state after this round's tombstones), then an
+        optional reclaim. Returns (delete statuses, new ids, result ids, result
+        distances)."""
+        dl = np.ascontiguousarray(np.zeros(0) if del_ids is None else del_ids, dtype=np.uint32)
+        x = self._vecs(np.zeros((0, self.dim)) if x is None else x)
+        q = self._vecs(np.zeros((0, self.dim)) if q is None else q)
+        st = np.zeros(dl.size, np.uint8)
+        ids = np.zeros(x.shape[0], np.uint32)
+        qi = np.zeros((q.shape[0], k), np.uint32)
+        qd = np.zeros((q.shape[0], k), np.int32 if self.metric == METRIC_L2_U8 else np.float64)
+        rc = self.lib.oracle_round(self.h, _p(dl), dl.size, _p(st), _p(x), x.shape[0], _p(ids), _p(q), q.shape[0],
+                                   k, L, _p(qi), _p(qd), int(reclaim))
+        if rc:
+            raise OracleError(rc, "round")
+        return st, ids, qi, qd
 
     def search(self, q: np.ndarray, k: int, L: int, counts: bool = False):
         q = self._vecs(q)

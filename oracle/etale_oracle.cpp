@@ -304,13 +304,42 @@ struct Oracle {
       if (!del[u]) entries.push_back((uint32_t)u);
   }
 
-  // ---- insert call (Algorithm 2 over a batch; one launch) -------------------
-  int insert(const void* vecs, uint64_t n, uint32_t* ids_out) {
-    if (n == 0) return OK;
-    if (next_id + n > cap) return ECAPACITY;
-    if (free_cnt < n * (uint64_t)(R + 2)) return EPOOL;
+  // ---- phases of one launch epoch (Definition 2) ---------------------------
+  // Each phase reads the state the previous one left. An insert call runs
+  // P0 (ids) P1 P2 P4 P5, a delete call P0 (tombstones) P3, and a round runs
+  // all of them: P0, P1 (insert and query searches on the same state), P2,
+  // P3, P4, P5, then the recycle that ends the epoch.
+
+  // P0, deletes: per-position status; the accepted ids, ascending.
+  std::vector<uint32_t> classify_deletes(const uint32_t* ids, uint64_t n, uint8_t* status) const {
+    std::vector<uint32_t> Dl;
+    for (uint64_t i = 0; i < n; ++i) {
+      uint32_t u = ids[i];
+      bool dup = false;
+      for (uint64_t j = 0; j < i && !dup; ++j) dup = ids[j] == u;
+      uint8_t st;
+      if (dup)
+        st = DEL_DUPLICATE;
+      else if (u >= next_id)
+        st = DEL_OUT_OF_RANGE;
+      else if (del[u])
+        st = DEL_NOT_LIVE;
+      else {
+        st = DEL_OK;
+        Dl.push_back(u);
+      }
+      if (status) status[i] = st;
+    }
+    std::sort(Dl.begin(), Dl.end());
+    return Dl;
+  }
+  // P0, tombstones: the flag is set, degree and slab kept
+  void tombstone(const std::vector<uint32_t>& Dl) {
+    for (uint32_t u : Dl) del[u] = 1;
+  }
+  // P0, inserts: ids in input order, vectors (and their bf16 / fp8 copies)
+  uint32_t store_rows(const void* vecs, uint64_t n, uint32_t* ids_out) {
     const uint32_t first = (uint32_t)next_id;
-    // P0: ids in input order, vectors (and their bf16 / fp8 copies) stored
     for (uint64_t i = 0; i < n; ++i) {
       uint32_t v = first + (uint32_t)i;
       if (ids_out) ids_out[i] = v;
@@ -330,10 +359,12 @@ struct Oracle {
       }
     }
     next_id += n;
-    const bool bootstrap = entries.empty();
+    return first;
+  }
+  // P1: candidate sets of the new nodes, from the state at the epoch's start;
+  // bootstrap (no live node): the visit_cap nearest other batch members
+  std::vector<std::vector<uint32_t>> candidates(uint32_t first, uint64_t n, bool bootstrap) {
     const uint32_t vcap = visit_cap(L_build);
-
-    // P1: candidate sets, all from the state at the call's start
     std::vector<std::vector<uint32_t>> cand(n);
     for (uint64_t i = 0; i < n; ++i) {
       uint32_t v = first + (uint32_t)i;
@@ -349,7 +380,10 @@ struct Oracle {
         for (const Entry& e : all) cand[i].push_back(e.id);
       }
     }
-    // P2: forward neighbors, own slab (uncontended)
+    return cand;
+  }
+  // P2: forward neighbors, own slab (uncontended)
+  std::vector<std::vector<Entry>> forward(uint32_t first, uint64_t n, const std::vector<std::vector<uint32_t>>& cand) {
     std::vector<std::vector<Entry>> F(n);
     for (uint64_t i = 0; i < n; ++i) {
       uint32_t v = first + (uint32_t)i;
@@ -357,7 +391,39 @@ struct Oracle {
       publish(v, F[i]);
       ++pub_forward;
     }
-    // P4: reverse edges, sorted by (target, source), one publish per target
+    return F;
+  }
+  // P3: repair every live out-neighbor a of each deleted u, pairs sorted by
+  // (a, u), one publication per a (Algorithm 3)
+  void repair(const std::vector<uint32_t>& Dl) {
+    std::vector<std::pair<uint32_t, uint32_t>> pairs;
+    for (uint32_t u : Dl)
+      for (const Entry& a : adj[u])
+        if (!del[a.id]) pairs.push_back({a.id, u});
+    std::sort(pairs.begin(), pairs.end());
+    for (size_t i = 0; i < pairs.size();) {
+      uint32_t a = pairs[i].first;
+      std::vector<Entry> N = adj[a];
+      size_t j = i;
+      for (; j < pairs.size() && pairs[j].first == a; ++j) {
+        uint32_t u = pairs[j].second;
+        std::vector<uint32_t> B;
+        for (const Entry& b : adj[u])
+          if (b.id != a) B.push_back(b.id);
+        std::vector<Entry> K = robust_prune(a, B);
+        std::vector<uint32_t> c;
+        for (const Entry& x : N)
+          if (x.id != u) c.push_back(x.id);
+        for (const Entry& x : K) c.push_back(x.id);
+        N = robust_prune(a, c);
+      }
+      publish(a, N);
+      ++pub_repair;
+      i = j;
+    }
+  }
+  // P4: reverse edges, sorted by (target, source), one publish per target
+  void reverse(uint32_t first, uint64_t n, const std::vector<std::vector<Entry>>& F) {
     std::vector<std::pair<uint32_t, uint32_t>> pairs;
     for (uint64_t i = 0; i < n; ++i)
       for (const Entry& w : F[i])
@@ -386,33 +452,46 @@ struct Oracle {
       ++pub_reverse;
       a = b;
     }
-    // P5: refine -- offer each new node the same-batch nodes two hops away
-    if (refine && !bootstrap) {
-      const uint32_t end = first + (uint32_t)n;
-      for (uint64_t i = 0; i < n; ++i) {
-        uint32_t v = first + (uint32_t)i;
-        std::vector<uint32_t> c;
-        for (const Entry& x : adj[v]) c.push_back(x.id);
-        const size_t own = c.size();
-        for (const Entry& w : adj[v])
-          for (const Entry& b : adj[w.id])
-            if (b.id >= first && b.id < end && b.id != v) c.push_back(b.id);
-        bool extra = false;
-        for (size_t j = own; j < c.size() && !extra; ++j) {
-          bool in = false;
-          for (size_t t = 0; t < own; ++t) in = in || c[t] == c[j];
-          extra = !in;
-        }
-        if (!extra) continue;
-        std::vector<Entry> N = robust_prune(v, c);
-        bool same = N.size() == adj[v].size();
-        for (size_t t = 0; same && t < N.size(); ++t) same = N[t].id == adj[v][t].id;
-        if (!same) {
-          publish(v, N);
-          ++pub_refine;
-        }
+  }
+  // P5: refine -- offer each new node the same-batch nodes two hops away
+  void refine_pass(uint32_t first, uint64_t n) {
+    const uint32_t end = first + (uint32_t)n;
+    for (uint64_t i = 0; i < n; ++i) {
+      uint32_t v = first + (uint32_t)i;
+      std::vector<uint32_t> c;
+      for (const Entry& x : adj[v]) c.push_back(x.id);
+      const size_t own = c.size();
+      for (const Entry& w : adj[v])
+        for (const Entry& b : adj[w.id])
+          if (b.id >= first && b.id < end && b.id != v) c.push_back(b.id);
+      bool extra = false;
+      for (size_t j = own; j < c.size() && !extra; ++j) {
+        bool in = false;
+        for (size_t t = 0; t < own; ++t) in = in || c[t] == c[j];
+        extra = !in;
+      }
+      if (!extra) continue;
+      std::vector<Entry> N = robust_prune(v, c);
+      bool same = N.size() == adj[v].size();
+      for (size_t t = 0; same && t < N.size(); ++t) same = N[t].id == adj[v][t].id;
+      if (!same) {
+        publish(v, N);
+        ++pub_refine;
       }
     }
+  }
+
+  // ---- insert call (Algorithm 2 over a batch; one launch) -------------------
+  int insert(const void* vecs, uint64_t n, uint32_t* ids_out) {
+    if (n == 0) return OK;
+    if (next_id + n > cap) return ECAPACITY;
+    if (free_cnt < n * (uint64_t)(R + 2)) return EPOOL;
+    const uint32_t first = store_rows(vecs, n, ids_out);
+    const bool bootstrap = entries.empty();
+    auto cand = candidates(first, n, bootstrap);
+    auto F = forward(first, n, cand);
+    reverse(first, n, F);
+    if (refine && !bootstrap) refine_pass(first, n);
     refresh_entries();
     recycle();
     return OK;
@@ -420,58 +499,39 @@ struct Oracle {
 
   // ---- delete call (Algorithm 3 over a batch; one launch) -------------------
   int remove(const uint32_t* ids, uint64_t n, uint8_t* status) {
-    std::vector<uint32_t> Dl;
-    std::vector<uint32_t> seen;
-    for (uint64_t i = 0; i < n; ++i) {
-      uint32_t u = ids[i];
-      bool dup = false;
-      for (uint64_t j = 0; j < i && !dup; ++j) dup = ids[j] == u;
-      uint8_t st;
-      if (dup)
-        st = DEL_DUPLICATE;
-      else if (u >= next_id)
-        st = DEL_OUT_OF_RANGE;
-      else if (del[u])
-        st = DEL_NOT_LIVE;
-      else {
-        st = DEL_OK;
-        Dl.push_back(u);
-      }
-      if (status) status[i] = st;
-    }
+    std::vector<uint32_t> Dl = classify_deletes(ids, n, status);
     if (!tombstone_only && free_cnt < Dl.size() * (uint64_t)R) return EPOOL;
-    std::sort(Dl.begin(), Dl.end());
-    // tombstone: the flag is set, degree and slab kept
-    for (uint32_t u : Dl) del[u] = 1;
+    tombstone(Dl);
     refresh_entries();
-    if (!tombstone_only) {
-      // repair every live out-neighbor a of each deleted u, sorted by (a, u)
-      std::vector<std::pair<uint32_t, uint32_t>> pairs;
-      for (uint32_t u : Dl)
-        for (const Entry& a : adj[u])
-          if (!del[a.id]) pairs.push_back({a.id, u});
-      std::sort(pairs.begin(), pairs.end());
-      for (size_t i = 0; i < pairs.size();) {
-        uint32_t a = pairs[i].first;
-        std::vector<Entry> N = adj[a];
-        size_t j = i;
-        for (; j < pairs.size() && pairs[j].first == a; ++j) {
-          uint32_t u = pairs[j].second;
-          std::vector<uint32_t> B;
-          for (const Entry& b : adj[u])
-            if (b.id != a) B.push_back(b.id);
-          std::vector<Entry> K = robust_prune(a, B);
-          std::vector<uint32_t> c;
-          for (const Entry& x : N)
-            if (x.id != u) c.push_back(x.id);
-          for (const Entry& x : K) c.push_back(x.id);
-          N = robust_prune(a, c);
-        }
-        publish(a, N);
-        ++pub_repair;
-        i = j;
-      }
-    }
+    if (!tombstone_only) repair(Dl);
+    recycle();
+    return OK;
+  }
+
+  // ---- round: deletes, inserts and queries in one launch epoch ---------------
+  // The queries and the insert searches see the same state: the one left by
+  // the tombstones (and the entry-set update) of this round, before any
+  // repair or publication. Both checks run before any mutation.
+  int round(const uint32_t* dids, uint64_t nd, uint8_t* status, const void* vecs, uint64_t ni, uint32_t* ids_out,
+            const void* q, uint64_t nq, uint32_t k, uint32_t L, uint32_t* qids, void* qd) {
+    std::vector<uint32_t> Dl = classify_deletes(dids, nd, status);
+    if (next_id + ni > cap) return ECAPACITY;
+    const uint64_t need = ni * (uint64_t)(R + 2) + (tombstone_only ? 0 : Dl.size() * (uint64_t)R);
+    if (free_cnt < need) return EPOOL;
+    tombstone(Dl);
+    refresh_entries();
+    const uint32_t first = store_rows(vecs, ni, ids_out);
+    const bool bootstrap = entries.empty();
+    auto cand = candidates(first, ni, bootstrap);
+    const size_t qb = metric == M_L2_U8 ? dim : dim * sizeof(float);
+    const size_t db = metric == M_L2_U8 ? sizeof(int32_t) : sizeof(double);
+    for (uint64_t i = 0; i < nq; ++i)
+      search((const uint8_t*)q + i * qb, k, L, qids + i * k, (uint8_t*)qd + i * k * db, nullptr, nullptr);
+    auto F = forward(first, ni, cand);
+    if (!tombstone_only) repair(Dl);
+    reverse(first, ni, F);
+    if (refine && !bootstrap) refine_pass(first, ni);
+    refresh_entries();
     recycle();
     return OK;
   }
@@ -596,6 +656,18 @@ int oracle_delete(void* h, const uint32_t* ids, uint64_t n, uint8_t* status_out)
 }
 
 int oracle_reclaim(void* h) { return ((Oracle*)h)->reclaim(); }
+
+// One round: deletes, inserts and queries in one epoch, then (reclaim != 0)
+// the reclaim call. Query results as for oracle_search.
+int oracle_round(void* h, const uint32_t* del_ids, uint64_t nd, uint8_t* status_out, const void* vecs, uint64_t ni,
+                 uint32_t* ids_out, const void* q, uint64_t nq, uint32_t k, uint32_t L, uint32_t* qids, void* qdists,
+                 int reclaim) {
+  Oracle* o = (Oracle*)h;
+  if (nq && (k == 0 || k > L)) return EINVAL;
+  int rc = o->round(del_ids, nd, status_out, vecs, ni, ids_out, q, nq, k, L, qids, qdists);
+  if (rc == OK && reclaim) rc = o->reclaim();
+  return rc;
+}
 
 // dists: int32 per result for the u8 metric, double for the float metric.
 // expansions / distances (optional): per-query counts of expanded nodes and
