@@ -14,6 +14,9 @@
  *   etale_search_batch   the query side of the problem statement (3.1): a
  *                        greedy beam search whose output admits only nodes
  *                        whose reference has deletion flag 0 (3.4.2)
+ *   etale_round          deletes, inserts and queries of one round in one
+ *                        launch epoch (Definition 2), counts read on the
+ *                        device, optionally replayed from a HIP graph
  *
  * Round semantics. Every mutating call is one round: its phases run in a
  * fixed order and each phase reads the state the previous one left. The
@@ -163,6 +166,62 @@ etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint
  * number of dirty nodes must be covered by free slabs, else ETALE_EPOOL with
  * nothing changed. A no-op in tombstone-only mode. */
 etale_status etale_reclaim(etale_t ix);
+
+/* One round (Definition 2 over a mixed batch): deletes, inserts and queries
+ * in one launch epoch, phases in this order:
+ *   P0  classify the deletes (as etale_delete_batch), check id space and the
+ *       worst-case slab demand n_ins*(R+2) + n_del_accepted*R (n_ins*(R+2)
+ *       with tombstone_only), then tombstone, update the entry set and hand
+ *       out the new ids in input order;
+ *   P1  the insert searches (or the bootstrap, when no live node is left) and
+ *       the queries, all on the state P0 left;
+ *   P2  forward prunes; P3 repairs (Algorithm 3); P4 reverse edges; P5 refine
+ *       (as the separate calls); then the retired slabs are recycled;
+ *   and, with reclaim != 0, the reclaim call (Algorithm 4).
+ * A round without deletes and queries is etale_insert_batch, one with only
+ * deletes is etale_delete_batch.
+ *
+ * Counts: `counts` (device, [3] = deletes, inserts, queries) is read by the
+ * kernels when they run, so a round can be enqueued before its inputs are
+ * known; NULL means the max_* values are the counts. The max_* values fix the
+ * launch shapes and the buffer sizes: del_ids [max_del], del_status
+ * [max_del] (optional), ins_vecs [max_ins x dim] (uint8 or FP32), ins_ids
+ * [max_ins] (optional), queries [max_q x dim], q_ids / q_dists [max_q x k]
+ * (int32 distances for the uint8 metric, FP32 for the float metric). All are
+ * device pointers owned by the caller.
+ *
+ * Status: status (device, int32 [2]) receives the round status (ETALE_OK,
+ * ETALE_EPOOL, ETALE_ECAPACITY, or ETALE_EINVAL for counts above their max or
+ * a bootstrap batch above 16384) and the reclaim status (ETALE_OK or
+ * ETALE_EPOOL). A failed round changes no index state (per-id delete statuses
+ * are still written: they are the classification, not a change); a failed
+ * reclaim changes nothing either. The call itself only checks its arguments
+ * and returns before the device work ends; read status after etale_sync.
+ *
+ * graph != 0: the round's launches are captured into a HIP graph on first
+ * use and replayed on later calls with the same descriptor (buffers, max_*,
+ * k, L, reclaim) and query traversal; write the next round's inputs and
+ * counts into the same buffers and call again. Returns before the device work
+ * ends, like every stream-ordered call. */
+typedef struct {
+  const uint32_t* del_ids;
+  uint8_t* del_status;
+  uint32_t max_del;
+  const void* ins_vecs;
+  uint32_t* ins_ids;
+  uint32_t max_ins;
+  const void* queries;
+  uint32_t* q_ids;
+  void* q_dists;
+  uint32_t max_q;
+  uint32_t k, L;
+  const uint32_t* counts;
+  int32_t* status;
+  int32_t reclaim;
+  int32_t graph;
+} etale_round_desc;
+
+etale_status etale_round(etale_t ix, const etale_round_desc* desc);
 
 /* Exact k nearest live nodes of each query by (distance, id), 1 <= k <= 16,
  * from the uint8 / FP32 rows: the plain definition used to measure recall. */

@@ -1,9 +1,10 @@
 // C-ABI of the ETALE index: argument checks, device memory, and the order of
 // the phase launches of each call. Every numeric step runs in the kernels of
 // etale_kernels.hip; this file only moves sizes, pointers and counters.
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include <array>
+#include <cstdio>
+#include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -37,21 +38,26 @@ struct etale_index {
   uint32_t* dlist = nullptr;
   uint32_t* dirty = nullptr;
   uint64_t* bitmap = nullptr;
+  uint32_t* seg = nullptr;        // run starts of a sorted pair list
+  uint32_t* hist = nullptr;       // radix-sort digit counts
+  int32_t* status = nullptr;      // round status words of the calls that do not take one
+  uint32_t pair_bits = 0;         // bits of an id (the sort range of pair targets)
   uint64_t* scan_keys = nullptr;  // [scan_chunk x 256] initial lists
   uint32_t* scan_n = nullptr;
   uint32_t* scan_dist = nullptr;  // [dist_cap] query x start-set distances
   uint64_t dist_cap = 0;
   uint32_t scan_chunk = 0;
-  uint64_t live = 0;              // ids with deletion flag 0 (host mirror)
+  uint64_t live = 0;
   int32_t qtrav = 0;              // query-side traversal copy
   uint32_t qrerank = 0;
   // opt-in stage timing of search calls: event quadruples per launch
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::array<hipEvent_t, 4>> ev_used;
-  void* sort_tmp = nullptr;
-  size_t sort_tmp_bytes = 0;
-  uint64_t next_id = 0;
+  // captured rounds, keyed by the descriptor they were captured from
+  hipStream_t cap_stream = nullptr;
+  std::map<std::string, hipGraphExec_t> graphs;
+  uint64_t next_id = 0;           // host mirrors of C_NEXT_ID / C_LIVE, refreshed by read_counters
   uint32_t vcap_build = 0;
   uint64_t bytes = 0;
   bool poisoned = false;
@@ -101,22 +107,25 @@ etale_status read_counters(etale_index* ix, unsigned long long* h) {
     ix->poisoned = true;
     return fail(ix, ETALE_ESTATE, "device invariant violated, error bits " + std::to_string(h[C_ERROR]));
   }
+  ix->next_id = h[C_NEXT_ID];
+  ix->live = h[C_LIVE];
   return ETALE_OK;
 }
 
-etale_status set_counter(etale_index* ix, Counter c, unsigned long long v) {
-  HIP_TRY(hipMemcpyAsync(ix->ctr + c, &v, sizeof(v), hipMemcpyHostToDevice, ix->stream));
-  HIP_TRY(hipStreamSynchronize(ix->stream));
-  return ETALE_OK;
+etale_status refresh_mirror(etale_index* ix) {
+  unsigned long long h[C_NCOUNTERS];
+  return read_counters(ix, h);
 }
 
-etale_status sort_keys(etale_index* ix, uint64_t* in, uint64_t* out, size_t n) {
-  if (n == 0) return ETALE_OK;
-  size_t bytes = 0;
-  HIP_TRY(rocprim::radix_sort_keys(nullptr, bytes, in, out, n, 0, 64, ix->stream));
-  if (bytes > ix->sort_tmp_bytes) return fail(ix, ETALE_EDEVICE, "sort scratch too small");
-  bytes = ix->sort_tmp_bytes;
-  HIP_TRY(rocprim::radix_sort_keys(ix->sort_tmp, bytes, in, out, n, 0, 64, ix->stream));
+// the round's status words, after the stream has drained
+etale_status round_status(etale_index* ix, const char* what) {
+  int32_t st[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(st, ix->status, sizeof(st), hipMemcpyDeviceToHost, ix->stream));
+  if (etale_status e = refresh_mirror(ix)) return e;
+  if (st[0] == ETALE_EPOOL) return fail(ix, ETALE_EPOOL, std::string(what) + ": slab pool cannot cover the worst case");
+  if (st[0] == ETALE_ECAPACITY) return fail(ix, ETALE_ECAPACITY, std::string(what) + ": id space exhausted");
+  if (st[0]) return fail(ix, ETALE_EINVAL, std::string(what) + ": rejected on the device");
+  if (st[1] == ETALE_EPOOL) return fail(ix, ETALE_EPOOL, std::string(what) + ": slab pool cannot cover compaction");
   return ETALE_OK;
 }
 
@@ -146,32 +155,43 @@ uint32_t maint_waves_per_block(const MaintArgs& a) {
   return w >= 4 ? 4 : (w >= 2 ? 2 : 1);
 }
 
-uint32_t n_entries(const etale_index* ix) { return (uint32_t)std::min<uint64_t>(ix->cfg.n_entry, ix->live); }
-
 // queries per launch so that the distance matrix fits its scratch
 uint32_t scan_chunk_for(const etale_index* ix, uint32_t ns) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ix->scan_chunk, ix->dist_cap / std::max(1u, ns)));
 }
 
-// start-set scoring, then the beam search, over queries [0, nq) in chunks
-etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t first, uint64_t nq, uint32_t k,
-                          uint32_t L, uint32_t vcap, uint32_t* out_ids, uint32_t* out_d, uint32_t* counts) {
-  const uint32_t ns = n_entries(ix);
+constexpr uint32_t BOOT_MAX = 16384;  // a bootstrap batch is scored as one start set
+
+// Start-set scoring, then the beam search, over up to nmax queries in chunks.
+// `base` gives the launch-time count of the queries (and, for insert
+// searches, the counter with the first new id) and the gate bits. With
+// counts known only on the device (a replayed graph sized for its maximum),
+// persistent search waves take queries from a work queue instead of one wave
+// per possible query.
+etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t nmax, uint32_t k, uint32_t L,
+                          uint32_t vcap, uint32_t* out_ids, uint32_t* out_d, uint32_t* counts, Dyn base,
+                          bool persistent = false) {
+  const uint32_t ns = ix->cfg.n_entry;  // upper bound; the kernels read the entry count
   const uint32_t chunk = scan_chunk_for(ix, ns);
-  for (uint64_t c = 0; c < nq; c += chunk) {
-    const uint32_t cn = (uint32_t)std::min<uint64_t>(chunk, nq - c);
+  const size_t qbytes = (size_t)ix->cfg.dim * (ix->cfg.metric == ETALE_METRIC_L2_U8 ? 1 : 4);
+  for (uint64_t c = 0; c < nmax; c += chunk) {
+    const uint32_t cn = (uint32_t)std::min<uint64_t>(chunk, nmax - c);
+    Dyn d = base;
+    d.c0 = (uint32_t)c;
     ScanArgs sc{};
     sc.mode = mode;
-    sc.q = mode == MODE_QUERY ? q + c * ix->cfg.dim * (ix->cfg.metric == ETALE_METRIC_L2_U8 ? 1 : 4) : nullptr;
-    sc.first = first + (uint32_t)c;
+    sc.q = mode == MODE_QUERY ? q + c * qbytes : nullptr;
+    sc.first = 0;
     sc.nq = cn;
     sc.L = L;
     sc.ns = ns;
+    sc.ns_ctr = C_N_ENTRIES;
     sc.dist = ix->scan_dist;
     sc.out_keys = ix->scan_keys;
     sc.out_n = ix->scan_n;
     sc.out_stride = L;
     sc.trav = mode == MODE_QUERY ? ix->qtrav : ix->dev.trav;
+    sc.d = d;
     std::array<hipEvent_t, 4> ev{};
     const bool timed = ix->timing && mode == MODE_QUERY;
     if (timed) {
@@ -187,20 +207,12 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t 
       ix->ev_used.push_back(ev);
       HIP_TRY(hipEventRecord(ev[0], ix->stream));
     }
-    if (ns == 0) {
-      HIP_TRY(hipMemsetAsync(ix->scan_n, 0, (size_t)cn * 4, ix->stream));
-      if (timed) {
-        HIP_TRY(hipEventRecord(ev[1], ix->stream));
-        HIP_TRY(hipEventRecord(ev[2], ix->stream));
-      }
-    } else {
-      HIP_TRY(launch_scan(ix->dev, sc, ix->stream, timed ? ev[1] : nullptr));
-      if (timed) HIP_TRY(hipEventRecord(ev[2], ix->stream));
-    }
+    HIP_TRY(launch_scan(ix->dev, sc, ix->stream, timed ? ev[1] : nullptr));
+    if (timed) HIP_TRY(hipEventRecord(ev[2], ix->stream));
     SearchArgs sa{};
     sa.mode = mode;
     sa.q = sc.q;
-    sa.first = sc.first;
+    sa.first = 0;
     sa.nq = cn;
     sa.L = L;
     sa.k = k;
@@ -213,6 +225,8 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t 
     sa.init_stride = L;
     sa.trav = sc.trav;
     sa.rerank = mode == MODE_QUERY ? ix->qrerank : 0;
+    sa.d = d;
+    sa.persistent = persistent ? 1u : 0u;
     if (mode == MODE_QUERY) {
       sa.out_ids = out_ids + c * k;
       sa.out_d = out_d + c * k;
@@ -228,23 +242,214 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint32_t 
 }
 
 // bootstrap: each new node's candidates are the vcap nearest other members
-etale_status run_bootstrap(etale_index* ix, uint32_t first, uint32_t n, uint32_t vcap) {
-  const uint32_t chunk = scan_chunk_for(ix, n);
-  for (uint32_t c = 0; c < n; c += chunk) {
+etale_status run_bootstrap(etale_index* ix, uint32_t nmax, uint32_t vcap, Dyn base) {
+  const uint32_t ns = std::min(nmax, BOOT_MAX);
+  const uint32_t chunk = scan_chunk_for(ix, ns);
+  for (uint32_t c = 0; c < ns; c += chunk) {
+    Dyn d = base;
+    d.c0 = c;
     ScanArgs sc{};
     sc.mode = MODE_BOOT;
-    sc.first = first;  // the start set is the whole batch
-    sc.nq = std::min(chunk, n - c);
+    sc.first = 0;
+    sc.nq = std::min(chunk, ns - c);
     sc.L = vcap;
-    sc.ns = n;
+    sc.ns = ns;
+    sc.ns_ctr = C_R_NINS;
     sc.dist = ix->scan_dist;
     sc.out_keys = ix->vis_keys + (size_t)c * vcap;
     sc.out_n = ix->vis_cnt + c;
     sc.out_stride = vcap;
     sc.qoff = c;
+    sc.d = d;
     HIP_TRY(launch_scan(ix->dev, sc, ix->stream));
   }
   return ETALE_OK;
+}
+
+// A round's launches (Definition 2), sized by the plan's upper bounds; every
+// kernel reads the actual counts from the counters the first kernel sets.
+struct RoundPlan {
+  uint32_t max_d = 0, max_i = 0, max_q = 0;
+  const uint32_t* counts = nullptr;  // device [3]; null: the max_* values are the counts
+  const uint32_t* del_ids = nullptr;
+  uint8_t* del_status = nullptr;
+  const void* vecs = nullptr;
+  uint32_t* ids_out = nullptr;
+  const void* q = nullptr;
+  uint32_t k = 0, L = 0;
+  uint32_t* q_ids = nullptr;
+  uint32_t* q_d = nullptr;
+  bool reclaim = false;
+  int32_t* status = nullptr;
+  int boot = -1;                     // 0 / 1 when the host knows it; -1: both variants, gated on the device
+  uint64_t n_ids_max = 0;            // id bound of the reclaim scans
+};
+
+etale_status enqueue_reclaim(etale_index* ix, uint64_t n_ids_max, int32_t* status) {
+  const Index& d = ix->dev;
+  Dyn dn;
+  dn.skip = G_FAIL;
+  dn.n_ctr = C_NEXT_ID;
+  HIP_TRY(launch_del_bitmap(d, n_ids_max, dn, ix->bitmap, ix->stream));
+  HIP_TRY(launch_dirty(d, n_ids_max, dn, ix->bitmap, ix->dirty, ix->stream));
+  HIP_TRY(launch_reclaim_gate(d, status, ix->stream));
+  Dyn dc;
+  dc.skip = G_FAIL | G_RFAIL;
+  dc.n_ctr = C_DIRTY;
+  HIP_TRY(launch_compact(d, ix->dirty, n_ids_max, dc, ix->bitmap, ix->stream));
+  Dyn df;
+  df.skip = G_FAIL | G_RFAIL;
+  df.n_ctr = C_NEXT_ID;
+  HIP_TRY(launch_free_tombstones(d, n_ids_max, df, ix->stream));
+  HIP_TRY(launch_recycle(d, ix->stream));
+  return ETALE_OK;
+}
+
+etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
+  const Index& d = ix->dev;
+  const uint32_t R = ix->cfg.R;
+  hipStream_t s = ix->stream;
+  HIP_TRY(launch_round_begin(d, p.counts, p.counts ? 0 : p.max_d, p.counts ? 0 : p.max_i, p.counts ? 0 : p.max_q,
+                             p.max_d, p.max_i, p.max_q, p.status, s));
+  // P0: classify the deletes (sorted by id, first occurrence wins), then the gate
+  if (p.max_d) {
+    Dyn dd;
+    dd.skip = G_FAIL;
+    dd.n_ctr = C_R_NDEL;
+    HIP_TRY(launch_del_keys(d, p.del_ids, p.max_d, dd, ix->pairs_a, s));
+    uint64_t* sorted = nullptr;
+    HIP_TRY(launch_sort(d, ix->pairs_a, ix->pairs_b, p.max_d, dd, 32, 32, ix->hist, s, &sorted));
+    HIP_TRY(launch_del_classify(d, sorted, p.max_d, dd, p.del_status, ix->dlist, s));
+  }
+  HIP_TRY(launch_round_gate(d, ix->cfg.tombstone_only, BOOT_MAX, p.status, s));
+  if (p.max_d) {
+    Dyn dt;
+    dt.skip = G_FAIL;
+    dt.n_ctr = C_DEL_OK;
+    HIP_TRY(launch_tombstone(d, ix->dlist, p.max_d, dt, s));
+    Dyn dr;
+    dr.skip = G_FAIL;
+    dr.first_ctr = C_R_FIRST;  // this round's new ids are not live yet
+    HIP_TRY(launch_refresh_entries(d, 0, ix->cfg.n_entry, dr, s));
+  }
+  Dyn di;
+  di.skip = G_FAIL;
+  di.n_ctr = C_R_NINS;
+  di.first_ctr = C_R_FIRST;
+  const uint32_t vcap = ix->vcap_build;
+  if (p.max_i) {
+    HIP_TRY(launch_store_rows(d, p.vecs, p.ids_out, 0, p.max_i, di, s));
+    if (ix->cfg.metric == ETALE_METRIC_IP_F32) HIP_TRY(launch_encode(d, 0, p.max_i, di, ix->xs, ix->xb, ix->x8, s));
+    // P1: the insert searches on the state the tombstones left, or the bootstrap
+    if (p.boot != 0) {
+      Dyn db = di;
+      db.skip = G_FAIL | G_NOBOOT;
+      if (etale_status st = run_bootstrap(ix, p.max_i, vcap, db)) return st;
+    }
+    if (p.boot != 1) {
+      Dyn ds = di;
+      ds.skip = G_FAIL | G_BOOT;
+      if (etale_status st = run_searches(ix, MODE_INSERT, nullptr, p.max_i, 0, ix->cfg.L_build, vcap, nullptr,
+                                         nullptr, nullptr, ds, p.counts != nullptr))
+        return st;
+    }
+  }
+  // P1: the round's queries, on the same state
+  if (p.max_q) {
+    Dyn dq;
+    dq.skip = G_FAIL;
+    dq.n_ctr = C_R_NQ;
+    if (etale_status st = run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(p.q), p.max_q, p.k, p.L,
+                                       ix->cfg.visit_mult * p.L, p.q_ids, p.q_d, nullptr, dq, p.counts != nullptr))
+      return st;
+  }
+  // P2: forward neighbors and the new node's own slab
+  if (p.max_i) {
+    MaintArgs fa = maint_args(ix, vcap);
+    fa.n = p.max_i;
+    fa.vis_keys = ix->vis_keys;
+    fa.vis_cnt = ix->vis_cnt;
+    fa.F = ix->F;
+    fa.d = di;
+    HIP_TRY(launch_maint(MK_FORWARD, d, fa, p.max_i, maint_waves_per_block(fa), s));
+  }
+  // P3: repair of the live out-neighbors of the deleted nodes, (a, u) order
+  if (p.max_d && !ix->cfg.tombstone_only) {
+    MaintArgs pa = maint_args(ix, 2 * R);
+    pa.n = p.max_d;
+    pa.dlist = ix->dlist;
+    pa.pairs = ix->pairs_a;
+    pa.d.skip = G_FAIL;
+    pa.d.n_ctr = C_DEL_OK;
+    HIP_TRY(launch_repair_pairs(d, pa, s));
+    Dyn dp;
+    dp.skip = G_FAIL;
+    dp.n_ctr = C_DEL_OK;
+    dp.n_mult = R;
+    uint64_t* sorted = nullptr;
+    // the deleted ids come in no particular order: sort on (target, source)
+    HIP_TRY(launch_sort(d, ix->pairs_a, ix->pairs_b, p.max_d * R, dp, 32, (int)ix->pair_bits, ix->hist, s, &sorted,
+                        (int)ix->pair_bits));
+    HIP_TRY(launch_segments(d, sorted, p.max_d * R, dp, ix->seg, s));
+    pa.pairs = sorted;
+    pa.npairs = p.max_d * R;
+    pa.np_ctr = C_DEL_OK;
+    pa.np_mult = R;
+    pa.seg = ix->seg;
+    HIP_TRY(launch_maint(MK_REPAIR, d, pa, pa.npairs, maint_waves_per_block(pa), s));
+  }
+  // P4: reverse edges in (target, source) order, one publication per target
+  if (p.max_i) {
+    MaintArgs fa = maint_args(ix, vcap);
+    fa.n = p.max_i;
+    fa.F = ix->F;
+    fa.pairs = ix->pairs_a;
+    fa.d = di;
+    HIP_TRY(launch_reverse_pairs(d, fa, s));
+    Dyn dp;
+    dp.skip = G_FAIL;
+    dp.n_ctr = C_R_NINS;
+    dp.n_mult = R;
+    uint64_t* sorted = nullptr;
+    // pairs are written in ascending source order: the target half alone
+    HIP_TRY(launch_sort(d, ix->pairs_a, ix->pairs_b, p.max_i * R, dp, 32, (int)ix->pair_bits, ix->hist, s, &sorted));
+    HIP_TRY(launch_segments(d, sorted, p.max_i * R, dp, ix->seg, s));
+    MaintArgs ra = maint_args(ix, R + 1);
+    ra.n = p.max_i;
+    ra.pairs = sorted;
+    ra.npairs = p.max_i * R;
+    ra.np_ctr = C_R_NINS;
+    ra.np_mult = R;
+    ra.seg = ix->seg;
+    ra.d = di;
+    HIP_TRY(launch_maint(MK_REVERSE, d, ra, ra.npairs, maint_waves_per_block(ra), s));
+    // P5: refine (not after a bootstrap)
+    if (ix->cfg.refine && p.boot != 1) {
+      MaintArgs ga = maint_args(ix, R + R * R);
+      ga.n = p.max_i;
+      ga.d = di;
+      ga.d.skip = G_FAIL | G_BOOT;
+      HIP_TRY(launch_maint(MK_REFINE, d, ga, p.max_i, maint_waves_per_block(ga), s));
+    }
+    Dyn de;
+    de.skip = G_FAIL;
+    de.first_ctr = C_NEXT_ID;
+    HIP_TRY(launch_refresh_entries(d, 0, ix->cfg.n_entry, de, s));
+  }
+  HIP_TRY(launch_recycle(d, s));  // end of the epoch (Lemma 1)
+  if (p.reclaim) return enqueue_reclaim(ix, p.n_ids_max, p.status);
+  return ETALE_OK;
+}
+
+// Graph key: every descriptor field that is baked into the captured launches,
+// and the query-side traversal settings.
+std::string graph_key(const etale_round_desc& r, int32_t qtrav, uint32_t qrerank) {
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "%p/%p/%u/%p/%p/%u/%p/%p/%p/%u/%u/%u/%p/%p/%d/%d/%u", (const void*)r.del_ids,
+                (const void*)r.del_status, r.max_del, r.ins_vecs, (const void*)r.ins_ids, r.max_ins, r.queries,
+                (const void*)r.q_ids, r.q_dists, r.max_q, r.k, r.L, (const void*)r.counts, (const void*)r.status,
+                r.reclaim, qtrav, qrerank);
+  return std::string(buf);
 }
 
 #define CHECK_HANDLE()                                       \
@@ -335,14 +540,9 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   ALLOC(ix->scan_n, (uint64_t)ix->scan_chunk * 4);
   ix->dist_cap = std::min<uint64_t>(1ull << 27, std::max<uint64_t>((uint64_t)ix->scan_chunk * c.n_entry, B * 4096));
   ALLOC(ix->scan_dist, ix->dist_cap * 4);
-  {
-    size_t bytes = 0;
-    if (rocprim::radix_sort_keys(nullptr, bytes, (uint64_t*)nullptr, (uint64_t*)nullptr, (size_t)(B * R), 0, 64,
-                                 ix->stream) != hipSuccess)
-      return cleanup(ETALE_EDEVICE, "sort size");
-    ix->sort_tmp_bytes = bytes;
-    ALLOC(ix->sort_tmp, bytes);
-  }
+  ALLOC(ix->seg, B * R * 4);
+  ALLOC(ix->hist, (uint64_t)sort_hist_words((uint32_t)(B * R)) * 4);
+  ALLOC(ix->status, 16);
 #undef ALLOC
   Index& d = ix->dev;
   d.dim = c.dim;
@@ -369,6 +569,8 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   d.retired_stack = ix->retired_stack;
   d.ctr = ix->ctr;
   d.entries = ix->entries;
+  ix->pair_bits = 1;
+  while ((1ull << ix->pair_bits) <= C) ++ix->pair_bits;  // every id < 2^bits - 1: a KEY_NONE target sorts last
   if (launch_init(d, ix->stream) != hipSuccess || hipStreamSynchronize(ix->stream) != hipSuccess)
     return cleanup(ETALE_EDEVICE, "init");
   *out = ix;
@@ -378,6 +580,8 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
 etale_status etale_destroy(etale_t ix) {
   if (!ix) return ETALE_OK;
   (void)hipStreamSynchronize(ix->stream);
+  for (auto& g : ix->graphs) (void)hipGraphExecDestroy(g.second);
+  if (ix->cap_stream) (void)hipStreamDestroy(ix->cap_stream);
   for (auto& q : ix->ev_used)
     for (hipEvent_t e : q) (void)hipEventDestroy(e);
   for (hipEvent_t e : ix->ev_pool) (void)hipEventDestroy(e);
@@ -396,104 +600,37 @@ etale_status etale_insert_batch(etale_t ix, const void* vecs_dev, uint64_t n, ui
   CHECK_HANDLE();
   if (n == 0) return ETALE_OK;
   if (!vecs_dev || n > ix->cfg.max_batch) return fail(ix, ETALE_EINVAL, "insert: null vectors or n > max_batch");
-  if (ix->next_id + n > ix->cfg.id_capacity) return fail(ix, ETALE_ECAPACITY, "insert: id space exhausted");
   unsigned long long h[C_NCOUNTERS];
   if (etale_status st = read_counters(ix, h)) return st;
-  const uint32_t R = ix->cfg.R;
-  if (h[C_N_ENTRIES] != n_entries(ix)) {
+  if (h[C_N_ENTRIES] != std::min<uint64_t>(ix->cfg.n_entry, h[C_LIVE])) {
     ix->poisoned = true;
     return fail(ix, ETALE_ESTATE, "entry-set size on the device disagrees with the live count");
   }
-  if (h[C_FREE_TOP] < n * (uint64_t)(R + 2)) return fail(ix, ETALE_EPOOL, "insert: slab pool cannot cover n*(R+2)");
-  const uint32_t first = (uint32_t)ix->next_id;
-  const Index& d = ix->dev;
-  if (ix->cfg.metric == ETALE_METRIC_L2_U8) {
-    HIP_TRY(hipMemcpyAsync(ix->x + (size_t)first * ix->cfg.dim, vecs_dev, n * ix->cfg.dim, hipMemcpyDeviceToDevice,
-                           ix->stream));
-  } else {
-    HIP_TRY(hipMemcpyAsync(ix->xf + (size_t)first * ix->cfg.dim, vecs_dev, n * ix->cfg.dim * 4,
-                           hipMemcpyDeviceToDevice, ix->stream));
-    HIP_TRY(launch_encode(d, first, (uint32_t)n, ix->xs, ix->xb, ix->x8, ix->stream));
-  }
-  if (ids_out_dev) HIP_TRY(launch_write_ids(ids_out_dev, first, n, ix->stream));
-  const bool bootstrap = ix->live == 0;
-  const uint32_t vcap = ix->vcap_build;
-
-  // searches on the graph as it was at the call's start, or the bootstrap:
-  // the visit_cap nearest other members of the batch
-  if (bootstrap) {
-    if (n > 16384) return fail(ix, ETALE_EINVAL, "insert: a bootstrap batch holds at most 16384 vectors");
-    if (etale_status st = run_bootstrap(ix, first, (uint32_t)n, vcap)) return st;
-  } else if (etale_status st = run_searches(ix, MODE_INSERT, nullptr, first, n, 0, ix->cfg.L_build, vcap, nullptr,
-                                            nullptr, nullptr)) {
-    return st;
-  }
-
-  // forward neighbors and the node's own slab
-  MaintArgs fa = maint_args(ix, vcap);
-  fa.first = first;
-  fa.n = (uint32_t)n;
-  fa.vis_keys = ix->vis_keys;
-  fa.vis_cnt = ix->vis_cnt;
-  fa.F = ix->F;
-  HIP_TRY(launch_maint(MK_FORWARD, d, fa, (uint32_t)n, maint_waves_per_block(fa), ix->stream));
-
-  // reverse edges, grouped by target in (target, source) order
-  {
-    fa.pairs = ix->pairs_a;
-    HIP_TRY(launch_reverse_pairs(d, fa, ix->stream));
-    if (etale_status st = sort_keys(ix, ix->pairs_a, ix->pairs_b, n * R)) return st;
-    MaintArgs ra = maint_args(ix, R + 1);
-    ra.first = first;
-    ra.n = (uint32_t)n;
-    ra.pairs = ix->pairs_b;
-    ra.npairs = (uint32_t)(n * R);
-    HIP_TRY(launch_maint(MK_REVERSE, d, ra, ra.npairs, maint_waves_per_block(ra), ix->stream));
-  }
-  if (ix->cfg.refine && !bootstrap) {
-    MaintArgs ga = maint_args(ix, R + R * R);
-    ga.first = first;
-    ga.n = (uint32_t)n;
-    HIP_TRY(launch_maint(MK_REFINE, d, ga, (uint32_t)n, maint_waves_per_block(ga), ix->stream));
-  }
-  HIP_TRY(launch_refresh_entries(d, first + (uint32_t)n, ix->cfg.n_entry, ix->stream));
-  HIP_TRY(launch_recycle(d, ix->stream));
-  ix->next_id += n;
-  ix->live += n;
-  return ETALE_OK;
+  if (h[C_NEXT_ID] + n > ix->cfg.id_capacity) return fail(ix, ETALE_ECAPACITY, "insert: id space exhausted");
+  if (h[C_FREE_TOP] < n * (uint64_t)(ix->cfg.R + 2))
+    return fail(ix, ETALE_EPOOL, "insert: slab pool cannot cover n*(R+2)");
+  const bool bootstrap = h[C_LIVE] == 0;
+  if (bootstrap && n > BOOT_MAX) return fail(ix, ETALE_EINVAL, "insert: a bootstrap batch holds at most 16384 vectors");
+  RoundPlan p;
+  p.max_i = (uint32_t)n;
+  p.vecs = vecs_dev;
+  p.ids_out = ids_out_dev;
+  p.status = ix->status;
+  p.boot = bootstrap ? 1 : 0;
+  return enqueue_round(ix, p);
 }
 
 etale_status etale_delete_batch(etale_t ix, const uint32_t* ids_dev, uint64_t n, uint8_t* status_out_dev) {
   CHECK_HANDLE();
   if (n == 0) return ETALE_OK;
   if (!ids_dev || n > ix->cfg.max_batch) return fail(ix, ETALE_EINVAL, "delete: null ids or n > max_batch");
-  const Index& d = ix->dev;
-  const uint32_t R = ix->cfg.R;
-  if (etale_status st = set_counter(ix, C_DEL_OK, 0)) return st;
-  HIP_TRY(launch_del_keys(ids_dev, n, ix->pairs_a, ix->stream));
-  if (etale_status st = sort_keys(ix, ix->pairs_a, ix->pairs_b, n)) return st;
-  HIP_TRY(launch_del_classify(d, ix->pairs_b, n, ix->next_id, status_out_dev, ix->dlist, ix->stream));
-  unsigned long long h[C_NCOUNTERS];
-  if (etale_status st = read_counters(ix, h)) return st;
-  const uint64_t dok = h[C_DEL_OK];
-  if (!ix->cfg.tombstone_only && h[C_FREE_TOP] < dok * R)
-    return fail(ix, ETALE_EPOOL, "delete: slab pool cannot cover the repairs");
-  HIP_TRY(launch_tombstone(d, ix->dlist, dok, ix->stream));
-  ix->live -= dok;
-  HIP_TRY(launch_refresh_entries(d, (uint32_t)ix->next_id, ix->cfg.n_entry, ix->stream));
-  if (!ix->cfg.tombstone_only && dok) {
-    MaintArgs pa = maint_args(ix, 2 * R);
-    pa.n = (uint32_t)dok;
-    pa.dlist = ix->dlist;
-    pa.pairs = ix->pairs_a;
-    HIP_TRY(launch_repair_pairs(d, pa, ix->stream));
-    if (etale_status st = sort_keys(ix, ix->pairs_a, ix->pairs_b, dok * R)) return st;
-    pa.pairs = ix->pairs_b;
-    pa.npairs = (uint32_t)(dok * R);
-    HIP_TRY(launch_maint(MK_REPAIR, d, pa, pa.npairs, maint_waves_per_block(pa), ix->stream));
-  }
-  HIP_TRY(launch_recycle(d, ix->stream));
-  return ETALE_OK;
+  RoundPlan p;
+  p.max_d = (uint32_t)n;
+  p.del_ids = ids_dev;
+  p.del_status = status_out_dev;
+  p.status = ix->status;
+  if (etale_status st = enqueue_round(ix, p)) return st;
+  return round_status(ix, "delete");  // the pool check ran on the device, before any change
 }
 
 etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
@@ -505,30 +642,75 @@ etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint
     return fail(ix, ETALE_EINVAL, "search: null buffer");
   if (ix->cfg.metric == ETALE_METRIC_IP_F32 && ix->qtrav != ETALE_TRAV_NATIVE && (uint64_t)ix->qrerank * k > 64)
     return fail(ix, ETALE_EINVAL, "search: rerank_mult * k must not exceed 64");
-  if (etale_status st = run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(q_dev), 0, nq, k, L,
-                                     ix->cfg.visit_mult * L, ids_out_dev, reinterpret_cast<uint32_t*>(dists_out_dev),
-                                     counts_out_dev))
-    return st;
-  return ETALE_OK;
+  return run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(q_dev), nq, k, L, ix->cfg.visit_mult * L,
+                      ids_out_dev, reinterpret_cast<uint32_t*>(dists_out_dev), counts_out_dev, Dyn{});
 }
 
 etale_status etale_reclaim(etale_t ix) {
   CHECK_HANDLE();
   if (ix->cfg.tombstone_only) return ETALE_OK;
-  const Index& d = ix->dev;
-  const uint64_t n_ids = ix->next_id;
-  if (etale_status st = set_counter(ix, C_DIRTY, 0)) return st;
-  if (etale_status st = set_counter(ix, C_DEAD, 0)) return st;
-  HIP_TRY(launch_del_bitmap(d, n_ids, ix->bitmap, ix->stream));
-  HIP_TRY(launch_dirty(d, n_ids, ix->bitmap, ix->dirty, ix->stream));
-  unsigned long long h[C_NCOUNTERS];
-  if (etale_status st = read_counters(ix, h)) return st;
-  const uint64_t nd = h[C_DIRTY];
-  if (h[C_FREE_TOP] < nd) return fail(ix, ETALE_EPOOL, "reclaim: slab pool cannot cover compaction");
-  HIP_TRY(launch_compact(d, ix->dirty, nd, ix->bitmap, ix->stream));
-  HIP_TRY(launch_free_tombstones(d, n_ids, ix->stream));
-  HIP_TRY(launch_recycle(d, ix->stream));
-  HIP_TRY(hipStreamSynchronize(ix->stream));
+  if (etale_status st = refresh_mirror(ix)) return st;
+  HIP_TRY(launch_round_begin(ix->dev, nullptr, 0, 0, 0, 0, 0, 0, ix->status, ix->stream));
+  if (etale_status st = enqueue_reclaim(ix, ix->next_id, ix->status)) return st;
+  return round_status(ix, "reclaim");
+}
+
+etale_status etale_round(etale_t ix, const etale_round_desc* r) {
+  CHECK_HANDLE();
+  if (!r || !r->status) return fail(ix, ETALE_EINVAL, "round: null descriptor or status");
+  const etale_round_desc& d = *r;
+  if (d.max_del > ix->cfg.max_batch || d.max_ins > ix->cfg.max_batch)
+    return fail(ix, ETALE_EINVAL, "round: max_del / max_ins above max_batch");
+  if ((d.max_del && !d.del_ids) || (d.max_ins && !d.ins_vecs) || (d.max_q && (!d.queries || !d.q_ids || !d.q_dists)))
+    return fail(ix, ETALE_EINVAL, "round: null buffer");
+  if (d.max_q && (d.k < 1 || d.k > d.L || d.L > 256)) return fail(ix, ETALE_EINVAL, "round: need 1 <= k <= L <= 256");
+  if (d.max_q && ix->cfg.metric == ETALE_METRIC_IP_F32 && ix->qtrav != ETALE_TRAV_NATIVE &&
+      (uint64_t)ix->qrerank * d.k > 64)
+    return fail(ix, ETALE_EINVAL, "round: rerank_mult * k must not exceed 64");
+  RoundPlan p;
+  p.max_d = d.max_del;
+  p.max_i = d.max_ins;
+  p.max_q = d.max_q;
+  p.counts = d.counts;
+  p.del_ids = d.del_ids;
+  p.del_status = d.del_status;
+  p.vecs = d.ins_vecs;
+  p.ids_out = d.ins_ids;
+  p.q = d.queries;
+  p.k = d.k;
+  p.L = d.L;
+  p.q_ids = d.q_ids;
+  p.q_d = reinterpret_cast<uint32_t*>(d.q_dists);
+  p.reclaim = d.reclaim != 0 && !ix->cfg.tombstone_only;
+  p.status = d.status;
+  p.n_ids_max = ix->cfg.id_capacity;  // the id count is only known on the device
+  if (!d.graph) return enqueue_round(ix, p);
+  // capture once per descriptor, replay afterwards
+  const std::string key = graph_key(d, ix->qtrav, ix->qrerank);
+  auto it = ix->graphs.find(key);
+  if (it == ix->graphs.end()) {
+    if (!ix->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ix->cap_stream, hipStreamNonBlocking));
+    const hipStream_t user = ix->stream;
+    const bool timing = ix->timing;
+    ix->timing = false;
+    ix->stream = ix->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(ix->cap_stream, hipStreamCaptureModeThreadLocal);
+    etale_status st = ETALE_OK;
+    if (e == hipSuccess) st = enqueue_round(ix, p);
+    const hipError_t e2 = hipStreamEndCapture(ix->cap_stream, &g);
+    ix->stream = user;
+    ix->timing = timing;
+    if (st) return st;
+    HIP_TRY(e);
+    HIP_TRY(e2);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(e3);
+    it = ix->graphs.emplace(key, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, ix->stream));
   return ETALE_OK;
 }
 
@@ -537,6 +719,7 @@ etale_status etale_bruteforce(etale_t ix, const void* q_dev, uint64_t nq, uint32
   CHECK_HANDLE();
   if (k < 1 || k > 16 || nq > 0xFFFFFFFFull) return fail(ix, ETALE_EINVAL, "bruteforce: need 1 <= k <= 16");
   if (nq == 0) return ETALE_OK;
+  if (etale_status st = refresh_mirror(ix)) return st;
   if (!q_dev || !ids_out_dev || !dists_out_dev) return fail(ix, ETALE_EINVAL, "bruteforce: null buffer");
   HIP_TRY(launch_bruteforce(ix->dev, q_dev, (uint32_t)nq, ix->next_id, k, ids_out_dev,
                             reinterpret_cast<uint32_t*>(dists_out_dev), ix->stream));
@@ -549,8 +732,8 @@ etale_status etale_get_stats(etale_t ix, etale_stats* out) {
   HIP_TRY(hipMemcpyAsync(h, ix->ctr, sizeof(h), hipMemcpyDeviceToHost, ix->stream));
   HIP_TRY(hipStreamSynchronize(ix->stream));
   etale_stats s{};
-  s.next_id = ix->next_id;
-  s.live = ix->next_id - h[C_TOMBSTONED];
+  s.next_id = h[C_NEXT_ID];
+  s.live = h[C_LIVE];
   s.tombstones = h[C_TOMBSTONED] - h[C_FREED];
   s.slab_capacity = ix->cfg.slab_capacity;
   s.free_slabs = h[C_FREE_TOP];
@@ -577,6 +760,7 @@ etale_status etale_get_stats(etale_t ix, etale_stats* out) {
 etale_status etale_export(etale_t ix, uint64_t n_ids, uint32_t* nbr_host, void* dist_host, uint8_t* deg_host,
                           uint8_t* del_host, uint8_t* has_slab_host) {
   CHECK_HANDLE();
+  if (etale_status st = refresh_mirror(ix)) return st;
   if (n_ids > ix->next_id) return fail(ix, ETALE_EINVAL, "export: n_ids > next id");
   if (n_ids == 0) return ETALE_OK;
   const uint64_t R = ix->cfg.R;
@@ -630,6 +814,7 @@ etale_status etale_set_lists(etale_t ix, uint64_t n, const uint32_t* ids_host, c
   CHECK_HANDLE();
   if (n == 0) return ETALE_OK;
   if (!ids_host || !nbr_host || !deg_host) return fail(ix, ETALE_EINVAL, "set_lists: null buffer");
+  if (etale_status st = refresh_mirror(ix)) return st;
   const uint32_t R = ix->cfg.R;
   std::vector<uint8_t> seen(ix->next_id, 0);
   for (uint64_t i = 0; i < n; ++i) {
@@ -673,6 +858,7 @@ etale_status etale_set_lists(etale_t ix, uint64_t n, const uint32_t* ids_host, c
 
 etale_status etale_export_rows(etale_t ix, uint64_t first, uint64_t n, int32_t which, void* out_host) {
   CHECK_HANDLE();
+  if (etale_status st = refresh_mirror(ix)) return st;
   if (!out_host || first + n > ix->next_id) return fail(ix, ETALE_EINVAL, "export_rows: range");
   const uint64_t dim = ix->cfg.dim;
   const void* src = nullptr;

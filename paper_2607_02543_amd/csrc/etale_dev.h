@@ -52,8 +52,22 @@ enum Counter {
   C_PUB_DROPPED,
   C_DEL_OK,
   C_TOMBSTONED,
+  C_NEXT_ID,   // ids handed out so far
+  C_LIVE,      // handed-out ids with deletion flag 0
+  C_R_NDEL,    // this round's requested deletes, inserts, queries
+  C_R_NINS,
+  C_R_NQ,
+  C_R_FIRST,   // this round's first new id
+  C_R_GATE,    // GateBits of this round
+  C_NSEG,      // segments (runs of one target) of the last sorted pair list
+  C_QUEUE,     // work queue of the running search launch
+  C_QDONE,     // waves of that launch that have left the queue
   C_NCOUNTERS = 32
 };
+
+// Round gate: set before any mutation of a round; kernels whose skip mask
+// meets it do nothing.
+enum GateBits : uint64_t { G_FAIL = 1, G_BOOT = 2, G_NOBOOT = 4, G_RFAIL = 8 };
 
 enum ErrorBits : uint64_t { ERR_POOL_EMPTY = 1, ERR_POOL_OVERFLOW = 2, ERR_BAD_LIST = 4 };
 
@@ -77,6 +91,22 @@ struct Index {
   uint32_t* retired_stack;
   unsigned long long* ctr;
   uint32_t* entries;
+};
+
+// ---- counts read at launch time --------------------------------------------------
+// A round replayed from a captured graph has launch shapes fixed at capture;
+// its item counts live in counters. A kernel resolves them when it starts:
+// n = min(cap, counter * mult - c0) items (the cap is the static count of the
+// launch), first id from a counter, and nothing at all when the round's gate
+// meets the skip mask. NO_CTR keeps the static value.
+constexpr uint32_t NO_CTR = 0xFFFFFFFFu;
+
+struct Dyn {
+  uint32_t skip = 0;          // GateBits that turn the launch into a no-op
+  uint32_t n_ctr = NO_CTR;    // counter with the item count
+  uint32_t n_mult = 1;        // items per counted unit
+  uint32_t c0 = 0;            // this launch covers items [c0, c0 + cap)
+  uint32_t first_ctr = NO_CTR;  // counter with the first id (added to c0)
 };
 
 // ---- wave primitives --------------------------------------------------------
@@ -103,6 +133,28 @@ __device__ inline uint64_t bcast64(uint64_t v) {
   uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
   return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline bool gated(const Index& ix, const Dyn& d) {
+  return d.skip != 0 && (ix.ctr[C_R_GATE] & (uint64_t)d.skip) != 0;
+}
+__device__ inline uint32_t dyn_count(const Index& ix, const Dyn& d, uint32_t cap) {
+  if (d.n_ctr == NO_CTR) return cap;
+  const uint64_t v = ix.ctr[d.n_ctr] * (uint64_t)d.n_mult;
+  return v <= d.c0 ? 0u : (uint32_t)(v - d.c0 < cap ? v - d.c0 : cap);
+}
+__device__ inline uint32_t dyn_first(const Index& ix, const Dyn& d, uint32_t first) {
+  return d.first_ctr == NO_CTR ? first : (uint32_t)ix.ctr[d.first_ctr] + d.c0;
+}
+__device__ inline uint32_t total_waves() { return gridDim.x * (blockDim.x >> 6); }
+
+// One ticket per wave from a counter. Every lane takes part in the atomic
+// (lane 0 adds 1, the others 0) so no lane-divergent branch precedes the
+// broadcast: inside a loop such a branch lets the compiler split the wave
+// into lanes that re-enter the loop without lane 0.
+__device__ inline uint32_t wave_ticket(unsigned long long* ctr) {
+  const unsigned long long v = atomicAdd(ctr, (threadIdx.x & 63u) == 0 ? 1ull : 0ull);
+  return __builtin_amdgcn_readfirstlane((uint32_t)v);
 }
 
 __device__ inline uint64_t load_ref(const Index& ix, uint32_t u) {

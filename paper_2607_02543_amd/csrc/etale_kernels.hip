@@ -41,9 +41,92 @@ __global__ void k_recycle(Index ix) {
   }
 }
 
-__global__ void k_write_ids(uint32_t* out, uint32_t first, uint64_t n) {
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = first + (uint32_t)i;
+// ---- round control --------------------------------------------------------------------
+// A round's counts come from a device array (a replayed graph) or from the
+// launch arguments. Counts above the launch shapes fail the round.
+constexpr int32_t ST_EINVAL = -1, ST_EPOOL = -3, ST_ECAPACITY = -4;
+
+__global__ void k_round_begin(Index ix, const uint32_t* counts, uint32_t nd, uint32_t ni, uint32_t nq,
+                              uint32_t max_d, uint32_t max_i, uint32_t max_q, int32_t* status) {
+  if (threadIdx.x != 0) return;
+  if (counts) {
+    nd = counts[0];
+    ni = counts[1];
+    nq = counts[2];
+  }
+  uint64_t gate = 0;
+  int32_t st = 0;
+  if (nd > max_d || ni > max_i || nq > max_q) {
+    gate = G_FAIL;
+    st = ST_EINVAL;
+    nd = ni = nq = 0;
+  }
+  ix.ctr[C_R_NDEL] = nd;
+  ix.ctr[C_R_NINS] = ni;
+  ix.ctr[C_R_NQ] = nq;
+  ix.ctr[C_R_GATE] = gate;
+  ix.ctr[C_DEL_OK] = 0;
+  ix.ctr[C_R_FIRST] = ix.ctr[C_NEXT_ID];
+  if (status) {
+    status[0] = st;
+    status[1] = 0;
+  }
+}
+
+// After the deletes are classified and before any mutation: id space and
+// the worst-case slab demand |I|(R+2) + |D|R (|I|(R+2) without repair); a
+// bootstrap (no live node left once this round's tombstones are set) takes at
+// most boot_max new vectors. On success the new ids are handed out.
+__global__ void k_round_gate(Index ix, uint32_t tombstone_only, uint32_t boot_max, int32_t* status) {
+  if (threadIdx.x != 0) return;
+  uint64_t gate = ix.ctr[C_R_GATE];
+  if (gate & G_FAIL) return;
+  const uint64_t dok = ix.ctr[C_DEL_OK], ni = ix.ctr[C_R_NINS];
+  const uint64_t next = ix.ctr[C_NEXT_ID], live = ix.ctr[C_LIVE];
+  const uint64_t need = ni * (ix.R + 2ull) + (tombstone_only ? 0ull : dok * ix.R);
+  const bool boot = ni > 0 && live == dok;
+  int32_t st = 0;
+  if (next + ni > ix.cap)
+    st = ST_ECAPACITY;
+  else if (ix.ctr[C_FREE_TOP] < need)
+    st = ST_EPOOL;
+  else if (boot && ni > boot_max)
+    st = ST_EINVAL;
+  if (st) {
+    gate |= G_FAIL;
+  } else {
+    gate |= boot ? G_BOOT : G_NOBOOT;
+    ix.ctr[C_R_FIRST] = next;
+    ix.ctr[C_NEXT_ID] = next + ni;
+    ix.ctr[C_LIVE] = live - dok + ni;
+  }
+  ix.ctr[C_R_GATE] = gate;
+  if (status) status[0] = st;
+}
+
+// reclaim: compaction republishes every dirty node, so it needs that many slabs
+__global__ void k_reclaim_gate(Index ix, int32_t* status) {
+  if (threadIdx.x != 0) return;
+  const uint64_t gate = ix.ctr[C_R_GATE];
+  if (gate & G_FAIL) return;
+  const bool ok = ix.ctr[C_FREE_TOP] >= ix.ctr[C_DIRTY];
+  if (!ok) ix.ctr[C_R_GATE] = gate | G_RFAIL;
+  if (status) status[1] = ok ? 0 : ST_EPOOL;
+}
+
+// new rows at ids [first, first + n) (16-byte words), and the ids handed out
+__global__ void k_store_rows(Index ix, const uint4* src, uint32_t* ids_out, uint32_t first, uint32_t n, Dyn d) {
+  if (gated(ix, d)) return;
+  n = dyn_count(ix, d, n);
+  first = dyn_first(ix, d, first);
+  const uint32_t words = ix.metric == 0 ? ix.dim / 16u : ix.dim / 4u;
+  uint4* dst = reinterpret_cast<uint4*>(ix.metric == 0 ? (void*)ix.x : (void*)ix.xf) + (size_t)first * words;
+  const uint64_t total = (uint64_t)n * words;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    dst[t] = src[t];
+    if (ids_out && t % words == 0) ids_out[t / words] = first + (uint32_t)(t / words);
+  }
 }
 
 // ---- entry set: the S smallest live ids ---------------------------------------------
@@ -63,8 +146,10 @@ __device__ inline uint32_t block_prefix(bool keep, uint32_t* wcnt, uint32_t* tot
   return before + lanes_below(m);
 }
 
-__global__ void __launch_bounds__(1024) k_refresh_entries(Index ix, uint32_t next_id, uint32_t S) {
+__global__ void __launch_bounds__(1024) k_refresh_entries(Index ix, uint32_t next_id, uint32_t S, Dyn d) {
   __shared__ uint32_t wcnt[16];
+  if (gated(ix, d)) return;
+  next_id = dyn_first(ix, d, next_id);  // ids at or above the bound are not yet live
   const uint32_t m_old = (uint32_t)ix.ctr[C_N_ENTRIES];
   const uint32_t start = m_old ? ix.entries[m_old - 1] + 1u : 0u;
   uint32_t out = 0;
@@ -107,12 +192,18 @@ __device__ inline uint32_t start_id(const Index& ix, const ScanArgs& a, uint32_t
   return a.mode == MODE_BOOT ? a.first + e : ix.entries[e];
 }
 
-__global__ void __launch_bounds__(256) k_scan_dist(Index ix, ScanArgs a) {
-  __shared__ uint4 qt[SD_Q * SD_STRIDE];
-  __shared__ uint4 et[SD_E * SD_STRIDE];
-  __shared__ uint32_t qn_s[SD_Q], en_s[SD_E];
+// launch-time counts: queries of this launch, start-set size, first id
+__device__ inline void resolve(const Index& ix, ScanArgs& a) {
+  a.nq = dyn_count(ix, a.d, a.nq);
+  // insert searches: query i of the launch is stored row first + c0 + i; a
+  // bootstrap's start set is the whole batch, so its first id is the batch's
+  if (a.d.first_ctr != NO_CTR) a.first = (uint32_t)ix.ctr[a.d.first_ctr] + (a.mode == MODE_BOOT ? 0u : a.d.c0);
+  if (a.ns_ctr != NO_CTR) a.ns = (uint32_t)min<uint64_t>(a.ns, ix.ctr[a.ns_ctr]);
+}
+
+__device__ inline void scan_dist_tile(const Index& ix, const ScanArgs& a, uint32_t e0, uint32_t q0, uint4* qt,
+                                      uint4* et, uint32_t* qn_s, uint32_t* en_s) {
   const int t = (int)threadIdx.x;
-  const uint32_t e0 = blockIdx.x * SD_E, q0 = blockIdx.y * SD_Q;
   const uint32_t ns = a.ns, dim = ix.dim;
   const int words = (int)dim / 16;
   const int qg = t / 32, eg = t % 32;
@@ -181,16 +272,26 @@ __global__ void __launch_bounds__(256) k_scan_dist(Index ix, ScanArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_scan_dist(Index ix, ScanArgs a) {
+  __shared__ uint4 qt[SD_Q * SD_STRIDE];
+  __shared__ uint4 et[SD_E * SD_STRIDE];
+  __shared__ uint32_t qn_s[SD_Q], en_s[SD_E];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  const uint32_t n_et = (a.ns + SD_E - 1) / SD_E, n_tiles = n_et * ((a.nq + SD_Q - 1) / SD_Q);
+  for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    __syncthreads();
+    scan_dist_tile(ix, a, (tile % n_et) * SD_E, (tile / n_et) * SD_Q, qt, et, qn_s, en_s);
+  }
+}
+
 // Float rows: the same 64 x 256 tiling over 16-element slices, in FP32; start
 // rows come from the traversal copy (FP8 rows as value/256, their scale
 // applied once per pair at the end).
 template <int TRAV>
-__global__ void __launch_bounds__(256) k_scan_dist_f(Index ix, ScanArgs a) {
-  __shared__ float4 qt[SD_Q * SD_STRIDE];
-  __shared__ float4 et[SD_E * SD_STRIDE];
-  __shared__ float es[SD_E];
+__device__ inline void scan_dist_f_tile(const Index& ix, const ScanArgs& a, uint32_t e0, uint32_t q0, float4* qt,
+                                        float4* et, float* es) {
   const int t = (int)threadIdx.x;
-  const uint32_t e0 = blockIdx.x * SD_E, q0 = blockIdx.y * SD_Q;
   const uint32_t ns = a.ns, dim = ix.dim;
   const int qg = t / 32, eg = t % 32;
   float acc[8][8];
@@ -280,19 +381,29 @@ __global__ void __launch_bounds__(256) k_scan_dist_f(Index ix, ScanArgs a) {
   }
 }
 
+template <int TRAV>
+__global__ void __launch_bounds__(256) k_scan_dist_f(Index ix, ScanArgs a) {
+  __shared__ float4 qt[SD_Q * SD_STRIDE];
+  __shared__ float4 et[SD_E * SD_STRIDE];
+  __shared__ float es[SD_E];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  const uint32_t n_et = (a.ns + SD_E - 1) / SD_E, n_tiles = n_et * ((a.nq + SD_Q - 1) / SD_Q);
+  for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    __syncthreads();
+    scan_dist_f_tile<TRAV>(ix, a, (tile % n_et) * SD_E, (tile / n_et) * SD_Q, qt, et, es);
+  }
+}
+
 // One wave per query: the exact L smallest (distance, row) pairs of its
 // distance row, by a most-significant-digit radix select on the distance
 // (8-bit digits from the highest set bit), then the rows below the threshold
 // plus the first rows (in row order) equal to it, sorted. The row is held in
 // registers (VPL values per lane, row i in lane i % 64, slot i / 64).
 template <int VPL>
-__global__ void __launch_bounds__(256) k_scan_select(Index ix, ScanArgs a, uint32_t sel_cap) {
-  extern __shared__ __align__(16) char smem[];
-  const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (qi >= a.nq) return;
+__device__ inline void scan_select_one(const Index& ix, const ScanArgs& a, uint32_t qi, uint32_t* hist,
+                                       uint64_t* sel) {
   const int l = lane_id();
-  uint32_t* hist = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * (1024 + 8 * sel_cap));
-  uint64_t* sel = reinterpret_cast<uint64_t*>(hist + 256);
   const uint32_t ns = a.ns;
   const uint32_t* D = a.dist + (size_t)qi * ns;
   uint32_t v[VPL];
@@ -380,6 +491,18 @@ __global__ void __launch_bounds__(256) k_scan_select(Index ix, ScanArgs a, uint3
   if (l == 0) a.out_n[qi] = cnt;
 }
 
+template <int VPL>
+__global__ void __launch_bounds__(256) k_scan_select(Index ix, ScanArgs a, uint32_t sel_cap) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  // one wave per query (the value registers leave no room for a loop)
+  const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (qi >= a.nq) return;
+  uint32_t* hist = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * (1024 + 8 * sel_cap));
+  scan_select_one<VPL>(ix, a, qi, hist, reinterpret_cast<uint64_t*>(hist + 256));
+}
+
 uint32_t scan_select_lds_per_wave(uint32_t L) { return 1024u + 8u * (uint32_t)next_pow2_ge64((int)L); }
 
 // ---- traversal policies ------------------------------------------------------------
@@ -433,14 +556,8 @@ struct TravFloat {
 // double-buffered candidate list (keys, reference words, expanded flags), one
 // batch of candidates, the merge scratch and the visited table.
 template <class TP>
-__global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
-  extern __shared__ __align__(16) char smem[];
-  const int wv = (int)(threadIdx.x >> 6);
-  const int nw = (int)(blockDim.x >> 6);
+__device__ inline void search_one(const Index& ix, const SearchArgs& a, char* base, uint32_t qi) {
   const int l = lane_id();
-  const uint32_t qi = blockIdx.x * (uint32_t)nw + (uint32_t)wv;
-  if (qi >= a.nq) return;
-  char* base = smem + (size_t)wv * a.lds_per_wave;
   CandList cl;
   uint64_t* p64 = reinterpret_cast<uint64_t*>(base);
   cl.k0 = p64;
@@ -589,6 +706,34 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   }
 }
 
+// Persistent waves: each takes the next query from the launch's work queue
+// until it is drained; the last wave to leave resets the queue for the next
+// launch on the stream.
+template <class TP>
+__global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  a.nq = dyn_count(ix, a.d, a.nq);
+  a.first = dyn_first(ix, a.d, a.first);
+  char* base = smem + (size_t)(threadIdx.x >> 6) * a.lds_per_wave;
+  if (!a.persistent) {  // one wave per query
+    const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (qi < a.nq) search_one<TP>(ix, a, base, qi);
+    return;
+  }
+  const int l = lane_id();
+  unsigned long long* queue = &ix.ctr[C_QUEUE];
+  for (uint32_t qi = wave_ticket(queue); qi < a.nq; qi = wave_ticket(queue)) {
+    wave_sync();
+    search_one<TP>(ix, a, base, qi);
+  }
+  const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
+  if (l == 0 && done + 1 == total_waves()) {
+    atomicExch(queue, 0ull);
+    atomicExch(&ix.ctr[C_QDONE], 0ull);
+  }
+}
+
 // ---- LDS carving for the maintenance kernels ------------------------------------------
 struct MaintLds {
   PruneLds pr;
@@ -689,13 +834,18 @@ struct MaintF32 {
   __device__ static uint32_t kd(uint32_t rho) { return fkey(__builtin_bit_cast(float, rho)); }
 };
 
+__device__ inline void resolve(const Index& ix, MaintArgs& a) {
+  a.n = dyn_count(ix, a.d, a.n);
+  a.first = dyn_first(ix, a.d, a.first);
+  if (a.np_ctr != NO_CTR) a.npairs = (uint32_t)min<uint64_t>(a.npairs, ix.ctr[a.np_ctr] * a.np_mult);
+}
+
+// Item loops of the maintenance kernels: persistent waves, item i, i + waves, ...
+#define FOR_EACH_WAVE_ITEM(i, n) for (uint32_t i = wave_index(); i < (n); i += total_waves())
+
 // ---- insert: forward prune + own publication (Algorithm 2, first lines) --------------
 template <class P>
-__global__ void __launch_bounds__(256) k_forward(Index ix, MaintArgs a) {
-  extern __shared__ __align__(16) char smem[];
-  const uint32_t qi = wave_index();
-  if (qi >= a.n) return;
-  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+__device__ inline void forward_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t qi) {
   const int l = lane_id();
   const uint32_t v = a.first + qi;
   const uint32_t nc = a.vis_cnt[qi];
@@ -706,31 +856,52 @@ __global__ void __launch_bounds__(256) k_forward(Index ix, MaintArgs a) {
   for (uint32_t j = (uint32_t)l; j < ix.R; j += 64) a.F[(size_t)qi * ix.R + j] = j < (uint32_t)cnt ? m.pr.out_ids[j] : NONE;
 }
 
+template <class P>
+__global__ void __launch_bounds__(256) k_forward(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  FOR_EACH_WAVE_ITEM(qi, a.n) {
+    wave_sync();
+    forward_one<P>(ix, a, m, qi);
+  }
+}
+
 __global__ void k_reverse_pairs(Index ix, MaintArgs a) {
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) ix.ctr[C_NSEG] = 0;
   if (t >= (uint64_t)a.n * ix.R) return;
   const uint32_t w = a.F[t];
   const uint32_t v = a.first + (uint32_t)(t / ix.R);
   a.pairs[t] = w == NONE ? KEY_NONE : pair_key(w, v);
 }
 
-// first wave of each run of equal targets in the sorted pair list owns it
-__device__ inline bool owns_segment(const MaintArgs& a, uint32_t t, uint32_t* target) {
-  if (t >= a.npairs) return false;
-  const uint64_t k = a.pairs[t];
-  if (k == KEY_NONE) return false;
-  *target = (uint32_t)(k >> 32);
-  return t == 0 || (uint32_t)(a.pairs[t - 1] >> 32) != *target;
+// Runs of one target in the sorted pair list: the start index of each run is
+// appended to seg (in no particular order; each run is applied by one wave,
+// and runs touch distinct targets).
+__global__ void k_segments(Index ix, const uint64_t* pairs, uint32_t n, Dyn d, uint32_t* seg) {
+  if (gated(ix, d)) return;
+  n = dyn_count(ix, d, n);
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  bool start = false;
+  if (t < n) {
+    const uint64_t k = pairs[t];
+    start = k != KEY_NONE && (t == 0 || (uint32_t)(pairs[t - 1] >> 32) != (uint32_t)(k >> 32));
+  }
+  const uint64_t m = ballot(start);
+  uint32_t base = 0;
+  if (lane_id() == 0 && m) base = (uint32_t)atomicAdd(&ix.ctr[C_NSEG], (unsigned long long)__popcll(m));
+  base = bcast(base);
+  if (start) seg[base + lanes_below(m)] = t;
 }
 
 // ---- insert: reverse edges in (target, source) order, one publication per target ------
 template <class P>
-__global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
-  extern __shared__ __align__(16) char smem[];
-  const uint32_t t = wave_index();
-  uint32_t w;
-  if (!owns_segment(a, t, &w)) return;
-  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+__device__ inline void reverse_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t t) {
+  const uint32_t w = (uint32_t)(a.pairs[t] >> 32);
   const int l = lane_id();
   const uint32_t R = ix.R;
   uint32_t n = load_list(ix, w, m.nl_id, m.nl_d);
@@ -771,13 +942,23 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
   publish(ix, w, m.nl_id, m.nl_d, n, C_PUB_REVERSE);
 }
 
+// one wave per run of the sorted (target, source) pairs
+template <class P>
+__global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
+  FOR_EACH_WAVE_ITEM(si, nseg) {
+    wave_sync();
+    reverse_one<P>(ix, a, m, a.seg[si]);
+  }
+}
+
 // ---- insert: refine -- same-batch nodes two hops away are offered ----------------------
 template <class P>
-__global__ void __launch_bounds__(256) k_refine(Index ix, MaintArgs a) {
-  extern __shared__ __align__(16) char smem[];
-  const uint32_t qi = wave_index();
-  if (qi >= a.n) return;
-  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+__device__ inline void refine_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t qi) {
   const int l = lane_id();
   const uint32_t v = a.first + qi;
   const uint32_t end = a.first + a.n;
@@ -800,6 +981,18 @@ __global__ void __launch_bounds__(256) k_refine(Index ix, MaintArgs a) {
   const int cnt = P::prune(ix, v, m.cand, (int)nc, m.pr);
   const bool diff = (uint32_t)cnt != own || ballot((uint32_t)l < own && m.pr.out_ids[l] != m.nl_id[l]) != 0ull;
   if (diff) publish(ix, v, m.pr.out_ids, m.pr.out_d, (uint32_t)cnt, C_PUB_REFINE);
+}
+
+template <class P>
+__global__ void __launch_bounds__(256) k_refine(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  FOR_EACH_WAVE_ITEM(qi, a.n) {
+    wave_sync();
+    refine_one<P>(ix, a, m, qi);
+  }
 }
 
 // ---- install given neighbor lists (import / test hook) -----------------------------------
@@ -843,14 +1036,20 @@ __global__ void __launch_bounds__(256) k_set_lists(Index ix, MaintArgs a, const 
 }
 
 // ---- delete: classify, tombstone, repair (Algorithm 3) ----------------------------------
-__global__ void k_del_keys(const uint32_t* ids, uint64_t n, uint64_t* keys) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) keys[t] = pair_key(ids[t], (uint32_t)t);
+__global__ void k_del_keys(Index ix, const uint32_t* ids, uint32_t n, Dyn d, uint64_t* keys) {
+  if (gated(ix, d)) return;
+  n = dyn_count(ix, d, n);
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) keys[t] = pair_key(ids[t], t);
 }
 
-__global__ void k_del_classify(Index ix, const uint64_t* sorted, uint64_t n, uint64_t next_id, uint8_t* status,
+// ids at or above the id count at the round's start are out of range
+__global__ void k_del_classify(Index ix, const uint64_t* sorted, uint32_t n, Dyn d, uint8_t* status,
                                uint32_t* dlist) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gated(ix, d)) return;
+  n = dyn_count(ix, d, n);
+  const uint64_t next_id = ix.ctr[C_NEXT_ID];
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const uint64_t k = sorted[t];
   const uint32_t id = (uint32_t)(k >> 32), pos = (uint32_t)k;
@@ -872,8 +1071,10 @@ __global__ void k_del_classify(Index ix, const uint64_t* sorted, uint64_t n, uin
 }
 
 // <0,d,s> -> <1,d,s>: the flag is set, degree and slab are kept
-__global__ void k_tombstone(Index ix, const uint32_t* dlist, uint64_t n) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_tombstone(Index ix, const uint32_t* dlist, uint32_t n, Dyn d) {
+  if (gated(ix, d)) return;
+  n = dyn_count(ix, d, n);
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const uint32_t u = dlist[t];
   uint64_t r = load_ref(ix, u);
@@ -888,7 +1089,10 @@ __global__ void k_tombstone(Index ix, const uint32_t* dlist, uint64_t n) {
 }
 
 __global__ void k_repair_pairs(Index ix, MaintArgs a) {
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
   const uint32_t i = wave_index();
+  if (i == 0 && lane_id() == 0) ix.ctr[C_NSEG] = 0;
   if (i >= a.n) return;
   const int l = lane_id();
   const uint32_t u = a.dlist[i];
@@ -904,12 +1108,8 @@ __global__ void k_repair_pairs(Index ix, MaintArgs a) {
 }
 
 template <class P>
-__global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
-  extern __shared__ __align__(16) char smem[];
-  const uint32_t t = wave_index();
-  uint32_t an;
-  if (!owns_segment(a, t, &an)) return;
-  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+__device__ inline void repair_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t t) {
+  const uint32_t an = (uint32_t)(a.pairs[t] >> 32);
   const int l = lane_id();
   const uint32_t R = ix.R;
   uint32_t n = load_list(ix, an, m.nl_id, m.nl_d);
@@ -940,20 +1140,144 @@ __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
   publish(ix, an, m.nl_id, m.nl_d, n, C_PUB_REPAIR);
 }
 
+template <class P>
+__global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
+  FOR_EACH_WAVE_ITEM(si, nseg) {
+    wave_sync();
+    repair_one<P>(ix, a, m, a.seg[si]);
+  }
+}
+
+// ---- stable LSD radix sort with a launch-time count --------------------------------------
+// 8-bit digits over a bit range. Per pass: digit counts per tile of 4,096
+// keys, an exclusive scan of each digit's counts over the tiles (one block
+// per digit), then a stable scatter: a tile is read in 16 rounds of 256 keys
+// in input order; a key's rank among equal digits is its rank within its wave
+// (ballots on the digit bits) plus the counts of the earlier waves and rounds.
+// Pair keys are produced in ascending source order, so sorting on the target
+// half alone gives (target, source) order.
+constexpr uint32_t RS_TILE = 4096;
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = (uint32_t)__shfl_up((int)v, o, 64);
+    if (l >= o) v += u;
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_rs_count(Index ix, const uint64_t* in, uint32_t cap, Dyn d, int shift,
+                                                  uint32_t mask, uint32_t* hist, uint32_t ntiles) {
+  __shared__ uint32_t h[256];
+  if (gated(ix, d)) return;
+  const uint32_t n = dyn_count(ix, d, cap);
+  const uint32_t t = threadIdx.x, tile = blockIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const uint32_t b0 = tile * RS_TILE, b1 = min(n, b0 + RS_TILE);
+  for (uint32_t i = b0 + t; i < b1; i += 256) atomicAdd(&h[(uint32_t)(in[i] >> shift) & mask], 1u);
+  __syncthreads();
+  hist[(size_t)t * ntiles + tile] = h[t];
+}
+
+__global__ void __launch_bounds__(256) k_rs_scan(Index ix, uint32_t* hist, uint32_t ntiles, uint32_t* tot, Dyn d) {
+  __shared__ uint32_t ws[4];
+  if (gated(ix, d)) return;
+  uint32_t* row = hist + (size_t)blockIdx.x * ntiles;
+  const uint32_t t = threadIdx.x, w = t >> 6;
+  uint32_t carry = 0;
+  for (uint32_t c = 0; c < ntiles; c += 256) {
+    const uint32_t i = c + t;
+    const uint32_t v = i < ntiles ? row[i] : 0u;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane_id() == 63) ws[w] = incl;
+    __syncthreads();
+    uint32_t before = carry;
+    for (uint32_t k = 0; k < w; ++k) before += ws[k];
+    if (i < ntiles) row[i] = before + incl - v;
+    carry += ws[0] + ws[1] + ws[2] + ws[3];
+    __syncthreads();
+  }
+  if (t == 0) tot[blockIdx.x] = carry;
+}
+
+__global__ void __launch_bounds__(256) k_rs_scatter(Index ix, const uint64_t* in, uint64_t* out, uint32_t cap, Dyn d,
+                                                    int shift, uint32_t mask, const uint32_t* hist,
+                                                    const uint32_t* tot, uint32_t ntiles) {
+  __shared__ uint32_t base[256], run[256], wh[4][256], ws[4];
+  if (gated(ix, d)) return;
+  const uint32_t n = dyn_count(ix, d, cap);
+  const uint32_t t = threadIdx.x, w = t >> 6, tile = blockIdx.x;
+  const uint32_t b0 = tile * RS_TILE;
+  if (b0 >= n) return;
+  {
+    const uint32_t v = tot[t];
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane_id() == 63) ws[w] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t k = 0; k < w; ++k) before += ws[k];
+    base[t] = before + incl - v + hist[(size_t)t * ntiles + tile];
+    run[t] = 0;
+    wh[0][t] = wh[1][t] = wh[2][t] = wh[3][t] = 0;
+  }
+  __syncthreads();
+  for (uint32_t r = 0; r < RS_TILE / 256 && b0 + r * 256 < n; ++r) {
+    const uint32_t i = b0 + r * 256 + t;
+    const bool valid = i < n;
+    uint64_t key = 0;
+    uint32_t dg = 0;
+    if (valid) {
+      key = in[i];
+      dg = (uint32_t)(key >> shift) & mask;
+    }
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (dg >> b) & 1u;
+      const uint64_t bb = ballot(valid && bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = lanes_below(peers);
+    if (valid && rank == 0) wh[w][dg] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = run[dg] + rank;
+      for (uint32_t k = 0; k < w; ++k) off += wh[k][dg];
+      out[base[dg] + off] = key;
+    }
+    __syncthreads();
+    run[t] += wh[0][t] + wh[1][t] + wh[2][t] + wh[3][t];
+    wh[0][t] = wh[1][t] = wh[2][t] = wh[3][t] = 0;
+    __syncthreads();
+  }
+}
+
 // ---- reclaim (Algorithm 4) -------------------------------------------------------------
-__global__ void k_del_bitmap(Index ix, uint64_t n_ids, uint64_t* bitmap) {
+__global__ void k_del_bitmap(Index ix, uint64_t n_ids, Dyn d, uint64_t* bitmap) {
+  if (gated(ix, d)) return;
+  n_ids = dyn_count(ix, d, (uint32_t)n_ids);
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool d = t < n_ids && ref_del(load_ref(ix, (uint32_t)t));
-  const uint64_t m = ballot(d);
+  if (t == 0) {
+    ix.ctr[C_DIRTY] = 0;
+    ix.ctr[C_DEAD] = 0;
+  }
+  const bool flagged = t < n_ids && ref_del(load_ref(ix, (uint32_t)t));
+  const uint64_t m = ballot(flagged);
   if (lane_id() == 0 && t < n_ids) bitmap[t >> 6] = m;
 }
 
 __device__ inline bool bit_set(const uint64_t* bm, uint32_t id) { return (bm[id >> 6] >> (id & 63u)) & 1ull; }
 
 // live nodes with an edge into a tombstone ("dirty"), and the count of such edges
-__global__ void k_dirty(Index ix, uint64_t n_ids, const uint64_t* bitmap, uint32_t* dirty) {
-  const uint32_t u = wave_index();
-  if (u >= n_ids) return;
+__device__ inline void dirty_one(const Index& ix, const uint64_t* bitmap, uint32_t* dirty, uint32_t u) {
   const int l = lane_id();
   const uint64_t r = bcast64(load_ref(ix, u));
   if (ref_del(r) || ref_slab(r) == NONE) return;
@@ -968,16 +1292,15 @@ __global__ void k_dirty(Index ix, uint64_t n_ids, const uint64_t* bitmap, uint32
   }
 }
 
+__global__ void k_dirty(Index ix, uint64_t n_ids, Dyn d, const uint64_t* bitmap, uint32_t* dirty) {
+  if (gated(ix, d)) return;
+  const uint32_t n = dyn_count(ix, d, (uint32_t)n_ids);
+  FOR_EACH_WAVE_ITEM(u, n) dirty_one(ix, bitmap, dirty, u);
+}
+
 // phase 1, compaction: republish each dirty node without its tombstoned entries
-__global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty, uint64_t n, const uint64_t* bitmap,
-                                                 uint32_t lds_per_wave) {
-  extern __shared__ __align__(16) char smem[];
-  const uint32_t i = wave_index();
-  if (i >= n) return;
+__device__ inline void compact_one(const Index& ix, const uint64_t* bitmap, uint32_t* ids, uint32_t* d, uint32_t u) {
   const int l = lane_id();
-  uint32_t* ids = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * lds_per_wave);
-  uint32_t* d = ids + 64;
-  const uint32_t u = dirty[i];
   const uint64_t r = bcast64(load_ref(ix, u));
   const uint32_t deg = ref_deg(r), s = ref_slab(r);
   uint32_t id = NONE, dd = 0;
@@ -995,8 +1318,22 @@ __global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty
   publish(ix, u, ids, d, (uint32_t)__popcll(m), C_PUB_COMPACT);
 }
 
+__global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty, uint64_t n, Dyn dn,
+                                                 const uint64_t* bitmap, uint32_t lds_per_wave) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, dn)) return;
+  const uint32_t cnt = dyn_count(ix, dn, (uint32_t)n);
+  uint32_t* ids = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * lds_per_wave);
+  FOR_EACH_WAVE_ITEM(i, cnt) {
+    wave_sync();
+    compact_one(ix, bitmap, ids, ids + 64, dirty[i]);
+  }
+}
+
 // phase 2: <1,d,s> -> <1,0,none> and the slab is retired
-__global__ void k_free_tombstones(Index ix, uint64_t n_ids) {
+__global__ void k_free_tombstones(Index ix, uint64_t n_ids, Dyn d) {
+  if (gated(ix, d)) return;
+  n_ids = dyn_count(ix, d, (uint32_t)n_ids);
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_ids) return;
   const uint32_t u = (uint32_t)t;
@@ -1081,8 +1418,11 @@ __global__ void __launch_bounds__(64) k_bruteforce_u8(Index ix, const uint8_t* q
 // ---- float rows: traversal copies written on insert ------------------------------------------
 // One wave per new row: bf16 copy (round to nearest even) and/or FP8 e4m3
 // copy of x / s with s = max|x_i| / 448 (s = 1 for an all-zero row).
-__global__ void __launch_bounds__(256) k_encode_f32(Index ix, uint32_t first, uint32_t n, float* xs, uint16_t* xb,
-                                                    uint8_t* x8) {
+__global__ void __launch_bounds__(256) k_encode_f32(Index ix, uint32_t first, uint32_t n, Dyn d, float* xs,
+                                                    uint16_t* xb, uint8_t* x8) {
+  if (gated(ix, d)) return;
+  n = dyn_count(ix, d, n);
+  first = dyn_first(ix, d, first);
   const uint32_t i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= n) return;
   const int l = lane_id();
@@ -1159,6 +1499,14 @@ __global__ void __launch_bounds__(64) k_bruteforce_f32(Index ix, const float* q,
 
 static inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
 
+// Item loops run on persistent waves: a launch never needs more workgroups
+// than this (the chip holds 256 CUs x a few workgroups; the rest would queue).
+constexpr unsigned PERSIST_BLOCKS = 2048;
+static inline unsigned persist_grid(uint64_t items, unsigned per_block) {
+  const unsigned b = blocks_for(items, per_block);
+  return b < PERSIST_BLOCKS ? (b ? b : 1u) : PERSIST_BLOCKS;
+}
+
 hipError_t launch_init(const Index& ix, hipStream_t s) {
   hipLaunchKernelGGL(k_init, dim3(1024), dim3(256), 0, s, ix);
   return hipGetLastError();
@@ -1169,14 +1517,74 @@ hipError_t launch_recycle(const Index& ix, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_write_ids(uint32_t* out, uint32_t first, uint64_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_write_ids, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, first, n);
+hipError_t launch_round_begin(const Index& ix, const uint32_t* counts, uint32_t nd, uint32_t ni, uint32_t nq,
+                              uint32_t max_d, uint32_t max_i, uint32_t max_q, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, ix, counts, nd, ni, nq, max_d, max_i, max_q, status);
   return hipGetLastError();
 }
 
-hipError_t launch_refresh_entries(const Index& ix, uint32_t next_id, uint32_t S, hipStream_t s) {
-  hipLaunchKernelGGL(k_refresh_entries, dim3(1), dim3(1024), 0, s, ix, next_id, S);
+hipError_t launch_round_gate(const Index& ix, uint32_t tombstone_only, uint32_t boot_max, int32_t* status,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_round_gate, dim3(1), dim3(64), 0, s, ix, tombstone_only, boot_max, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_reclaim_gate(const Index& ix, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_reclaim_gate, dim3(1), dim3(64), 0, s, ix, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_rows(const Index& ix, const void* src, uint32_t* ids_out, uint32_t first, uint32_t n, Dyn d,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t words = (uint64_t)n * (ix.metric == 0 ? ix.dim / 16u : ix.dim / 4u);
+  hipLaunchKernelGGL(k_store_rows, dim3(persist_grid(words, 256)), dim3(256), 0, s, ix, (const uint4*)src, ids_out,
+                     first, n, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_entries(const Index& ix, uint32_t bound, uint32_t S, Dyn d, hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh_entries, dim3(1), dim3(1024), 0, s, ix, bound, S, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_segments(const Index& ix, const uint64_t* pairs, uint32_t nmax, Dyn d, uint32_t* seg,
+                           hipStream_t s) {
+  if (nmax == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segments, dim3(blocks_for(nmax, 256)), dim3(256), 0, s, ix, pairs, nmax, d, seg);
+  return hipGetLastError();
+}
+
+uint32_t sort_hist_words(uint32_t nmax) {
+  const uint32_t tiles = nmax ? blocks_for(nmax, RS_TILE) : 1u;
+  return 256u * tiles + 256u;
+}
+
+hipError_t launch_sort(const Index& ix, uint64_t* a, uint64_t* b, uint32_t nmax, Dyn d, int lo, int nbits,
+                       uint32_t* hist, hipStream_t s, uint64_t** result, int low_bits) {
+  *result = a;
+  if (nmax == 0) return hipSuccess;
+  const uint32_t ntiles = blocks_for(nmax, RS_TILE);
+  uint32_t* tot = hist + 256u * ntiles;
+  uint64_t* src = a;
+  uint64_t* dst = b;
+  // least significant digits first: bits [0, low_bits), then [lo, lo + nbits)
+  for (int part = 0; part < 2; ++part) {
+    const int from = part == 0 ? 0 : lo, width_all = part == 0 ? low_bits : nbits;
+    for (int sh = 0; sh < width_all; sh += 8) {
+      const int width = width_all - sh < 8 ? width_all - sh : 8;
+      const uint32_t mask = (1u << width) - 1u;
+      hipLaunchKernelGGL(k_rs_count, dim3(ntiles), dim3(256), 0, s, ix, (const uint64_t*)src, nmax, d, from + sh,
+                         mask, hist, ntiles);
+      hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(256), 0, s, ix, hist, ntiles, tot, d);
+      hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(256), 0, s, ix, (const uint64_t*)src, dst, nmax, d,
+                         from + sh, mask, (const uint32_t*)hist, (const uint32_t*)tot, ntiles);
+      uint64_t* t = src;
+      src = dst;
+      dst = t;
+    }
+  }
+  *result = src;
   return hipGetLastError();
 }
 
@@ -1190,8 +1598,10 @@ uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots) {
 static inline int float_lanes(uint32_t dim, int elem_bytes) { return (int)(dim * (uint32_t)elem_bytes / 16u / 3u); }
 
 hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEvent_t after_dist) {
-  if (a.nq == 0 || a.ns == 0) return hipSuccess;
-  const dim3 dgrid(blocks_for(a.ns, SD_E), blocks_for(a.nq, SD_Q));
+  if (a.nq == 0) return hipSuccess;
+  // shapes from the upper bounds; the kernels resolve the launch-time counts
+  const uint64_t tiles = (uint64_t)blocks_for(a.ns ? a.ns : 1u, SD_E) * blocks_for(a.nq, SD_Q);
+  const dim3 dgrid(tiles < 2 * PERSIST_BLOCKS ? (unsigned)tiles : 2 * PERSIST_BLOCKS);
   if (ix.metric == 0) {
     hipLaunchKernelGGL(k_scan_dist, dgrid, dim3(256), 0, s, ix, a);
   } else {
@@ -1230,7 +1640,7 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEve
 
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s) {
   if (a.nq == 0) return hipSuccess;
-  const unsigned grid = blocks_for(a.nq, waves_per_block);
+  const unsigned grid = a.persistent ? persist_grid(a.nq, waves_per_block) : blocks_for(a.nq, waves_per_block);
   const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
   if (ix.metric == 0) {
     switch (ix.dim / 16) {
@@ -1292,7 +1702,7 @@ static void launch_maint_p(MaintKernel which, const Index& ix, const MaintArgs& 
 hipError_t launch_maint(MaintKernel which, const Index& ix, const MaintArgs& a, uint32_t nwaves,
                         uint32_t waves_per_block, hipStream_t s) {
   if (nwaves == 0) return hipSuccess;
-  const unsigned grid = blocks_for(nwaves, waves_per_block);
+  const unsigned grid = persist_grid(nwaves, waves_per_block);
   const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
   const dim3 blk(64 * waves_per_block);
   if (ix.metric == 0) {
@@ -1346,10 +1756,10 @@ hipError_t launch_set_lists(const Index& ix, const MaintArgs& a, const uint32_t*
   return hipGetLastError();
 }
 
-hipError_t launch_encode(const Index& ix, uint32_t first, uint32_t n, float* xs, uint16_t* xb, uint8_t* x8,
+hipError_t launch_encode(const Index& ix, uint32_t first, uint32_t n, Dyn d, float* xs, uint16_t* xb, uint8_t* x8,
                          hipStream_t s) {
   if (n == 0 || (!xb && !x8)) return hipSuccess;
-  hipLaunchKernelGGL(k_encode_f32, dim3(blocks_for(n, 4)), dim3(256), 0, s, ix, first, n, xs, xb, x8);
+  hipLaunchKernelGGL(k_encode_f32, dim3(blocks_for(n, 4)), dim3(256), 0, s, ix, first, n, d, xs, xb, x8);
   return hipGetLastError();
 }
 
@@ -1361,54 +1771,55 @@ hipError_t launch_reverse_pairs(const Index& ix, const MaintArgs& a, hipStream_t
 }
 
 hipError_t launch_repair_pairs(const Index& ix, const MaintArgs& a, hipStream_t s) {
-  if (a.n == 0) return hipSuccess;
+  if (a.n == 0) return hipSuccess;  // a.n: upper bound; the kernel reads the accepted count
   hipLaunchKernelGGL(k_repair_pairs, dim3(blocks_for(a.n, 4)), dim3(256), 0, s, ix, a);
   return hipGetLastError();
 }
 
-hipError_t launch_del_keys(const uint32_t* ids, uint64_t n, uint64_t* keys, hipStream_t s) {
+hipError_t launch_del_keys(const Index& ix, const uint32_t* ids, uint32_t n, Dyn d, uint64_t* keys, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_del_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, ids, n, keys);
+  hipLaunchKernelGGL(k_del_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, ix, ids, n, d, keys);
   return hipGetLastError();
 }
 
-hipError_t launch_del_classify(const Index& ix, const uint64_t* sorted, uint64_t n, uint64_t next_id,
-                               uint8_t* status, uint32_t* dlist, hipStream_t s) {
+hipError_t launch_del_classify(const Index& ix, const uint64_t* sorted, uint32_t n, Dyn d, uint8_t* status,
+                               uint32_t* dlist, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_del_classify, dim3(blocks_for(n, 256)), dim3(256), 0, s, ix, sorted, n, next_id, status,
-                     dlist);
+  hipLaunchKernelGGL(k_del_classify, dim3(blocks_for(n, 256)), dim3(256), 0, s, ix, sorted, n, d, status, dlist);
   return hipGetLastError();
 }
 
-hipError_t launch_tombstone(const Index& ix, const uint32_t* dlist, uint64_t n, hipStream_t s) {
+hipError_t launch_tombstone(const Index& ix, const uint32_t* dlist, uint32_t n, Dyn d, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tombstone, dim3(blocks_for(n, 256)), dim3(256), 0, s, ix, dlist, n);
+  hipLaunchKernelGGL(k_tombstone, dim3(blocks_for(n, 256)), dim3(256), 0, s, ix, dlist, n, d);
   return hipGetLastError();
 }
 
-hipError_t launch_del_bitmap(const Index& ix, uint64_t n_ids, uint64_t* bitmap, hipStream_t s) {
+hipError_t launch_del_bitmap(const Index& ix, uint64_t n_ids, Dyn d, uint64_t* bitmap, hipStream_t s) {
   if (n_ids == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_del_bitmap, dim3(blocks_for(n_ids, 256)), dim3(256), 0, s, ix, n_ids, bitmap);
+  hipLaunchKernelGGL(k_del_bitmap, dim3(blocks_for(n_ids, 256)), dim3(256), 0, s, ix, n_ids, d, bitmap);
   return hipGetLastError();
 }
 
-hipError_t launch_dirty(const Index& ix, uint64_t n_ids, const uint64_t* bitmap, uint32_t* dirty, hipStream_t s) {
+hipError_t launch_dirty(const Index& ix, uint64_t n_ids, Dyn d, const uint64_t* bitmap, uint32_t* dirty,
+                        hipStream_t s) {
   if (n_ids == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dirty, dim3(blocks_for(n_ids, 4)), dim3(256), 0, s, ix, n_ids, bitmap, dirty);
+  hipLaunchKernelGGL(k_dirty, dim3(persist_grid(n_ids, 4)), dim3(256), 0, s, ix, n_ids, d, bitmap, dirty);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const Index& ix, const uint32_t* dirty, uint64_t n, const uint64_t* bitmap,
+hipError_t launch_compact(const Index& ix, const uint32_t* dirty, uint64_t n, Dyn d, const uint64_t* bitmap,
                           hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint32_t per_wave = 512;
-  hipLaunchKernelGGL(k_compact, dim3(blocks_for(n, 4)), dim3(256), 4 * per_wave, s, ix, dirty, n, bitmap, per_wave);
+  hipLaunchKernelGGL(k_compact, dim3(persist_grid(n, 4)), dim3(256), 4 * per_wave, s, ix, dirty, n, d, bitmap,
+                     per_wave);
   return hipGetLastError();
 }
 
-hipError_t launch_free_tombstones(const Index& ix, uint64_t n_ids, hipStream_t s) {
+hipError_t launch_free_tombstones(const Index& ix, uint64_t n_ids, Dyn d, hipStream_t s) {
   if (n_ids == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_free_tombstones, dim3(blocks_for(n_ids, 256)), dim3(256), 0, s, ix, n_ids);
+  hipLaunchKernelGGL(k_free_tombstones, dim3(blocks_for(n_ids, 256)), dim3(256), 0, s, ix, n_ids, d);
   return hipGetLastError();
 }
 

@@ -5,9 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace etale {
+#include "etale_dev.h"
 
-struct Index;
+namespace etale {
 
 enum SearchMode { MODE_QUERY = 0, MODE_INSERT = 1, MODE_BOOT = 2 };
 enum DelStatus { DEL_OK = 0, DEL_NOT_LIVE = 1, DEL_OUT_OF_RANGE = 2, DEL_DUPLICATE = 3 };
@@ -29,6 +29,8 @@ struct SearchArgs {
   uint64_t* vis_keys;  // MODE_INSERT: [nq x vcap] expanded keys
   uint32_t* vis_cnt;   // [nq]
   uint32_t* counts;    // optional [nq x 2]: expansions, distance evaluations
+  Dyn d;               // launch-time count (nq) and first id
+  uint32_t persistent; // 1: waves take queries from a work queue (count known only on the device)
 };
 
 // k_scan: the L best start nodes (entry set, or the batch for a bootstrap,
@@ -43,6 +45,8 @@ struct ScanArgs {
   uint64_t* out_keys;  // [nq x out_stride]
   uint32_t* out_n;     // [nq]
   uint32_t out_stride;
+  uint32_t ns_ctr;     // counter with the start-set size (NO_CTR: ns as given)
+  Dyn d;               // launch-time count (nq) and first id
 };
 
 struct MaintArgs {
@@ -59,14 +63,24 @@ struct MaintArgs {
   uint32_t prune_cap;      // LDS staging rows
   uint32_t vstride;        // bytes per staged row
   uint32_t lds_per_wave;
+  const uint32_t* seg;     // starts of the runs of one target in the sorted pairs
+  uint32_t np_ctr = NO_CTR, np_mult = 1;  // launch-time pair count
+  Dyn d;                   // launch-time count (n) and first id
 };
 
 enum MaintKernel { MK_FORWARD = 0, MK_REVERSE = 1, MK_REFINE = 2, MK_REPAIR = 3 };
 
 hipError_t launch_init(const Index& ix, hipStream_t s);
 hipError_t launch_recycle(const Index& ix, hipStream_t s);
-hipError_t launch_write_ids(uint32_t* out, uint32_t first, uint64_t n, hipStream_t s);
-hipError_t launch_refresh_entries(const Index& ix, uint32_t next_id, uint32_t S, hipStream_t s);
+// round control: counts (device array, or the host values when null), gate
+hipError_t launch_round_begin(const Index& ix, const uint32_t* counts, uint32_t nd, uint32_t ni, uint32_t nq,
+                              uint32_t max_d, uint32_t max_i, uint32_t max_q, int32_t* status, hipStream_t s);
+hipError_t launch_round_gate(const Index& ix, uint32_t tombstone_only, uint32_t boot_max, int32_t* status,
+                             hipStream_t s);
+hipError_t launch_reclaim_gate(const Index& ix, int32_t* status, hipStream_t s);
+hipError_t launch_store_rows(const Index& ix, const void* src, uint32_t* ids_out, uint32_t first, uint32_t n, Dyn d,
+                             hipStream_t s);
+hipError_t launch_refresh_entries(const Index& ix, uint32_t bound, uint32_t S, Dyn d, hipStream_t s);
 uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots);
 uint32_t scan_select_lds_per_wave(uint32_t L);
 hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEvent_t after_dist = nullptr);
@@ -76,20 +90,29 @@ hipError_t launch_maint(MaintKernel which, const Index& ix, const MaintArgs& a, 
                         uint32_t waves_per_block, hipStream_t s);
 hipError_t launch_reverse_pairs(const Index& ix, const MaintArgs& a, hipStream_t s);
 hipError_t launch_repair_pairs(const Index& ix, const MaintArgs& a, hipStream_t s);
-hipError_t launch_del_keys(const uint32_t* ids, uint64_t n, uint64_t* keys, hipStream_t s);
-hipError_t launch_del_classify(const Index& ix, const uint64_t* sorted, uint64_t n, uint64_t next_id,
-                               uint8_t* status, uint32_t* dlist, hipStream_t s);
-hipError_t launch_tombstone(const Index& ix, const uint32_t* dlist, uint64_t n, hipStream_t s);
-hipError_t launch_del_bitmap(const Index& ix, uint64_t n_ids, uint64_t* bitmap, hipStream_t s);
-hipError_t launch_dirty(const Index& ix, uint64_t n_ids, const uint64_t* bitmap, uint32_t* dirty, hipStream_t s);
-hipError_t launch_compact(const Index& ix, const uint32_t* dirty, uint64_t n, const uint64_t* bitmap,
+hipError_t launch_segments(const Index& ix, const uint64_t* pairs, uint32_t nmax, Dyn d, uint32_t* seg,
+                           hipStream_t s);
+// stable LSD radix sort of 64-bit keys on bits [lo, lo + nbits), preceded by
+// bits [0, low_bits) (so the order is by the high range, then the low one);
+// count read at launch time; returns the buffer (a or b) holding the result
+uint32_t sort_hist_words(uint32_t nmax);
+hipError_t launch_sort(const Index& ix, uint64_t* a, uint64_t* b, uint32_t nmax, Dyn d, int lo, int nbits,
+                       uint32_t* hist, hipStream_t s, uint64_t** result, int low_bits = 0);
+hipError_t launch_del_keys(const Index& ix, const uint32_t* ids, uint32_t n, Dyn d, uint64_t* keys, hipStream_t s);
+hipError_t launch_del_classify(const Index& ix, const uint64_t* sorted, uint32_t n, Dyn d, uint8_t* status,
+                               uint32_t* dlist, hipStream_t s);
+hipError_t launch_tombstone(const Index& ix, const uint32_t* dlist, uint32_t n, Dyn d, hipStream_t s);
+hipError_t launch_del_bitmap(const Index& ix, uint64_t n_ids, Dyn d, uint64_t* bitmap, hipStream_t s);
+hipError_t launch_dirty(const Index& ix, uint64_t n_ids, Dyn d, const uint64_t* bitmap, uint32_t* dirty,
+                        hipStream_t s);
+hipError_t launch_compact(const Index& ix, const uint32_t* dirty, uint64_t n, Dyn d, const uint64_t* bitmap,
                           hipStream_t s);
-hipError_t launch_free_tombstones(const Index& ix, uint64_t n_ids, hipStream_t s);
+hipError_t launch_free_tombstones(const Index& ix, uint64_t n_ids, Dyn d, hipStream_t s);
 hipError_t launch_export(const Index& ix, uint64_t n_ids, uint32_t* nbr, uint32_t* rho, uint8_t* deg, uint8_t* del,
                          uint8_t* has_slab, hipStream_t s);
 hipError_t launch_bruteforce(const Index& ix, const void* q, uint32_t nq, uint64_t n_ids, uint32_t k,
                              uint32_t* out_ids, uint32_t* out_d, hipStream_t s);
-hipError_t launch_encode(const Index& ix, uint32_t first, uint32_t n, float* xs, uint16_t* xb, uint8_t* x8,
+hipError_t launch_encode(const Index& ix, uint32_t first, uint32_t n, Dyn d, float* xs, uint16_t* xb, uint8_t* x8,
                          hipStream_t s);
 hipError_t launch_set_lists(const Index& ix, const MaintArgs& a, const uint32_t* ids, const uint32_t* nbr,
                             const uint32_t* deg, hipStream_t s);

@@ -54,6 +54,16 @@ class Stats(C.Structure):
         "device_bytes", "error_bits")]
 
 
+class RoundDesc(C.Structure):
+    _fields_ = [
+        ("del_ids", C.c_void_p), ("del_status", C.c_void_p), ("max_del", C.c_uint32),
+        ("ins_vecs", C.c_void_p), ("ins_ids", C.c_void_p), ("max_ins", C.c_uint32),
+        ("queries", C.c_void_p), ("q_ids", C.c_void_p), ("q_dists", C.c_void_p), ("max_q", C.c_uint32),
+        ("k", C.c_uint32), ("L", C.c_uint32), ("counts", C.c_void_p), ("status", C.c_void_p),
+        ("reclaim", C.c_int32), ("graph", C.c_int32),
+    ]
+
+
 _lib = None
 
 
@@ -78,6 +88,7 @@ def load() -> C.CDLL:
         "etale_delete_batch": ([vp, vp, u64, vp], i32),
         "etale_search_batch": ([vp, vp, u64, u32, u32, vp, vp, vp], i32),
         "etale_reclaim": ([vp], i32),
+        "etale_round": ([vp, C.POINTER(RoundDesc)], i32),
         "etale_bruteforce": ([vp, vp, u64, u32, vp, vp], i32),
         "etale_get_stats": ([vp, C.POINTER(Stats)], i32),
         "etale_export": ([vp, u64, vp, vp, vp, vp, vp], i32),
@@ -192,6 +203,30 @@ class Index:
     def reclaim(self):
         self._check(self.lib.etale_reclaim(self.h), "reclaim")
 
+    def round(self, del_ids=None, x=None, q=None, k: int = 10, L: int = 64, reclaim: bool = False) -> dict:
+        """One round (deletes, inserts, queries in one epoch) with the counts
+        given by the inputs. Returns device tensors; `status` holds the round
+        and reclaim status words once the stream has reached them."""
+        torch = self.torch
+        dev = torch.device("cuda")
+        dl = self._dev(del_ids, torch.int32) if del_ids is not None else None
+        xv = self._dev(x, self._vdtype) if x is not None else None
+        qv = self._dev(q, self._vdtype) if q is not None else None
+        nd = 0 if dl is None else dl.numel()
+        ni = 0 if xv is None else xv.shape[0]
+        nq = 0 if qv is None else qv.shape[0]
+        out = {"status": torch.zeros(2, dtype=torch.int32, device=dev),
+               "del_status": torch.empty(nd, dtype=torch.uint8, device=dev),
+               "ids": torch.empty(ni, dtype=torch.int32, device=dev),
+               "q_ids": torch.empty((nq, k), dtype=torch.int32, device=dev),
+               "q_dists": torch.empty((nq, k), dtype=self._ddtype, device=dev)}
+        desc = RoundDesc(_ptr(dl), _ptr(out["del_status"]), nd, _ptr(xv), _ptr(out["ids"]), ni, _ptr(qv),
+                         _ptr(out["q_ids"]), _ptr(out["q_dists"]), nq, k, L, None, _ptr(out["status"]),
+                         int(reclaim), 0)
+        self._keep = (dl, xv, qv)  # inputs stay alive until the next call
+        self._check(self.lib.etale_round(self.h, C.byref(desc)), "round")
+        return out
+
     def bruteforce(self, q, k: int):
         torch = self.torch
         q = self._dev(q, self._vdtype)
@@ -264,3 +299,51 @@ class Index:
         self._check(self.lib.etale_get_search_timing(self.h, ms.ctypes.data_as(C.c_void_p), cap, C.byref(n)),
                     "get_search_timing")
         return ms[:min(n.value, cap)].copy()
+
+
+class RoundRunner:
+    """Rounds of uneven sizes through fixed device buffers, so that one
+    captured HIP graph serves every round: the counts are written into device
+    memory before each replay and the kernels read them when they run.
+
+    Inputs are copied into the buffers on the index's stream; outputs are
+    views of the buffers, valid until the next call."""
+
+    def __init__(self, index: Index, max_del: int, max_ins: int, max_q: int, k: int = 10, L: int = 64,
+                 reclaim: bool = False, graph: bool = True):
+        torch = index.torch
+        self.ix, self.torch = index, torch
+        dev = torch.device("cuda")
+        self.max_del, self.max_ins, self.max_q, self.k = max_del, max_ins, max_q, k
+        self.del_ids = torch.zeros(max(max_del, 1), dtype=torch.int32, device=dev)
+        self.del_status = torch.zeros(max(max_del, 1), dtype=torch.uint8, device=dev)
+        self.vecs = torch.zeros((max(max_ins, 1), index.dim), dtype=index._vdtype, device=dev)
+        self.ids = torch.zeros(max(max_ins, 1), dtype=torch.int32, device=dev)
+        self.q = torch.zeros((max(max_q, 1), index.dim), dtype=index._vdtype, device=dev)
+        self.q_ids = torch.zeros((max(max_q, 1), k), dtype=torch.int32, device=dev)
+        self.q_dists = torch.zeros((max(max_q, 1), k), dtype=index._ddtype, device=dev)
+        self.counts = torch.zeros(3, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.desc = RoundDesc(_ptr(self.del_ids), _ptr(self.del_status), max_del, _ptr(self.vecs), _ptr(self.ids),
+                              max_ins, _ptr(self.q), _ptr(self.q_ids), _ptr(self.q_dists), max_q, k, L,
+                              _ptr(self.counts), _ptr(self.status), int(reclaim), int(graph))
+
+    def __call__(self, del_ids=None, x=None, q=None, counts=None) -> dict:
+        """Copy this round's inputs into the buffers, set the counts and run
+        the round. `counts` (nd, ni, nq) may override the input lengths, e.g.
+        to pass counts above the maximum on purpose."""
+        nd = 0 if del_ids is None else del_ids.numel()
+        ni = 0 if x is None else x.shape[0]
+        nq = 0 if q is None else q.shape[0]
+        if nd:
+            self.del_ids[:nd].copy_(del_ids.reshape(-1))
+        if ni:
+            self.vecs[:ni].copy_(x)
+        if nq:
+            self.q[:nq].copy_(q)
+        c = counts if counts is not None else (nd, ni, nq)
+        for i in range(3):
+            self.counts[i].fill_(int(c[i]))
+        self.ix._check(self.ix.lib.etale_round(self.ix.h, C.byref(self.desc)), "round")
+        return {"status": self.status, "del_status": self.del_status[:nd], "ids": self.ids[:ni],
+                "q_ids": self.q_ids[:nq], "q_dists": self.q_dists[:nq]}

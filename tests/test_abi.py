@@ -21,7 +21,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("etale_create", "etale_destroy", "etale_insert_batch", "etale_delete_batch", "etale_search_batch",
-              "etale_reclaim", "etale_get_stats", "etale_export", "etale_sync", "etale_last_error"):
+              "etale_reclaim", "etale_round", "etale_get_stats", "etale_export", "etale_sync", "etale_last_error"):
         assert n in names
 
 
@@ -38,8 +38,10 @@ def _c_layout():
 #include <stddef.h>
 #include "etale.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(etale_config), offsetof(etale_config, id_capacity),
-         offsetof(etale_config, hip_stream), sizeof(etale_stats), offsetof(etale_stats, error_bits));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(etale_config), offsetof(etale_config, id_capacity),
+         offsetof(etale_config, hip_stream), sizeof(etale_stats), offsetof(etale_stats, error_bits),
+         sizeof(etale_round_desc), offsetof(etale_round_desc, max_q), offsetof(etale_round_desc, counts),
+         offsetof(etale_round_desc, graph));
   return 0;
 }
 """
@@ -53,12 +55,16 @@ int main(void) {
 
 def test_struct_layout_matches_header():
     from paper_2607_02543_amd import etale
-    size, off_cap, off_stream, ssize, off_err = _c_layout()
+    size, off_cap, off_stream, ssize, off_err, rsize, off_mq, off_cnt, off_graph = _c_layout()
     assert C.sizeof(etale.Config) == size
     assert etale.Config.id_capacity.offset == off_cap
     assert etale.Config.hip_stream.offset == off_stream
     assert C.sizeof(etale.Stats) == ssize
     assert etale.Stats.error_bits.offset == off_err
+    assert C.sizeof(etale.RoundDesc) == rsize
+    assert etale.RoundDesc.max_q.offset == off_mq
+    assert etale.RoundDesc.counts.offset == off_cnt
+    assert etale.RoundDesc.graph.offset == off_graph
 
 
 def test_create_rejects_bad_configs_without_touching_a_device():
