@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=5000)
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", default="scale_u8_1m", choices=["scale_u8_1m", "precision_f32"])
+    ap.add_argument("--workload", default="scale_u8_1m", choices=["scale_u8_1m", "precision_f32", "batching_f32"])
+    ap.add_argument("--rounds", type=int, default=0, help="batching workload: timed rounds (default 50)")
     ap.add_argument("--prune-cap", type=int, default=0)
     ap.add_argument("--W", type=int, default=2, help="expansions per search iteration (1 or 2)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -236,6 +237,138 @@ def run_precision(args):
     }
 
 
+def run_batching(args):
+    """Uneven rounds on a 4M x 96-d float index: one launch per phase (host
+    counts, exact grids) against the same rounds replayed from a captured HIP
+    graph (device counts, launch shapes fixed at the largest round). Both run
+    on identical indexes built from the same inputs; their outputs must agree."""
+    import torch
+
+    from paper_2607_02543_amd import datagen as dg
+    from paper_2607_02543_amd import etale
+
+    dev = torch.device("cuda:0")
+    n_base = args.n_base if args.n_base != 1_000_000 else 4_000_000
+    n_rounds = args.rounds or 50
+    wl = dg.batching_f32(n_base=n_base, rounds=n_rounds)
+    st = dg.Stream(wl)
+    params = [st.round_params(n_base) for _ in range(args.warmup + n_rounds)]
+    max_n = max(max(p["n_ins"] for p in params), 1)
+    max_b = max(max_n, wl.build_batch_max)
+    cap = n_base + sum(p["n_ins"] for p in params) + 16
+    slab_cap = 2 * n_base + 3 * max_b * (wl.R + 2)
+    n_entry = args.n_entry
+    kw = dict(R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den), n_entry=n_entry, id_capacity=cap,
+              slab_capacity=slab_cap, max_batch=max_b, metric=etale.METRIC_IP_F32, W=args.W)
+    t0 = time.perf_counter()
+    A = etale.Index(wl.dim, **kw)
+    B = etale.Index(wl.dim, **kw)
+    live = np.zeros(cap, bool)
+    done = 0
+    for b in wl.build_batches():
+        x = torch.from_numpy(st.base(b)).to(dev)
+        A.insert(x)
+        B.insert(x)
+        live[done:done + b] = True
+        done += b
+        log(args, f"built {done}")
+    torch.cuda.synchronize()
+    t_build = (time.perf_counter() - t0) / 2
+    next_id = done
+    # result-invariant knobs, tuned on one query batch, applied to both modes
+    qt = torch.from_numpy(st.queries(10000)).to(dev)
+    tune = B.autotune(qt, 10, 64)
+    A.set_search_knobs(tune["waves_per_block"], tune["vt_slots"])
+    runners = {k: etale.RoundRunner(B, max_n, max_n, 65536, k=k, L=max(64, k), reclaim=True, graph=True,
+                                    buckets=True) for k in (10, 100)}
+    # every size bucket of the run is captured before timing (zero-count rounds change nothing)
+    t_cap = time.perf_counter()
+    for k in (10, 100):
+        runners[k].prepare([(p["n_del"], p["n_ins"], p["n_q"]) for p in params if p["k"] == k])
+    torch.cuda.synchronize()
+    t_cap = time.perf_counter() - t_cap
+    rows = []
+    mismatch = 0
+    for r, p in enumerate(params):
+        lids = np.nonzero(live[:next_id])[0].astype(np.uint32)
+        dl = st.deletes(lids, p["n_del"])
+        x = st.inserts(p["n_ins"])
+        q = st.queries(p["n_q"])
+        live[dl] = False
+        live[next_id:next_id + p["n_ins"]] = True
+        next_id += p["n_ins"]
+        dlt = torch.from_numpy(dl.astype(np.int32)).to(dev)
+        xt = torch.from_numpy(x).to(dev)
+        q_t = torch.from_numpy(q).to(dev)
+        k, L = p["k"], max(64, p["k"])
+        runner = runners[k]
+        replay = runner.captured(p["n_del"], p["n_ins"], p["n_q"])
+        runner.load(dlt, xt, q_t)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        oa = A.round(dlt, xt, q_t, k=k, L=L, reclaim=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ob = runner.run()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        sa, sb = oa["status"].cpu().numpy(), ob["status"].cpu().numpy()
+        assert not sa.any() and not sb.any(), f"round {r} status {sa} {sb}"
+        same = torch.equal(oa["q_ids"], ob["q_ids"]) and torch.equal(oa["ids"], ob["ids"])
+        mismatch += 0 if same else 1
+        if r >= args.warmup:
+            rows.append({**p, "per_op_ms": (t2 - t1) * 1e3, "graph_ms": (t3 - t2) * 1e3, "replay": replay})
+        log(args, f"round {r} {p} per-op {(t2 - t1) * 1e3:.2f} ms graph {(t3 - t2) * 1e3:.2f} ms same={same}")
+    # recall at k = 10 on a sample, against brute force over the live set
+    qs = torch.from_numpy(st.queries(1000)).to(dev)
+    gt, _ = B.bruteforce(qs, 10)
+    ids_s, _ = B.search(qs, 10, 64)
+    rec = recall(ids_s.cpu().numpy(), gt.cpu().numpy())
+    cap_rows = [x for x in rows if not x["replay"]]
+    rows_all = rows
+    rows = [x for x in rows if x["replay"]] or rows  # steady state: rounds that replayed a captured graph
+    po = np.array([x["per_op_ms"] for x in rows])
+    gr = np.array([x["graph_ms"] for x in rows])
+    nq_tot = sum(x["n_q"] for x in rows)
+    by = {}
+    for f in (0.001, 0.01, 0.05):
+        sel = [x for x in rows if x["churn_frac"] == f]
+        if sel:
+            by[str(f)] = {"rounds": len(sel), "per_op_ms": round(float(np.mean([x["per_op_ms"] for x in sel])), 3),
+                          "graph_ms": round(float(np.mean([x["graph_ms"] for x in sel])), 3)}
+    small = [x for x in rows if x["n_q"] <= 64 and x["churn_frac"] == 0.001]
+    out = {
+        "metric": "ms per uneven round (deletes + inserts + queries + reclaim): one launch per phase vs "
+                  "captured HIP graph, 1 GPU",
+        "value": round(float(gr.mean()), 3), "unit": "ms/round (graph)", "higher_is_better": False,
+        "n_gpus": 1, "steps": len(rows), "warmup": args.warmup, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batching_f32_96d_4m", "n_base": n_base, "dim": wl.dim, "clusters": 4096,
+                   "R": wl.R, "L_build": wl.L_build, "n_entry": n_entry, "W": args.W,
+                   "churn_fracs": [0.001, 0.01, 0.05], "queries": "log-uniform 1..65536", "k": [10, 100],
+                   "parallelism": "single GPU"},
+        "per_op_ms_mean": round(float(po.mean()), 3), "graph_ms_mean": round(float(gr.mean()), 3),
+        "per_op_ms_p50": round(float(np.median(po)), 3), "graph_ms_p50": round(float(np.median(gr)), 3),
+        "per_op_ms_p99": round(float(np.percentile(po, 99)), 3), "graph_ms_p99": round(float(np.percentile(gr, 99)), 3),
+        "speedup_mean": round(float(po.mean() / gr.mean()), 3),
+        "qps_per_op": round(nq_tot / (po.sum() * 1e-3), 1), "qps_graph": round(nq_tot / (gr.sum() * 1e-3), 1),
+        "by_churn": by,
+        "small_rounds": {"rounds": len(small),
+                         "per_op_ms": round(float(np.mean([x["per_op_ms"] for x in small])), 3) if small else None,
+                         "graph_ms": round(float(np.mean([x["graph_ms"] for x in small])), 3) if small else None},
+        "outputs_identical_rounds": len(params) - mismatch, "rounds_total": len(params),
+        "graphs_captured": sum(len(r.descs) for r in runners.values()),
+        "rounds_timed_replay": len(rows), "rounds_with_capture": len(cap_rows),
+        "capture_round_ms_mean": round(float(np.mean([x["graph_ms"] for x in cap_rows])), 3) if cap_rows else None,
+        "capture_all_s": round(t_cap, 3),
+        "per_op_ms_all_rounds": round(float(np.mean([x["per_op_ms"] for x in rows_all])), 3),
+        "recall_at_10_L64": round(rec, 4), "autotune": tune, "build_s": round(t_build, 2),
+        "device_bytes_per_index": B.stats()["device_bytes"],
+    }
+    A.close()
+    B.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -244,6 +377,9 @@ def main():
         sys.exit(2)
     if args.workload == "precision_f32":
         print(json.dumps(run_precision(args)), flush=True)
+        return
+    if args.workload == "batching_f32":
+        print(json.dumps(run_batching(args)), flush=True)
         return
     import torch
 

@@ -267,6 +267,75 @@ etale_status etale_export_rows(etale_t ix, uint64_t first, uint64_t n, int32_t w
  * synchronizes, writes up to cap launches as (scan, select, search)
  * millisecond triples in launch order into ms_host (cap x 3), the number of
  * recorded launches into *launches, and forgets them. */
+/* ---- serving: continuous batching of a request trace ----------------------
+ * Requests arrive at given times; each tick admits every request that has
+ * arrived (up to max_tick) and runs them as one round (etale_round):
+ * deletes, inserts and searches of a tick see the state left by the previous
+ * tick (the tick's own tombstones applied first, as in every round). Ticks
+ * run back to back; a tick that finds no pending request waits for the next
+ * arrival. Time is the trace's clock: a tick starts at max(end of the
+ * previous tick, first pending arrival) and lasts the measured wall time of
+ * its host work and device work (one synchronization per tick); a request's
+ * latency is its tick's end minus its arrival. With graph != 0 each tick
+ * replays a captured round for the power-of-two size bucket of its counts.
+ * Retired slabs return to the pool at the end of each tick (the epoch of
+ * Lemma 1 is the tick). */
+enum { ETALE_REQ_SEARCH = 0, ETALE_REQ_INSERT = 1, ETALE_REQ_DELETE = 2 };
+
+typedef struct {
+  double t_arrive; /* seconds on the trace clock, nondecreasing */
+  uint32_t kind;   /* ETALE_REQ_* */
+  uint32_t arg;    /* search / insert: row of rows_dev; delete: the id */
+} etale_request;
+
+typedef struct {
+  uint32_t k, L;            /* every search: top k from a list of L */
+  uint32_t max_tick;        /* requests admitted per tick, at most max_batch */
+  uint32_t reclaim_every;   /* ticks between reclaims (0: never) */
+  uint64_t hbm_budget_bytes; /* 0, or: an insert is rejected (latency -1) when
+                                rows + resident slabs + the library's fixed
+                                buffers would exceed it after the tick */
+  int32_t graph;            /* replay size-bucketed captured rounds */
+  uint32_t reserved;
+} etale_serve_config;
+
+typedef struct {
+  uint64_t ticks, searches, inserts, deletes, rejected_inserts, reclaims, failed_ticks;
+  uint64_t peak_resident_slabs, final_resident_slabs, ids_handed_out, graphs;
+  double trace_seconds; /* first arrival to the end of the last tick */
+  double busy_seconds;  /* sum of tick durations */
+} etale_serve_stats;
+
+/* Serve reqs_host[0..n) against the index. rows_dev holds n_rows vectors
+ * (dim elements each, uint8 or FP32 as the index) that search and insert
+ * requests name by row. latency_ms_host (n floats, may be NULL) receives each
+ * request's latency in ms (-1 for a rejected insert). Synchronizes. Errors:
+ * EINVAL (bad arguments, a row or kind out of range), and those of
+ * etale_round; a tick whose round fails on the device is counted in
+ * failed_ticks and its requests get latency -1. */
+etale_status etale_serve(etale_t ix, const etale_serve_config* cfg, const etale_request* reqs_host, uint64_t n,
+                         const void* rows_dev, uint64_t n_rows, float* latency_ms_host, etale_serve_stats* out_host);
+
+/* Result-invariant launch knobs of the beam search: waves per workgroup (1,
+ * 2 or 4; halved further while a workgroup's LDS would exceed 64 KiB) and
+ * visited-table slots (a power of two, 64..16384; the table may forget ids,
+ * which only repeats distance evaluations). Rounds captured as graphs are
+ * keyed by these values, so a change never alters a captured round. */
+etale_status etale_set_search_knobs(etale_t ix, uint32_t waves_per_block, uint32_t vt_slots);
+
+typedef struct {
+  uint32_t waves_per_block;
+  uint32_t vt_slots;
+  float ms;          /* mean search time of the chosen setting on the batch */
+  float ms_default;  /* the same for the setting in force before the call */
+} etale_tune_result;
+
+/* Autotuner: times the query search on the caller's batch (q_dev [nq x dim],
+ * k, L) for every knob setting above (waves 1/2/4 x slots 256..4096) and
+ * keeps the fastest. Allocates its own output scratch; synchronizes. */
+etale_status etale_autotune(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
+                            etale_tune_result* out_host);
+
 etale_status etale_set_search_timing(etale_t ix, int32_t enable);
 etale_status etale_get_search_timing(etale_t ix, float* ms_host, uint64_t cap, uint64_t* launches);
 

@@ -1,7 +1,9 @@
 // C-ABI of the ETALE index: argument checks, device memory, and the order of
 // the phase launches of each call. Every numeric step runs in the kernels of
 // etale_kernels.hip; this file only moves sizes, pointers and counters.
+#include <algorithm>
 #include <array>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -42,6 +44,7 @@ struct etale_index {
   uint32_t* hist = nullptr;       // radix-sort digit counts
   int32_t* status = nullptr;      // round status words of the calls that do not take one
   uint32_t pair_bits = 0;         // bits of an id (the sort range of pair targets)
+  bool no_chain = false;          // reverse edges without the cached candidate state
   uint64_t* scan_keys = nullptr;  // [scan_chunk x 256] initial lists
   uint32_t* scan_n = nullptr;
   uint32_t* scan_dist = nullptr;  // [dist_cap] query x start-set distances
@@ -415,6 +418,10 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     HIP_TRY(launch_sort(d, ix->pairs_a, ix->pairs_b, p.max_i * R, dp, 32, (int)ix->pair_bits, ix->hist, s, &sorted));
     HIP_TRY(launch_segments(d, sorted, p.max_i * R, dp, ix->seg, s));
     MaintArgs ra = maint_args(ix, R + 1);
+    if (ix->cfg.metric == ETALE_METRIC_L2_U8 && R <= 32 && !ix->no_chain) {
+      ra.chain = 1;
+      ra.lds_per_wave = std::max(ra.lds_per_wave, chain_lds_per_wave(R, ra.vstride));
+    }
     ra.n = p.max_i;
     ra.pairs = sorted;
     ra.npairs = p.max_i * R;
@@ -686,7 +693,8 @@ etale_status etale_round(etale_t ix, const etale_round_desc* r) {
   p.n_ids_max = ix->cfg.id_capacity;  // the id count is only known on the device
   if (!d.graph) return enqueue_round(ix, p);
   // capture once per descriptor, replay afterwards
-  const std::string key = graph_key(d, ix->qtrav, ix->qrerank);
+  const std::string key = graph_key(d, ix->qtrav, ix->qrerank) + "/" + std::to_string(ix->cfg.waves_per_block) +
+                          "/" + std::to_string(ix->cfg.vt_slots);
   auto it = ix->graphs.find(key);
   if (it == ix->graphs.end()) {
     if (!ix->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ix->cap_stream, hipStreamNonBlocking));
@@ -878,6 +886,277 @@ etale_status etale_export_rows(etale_t ix, uint64_t first, uint64_t n, int32_t w
   HIP_TRY(hipMemcpyAsync(out_host, (const uint8_t*)src + first * row_bytes, n * row_bytes, hipMemcpyDeviceToHost,
                          ix->stream));
   HIP_TRY(hipStreamSynchronize(ix->stream));
+  return ETALE_OK;
+}
+
+namespace {
+uint32_t size_bucket(uint32_t n, uint32_t floor, uint32_t cap) {
+  if (n == 0) return 0;
+  uint32_t b = floor;
+  while (b < n) b <<= 1;
+  return b < cap ? b : cap;
+}
+}  // namespace
+
+etale_status etale_serve(etale_t ix, const etale_serve_config* cfg, const etale_request* reqs, uint64_t n,
+                         const void* rows_dev, uint64_t n_rows, float* latency_ms, etale_serve_stats* out) {
+  CHECK_HANDLE();
+  if (!cfg || !out || (n && !reqs)) return fail(ix, ETALE_EINVAL, "serve: null argument");
+  const etale_serve_config c = *cfg;
+  if (c.max_tick < 1 || c.max_tick > ix->cfg.max_batch || c.k < 1 || c.k > c.L || c.L > 256)
+    return fail(ix, ETALE_EINVAL, "serve: need 1 <= max_tick <= max_batch and 1 <= k <= L <= 256");
+  for (uint64_t i = 0; i < n; ++i) {
+    if (reqs[i].kind > ETALE_REQ_DELETE || (i && reqs[i].t_arrive < reqs[i - 1].t_arrive))
+      return fail(ix, ETALE_EINVAL, "serve: bad kind or arrival order");
+    if (reqs[i].kind != ETALE_REQ_DELETE && (!rows_dev || reqs[i].arg >= n_rows))
+      return fail(ix, ETALE_EINVAL, "serve: row out of range");
+  }
+  if (etale_status st = refresh_mirror(ix)) return st;
+  const uint32_t T = c.max_tick, k = c.k;
+  const uint64_t row_bytes = (uint64_t)ix->cfg.dim * (ix->cfg.metric == ETALE_METRIC_L2_U8 ? 1 : 4);
+  const uint64_t slab_bytes = 8ull * ix->cfg.R;
+  const uint64_t fixed = ix->bytes - ix->cfg.id_capacity * row_bytes - ix->cfg.slab_capacity * slab_bytes;
+  // tick buffers: device, and pinned host staging (reused after each tick's synchronization)
+  uint32_t *d_idx = nullptr, *d_qids = nullptr, *d_qd = nullptr, *d_counts = nullptr, *d_ids = nullptr;
+  uint8_t *d_vecs = nullptr, *d_q = nullptr, *d_dst = nullptr;
+  int32_t* d_status = nullptr;
+  uint32_t* h_idx = nullptr;
+  int32_t* h_status = nullptr;
+  unsigned long long* h_ctr = nullptr;
+  std::vector<void*> dev_bufs, host_bufs;
+  auto dev = [&](auto** p, size_t bytes) {
+    hipError_t e = hipMalloc((void**)p, bytes ? bytes : 16);
+    if (e == hipSuccess) dev_bufs.push_back(*p);
+    return e;
+  };
+  auto host = [&](auto** p, size_t bytes) {
+    hipError_t e = hipHostMalloc((void**)p, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) host_bufs.push_back(*p);
+    return e;
+  };
+  auto release = [&]() {
+    for (void* p : dev_bufs) (void)hipFree(p);
+    for (void* p : host_bufs) (void)hipHostFree(p);
+  };
+  hipError_t e = dev(&d_idx, (size_t)3 * T * 4);
+  if (e == hipSuccess) e = dev(&d_vecs, (size_t)T * row_bytes);
+  if (e == hipSuccess) e = dev(&d_q, (size_t)T * row_bytes);
+  if (e == hipSuccess) e = dev(&d_qids, (size_t)T * k * 4);
+  if (e == hipSuccess) e = dev(&d_qd, (size_t)T * k * 4);
+  if (e == hipSuccess) e = dev(&d_counts, 16);
+  if (e == hipSuccess) e = dev(&d_ids, (size_t)T * 4);
+  if (e == hipSuccess) e = dev(&d_dst, (size_t)T);
+  if (e == hipSuccess) e = dev(&d_status, 16);
+  if (e == hipSuccess) e = host(&h_idx, (size_t)3 * T * 4 + 16);
+  if (e == hipSuccess) e = host(&h_status, 16);
+  if (e == hipSuccess) e = host(&h_ctr, 16);
+  if (e != hipSuccess) {
+    release();
+    return fail(ix, ETALE_ENOMEM, "serve: tick buffers");
+  }
+  uint32_t* h_del = h_idx;
+  uint32_t* h_ins = h_idx + T;
+  uint32_t* h_qr = h_idx + 2 * T;
+  uint32_t* h_cnt = h_idx + 3 * T;
+  etale_serve_stats S{};
+  std::vector<std::string> keys_before;
+  for (auto& g : ix->graphs) keys_before.push_back(g.first);
+  uint64_t next_id = ix->next_id;
+  uint64_t resident = 0;
+  {
+    unsigned long long h[C_NCOUNTERS];
+    if (etale_status st = read_counters(ix, h)) {
+      release();
+      return st;
+    }
+    resident = ix->cfg.slab_capacity - h[C_FREE_TOP] - h[C_RETIRED_TOP];
+  }
+  S.peak_resident_slabs = resident;
+  std::vector<uint64_t> members;  // request indices of the current tick, in admission order
+  members.reserve(T);
+  double t = n ? reqs[0].t_arrive : 0.0;
+  uint64_t i = 0;
+  etale_status result = ETALE_OK;
+  while (i < n) {
+    if (reqs[i].t_arrive > t) t = reqs[i].t_arrive;  // idle until the next arrival
+    const auto w0 = std::chrono::steady_clock::now();
+    uint32_t nd = 0, ni = 0, nq = 0;
+    members.clear();
+    uint64_t j = i;
+    uint64_t used = next_id * row_bytes + resident * slab_bytes + fixed;
+    for (; j < n && reqs[j].t_arrive <= t && members.size() < T; ++j) {
+      const etale_request& r = reqs[j];
+      if (r.kind == ETALE_REQ_DELETE) {
+        h_del[nd++] = r.arg;
+      } else if (r.kind == ETALE_REQ_INSERT) {
+        if (c.hbm_budget_bytes && used + row_bytes + slab_bytes > c.hbm_budget_bytes) {
+          if (latency_ms) latency_ms[j] = -1.0f;
+          ++S.rejected_inserts;
+          continue;
+        }
+        used += row_bytes + slab_bytes;
+        h_ins[ni++] = r.arg;
+      } else {
+        h_qr[nq++] = r.arg;
+      }
+      members.push_back(j);
+    }
+    h_cnt[0] = nd;
+    h_cnt[1] = ni;
+    h_cnt[2] = nq;
+    const bool reclaim = c.reclaim_every && (S.ticks + 1) % c.reclaim_every == 0;
+    hipStream_t s = ix->stream;
+    e = hipMemcpyAsync(d_idx, h_idx, (size_t)3 * T * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_counts, h_cnt, 12, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_gather_rows(rows_dev, d_idx + T, ni, (uint32_t)row_bytes, d_vecs, s);
+    if (e == hipSuccess) e = launch_gather_rows(rows_dev, d_idx + 2 * T, nq, (uint32_t)row_bytes, d_q, s);
+    if (e != hipSuccess) {
+      result = fail(ix, ETALE_EDEVICE, std::string("serve: ") + hipGetErrorString(e));
+      break;
+    }
+    etale_round_desc d{};
+    d.del_ids = d_idx;
+    d.del_status = d_dst;
+    d.ins_vecs = d_vecs;
+    d.ins_ids = d_ids;
+    d.queries = d_q;
+    d.q_ids = d_qids;
+    d.q_dists = d_qd;
+    d.k = c.k;
+    d.L = c.L;
+    d.counts = d_counts;
+    d.status = d_status;
+    d.reclaim = reclaim ? 1 : 0;
+    d.graph = c.graph;
+    d.max_del = c.graph ? size_bucket(nd, 256, T) : nd;
+    d.max_ins = c.graph ? size_bucket(ni, 256, T) : ni;
+    d.max_q = c.graph ? size_bucket(nq, 64, T) : nq;
+    if (etale_status st = etale_round(ix, &d)) {
+      result = st;
+      break;
+    }
+    e = hipMemcpyAsync(h_status, d_status, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, ix->ctr + C_FREE_TOP, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      result = fail(ix, ETALE_EDEVICE, std::string("serve: ") + hipGetErrorString(e));
+      break;
+    }
+    const double dur = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
+    const double t_end = t + dur;
+    const bool ok = h_status[0] == 0;
+    for (uint64_t m : members)
+      if (latency_ms) latency_ms[m] = ok ? (float)((t_end - reqs[m].t_arrive) * 1e3) : -1.0f;
+    if (ok) {
+      S.searches += nq;
+      S.inserts += ni;
+      S.deletes += nd;
+      next_id += ni;
+      if (reclaim) S.reclaims += h_status[1] == 0;
+    } else {
+      ++S.failed_ticks;
+    }
+    resident = ix->cfg.slab_capacity - h_ctr[0] - h_ctr[1];
+    if (resident > S.peak_resident_slabs) S.peak_resident_slabs = resident;
+    ++S.ticks;
+    S.busy_seconds += dur;
+    t = t_end;
+    i = j;
+  }
+  S.final_resident_slabs = resident;
+  S.ids_handed_out = next_id;
+  S.trace_seconds = n ? t - reqs[0].t_arrive : 0.0;
+  S.graphs = ix->graphs.size() - keys_before.size();
+  // the rounds captured here name this call's buffers: drop them with the buffers
+  for (auto it = ix->graphs.begin(); it != ix->graphs.end();) {
+    if (std::find(keys_before.begin(), keys_before.end(), it->first) == keys_before.end()) {
+      (void)hipGraphExecDestroy(it->second);
+      it = ix->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  release();
+  if (result) return result;
+  ix->next_id = next_id;
+  *out = S;
+  return ETALE_OK;
+}
+
+etale_status etale_set_search_knobs(etale_t ix, uint32_t waves_per_block, uint32_t vt_slots) {
+  CHECK_HANDLE();
+  if ((waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4) || !pow2(vt_slots) || vt_slots < 64 ||
+      vt_slots > 16384)
+    return fail(ix, ETALE_EINVAL, "search knobs: waves 1/2/4, slots a power of two in 64..16384");
+  if (search_lds_per_wave(SCAN_L_MAX, vt_slots) > 65536u) return fail(ix, ETALE_EINVAL, "search knobs: LDS");
+  ix->cfg.waves_per_block = waves_per_block;
+  ix->cfg.vt_slots = vt_slots;
+  return ETALE_OK;
+}
+
+etale_status etale_autotune(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
+                            etale_tune_result* out) {
+  CHECK_HANDLE();
+  if (!q_dev || !out || nq == 0 || nq > 0xFFFFFFFFull || k < 1 || k > L || L > 256)
+    return fail(ix, ETALE_EINVAL, "autotune: bad batch");
+  uint32_t* ids = nullptr;
+  uint32_t* d = nullptr;
+  HIP_TRY(hipMalloc(&ids, nq * k * 4));
+  HIP_TRY(hipMalloc(&d, nq * k * 4));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const uint32_t wpb0 = ix->cfg.waves_per_block, vt0 = ix->cfg.vt_slots;
+  const bool timing = ix->timing;
+  ix->timing = false;
+  auto time_one = [&](uint32_t wpb, uint32_t vt, float* ms) -> etale_status {
+    ix->cfg.waves_per_block = wpb;
+    ix->cfg.vt_slots = vt;
+    const uint32_t vcap = ix->cfg.visit_mult * L;
+    if (etale_status st = run_searches(ix, MODE_QUERY, (const uint8_t*)q_dev, nq, k, L, vcap, ids, d, nullptr, Dyn{}))
+      return st;  // warm-up
+    HIP_TRY(hipEventRecord(e0, ix->stream));
+    for (int rep = 0; rep < 3; ++rep)
+      if (etale_status st = run_searches(ix, MODE_QUERY, (const uint8_t*)q_dev, nq, k, L, vcap, ids, d, nullptr,
+                                         Dyn{}))
+        return st;
+    HIP_TRY(hipEventRecord(e1, ix->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    *ms /= 3.0f;
+    return ETALE_OK;
+  };
+  etale_status st = ETALE_OK;
+  float best = 0.f, base = 0.f;
+  uint32_t bw = wpb0, bv = vt0;
+  st = time_one(wpb0, vt0, &base);
+  best = base;
+  const uint32_t waves[] = {1, 2, 4};
+  const uint32_t slots[] = {256, 512, 1024, 2048, 4096};
+  for (uint32_t w : waves)
+    for (uint32_t v : slots) {
+      if (st) break;
+      if (search_lds_per_wave(L, v) > 65536u) continue;
+      float ms = 0.f;
+      st = time_one(w, v, &ms);
+      if (!st && ms < best) {
+        best = ms;
+        bw = w;
+        bv = v;
+      }
+    }
+  ix->cfg.waves_per_block = st ? wpb0 : bw;
+  ix->cfg.vt_slots = st ? vt0 : bv;
+  ix->timing = timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(ids);
+  (void)hipFree(d);
+  if (st) return st;
+  out->waves_per_block = bw;
+  out->vt_slots = bv;
+  out->ms = best;
+  out->ms_default = base;
   return ETALE_OK;
 }
 

@@ -821,6 +821,8 @@ struct MaintU8 {
     return key_dist(ck[0]);
   }
   __device__ static uint32_t kd(uint32_t rho) { return rho; }
+  static constexpr bool CHAIN = true;  // reverse edges keep a cached candidate state
+  static constexpr int GL = G;
 };
 
 template <int G>
@@ -832,6 +834,8 @@ struct MaintF32 {
     return dist1_f32<G>(ix, w, v);
   }
   __device__ static uint32_t kd(uint32_t rho) { return fkey(__builtin_bit_cast(float, rho)); }
+  static constexpr bool CHAIN = false;
+  static constexpr int GL = G;
 };
 
 __device__ inline void resolve(const Index& ix, MaintArgs& a) {
@@ -942,14 +946,241 @@ __device__ inline void reverse_one(const Index& ix, const MaintArgs& a, MaintLds
   publish(ix, w, m.nl_id, m.nl_d, n, C_PUB_REVERSE);
 }
 
+
+// ---- reverse edges with a cached candidate state (uint8 rows, R <= 32) --------------
+// A target w takes its offers v in ascending source order: a listed v changes
+// nothing, below R the offer is inserted in (distance, id) order, at R the list
+// is re-pruned with v. Consecutive prunes of one target share all but one
+// candidate, so the wave keeps, per slot (R + 1 of them), the candidate's row,
+// norm, id, distance to w and deletion flag, and the matrix of squared
+// distances between the slots' rows. An offer then costs one row load and at
+// most R distances from LDS instead of a full RobustPrune. The distances are
+// exact integers, so the result is the one RobustPrune gives.
+struct ChainLds {
+  uint8_t* rows;    // [S][vstride]
+  uint32_t* norm;   // [S]
+  uint32_t* M;      // [S][S]
+  uint32_t* id;     // [S]
+  uint32_t* dw;     // [S] squared distance to the target
+  uint32_t* dead;   // [S] deletion flag of the candidate
+  uint32_t* order;  // [S] list position -> slot
+  uint32_t* out_id; // [S]
+  uint32_t* out_d;  // [S]
+  uint32_t S, vstride;
+};
+
+__host__ __device__ inline uint32_t chain_lds_bytes(uint32_t R, uint32_t vstride) {
+  const uint32_t S = R + 1;
+  const uint32_t b = S * vstride + S * 4 + S * S * 4 + 7 * S * 4;
+  return (b + 15u) & ~15u;
+}
+
+__device__ inline ChainLds carve_chain(char* base, uint32_t R, uint32_t vstride) {
+  ChainLds c;
+  c.S = R + 1;
+  c.vstride = vstride;
+  c.rows = reinterpret_cast<uint8_t*>(base);
+  uint32_t* p = reinterpret_cast<uint32_t*>(base + (size_t)c.S * vstride);
+  c.norm = p;
+  p += c.S;
+  c.M = p;
+  p += c.S * c.S;
+  c.id = p;
+  p += c.S;
+  c.dw = p;
+  p += c.S;
+  c.dead = p;
+  p += c.S;
+  c.order = p;
+  p += c.S;
+  c.out_id = p;
+  p += c.S;
+  c.out_d = p;
+  return c;
+}
+
+// stage the rows of `cnt` slots (listed in slots[0..cnt)) with their norms
+template <int G>
+__device__ inline void chain_stage_rows(const Index& ix, const ChainLds& c, const uint32_t* slots, int cnt) {
+  constexpr int VPP = 64 / G;
+  const int l = lane_id();
+  const int ch = l % G, grp = l / G;
+  for (int base = 0; base < cnt; base += 4 * VPP) {
+    uint4 v[4];
+    int sl[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = base + u * VPP + grp;
+      sl[u] = k < cnt ? (int)slots[k] : -1;
+      v[u] = make_uint4(0, 0, 0, 0);
+      if (sl[u] >= 0) v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)c.id[sl[u]] * ix.dim)[ch];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t nn = group_sum<G>(dot16(v[u], v[u], 0u));
+      if (sl[u] >= 0) {
+        *reinterpret_cast<uint4*>(c.rows + (size_t)sl[u] * c.vstride + ch * 16) = v[u];
+        if (ch == 0) c.norm[sl[u]] = nn;
+      }
+    }
+  }
+  wave_sync();
+}
+
+// M[a][b] = M[b][a] = squared distance, for slot a against slots[0..cnt)
+template <int G>
+__device__ inline void chain_fill_row(const ChainLds& c, uint32_t a, const uint32_t* slots, int cnt) {
+  constexpr int VPP = 64 / G;
+  const int l = lane_id();
+  const int ch = l % G, grp = l / G;
+  const uint4 av = *reinterpret_cast<const uint4*>(c.rows + (size_t)a * c.vstride + ch * 16);
+  const uint32_t na = c.norm[a];
+  for (int base = 0; base < cnt; base += VPP) {
+    const int k = base + grp;
+    const uint32_t b = k < cnt ? slots[k] : a;
+    const uint4 bv = *reinterpret_cast<const uint4*>(c.rows + (size_t)b * c.vstride + ch * 16);
+    const uint32_t dot = group_sum<G>(dot16(av, bv, 0u));
+    if (k < cnt && ch == 0) {
+      const uint32_t d = na + c.norm[b] - 2u * dot;
+      c.M[a * c.S + b] = d;
+      c.M[b * c.S + a] = d;
+    }
+  }
+  wave_sync();
+}
+
+template <int G>
+__device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, const ChainLds& c, uint32_t t) {
+  const int l = lane_id();
+  const int ch = l % G;
+  const uint32_t R = ix.R;
+  const uint32_t w = (uint32_t)(a.pairs[t] >> 32);
+  const uint4 wf = load_frag<G>(ix.x + (size_t)w * ix.dim);
+  const uint32_t ww = group_sum<G>(dot16(wf, wf, 0u));
+  // the target's list; slot i holds position i
+  const uint64_t r = bcast64(load_ref(ix, w));
+  uint32_t n = ref_slab(r) == NONE ? 0u : ref_deg(r);
+  if ((uint32_t)l < n) {
+    const uint32_t s = ref_slab(r);
+    c.id[l] = ix.slabs[(size_t)s * 2u * R + (uint32_t)l];
+    c.dw[l] = ix.slabs[(size_t)s * 2u * R + R + (uint32_t)l];
+    c.order[l] = (uint32_t)l;
+  }
+  wave_sync();
+  uint64_t used = (1ull << n) - 1ull;  // slots holding a list entry (n <= 32)
+  uint64_t staged = 0;                 // slots whose row, norm and flag are in LDS
+  bool cached = false;                 // M holds every pair of used slots
+  const uint32_t cap = ix.prune_cap < 64u ? ix.prune_cap : 64u;
+  for (uint32_t u = t; u < a.npairs && a.pairs[u] != KEY_NONE && (uint32_t)(a.pairs[u] >> 32) == w; ++u) {
+    const uint32_t v = (uint32_t)a.pairs[u];
+    if (ballot((uint32_t)l < n && c.id[c.order[l]] == v) != 0ull) continue;  // a set union
+    // the offer takes a free slot: its row, norm, flag and distance to w
+    const uint32_t f = (uint32_t)__builtin_ctzll(~used);
+    {
+      const uint4 vv = reinterpret_cast<const uint4*>(ix.x + (size_t)v * ix.dim)[ch];
+      const uint32_t vn = group_sum<G>(dot16(vv, vv, 0u));
+      const uint32_t dot = group_sum<G>(dot16(wf, vv, 0u));
+      if (l < G) *reinterpret_cast<uint4*>(c.rows + (size_t)f * c.vstride + ch * 16) = vv;
+      if (l == 0) {
+        c.id[f] = v;
+        c.dead[f] = 0u;  // the round's new nodes are live
+        c.norm[f] = vn;
+        c.dw[f] = ww + vn - 2u * dot;
+      }
+    }
+    wave_sync();
+    staged |= 1ull << f;
+    const uint64_t kv = make_key(c.dw[f], v);
+    const uint32_t sl = (uint32_t)l < n ? c.order[l] : 0u;
+    const uint32_t pos = (uint32_t)__popcll(ballot((uint32_t)l < n && make_key(c.dw[sl], c.id[sl]) < kv));
+    if (n < R) {
+      // below R: insert in (distance, id) order
+      wave_sync();
+      if ((uint32_t)l < n && (uint32_t)l >= pos) c.order[l + 1] = sl;
+      if (l == 0) c.order[pos] = f;
+      wave_sync();
+      if (cached) chain_fill_row<G>(c, f, c.order, (int)n + 1);  // M stays complete
+      used |= 1ull << f;
+      ++n;
+      continue;
+    }
+    // at R: RobustPrune(w, list + v) over the cached state
+    if (!cached) {
+      // first prune of this target: rows and flags of the list entries, then all of M
+      const bool need = (uint32_t)l < n && !((staged >> sl) & 1ull);
+      const uint64_t nm = ballot(need);
+      if (need) {
+        c.out_id[lanes_below(nm)] = sl;
+        c.dead[sl] = ref_del(load_ref(ix, c.id[sl]));
+      }
+      wave_sync();
+      chain_stage_rows<G>(ix, c, c.out_id, __popcll(nm));
+      staged |= used;
+      for (uint32_t x = 0; x < n; ++x) chain_fill_row<G>(c, c.order[x], c.order, (int)n);
+      cached = true;
+    }
+    chain_fill_row<G>(c, f, c.order, (int)n);
+    // candidates in (distance, id) order: the list with v at position pos
+    uint32_t cs = f;
+    if ((uint32_t)l < pos) cs = sl;
+    else if ((uint32_t)l > pos && (uint32_t)l <= n) cs = c.order[l - 1];
+    const bool is_cand = (uint32_t)l <= n;
+    const uint32_t cdw = is_cand ? c.dw[cs] : 0u;
+    uint64_t alive = ballot(is_cand && c.dead[cs] == 0u);
+    {  // at most prune_cap candidates are considered, the first in order
+      uint64_t rest = alive;
+      for (uint32_t k = 0; k < cap && rest; ++k) rest &= rest - 1ull;
+      alive &= ~rest;
+    }
+    uint32_t cnt = 0, from = 0, ns = 0;
+    while (cnt < R) {
+      const uint64_t m = alive & (~0ull << from);
+      if (!m) break;
+      const uint32_t j = (uint32_t)__builtin_ctzll(m);
+      const uint32_t sj = (uint32_t)__shfl((int)cs, (int)j, 64);
+      if ((uint32_t)l == cnt) ns = sj;
+      ++cnt;
+      from = j + 1;
+      if (cnt == R) break;
+      const bool kill = (uint32_t)l > j && ((alive >> l) & 1ull) &&
+                        (uint64_t)ix.a2 * c.M[sj * c.S + cs] <= (uint64_t)ix.b2 * (uint64_t)cdw;
+      alive &= ~ballot(kill);
+    }
+    // the kept candidates, in order, are the new list
+    wave_sync();
+    if ((uint32_t)l < cnt) c.order[l] = ns;
+    used = 0;
+    for (uint32_t i = 0; i < cnt; ++i) used |= 1ull << (uint32_t)__shfl((int)ns, (int)i, 64);
+    n = cnt;
+    wave_sync();
+  }
+  if ((uint32_t)l < n) {
+    const uint32_t sl = c.order[l];
+    c.out_id[l] = c.id[sl];
+    c.out_d[l] = c.dw[sl];
+  }
+  wave_sync();
+  publish(ix, w, c.out_id, c.out_d, n, C_PUB_REVERSE);
+}
+
 // one wave per run of the sorted (target, source) pairs
 template <class P>
 __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, a.d)) return;
   resolve(ix, a);
-  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
+  if constexpr (P::CHAIN) {
+    if (a.chain) {
+      const ChainLds c = carve_chain(wave_lds(smem, a), ix.R, a.vstride);
+      FOR_EACH_WAVE_ITEM(si, nseg) {
+        wave_sync();
+        reverse_chain_u8<P::GL>(ix, a, c, a.seg[si]);
+      }
+      return;
+    }
+  }
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   FOR_EACH_WAVE_ITEM(si, nseg) {
     wave_sync();
     reverse_one<P>(ix, a, m, a.seg[si]);
@@ -1276,26 +1507,50 @@ __global__ void k_del_bitmap(Index ix, uint64_t n_ids, Dyn d, uint64_t* bitmap) 
 
 __device__ inline bool bit_set(const uint64_t* bm, uint32_t id) { return (bm[id >> 6] >> (id & 63u)) & 1ull; }
 
-// live nodes with an edge into a tombstone ("dirty"), and the count of such edges
-__device__ inline void dirty_one(const Index& ix, const uint64_t* bitmap, uint32_t* dirty, uint32_t u) {
-  const int l = lane_id();
-  const uint64_t r = bcast64(load_ref(ix, u));
-  if (ref_del(r) || ref_slab(r) == NONE) return;
-  const uint32_t deg = ref_deg(r), s = ref_slab(r);
-  bool dead = false;
-  if ((uint32_t)l < deg) dead = bit_set(bitmap, ix.slabs[(size_t)s * 2u * ix.R + (uint32_t)l]);
-  const uint64_t m = ballot(dead);
-  if (m && l == 0) {
-    const unsigned long long i = atomicAdd(&ix.ctr[C_DIRTY], 1ull);
-    dirty[i] = u;
-    atomicAdd(&ix.ctr[C_DEAD], (unsigned long long)__popcll(m));
-  }
-}
-
-__global__ void k_dirty(Index ix, uint64_t n_ids, Dyn d, const uint64_t* bitmap, uint32_t* dirty) {
+// live nodes with an edge into a tombstone ("dirty"), and the count of such
+// edges. One thread per node: reference words are read coalesced, each slab's
+// id half as whole 16-byte words, neighbors tested against the deletion bitmap.
+__global__ void __launch_bounds__(256) k_dirty(Index ix, uint64_t n_ids, Dyn d, const uint64_t* bitmap,
+                                               uint32_t* dirty) {
   if (gated(ix, d)) return;
   const uint32_t n = dyn_count(ix, d, (uint32_t)n_ids);
-  FOR_EACH_WAVE_ITEM(u, n) dirty_one(ix, bitmap, dirty, u);
+  const uint32_t R = ix.R;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  const uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
+  // every lane runs the same number of iterations, so the wave-wide ballot
+  // and the one atomic per wave see all lanes
+  for (uint32_t base = first - lane_id(); base < n; base += stride) {
+    const uint32_t u = base + (uint32_t)lane_id();
+    uint32_t dead = 0;
+    if (u < n) {
+      const uint64_t r = load_ref(ix, u);
+      const uint32_t deg = ref_deg(r), s = ref_slab(r);
+      if (!ref_del(r) && s != NONE) {
+        const uint32_t* ids = ix.slabs + (size_t)s * 2u * R;
+        if ((R & 3u) == 0) {
+          for (uint32_t j = 0; j < deg; j += 4) {
+            const uint4 v = *reinterpret_cast<const uint4*>(ids + j);
+            dead += bit_set(bitmap, v.x);
+            if (j + 1 < deg) dead += bit_set(bitmap, v.y);
+            if (j + 2 < deg) dead += bit_set(bitmap, v.z);
+            if (j + 3 < deg) dead += bit_set(bitmap, v.w);
+          }
+        } else {
+          for (uint32_t j = 0; j < deg; ++j) dead += bit_set(bitmap, ids[j]);
+        }
+      }
+    }
+    const uint64_t m = ballot(dead != 0);
+    uint32_t total = dead;
+    for (int o = 32; o > 0; o >>= 1) total += (uint32_t)__shfl_xor((int)total, o, 64);
+    uint32_t at = 0;
+    if (lane_id() == 0 && m) {
+      at = (uint32_t)atomicAdd(&ix.ctr[C_DIRTY], (unsigned long long)__popcll(m));
+      atomicAdd(&ix.ctr[C_DEAD], (unsigned long long)total);
+    }
+    at = (uint32_t)__shfl((int)at, 0, 64);
+    if (dead) dirty[at + lanes_below(m)] = u;
+  }
 }
 
 // phase 1, compaction: republish each dirty node without its tombstoned entries
@@ -1543,6 +1798,23 @@ hipError_t launch_store_rows(const Index& ix, const void* src, uint32_t* ids_out
   return hipGetLastError();
 }
 
+// rows named by index into a contiguous batch (16-byte words)
+__global__ void k_gather_rows(const uint4* rows, const uint32_t* idx, uint32_t n, uint32_t words, uint4* out) {
+  const uint64_t total = (uint64_t)n * words;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride)
+    out[t] = rows[(size_t)idx[t / words] * words + t % words];
+}
+
+hipError_t launch_gather_rows(const void* rows, const uint32_t* idx, uint32_t n, uint32_t row_bytes, void* out,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t words = row_bytes / 16u;
+  hipLaunchKernelGGL(k_gather_rows, dim3(persist_grid((uint64_t)n * words, 256)), dim3(256), 0, s,
+                     (const uint4*)rows, idx, n, words, (uint4*)out);
+  return hipGetLastError();
+}
+
 hipError_t launch_refresh_entries(const Index& ix, uint32_t bound, uint32_t S, Dyn d, hipStream_t s) {
   hipLaunchKernelGGL(k_refresh_entries, dim3(1), dim3(1024), 0, s, ix, bound, S, d);
   return hipGetLastError();
@@ -1682,6 +1954,8 @@ hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_pe
 }
 #undef LS
 
+uint32_t chain_lds_per_wave(uint32_t R, uint32_t vstride) { return chain_lds_bytes(R, vstride); }
+
 uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R) {
   size_t b = (size_t)a.nsort * 8 + (size_t)a.prune_cap * 8 + (size_t)a.prune_cap * a.vstride + (size_t)a.prune_cap * 8 +
              (size_t)(R + 1) * 8 + (size_t)a.nmax * 4 + (size_t)(R + 1) * 12 + (size_t)a.prune_cap;
@@ -1804,7 +2078,9 @@ hipError_t launch_del_bitmap(const Index& ix, uint64_t n_ids, Dyn d, uint64_t* b
 hipError_t launch_dirty(const Index& ix, uint64_t n_ids, Dyn d, const uint64_t* bitmap, uint32_t* dirty,
                         hipStream_t s) {
   if (n_ids == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dirty, dim3(persist_grid(n_ids, 4)), dim3(256), 0, s, ix, n_ids, d, bitmap, dirty);
+  const unsigned blocks = blocks_for(n_ids, 256);
+  hipLaunchKernelGGL(k_dirty, dim3(blocks < 4 * PERSIST_BLOCKS ? blocks : 4 * PERSIST_BLOCKS), dim3(256), 0, s, ix,
+                     n_ids, d, bitmap, dirty);
   return hipGetLastError();
 }
 

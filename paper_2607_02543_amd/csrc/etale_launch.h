@@ -65,6 +65,7 @@ struct MaintArgs {
   uint32_t lds_per_wave;
   const uint32_t* seg;     // starts of the runs of one target in the sorted pairs
   uint32_t np_ctr = NO_CTR, np_mult = 1;  // launch-time pair count
+  uint32_t chain = 0;      // reverse edges: cached candidate state (uint8 rows, R <= 32)
   Dyn d;                   // launch-time count (n) and first id
 };
 
@@ -81,11 +82,14 @@ hipError_t launch_reclaim_gate(const Index& ix, int32_t* status, hipStream_t s);
 hipError_t launch_store_rows(const Index& ix, const void* src, uint32_t* ids_out, uint32_t first, uint32_t n, Dyn d,
                              hipStream_t s);
 hipError_t launch_refresh_entries(const Index& ix, uint32_t bound, uint32_t S, Dyn d, hipStream_t s);
+hipError_t launch_gather_rows(const void* rows, const uint32_t* idx, uint32_t n, uint32_t row_bytes, void* out,
+                              hipStream_t s);
 uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots);
 uint32_t scan_select_lds_per_wave(uint32_t L);
 hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEvent_t after_dist = nullptr);
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s);
 uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R);
+uint32_t chain_lds_per_wave(uint32_t R, uint32_t vstride);
 hipError_t launch_maint(MaintKernel which, const Index& ix, const MaintArgs& a, uint32_t nwaves,
                         uint32_t waves_per_block, hipStream_t s);
 hipError_t launch_reverse_pairs(const Index& ix, const MaintArgs& a, hipStream_t s);

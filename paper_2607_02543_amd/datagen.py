@@ -142,6 +142,13 @@ def precision_f32(n_base: int = 1_000_000, rounds: int = 20, n_queries: int = 10
                     rounds, 0.01, n_queries, 10, (96,), seed, 1000, 10000)
 
 
+def batching_f32(n_base: int = 4_000_000, rounds: int = 50, seed: int = 0) -> Workload:
+    """96-d unit-norm float32, 4,096 centers, noise 0.3, inner product, R=32,
+    L=64; rounds of uneven size (see Stream.round_params)."""
+    return Workload("batching_f32_96d_4m", Mixture(96, 4096, 0.3, METRIC_IP_F32), n_base, 32, 64, 6, 5,
+                    rounds, 0.05, 0, 10, (64,), seed, 1000, 200_000)
+
+
 class Stream:
     """Draws the vectors of one workload in a fixed order from independent streams."""
 
@@ -167,6 +174,17 @@ class Stream:
 
     def uniform_ints(self, lo: int, hi: int, n: int) -> np.ndarray:
         return self.rng["rounds"].integers(lo, hi, size=n)
+
+    def round_params(self, live: int) -> dict:
+        """One uneven round: churn fraction drawn from {0.1%, 1%, 5%} of the
+        live count (that many deletes and as many inserts), a log-uniform
+        query count in [1, 65536], and k drawn from {10, 100}."""
+        r = self.rng["rounds"]
+        frac = (0.001, 0.01, 0.05)[int(r.integers(0, 3))]
+        n = int(round(frac * live))
+        nq = log_uniform_batch(r, 1, 65536)
+        k = (10, 100)[int(r.integers(0, 2))]
+        return {"churn_frac": frac, "n_del": n, "n_ins": n, "n_q": nq, "k": k}
 
 
 def churn_schedule(wl: Workload) -> Iterator[int]:

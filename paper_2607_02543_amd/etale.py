@@ -54,6 +54,30 @@ class Stats(C.Structure):
         "device_bytes", "error_bits")]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("waves_per_block", C.c_uint32), ("vt_slots", C.c_uint32), ("ms", C.c_float),
+                ("ms_default", C.c_float)]
+
+
+class Request(C.Structure):
+    _fields_ = [("t_arrive", C.c_double), ("kind", C.c_uint32), ("arg", C.c_uint32)]
+
+
+class ServeConfig(C.Structure):
+    _fields_ = [("k", C.c_uint32), ("L", C.c_uint32), ("max_tick", C.c_uint32), ("reclaim_every", C.c_uint32),
+                ("hbm_budget_bytes", C.c_uint64), ("graph", C.c_int32), ("reserved", C.c_uint32)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "ticks", "searches", "inserts", "deletes", "rejected_inserts", "reclaims", "failed_ticks",
+        "peak_resident_slabs", "final_resident_slabs", "ids_handed_out", "graphs")] + \
+        [("trace_seconds", C.c_double), ("busy_seconds", C.c_double)]
+
+
+REQ_SEARCH, REQ_INSERT, REQ_DELETE = 0, 1, 2
+
+
 class RoundDesc(C.Structure):
     _fields_ = [
         ("del_ids", C.c_void_p), ("del_status", C.c_void_p), ("max_del", C.c_uint32),
@@ -96,6 +120,9 @@ def load() -> C.CDLL:
         "etale_set_lists": ([vp, u64, vp, vp, vp], i32),
         "etale_set_query_traversal": ([vp, i32, u32], i32),
         "etale_export_rows": ([vp, u64, u64, i32, vp], i32),
+        "etale_set_search_knobs": ([vp, u32, u32], i32),
+        "etale_serve": ([vp, C.POINTER(ServeConfig), vp, u64, vp, u64, vp, C.POINTER(ServeStats)], i32),
+        "etale_autotune": ([vp, vp, u64, u32, u32, C.POINTER(TuneResult)], i32),
         "etale_set_search_timing": ([vp, i32], i32),
         "etale_get_search_timing": ([vp, vp, u64, C.POINTER(u64)], i32),
         "etale_sync": ([vp], i32),
@@ -289,6 +316,33 @@ class Index:
         self._check(self.lib.etale_export_rows(self.h, first, n, which, out.ctypes.data_as(C.c_void_p)), "export_rows")
         return out
 
+    def serve(self, t_arrive: np.ndarray, kind: np.ndarray, arg: np.ndarray, rows, k: int = 10, L: int = 64,
+              max_tick: int = 4096, reclaim_every: int = 0, hbm_budget_bytes: int = 0, graph: bool = True):
+        """Run a request trace through the library's serving loop (continuous
+        batching into rounds). Returns (per-request latency in ms, stats)."""
+        n = int(t_arrive.size)
+        reqs = np.zeros(n, dtype=np.dtype([("t", np.float64), ("kind", np.uint32), ("arg", np.uint32)]))
+        reqs["t"], reqs["kind"], reqs["arg"] = t_arrive, kind, arg
+        rows = self._dev(rows, self._vdtype)
+        lat = np.zeros(n, np.float32)
+        cfg = ServeConfig(k, L, max_tick, reclaim_every, hbm_budget_bytes, int(graph), 0)
+        st = ServeStats()
+        p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        self._check(self.lib.etale_serve(self.h, C.byref(cfg), p(reqs), n, _ptr(rows), rows.shape[0], p(lat),
+                                         C.byref(st)), "serve")
+        stats = {name: getattr(st, name) for name, _ in ServeStats._fields_}
+        return lat, stats
+
+    def set_search_knobs(self, waves_per_block: int, vt_slots: int):
+        self._check(self.lib.etale_set_search_knobs(self.h, waves_per_block, vt_slots), "set_search_knobs")
+
+    def autotune(self, q, k: int, L: int) -> dict:
+        """Pick the fastest result-invariant search knobs on this query batch."""
+        q = self._dev(q, self._vdtype)
+        r = TuneResult()
+        self._check(self.lib.etale_autotune(self.h, _ptr(q), q.shape[0], k, L, C.byref(r)), "autotune")
+        return {"waves_per_block": r.waves_per_block, "vt_slots": r.vt_slots, "ms": r.ms, "ms_default": r.ms_default}
+
     def set_search_timing(self, enable: bool = True):
         self._check(self.lib.etale_set_search_timing(self.h, int(enable)), "set_search_timing")
 
@@ -310,7 +364,7 @@ class RoundRunner:
     views of the buffers, valid until the next call."""
 
     def __init__(self, index: Index, max_del: int, max_ins: int, max_q: int, k: int = 10, L: int = 64,
-                 reclaim: bool = False, graph: bool = True):
+                 reclaim: bool = False, graph: bool = True, buckets: bool = False):
         torch = index.torch
         self.ix, self.torch = index, torch
         dev = torch.device("cuda")
@@ -324,13 +378,59 @@ class RoundRunner:
         self.q_dists = torch.zeros((max(max_q, 1), k), dtype=index._ddtype, device=dev)
         self.counts = torch.zeros(3, dtype=torch.int32, device=dev)
         self.status = torch.zeros(2, dtype=torch.int32, device=dev)
-        self.desc = RoundDesc(_ptr(self.del_ids), _ptr(self.del_status), max_del, _ptr(self.vecs), _ptr(self.ids),
-                              max_ins, _ptr(self.q), _ptr(self.q_ids), _ptr(self.q_dists), max_q, k, L,
-                              _ptr(self.counts), _ptr(self.status), int(reclaim), int(graph))
+        self.L, self.reclaim, self.graph, self.buckets = L, reclaim, graph, buckets
+        self.desc = self._desc(max_del, max_ins, max_q)
+        self.descs = {}
 
-    def __call__(self, del_ids=None, x=None, q=None, counts=None) -> dict:
-        """Copy this round's inputs into the buffers, set the counts and run
-        the round. `counts` (nd, ni, nq) may override the input lengths, e.g.
+    def _desc(self, md: int, mi: int, mq: int) -> RoundDesc:
+        return RoundDesc(_ptr(self.del_ids), _ptr(self.del_status), md, _ptr(self.vecs), _ptr(self.ids), mi,
+                         _ptr(self.q), _ptr(self.q_ids), _ptr(self.q_dists), mq, self.k, self.L, _ptr(self.counts),
+                         _ptr(self.status), int(self.reclaim), int(self.graph))
+
+    @staticmethod
+    def _bucket(n: int, floor: int, cap: int) -> int:
+        if n == 0:
+            return 0
+        b = floor
+        while b < n:
+            b *= 2
+        return min(b, cap)
+
+    def captured(self, nd: int, ni: int, nq: int) -> bool:
+        """Whether a round of these counts replays an already captured graph."""
+        if not self.buckets:
+            return bool(self.descs) or getattr(self, "_ran", False)
+        key = (self._bucket(nd, 1024, self.max_del), self._bucket(ni, 1024, self.max_ins),
+               self._bucket(nq, 64, self.max_q))
+        return key in self.descs
+
+    def desc_for(self, nd: int, ni: int, nq: int) -> RoundDesc:
+        """Launch shapes of a round: the largest ones, or (buckets) the next
+        power of two above each count, so that every bucket is one graph."""
+        if not self.buckets:
+            return self.desc
+        key = (self._bucket(nd, 1024, self.max_del), self._bucket(ni, 1024, self.max_ins),
+               self._bucket(nq, 64, self.max_q))
+        if key not in self.descs:
+            self.descs[key] = self._desc(*key)
+        return self.descs[key]
+
+    def prepare(self, sizes):
+        """Capture the graphs of the size buckets of `sizes` ((nd, ni, nq)
+        triples) ahead of time by running rounds with zero counts, which
+        change no index state."""
+        for nd, ni, nq in sizes:
+            if self.captured(nd, ni, nq):
+                continue
+            self.counts.zero_()
+            self.n = (0, 0, 0)
+            desc = self.desc_for(nd, ni, nq)
+            self.ix._check(self.ix.lib.etale_round(self.ix.h, C.byref(desc)), "round")
+            self._ran = True
+
+    def load(self, del_ids=None, x=None, q=None, counts=None):
+        """Copy a round's inputs into the buffers and set its counts (stream
+        ordered). `counts` (nd, ni, nq) may override the input lengths, e.g.
         to pass counts above the maximum on purpose."""
         nd = 0 if del_ids is None else del_ids.numel()
         ni = 0 if x is None else x.shape[0]
@@ -344,6 +444,16 @@ class RoundRunner:
         c = counts if counts is not None else (nd, ni, nq)
         for i in range(3):
             self.counts[i].fill_(int(c[i]))
-        self.ix._check(self.ix.lib.etale_round(self.ix.h, C.byref(self.desc)), "round")
+        self.n = (nd, ni, nq)
+
+    def run(self) -> dict:
+        """Run the round on the loaded inputs (replays the graph after the first call)."""
+        nd, ni, nq = self.n
+        self.ix._check(self.ix.lib.etale_round(self.ix.h, C.byref(self.desc_for(nd, ni, nq))), "round")
+        self._ran = True
         return {"status": self.status, "del_status": self.del_status[:nd], "ids": self.ids[:ni],
                 "q_ids": self.q_ids[:nq], "q_dists": self.q_dists[:nq]}
+
+    def __call__(self, del_ids=None, x=None, q=None, counts=None) -> dict:
+        self.load(del_ids, x, q, counts)
+        return self.run()

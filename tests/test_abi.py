@@ -42,6 +42,8 @@ int main(void) {
          offsetof(etale_config, hip_stream), sizeof(etale_stats), offsetof(etale_stats, error_bits),
          sizeof(etale_round_desc), offsetof(etale_round_desc, max_q), offsetof(etale_round_desc, counts),
          offsetof(etale_round_desc, graph));
+  printf("%zu %zu %zu %zu\n", sizeof(etale_request), sizeof(etale_serve_config), sizeof(etale_serve_stats),
+         offsetof(etale_serve_stats, trace_seconds));
   return 0;
 }
 """
@@ -55,7 +57,8 @@ int main(void) {
 
 def test_struct_layout_matches_header():
     from paper_2607_02543_amd import etale
-    size, off_cap, off_stream, ssize, off_err, rsize, off_mq, off_cnt, off_graph = _c_layout()
+    size, off_cap, off_stream, ssize, off_err, rsize, off_mq, off_cnt, off_graph, qsize, scsize, sssize, off_ts = \
+        _c_layout()
     assert C.sizeof(etale.Config) == size
     assert etale.Config.id_capacity.offset == off_cap
     assert etale.Config.hip_stream.offset == off_stream
@@ -65,6 +68,10 @@ def test_struct_layout_matches_header():
     assert etale.RoundDesc.max_q.offset == off_mq
     assert etale.RoundDesc.counts.offset == off_cnt
     assert etale.RoundDesc.graph.offset == off_graph
+    assert C.sizeof(etale.Request) == qsize
+    assert C.sizeof(etale.ServeConfig) == scsize
+    assert C.sizeof(etale.ServeStats) == sssize
+    assert etale.ServeStats.trace_seconds.offset == off_ts
 
 
 def test_create_rejects_bad_configs_without_touching_a_device():

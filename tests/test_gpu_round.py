@@ -66,16 +66,18 @@ def test_round_parity_direct(reclaim):
     g.close()
 
 
-def test_round_parity_graph_replay_uneven_counts():
-    # one captured graph serves rounds of different sizes; eager calls run
-    # between the replays and every replay is checked
+@pytest.mark.parametrize("buckets", [False, True])
+def test_round_parity_graph_replay_uneven_counts(buckets):
+    # one captured graph (or one per size bucket) serves rounds of different
+    # sizes; eager calls run between the replays and every replay is checked
     torch = _torch()
     from paper_2607_02543_amd import etale
-    wl = small_workload(seed=42, n_base=1500, rounds=4, churn=0.05)
+    wl = small_workload(seed=42, n_base=1500, rounds=6, churn=0.05)
     p = index_params(wl, n_entry=48)
     o, g, st = _build(wl, p)
-    runner = etale.RoundRunner(g, max_del=90, max_ins=90, max_q=64, k=10, L=48, reclaim=True, graph=True)
-    sizes = [(80, 33, 64), (0, 90, 5), (61, 0, 1), (17, 71, 0), (90, 90, 64), (3, 1, 2)]
+    runner = etale.RoundRunner(g, max_del=90, max_ins=90, max_q=64, k=10, L=48, reclaim=True, graph=True,
+                               buckets=buckets)
+    sizes = [(80, 33, 64), (0, 90, 5), (61, 0, 1), (17, 71, 0), (90, 90, 64), (3, 1, 2), (80, 33, 60)]
     for r, (nd, ni, nq) in enumerate(sizes):
         print(f"[round] graph replay {r} sizes {nd, ni, nq}", flush=True)
         live = np.nonzero(~o.export()["deleted"])[0].astype(np.uint32)
