@@ -375,20 +375,104 @@ __device__ inline void retire_slab(const Index& ix, uint32_t s) {
   ix.retired_stack[idx] = s;
 }
 
+// Slabs reserved by one wave for the publications it will make. In the
+// deterministic phases every item publishes once with an uncontended CAS, so a
+// persistent wave pops all its fresh slabs and reserves all its retired-stack
+// slots with one atomic each, and counts its publications locally; the shared
+// stack tops and counters then see one atomic per wave instead of several per
+// publication. A retry after a lost CAS falls back to single atomics.
+struct SlabCursor {
+  uint64_t free_hi = 0;  // reserved free-stack entries are [free_hi - free_left, free_hi)
+  uint32_t free_left = 0;
+  uint64_t ret_next = 0;  // reserved retired-stack entries are [ret_next, ret_next + ret_left)
+  uint32_t ret_left = 0;
+  uint32_t pubs = 0;
+};
+
+// every lane takes part; lane 0's value is the one used (see wave_ticket)
+__device__ inline uint64_t wave_atomic_add(unsigned long long* ctr, unsigned long long v) {
+  const unsigned long long r = atomicAdd(ctr, (threadIdx.x & 63u) == 0 ? v : 0ull);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)r);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(r >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline SlabCursor reserve_slabs(const Index& ix, uint32_t n_alloc, uint32_t n_retire) {
+  SlabCursor c;
+  if (n_alloc) {
+    const uint64_t top = wave_atomic_add(&ix.ctr[C_FREE_TOP], (unsigned long long)(-(long long)n_alloc));
+    if (top >= n_alloc && top <= ix.P) {
+      c.free_hi = top;
+      c.free_left = n_alloc;
+    } else {
+      wave_atomic_add(&ix.ctr[C_FREE_TOP], (unsigned long long)n_alloc);  // give back; single allocs report the shortage
+    }
+  }
+  if (n_retire) {
+    const uint64_t at = wave_atomic_add(&ix.ctr[C_RETIRED_TOP], (unsigned long long)n_retire);
+    if (at + n_retire <= ix.P) {
+      c.ret_next = at;
+      c.ret_left = n_retire;
+    } else {
+      wave_atomic_add(&ix.ctr[C_RETIRED_TOP], (unsigned long long)(-(long long)n_retire));
+    }
+  }
+  return c;
+}
+
+// after a wave's last item: reserved slots left unused go back to the pool
+// (every reserved retired slot must name a slab), then the phase counter
+__device__ inline void finish_slabs(const Index& ix, SlabCursor& c, Counter which) {
+  const int l = lane_id();
+  while (c.ret_left) {  // fill with an unused reserved slab, else a freshly popped one
+    uint32_t s = NONE;
+    if (c.free_left) {
+      s = ix.free_stack[c.free_hi - 1];
+      --c.free_hi;
+      --c.free_left;
+    } else {
+      const uint64_t top = wave_atomic_add(&ix.ctr[C_FREE_TOP], ~0ull);
+      if (top == 0 || top > ix.P) {
+        wave_atomic_add(&ix.ctr[C_FREE_TOP], 1ull);
+        if (l == 0) atomicOr(&ix.ctr[C_ERROR], (unsigned long long)ERR_POOL_EMPTY);
+        break;
+      }
+      s = ix.free_stack[top - 1];
+    }
+    if (l == 0) ix.retired_stack[c.ret_next] = s;
+    ++c.ret_next;
+    --c.ret_left;
+  }
+  while (c.free_left) {  // popped but unused: retire, they rejoin the pool at the recycle
+    const uint32_t s = ix.free_stack[c.free_hi - 1];
+    --c.free_hi;
+    --c.free_left;
+    if (l == 0) retire_slab(ix, s);
+  }
+  if (c.pubs) wave_atomic_add(&ix.ctr[which], (unsigned long long)c.pubs);
+  c.pubs = 0;
+}
+
 // Copy-on-write publication of list (ids, d)[0..n) for node u by the whole
 // wave: snapshot the reference, take a fresh slab, write it, fence, CAS the
 // reference from the snapshot to <flag of snapshot, n, fresh slab>; on
 // success retire the displaced slab, on failure retire the fresh one and
 // retry, up to the attempt budget. Returns true when installed.
 __device__ inline bool publish(const Index& ix, uint32_t u, const uint32_t* ids, const uint32_t* d, uint32_t n,
-                               Counter which) {
+                               Counter which, SlabCursor* cur = nullptr) {
   const int l = lane_id();
   const uint32_t R = ix.R;
   for (uint32_t attempt = 0; attempt < ix.publish_attempts; ++attempt) {
     const uint64_t snap = bcast64(load_ref(ix, u));
     uint32_t s = 0;
-    if (l == 0) s = alloc_slab(ix);
-    s = bcast(s);
+    if (cur && cur->free_left) {
+      s = ix.free_stack[cur->free_hi - 1];
+      --cur->free_hi;
+      --cur->free_left;
+    } else {
+      if (l == 0) s = alloc_slab(ix);
+      s = bcast(s);
+    }
     if (s == NONE) return false;
     uint32_t* slab = ix.slabs + (size_t)s * 2u * R;
     for (uint32_t j = (uint32_t)l; j < R; j += 64) {
@@ -397,19 +481,32 @@ __device__ inline bool publish(const Index& ix, uint32_t u, const uint32_t* ids,
     }
     __threadfence();  // slab contents before the reference that names them
     uint32_t won = 0;
+    const bool reserved_retire = cur && cur->ret_left && ref_slab(snap) != NONE;
     if (l == 0) {
       const uint64_t want = make_ref(ref_del(snap), n, s);
       const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)snap, (unsigned long long)want);
       if (prev == snap) {
         won = 1;
-        if (ref_slab(snap) != NONE) retire_slab(ix, ref_slab(snap));
-        atomicAdd(&ix.ctr[which], 1ull);
+        if (reserved_retire)
+          ix.retired_stack[cur->ret_next] = ref_slab(snap);
+        else if (ref_slab(snap) != NONE)
+          retire_slab(ix, ref_slab(snap));
+        if (!cur) atomicAdd(&ix.ctr[which], 1ull);
       } else {
         retire_slab(ix, s);
         atomicAdd(&ix.ctr[C_CAS_FAIL], 1ull);
       }
     }
-    if (bcast(won)) return true;
+    if (bcast(won)) {
+      if (cur) {
+        ++cur->pubs;
+        if (reserved_retire) {
+          ++cur->ret_next;
+          --cur->ret_left;
+        }
+      }
+      return true;
+    }
   }
   if (l == 0) atomicAdd(&ix.ctr[C_PUB_DROPPED], 1ull);
   return false;

@@ -847,16 +847,22 @@ __device__ inline void resolve(const Index& ix, MaintArgs& a) {
 // Item loops of the maintenance kernels: persistent waves, item i, i + waves, ...
 #define FOR_EACH_WAVE_ITEM(i, n) for (uint32_t i = wave_index(); i < (n); i += total_waves())
 
+// items the calling wave takes in FOR_EACH_WAVE_ITEM over n items
+__device__ inline uint32_t wave_items(uint32_t n) {
+  const uint32_t w = wave_index(), W = total_waves();
+  return n > w ? (n - 1u - w) / W + 1u : 0u;
+}
+
 // ---- insert: forward prune + own publication (Algorithm 2, first lines) --------------
 template <class P>
-__device__ inline void forward_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t qi) {
+__device__ inline void forward_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t qi, SlabCursor& cur) {
   const int l = lane_id();
   const uint32_t v = a.first + qi;
   const uint32_t nc = a.vis_cnt[qi];
   for (uint32_t j = (uint32_t)l; j < nc; j += 64) m.cand[j] = key_id(a.vis_keys[(size_t)qi * a.vcap + j]);
   wave_sync();
   const int cnt = P::prune(ix, v, m.cand, (int)nc, m.pr);
-  publish(ix, v, m.pr.out_ids, m.pr.out_d, (uint32_t)cnt, C_PUB_FORWARD);
+  publish(ix, v, m.pr.out_ids, m.pr.out_d, (uint32_t)cnt, C_PUB_FORWARD, &cur);
   for (uint32_t j = (uint32_t)l; j < ix.R; j += 64) a.F[(size_t)qi * ix.R + j] = j < (uint32_t)cnt ? m.pr.out_ids[j] : NONE;
 }
 
@@ -866,10 +872,12 @@ __global__ void __launch_bounds__(256) k_forward(Index ix, MaintArgs a) {
   if (gated(ix, a.d)) return;
   resolve(ix, a);
   MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  SlabCursor cur = reserve_slabs(ix, wave_items(a.n), 0);  // new nodes hold no slab yet
   FOR_EACH_WAVE_ITEM(qi, a.n) {
     wave_sync();
-    forward_one<P>(ix, a, m, qi);
+    forward_one<P>(ix, a, m, qi, cur);
   }
+  finish_slabs(ix, cur, C_PUB_FORWARD);
 }
 
 __global__ void k_reverse_pairs(Index ix, MaintArgs a) {
@@ -904,7 +912,7 @@ __global__ void k_segments(Index ix, const uint64_t* pairs, uint32_t n, Dyn d, u
 
 // ---- insert: reverse edges in (target, source) order, one publication per target ------
 template <class P>
-__device__ inline void reverse_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t t) {
+__device__ inline void reverse_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t t, SlabCursor& cur) {
   const uint32_t w = (uint32_t)(a.pairs[t] >> 32);
   const int l = lane_id();
   const uint32_t R = ix.R;
@@ -943,7 +951,7 @@ __device__ inline void reverse_one(const Index& ix, const MaintArgs& a, MaintLds
       copy_out(m, n);
     }
   }
-  publish(ix, w, m.nl_id, m.nl_d, n, C_PUB_REVERSE);
+  publish(ix, w, m.nl_id, m.nl_d, n, C_PUB_REVERSE, &cur);
 }
 
 
@@ -1050,7 +1058,8 @@ __device__ inline void chain_fill_row(const ChainLds& c, uint32_t a, const uint3
 }
 
 template <int G>
-__device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, const ChainLds& c, uint32_t t) {
+__device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, const ChainLds& c, uint32_t t,
+                                        SlabCursor& cur) {
   const int l = lane_id();
   const int ch = l % G;
   const uint32_t R = ix.R;
@@ -1160,7 +1169,7 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
     c.out_d[l] = c.dw[sl];
   }
   wave_sync();
-  publish(ix, w, c.out_id, c.out_d, n, C_PUB_REVERSE);
+  publish(ix, w, c.out_id, c.out_d, n, C_PUB_REVERSE, &cur);
 }
 
 // one wave per run of the sorted (target, source) pairs
@@ -1170,21 +1179,25 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
   if (gated(ix, a.d)) return;
   resolve(ix, a);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
+  // every target is a live node with a slab: one fresh slab and one retired slab each
+  SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
   if constexpr (P::CHAIN) {
     if (a.chain) {
       const ChainLds c = carve_chain(wave_lds(smem, a), ix.R, a.vstride);
       FOR_EACH_WAVE_ITEM(si, nseg) {
         wave_sync();
-        reverse_chain_u8<P::GL>(ix, a, c, a.seg[si]);
+        reverse_chain_u8<P::GL>(ix, a, c, a.seg[si], cur);
       }
+      finish_slabs(ix, cur, C_PUB_REVERSE);
       return;
     }
   }
   MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   FOR_EACH_WAVE_ITEM(si, nseg) {
     wave_sync();
-    reverse_one<P>(ix, a, m, a.seg[si]);
+    reverse_one<P>(ix, a, m, a.seg[si], cur);
   }
+  finish_slabs(ix, cur, C_PUB_REVERSE);
 }
 
 // ---- insert: refine -- same-batch nodes two hops away are offered ----------------------
@@ -1339,7 +1352,7 @@ __global__ void k_repair_pairs(Index ix, MaintArgs a) {
 }
 
 template <class P>
-__device__ inline void repair_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t t) {
+__device__ inline void repair_one(const Index& ix, const MaintArgs& a, MaintLds& m, uint32_t t, SlabCursor& cur) {
   const uint32_t an = (uint32_t)(a.pairs[t] >> 32);
   const int l = lane_id();
   const uint32_t R = ix.R;
@@ -1368,7 +1381,7 @@ __device__ inline void repair_one(const Index& ix, const MaintArgs& a, MaintLds&
     n = (uint32_t)P::prune(ix, an, m.cand, (int)(nk + (uint32_t)kc), m.pr);
     copy_out(m, n);
   }
-  publish(ix, an, m.nl_id, m.nl_d, n, C_PUB_REPAIR);
+  publish(ix, an, m.nl_id, m.nl_d, n, C_PUB_REPAIR, &cur);
 }
 
 template <class P>
@@ -1378,10 +1391,12 @@ __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
   resolve(ix, a);
   MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
+  SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
   FOR_EACH_WAVE_ITEM(si, nseg) {
     wave_sync();
-    repair_one<P>(ix, a, m, a.seg[si]);
+    repair_one<P>(ix, a, m, a.seg[si], cur);
   }
+  finish_slabs(ix, cur, C_PUB_REPAIR);
 }
 
 // ---- stable LSD radix sort with a launch-time count --------------------------------------
@@ -1554,7 +1569,8 @@ __global__ void __launch_bounds__(256) k_dirty(Index ix, uint64_t n_ids, Dyn d, 
 }
 
 // phase 1, compaction: republish each dirty node without its tombstoned entries
-__device__ inline void compact_one(const Index& ix, const uint64_t* bitmap, uint32_t* ids, uint32_t* d, uint32_t u) {
+__device__ inline void compact_one(const Index& ix, const uint64_t* bitmap, uint32_t* ids, uint32_t* d, uint32_t u,
+                                   SlabCursor& cur) {
   const int l = lane_id();
   const uint64_t r = bcast64(load_ref(ix, u));
   const uint32_t deg = ref_deg(r), s = ref_slab(r);
@@ -1570,7 +1586,7 @@ __device__ inline void compact_one(const Index& ix, const uint64_t* bitmap, uint
     d[lanes_below(m)] = dd;
   }
   wave_sync();
-  publish(ix, u, ids, d, (uint32_t)__popcll(m), C_PUB_COMPACT);
+  publish(ix, u, ids, d, (uint32_t)__popcll(m), C_PUB_COMPACT, &cur);
 }
 
 __global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty, uint64_t n, Dyn dn,
@@ -1579,10 +1595,12 @@ __global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty
   if (gated(ix, dn)) return;
   const uint32_t cnt = dyn_count(ix, dn, (uint32_t)n);
   uint32_t* ids = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * lds_per_wave);
+  SlabCursor cur = reserve_slabs(ix, wave_items(cnt), wave_items(cnt));
   FOR_EACH_WAVE_ITEM(i, cnt) {
     wave_sync();
-    compact_one(ix, bitmap, ids, ids + 64, dirty[i]);
+    compact_one(ix, bitmap, ids, ids + 64, dirty[i], cur);
   }
+  finish_slabs(ix, cur, C_PUB_COMPACT);
 }
 
 // phase 2: <1,d,s> -> <1,0,none> and the slab is retired
