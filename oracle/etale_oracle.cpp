@@ -453,9 +453,13 @@ struct Oracle {
       a = b;
     }
   }
-  // P5: refine -- offer each new node the same-batch nodes two hops away
+  // P5: refine -- offer each new node the same-batch nodes two hops away.
+  // Every new node reads the lists as they stand when the pass starts; the
+  // changed lists are published after all are computed.
   void refine_pass(uint32_t first, uint64_t n) {
     const uint32_t end = first + (uint32_t)n;
+    std::vector<std::vector<Entry>> out(n);
+    std::vector<char> changed(n, 0);
     for (uint64_t i = 0; i < n; ++i) {
       uint32_t v = first + (uint32_t)i;
       std::vector<uint32_t> c;
@@ -471,14 +475,16 @@ struct Oracle {
         extra = !in;
       }
       if (!extra) continue;
-      std::vector<Entry> N = robust_prune(v, c);
-      bool same = N.size() == adj[v].size();
-      for (size_t t = 0; same && t < N.size(); ++t) same = N[t].id == adj[v][t].id;
-      if (!same) {
-        publish(v, N);
+      out[i] = robust_prune(v, c);
+      bool same = out[i].size() == adj[v].size();
+      for (size_t t = 0; same && t < out[i].size(); ++t) same = out[i][t].id == adj[v][t].id;
+      changed[i] = !same;
+    }
+    for (uint64_t i = 0; i < n; ++i)
+      if (changed[i]) {
+        publish(first + (uint32_t)i, out[i]);
         ++pub_refine;
       }
-    }
   }
 
   // ---- insert call (Algorithm 2 over a batch; one launch) -------------------

@@ -396,6 +396,11 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     HIP_TRY(launch_segments(d, sorted, p.max_d * R, dp, ix->seg, s));
     pa.pairs = sorted;
     pa.npairs = p.max_d * R;
+    if (ix->cfg.metric == ETALE_METRIC_L2_U8 && R <= 32 && !ix->no_chain &&
+        pool_lds_per_wave(pa.vstride) <= 65536u) {
+      pa.chain = 1;
+      pa.lds_per_wave = std::max(pa.lds_per_wave, pool_lds_per_wave(pa.vstride));
+    }
     pa.np_ctr = C_DEL_OK;
     pa.np_mult = R;
     pa.seg = ix->seg;
@@ -434,6 +439,9 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     if (ix->cfg.refine && p.boot != 1) {
       MaintArgs ga = maint_args(ix, R + R * R);
       ga.n = p.max_i;
+      ga.vis_keys = ix->vis_keys;  // free after P2: holds the refined lists until they are published
+      ga.vis_cnt = ix->vis_cnt;
+      ga.vcap = std::max(ga.vcap, R);
       ga.d = di;
       ga.d.skip = G_FAIL | G_BOOT;
       HIP_TRY(launch_maint(MK_REFINE, d, ga, p.max_i, maint_waves_per_block(ga), s));
@@ -534,7 +542,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   ALLOC(ix->retired_stack, P * 4);
   ALLOC(ix->ctr, C_NCOUNTERS * 8);
   ALLOC(ix->entries, (uint64_t)c.n_entry * 4);
-  ALLOC(ix->vis_keys, B * ix->vcap_build * 8);
+  ALLOC(ix->vis_keys, B * std::max<uint64_t>(ix->vcap_build, R) * 8);  // also the refined lists (R per node)
   ALLOC(ix->vis_cnt, B * 4);
   ALLOC(ix->F, B * R * 4);
   ALLOC(ix->pairs_a, B * R * 8);
@@ -557,6 +565,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   d.a2 = c.alpha_num * c.alpha_num;
   d.b2 = c.alpha_den * c.alpha_den;
   d.publish_attempts = c.publish_attempts;
+  d.fence = 0;  // every call is a round-synchronous launch sequence
   d.prune_cap = c.prune_cap;
   d.metric = c.metric;
   d.trav = c.metric == ETALE_METRIC_IP_F32 ? c.traversal : 0;

@@ -75,6 +75,7 @@ struct Index {
   uint32_t dim, R;
   uint32_t a2, b2;  // alpha = a/b, applied squared: a^2 * D1 <= b^2 * D2
   uint32_t publish_attempts;
+  uint32_t fence;   // 1: a release fence orders a slab's contents before its reference (concurrent readers)
   uint32_t prune_cap;
   int32_t metric;   // 0: uint8 squared L2, 1: FP32 inner product (d = 1 - <a,b>)
   int32_t trav;     // traversal copy for the float metric: 0 FP32, 1 bf16, 2 FP8 e4m3 + scale
@@ -479,7 +480,12 @@ __device__ inline bool publish(const Index& ix, uint32_t u, const uint32_t* ids,
       slab[j] = j < n ? ids[j] : NONE;
       slab[R + j] = j < n ? d[j] : 0u;
     }
-    __threadfence();  // slab contents before the reference that names them
+    // Slab contents before the reference that names them, for readers running
+    // concurrently with the publication. In the round-synchronous launches no
+    // wavefront reads a slab published by another one in the same launch
+    // (the launch boundary orders them), so the fence is taken only when
+    // concurrent readers are possible.
+    if (ix.fence) __threadfence();
     uint32_t won = 0;
     const bool reserved_retire = cur && cur->ret_left && ref_slab(snap) != NONE;
     if (l == 0) {

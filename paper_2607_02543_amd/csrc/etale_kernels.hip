@@ -1221,12 +1221,21 @@ __device__ inline void refine_one(const Index& ix, const MaintArgs& a, MaintLds&
     nc += (uint32_t)__popcll(bm);
   }
   wave_sync();
-  if (nc == own) return;  // no same-batch node within two hops
-  const int cnt = P::prune(ix, v, m.cand, (int)nc, m.pr);
-  const bool diff = (uint32_t)cnt != own || ballot((uint32_t)l < own && m.pr.out_ids[l] != m.nl_id[l]) != 0ull;
-  if (diff) publish(ix, v, m.pr.out_ids, m.pr.out_d, (uint32_t)cnt, C_PUB_REFINE);
+  uint32_t cnt = NONE;  // unchanged
+  if (nc != own) {      // some same-batch node within two hops
+    const int c = P::prune(ix, v, m.cand, (int)nc, m.pr);
+    const bool diff = (uint32_t)c != own || ballot((uint32_t)l < own && m.pr.out_ids[l] != m.nl_id[l]) != 0ull;
+    if (diff) {
+      cnt = (uint32_t)c;
+      if ((uint32_t)l < cnt) a.vis_keys[(size_t)qi * a.vcap + l] = make_key(m.pr.out_d[l], m.pr.out_ids[l]);
+    }
+  }
+  if (l == 0) a.vis_cnt[qi] = cnt;
 }
 
+// Refine reads every list as it stands when the pass starts: the new lists
+// are computed into the insert searches' scratch first (k_refine), then
+// published (k_refine_publish).
 template <class P>
 __global__ void __launch_bounds__(256) k_refine(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
@@ -1236,6 +1245,27 @@ __global__ void __launch_bounds__(256) k_refine(Index ix, MaintArgs a) {
   FOR_EACH_WAVE_ITEM(qi, a.n) {
     wave_sync();
     refine_one<P>(ix, a, m, qi);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_refine_publish(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  uint32_t* ids = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * 512u);
+  uint32_t* d = ids + 64;
+  const int l = lane_id();
+  FOR_EACH_WAVE_ITEM(qi, a.n) {
+    const uint32_t cnt = a.vis_cnt[qi];
+    if (cnt == NONE) continue;
+    wave_sync();
+    if ((uint32_t)l < cnt) {
+      const uint64_t k = a.vis_keys[(size_t)qi * a.vcap + l];
+      ids[l] = key_id(k);
+      d[l] = key_dist(k);
+    }
+    wave_sync();
+    publish(ix, a.first + qi, ids, d, cnt, C_PUB_REFINE);
   }
 }
 
@@ -1384,14 +1414,247 @@ __device__ inline void repair_one(const Index& ix, const MaintArgs& a, MaintLds&
   publish(ix, an, m.nl_id, m.nl_d, n, C_PUB_REPAIR, &cur);
 }
 
+
+// ---- repair with a wave-local candidate pool (uint8 rows, R <= 32) ------------------
+// Algorithm 3 for one target a: for each deleted u in ascending order,
+// K = RobustPrune(a, N(u) \ {a}), then N(a) = RobustPrune(a, (N(a) \ {u}) U K).
+// A pool of 64 slots holds the rows, norms, ids, distances to a and deletion
+// flags of a's list and of one N(u); a's list is staged once, and per u only
+// the rows and flags of the members of N(u) that are not already pooled are
+// fetched (one round trip). Both prunes then run from LDS: candidates are
+// ranked by (distance, id) with duplicates, a and tombstones dropped, at most
+// prune_cap are considered, and the distances between a kept candidate and
+// the later live ones are computed when needed, one candidate per lane.
+struct PoolLds {
+  uint8_t* rows;     // [64][vstride]
+  uint32_t* norm;    // [64]
+  uint32_t* id;      // [64]
+  uint32_t* dw;      // [64] squared distance to the target
+  uint32_t* dead;    // [64]
+  uint32_t* list;    // [64] list position -> slot
+  uint32_t* cand;    // [64] candidate slots of a prune
+  uint32_t* sorted;  // [64] candidate slots in (distance, id) order
+  uint32_t* kept;    // [64] output slots of a prune
+  uint32_t vstride;
+};
+
+constexpr uint32_t POOL = 64;
+
+__host__ __device__ inline uint32_t pool_lds_bytes(uint32_t vstride) {
+  return ((POOL * vstride + 8u * POOL * 4u) + 15u) & ~15u;
+}
+
+__device__ inline PoolLds carve_pool(char* base, uint32_t vstride) {
+  PoolLds p;
+  p.vstride = vstride;
+  p.rows = reinterpret_cast<uint8_t*>(base);
+  uint32_t* q = reinterpret_cast<uint32_t*>(base + (size_t)POOL * vstride);
+  p.norm = q;
+  p.id = q + POOL;
+  p.dw = q + 2 * POOL;
+  p.dead = q + 3 * POOL;
+  p.list = q + 4 * POOL;
+  p.cand = q + 5 * POOL;
+  p.sorted = q + 6 * POOL;
+  p.kept = q + 7 * POOL;
+  return p;
+}
+
+// rows, norms, deletion flags and distances to the target (fragment wf, norm
+// ww) of slots[0..cnt), all loads issued before any is used
+template <int G>
+__device__ inline void pool_stage(const Index& ix, const PoolLds& p, const uint32_t* slots, int cnt, uint4 wf,
+                                  uint32_t ww) {
+  constexpr int VPP = 64 / G;
+  const int l = lane_id();
+  const int ch = l % G, grp = l / G;
+  uint64_t ref = 0;
+  const uint32_t my = l < cnt ? slots[l] : 0u;
+  if (l < cnt) ref = load_ref(ix, p.id[my]);
+  for (int base = 0; base < cnt; base += 4 * VPP) {
+    uint4 v[4];
+    int sl[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = base + u * VPP + grp;
+      sl[u] = k < cnt ? (int)slots[k] : -1;
+      v[u] = make_uint4(0, 0, 0, 0);
+      if (sl[u] >= 0) v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)p.id[sl[u]] * ix.dim)[ch];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t nn = group_sum<G>(dot16(v[u], v[u], 0u));
+      const uint32_t dt = group_sum<G>(dot16(wf, v[u], 0u));
+      if (sl[u] >= 0) {
+        *reinterpret_cast<uint4*>(p.rows + (size_t)sl[u] * p.vstride + ch * 16) = v[u];
+        if (ch == 0) {
+          p.norm[sl[u]] = nn;
+          p.dw[sl[u]] = ww + nn - 2u * dt;
+        }
+      }
+    }
+  }
+  if (l < cnt) p.dead[my] = ref_del(ref);
+  wave_sync();
+}
+
+// squared distance between the pooled rows of slots a and b, by one lane
+__device__ inline uint32_t pool_dist(const PoolLds& p, uint32_t a, uint32_t b, int words) {
+  const uint4* ra = reinterpret_cast<const uint4*>(p.rows + (size_t)a * p.vstride);
+  const uint4* rb = reinterpret_cast<const uint4*>(p.rows + (size_t)b * p.vstride);
+  uint32_t dot = 0;
+  for (int w = 0; w < words; ++w) dot = dot16(ra[w], rb[w], dot);
+  return p.norm[a] + p.norm[b] - 2u * dot;
+}
+
+// RobustPrune(self, candidate slots cs[0..m)) into out[0..return); m <= 64
+__device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const uint32_t* cs, uint32_t m,
+                                      uint32_t self, uint32_t* out) {
+  const int l = lane_id();
+  const int words = (int)ix.dim / 16;
+  const uint32_t my = (uint32_t)l < m ? cs[l] : 0u;
+  const uint32_t myid = (uint32_t)l < m ? p.id[my] : NONE;
+  bool valid = (uint32_t)l < m && myid != self && p.dead[my] == 0u;
+  for (uint32_t j = 0; j < (uint32_t)l && j < m; ++j) {  // of repeated ids the first copy stays
+    const uint32_t sj = cs[j];
+    if (p.id[sj] == myid && p.id[sj] != self && p.dead[sj] == 0u) valid = false;
+  }
+  const uint64_t vm = ballot(valid);
+  const uint64_t mykey = make_key(p.dw[my], myid);
+  uint32_t rank = 0;  // keys of the surviving candidates are distinct
+  for (uint32_t j = 0; j < m; ++j)
+    if (((vm >> j) & 1ull) && make_key(p.dw[cs[j]], p.id[cs[j]]) < mykey) ++rank;
+  wave_sync();
+  if (valid) p.sorted[rank] = my;
+  wave_sync();
+  uint32_t mm = (uint32_t)__popcll(vm);
+  const uint32_t cap = ix.prune_cap < POOL ? ix.prune_cap : POOL;
+  if (mm > cap) mm = cap;
+  const uint32_t csl = (uint32_t)l < mm ? p.sorted[l] : 0u;
+  const uint32_t cdw = (uint32_t)l < mm ? p.dw[csl] : 0u;
+  uint64_t alive = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
+  uint32_t cnt = 0, from = 0, keep_slot = 0;
+  while (cnt < ix.R) {
+    const uint64_t mk = from < 64 ? (alive & (~0ull << from)) : 0ull;
+    if (!mk) break;
+    const uint32_t j = (uint32_t)__builtin_ctzll(mk);
+    const uint32_t sj = (uint32_t)__shfl((int)csl, (int)j, 64);
+    if ((uint32_t)l == cnt) keep_slot = sj;
+    ++cnt;
+    from = j + 1;
+    if (cnt == ix.R) break;
+    bool kill = false;
+    if ((uint32_t)l > j && ((alive >> l) & 1ull)) {
+      const uint32_t d = pool_dist(p, sj, csl, words);
+      kill = (uint64_t)ix.a2 * d <= (uint64_t)ix.b2 * (uint64_t)cdw;
+    }
+    alive &= ~ballot(kill);
+  }
+  wave_sync();
+  if ((uint32_t)l < cnt) out[l] = keep_slot;
+  wave_sync();
+  return cnt;
+}
+
+template <int G>
+__device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, const PoolLds& p, uint32_t t,
+                                       SlabCursor& cur) {
+  const int l = lane_id();
+  const uint32_t R = ix.R;
+  const uint32_t an = (uint32_t)(a.pairs[t] >> 32);
+  const uint4 wf = load_frag<G>(ix.x + (size_t)an * ix.dim);
+  const uint32_t ww = group_sum<G>(dot16(wf, wf, 0u));
+  // a's list in slots 0..n-1, rows and flags staged once
+  const uint64_t r = bcast64(load_ref(ix, an));
+  uint32_t n = ref_slab(r) == NONE ? 0u : ref_deg(r);
+  if ((uint32_t)l < n) {
+    p.id[l] = ix.slabs[(size_t)ref_slab(r) * 2u * R + (uint32_t)l];
+    p.list[l] = (uint32_t)l;
+    p.cand[l] = (uint32_t)l;
+  }
+  wave_sync();
+  pool_stage<G>(ix, p, p.cand, (int)n, wf, ww);
+  uint64_t used = (1ull << n) - 1ull;
+  for (uint32_t q = t; q < a.npairs && a.pairs[q] != KEY_NONE && (uint32_t)(a.pairs[q] >> 32) == an; ++q) {
+    const uint32_t u = (uint32_t)a.pairs[q];
+    // B = N(u) \ {a}: members already pooled keep their slot, the others take free slots
+    const uint64_t ru = bcast64(load_ref(ix, u));
+    const uint32_t du = ref_slab(ru) == NONE ? 0u : ref_deg(ru);
+    uint32_t b = NONE;
+    if ((uint32_t)l < du) b = ix.slabs[(size_t)ref_slab(ru) * 2u * R + (uint32_t)l];
+    const bool ok = b != NONE && b != an;
+    int at = -1;
+    if (ok)
+      for (uint32_t x = 0; x < n; ++x)
+        if (p.id[p.list[x]] == b) at = (int)p.list[x];
+    const bool fresh = ok && at < 0;
+    const uint64_t fm = ballot(fresh);
+    if (fresh) {  // the k-th fresh member takes the k-th free slot
+      uint64_t fr = ~used;
+      for (uint32_t k = lanes_below(fm); k; --k) fr &= fr - 1ull;
+      at = __builtin_ctzll(fr);
+      p.id[at] = b;
+    }
+    const uint64_t om = ballot(ok);
+    if (ok) p.cand[lanes_below(om)] = (uint32_t)at;
+    wave_sync();
+    {  // stage the fresh members
+      uint32_t* fs = p.kept;
+      if (fresh) fs[lanes_below(fm)] = (uint32_t)at;
+      wave_sync();
+      pool_stage<G>(ix, p, fs, __popcll(fm), wf, ww);
+    }
+    // K = RobustPrune(a, B)
+    const uint32_t kc = pool_prune(ix, p, p.cand, (uint32_t)__popcll(om), an, p.kept);
+    // N = RobustPrune(a, (N \ {u}) U K)
+    const uint32_t ks = (uint32_t)l < kc ? p.kept[l] : 0u;
+    const uint32_t ls = (uint32_t)l < n ? p.list[l] : 0u;
+    const bool stay = (uint32_t)l < n && p.id[ls] != u;
+    const uint64_t sm = ballot(stay);
+    const uint32_t ns = (uint32_t)__popcll(sm);
+    wave_sync();
+    if (stay) p.cand[lanes_below(sm)] = ls;
+    if ((uint32_t)l < kc) p.cand[ns + (uint32_t)l] = ks;
+    wave_sync();
+    n = pool_prune(ix, p, p.cand, ns + kc, an, p.list);
+    // slots not on the new list become free
+    used = 0;
+    for (uint32_t k = 0; k < n; ++k) used |= 1ull << p.list[k];
+  }
+  // publish (ids and distances in list order)
+  uint32_t oid = 0, od = 0;
+  if ((uint32_t)l < n) {
+    oid = p.id[p.list[l]];
+    od = p.dw[p.list[l]];
+  }
+  wave_sync();
+  if ((uint32_t)l < n) {
+    p.cand[l] = oid;
+    p.sorted[l] = od;
+  }
+  wave_sync();
+  publish(ix, an, p.cand, p.sorted, n, C_PUB_REPAIR, &cur);
+}
+
 template <class P>
 __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, a.d)) return;
   resolve(ix, a);
-  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
   SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
+  if constexpr (P::CHAIN) {
+    if (a.chain) {
+      const PoolLds p = carve_pool(wave_lds(smem, a), a.vstride);
+      FOR_EACH_WAVE_ITEM(si, nseg) {
+        wave_sync();
+        repair_chain_u8<P::GL>(ix, a, p, a.seg[si], cur);
+      }
+      finish_slabs(ix, cur, C_PUB_REPAIR);
+      return;
+    }
+  }
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   FOR_EACH_WAVE_ITEM(si, nseg) {
     wave_sync();
     repair_one<P>(ix, a, m, a.seg[si], cur);
@@ -1973,6 +2236,7 @@ hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_pe
 #undef LS
 
 uint32_t chain_lds_per_wave(uint32_t R, uint32_t vstride) { return chain_lds_bytes(R, vstride); }
+uint32_t pool_lds_per_wave(uint32_t vstride) { return pool_lds_bytes(vstride); }
 
 uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R) {
   size_t b = (size_t)a.nsort * 8 + (size_t)a.prune_cap * 8 + (size_t)a.prune_cap * a.vstride + (size_t)a.prune_cap * 8 +
@@ -1986,7 +2250,10 @@ static void launch_maint_p(MaintKernel which, const Index& ix, const MaintArgs& 
   switch (which) {
     case MK_FORWARD: hipLaunchKernelGGL(k_forward<P>, dim3(grid), blk, lds, s, ix, a); break;
     case MK_REVERSE: hipLaunchKernelGGL(k_reverse_apply<P>, dim3(grid), blk, lds, s, ix, a); break;
-    case MK_REFINE: hipLaunchKernelGGL(k_refine<P>, dim3(grid), blk, lds, s, ix, a); break;
+    case MK_REFINE:
+      hipLaunchKernelGGL(k_refine<P>, dim3(grid), blk, lds, s, ix, a);
+      hipLaunchKernelGGL(k_refine_publish, dim3(grid), blk, 512u * (blk.x / 64u), s, ix, a);
+      break;
     case MK_REPAIR: hipLaunchKernelGGL(k_repair_apply<P>, dim3(grid), blk, lds, s, ix, a); break;
   }
 }

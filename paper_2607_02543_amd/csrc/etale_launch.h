@@ -52,8 +52,8 @@ struct ScanArgs {
 struct MaintArgs {
   uint32_t first, n;       // new ids [first, first + n) / number of deleted ids
   uint32_t vcap;
-  const uint64_t* vis_keys;
-  const uint32_t* vis_cnt;
+  uint64_t* vis_keys;       // insert searches' expanded keys; refine's new lists
+  uint32_t* vis_cnt;
   uint32_t* F;             // [n x R] forward lists
   uint64_t* pairs;         // (target, source) keys, sorted for the apply kernels
   uint32_t npairs;
@@ -90,6 +90,7 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEve
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s);
 uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R);
 uint32_t chain_lds_per_wave(uint32_t R, uint32_t vstride);
+uint32_t pool_lds_per_wave(uint32_t vstride);
 hipError_t launch_maint(MaintKernel which, const Index& ix, const MaintArgs& a, uint32_t nwaves,
                         uint32_t waves_per_block, hipStream_t s);
 hipError_t launch_reverse_pairs(const Index& ix, const MaintArgs& a, hipStream_t s);
