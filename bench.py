@@ -42,7 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=5000)
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--workload", default="scale_u8_1m", choices=["scale_u8_1m", "precision_f32", "batching_f32"])
+    ap.add_argument("--workload", default="scale_u8_1m", choices=["scale_u8_1m", "precision_f32", "batching_f32",
+                                                                   "serving_u8"])
+    ap.add_argument("--rates", default="20000,50000,100000", help="serving: request rates per second")
+    ap.add_argument("--seconds", type=float, default=5.0, help="serving: trace length per rate")
     ap.add_argument("--rounds", type=int, default=0, help="batching workload: timed rounds (default 50)")
     ap.add_argument("--prune-cap", type=int, default=0)
     ap.add_argument("--W", type=int, default=2, help="expansions per search iteration (1 or 2)")
@@ -322,8 +325,12 @@ def run_batching(args):
     # recall at k = 10 on a sample, against brute force over the live set
     qs = torch.from_numpy(st.queries(1000)).to(dev)
     gt, _ = B.bruteforce(qs, 10)
-    ids_s, _ = B.search(qs, 10, 64)
-    rec = recall(ids_s.cpu().numpy(), gt.cpu().numpy())
+    gt = gt.cpu().numpy()
+    rec_l = {}
+    for Lr in (64, 128, 256):
+        ids_s, _ = B.search(qs, 10, Lr)
+        rec_l[Lr] = round(recall(ids_s.cpu().numpy(), gt), 4)
+    rec = rec_l[64]
     cap_rows = [x for x in rows if not x["replay"]]
     rows_all = rows
     rows = [x for x in rows if x["replay"]] or rows  # steady state: rounds that replayed a captured graph
@@ -361,11 +368,109 @@ def run_batching(args):
         "capture_round_ms_mean": round(float(np.mean([x["graph_ms"] for x in cap_rows])), 3) if cap_rows else None,
         "capture_all_s": round(t_cap, 3),
         "per_op_ms_all_rounds": round(float(np.mean([x["per_op_ms"] for x in rows_all])), 3),
-        "recall_at_10_L64": round(rec, 4), "autotune": tune, "build_s": round(t_build, 2),
+        "recall_at_10_L64": round(rec, 4), "recall_at_10_L128": rec_l[128], "recall_at_10_L256": rec_l[256],
+        "autotune": tune, "build_s": round(t_build, 2),
         "device_bytes_per_index": B.stats()["device_bytes"],
     }
     A.close()
     B.close()
+    return out
+
+
+def run_serving(args):
+    """Open-loop serving: Poisson request traces (90% search, 5% insert, 5%
+    delete of a live base id) against a 10M x 128-d uint8 index, continuously
+    batched into rounds by the library's serving loop (etale_serve), one trace
+    per rate on the same index."""
+    import torch
+
+    from paper_2607_02543_amd import datagen as dg
+    from paper_2607_02543_amd import etale
+
+    dev = torch.device("cuda:0")
+    n_base = args.n_base if args.n_base != 1_000_000 else 10_000_000
+    rates = [float(v) for v in args.rates.split(",")]
+    wl = dg.serving_u8(n_base=n_base)
+    st = dg.Stream(wl)
+    traces, t0 = [], 0.0
+    for rate in rates:
+        tr = st.trace(rate, args.seconds, t0)
+        traces.append(tr)
+        t0 = float(tr["t"][-1]) + 1.0 if tr["t"].size else t0 + 1.0
+    n_ins = int(sum((tr["kind"] == 1).sum() for tr in traces))
+    n_del = int(sum((tr["kind"] == 2).sum() for tr in traces))
+    n_srch = int(sum((tr["kind"] == 0).sum() for tr in traces))
+    max_tick = 8192
+    cap = n_base + n_ins + 16
+    max_b = max(wl.build_batch_max, max_tick)
+    slab_cap = 2 * cap + max_b * (wl.R + 2)
+    t_b = time.perf_counter()
+    ix = etale.Index(wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den), n_entry=args.n_entry,
+                     id_capacity=cap, slab_capacity=slab_cap, max_batch=max_b, W=args.W)
+    done = 0
+    for b in wl.build_batches():
+        ix.insert(torch.from_numpy(st.base(b)).to(dev))
+        done += b
+        if done % 1_000_000 < b:
+            log(args, f"built {done}")
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t_b
+    # request payloads: a pool of query rows (reused), one fresh row per insert,
+    # and distinct live base ids for the deletes
+    q_pool = min(max(n_srch, 1), 65536)
+    rows = torch.from_numpy(np.concatenate([st.queries(q_pool), st.inserts(n_ins)])).to(dev)
+    del_ids = st.deletes(np.arange(n_base, dtype=np.uint32), n_del)
+    st.rng["deletes"].shuffle(del_ids)
+    qi = ii = di = 0
+    out = {"metric": "serving: request latency p50 / p99 (ms) and sustained requests/s under Poisson load, 1 GPU",
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "serving_u8_10m", "n_base": n_base, "dim": wl.dim, "R": wl.R, "k": 10, "L": 64,
+                      "mix": "90% search / 5% insert / 5% delete", "rates": rates, "seconds_per_rate": args.seconds,
+                      "max_tick": max_tick, "hbm_budget_gb": 64, "n_entry": args.n_entry, "W": args.W,
+                      "parallelism": "single GPU"},
+           "build_s": round(t_build, 2), "per_rate": []}
+    for rate, tr in zip(rates, traces):
+        kind = tr["kind"]
+        arg = np.zeros(kind.size, np.uint32)
+        s_idx = np.nonzero(kind == 0)[0]
+        i_idx = np.nonzero(kind == 1)[0]
+        d_idx = np.nonzero(kind == 2)[0]
+        arg[s_idx] = st.rng["arrivals"].integers(0, q_pool, size=s_idx.size)
+        arg[i_idx] = q_pool + ii + np.arange(i_idx.size)
+        arg[d_idx] = del_ids[di:di + d_idx.size]
+        ii += i_idx.size
+        di += d_idx.size
+        lat, sst = ix.serve(tr["t"], kind, arg, rows, k=10, L=64, max_tick=max_tick, reclaim_every=200,
+                            hbm_budget_bytes=64 << 30, graph=True)
+        ok = lat >= 0
+        srch = lat[(kind == 0) & ok]
+        upd = lat[(kind != 0) & ok]
+        pct = lambda a, q: round(float(np.percentile(a, q)), 3) if a.size else None  # noqa: E731
+        row = {"rate": rate, "requests": int(kind.size), "completed": int(ok.sum()),
+               "throughput_rps": round(float(ok.sum()) / max(sst["trace_seconds"], 1e-9), 1),
+               "search_p50_ms": pct(srch, 50), "search_p99_ms": pct(srch, 99), "search_p999_ms": pct(srch, 99.9),
+               "update_p50_ms": pct(upd, 50), "update_p99_ms": pct(upd, 99), "max_ms": pct(lat[ok], 100),
+               "ticks": int(sst["ticks"]), "mean_tick_requests": round(float(ok.sum()) / max(sst["ticks"], 1), 1),
+               "busy_fraction": round(sst["busy_seconds"] / max(sst["trace_seconds"], 1e-9), 3),
+               "rejected_inserts": int(sst["rejected_inserts"]), "failed_ticks": int(sst["failed_ticks"]),
+               "reclaims": int(sst["reclaims"]), "graphs": int(sst["graphs"]),
+               "peak_resident_slabs": int(sst["peak_resident_slabs"]),
+               "final_resident_slabs": int(sst["final_resident_slabs"]),
+               "tombstone_only_resident_slabs": int(sst["ids_handed_out"])}
+        out["per_rate"].append(row)
+        log(args, f"rate {rate}: {row}")
+    qs = torch.from_numpy(st.queries(1000)).to(dev)
+    gt, _ = ix.bruteforce(qs, 10)
+    gt = gt.cpu().numpy()
+    for L in (64, 128, 256):
+        ids_s, _ = ix.search(qs, 10, L)
+        out[f"recall_at_10_L{L}_end"] = round(recall(ids_s.cpu().numpy(), gt), 4)
+    last = out["per_rate"][-1]
+    out["value"] = last["search_p99_ms"]
+    out["slab_bytes_peak"] = max(r["peak_resident_slabs"] for r in out["per_rate"]) * wl.R * 8
+    out["slab_bytes_tombstone_only"] = out["per_rate"][-1]["tombstone_only_resident_slabs"] * wl.R * 8
+    out["device_bytes"] = ix.stats()["device_bytes"]
+    ix.close()
     return out
 
 
@@ -380,6 +485,9 @@ def main():
         return
     if args.workload == "batching_f32":
         print(json.dumps(run_batching(args)), flush=True)
+        return
+    if args.workload == "serving_u8":
+        print(json.dumps(run_serving(args)), flush=True)
         return
     import torch
 

@@ -142,6 +142,13 @@ def precision_f32(n_base: int = 1_000_000, rounds: int = 20, n_queries: int = 10
                     rounds, 0.01, n_queries, 10, (96,), seed, 1000, 10000)
 
 
+def serving_u8(n_base: int = 10_000_000, seed: int = 0) -> Workload:
+    """The scale mixture (128-d uint8, 1,024 clusters, sigma 18) at 10M
+    vectors, served as a request stream (see Stream.trace)."""
+    return Workload("serving_u8_10m", Mixture(128, 1024, 18.0, METRIC_L2_U8), n_base, 32, 64, 6, 5,
+                    0, 0.0, 0, 10, (64,), seed, 1000, 100_000)
+
+
 def batching_f32(n_base: int = 4_000_000, rounds: int = 50, seed: int = 0) -> Workload:
     """96-d unit-norm float32, 4,096 centers, noise 0.3, inner product, R=32,
     L=64; rounds of uneven size (see Stream.round_params)."""
@@ -174,6 +181,18 @@ class Stream:
 
     def uniform_ints(self, lo: int, hi: int, n: int) -> np.ndarray:
         return self.rng["rounds"].integers(lo, hi, size=n)
+
+    def trace(self, rate: float, seconds: float, t0: float = 0.0, p_insert: float = 0.05,
+              p_delete: float = 0.05) -> dict:
+        """Poisson arrivals at `rate` per second for `seconds`: arrival times,
+        and for each request its kind (0 search, 1 insert, 2 delete)."""
+        r = self.rng["arrivals"]
+        n_est = int(rate * seconds * 1.2) + 16
+        t = t0 + np.cumsum(r.exponential(1.0 / rate, size=n_est))
+        t = t[t < t0 + seconds]
+        u = r.random(t.size)
+        kind = np.where(u < p_insert, 1, np.where(u < p_insert + p_delete, 2, 0)).astype(np.uint32)
+        return {"t": t, "kind": kind}
 
     def round_params(self, live: int) -> dict:
         """One uneven round: churn fraction drawn from {0.1%, 1%, 5%} of the
