@@ -1498,40 +1498,60 @@ __device__ inline void pool_stage(const Index& ix, const PoolLds& p, const uint3
   wave_sync();
 }
 
-// squared distance between the pooled rows of slots a and b, by one lane
-__device__ inline uint32_t pool_dist(const PoolLds& p, uint32_t a, uint32_t b, int words) {
-  const uint4* ra = reinterpret_cast<const uint4*>(p.rows + (size_t)a * p.vstride);
-  const uint4* rb = reinterpret_cast<const uint4*>(p.rows + (size_t)b * p.vstride);
-  uint32_t dot = 0;
-  for (int w = 0; w < words; ++w) dot = dot16(ra[w], rb[w], dot);
-  return p.norm[a] + p.norm[b] - 2u * dot;
+// 64-lane bitonic sort of (key, value) pairs held one per lane, ascending
+__device__ inline void lane_bitonic_sort(uint64_t& key, uint32_t& val) {
+  const int l = lane_id();
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t olo = (uint32_t)__shfl_xor((int)(uint32_t)key, j, 64);
+      const uint32_t ohi = (uint32_t)__shfl_xor((int)(uint32_t)(key >> 32), j, 64);
+      const uint32_t ov = (uint32_t)__shfl_xor((int)val, j, 64);
+      const uint64_t ok = ((uint64_t)ohi << 32) | olo;
+      const bool up = (l & k) == 0, lower = (l & j) == 0;
+      const bool take = lower == up ? ok < key : ok > key;
+      if (take) {
+        key = ok;
+        val = ov;
+      }
+    }
+  }
 }
 
-// RobustPrune(self, candidate slots cs[0..m)) into out[0..return); m <= 64
+// RobustPrune(self, candidate slots cs[0..m)) into out[0..return); m <= 64.
+// Candidates are ranked in registers (one per lane); during the selection each
+// lane keeps its own candidate's row in registers and reads the kept one.
+template <int G>
 __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const uint32_t* cs, uint32_t m,
                                       uint32_t self, uint32_t* out) {
   const int l = lane_id();
-  const int words = (int)ix.dim / 16;
-  const uint32_t my = (uint32_t)l < m ? cs[l] : 0u;
-  const uint32_t myid = (uint32_t)l < m ? p.id[my] : NONE;
-  bool valid = (uint32_t)l < m && myid != self && p.dead[my] == 0u;
-  for (uint32_t j = 0; j < (uint32_t)l && j < m; ++j) {  // of repeated ids the first copy stays
-    const uint32_t sj = cs[j];
-    if (p.id[sj] == myid && p.id[sj] != self && p.dead[sj] == 0u) valid = false;
+  uint32_t slot = (uint32_t)l < m ? cs[l] : 0u;
+  uint64_t key = KEY_NONE;
+  if ((uint32_t)l < m) {
+    const uint32_t id = p.id[slot];
+    if (id != self && p.dead[slot] == 0u) key = make_key(p.dw[slot], id);
   }
-  const uint64_t vm = ballot(valid);
-  const uint64_t mykey = make_key(p.dw[my], myid);
-  uint32_t rank = 0;  // keys of the surviving candidates are distinct
-  for (uint32_t j = 0; j < m; ++j)
-    if (((vm >> j) & 1ull) && make_key(p.dw[cs[j]], p.id[cs[j]]) < mykey) ++rank;
+  lane_bitonic_sort(key, slot);
+  // repeated ids are adjacent with equal keys: one copy stays
+  const uint64_t prev_lo = (uint32_t)__shfl_up((int)(uint32_t)key, 1, 64);
+  const uint64_t prev_hi = (uint32_t)__shfl_up((int)(uint32_t)(key >> 32), 1, 64);
+  const bool keep = key != KEY_NONE && (l == 0 || ((prev_hi << 32) | prev_lo) != key);
+  const uint64_t km = ballot(keep);
   wave_sync();
-  if (valid) p.sorted[rank] = my;
+  if (keep) p.sorted[lanes_below(km)] = slot;
   wave_sync();
-  uint32_t mm = (uint32_t)__popcll(vm);
+  uint32_t mm = (uint32_t)__popcll(km);
   const uint32_t cap = ix.prune_cap < POOL ? ix.prune_cap : POOL;
   if (mm > cap) mm = cap;
   const uint32_t csl = (uint32_t)l < mm ? p.sorted[l] : 0u;
   const uint32_t cdw = (uint32_t)l < mm ? p.dw[csl] : 0u;
+  const uint32_t cn = p.norm[csl];
+  constexpr int GR = G <= 16 ? G : 1;  // rows of up to 256 bytes stay in registers
+  uint4 rv[GR];
+  const uint4* rc = reinterpret_cast<const uint4*>(p.rows + (size_t)csl * p.vstride);
+#pragma unroll
+  for (int w = 0; w < GR; ++w) rv[w] = rc[w];
   uint64_t alive = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
   uint32_t cnt = 0, from = 0, keep_slot = 0;
   while (cnt < ix.R) {
@@ -1543,11 +1563,17 @@ __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const u
     ++cnt;
     from = j + 1;
     if (cnt == ix.R) break;
-    bool kill = false;
-    if ((uint32_t)l > j && ((alive >> l) & 1ull)) {
-      const uint32_t d = pool_dist(p, sj, csl, words);
-      kill = (uint64_t)ix.a2 * d <= (uint64_t)ix.b2 * (uint64_t)cdw;
+    const uint4* rj = reinterpret_cast<const uint4*>(p.rows + (size_t)sj * p.vstride);
+    uint32_t dot = 0;
+    if constexpr (G <= 16) {
+#pragma unroll
+      for (int w = 0; w < G; ++w) dot = dot16(rv[w], rj[w], dot);
+    } else {
+      for (int w = 0; w < G; ++w) dot = dot16(rc[w], rj[w], dot);
     }
+    const uint32_t d = p.norm[sj] + cn - 2u * dot;
+    const bool kill = (uint32_t)l > j && ((alive >> l) & 1ull) &&
+                      (uint64_t)ix.a2 * d <= (uint64_t)ix.b2 * (uint64_t)cdw;
     alive &= ~ballot(kill);
   }
   wave_sync();
@@ -1605,7 +1631,7 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
       pool_stage<G>(ix, p, fs, __popcll(fm), wf, ww);
     }
     // K = RobustPrune(a, B)
-    const uint32_t kc = pool_prune(ix, p, p.cand, (uint32_t)__popcll(om), an, p.kept);
+    const uint32_t kc = pool_prune<G>(ix, p, p.cand, (uint32_t)__popcll(om), an, p.kept);
     // N = RobustPrune(a, (N \ {u}) U K)
     const uint32_t ks = (uint32_t)l < kc ? p.kept[l] : 0u;
     const uint32_t ls = (uint32_t)l < n ? p.list[l] : 0u;
@@ -1616,7 +1642,7 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
     if (stay) p.cand[lanes_below(sm)] = ls;
     if ((uint32_t)l < kc) p.cand[ns + (uint32_t)l] = ks;
     wave_sync();
-    n = pool_prune(ix, p, p.cand, ns + kc, an, p.list);
+    n = pool_prune<G>(ix, p, p.cand, ns + kc, an, p.list);
     // slots not on the new list become free
     used = 0;
     for (uint32_t k = 0; k < n; ++k) used |= 1ull << p.list[k];
