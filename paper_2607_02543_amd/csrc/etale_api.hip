@@ -49,6 +49,8 @@ struct etale_index {
   uint32_t* scan_n = nullptr;
   uint32_t* scan_dist = nullptr;  // [dist_cap] query x start-set distances
   uint64_t dist_cap = 0;
+  uint32_t* scan_gmin = nullptr;  // [gmin_cap] per-query group minima of those distances
+  uint64_t gmin_cap = 0;
   uint32_t scan_chunk = 0;
   uint64_t live = 0;
   int32_t qtrav = 0;              // query-side traversal copy
@@ -190,6 +192,7 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
     sc.ns = ns;
     sc.ns_ctr = C_N_ENTRIES;
     sc.dist = ix->scan_dist;
+    sc.gmin = ix->scan_gmin;
     sc.out_keys = ix->scan_keys;
     sc.out_n = ix->scan_n;
     sc.out_stride = L;
@@ -259,6 +262,7 @@ etale_status run_bootstrap(etale_index* ix, uint32_t nmax, uint32_t vcap, Dyn ba
     sc.ns = ns;
     sc.ns_ctr = C_R_NINS;
     sc.dist = ix->scan_dist;
+    sc.gmin = ix->scan_gmin;
     sc.out_keys = ix->vis_keys + (size_t)c * vcap;
     sc.out_n = ix->vis_cnt + c;
     sc.out_stride = vcap;
@@ -555,6 +559,9 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   ALLOC(ix->scan_n, (uint64_t)ix->scan_chunk * 4);
   ix->dist_cap = std::min<uint64_t>(1ull << 27, std::max<uint64_t>((uint64_t)ix->scan_chunk * c.n_entry, B * 4096));
   ALLOC(ix->scan_dist, ix->dist_cap * 4);
+  // a chunk of n queries over ns start rows has at most n (ns / 32 + 8) group slots
+  ix->gmin_cap = ix->dist_cap / 32 + 8ull * ix->scan_chunk;
+  ALLOC(ix->scan_gmin, ix->gmin_cap * 4);
   ALLOC(ix->seg, B * R * 4);
   ALLOC(ix->hist, (uint64_t)sort_hist_words((uint32_t)(B * R)) * 4);
   ALLOC(ix->status, 16);

@@ -179,12 +179,11 @@ __global__ void __launch_bounds__(1024) k_refresh_entries(Index ix, uint32_t nex
 // ---- start-set scoring: the L best start nodes of every query --------------------------
 // The start set (the entry set, or the batch itself for a bootstrap) is the
 // same for every query of a launch, so scoring it is one dense block of
-// distances: k_scan_dist tiles 64 queries x 256 start rows per workgroup
-// (8 x 8 distances per thread, the byte dimension staged through LDS in
-// 64-byte slices) and writes the distance matrix; k_scan_select then takes,
-// with one wave per query, the exact L smallest (distance, id) keys by a
-// radix select on the distances. Start rows are in ascending id order, so the
-// row index breaks distance ties exactly as the id does.
+// distances: k_scan_dist (uint8 rows, on the matrix cores) and k_scan_dist_f
+// (float rows, 64 queries x 256 start rows per workgroup staged through LDS)
+// write the distance matrix; k_scan_select then takes, with one wave per
+// query, the exact L smallest (distance, id) keys. Start rows are in ascending
+// id order, so the row index breaks distance ties exactly as the id does.
 constexpr int SD_Q = 64, SD_E = 256, SD_KW = 4, SD_STRIDE = SD_KW + 1;  // in 16-byte words
 constexpr uint32_t D_INVALID = 0xFFFFFFFFu;
 
@@ -201,88 +200,126 @@ __device__ inline void resolve(const Index& ix, ScanArgs& a) {
   if (a.ns_ctr != NO_CTR) a.ns = (uint32_t)min<uint64_t>(a.ns, ix.ctr[a.ns_ctr]);
 }
 
-__device__ inline void scan_dist_tile(const Index& ix, const ScanArgs& a, uint32_t e0, uint32_t q0, uint4* qt,
-                                      uint4* et, uint32_t* qn_s, uint32_t* en_s) {
-  const int t = (int)threadIdx.x;
-  const uint32_t ns = a.ns, dim = ix.dim;
-  const int words = (int)dim / 16;
-  const int qg = t / 32, eg = t % 32;
-  uint32_t acc[8][8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = 0;
-  uint32_t qn = 0, en = 0;  // norms of query row t (t < 64) and start row t
-  const uint32_t my_e = e0 + (uint32_t)t;
-  const uint32_t my_eid = my_e < ns ? start_id(ix, a, my_e) : NONE;
-  const uint32_t my_q = q0 + (uint32_t)(t & 63);
-  const uint8_t* qrow = nullptr;
-  if (my_q < a.nq)
-    qrow = a.mode == MODE_QUERY ? (const uint8_t*)a.q + (size_t)my_q * dim
-                                : ix.x + (size_t)(a.first + a.qoff + my_q) * dim;
-  for (int kw = 0; kw < words; kw += SD_KW) {
-    __syncthreads();
-    // query slice: 64 rows x 4 words, one word per thread
-    {
-      const int r = t & 63, c = t >> 6;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (qrow && kw + c < words) v = reinterpret_cast<const uint4*>(qrow)[kw + c];
-      qt[r * SD_STRIDE + c] = v;
-    }
-    // start slice: 256 rows x 4 words, this thread's own row
-#pragma unroll
-    for (int c = 0; c < SD_KW; ++c) {
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (my_eid != NONE && kw + c < words) v = reinterpret_cast<const uint4*>(ix.x + (size_t)my_eid * dim)[kw + c];
-      et[t * SD_STRIDE + c] = v;
-      en = dot16(v, v, en);
-    }
-    __syncthreads();
-    if (t < 64)
-#pragma unroll
-      for (int c = 0; c < SD_KW; ++c) qn = dot16(qt[t * SD_STRIDE + c], qt[t * SD_STRIDE + c], qn);
-#pragma unroll
-    for (int c = 0; c < SD_KW; ++c) {
-      uint4 qv[8], ev[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) qv[i] = qt[(qg * 8 + i) * SD_STRIDE + c];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) ev[j] = et[(eg + 32 * j) * SD_STRIDE + c];
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = dot16(qv[i], ev[j], acc[i][j]);
-    }
+// uint8 rows on the matrix cores: every byte is shifted to a signed value
+// (x - 128, an XOR with 0x80), which leaves every difference and so every
+// squared distance unchanged, and d = |q'|^2 + |e'|^2 - 2 q'.e' is exact in
+// int32. One wave scores 64 start rows x 64 queries as 4 x 4 tiles of
+// v_mfma_i32_16x16x64_i8 (start rows as the M operand, queries as N), one
+// 64-byte slice of the rows per step; the operands are read straight from
+// memory (the start rows stay in L2 across the query tiles). In the result
+// tile lane l holds query l % 16 and the four start rows 4 (l / 16) + i, so
+// each lane stores 16 contiguous bytes of its query's distance row.
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+constexpr int SD_WT = 64;  // start rows and queries per wave tile
+
+__device__ inline v4i32 signed_frag(const uint8_t* row, uint32_t off, uint32_t dim) {
+  v4i32 f = {0, 0, 0, 0};
+  if (row && off < dim) {
+    const uint4 w = *reinterpret_cast<const uint4*>(row + off);
+    f = v4i32{(int)(w.x ^ 0x80808080u), (int)(w.y ^ 0x80808080u), (int)(w.z ^ 0x80808080u),
+              (int)(w.w ^ 0x80808080u)};
   }
-  if (t < 64) qn_s[t] = qn;
-  en_s[t] = en;
-  __syncthreads();
+  return f;
+}
+
+__device__ inline int frag_sq(v4i32 f) {
+  int s = __builtin_amdgcn_sdot4(f.x, f.x, 0, false);
+  s = __builtin_amdgcn_sdot4(f.y, f.y, s, false);
+  s = __builtin_amdgcn_sdot4(f.z, f.z, s, false);
+  return __builtin_amdgcn_sdot4(f.w, f.w, s, false);
+}
+
+__device__ inline void scan_dist_wave_tile(const Index& ix, const ScanArgs& a, uint32_t e0, uint32_t q0) {
+  const int l = lane_id();
+  const uint32_t ns = a.ns, dim = ix.dim, r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u;
+  const uint8_t* erow[4];
+  const uint8_t* qrow[4];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const uint32_t qi = q0 + (uint32_t)(qg * 8 + i);
-    if (qi >= a.nq) continue;
-    const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;  // a bootstrap row never scores itself
+  for (int m = 0; m < 4; ++m) {
+    const uint32_t e = e0 + (uint32_t)m * 16u + r;
+    erow[m] = e < ns ? ix.x + (size_t)start_id(ix, a, e) * dim : nullptr;
+    const uint32_t q = q0 + (uint32_t)m * 16u + r;
+    qrow[m] = q >= a.nq ? nullptr
+              : a.mode == MODE_QUERY ? (const uint8_t*)a.q + (size_t)q * dim
+                                     : ix.x + (size_t)(a.first + a.qoff + q) * dim;
+  }
+  v4i32 acc[4][4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const uint32_t e = e0 + (uint32_t)(eg + 32 * j);
-      if (e >= ns) continue;
-      const uint32_t d = qn_s[qg * 8 + i] + en_s[eg + 32 * j] - 2u * acc[i][j];
-      a.dist[(size_t)qi * ns + e] = e == self ? D_INVALID : d;
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[m][n] = v4i32{0, 0, 0, 0};
+  int en[4] = {0, 0, 0, 0}, qn[4] = {0, 0, 0, 0};
+  for (uint32_t k0 = 0; k0 < dim; k0 += 64) {
+    v4i32 ef[4], qf[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ef[m] = signed_frag(erow[m], k0 + kc, dim);
+      qf[m] = signed_frag(qrow[m], k0 + kc, dim);
     }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      en[m] += frag_sq(ef[m]);
+      qn[m] += frag_sq(qf[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ef[m], qf[n], acc[m][n], 0, 0, 0);
+  }
+  // full squared norms: lane l then holds start row m*16 + l%16 and query n*16 + l%16
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    en[m] += __shfl_xor(en[m], 16, 64);
+    en[m] += __shfl_xor(en[m], 32, 64);
+    qn[m] += __shfl_xor(qn[m], 16, 64);
+    qn[m] += __shfl_xor(qn[m], 32, 64);
+  }
+  const uint32_t rb = (uint32_t)(l >> 4) * 4u;  // first of this lane's four start rows within a 16-row tile
+  const bool vec = (ns & 3u) == 0;
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const uint32_t qi = q0 + (uint32_t)n * 16u + r;
+    const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;  // a bootstrap row never scores itself
+    uint32_t g[2] = {D_INVALID, D_INVALID};  // minima of start rows [e0, e0 + 32) and [e0 + 32, e0 + 64)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      uint32_t d[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e_n = __shfl(en[m], (int)rb + i, 64);
+        const uint32_t e = e0 + (uint32_t)m * 16u + rb + (uint32_t)i;
+        d[i] = e == self || e >= ns ? D_INVALID : (uint32_t)(qn[n] + e_n - 2 * acc[m][n][i]);
+        g[m >> 1] = min(g[m >> 1], d[i]);
+      }
+      if (qi >= a.nq) continue;
+      const uint32_t e = e0 + (uint32_t)m * 16u + rb;
+      uint32_t* out = a.dist + (size_t)qi * ns + e;
+      if (vec && e + 3 < ns) {
+        *reinterpret_cast<uint4*>(out) = make_uint4(d[0], d[1], d[2], d[3]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (e + (uint32_t)i < ns) out[i] = d[i];
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      g[h] = min(g[h], (uint32_t)__shfl_xor((int)g[h], 16, 64));
+      g[h] = min(g[h], (uint32_t)__shfl_xor((int)g[h], 32, 64));
+    }
+    // lanes 0-15 write group 0, lanes 16-31 group 1 (group slots 2 per 64-row tile)
+    if (qi < a.nq && l < 32) a.gmin[(size_t)qi * a.g_stride + (e0 >> 5) + (uint32_t)(l >> 4)] = l < 16 ? g[0] : g[1];
   }
 }
 
 __global__ void __launch_bounds__(256) k_scan_dist(Index ix, ScanArgs a) {
-  __shared__ uint4 qt[SD_Q * SD_STRIDE];
-  __shared__ uint4 et[SD_E * SD_STRIDE];
-  __shared__ uint32_t qn_s[SD_Q], en_s[SD_E];
   if (gated(ix, a.d)) return;
   resolve(ix, a);
-  const uint32_t n_et = (a.ns + SD_E - 1) / SD_E, n_tiles = n_et * ((a.nq + SD_Q - 1) / SD_Q);
-  for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    __syncthreads();
-    scan_dist_tile(ix, a, (tile % n_et) * SD_E, (tile / n_et) * SD_Q, qt, et, qn_s, en_s);
-  }
+  const uint32_t n_et = (a.ns + SD_WT - 1) / SD_WT, n_tiles = n_et * ((a.nq + SD_WT - 1) / SD_WT);
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  // consecutive waves take consecutive start tiles of one query tile
+  for (uint32_t tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < n_tiles; tile += waves)
+    scan_dist_wave_tile(ix, a, (tile % n_et) * SD_WT, (tile / n_et) * SD_WT);
 }
 
 // Float rows: the same 64 x 256 tiling over 16-element slices, in FP32; start
@@ -366,18 +403,25 @@ __device__ inline void scan_dist_f_tile(const Index& ix, const ScanArgs& a, uint
     }
   }
   __syncthreads();
+  // group minima: the 32 start rows e0 + 4 (eg / 4) + {0..3} + 32 j form group
+  // e0 / 32 + eg / 4 (8 group slots per 256-row tile), reduced over the four
+  // adjacent threads that hold them
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const uint32_t qi = q0 + (uint32_t)(qg * 8 + i);
-    if (qi >= a.nq) continue;
     const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;
+    uint32_t g = D_INVALID;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const uint32_t e = e0 + (uint32_t)(eg + 32 * j);
-      if (e >= ns) continue;
       const float d = 1.0f - es[eg + 32 * j] * acc[i][j];
-      a.dist[(size_t)qi * ns + e] = e == self ? D_INVALID : fkey(d);
+      const uint32_t key = e == self || e >= ns ? D_INVALID : fkey(d);
+      g = min(g, key);
+      if (qi < a.nq && e < ns) a.dist[(size_t)qi * ns + e] = key;
     }
+    g = min(g, (uint32_t)__shfl_xor((int)g, 1, 64));
+    g = min(g, (uint32_t)__shfl_xor((int)g, 2, 64));
+    if (qi < a.nq && (eg & 3) == 0) a.gmin[(size_t)qi * a.g_stride + (e0 >> 5) + (uint32_t)(eg >> 2)] = g;
   }
 }
 
@@ -396,114 +440,168 @@ __global__ void __launch_bounds__(256) k_scan_dist_f(Index ix, ScanArgs a) {
 }
 
 // One wave per query: the exact L smallest (distance, row) pairs of its
-// distance row, by a most-significant-digit radix select on the distance
-// (8-bit digits from the highest set bit), then the rows below the threshold
-// plus the first rows (in row order) equal to it, sorted. The row is held in
-// registers (VPL values per lane, row i in lane i % 64, slot i / 64).
-template <int VPL>
-__device__ inline void scan_select_one(const Index& ix, const ScanArgs& a, uint32_t qi, uint32_t* hist,
-                                       uint64_t* sel) {
+// distance row. The scoring kernels leave, per query, the smallest distance of
+// every group of 32 start rows. If at least L groups hold a valid row, the L-th
+// smallest group minimum b bounds the L-th smallest distance from above (the L
+// groups at or below b each hold a row at or below it). One pass over the row
+// compacts every row at or below b, as a (distance, row) key, to LDS; a
+// bitonic sort then puts the answer first. Should more than `cap` rows lie at
+// or below b (ties, or no bound), bisection over the row, counting with
+// ballots, lowers the bound until they fit; if more than `cap` rows tie at the
+// L-th value itself, the rows below it plus the first ones (in row order)
+// equal to it are taken. Rows ascend with ids, so (distance, row) sorts as
+// (distance, id); ids are looked up at the end.
+constexpr uint32_t SEL_COMPACT = 512;  // rows compacted per query
+constexpr int SEL_GPL = 8;             // group minima per lane: up to 512 groups (16,384 start rows)
+constexpr int SEL_CH = 8;              // row values per lane per step of a pass
+
+// rows of D at or below hi, counted
+__device__ inline uint32_t sel_count(const uint32_t* D, uint32_t ns, uint32_t hi) {
+  const int l = lane_id();
+  uint32_t c = 0;
+  for (uint32_t base = 0; base < ns; base += 64 * SEL_CH) {
+    uint32_t v[SEL_CH];
+#pragma unroll
+    for (int t = 0; t < SEL_CH; ++t) {
+      const uint32_t i = base + (uint32_t)(t * 64 + l);
+      v[t] = i < ns ? D[i] : D_INVALID;
+    }
+#pragma unroll
+    for (int t = 0; t < SEL_CH; ++t) c += (uint32_t)__popcll(ballot(v[t] <= hi));
+  }
+  return c;
+}
+
+// keys of the rows at or below hi, in row order, the first `cap` of them
+// written; returns their number (may exceed cap)
+__device__ inline uint32_t sel_compact(const uint32_t* D, uint32_t ns, uint32_t hi, uint64_t* sel, uint32_t cap,
+                                       uint32_t* lmin) {
+  const int l = lane_id();
+  uint32_t n = 0, mn = D_INVALID;
+  for (uint32_t base = 0; base < ns; base += 64 * SEL_CH) {
+    uint32_t v[SEL_CH];
+#pragma unroll
+    for (int t = 0; t < SEL_CH; ++t) {
+      const uint32_t i = base + (uint32_t)(t * 64 + l);
+      v[t] = i < ns ? D[i] : D_INVALID;
+    }
+#pragma unroll
+    for (int t = 0; t < SEL_CH; ++t) {
+      mn = min(mn, v[t]);
+      const bool in = v[t] <= hi;
+      const uint64_t m = ballot(in);
+      const uint32_t pos = n + lanes_below(m);
+      if (in && pos < cap) sel[pos] = make_key(v[t], base + (uint32_t)(t * 64 + l));
+      n += (uint32_t)__popcll(m);
+    }
+  }
+  *lmin = mn;
+  return n;
+}
+
+__device__ inline void scan_select_one(const Index& ix, const ScanArgs& a, uint32_t qi, uint64_t* sel, uint32_t cap) {
   const int l = lane_id();
   const uint32_t ns = a.ns;
   const uint32_t* D = a.dist + (size_t)qi * ns;
-  uint32_t v[VPL];
-  uint32_t vmax = 0, nvalid = 0;
+  const bool self_in = a.mode == MODE_BOOT && a.qoff + qi < ns;  // the one row scored D_INVALID
+  const uint32_t need_all = min(a.L, ns - (self_in ? 1u : 0u));
+  uint32_t cnt = 0;
+  if (need_all > 0) {
+    // the bound from the group minima
+    const uint32_t ng = (ns + a.g_rows - 1) / a.g_rows * (a.g_rows / 32);
+    const uint32_t* G = a.gmin + (size_t)qi * a.g_stride;
+    uint32_t gv[SEL_GPL];
+    uint32_t glo = D_INVALID, ghi = 0, gvalid = 0;
 #pragma unroll
-  for (int t = 0; t < VPL; ++t) {
-    const uint32_t i = (uint32_t)(t * 64 + l);
-    v[t] = i < ns ? D[i] : D_INVALID;
-    if (v[t] != D_INVALID) {
-      vmax = max(vmax, v[t]);
-      ++nvalid;
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, o, 64));
-    nvalid += (uint32_t)__shfl_xor((int)nvalid, o, 64);
-  }
-  uint32_t need = min(a.L, nvalid);
-  uint32_t prefix = 0, pmask = 0;
-  if (need > 0) {
-    for (int hi = 31 - __clz((int)(vmax | 1u)); hi >= 0; hi -= 8) {
-      const int lo = max(0, hi - 7), width = hi - lo + 1;
-      const uint32_t dmask = (1u << width) - 1u;
-      for (int b = l; b < 256; b += 64) hist[b] = 0;
-      wave_sync();
-#pragma unroll
-      for (int t = 0; t < VPL; ++t)
-        if (v[t] != D_INVALID && (v[t] & pmask) == prefix) atomicAdd(&hist[(v[t] >> lo) & dmask], 1u);
-      wave_sync();
-      // the digit whose cumulative count first reaches `need`
-      uint32_t c0 = hist[4 * l], c1 = hist[4 * l + 1], c2 = hist[4 * l + 2], c3 = hist[4 * l + 3];
-      const uint32_t own = c0 + c1 + c2 + c3;
-      uint32_t incl = own;
-      for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
-        if (l >= o) incl += u;
+    for (int t = 0; t < SEL_GPL; ++t) {
+      const uint32_t i = (uint32_t)(t * 64 + l);
+      gv[t] = i < ng ? G[i] : D_INVALID;
+      if (gv[t] != D_INVALID) {
+        glo = min(glo, gv[t]);
+        ghi = max(ghi, gv[t]);
+        ++gvalid;
       }
-      const uint32_t excl = incl - own;
-      const bool here = excl < need && incl >= need;
-      uint32_t digit = 0, before = 0;
-      if (here) {
-        uint32_t run = excl;
-        if (run + c0 >= need) {
-          digit = 4 * l;
-        } else if ((run += c0) + c1 >= need) {
-          digit = 4 * l + 1;
-        } else if ((run += c1) + c2 >= need) {
-          digit = 4 * l + 2;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      glo = min(glo, (uint32_t)__shfl_xor((int)glo, o, 64));
+      ghi = max(ghi, (uint32_t)__shfl_xor((int)ghi, o, 64));
+      gvalid += (uint32_t)__shfl_xor((int)gvalid, o, 64);
+    }
+    uint32_t hi = D_INVALID - 1;  // no bound: every valid row
+    if (bcast(gvalid) >= need_all) {
+      uint32_t lo = bcast(glo);
+      hi = bcast(ghi);
+      while (lo < hi) {  // the need_all-th smallest group minimum
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        uint32_t c = 0;
+#pragma unroll
+        for (int t = 0; t < SEL_GPL; ++t) c += (uint32_t)__popcll(ballot(gv[t] <= mid));
+        if (c >= need_all) hi = mid;
+        else lo = mid + 1;
+      }
+    }
+    uint32_t lmin;
+    cnt = sel_compact(D, ns, hi, sel, cap, &lmin);
+    if (cnt > cap) {
+      // invariant: #{v < lo} < need_all <= #{v <= hi} = cnt
+      for (int o = 32; o > 0; o >>= 1) lmin = min(lmin, (uint32_t)__shfl_xor((int)lmin, o, 64));
+      uint32_t lo = bcast(lmin);
+      while (cnt > cap && lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        const uint32_t c = sel_count(D, ns, mid);
+        if (c >= need_all) {
+          hi = mid;
+          cnt = c;
         } else {
-          run += c2;
-          digit = 4 * l + 3;
+          lo = mid + 1;
         }
-        before = run;
       }
-      const uint64_t hm = ballot(here);
-      const int src = (int)__builtin_ctzll(hm);
-      digit = (uint32_t)__shfl((int)digit, src, 64);
-      before = (uint32_t)__shfl((int)before, src, 64);
-      need -= before;
-      prefix |= digit << lo;
-      pmask |= dmask << lo;
       wave_sync();
+      if (cnt <= cap) {
+        cnt = sel_compact(D, ns, hi, sel, cap, &lmin);
+      } else {
+        // more than cap rows share the value tau = lo = hi
+        const uint32_t need = need_all - (lo ? sel_count(D, ns, lo - 1) : 0u);
+        uint32_t eq_seen = 0;
+        cnt = 0;
+        for (uint32_t base = 0; base < ns; base += 64) {
+          const uint32_t i = base + (uint32_t)l;
+          const uint32_t v = i < ns ? D[i] : D_INVALID;
+          const bool eq = v == lo;
+          const uint64_t meq = ballot(eq);
+          const bool take = v < lo || (eq && eq_seen + lanes_below(meq) < need);
+          const uint64_t mt = ballot(take);
+          if (take) sel[cnt + lanes_below(mt)] = make_key(v, i);
+          cnt += (uint32_t)__popcll(mt);
+          eq_seen += (uint32_t)__popcll(meq);
+        }
+      }
     }
-  }
-  // rows below the threshold, then the first `need` rows equal to it
-  const uint32_t tau = prefix;
-  uint32_t cnt = 0, eq_seen = 0;
-#pragma unroll
-  for (int t = 0; t < VPL; ++t) {
-    const uint32_t i = (uint32_t)(t * 64 + l);
-    const bool lt = v[t] != D_INVALID && v[t] < tau;
-    const bool eq = v[t] != D_INVALID && v[t] == tau;
-    const uint64_t meq = ballot(eq);
-    const bool take = lt || (eq && eq_seen + lanes_below(meq) < need);
-    const uint64_t mt = ballot(take);
-    if (take) sel[cnt + lanes_below(mt)] = make_key(v[t], start_id(ix, a, i));
-    cnt += (uint32_t)__popcll(mt);
-    eq_seen += (uint32_t)__popcll(meq);
   }
   const int np = next_pow2_ge64((int)cnt);
   for (int i = (int)cnt + l; i < np; i += 64) sel[i] = KEY_NONE;
   wave_sync();
   wave_bitonic_sort(sel, np);
-  for (uint32_t i = (uint32_t)l; i < cnt; i += 64) a.out_keys[(size_t)qi * a.out_stride + i] = sel[i];
+  cnt = min(cnt, need_all);
+  for (uint32_t i = (uint32_t)l; i < cnt; i += 64) {
+    const uint64_t k = sel[i];
+    a.out_keys[(size_t)qi * a.out_stride + i] = make_key(key_dist(k), start_id(ix, a, key_id(k)));
+  }
   if (l == 0) a.out_n[qi] = cnt;
 }
 
-template <int VPL>
 __global__ void __launch_bounds__(256) k_scan_select(Index ix, ScanArgs a, uint32_t sel_cap) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, a.d)) return;
   resolve(ix, a);
-  // one wave per query (the value registers leave no room for a loop)
   const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (qi >= a.nq) return;
-  uint32_t* hist = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * (1024 + 8 * sel_cap));
-  scan_select_one<VPL>(ix, a, qi, hist, reinterpret_cast<uint64_t*>(hist + 256));
+  scan_select_one(ix, a, qi, reinterpret_cast<uint64_t*>(smem + (size_t)(threadIdx.x >> 6) * 8 * sel_cap), sel_cap);
 }
 
-uint32_t scan_select_lds_per_wave(uint32_t L) { return 1024u + 8u * (uint32_t)next_pow2_ge64((int)L); }
+// keys per wave: the compacted rows, or the L selected ones
+uint32_t scan_select_keys(uint32_t L) { return (uint32_t)max((int)SEL_COMPACT, next_pow2_ge64((int)L)); }
+uint32_t scan_select_lds_per_wave(uint32_t L) { return 8u * scan_select_keys(L); }
 
 // ---- traversal policies ------------------------------------------------------------
 // uint8 rows: G = dim/16 lanes per row, one 16-byte chunk each
@@ -2176,13 +2274,20 @@ uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots) {
 // lanes per row of a float copy: 3 chunks of 16 bytes per lane
 static inline int float_lanes(uint32_t dim, int elem_bytes) { return (int)(dim * (uint32_t)elem_bytes / 16u / 3u); }
 
-hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEvent_t after_dist) {
-  if (a.nq == 0) return hipSuccess;
+hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hipEvent_t after_dist) {
+  if (args.nq == 0) return hipSuccess;
+  ScanArgs a = args;
+  a.g_rows = ix.metric == 0 ? (uint32_t)SD_WT : (uint32_t)SD_E;
+  a.g_stride = blocks_for(a.ns ? a.ns : 1u, a.g_rows) * (a.g_rows / 32);
   // shapes from the upper bounds; the kernels resolve the launch-time counts
   const uint64_t tiles = (uint64_t)blocks_for(a.ns ? a.ns : 1u, SD_E) * blocks_for(a.nq, SD_Q);
   const dim3 dgrid(tiles < 2 * PERSIST_BLOCKS ? (unsigned)tiles : 2 * PERSIST_BLOCKS);
   if (ix.metric == 0) {
-    hipLaunchKernelGGL(k_scan_dist, dgrid, dim3(256), 0, s, ix, a);
+    // one 64 x 64 tile per wave, four waves per workgroup
+    const uint64_t wt = (uint64_t)blocks_for(a.ns ? a.ns : 1u, SD_WT) * blocks_for(a.nq, SD_WT);
+    const uint64_t wg = (wt + 3) / 4;
+    hipLaunchKernelGGL(k_scan_dist, dim3(wg < 4 * PERSIST_BLOCKS ? (unsigned)wg : 4 * PERSIST_BLOCKS), dim3(256), 0, s,
+                       ix, a);
   } else {
     const int trav = a.mode == MODE_BOOT ? TRAV_NATIVE : a.trav;
     if (trav == TRAV_NATIVE)
@@ -2196,22 +2301,11 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEve
     const hipError_t e = hipEventRecord(after_dist, s);
     if (e != hipSuccess) return e;
   }
-  const uint32_t cap = (uint32_t)next_pow2_ge64((int)a.L);
+  const uint32_t cap = scan_select_keys(a.L);
   const dim3 grid(blocks_for(a.nq, 4)), blk(256);
   const size_t lds = 4 * scan_select_lds_per_wave(a.L);
-  const uint32_t vpl = (a.ns + 63) / 64;
-  if (vpl <= 16)
-    hipLaunchKernelGGL(k_scan_select<16>, grid, blk, lds, s, ix, a, cap);
-  else if (vpl <= 32)
-    hipLaunchKernelGGL(k_scan_select<32>, grid, blk, lds, s, ix, a, cap);
-  else if (vpl <= 64)
-    hipLaunchKernelGGL(k_scan_select<64>, grid, blk, lds, s, ix, a, cap);
-  else if (vpl <= 128)
-    hipLaunchKernelGGL(k_scan_select<128>, grid, blk, lds, s, ix, a, cap);
-  else if (vpl <= 256)
-    hipLaunchKernelGGL(k_scan_select<256>, grid, blk, lds, s, ix, a, cap);
-  else
-    return hipErrorInvalidValue;
+  if (a.ns > SEL_GPL * 64 * 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan_select, grid, blk, lds, s, ix, a, cap);
   return hipGetLastError();
 }
 

@@ -42,6 +42,9 @@ struct ScanArgs {
   int32_t trav;        // float rows: traversal copy the start rows are read from
   uint32_t ns;         // start-set size (entry count, or the batch size for a bootstrap)
   uint32_t* dist;      // [nq x ns] scratch distance matrix
+  uint32_t* gmin;      // [nq x g_stride] smallest distance of each group of start rows
+  uint32_t g_stride;   // group slots per query (upper bound over the launch-time ns)
+  uint32_t g_rows;     // start rows per scoring tile; each tile has g_rows / 32 group slots
   uint64_t* out_keys;  // [nq x out_stride]
   uint32_t* out_n;     // [nq]
   uint32_t out_stride;

@@ -96,3 +96,50 @@ def test_parity_knob_invariance():
 def test_parity_two_expansions_per_iteration():
     # W = 2: two slabs read side by side by one wavefront
     run_parity(small_workload(seed=6, rounds=2), W=2, search_L=(16, 64, 101))
+
+
+def test_parity_heavy_ties():
+    # Two distinct vectors repeated (a tenth of the rows nudged by one or two
+    # units): most distances tie, so more start rows lie at or below the
+    # selection bound than fit in LDS, and the initial lists come from the
+    # bisection and tie paths of the start-set selection.
+    torch = _torch()
+    wl = small_workload(n_base=3000, seed=8, batch=1500, rounds=1, dim=32)
+    p = index_params(wl, n_entry=2048)
+    o, g = make_oracle(p), make_gpu(p)
+    rng = np.random.default_rng(8)
+    pats = rng.integers(0, 256, size=(2, 32), dtype=np.uint8)
+
+    def rows(n):
+        x = pats[rng.integers(0, 2, size=n)].copy()
+        m = rng.random(n) < 0.1
+        x[m, 0] ^= rng.integers(1, 3, size=int(m.sum())).astype(np.uint8)
+        return x
+
+    def check_search(where):
+        q = rows(100)
+        for L in (16, 64):
+            io, do = o.search(q, 10, L)
+            ig, dgpu = g.search(torch.from_numpy(q).cuda(), 10, L)
+            assert np.array_equal(io, ig.cpu().numpy().astype(np.uint32)), f"{where} L={L}: ids"
+            assert np.array_equal(do, dgpu.cpu().numpy()), f"{where} L={L}: distances"
+
+    print("[parity] heavy ties", flush=True)
+    for bi in range(2):
+        x = rows(1500)
+        ido = o.insert(x)
+        idg = g.insert(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.uint32)
+        assert np.array_equal(ido, idg)
+        assert_same_state(o, g, f"ties batch {bi}")
+    check_search("ties after build")
+    live = np.nonzero(~o.export()["deleted"])[0].astype(np.uint32)
+    dl = rng.choice(live, size=150, replace=False).astype(np.uint32)
+    assert np.array_equal(o.delete(dl), g.delete(torch.from_numpy(dl.astype(np.int32)).cuda()).cpu().numpy())
+    x = rows(150)
+    o.insert(x)
+    g.insert(torch.from_numpy(x).cuda())
+    o.reclaim()
+    g.reclaim()
+    assert_same_state(o, g, "ties after churn")
+    check_search("ties after churn")
+    g.close()
