@@ -183,27 +183,31 @@ __device__ inline uint32_t group_sum(uint32_t v) {
 }
 
 // ---- visited table: exact ids, open addressing, may forget -----------------------
-// A lookup that finds the id reports "seen"; a table too crowded to take the
-// id reports "unseen" without storing it. Forgetting only costs a repeated
+// A lookup that finds the id reports VT_SEEN; a table too crowded to take the
+// id reports VT_CROWDED without storing it. Forgetting only costs a repeated
 // distance evaluation: the list merge drops keys already listed, and a key
 // rejected or evicted earlier is rejected again (the list's worst key never
-// increases), so results do not depend on the table size.
+// increases), so results do not depend on the table size. Two lanes that
+// insert the same id in one call cannot both get VT_NEW (the compare-and-swap
+// or the later lookup sees the other's id), but both can get VT_CROWDED: the
+// caller removes such duplicates from its batch.
 constexpr int VT_PROBES = 8;
+enum VtResult : uint32_t { VT_SEEN = 0, VT_NEW = 1, VT_CROWDED = 2 };
 
-__device__ inline bool vt_insert(uint32_t* vt, uint32_t mask, uint32_t id) {
+__device__ inline uint32_t vt_insert(uint32_t* vt, uint32_t mask, uint32_t id) {
   uint32_t h = (id * 2654435761u) & mask;
 #pragma unroll 1
   for (int i = 0; i < VT_PROBES; ++i) {
     uint32_t s = (h + (uint32_t)i) & mask;
     uint32_t v = vt[s];
-    if (v == id) return false;
+    if (v == id) return VT_SEEN;
     if (v == NONE) {
       uint32_t prev = atomicCAS(&vt[s], NONE, id);
-      if (prev == NONE) return true;
-      if (prev == id) return false;
+      if (prev == NONE) return VT_NEW;
+      if (prev == id) return VT_SEEN;
     }
   }
-  return true;
+  return VT_CROWDED;
 }
 
 // ---- the candidate list (sorted keys + expanded flags, double-buffered) --------

@@ -689,7 +689,7 @@ __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* ba
   }
   cl.n = (int)n0;
   wave_sync();
-  for (int i = l; i < cl.n; i += 64) vt_insert(vt, a.vt_mask, key_id(cl.k0[i]));
+  for (int i = l; i < cl.n; i += 64) (void)vt_insert(vt, a.vt_mask, key_id(cl.k0[i]));
   wave_sync();
   uint32_t ndist = (uint32_t)ix.ctr[C_N_ENTRIES];  // scored by the start-set scan
   uint32_t nexp = 0;
@@ -723,8 +723,21 @@ __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* ba
       const uint32_t slot = second ? (uint32_t)l - R : (uint32_t)l;
       const uint32_t deg = (second && j1 < 0) ? 0u : ref_deg(r), s = ref_slab(r);
       uint32_t nid = NONE;
-      if (slot < deg && s != NONE) nid = ix.slabs[(size_t)s * 2u * R + slot];
-      const bool fresh = nid != NONE && vt_insert(vt, a.vt_mask, nid);
+      if (slot < deg && s < ix.P) nid = ix.slabs[(size_t)s * 2u * R + slot];
+      const uint32_t vr = nid != NONE ? vt_insert(vt, a.vt_mask, nid) : VT_SEEN;
+      bool fresh = vr != VT_SEEN;
+      const uint64_t crowded = ballot(vr == VT_CROWDED);
+      if (crowded) {
+        // a crowded table can pass an id listed in both slabs twice; the
+        // merge needs distinct candidates: a crowded lane gives way to a lane
+        // that stored the id, and to a lower crowded lane
+        ci[l] = fresh ? nid : NONE;
+        wave_sync();
+        if (vr == VT_CROWDED)
+          for (int t = 0; t < 64; ++t)
+            if (t != l && ci[t] == nid && (t < l || !((crowded >> t) & 1ull))) fresh = false;
+        wave_sync();
+      }
       const uint64_t m = ballot(fresh);
       if (fresh) ci[lanes_below(m)] = nid;
       const int cnt = __popcll(m);

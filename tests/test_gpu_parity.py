@@ -98,6 +98,12 @@ def test_parity_two_expansions_per_iteration():
     run_parity(small_workload(seed=6, rounds=2), W=2, search_L=(16, 64, 101))
 
 
+def test_parity_two_expansions_crowded_visited_table():
+    # W = 2 with a visited table far too small: ids listed in both slabs pass
+    # the crowded table twice and must reach the merge once
+    run_parity(small_workload(seed=9, rounds=2), W=2, search_L=(16, 64, 101), vt_slots=64)
+
+
 def test_parity_heavy_ties():
     # Two distinct vectors repeated (a tenth of the rows nudged by one or two
     # units): most distances tie, so more start rows lie at or below the
