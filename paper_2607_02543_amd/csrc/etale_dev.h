@@ -136,6 +136,21 @@ __device__ inline uint64_t bcast64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// the value of `lane` (the same lane in every lane of the wave)
+__device__ inline uint64_t bcast_lane64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// lane i receives lane i - 1's value (lane 0 receives 0): a whole-wave DPP shift
+__device__ inline uint32_t lane_shr1(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+}
+__device__ inline uint64_t lane_shr1_64(uint64_t v) {
+  return ((uint64_t)lane_shr1((uint32_t)(v >> 32)) << 32) | lane_shr1((uint32_t)v);
+}
+
 __device__ inline bool gated(const Index& ix, const Dyn& d) {
   return d.skip != 0 && (ix.ctr[C_R_GATE] & (uint64_t)d.skip) != 0;
 }

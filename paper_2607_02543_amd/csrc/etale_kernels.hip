@@ -649,10 +649,108 @@ struct TravFloat {
 };
 
 // ---- greedy beam search (queries and insert searches) ---------------------------------
+// Candidates of one expansion batch after the visited table: lane l holds id
+// nid, vr its table result, fresh whether it is to be scored. Only ids that
+// met a crowded table (VT_CROWDED) can repeat an id of another lane or of the
+// list, so each crowded lane is checked with one ballot: it gives way to a
+// lane that stored the same id, to a lower crowded lane with it and (with a
+// list in registers, lanes below n holding keys lk) to a listed entry.
+__device__ inline bool drop_crowded_twins(uint32_t nid, uint32_t vr, bool fresh, uint64_t lk = KEY_NONE,
+                                          int n = 0) {
+  const int l = lane_id();
+  const uint64_t crowded = ballot(vr == VT_CROWDED);
+  if (!crowded) return fresh;
+  const uint64_t fr = ballot(fresh);
+  bool keep = fresh;
+  for (uint64_t cm = crowded & fr; cm; cm &= cm - 1) {
+    const int c = (int)__builtin_ctzll(cm);
+    const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)nid, c);
+    const uint64_t others = ballot(nid == id) & fr & ~(1ull << c);
+    bool drop = (others & ((1ull << c) - 1ull)) != 0 || (others & ~crowded) != 0;
+    if (n > 0) drop = drop || ballot(l < n && key_id(lk) == id) != 0;
+    if (drop && l == c) keep = false;
+  }
+  return keep;
+}
+
+// The search's results from its final list (keys lk, reference words lr, n
+// entries): a query's k nearest non-deleted listed nodes (re-ranked from the
+// FP32 rows for a bf16 / FP8 traversal), or an insert search's visit count;
+// then the per-query counters. ci and ck are the wave's 64-entry scratch.
+template <class TP>
+__device__ inline void search_finish(const Index& ix, const SearchArgs& a, uint32_t qi, const void* qrow,
+                                     const uint64_t* lk, const uint64_t* lr, int n, uint32_t* ci, uint64_t* ck,
+                                     uint32_t nexp, uint32_t ndist) {
+  const int l = lane_id();
+  if (a.mode == MODE_QUERY) {
+    // the first `want` listed nodes whose reference has flag 0: k of them, or
+    // rerank*k for a bf16 / FP8 traversal, which are then re-scored from the
+    // FP32 rows and cut to k
+    bool rerank = false;
+    if constexpr (TP::FLOAT) rerank = TP::MODE != TRAV_NATIVE;
+    if (a.rerank == 0) rerank = false;
+    const uint32_t want = rerank ? min(64u, a.rerank * a.k) : a.k;
+    uint32_t got = 0;
+    for (int b = 0; b < n && got < want; b += 64) {
+      const int i = b + l;
+      bool live = false;
+      uint64_t key = 0;
+      if (i < n) {
+        key = lk[i];
+        live = !ref_del(lr[i]);
+      }
+      const uint64_t m = ballot(live);
+      const uint32_t idx = got + lanes_below(m);
+      if (live && idx < want) {
+        if (rerank) {
+          ci[idx] = key_id(key);
+        } else {
+          a.out_ids[(size_t)qi * a.k + idx] = key_id(key);
+          a.out_d[(size_t)qi * a.k + idx] = TP::out_bits(key_dist(key));
+        }
+      }
+      got += (uint32_t)__popcll(m);
+    }
+    got = min(got, want);
+    if constexpr (TP::FLOAT) {
+      if (rerank) {
+        wave_sync();
+        using E = typename TP::Exact;
+        E::dist_batch(ix, E::load_query(reinterpret_cast<const float*>(qrow)), ci, (int)got, ck, nullptr);
+        for (int i = (int)got + l; i < 64; i += 64) ck[i] = KEY_NONE;
+        wave_sync();
+        wave_bitonic_sort(ck, 64);
+        got = min(got, a.k);
+        for (uint32_t i = (uint32_t)l; i < got; i += 64) {
+          a.out_ids[(size_t)qi * a.k + i] = key_id(ck[i]);
+          a.out_d[(size_t)qi * a.k + i] = TP::out_bits(key_dist(ck[i]));
+        }
+      }
+    }
+    for (uint32_t i = got + (uint32_t)l; i < a.k; i += 64) {
+      a.out_ids[(size_t)qi * a.k + i] = NONE;
+      a.out_d[(size_t)qi * a.k + i] = TP::pad_bits();
+    }
+  } else if (l == 0) {
+    a.vis_cnt[qi] = nexp;
+  }
+  if (l == 0) {
+    if (a.mode == MODE_QUERY) {
+      atomicAdd(&ix.ctr[C_SEARCH_EXP], (unsigned long long)nexp);
+      atomicAdd(&ix.ctr[C_SEARCH_DIST], (unsigned long long)ndist);
+    }
+    if (a.counts) {
+      a.counts[2 * (size_t)qi] = nexp;
+      a.counts[2 * (size_t)qi + 1] = ndist;
+    }
+  }
+}
+
 // One wavefront per query, starting from the initial list the start-set scan
-// left (the L best members of the entry set). Per-wave LDS: the
-// double-buffered candidate list (keys, reference words, expanded flags), one
-// batch of candidates, the merge scratch and the visited table.
+// left (the L best members of the entry set). This variant (L > 64) keeps the
+// list in LDS. Per-wave LDS: the double-buffered candidate list (keys,
+// reference words, expanded flags), one batch of candidates, the merge
+// scratch and the visited table.
 template <class TP>
 __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* base, uint32_t qi) {
   const int l = lane_id();
@@ -726,18 +824,9 @@ __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* ba
       if (slot < deg && s < ix.P) nid = ix.slabs[(size_t)s * 2u * R + slot];
       const uint32_t vr = nid != NONE ? vt_insert(vt, a.vt_mask, nid) : VT_SEEN;
       bool fresh = vr != VT_SEEN;
-      const uint64_t crowded = ballot(vr == VT_CROWDED);
-      if (crowded) {
-        // a crowded table can pass an id listed in both slabs twice; the
-        // merge needs distinct candidates: a crowded lane gives way to a lane
-        // that stored the id, and to a lower crowded lane
-        ci[l] = fresh ? nid : NONE;
-        wave_sync();
-        if (vr == VT_CROWDED)
-          for (int t = 0; t < 64; ++t)
-            if (t != l && ci[t] == nid && (t < l || !((crowded >> t) & 1ull))) fresh = false;
-        wave_sync();
-      }
+      // a crowded table can pass an id listed in both slabs twice; the merge
+      // needs distinct candidates
+      fresh = drop_crowded_twins(nid, vr, fresh);
       const uint64_t m = ballot(fresh);
       if (fresh) ci[lanes_below(m)] = nid;
       const int cnt = __popcll(m);
@@ -751,76 +840,119 @@ __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* ba
     }
   }
 
-  const uint64_t* lk = cl.keys();
-  const uint64_t* lr = cl.refs();
-  if (a.mode == MODE_QUERY) {
-    // the first `want` listed nodes whose reference has flag 0: k of them, or
-    // rerank*k for a bf16 / FP8 traversal, which are then re-scored from the
-    // FP32 rows and cut to k
-    bool rerank = false;
-    if constexpr (TP::FLOAT) rerank = TP::MODE != TRAV_NATIVE;
-    if (a.rerank == 0) rerank = false;
-    const uint32_t want = rerank ? min(64u, a.rerank * a.k) : a.k;
-    uint32_t got = 0;
-    for (int b = 0; b < cl.n && got < want; b += 64) {
-      const int i = b + l;
-      bool live = false;
-      uint64_t key = 0;
-      if (i < cl.n) {
-        key = lk[i];
-        live = !ref_del(lr[i]);
-      }
-      const uint64_t m = ballot(live);
-      const uint32_t idx = got + lanes_below(m);
-      if (live && idx < want) {
-        if (rerank) {
-          ci[idx] = key_id(key);
-        } else {
-          a.out_ids[(size_t)qi * a.k + idx] = key_id(key);
-          a.out_d[(size_t)qi * a.k + idx] = TP::out_bits(key_dist(key));
-        }
-      }
-      got += (uint32_t)__popcll(m);
-    }
-    got = min(got, want);
-    if constexpr (TP::FLOAT) {
-      if (rerank) {
-        wave_sync();
-        using E = typename TP::Exact;
-        E::dist_batch(ix, E::load_query(reinterpret_cast<const float*>(qrow)), ci, (int)got, ck, nullptr);
-        for (int i = (int)got + l; i < 64; i += 64) ck[i] = KEY_NONE;
-        wave_sync();
-        wave_bitonic_sort(ck, 64);
-        got = min(got, a.k);
-        for (uint32_t i = (uint32_t)l; i < got; i += 64) {
-          a.out_ids[(size_t)qi * a.k + i] = key_id(ck[i]);
-          a.out_d[(size_t)qi * a.k + i] = TP::out_bits(key_dist(ck[i]));
-        }
-      }
-    }
-    for (uint32_t i = got + (uint32_t)l; i < a.k; i += 64) {
-      a.out_ids[(size_t)qi * a.k + i] = NONE;
-      a.out_d[(size_t)qi * a.k + i] = TP::pad_bits();
-    }
-  } else if (l == 0) {
-    a.vis_cnt[qi] = nexp;
-  }
-  if (l == 0) {
-    if (a.mode == MODE_QUERY) {
-      atomicAdd(&ix.ctr[C_SEARCH_EXP], (unsigned long long)nexp);
-      atomicAdd(&ix.ctr[C_SEARCH_DIST], (unsigned long long)ndist);
-    }
-    if (a.counts) {
-      a.counts[2 * (size_t)qi] = nexp;
-      a.counts[2 * (size_t)qi + 1] = ndist;
-    }
-  }
+  search_finish<TP>(ix, a, qi, qrow, cl.keys(), cl.refs(), cl.n, ci, ck, nexp, ndist);
 }
 
-// Persistent waves: each takes the next query from the launch's work queue
-// until it is drained; the last wave to leave resets the queue for the next
-// launch on the stream.
+// The same search for L <= 64 with the list in registers: lane i holds entry
+// i (key, reference word, expanded flag), entries at or past n hold KEY_NONE.
+// The next entries to expand are the lowest lanes of one ballot, and each
+// accepted candidate is inserted at its rank (a ballot count) by shifting the
+// lanes above it up one, so the list never leaves the registers. Per-wave
+// LDS: one batch of candidates and the visited table.
 template <class TP>
+__device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char* base, uint32_t qi) {
+  const int l = lane_id();
+  uint64_t* ck = reinterpret_cast<uint64_t*>(base);
+  uint64_t* cr = ck + 64;
+  uint32_t* ci = reinterpret_cast<uint32_t*>(cr + 64);
+  uint32_t* vt = ci + 64;
+  const int L = (int)a.L;
+  const void* qrow = a.mode == MODE_QUERY ? (const void*)((const uint8_t*)a.q + (size_t)qi * TP::query_bytes(ix))
+                                          : TP::stored_row(ix, a.first + qi);
+  const typename TP::Q qv = TP::load_query(qrow);
+  for (uint32_t i = (uint32_t)l; i <= a.vt_mask; i += 64) vt[i] = NONE;
+  // the initial list: the L best start nodes, with their reference words
+  int n = (int)a.init_n[qi];
+  uint64_t lk = KEY_NONE, lr = 0;
+  uint32_t lx = 0;
+  if (l < n) {
+    lk = a.init_keys[(size_t)qi * a.init_stride + l];
+    lr = load_ref(ix, key_id(lk));
+  }
+  wave_sync();
+  if (l < n) (void)vt_insert(vt, a.vt_mask, key_id(lk));
+  wave_sync();
+  uint32_t ndist = (uint32_t)ix.ctr[C_N_ENTRIES];  // scored by the start-set scan
+  uint32_t nexp = 0;
+  const uint32_t R = ix.R;
+  while (nexp < a.vcap) {
+    // up to W best unexpanded entries, within the visit cap
+    uint64_t open = ballot(l < n && lx == 0);
+    if (!open) break;
+    const int j0 = (int)__builtin_ctzll(open);
+    open &= open - 1;
+    const int j1 = (a.W > 1 && nexp + 1 < a.vcap && open) ? (int)__builtin_ctzll(open) : -1;
+    const uint64_t key0 = bcast_lane64(lk, j0), r0 = bcast_lane64(lr, j0);
+    uint64_t key1 = 0, r1 = 0;
+    if (j1 >= 0) {
+      key1 = bcast_lane64(lk, j1);
+      r1 = bcast_lane64(lr, j1);
+    }
+    if (l == j0 || l == j1) lx = 1;
+    if (l == 0 && a.mode == MODE_INSERT) {
+      a.vis_keys[(size_t)qi * a.vcap + nexp] = key0;
+      if (j1 >= 0) a.vis_keys[(size_t)qi * a.vcap + nexp + 1] = key1;
+    }
+    nexp += j1 >= 0 ? 2u : 1u;
+    // their slabs side by side: lanes [w*R, (w+1)*R) read the w-th
+    const bool second = (uint32_t)l >= R;
+    const uint64_t r = second ? r1 : r0;
+    const uint32_t slot = second ? (uint32_t)l - R : (uint32_t)l;
+    const uint32_t deg = (second && j1 < 0) ? 0u : ref_deg(r), s = ref_slab(r);
+    uint32_t nid = NONE;
+    if (slot < deg && s < ix.P) nid = ix.slabs[(size_t)s * 2u * R + slot];
+    if (nid >= ix.cap) nid = NONE;
+    const uint32_t vr = nid != NONE ? vt_insert(vt, a.vt_mask, nid) : VT_SEEN;
+    bool fresh = vr != VT_SEEN;
+    // a crowded table can pass an id listed in both slabs twice, or one
+    // already listed; the insertion below needs distinct, unlisted candidates
+    fresh = drop_crowded_twins(nid, vr, fresh, lk, n);
+    const uint64_t m = ballot(fresh);
+    if (fresh) ci[lanes_below(m)] = nid;
+    const int cnt = __popcll(m);
+    wave_sync();
+    if (!cnt) continue;
+    TP::dist_batch(ix, qv, ci, cnt, ck, cr);
+    wave_sync();
+    ndist += (uint32_t)cnt;
+    // merge: the candidates below the current worst entry, each at its rank
+    uint64_t cand = KEY_NONE, cref = 0;
+    if (l < cnt) {
+      cand = ck[l];
+      cref = cr[l];
+    }
+    uint64_t worst = n == L ? bcast_lane64(lk, L - 1) : KEY_NONE;
+    for (uint64_t acc = ballot(l < cnt && cand < worst); acc; acc &= acc - 1) {
+      const int c = (int)__builtin_ctzll(acc);
+      const uint64_t key = bcast_lane64(cand, c);
+      if (key >= worst) continue;  // the list filled up or improved meanwhile
+      const uint64_t rf = bcast_lane64(cref, c);
+      const int pos = __popcll(ballot(lk < key));
+      // shift lanes above pos up by one, then place the candidate at pos
+      const uint64_t sk = lane_shr1_64(lk), sr = lane_shr1_64(lr);
+      const uint32_t sx = lane_shr1(lx);
+      if (l > pos) {
+        lk = sk;
+        lr = sr;
+        lx = sx;
+      } else if (l == pos) {
+        lk = key;
+        lr = rf;
+        lx = 0;
+      }
+      if (l >= L) lk = KEY_NONE;
+      n = min(n + 1, L);
+      worst = n == L ? bcast_lane64(lk, L - 1) : KEY_NONE;
+    }
+  }
+  // the list to LDS for the shared result stage (the candidate scratch is free)
+  ck[l] = lk;
+  cr[l] = lr;
+  wave_sync();
+  search_finish<TP>(ix, a, qi, qrow, ck, cr, n, ci, ck, nexp, ndist);
+}
+
+template <class TP, bool RL>
 __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, a.d)) return;
@@ -829,14 +961,18 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   char* base = smem + (size_t)(threadIdx.x >> 6) * a.lds_per_wave;
   if (!a.persistent) {  // one wave per query
     const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (qi < a.nq) search_one<TP>(ix, a, base, qi);
+    if (qi < a.nq) {
+      if constexpr (RL) search_one_rl<TP>(ix, a, base, qi);
+      else search_one<TP>(ix, a, base, qi);
+    }
     return;
   }
   const int l = lane_id();
   unsigned long long* queue = &ix.ctr[C_QUEUE];
   for (uint32_t qi = wave_ticket(queue); qi < a.nq; qi = wave_ticket(queue)) {
     wave_sync();
-    search_one<TP>(ix, a, base, qi);
+    if constexpr (RL) search_one_rl<TP>(ix, a, base, qi);
+    else search_one<TP>(ix, a, base, qi);
   }
   const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
   if (l == 0 && done + 1 == total_waves()) {
@@ -2279,6 +2415,8 @@ hipError_t launch_sort(const Index& ix, uint64_t* a, uint64_t* b, uint32_t nmax,
 }
 
 uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots) {
+  // L <= 64 (list in registers): candidate keys/refs, ids, visited table
+  if (L <= 64) return 2u * 512u + 256u + 4u * vt_slots;
   // keys + refs (double-buffered), candidate keys/refs, merge scratch, ids,
   // insertion points, visited table, expanded flags
   return 32u * L + 4u * 512u + 2u * 256u + 4u * vt_slots + ((2u * L + 15u) & ~15u);
@@ -2322,7 +2460,14 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
   return hipGetLastError();
 }
 
-#define LS(TP) hipLaunchKernelGGL(k_search<TP>, dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a)
+// the list lives in registers for L <= 64
+#define LS(TP)                                                                                   \
+  do {                                                                                           \
+    if (a.L <= 64)                                                                               \
+      hipLaunchKernelGGL((k_search<TP, true>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a); \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_search<TP, false>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a); \
+  } while (0)
 
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s) {
   if (a.nq == 0) return hipSuccess;
