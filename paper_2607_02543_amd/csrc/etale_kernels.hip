@@ -953,8 +953,7 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
 }
 
 template <class TP, bool RL>
-__global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
-  extern __shared__ __align__(16) char smem[];
+__device__ inline void search_kernel(const Index& ix, SearchArgs& a, char* smem) {
   if (gated(ix, a.d)) return;
   a.nq = dyn_count(ix, a.d, a.nq);
   a.first = dyn_first(ix, a.d, a.first);
@@ -979,6 +978,21 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
     atomicExch(queue, 0ull);
     atomicExch(&ix.ctr[C_QDONE], 0ull);
   }
+}
+
+// list in registers; uint8 rows hold their registers to 7 waves per SIMD (the
+// LDS of 7 four-wave blocks fits a CU at the default visited-table size),
+// float rows keep theirs (they would spill)
+template <class TP, unsigned WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) k_search_rl(Index ix, SearchArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  search_kernel<TP, true>(ix, a, smem);
+}
+
+template <class TP>
+__global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  search_kernel<TP, false>(ix, a, smem);
 }
 
 // ---- LDS carving for the maintenance kernels ------------------------------------------
@@ -2464,9 +2478,9 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
 #define LS(TP)                                                                                   \
   do {                                                                                           \
     if (a.L <= 64)                                                                               \
-      hipLaunchKernelGGL((k_search<TP, true>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a); \
+      hipLaunchKernelGGL((k_search_rl<TP, TP::FLOAT ? 1u : 7u>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a); \
     else                                                                                         \
-      hipLaunchKernelGGL((k_search<TP, false>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a); \
+      hipLaunchKernelGGL((k_search<TP>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a); \
   } while (0)
 
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s) {
