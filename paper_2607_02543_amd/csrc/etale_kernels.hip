@@ -1318,6 +1318,64 @@ __device__ inline void chain_fill_row(const ChainLds& c, uint32_t a, const uint3
   wave_sync();
 }
 
+// All of M at once, on the matrix cores: every pair of slots below S (S <= 64)
+// from the staged rows (slots that hold no row give values never read). The
+// bytes are shifted to signed values (an XOR with 0x80), which leaves every
+// squared distance unchanged: d = |r'|^2 + |c'|^2 - 2 r'.c', exact in int32.
+// The shifted squared norms come from the diagonal tiles first (into nrm,
+// S words of scratch), then each tile pair (a <= b) of 16 x 16 slots fills
+// M[r][c] and M[c][r].
+__device__ inline v4i32 chain_frag(const ChainLds& c, uint32_t slot, uint32_t off, uint32_t dim) {
+  v4i32 f = {0, 0, 0, 0};
+  if (slot < c.S && off < dim) {
+    const uint4 w = *reinterpret_cast<const uint4*>(c.rows + (size_t)slot * c.vstride + off);
+    f = v4i32{(int)(w.x ^ 0x80808080u), (int)(w.y ^ 0x80808080u), (int)(w.z ^ 0x80808080u),
+              (int)(w.w ^ 0x80808080u)};
+  }
+  return f;
+}
+
+__device__ inline v4i32 chain_tile(const ChainLds& c, uint32_t ta, uint32_t tb, uint32_t dim) {
+  const int l = lane_id();
+  const uint32_t r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u;
+  v4i32 acc = {0, 0, 0, 0};
+  for (uint32_t k0 = 0; k0 < dim; k0 += 64)
+    acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(chain_frag(c, ta * 16u + r, k0 + kc, dim),
+                                               chain_frag(c, tb * 16u + r, k0 + kc, dim), acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ inline void chain_fill_mfma(const Index& ix, const ChainLds& c, uint32_t* nrm) {
+  const int l = lane_id();
+  const uint32_t S = c.S, T = (S + 15u) / 16u, dim = ix.dim;
+  const uint32_t r = (uint32_t)(l & 15), rb = (uint32_t)(l >> 4) * 4u;
+  // lane l holds rows rb + i, column r of a tile: the diagonal is row == column
+  for (uint32_t ta = 0; ta < T; ++ta) {
+    const v4i32 acc = chain_tile(c, ta, ta, dim);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (rb + (uint32_t)i == r && ta * 16u + r < S) nrm[ta * 16u + r] = (uint32_t)acc[i];
+  }
+  wave_sync();
+  for (uint32_t ta = 0; ta < T; ++ta)
+    for (uint32_t tb = ta; tb < T; ++tb) {
+      const v4i32 acc = chain_tile(c, ta, tb, dim);
+      const uint32_t col = tb * 16u + r;
+      if (col >= S) continue;
+      const uint32_t nc = nrm[col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t row = ta * 16u + rb + (uint32_t)i;
+        if (row < S) {
+          const uint32_t d = nrm[row] + nc - 2u * (uint32_t)acc[i];
+          c.M[row * S + col] = d;
+          c.M[col * S + row] = d;
+        }
+      }
+    }
+  wave_sync();
+}
+
 template <int G>
 __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, const ChainLds& c, uint32_t t,
                                         SlabCursor& cur) {
@@ -1386,10 +1444,11 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
       wave_sync();
       chain_stage_rows<G>(ix, c, c.out_id, __popcll(nm));
       staged |= used;
-      for (uint32_t x = 0; x < n; ++x) chain_fill_row<G>(c, c.order[x], c.order, (int)n);
+      chain_fill_mfma(ix, c, c.out_d);  // every staged pair, v's row included
       cached = true;
+    } else {
+      chain_fill_row<G>(c, f, c.order, (int)n);
     }
-    chain_fill_row<G>(c, f, c.order, (int)n);
     // candidates in (distance, id) order: the list with v at position pos
     uint32_t cs = f;
     if ((uint32_t)l < pos) cs = sl;
