@@ -8,6 +8,9 @@
 #include "etale_float.h"
 #include "etale_launch.h"
 
+#include <map>
+#include <mutex>
+
 namespace etale {
 
 __host__ __device__ inline uint64_t pair_key(uint32_t target, uint32_t source) {
@@ -1738,56 +1741,65 @@ __device__ inline void repair_one(const Index& ix, const MaintArgs& a, MaintLds&
 // ---- repair with a wave-local candidate pool (uint8 rows, R <= 32) ------------------
 // Algorithm 3 for one target a: for each deleted u in ascending order,
 // K = RobustPrune(a, N(u) \ {a}), then N(a) = RobustPrune(a, (N(a) \ {u}) U K).
-// A pool of 64 slots holds the rows, norms, ids, distances to a and deletion
-// flags of a's list and of one N(u); a's list is staged once, and per u only
-// the rows and flags of the members of N(u) that are not already pooled are
-// fetched (one round trip). Both prunes then run from LDS: candidates are
-// ranked by (distance, id) with duplicates, a and tombstones dropped, at most
-// prune_cap are considered, and the distances between a kept candidate and
-// the later live ones are computed when needed, one candidate per lane.
+// A pool of 64 slots holds the ids, distances to a and deletion flags of a's
+// list and of one N(u), and the squared distances between every two occupied
+// slots (a triangular cache). a's list is staged once; per u only the members
+// of N(u) that are not already pooled are fetched, and their distances to the
+// occupied slots are filled on the matrix cores. Both prunes then run from
+// LDS: candidates are ranked by (distance, id) with duplicates, a and
+// tombstones dropped, at most prune_cap are considered, and every distance
+// between a kept candidate and a later one is one cache read.
 struct PoolLds {
-  uint8_t* rows;     // [64][vstride]
-  uint32_t* norm;    // [64]
+  uint32_t* M;       // [64 * 63 / 2 + 1] squared distances, tri(x, y) = max(x,y)(max-1)/2 + min(x,y)
+  uint32_t* norm;    // [64] squared norm of the row shifted to signed bytes
   uint32_t* id;      // [64]
-  uint32_t* dw;      // [64] squared distance to the target
-  uint32_t* dead;    // [64]
+  uint32_t* dw;      // [64] squared distance to the target (< 2^27), bit 31: deletion flag
   uint32_t* list;    // [64] list position -> slot
   uint32_t* cand;    // [64] candidate slots of a prune
   uint32_t* sorted;  // [64] candidate slots in (distance, id) order
   uint32_t* kept;    // [64] output slots of a prune
-  uint32_t vstride;
 };
 
 constexpr uint32_t POOL = 64;
 
-__host__ __device__ inline uint32_t pool_lds_bytes(uint32_t vstride) {
-  return ((POOL * vstride + 8u * POOL * 4u) + 15u) & ~15u;
-}
+// the distances of distinct slots (the diagonal is never read for a decision;
+// its index, at most one past the last pair, stays inside the array), sized
+// so that 16 waves fit a CU's LDS
+constexpr uint32_t POOL_M = POOL * (POOL - 1u) / 2u + 1u;
 
-__device__ inline PoolLds carve_pool(char* base, uint32_t vstride) {
+__host__ __device__ inline uint32_t pool_lds_bytes(uint32_t) {
+  return ((POOL_M * 4u + 7u * POOL * 4u) + 15u) & ~15u;
+}
+constexpr uint32_t DW_DEAD = 0x80000000u;
+
+__device__ inline PoolLds carve_pool(char* base, uint32_t) {
   PoolLds p;
-  p.vstride = vstride;
-  p.rows = reinterpret_cast<uint8_t*>(base);
-  uint32_t* q = reinterpret_cast<uint32_t*>(base + (size_t)POOL * vstride);
+  p.M = reinterpret_cast<uint32_t*>(base);
+  uint32_t* q = p.M + ((POOL_M + 3u) & ~3u);
   p.norm = q;
   p.id = q + POOL;
   p.dw = q + 2 * POOL;
-  p.dead = q + 3 * POOL;
-  p.list = q + 4 * POOL;
-  p.cand = q + 5 * POOL;
-  p.sorted = q + 6 * POOL;
-  p.kept = q + 7 * POOL;
+  p.list = q + 3 * POOL;
+  p.cand = q + 4 * POOL;
+  p.sorted = q + 5 * POOL;
+  p.kept = q + 6 * POOL;
   return p;
 }
 
-// rows, norms, deletion flags and distances to the target (fragment wf, norm
-// ww) of slots[0..cnt), all loads issued before any is used
+__device__ inline uint32_t tri(uint32_t x, uint32_t y) {
+  const uint32_t hi = max(x, y), lo = min(x, y);
+  return hi * (hi - 1u) / 2u + lo;  // hi = lo = 0 gives 0, hi = lo = 63 gives POOL_M - 1
+}
+
+// shifted squared norms, deletion flags and distances to the target (fragment
+// wf, norm ww) of slots[0..cnt), all loads issued before any is used
 template <int G>
 __device__ inline void pool_stage(const Index& ix, const PoolLds& p, const uint32_t* slots, int cnt, uint4 wf,
                                   uint32_t ww) {
   constexpr int VPP = 64 / G;
   const int l = lane_id();
   const int ch = l % G, grp = l / G;
+  const uint4 ones = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
   uint64_t ref = 0;
   const uint32_t my = l < cnt ? slots[l] : 0u;
   if (l < cnt) ref = load_ref(ix, p.id[my]);
@@ -1804,17 +1816,67 @@ __device__ inline void pool_stage(const Index& ix, const PoolLds& p, const uint3
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint32_t nn = group_sum<G>(dot16(v[u], v[u], 0u));
+      const uint32_t sm = group_sum<G>(dot16(v[u], ones, 0u));
       const uint32_t dt = group_sum<G>(dot16(wf, v[u], 0u));
-      if (sl[u] >= 0) {
-        *reinterpret_cast<uint4*>(p.rows + (size_t)sl[u] * p.vstride + ch * 16) = v[u];
-        if (ch == 0) {
-          p.norm[sl[u]] = nn;
-          p.dw[sl[u]] = ww + nn - 2u * dt;
+      if (sl[u] >= 0 && ch == 0) {
+        // |x - 128|^2 = |x|^2 - 256 sum(x) + 128^2 dim
+        p.norm[sl[u]] = nn - 256u * sm + 16384u * ix.dim;
+        p.dw[sl[u]] = ww + nn - 2u * dt;
+      }
+    }
+  }
+  wave_sync();
+  if (l < cnt && ref_del(ref)) p.dw[my] |= DW_DEAD;
+  wave_sync();
+}
+
+// The cache entries between the nf slots fresh[0..nf) and every slot of the
+// mask occ (fresh ones included), on the matrix cores: 16 fresh rows x 16
+// slots per v_mfma_i32_16x16x64_i8 tile over the rows shifted to signed bytes
+// (exact in int32), the rows read from memory. Needs the shifted norms.
+__device__ inline v4i32 pool_frag(const Index& ix, const PoolLds& p, uint32_t slot, bool valid, uint32_t off) {
+  v4i32 f = {0, 0, 0, 0};
+  if (valid && off < ix.dim) {
+    const uint4 w = *reinterpret_cast<const uint4*>(ix.x + (size_t)p.id[slot] * ix.dim + off);
+    f = v4i32{(int)(w.x ^ 0x80808080u), (int)(w.y ^ 0x80808080u), (int)(w.z ^ 0x80808080u),
+              (int)(w.w ^ 0x80808080u)};
+  }
+  return f;
+}
+
+__device__ inline void pool_fill(const Index& ix, const PoolLds& p, const uint32_t* fresh, uint32_t nf, uint64_t occ) {
+  const int l = lane_id();
+  const uint32_t r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u, rb = (uint32_t)(l >> 4) * 4u;
+  for (uint32_t f0 = 0; f0 < nf; f0 += 16) {
+    const uint32_t fa = f0 + r < nf ? fresh[f0 + r] : 0u;
+    v4i32 acc[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) acc[st] = v4i32{0, 0, 0, 0};
+    for (uint32_t k0 = 0; k0 < ix.dim; k0 += 64) {
+      const v4i32 fa_frag = pool_frag(ix, p, fa, f0 + r < nf, k0 + kc);
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const uint32_t sb = (uint32_t)st * 16u + r;
+        acc[st] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa_frag, pool_frag(ix, p, sb, (occ >> sb) & 1ull, k0 + kc),
+                                                        acc[st], 0, 0, 0);
+      }
+    }
+    // lane l holds fresh rows f0 + rb + i against slot 16 st + r
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const uint32_t sb = (uint32_t)st * 16u + r;
+      if (!((occ >> sb) & 1ull)) continue;
+      const uint32_t nb = p.norm[sb];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t fi = f0 + rb + (uint32_t)i;
+        if (fi < nf) {
+          const uint32_t fs = fresh[fi];
+          if (fs != sb) p.M[tri(fs, sb)] = p.norm[fs] + nb - 2u * (uint32_t)acc[st][i];
         }
       }
     }
   }
-  if (l < cnt) p.dead[my] = ref_del(ref);
   wave_sync();
 }
 
@@ -1841,8 +1903,7 @@ __device__ inline void lane_bitonic_sort(uint64_t& key, uint32_t& val) {
 
 // RobustPrune(self, candidate slots cs[0..m)) into out[0..return); m <= 64.
 // Candidates are ranked in registers (one per lane); during the selection each
-// lane keeps its own candidate's row in registers and reads the kept one.
-template <int G>
+// lane reads the distance from the kept candidate to its own from the cache.
 __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const uint32_t* cs, uint32_t m,
                                       uint32_t self, uint32_t* out) {
   const int l = lane_id();
@@ -1850,7 +1911,8 @@ __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const u
   uint64_t key = KEY_NONE;
   if ((uint32_t)l < m) {
     const uint32_t id = p.id[slot];
-    if (id != self && p.dead[slot] == 0u) key = make_key(p.dw[slot], id);
+    const uint32_t w = p.dw[slot];
+    if (id != self && !(w & DW_DEAD)) key = make_key(w, id);
   }
   lane_bitonic_sort(key, slot);
   // repeated ids are adjacent with equal keys: one copy stays
@@ -1866,32 +1928,18 @@ __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const u
   if (mm > cap) mm = cap;
   const uint32_t csl = (uint32_t)l < mm ? p.sorted[l] : 0u;
   const uint32_t cdw = (uint32_t)l < mm ? p.dw[csl] : 0u;
-  const uint32_t cn = p.norm[csl];
-  constexpr int GR = G <= 16 ? G : 1;  // rows of up to 256 bytes stay in registers
-  uint4 rv[GR];
-  const uint4* rc = reinterpret_cast<const uint4*>(p.rows + (size_t)csl * p.vstride);
-#pragma unroll
-  for (int w = 0; w < GR; ++w) rv[w] = rc[w];
   uint64_t alive = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
   uint32_t cnt = 0, from = 0, keep_slot = 0;
   while (cnt < ix.R) {
     const uint64_t mk = from < 64 ? (alive & (~0ull << from)) : 0ull;
     if (!mk) break;
     const uint32_t j = (uint32_t)__builtin_ctzll(mk);
-    const uint32_t sj = (uint32_t)__shfl((int)csl, (int)j, 64);
+    const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)csl, (int)j);
     if ((uint32_t)l == cnt) keep_slot = sj;
     ++cnt;
     from = j + 1;
     if (cnt == ix.R) break;
-    const uint4* rj = reinterpret_cast<const uint4*>(p.rows + (size_t)sj * p.vstride);
-    uint32_t dot = 0;
-    if constexpr (G <= 16) {
-#pragma unroll
-      for (int w = 0; w < G; ++w) dot = dot16(rv[w], rj[w], dot);
-    } else {
-      for (int w = 0; w < G; ++w) dot = dot16(rc[w], rj[w], dot);
-    }
-    const uint32_t d = p.norm[sj] + cn - 2u * dot;
+    const uint32_t d = p.M[tri(sj, csl)];
     const bool kill = (uint32_t)l > j && ((alive >> l) & 1ull) &&
                       (uint64_t)ix.a2 * d <= (uint64_t)ix.b2 * (uint64_t)cdw;
     alive &= ~ballot(kill);
@@ -1910,72 +1958,88 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
   const uint32_t an = (uint32_t)(a.pairs[t] >> 32);
   const uint4 wf = load_frag<G>(ix.x + (size_t)an * ix.dim);
   const uint32_t ww = group_sum<G>(dot16(wf, wf, 0u));
-  // a's list in slots 0..n-1, rows and flags staged once
-  const uint64_t r = bcast64(load_ref(ix, an));
-  uint32_t n = ref_slab(r) == NONE ? 0u : ref_deg(r);
+  // a's list and the first N(u), read side by side; the list lives in slots
+  // 0..n-1 and in registers (lane x: slot and id of list entry x)
+  uint32_t u = (uint32_t)a.pairs[t];
+  const uint64_t ra = bcast64(load_ref(ix, an));
+  uint64_t ru = bcast64(load_ref(ix, u));
+  uint32_t n = ref_slab(ra) == NONE ? 0u : ref_deg(ra);
+  uint32_t du = ref_slab(ru) == NONE ? 0u : ref_deg(ru);
+  uint32_t lid = NONE, b = NONE;
+  if ((uint32_t)l < n) lid = ix.slabs[(size_t)ref_slab(ra) * 2u * R + (uint32_t)l];
+  if ((uint32_t)l < du) b = ix.slabs[(size_t)ref_slab(ru) * 2u * R + (uint32_t)l];
+  uint32_t lslot = (uint32_t)l;
   if ((uint32_t)l < n) {
-    p.id[l] = ix.slabs[(size_t)ref_slab(r) * 2u * R + (uint32_t)l];
+    p.id[l] = lid;
     p.list[l] = (uint32_t)l;
-    p.cand[l] = (uint32_t)l;
   }
-  wave_sync();
-  pool_stage<G>(ix, p, p.cand, (int)n, wf, ww);
-  uint64_t used = (1ull << n) - 1ull;
+  uint64_t used = n == 64 ? ~0ull : ((1ull << n) - 1ull);
+  bool first = true;
   for (uint32_t q = t; q < a.npairs && a.pairs[q] != KEY_NONE && (uint32_t)(a.pairs[q] >> 32) == an; ++q) {
-    const uint32_t u = (uint32_t)a.pairs[q];
-    // B = N(u) \ {a}: members already pooled keep their slot, the others take free slots
-    const uint64_t ru = bcast64(load_ref(ix, u));
-    const uint32_t du = ref_slab(ru) == NONE ? 0u : ref_deg(ru);
-    uint32_t b = NONE;
-    if ((uint32_t)l < du) b = ix.slabs[(size_t)ref_slab(ru) * 2u * R + (uint32_t)l];
+    if (!first) {
+      u = (uint32_t)a.pairs[q];
+      ru = bcast64(load_ref(ix, u));
+      du = ref_slab(ru) == NONE ? 0u : ref_deg(ru);
+      b = NONE;
+      if ((uint32_t)l < du) b = ix.slabs[(size_t)ref_slab(ru) * 2u * R + (uint32_t)l];
+    }
+    // B = N(u) \ {a}: members on the list keep their slot, the others take free slots
     const bool ok = b != NONE && b != an;
     int at = -1;
-    if (ok)
-      for (uint32_t x = 0; x < n; ++x)
-        if (p.id[p.list[x]] == b) at = (int)p.list[x];
+    for (uint32_t x = 0; x < n; ++x)
+      if ((uint32_t)__builtin_amdgcn_readlane((int)lid, (int)x) == b)
+        at = __builtin_amdgcn_readlane((int)lslot, (int)x);
+    if (!ok) at = -1;
     const bool fresh = ok && at < 0;
     const uint64_t fm = ballot(fresh);
-    if (fresh) {  // the k-th fresh member takes the k-th free slot
+    {  // the k-th fresh member takes the k-th free slot
       uint64_t fr = ~used;
-      for (uint32_t k = lanes_below(fm); k; --k) fr &= fr - 1ull;
-      at = __builtin_ctzll(fr);
-      p.id[at] = b;
+      for (uint64_t m2 = fm; m2; m2 &= m2 - 1ull) {
+        if (l == (int)__builtin_ctzll(m2)) at = (int)__builtin_ctzll(fr);
+        fr &= fr - 1ull;
+      }
     }
+    if (fresh) p.id[at] = b;
     const uint64_t om = ballot(ok);
     if (ok) p.cand[lanes_below(om)] = (uint32_t)at;
+    // slots to stage: the fresh members (and, for the first u, a's list)
+    uint32_t* fs = p.kept;
+    const uint32_t nl = first ? n : 0u;
+    if ((uint32_t)l < nl) fs[l] = (uint32_t)l;
+    if (fresh) fs[nl + lanes_below(fm)] = (uint32_t)at;
     wave_sync();
-    {  // stage the fresh members
-      uint32_t* fs = p.kept;
-      if (fresh) fs[lanes_below(fm)] = (uint32_t)at;
-      wave_sync();
-      pool_stage<G>(ix, p, fs, __popcll(fm), wf, ww);
+    const uint32_t nf = nl + (uint32_t)__popcll(fm);
+    uint64_t occ = used;
+    for (uint64_t m2 = fm; m2; m2 &= m2 - 1ull)
+      occ |= 1ull << (uint32_t)__builtin_amdgcn_readlane(at, (int)__builtin_ctzll(m2));
+    if (nf) {
+      pool_stage<G>(ix, p, fs, (int)nf, wf, ww);
+      pool_fill(ix, p, fs, nf, occ);
     }
+    first = false;
     // K = RobustPrune(a, B)
-    const uint32_t kc = pool_prune<G>(ix, p, p.cand, (uint32_t)__popcll(om), an, p.kept);
+    const uint32_t kc = pool_prune(ix, p, p.cand, (uint32_t)__popcll(om), an, p.kept);
     // N = RobustPrune(a, (N \ {u}) U K)
     const uint32_t ks = (uint32_t)l < kc ? p.kept[l] : 0u;
-    const uint32_t ls = (uint32_t)l < n ? p.list[l] : 0u;
-    const bool stay = (uint32_t)l < n && p.id[ls] != u;
+    const bool stay = (uint32_t)l < n && lid != u;
     const uint64_t sm = ballot(stay);
     const uint32_t ns = (uint32_t)__popcll(sm);
     wave_sync();
-    if (stay) p.cand[lanes_below(sm)] = ls;
+    if (stay) p.cand[lanes_below(sm)] = lslot;
     if ((uint32_t)l < kc) p.cand[ns + (uint32_t)l] = ks;
     wave_sync();
-    n = pool_prune<G>(ix, p, p.cand, ns + kc, an, p.list);
+    n = pool_prune(ix, p, p.cand, ns + kc, an, p.list);
+    lslot = (uint32_t)l < n ? p.list[l] : 0u;
+    lid = (uint32_t)l < n ? p.id[lslot] : NONE;
     // slots not on the new list become free
     used = 0;
-    for (uint32_t k = 0; k < n; ++k) used |= 1ull << p.list[k];
+    for (uint32_t k = 0; k < n; ++k) used |= 1ull << (uint32_t)__builtin_amdgcn_readlane((int)lslot, (int)k);
   }
   // publish (ids and distances in list order)
-  uint32_t oid = 0, od = 0;
-  if ((uint32_t)l < n) {
-    oid = p.id[p.list[l]];
-    od = p.dw[p.list[l]];
-  }
+  const uint32_t od = (uint32_t)l < n ? p.dw[lslot] : 0u;
   wave_sync();
   if ((uint32_t)l < n) {
-    p.cand[l] = oid;
+    p.cand[l] = lid;
     p.sorted[l] = od;
   }
   wave_sync();
@@ -1988,18 +2052,35 @@ __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
   if (gated(ix, a.d)) return;
   resolve(ix, a);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
-  SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
   if constexpr (P::CHAIN) {
     if (a.chain) {
+      // targets differ in cost (one to a dozen deleted out-neighbors), so
+      // waves take them from a queue in batches, each batch with its own
+      // slab reservation (one fresh and one retired slab per target)
+      constexpr uint32_t BATCH = 4;
       const PoolLds p = carve_pool(wave_lds(smem, a), a.vstride);
-      FOR_EACH_WAVE_ITEM(si, nseg) {
-        wave_sync();
-        repair_chain_u8<P::GL>(ix, a, p, a.seg[si], cur);
+      unsigned long long* queue = &ix.ctr[C_QUEUE];
+      for (;;) {
+        const uint32_t b0 = (uint32_t)wave_atomic_add(queue, BATCH);
+        if (b0 >= nseg) break;
+        const uint32_t nb = min(BATCH, nseg - b0);
+        SlabCursor cur = reserve_slabs(ix, nb, nb);
+        for (uint32_t si = b0; si < b0 + nb; ++si) {
+          wave_sync();
+          repair_chain_u8<P::GL>(ix, a, p, a.seg[si], cur);
+        }
+        finish_slabs(ix, cur, C_PUB_REPAIR);
       }
-      finish_slabs(ix, cur, C_PUB_REPAIR);
+      // the last wave out resets the queue for the next launch
+      const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
+      if (lane_id() == 0 && done + 1 == total_waves()) {
+        atomicExch(queue, 0ull);
+        atomicExch(&ix.ctr[C_QDONE], 0ull);
+      }
       return;
     }
   }
+  SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
   MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   FOR_EACH_WAVE_ITEM(si, nseg) {
     wave_sync();
@@ -2595,17 +2676,60 @@ uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R) {
   return (uint32_t)((b + 15) & ~(size_t)15);
 }
 
+// Blocks of kernel f (block size threads, dynamic LDS lds) that are resident
+// on the whole device at once: a persistent launch larger than this runs its
+// waves in generations, each wave with the same share of the items, so the
+// last generation leaves the device partly idle. Cached per (kernel, shape).
+template <class F>
+static unsigned resident_blocks(F f, unsigned threads, size_t lds) {
+  struct Key {
+    const void* f;
+    unsigned threads;
+    size_t lds;
+    bool operator<(const Key& o) const {
+      return f != o.f ? f < o.f : threads != o.threads ? threads < o.threads : lds < o.lds;
+    }
+  };
+  static std::mutex mu;
+  static std::map<Key, unsigned> cache;
+  static int cus = 0;
+  const Key k{reinterpret_cast<const void*>(f), threads, lds};
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(k);
+  if (it != cache.end()) return it->second;
+  int dev = 0, per_cu = 0;
+  if (cus == 0 && (hipGetDevice(&dev) != hipSuccess ||
+                   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess))
+    cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, (int)threads, lds) != hipSuccess) per_cu = 0;
+  const unsigned r = cus > 0 && per_cu > 0 ? (unsigned)(per_cu * cus) : 0u;  // 0: unknown
+  cache[k] = r;
+  return r;
+}
+
+template <class F>
+static dim3 resident_grid(F f, unsigned grid, dim3 blk, size_t lds) {
+  const unsigned r = resident_blocks(f, blk.x, lds);
+  return dim3(r && grid > r ? r : grid);
+}
+
 template <class P>
 static void launch_maint_p(MaintKernel which, const Index& ix, const MaintArgs& a, unsigned grid, dim3 blk,
                            size_t lds, hipStream_t s) {
   switch (which) {
-    case MK_FORWARD: hipLaunchKernelGGL(k_forward<P>, dim3(grid), blk, lds, s, ix, a); break;
-    case MK_REVERSE: hipLaunchKernelGGL(k_reverse_apply<P>, dim3(grid), blk, lds, s, ix, a); break;
+    case MK_FORWARD:
+      hipLaunchKernelGGL(k_forward<P>, resident_grid(k_forward<P>, grid, blk, lds), blk, lds, s, ix, a);
+      break;
+    case MK_REVERSE:
+      hipLaunchKernelGGL(k_reverse_apply<P>, resident_grid(k_reverse_apply<P>, grid, blk, lds), blk, lds, s, ix, a);
+      break;
     case MK_REFINE:
-      hipLaunchKernelGGL(k_refine<P>, dim3(grid), blk, lds, s, ix, a);
+      hipLaunchKernelGGL(k_refine<P>, resident_grid(k_refine<P>, grid, blk, lds), blk, lds, s, ix, a);
       hipLaunchKernelGGL(k_refine_publish, dim3(grid), blk, 512u * (blk.x / 64u), s, ix, a);
       break;
-    case MK_REPAIR: hipLaunchKernelGGL(k_repair_apply<P>, dim3(grid), blk, lds, s, ix, a); break;
+    case MK_REPAIR:
+      hipLaunchKernelGGL(k_repair_apply<P>, resident_grid(k_repair_apply<P>, grid, blk, lds), blk, lds, s, ix, a);
+      break;
   }
 }
 
