@@ -189,12 +189,50 @@ __device__ inline uint32_t dot16(uint4 a, uint4 b, uint32_t acc) {
   return acc;
 }
 
-// sum over the G consecutive lanes of a group (G a power of two)
+// The value of lane l ^ J. Distances within a row of 16 lanes move by DPP
+// (quad permutes, row shifts and rotates: ALU latency, no LDS crossbar);
+// 16 and 32 go through ds_bpermute.
+template <int J>
+__device__ inline uint32_t lane_xor(uint32_t v) {
+  static_assert(J == 1 || J == 2 || J == 4 || J == 8 || J == 16 || J == 32, "lane distance");
+  if constexpr (J == 1) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);  // quad_perm 1,0,3,2
+  } else if constexpr (J == 2) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);  // quad_perm 2,3,0,1
+  } else if constexpr (J == 4) {
+    const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x104, 0xf, 0xf, false);  // row_shl:4
+    const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    return (threadIdx.x & 4u) ? dn : up;
+  } else if constexpr (J == 8) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);  // row_ror:8
+  } else {
+    return (uint32_t)__shfl_xor((int)v, J, 64);
+  }
+}
+template <int J>
+__device__ inline float lane_xor(float v) {
+  return __builtin_bit_cast(float, lane_xor<J>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int J>
+__device__ inline uint64_t lane_xor(uint64_t v) {
+  return ((uint64_t)lane_xor<J>((uint32_t)(v >> 32)) << 32) | lane_xor<J>((uint32_t)v);
+}
+
+// sum over the G consecutive lanes of a group (G a power of two), every lane
+// of the group ending with the same value
+template <int G, class T>
+__device__ inline T group_sum_t(T v) {
+  if constexpr (G > 1) v += lane_xor<1>(v);
+  if constexpr (G > 2) v += lane_xor<2>(v);
+  if constexpr (G > 4) v += lane_xor<4>(v);
+  if constexpr (G > 8) v += lane_xor<8>(v);
+  if constexpr (G > 16) v += lane_xor<16>(v);
+  if constexpr (G > 32) v += lane_xor<32>(v);
+  return v;
+}
 template <int G>
 __device__ inline uint32_t group_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return group_sum_t<G, uint32_t>(v);
 }
 
 // ---- visited table: exact ids, open addressing, may forget -----------------------

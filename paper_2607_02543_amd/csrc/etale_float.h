@@ -156,8 +156,7 @@ struct TravF {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         float dot = partial(q, w[u]);
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) dot += __shfl_xor(dot, o, 64);
+        dot = group_sum_t<G, float>(dot);
         const int vi = base + u * VPP + grp;
         if (c == 0 && vi < cnt) {
           ck[vi] = make_key(fkey(1.0f - sc[u] * dot), id[u]);
@@ -188,9 +187,7 @@ struct RowF {
       acc = __builtin_fmaf(a[t].z, b[t].z, acc);
       acc = __builtin_fmaf(a[t].w, b[t].w, acc);
     }
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) acc += __shfl_xor(acc, o, 64);
-    return acc;
+    return group_sum_t<G, float>(acc);
   }
 };
 

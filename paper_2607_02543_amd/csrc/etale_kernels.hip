@@ -1881,25 +1881,27 @@ __device__ inline void pool_fill(const Index& ix, const PoolLds& p, const uint32
 }
 
 // 64-lane bitonic sort of (key, value) pairs held one per lane, ascending
-__device__ inline void lane_bitonic_sort(uint64_t& key, uint32_t& val) {
+template <int K, int J>
+__device__ inline void lane_bitonic_step(uint64_t& key, uint32_t& val) {
   const int l = lane_id();
-#pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t olo = (uint32_t)__shfl_xor((int)(uint32_t)key, j, 64);
-      const uint32_t ohi = (uint32_t)__shfl_xor((int)(uint32_t)(key >> 32), j, 64);
-      const uint32_t ov = (uint32_t)__shfl_xor((int)val, j, 64);
-      const uint64_t ok = ((uint64_t)ohi << 32) | olo;
-      const bool up = (l & k) == 0, lower = (l & j) == 0;
-      const bool take = lower == up ? ok < key : ok > key;
-      if (take) {
-        key = ok;
-        val = ov;
-      }
-    }
+  const uint64_t ok = lane_xor<J>(key);
+  const uint32_t ov = lane_xor<J>(val);
+  const bool up = (l & K) == 0, lower = (l & J) == 0;
+  const bool take = lower == up ? ok < key : ok > key;
+  if (take) {
+    key = ok;
+    val = ov;
   }
+  if constexpr (J > 1) lane_bitonic_step<K, J / 2>(key, val);
 }
+
+template <int K>
+__device__ inline void lane_bitonic_stage(uint64_t& key, uint32_t& val) {
+  lane_bitonic_step<K, K / 2>(key, val);
+  if constexpr (K < 64) lane_bitonic_stage<K * 2>(key, val);
+}
+
+__device__ inline void lane_bitonic_sort(uint64_t& key, uint32_t& val) { lane_bitonic_stage<2>(key, val); }
 
 // RobustPrune(self, candidate slots cs[0..m)) into out[0..return); m <= 64.
 // Candidates are ranked in registers (one per lane); during the selection each
