@@ -1464,19 +1464,36 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
       for (uint32_t k = 0; k < cap && rest; ++k) rest &= rest - 1ull;
       alive &= ~rest;
     }
-    uint32_t cnt = 0, from = 0, ns = 0;
-    while (cnt < R) {
-      const uint64_t m = alive & (~0ull << from);
-      if (!m) break;
-      const uint32_t j = (uint32_t)__builtin_ctzll(m);
-      const uint32_t sj = (uint32_t)__shfl((int)cs, (int)j, 64);
-      if ((uint32_t)l == cnt) ns = sj;
-      ++cnt;
-      from = j + 1;
-      if (cnt == R) break;
-      const bool kill = (uint32_t)l > j && ((alive >> l) & 1ull) &&
-                        (uint64_t)ix.a2 * c.M[sj * c.S + cs] <= (uint64_t)ix.b2 * (uint64_t)cdw;
-      alive &= ~ballot(kill);
+    // the selection in order, four live candidates per step (their distances
+    // read together, then decided in order; one killed by an earlier one of
+    // the four is skipped)
+    uint32_t cnt = 0, ns = 0;
+    const uint64_t thr = (uint64_t)ix.b2 * (uint64_t)cdw;
+    uint64_t rest = alive;
+    while (cnt < R && rest) {
+      int j[4];
+      uint32_t d[4];
+      uint64_t m = rest;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        j[k] = m ? (int)__builtin_ctzll(m) : -1;
+        if (m) m &= m - 1ull;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        d[k] = j[k] >= 0 ? c.M[(uint32_t)__builtin_amdgcn_readlane((int)cs, j[k]) * c.S + cs] : 0u;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (j[k] < 0 || cnt >= R) break;
+        if (!((rest >> j[k]) & 1ull)) continue;
+        if ((uint32_t)l == cnt) ns = (uint32_t)__builtin_amdgcn_readlane((int)cs, j[k]);
+        ++cnt;
+        const uint64_t above = j[k] == 63 ? 0ull : (~0ull << (j[k] + 1));
+        const uint64_t kill = ballot((uint64_t)ix.a2 * d[k] <= thr) & rest & above;
+        rest &= ~kill & ~(1ull << j[k]);
+      }
+      const int last = j[3] >= 0 ? j[3] : 63;
+      rest &= last == 63 ? 0ull : (~0ull << (last + 1));
     }
     // the kept candidates, in order, are the new list
     wave_sync();
@@ -1931,20 +1948,37 @@ __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const u
   const uint32_t csl = (uint32_t)l < mm ? p.sorted[l] : 0u;
   const uint32_t cdw = (uint32_t)l < mm ? p.dw[csl] : 0u;
   uint64_t alive = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
-  uint32_t cnt = 0, from = 0, keep_slot = 0;
-  while (cnt < ix.R) {
-    const uint64_t mk = from < 64 ? (alive & (~0ull << from)) : 0ull;
-    if (!mk) break;
-    const uint32_t j = (uint32_t)__builtin_ctzll(mk);
-    const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)csl, (int)j);
-    if ((uint32_t)l == cnt) keep_slot = sj;
-    ++cnt;
-    from = j + 1;
-    if (cnt == ix.R) break;
-    const uint32_t d = p.M[tri(sj, csl)];
-    const bool kill = (uint32_t)l > j && ((alive >> l) & 1ull) &&
-                      (uint64_t)ix.a2 * d <= (uint64_t)ix.b2 * (uint64_t)cdw;
-    alive &= ~ballot(kill);
+  uint32_t cnt = 0, keep_slot = 0;
+  // the selection in order of rank; the distances from the next four live
+  // candidates are read together and the four are then decided in order
+  // (one killed by an earlier one of the four is skipped)
+  const uint64_t thr = (uint64_t)ix.b2 * (uint64_t)cdw;
+  uint64_t rest = alive;  // live candidates not yet decided
+  while (cnt < ix.R && rest) {
+    int j[4];
+    uint32_t d[4];
+    uint64_t m = rest;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      j[k] = m ? (int)__builtin_ctzll(m) : -1;
+      if (m) m &= m - 1ull;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      d[k] = j[k] >= 0 ? p.M[tri((uint32_t)__builtin_amdgcn_readlane((int)csl, j[k]), csl)] : 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (j[k] < 0 || cnt >= ix.R) break;
+      if (!((rest >> j[k]) & 1ull)) continue;  // killed by an earlier one of the four
+      if ((uint32_t)l == cnt) keep_slot = (uint32_t)__builtin_amdgcn_readlane((int)csl, j[k]);
+      ++cnt;
+      const uint64_t above = j[k] == 63 ? 0ull : (~0ull << (j[k] + 1));
+      const uint64_t kill = ballot((uint64_t)ix.a2 * d[k] <= thr) & rest & above;
+      rest &= ~kill & ~(1ull << j[k]);
+    }
+    // every candidate up to the last of the four is decided
+    const int last = j[3] >= 0 ? j[3] : 63;
+    rest &= last == 63 ? 0ull : (~0ull << (last + 1));
   }
   wave_sync();
   if ((uint32_t)l < cnt) out[l] = keep_slot;
