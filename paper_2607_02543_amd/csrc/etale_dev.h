@@ -236,26 +236,33 @@ __device__ inline uint32_t group_sum(uint32_t v) {
 }
 
 // ---- visited table: exact ids, open addressing, may forget -----------------------
-// A lookup that finds the id reports VT_SEEN; a table too crowded to take the
-// id reports VT_CROWDED without storing it. Forgetting only costs a repeated
-// distance evaluation: the list merge drops keys already listed, and a key
-// rejected or evicted earlier is rejected again (the list's worst key never
-// increases), so results do not depend on the table size. Two lanes that
-// insert the same id in one call cannot both get VT_NEW (the compare-and-swap
-// or the later lookup sees the other's id), but both can get VT_CROWDED: the
-// caller removes such duplicates from its batch.
-constexpr int VT_PROBES = 8;
+// Buckets of four slots, each read as one 16-byte LDS load: an id is looked
+// for in its bucket and the next one; a miss takes the first empty slot of
+// the bucket by compare-and-swap (re-reading the bucket when another id won
+// the slot). A lookup that finds the id reports VT_SEEN; a table too crowded
+// to take the id reports VT_CROWDED without storing it. Forgetting only costs
+// a repeated distance evaluation: the list merge drops keys already listed,
+// and a key rejected or evicted earlier is rejected again (the list's worst
+// key never increases), so results do not depend on the table size. Two
+// lanes that insert the same id in one call cannot both get VT_NEW (they try
+// the same slots in the same order), but both can get VT_CROWDED: the caller
+// removes such duplicates from its batch.
+constexpr int VT_BUCKETS = 2;  // buckets looked at per id (8 slots)
 enum VtResult : uint32_t { VT_SEEN = 0, VT_NEW = 1, VT_CROWDED = 2 };
 
 __device__ inline uint32_t vt_insert(uint32_t* vt, uint32_t mask, uint32_t id) {
-  uint32_t h = (id * 2654435761u) & mask;
+  const uint32_t bmask = (mask + 1u) / 4u - 1u;
+  const uint32_t b = (id * 2654435761u) & bmask;
 #pragma unroll 1
-  for (int i = 0; i < VT_PROBES; ++i) {
-    uint32_t s = (h + (uint32_t)i) & mask;
-    uint32_t v = vt[s];
-    if (v == id) return VT_SEEN;
-    if (v == NONE) {
-      uint32_t prev = atomicCAS(&vt[s], NONE, id);
+  for (int k = 0; k < VT_BUCKETS; ++k) {
+    uint32_t* slot = vt + 4u * ((b + (uint32_t)k) & bmask);
+#pragma unroll 1
+    for (int tries = 0; tries < 4; ++tries) {
+      const uint4 w = *reinterpret_cast<const uint4*>(slot);
+      if (w.x == id || w.y == id || w.z == id || w.w == id) return VT_SEEN;
+      const int e = w.x == NONE ? 0 : w.y == NONE ? 1 : w.z == NONE ? 2 : w.w == NONE ? 3 : -1;
+      if (e < 0) break;  // full: the next bucket
+      const uint32_t prev = atomicCAS(&slot[e], NONE, id);
       if (prev == NONE) return VT_NEW;
       if (prev == id) return VT_SEEN;
     }
@@ -380,22 +387,29 @@ __device__ inline void dist_batch_u8(const Index& ix, uint4 qf, uint32_t qq, con
   const int l = lane_id();
   const int c = l % G, grp = l / G;
   for (int base = 0; base < cnt; base += 4 * VPP) {
+    // sub-batches past cnt are skipped (a uniform branch), all loads of the
+    // used ones are issued before any is used
+    const int used = min(4, (cnt - base + VPP - 1) / VPP);
     uint4 v[4];
     uint32_t id[4];
     uint64_t r[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       int vi = base + u * VPP + grp;
-      id[u] = vi < cnt ? ids[vi] : NONE;
+      id[u] = NONE;
       v[u] = make_uint4(0, 0, 0, 0);
       r[u] = 0;
-      if (id[u] != NONE) {
-        v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim)[c];
-        if (cr && c == 0) r[u] = load_ref(ix, id[u]);
+      if (u < used) {
+        id[u] = vi < cnt ? ids[vi] : NONE;
+        if (id[u] != NONE) {
+          v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim)[c];
+          if (cr && c == 0) r[u] = load_ref(ix, id[u]);
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
+      if (u >= used) break;
       uint32_t qx = group_sum<G>(dot16(qf, v[u], 0u));
       uint32_t xx = group_sum<G>(dot16(v[u], v[u], 0u));
       int vi = base + u * VPP + grp;

@@ -846,6 +846,19 @@ __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* ba
   search_finish<TP>(ix, a, qi, qrow, cl.keys(), cl.refs(), cl.n, ci, ck, nexp, ndist);
 }
 
+// The ids in the slabs of one or two list entries (reference words r0, r1),
+// side by side: lanes [0, R) read the first slab, lanes [R, 2R) the second.
+__device__ inline uint32_t expansion_ids(const Index& ix, uint64_t r0, uint64_t r1, bool two) {
+  const uint32_t l = (uint32_t)lane_id(), R = ix.R;
+  const bool second = l >= R;
+  const uint64_t r = second ? r1 : r0;
+  const uint32_t slot = second ? l - R : l;
+  const uint32_t deg = (second && !two) ? 0u : ref_deg(r), s = ref_slab(r);
+  uint32_t nid = NONE;
+  if (slot < deg && s < ix.P) nid = ix.slabs[(size_t)s * 2u * R + slot];
+  return nid < ix.cap ? nid : NONE;
+}
+
 // The same search for L <= 64 with the list in registers: lane i holds entry
 // i (key, reference word, expanded flag), entries at or past n hold KEY_NONE.
 // The next entries to expand are the lowest lanes of one ballot, and each
@@ -878,6 +891,11 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
   uint32_t ndist = (uint32_t)ix.ctr[C_N_ENTRIES];  // scored by the start-set scan
   uint32_t nexp = 0;
   const uint32_t R = ix.R;
+  // slab ids of the entries the next step is expected to expand, read while
+  // this step's vectors are in flight; used when the merge leaves those
+  // entries first (their keys identify them)
+  uint32_t pre_nid = NONE;
+  uint64_t pre_k0 = KEY_NONE, pre_k1 = KEY_NONE;
   while (nexp < a.vcap) {
     // up to W best unexpanded entries, within the visit cap
     uint64_t open = ballot(l < n && lx == 0);
@@ -885,6 +903,7 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     const int j0 = (int)__builtin_ctzll(open);
     open &= open - 1;
     const int j1 = (a.W > 1 && nexp + 1 < a.vcap && open) ? (int)__builtin_ctzll(open) : -1;
+    if (j1 >= 0) open &= open - 1;  // now the open entries after both
     const uint64_t key0 = bcast_lane64(lk, j0), r0 = bcast_lane64(lr, j0);
     uint64_t key1 = 0, r1 = 0;
     if (j1 >= 0) {
@@ -898,13 +917,19 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     }
     nexp += j1 >= 0 ? 2u : 1u;
     // their slabs side by side: lanes [w*R, (w+1)*R) read the w-th
-    const bool second = (uint32_t)l >= R;
-    const uint64_t r = second ? r1 : r0;
-    const uint32_t slot = second ? (uint32_t)l - R : (uint32_t)l;
-    const uint32_t deg = (second && j1 < 0) ? 0u : ref_deg(r), s = ref_slab(r);
-    uint32_t nid = NONE;
-    if (slot < deg && s < ix.P) nid = ix.slabs[(size_t)s * 2u * R + slot];
-    if (nid >= ix.cap) nid = NONE;
+    const uint32_t nid = (key0 == pre_k0 && (j1 >= 0 ? key1 : KEY_NONE) == pre_k1)
+                             ? pre_nid
+                             : expansion_ids(ix, r0, r1, j1 >= 0);
+    pre_k0 = pre_k1 = KEY_NONE;
+    pre_nid = NONE;
+    if (nexp < a.vcap && open) {
+      const int p0 = (int)__builtin_ctzll(open);
+      const uint64_t o2 = open & (open - 1);
+      const int p1 = (a.W > 1 && nexp + 1 < a.vcap && o2) ? (int)__builtin_ctzll(o2) : -1;
+      pre_k0 = bcast_lane64(lk, p0);
+      pre_k1 = p1 >= 0 ? bcast_lane64(lk, p1) : KEY_NONE;
+      pre_nid = expansion_ids(ix, bcast_lane64(lr, p0), p1 >= 0 ? bcast_lane64(lr, p1) : 0ull, p1 >= 0);
+    }
     const uint32_t vr = nid != NONE ? vt_insert(vt, a.vt_mask, nid) : VT_SEEN;
     bool fresh = vr != VT_SEEN;
     // a crowded table can pass an id listed in both slabs twice, or one
