@@ -103,7 +103,7 @@ typedef struct {
   uint32_t rerank_mult;      /* bf16 / FP8 traversal: re-rank rerank_mult*k results in FP32 (k*mult <= 64);
                                 0 returns the traversal distances themselves */
   uint32_t copies;           /* extra traversal copies to keep (1: bf16, 2: FP8), for query-side switching */
-  uint32_t W;                /* expansions per search iteration: 1, or 2 when 2R <= 64 */
+  uint32_t W;                /* entries expanded per search step: 1, 2 or 4 (2 and 4 need 2R <= 64) */
   uint32_t reserved;
   uint64_t id_capacity;      /* size of the id space */
   uint64_t slab_capacity;    /* slabs in the pool */

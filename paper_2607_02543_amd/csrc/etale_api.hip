@@ -225,7 +225,7 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
     sa.vcap = vcap;
     sa.vt_mask = ix->cfg.vt_slots - 1;
     sa.W = ix->cfg.W;
-    sa.lds_per_wave = search_lds_per_wave(L, ix->cfg.vt_slots);
+    sa.lds_per_wave = search_lds_per_wave(L, ix->cfg.vt_slots, ix->cfg.W);
     sa.init_keys = ix->scan_keys;
     sa.init_n = ix->scan_n;
     sa.init_stride = L;
@@ -499,7 +499,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   if (c.prune_cap < c.R || c.prune_cap > 2048) return ETALE_EINVAL;
   if (c.n_entry < 1 || c.n_entry > 16384) return ETALE_EINVAL;  // a start set is scored in registers
   if (c.publish_attempts < 1 || c.max_batch < 1) return ETALE_EINVAL;
-  if (c.W < 1 || c.W > 2 || c.W * c.R > 64) return ETALE_EINVAL;
+  if ((c.W != 1 && c.W != 2 && c.W != 4) || (c.W > 1 && 2 * c.R > 64)) return ETALE_EINVAL;
   if (!pow2(c.vt_slots) || c.vt_slots < 64 || c.vt_slots > 16384) return ETALE_EINVAL;
   if (c.waves_per_block != 1 && c.waves_per_block != 2 && c.waves_per_block != 4) return ETALE_EINVAL;
   if (c.id_capacity < 1 || c.id_capacity >= 0xFFFFFFFFull || c.slab_capacity < 1 || c.slab_capacity >= 0xFFFFFFFFull)
@@ -513,7 +513,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
     const uint32_t worst_nmax[] = {probe.vcap_build, c.R + 1, 2 * c.R, c.R + c.R * c.R};
     for (uint32_t nm : worst_nmax)
       if (maint_args(&probe, nm).lds_per_wave > 65536u) return ETALE_EINVAL;
-    if (search_lds_per_wave(SCAN_L_MAX, c.vt_slots) > 65536u) return ETALE_EINVAL;
+    if (search_lds_per_wave(SCAN_L_MAX, c.vt_slots, c.W) > 65536u) return ETALE_EINVAL;
     if (4 * scan_select_lds_per_wave(std::max(SCAN_L_MAX, probe.vcap_build)) > 65536u) return ETALE_EINVAL;
   }
 
@@ -1104,7 +1104,7 @@ etale_status etale_set_search_knobs(etale_t ix, uint32_t waves_per_block, uint32
   if ((waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4) || !pow2(vt_slots) || vt_slots < 64 ||
       vt_slots > 16384)
     return fail(ix, ETALE_EINVAL, "search knobs: waves 1/2/4, slots a power of two in 64..16384");
-  if (search_lds_per_wave(SCAN_L_MAX, vt_slots) > 65536u) return fail(ix, ETALE_EINVAL, "search knobs: LDS");
+  if (search_lds_per_wave(SCAN_L_MAX, vt_slots, ix->cfg.W) > 65536u) return fail(ix, ETALE_EINVAL, "search knobs: LDS");
   ix->cfg.waves_per_block = waves_per_block;
   ix->cfg.vt_slots = vt_slots;
   return ETALE_OK;
@@ -1152,7 +1152,7 @@ etale_status etale_autotune(etale_t ix, const void* q_dev, uint64_t nq, uint32_t
   for (uint32_t w : waves)
     for (uint32_t v : slots) {
       if (st) break;
-      if (search_lds_per_wave(L, v) > 65536u) continue;
+      if (search_lds_per_wave(L, v, ix->cfg.W) > 65536u) continue;
       float ms = 0.f;
       st = time_one(w, v, &ms);
       if (!st && ms < best) {

@@ -749,6 +749,19 @@ __device__ inline void search_finish(const Index& ix, const SearchArgs& a, uint3
   }
 }
 
+// The ids in the slabs of one or two list entries (reference words r0, r1),
+// side by side: lanes [0, R) read the first slab, lanes [R, 2R) the second.
+__device__ inline uint32_t expansion_ids(const Index& ix, uint64_t r0, uint64_t r1, bool two) {
+  const uint32_t l = (uint32_t)lane_id(), R = ix.R;
+  const bool second = l >= R;
+  const uint64_t r = second ? r1 : r0;
+  const uint32_t slot = second ? l - R : l;
+  const uint32_t deg = (second && !two) ? 0u : ref_deg(r), s = ref_slab(r);
+  uint32_t nid = NONE;
+  if (slot < deg && s < ix.P) nid = ix.slabs[(size_t)s * 2u * R + slot];
+  return nid < ix.cap ? nid : NONE;
+}
+
 // One wavefront per query, starting from the initial list the start-set scan
 // left (the L best members of the entry set). This variant (L > 64) keeps the
 // list in LDS. Per-wave LDS: the double-buffered candidate list (keys,
@@ -795,50 +808,50 @@ __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* ba
   uint32_t ndist = (uint32_t)ix.ctr[C_N_ENTRIES];  // scored by the start-set scan
   uint32_t nexp = 0;
   {
-    const uint32_t R = ix.R;
     while (nexp < a.vcap) {
-      // up to W best unexpanded entries, within the visit cap; their slabs are
-      // read side by side (lanes [w*R, (w+1)*R) read the w-th)
-      const int j0 = list_first_open(cl);
-      if (j0 < 0) break;
-      int j1 = -1;
-      if (a.W > 1 && nexp + 1 < a.vcap) j1 = list_first_open(cl, j0 + 1);
-      const uint64_t key0 = cl.keys()[j0];
-      const uint64_t r0 = cl.refs()[j0];
-      uint64_t key1 = 0, r1 = 0;
-      if (j1 >= 0) {
-        key1 = cl.keys()[j1];
-        r1 = cl.refs()[j1];
-      }
-      if (l == 0) {
-        cl.flags()[j0] = 1;
-        if (a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp] = key0;
-        if (j1 >= 0) {
-          cl.flags()[j1] = 1;
-          if (a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp + 1] = key1;
+      // up to W best unexpanded entries, within the visit cap, all picked
+      // before any neighbor is merged; their slabs are read two at a time side
+      // by side (lanes [w*R, (w+1)*R) read the w-th), each pair scored and
+      // merged in turn (the merge keeps the L smallest of the union, so the
+      // result is that of one merge of all)
+      uint64_t pk[4], pr[4];
+      uint32_t np = 0;
+      int from = 0;
+      for (uint32_t k = 0; k < 4; ++k) {
+        pk[k] = KEY_NONE;
+        pr[k] = 0;
+        if (k > 0 && (k >= a.W || nexp + k >= a.vcap)) continue;
+        const int j = list_first_open(cl, from);
+        if (j < 0) break;
+        from = j + 1;
+        pk[k] = cl.keys()[j];
+        pr[k] = cl.refs()[j];
+        if (l == 0) {
+          cl.flags()[j] = 1;
+          if (a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp + k] = pk[k];
         }
+        ++np;
       }
-      nexp += j1 >= 0 ? 2u : 1u;
-      const bool second = (uint32_t)l >= R;
-      const uint64_t r = second ? r1 : r0;
-      const uint32_t slot = second ? (uint32_t)l - R : (uint32_t)l;
-      const uint32_t deg = (second && j1 < 0) ? 0u : ref_deg(r), s = ref_slab(r);
-      uint32_t nid = NONE;
-      if (slot < deg && s < ix.P) nid = ix.slabs[(size_t)s * 2u * R + slot];
-      const uint32_t vr = nid != NONE ? vt_insert(vt, a.vt_mask, nid) : VT_SEEN;
-      bool fresh = vr != VT_SEEN;
-      // a crowded table can pass an id listed in both slabs twice; the merge
-      // needs distinct candidates
-      fresh = drop_crowded_twins(nid, vr, fresh);
-      const uint64_t m = ballot(fresh);
-      if (fresh) ci[lanes_below(m)] = nid;
-      const int cnt = __popcll(m);
+      if (np == 0) break;
       wave_sync();
-      if (cnt) {
-        TP::dist_batch(ix, qv, ci, cnt, ck, cr);
+      nexp += np;
+      for (uint32_t h = 0; 2 * h < np; ++h) {
+        const uint32_t nid = expansion_ids(ix, pr[2 * h], pr[2 * h + 1], 2 * h + 1 < np);
+        const uint32_t vr = nid != NONE ? vt_insert(vt, a.vt_mask, nid) : VT_SEEN;
+        bool fresh = vr != VT_SEEN;
+        // a crowded table can pass an id listed in both slabs twice; the merge
+        // needs distinct candidates
+        fresh = drop_crowded_twins(nid, vr, fresh);
+        const uint64_t m = ballot(fresh);
+        if (fresh) ci[lanes_below(m)] = nid;
+        const int cnt = __popcll(m);
         wave_sync();
-        list_merge(cl, ck, cr, cnt);
-        ndist += (uint32_t)cnt;
+        if (cnt) {
+          TP::dist_batch(ix, qv, ci, cnt, ck, cr);
+          wave_sync();
+          list_merge(cl, ck, cr, cnt);
+          ndist += (uint32_t)cnt;
+        }
       }
     }
   }
@@ -846,32 +859,55 @@ __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* ba
   search_finish<TP>(ix, a, qi, qrow, cl.keys(), cl.refs(), cl.n, ci, ck, nexp, ndist);
 }
 
-// The ids in the slabs of one or two list entries (reference words r0, r1),
-// side by side: lanes [0, R) read the first slab, lanes [R, 2R) the second.
-__device__ inline uint32_t expansion_ids(const Index& ix, uint64_t r0, uint64_t r1, bool two) {
-  const uint32_t l = (uint32_t)lane_id(), R = ix.R;
-  const bool second = l >= R;
-  const uint64_t r = second ? r1 : r0;
-  const uint32_t slot = second ? l - R : l;
-  const uint32_t deg = (second && !two) ? 0u : ref_deg(r), s = ref_slab(r);
-  uint32_t nid = NONE;
-  if (slot < deg && s < ix.P) nid = ix.slabs[(size_t)s * 2u * R + slot];
-  return nid < ix.cap ? nid : NONE;
+// Crowded-table twins of a step with H halves of 64 slab entries (half h
+// holds the slabs of the step's entries 2h and 2h + 1, in rank order). A
+// crowded lane drops its id when an earlier half, a lane of its own half that
+// stored it or a lower crowded lane of its own half offers it too, or when it
+// is listed (lanes below n hold the list's keys lk).
+template <int H>
+__device__ inline void drop_crowded_twins_h(const uint32_t (&nid)[H], const uint32_t (&vr)[H], bool (&fresh)[H],
+                                            uint64_t lk, int n) {
+  const int l = lane_id();
+  uint64_t crowded[H], fr[H];
+  uint64_t any = 0;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    crowded[h] = ballot(vr[h] == VT_CROWDED);
+    fr[h] = ballot(fresh[h]);
+    any |= crowded[h];
+  }
+  if (!any) return;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    for (uint64_t cm = crowded[h] & fr[h]; cm; cm &= cm - 1) {
+      const int c = (int)__builtin_ctzll(cm);
+      const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)nid[h], c);
+      const uint64_t others = ballot(nid[h] == id) & fr[h] & ~(1ull << c);
+      bool drop = (others & ((1ull << c) - 1ull)) != 0 || (others & ~crowded[h]) != 0;
+#pragma unroll
+      for (int e = 0; e < h; ++e) drop = drop || (ballot(nid[e] == id) & fr[e]) != 0;
+      drop = drop || ballot(l < n && key_id(lk) == id) != 0;
+      if (drop && l == c) fresh[h] = false;
+    }
+  }
 }
 
 // The same search for L <= 64 with the list in registers: lane i holds entry
 // i (key, reference word, expanded flag), entries at or past n hold KEY_NONE.
 // The next entries to expand are the lowest lanes of one ballot, and each
 // accepted candidate is inserted at its rank (a ballot count) by shifting the
-// lanes above it up one, so the list never leaves the registers. Per-wave
-// LDS: one batch of candidates and the visited table.
-template <class TP>
+// lanes above it up one, so the list never leaves the registers. A step
+// expands up to W entries (H = 2 halves of 64 slab entries when W = 4), scores
+// all their fresh neighbors in one batch and merges them. Per-wave LDS: one
+// batch of candidates (64H) and the visited table.
+template <class TP, int H>
 __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char* base, uint32_t qi) {
+  constexpr int WMAX = 2 * H;
   const int l = lane_id();
   uint64_t* ck = reinterpret_cast<uint64_t*>(base);
-  uint64_t* cr = ck + 64;
-  uint32_t* ci = reinterpret_cast<uint32_t*>(cr + 64);
-  uint32_t* vt = ci + 64;
+  uint64_t* cr = ck + 64 * H;
+  uint32_t* ci = reinterpret_cast<uint32_t*>(cr + 64 * H);
+  uint32_t* vt = ci + 64 * H;
   const int L = (int)a.L;
   const void* qrow = a.mode == MODE_QUERY ? (const void*)((const uint8_t*)a.q + (size_t)qi * TP::query_bytes(ix))
                                           : TP::stored_row(ix, a.first + qi);
@@ -890,87 +926,119 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
   wave_sync();
   uint32_t ndist = (uint32_t)ix.ctr[C_N_ENTRIES];  // scored by the start-set scan
   uint32_t nexp = 0;
-  const uint32_t R = ix.R;
   // slab ids of the entries the next step is expected to expand, read while
   // this step's vectors are in flight; used when the merge leaves those
   // entries first (their keys identify them)
-  uint32_t pre_nid = NONE;
-  uint64_t pre_k0 = KEY_NONE, pre_k1 = KEY_NONE;
+  uint32_t pre_nid[H];
+  uint64_t pre_k[WMAX];
+#pragma unroll
+  for (int h = 0; h < H; ++h) pre_nid[h] = NONE;
+#pragma unroll
+  for (int k = 0; k < WMAX; ++k) pre_k[k] = KEY_NONE;
   while (nexp < a.vcap) {
     // up to W best unexpanded entries, within the visit cap
     uint64_t open = ballot(l < n && lx == 0);
     if (!open) break;
-    const int j0 = (int)__builtin_ctzll(open);
-    open &= open - 1;
-    const int j1 = (a.W > 1 && nexp + 1 < a.vcap && open) ? (int)__builtin_ctzll(open) : -1;
-    if (j1 >= 0) open &= open - 1;  // now the open entries after both
-    const uint64_t key0 = bcast_lane64(lk, j0), r0 = bcast_lane64(lr, j0);
-    uint64_t key1 = 0, r1 = 0;
-    if (j1 >= 0) {
-      key1 = bcast_lane64(lk, j1);
-      r1 = bcast_lane64(lr, j1);
+    uint64_t key[WMAX], ref[WMAX];
+    uint32_t np = 0;
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+      key[k] = KEY_NONE;
+      ref[k] = 0;
+      if (open && (k == 0 || ((uint32_t)k < a.W && nexp + (uint32_t)k < a.vcap))) {
+        const int j = (int)__builtin_ctzll(open);
+        open &= open - 1;  // then the open entries after the picked ones
+        key[k] = bcast_lane64(lk, j);
+        ref[k] = bcast_lane64(lr, j);
+        if (l == j) lx = 1;
+        if (l == 0 && a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp + (uint32_t)k] = key[k];
+        ++np;
+      }
     }
-    if (l == j0 || l == j1) lx = 1;
-    if (l == 0 && a.mode == MODE_INSERT) {
-      a.vis_keys[(size_t)qi * a.vcap + nexp] = key0;
-      if (j1 >= 0) a.vis_keys[(size_t)qi * a.vcap + nexp + 1] = key1;
-    }
-    nexp += j1 >= 0 ? 2u : 1u;
-    // their slabs side by side: lanes [w*R, (w+1)*R) read the w-th
-    const uint32_t nid = (key0 == pre_k0 && (j1 >= 0 ? key1 : KEY_NONE) == pre_k1)
-                             ? pre_nid
-                             : expansion_ids(ix, r0, r1, j1 >= 0);
-    pre_k0 = pre_k1 = KEY_NONE;
-    pre_nid = NONE;
+    nexp += np;
+    // the slabs of entries 2h, 2h + 1 side by side in half h: lanes
+    // [w*R, (w+1)*R) read the w-th
+    uint32_t nid[H];
+    bool hit = true;
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) hit = hit && key[k] == pre_k[k];
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+      nid[h] = hit ? pre_nid[h] : expansion_ids(ix, ref[2 * h], ref[2 * h + 1], key[2 * h + 1] != KEY_NONE);
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) pre_k[k] = KEY_NONE;
+#pragma unroll
+    for (int h = 0; h < H; ++h) pre_nid[h] = NONE;
     if (nexp < a.vcap && open) {
-      const int p0 = (int)__builtin_ctzll(open);
-      const uint64_t o2 = open & (open - 1);
-      const int p1 = (a.W > 1 && nexp + 1 < a.vcap && o2) ? (int)__builtin_ctzll(o2) : -1;
-      pre_k0 = bcast_lane64(lk, p0);
-      pre_k1 = p1 >= 0 ? bcast_lane64(lk, p1) : KEY_NONE;
-      pre_nid = expansion_ids(ix, bcast_lane64(lr, p0), p1 >= 0 ? bcast_lane64(lr, p1) : 0ull, p1 >= 0);
+      uint64_t pref[WMAX];
+      uint64_t o = open;
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k) {
+        pref[k] = 0;
+        if (o && (k == 0 || ((uint32_t)k < a.W && nexp + (uint32_t)k < a.vcap))) {
+          const int j = (int)__builtin_ctzll(o);
+          o &= o - 1;
+          pre_k[k] = bcast_lane64(lk, j);
+          pref[k] = bcast_lane64(lr, j);
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+        pre_nid[h] = expansion_ids(ix, pref[2 * h], pref[2 * h + 1], pre_k[2 * h + 1] != KEY_NONE);
     }
-    const uint32_t vr = nid != NONE ? vt_insert(vt, a.vt_mask, nid) : VT_SEEN;
-    bool fresh = vr != VT_SEEN;
-    // a crowded table can pass an id listed in both slabs twice, or one
-    // already listed; the insertion below needs distinct, unlisted candidates
-    fresh = drop_crowded_twins(nid, vr, fresh, lk, n);
-    const uint64_t m = ballot(fresh);
-    if (fresh) ci[lanes_below(m)] = nid;
-    const int cnt = __popcll(m);
+    uint32_t vr[H];
+    bool fresh[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      vr[h] = nid[h] != NONE ? vt_insert(vt, a.vt_mask, nid[h]) : VT_SEEN;
+      fresh[h] = vr[h] != VT_SEEN;
+    }
+    // a crowded table can pass an id twice (two slabs list it) or one already
+    // listed; the insertion below needs distinct, unlisted candidates
+    drop_crowded_twins_h<H>(nid, vr, fresh, lk, n);
+    int cnt = 0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const uint64_t m = ballot(fresh[h]);
+      if (fresh[h]) ci[cnt + (int)lanes_below(m)] = nid[h];
+      cnt += __popcll(m);
+    }
     wave_sync();
     if (!cnt) continue;
     TP::dist_batch(ix, qv, ci, cnt, ck, cr);
     wave_sync();
     ndist += (uint32_t)cnt;
     // merge: the candidates below the current worst entry, each at its rank
-    uint64_t cand = KEY_NONE, cref = 0;
-    if (l < cnt) {
-      cand = ck[l];
-      cref = cr[l];
-    }
     uint64_t worst = n == L ? bcast_lane64(lk, L - 1) : KEY_NONE;
-    for (uint64_t acc = ballot(l < cnt && cand < worst); acc; acc &= acc - 1) {
-      const int c = (int)__builtin_ctzll(acc);
-      const uint64_t key = bcast_lane64(cand, c);
-      if (key >= worst) continue;  // the list filled up or improved meanwhile
-      const uint64_t rf = bcast_lane64(cref, c);
-      const int pos = __popcll(ballot(lk < key));
-      // shift lanes above pos up by one, then place the candidate at pos
-      const uint64_t sk = lane_shr1_64(lk), sr = lane_shr1_64(lr);
-      const uint32_t sx = lane_shr1(lx);
-      if (l > pos) {
-        lk = sk;
-        lr = sr;
-        lx = sx;
-      } else if (l == pos) {
-        lk = key;
-        lr = rf;
-        lx = 0;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      uint64_t cand = KEY_NONE, cref = 0;
+      if (64 * h + l < cnt) {
+        cand = ck[64 * h + l];
+        cref = cr[64 * h + l];
       }
-      if (l >= L) lk = KEY_NONE;
-      n = min(n + 1, L);
-      worst = n == L ? bcast_lane64(lk, L - 1) : KEY_NONE;
+      for (uint64_t acc = ballot(64 * h + l < cnt && cand < worst); acc; acc &= acc - 1) {
+        const int c = (int)__builtin_ctzll(acc);
+        const uint64_t kc = bcast_lane64(cand, c);
+        if (kc >= worst) continue;  // the list filled up or improved meanwhile
+        const uint64_t rf = bcast_lane64(cref, c);
+        const int pos = __popcll(ballot(lk < kc));
+        // shift lanes above pos up by one, then place the candidate at pos
+        const uint64_t sk = lane_shr1_64(lk), sr = lane_shr1_64(lr);
+        const uint32_t sx = lane_shr1(lx);
+        if (l > pos) {
+          lk = sk;
+          lr = sr;
+          lx = sx;
+        } else if (l == pos) {
+          lk = kc;
+          lr = rf;
+          lx = 0;
+        }
+        if (l >= L) lk = KEY_NONE;
+        n = min(n + 1, L);
+        worst = n == L ? bcast_lane64(lk, L - 1) : KEY_NONE;
+      }
     }
   }
   // the list to LDS for the shared result stage (the candidate scratch is free)
@@ -980,7 +1048,7 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
   search_finish<TP>(ix, a, qi, qrow, ck, cr, n, ci, ck, nexp, ndist);
 }
 
-template <class TP, bool RL>
+template <class TP, bool RL, int H>
 __device__ inline void search_kernel(const Index& ix, SearchArgs& a, char* smem) {
   if (gated(ix, a.d)) return;
   a.nq = dyn_count(ix, a.d, a.nq);
@@ -989,7 +1057,7 @@ __device__ inline void search_kernel(const Index& ix, SearchArgs& a, char* smem)
   if (!a.persistent) {  // one wave per query
     const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (qi < a.nq) {
-      if constexpr (RL) search_one_rl<TP>(ix, a, base, qi);
+      if constexpr (RL) search_one_rl<TP, H>(ix, a, base, qi);
       else search_one<TP>(ix, a, base, qi);
     }
     return;
@@ -998,7 +1066,7 @@ __device__ inline void search_kernel(const Index& ix, SearchArgs& a, char* smem)
   unsigned long long* queue = &ix.ctr[C_QUEUE];
   for (uint32_t qi = wave_ticket(queue); qi < a.nq; qi = wave_ticket(queue)) {
     wave_sync();
-    if constexpr (RL) search_one_rl<TP>(ix, a, base, qi);
+    if constexpr (RL) search_one_rl<TP, H>(ix, a, base, qi);
     else search_one<TP>(ix, a, base, qi);
   }
   const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
@@ -1011,16 +1079,16 @@ __device__ inline void search_kernel(const Index& ix, SearchArgs& a, char* smem)
 // list in registers; uint8 rows hold their registers to 7 waves per SIMD (the
 // LDS of 7 four-wave blocks fits a CU at the default visited-table size),
 // float rows keep theirs (they would spill)
-template <class TP, unsigned WPE>
+template <class TP, unsigned WPE, int H>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) k_search_rl(Index ix, SearchArgs a) {
   extern __shared__ __align__(16) char smem[];
-  search_kernel<TP, true>(ix, a, smem);
+  search_kernel<TP, true, H>(ix, a, smem);
 }
 
 template <class TP>
 __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   extern __shared__ __align__(16) char smem[];
-  search_kernel<TP, false>(ix, a, smem);
+  search_kernel<TP, false, 1>(ix, a, smem);
 }
 
 // ---- LDS carving for the maintenance kernels ------------------------------------------
@@ -2629,9 +2697,10 @@ hipError_t launch_sort(const Index& ix, uint64_t* a, uint64_t* b, uint32_t nmax,
   return hipGetLastError();
 }
 
-uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots) {
-  // L <= 64 (list in registers): candidate keys/refs, ids, visited table
-  if (L <= 64) return 2u * 512u + 256u + 4u * vt_slots;
+uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots, uint32_t W) {
+  // L <= 64 (list in registers): candidate keys/refs, ids (64 per two
+  // expansions of a step), visited table
+  if (L <= 64) return (W > 2 ? 2u : 1u) * (2u * 512u + 256u) + 4u * vt_slots;
   // keys + refs (double-buffered), candidate keys/refs, merge scratch, ids,
   // insertion points, visited table, expanded flags
   return 32u * L + 4u * 512u + 2u * 256u + 4u * vt_slots + ((2u * L + 15u) & ~15u);
@@ -2679,7 +2748,12 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
 #define LS(TP)                                                                                   \
   do {                                                                                           \
     if (a.L <= 64)                                                                               \
-      hipLaunchKernelGGL((k_search_rl<TP, TP::FLOAT ? 1u : 7u>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a); \
+      if (a.W > 2)                                                                                \
+        hipLaunchKernelGGL((k_search_rl<TP, TP::FLOAT ? 1u : 6u, 2>), dim3(grid), dim3(64 * waves_per_block), lds, s, \
+                           ix, a);                                                                \
+      else                                                                                        \
+        hipLaunchKernelGGL((k_search_rl<TP, TP::FLOAT ? 1u : 7u, 1>), dim3(grid), dim3(64 * waves_per_block), lds, s, \
+                           ix, a);                                                                \
     else                                                                                         \
       hipLaunchKernelGGL((k_search<TP>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a); \
   } while (0)

@@ -17,7 +17,7 @@ struct SearchArgs {
   const void* q;       // MODE_QUERY: [nq x dim] query rows (uint8 or FP32)
   uint32_t first;      // MODE_INSERT: query i is stored vector first + i
   uint32_t nq, L, k, vcap, vt_mask;
-  uint32_t W;          // expansions per iteration (1, or 2 when 2R <= 64)
+  uint32_t W;          // expansions per step: 1, 2 (2R <= 64) or 4 (2R <= 64, two halves of 64 lanes)
   uint32_t lds_per_wave;
   int32_t trav;        // float rows: traversal copy of this launch
   uint32_t rerank;     // float rows, bf16 / FP8 copy: re-rank rerank*k candidates (0: none)
@@ -87,7 +87,7 @@ hipError_t launch_store_rows(const Index& ix, const void* src, uint32_t* ids_out
 hipError_t launch_refresh_entries(const Index& ix, uint32_t bound, uint32_t S, Dyn d, hipStream_t s);
 hipError_t launch_gather_rows(const void* rows, const uint32_t* idx, uint32_t n, uint32_t row_bytes, void* out,
                               hipStream_t s);
-uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots);
+uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots, uint32_t W);
 uint32_t scan_select_lds_per_wave(uint32_t L);
 hipError_t launch_scan(const Index& ix, const ScanArgs& a, hipStream_t s, hipEvent_t after_dist = nullptr);
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s);

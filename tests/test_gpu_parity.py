@@ -149,3 +149,13 @@ def test_parity_heavy_ties():
     assert_same_state(o, g, "ties after churn")
     check_search("ties after churn")
     g.close()
+
+
+def test_parity_four_expansions_per_step():
+    # W = 4: four slabs per step, scored in one batch (two halves of 64 lanes)
+    # for L <= 64, in two merges for longer lists
+    run_parity(small_workload(seed=10, rounds=2), W=4, search_L=(16, 64, 101))
+
+
+def test_parity_four_expansions_crowded_visited_table():
+    run_parity(small_workload(seed=11, rounds=1), W=4, search_L=(32, 100), vt_slots=64)
