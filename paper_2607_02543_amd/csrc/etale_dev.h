@@ -635,6 +635,10 @@ __device__ inline void wave_bitonic_sort(uint64_t* keys, int np) {
 // by (D(p,c), id), keep at most prune_cap, then select in order: keep c unless
 // an already kept c' has a^2 * D(c', c) <= b^2 * D(p, c). Result (ids, D) in
 // lds.out_ids / lds.out_d, in (D, id) order; returns its length.
+// candidate tiles of 64 whose distances a prune's batched selection keeps in
+// registers (up to 128 candidates; more take the one-at-a-time selection)
+constexpr int PRUNE_TILES = 2;
+
 template <int G>
 __device__ inline int robust_prune_u8(const Index& ix, uint32_t p, const uint32_t* cand, int n, PruneLds& s) {
   constexpr int VPP = 64 / G;
@@ -697,7 +701,11 @@ __device__ inline int robust_prune_u8(const Index& ix, uint32_t p, const uint32_
     }
   }
   wave_sync();
-  // 4. ordered selection; lane l owns candidates l, l+64, ...
+  // 4. ordered selection; lane l owns candidates l, l+64, ... The next four
+  // live candidates are taken together: each lane computes its candidates'
+  // distances to all four in one pass over its rows, then the four are
+  // decided in order (one killed by an earlier one of the four is skipped), so
+  // the kept set is that of the one-at-a-time selection.
   const int T = (m + 63) >> 6;
   uint32_t alive = 0;
   for (int t = 0; t < T; ++t)
@@ -705,33 +713,101 @@ __device__ inline int robust_prune_u8(const Index& ix, uint32_t p, const uint32_
   int cnt = 0, from = 0;
   const uint64_t a2 = ix.a2, b2 = ix.b2;
   const int words = (int)ix.dim / 16;
+  if (T > PRUNE_TILES) {  // more candidates than the registers hold: one at a time
+    while (cnt < (int)ix.R) {
+      int j = -1;
+      for (int t = from >> 6; t < T && j < 0; ++t) {
+        uint64_t bm = ballot(((alive >> t) & 1u) && (t * 64 + l) >= from);
+        if (bm) j = t * 64 + (int)__builtin_ctzll(bm);
+      }
+      if (j < 0) break;
+      const uint64_t kj = s.keys2[j];
+      if (l == 0) {
+        s.out_ids[cnt] = key_id(kj);
+        s.out_d[cnt] = key_dist(kj);
+      }
+      ++cnt;
+      from = j + 1;
+      if (cnt == (int)ix.R) break;
+      const uint4* vj = reinterpret_cast<const uint4*>(s.vec + (size_t)j * s.vstride);
+      const uint32_t nj = s.norm[j];
+      for (int t = from >> 6; t < T; ++t) {
+        int i = t * 64 + l;
+        if (!((alive >> t) & 1u) || i < from) continue;
+        const uint4* vi = reinterpret_cast<const uint4*>(s.vec + (size_t)i * s.vstride);
+        uint32_t dot = 0;
+        for (int w = 0; w < words; ++w) dot = dot16(vi[w], vj[w], dot);
+        const uint64_t dji = (uint64_t)(nj + s.norm[i] - 2u * dot);
+        const uint64_t dpi = (uint64_t)key_dist(s.keys2[i]);
+        if (a2 * dji <= b2 * dpi) alive &= ~(1u << t);
+      }
+    }
+    wave_sync();
+    return cnt;
+  }
   while (cnt < (int)ix.R) {
-    int j = -1;
-    for (int t = from >> 6; t < T && j < 0; ++t) {
+    int j[4] = {-1, -1, -1, -1};
+    int nj4 = 0;
+    for (int t = from >> 6; t < T && nj4 < 4; ++t) {
       uint64_t bm = ballot(((alive >> t) & 1u) && (t * 64 + l) >= from);
-      if (bm) j = t * 64 + (int)__builtin_ctzll(bm);
+      while (bm && nj4 < 4) {
+        j[nj4++] = t * 64 + (int)__builtin_ctzll(bm);
+        bm &= bm - 1;
+      }
     }
-    if (j < 0) break;
-    const uint64_t kj = s.keys2[j];
-    if (l == 0) {
-      s.out_ids[cnt] = key_id(kj);
-      s.out_d[cnt] = key_dist(kj);
+    if (nj4 == 0) break;
+    // distances from this lane's later live candidates to the (up to) four
+    uint32_t dk[4][PRUNE_TILES];
+    uint32_t nk[4];
+    const uint4* vk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int jj = j[k] >= 0 ? j[k] : j[0];
+      vk[k] = reinterpret_cast<const uint4*>(s.vec + (size_t)jj * s.vstride);
+      nk[k] = s.norm[jj];
     }
-    ++cnt;
-    from = j + 1;
-    if (cnt == (int)ix.R) break;
-    const uint4* vj = reinterpret_cast<const uint4*>(s.vec + (size_t)j * s.vstride);
-    const uint32_t nj = s.norm[j];
-    for (int t = from >> 6; t < T; ++t) {
-      int i = t * 64 + l;
-      if (!((alive >> t) & 1u) || i < from) continue;
-      const uint4* vi = reinterpret_cast<const uint4*>(s.vec + (size_t)i * s.vstride);
-      uint32_t dot = 0;
-      for (int w = 0; w < words; ++w) dot = dot16(vi[w], vj[w], dot);
-      const uint64_t dji = (uint64_t)(nj + s.norm[i] - 2u * dot);
-      const uint64_t dpi = (uint64_t)key_dist(s.keys2[i]);
-      if (a2 * dji <= b2 * dpi) alive &= ~(1u << t);
+#pragma unroll
+    for (int t = 0; t < PRUNE_TILES; ++t) {
+      if (t >= T) break;
+      const int i = t * 64 + l;
+      uint32_t dot[4] = {0, 0, 0, 0};
+      if (((alive >> t) & 1u) && i > j[0]) {
+        const uint4* vi = reinterpret_cast<const uint4*>(s.vec + (size_t)i * s.vstride);
+        for (int w = 0; w < words; ++w) {
+          const uint4 x = vi[w];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) dot[k] = dot16(x, vk[k][w], dot[k]);
+        }
+      }
+      const uint32_t ni = i < m ? s.norm[i] : 0u;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dk[k][t] = nk[k] + ni - 2u * dot[k];
     }
+    // decide the four in order
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (j[k] < 0 || cnt >= (int)ix.R) break;
+      const uint32_t owner = (uint32_t)__builtin_amdgcn_readlane((int)alive, j[k] & 63);
+      if (!((owner >> (j[k] >> 6)) & 1u)) continue;  // killed by an earlier one of the four
+      const uint64_t kj = s.keys2[j[k]];
+      if (l == 0) {
+        s.out_ids[cnt] = key_id(kj);
+        s.out_d[cnt] = key_dist(kj);
+      }
+      ++cnt;
+      if (cnt == (int)ix.R) break;
+#pragma unroll
+      for (int t = 0; t < PRUNE_TILES; ++t) {
+        if (t >= T) break;
+        const int i = t * 64 + l;
+        if (!((alive >> t) & 1u) || i <= j[k]) continue;
+        const uint64_t dpi = (uint64_t)key_dist(s.keys2[i]);
+        if (a2 * (uint64_t)dk[k][t] <= b2 * dpi) alive &= ~(1u << t);
+      }
+    }
+    // every candidate up to the last of the four is decided
+    from = (j[3] >= 0 ? j[3] : (T * 64)) + 1;
+    if (j[3] < 0) break;
   }
   wave_sync();
   return cnt;

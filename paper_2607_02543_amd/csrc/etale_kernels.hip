@@ -1614,21 +1614,27 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
   // every target is a live node with a slab: one fresh slab and one retired slab each
   SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
-  if constexpr (P::CHAIN) {
-    if (a.chain) {
-      const ChainLds c = carve_chain(wave_lds(smem, a), ix.R, a.vstride);
-      FOR_EACH_WAVE_ITEM(si, nseg) {
-        wave_sync();
-        reverse_chain_u8<P::GL>(ix, a, c, a.seg[si], cur);
-      }
-      finish_slabs(ix, cur, C_PUB_REVERSE);
-      return;
-    }
-  }
   MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   FOR_EACH_WAVE_ITEM(si, nseg) {
     wave_sync();
     reverse_one<P>(ix, a, m, a.seg[si], cur);
+  }
+  finish_slabs(ix, cur, C_PUB_REVERSE);
+}
+
+// the same with the cached candidate state (uint8 rows, R <= 32): a kernel of
+// its own so that its registers are not those of the generic path
+template <int G>
+__global__ void __launch_bounds__(256) k_reverse_chain(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
+  SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
+  const ChainLds c = carve_chain(wave_lds(smem, a), ix.R, a.vstride);
+  FOR_EACH_WAVE_ITEM(si, nseg) {
+    wave_sync();
+    reverse_chain_u8<G>(ix, a, c, a.seg[si], cur);
   }
   finish_slabs(ix, cur, C_PUB_REVERSE);
 }
@@ -2181,34 +2187,6 @@ __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
   if (gated(ix, a.d)) return;
   resolve(ix, a);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
-  if constexpr (P::CHAIN) {
-    if (a.chain) {
-      // targets differ in cost (one to a dozen deleted out-neighbors), so
-      // waves take them from a queue in batches, each batch with its own
-      // slab reservation (one fresh and one retired slab per target)
-      constexpr uint32_t BATCH = 4;
-      const PoolLds p = carve_pool(wave_lds(smem, a), a.vstride);
-      unsigned long long* queue = &ix.ctr[C_QUEUE];
-      for (;;) {
-        const uint32_t b0 = (uint32_t)wave_atomic_add(queue, BATCH);
-        if (b0 >= nseg) break;
-        const uint32_t nb = min(BATCH, nseg - b0);
-        SlabCursor cur = reserve_slabs(ix, nb, nb);
-        for (uint32_t si = b0; si < b0 + nb; ++si) {
-          wave_sync();
-          repair_chain_u8<P::GL>(ix, a, p, a.seg[si], cur);
-        }
-        finish_slabs(ix, cur, C_PUB_REPAIR);
-      }
-      // the last wave out resets the queue for the next launch
-      const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
-      if (lane_id() == 0 && done + 1 == total_waves()) {
-        atomicExch(queue, 0ull);
-        atomicExch(&ix.ctr[C_QDONE], 0ull);
-      }
-      return;
-    }
-  }
   SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
   MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   FOR_EACH_WAVE_ITEM(si, nseg) {
@@ -2216,6 +2194,38 @@ __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
     repair_one<P>(ix, a, m, a.seg[si], cur);
   }
   finish_slabs(ix, cur, C_PUB_REPAIR);
+}
+
+// the same with the wave-local candidate pool (uint8 rows, R <= 32), a kernel
+// of its own. Targets differ in cost (one to a dozen deleted out-neighbors),
+// so waves take them from a queue in batches, each batch with its own slab
+// reservation (one fresh and one retired slab per target).
+template <int G>
+__global__ void __launch_bounds__(256) k_repair_pool(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
+  constexpr uint32_t BATCH = 4;
+  const PoolLds p = carve_pool(wave_lds(smem, a), a.vstride);
+  unsigned long long* queue = &ix.ctr[C_QUEUE];
+  for (;;) {
+    const uint32_t b0 = (uint32_t)wave_atomic_add(queue, BATCH);
+    if (b0 >= nseg) break;
+    const uint32_t nb = min(BATCH, nseg - b0);
+    SlabCursor cur = reserve_slabs(ix, nb, nb);
+    for (uint32_t si = b0; si < b0 + nb; ++si) {
+      wave_sync();
+      repair_chain_u8<G>(ix, a, p, a.seg[si], cur);
+    }
+    finish_slabs(ix, cur, C_PUB_REPAIR);
+  }
+  // the last wave out resets the queue for the next launch
+  const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
+  if (lane_id() == 0 && done + 1 == total_waves()) {
+    atomicExch(queue, 0ull);
+    atomicExch(&ix.ctr[C_QDONE], 0ull);
+  }
 }
 
 // ---- stable LSD radix sort with a launch-time count --------------------------------------
@@ -2856,6 +2866,13 @@ static void launch_maint_p(MaintKernel which, const Index& ix, const MaintArgs& 
       hipLaunchKernelGGL(k_forward<P>, resident_grid(k_forward<P>, grid, blk, lds), blk, lds, s, ix, a);
       break;
     case MK_REVERSE:
+      if constexpr (P::CHAIN) {
+        if (a.chain) {
+          hipLaunchKernelGGL(k_reverse_chain<P::GL>, resident_grid(k_reverse_chain<P::GL>, grid, blk, lds), blk, lds,
+                             s, ix, a);
+          break;
+        }
+      }
       hipLaunchKernelGGL(k_reverse_apply<P>, resident_grid(k_reverse_apply<P>, grid, blk, lds), blk, lds, s, ix, a);
       break;
     case MK_REFINE:
@@ -2863,6 +2880,13 @@ static void launch_maint_p(MaintKernel which, const Index& ix, const MaintArgs& 
       hipLaunchKernelGGL(k_refine_publish, dim3(grid), blk, 512u * (blk.x / 64u), s, ix, a);
       break;
     case MK_REPAIR:
+      if constexpr (P::CHAIN) {
+        if (a.chain) {
+          hipLaunchKernelGGL(k_repair_pool<P::GL>, resident_grid(k_repair_pool<P::GL>, grid, blk, lds), blk, lds, s,
+                             ix, a);
+          break;
+        }
+      }
       hipLaunchKernelGGL(k_repair_apply<P>, resident_grid(k_repair_apply<P>, grid, blk, lds), blk, lds, s, ix, a);
       break;
   }
