@@ -2085,19 +2085,48 @@ __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const u
   return cnt;
 }
 
+// The words a repair target starts from, read for a batch of targets at once
+// (lane k: the batch's k-th target): its first pair (a, u), the pair after
+// it, and the reference words of a and u.
+struct RepairHead {
+  uint64_t pair, next;
+  uint64_t ra, ru;
+};
+
+__device__ inline RepairHead repair_heads(const Index& ix, const MaintArgs& a, uint32_t b0, uint32_t nb) {
+  const uint32_t l = (uint32_t)lane_id();
+  RepairHead h{KEY_NONE, KEY_NONE, 0, 0};
+  if (l < nb) {
+    const uint32_t t = a.seg[b0 + l];
+    h.pair = a.pairs[t];
+    h.next = t + 1 < a.npairs ? a.pairs[t + 1] : KEY_NONE;
+    h.ra = load_ref(ix, (uint32_t)(h.pair >> 32));
+    h.ru = load_ref(ix, (uint32_t)h.pair);
+  }
+  return h;
+}
+
+// lane k < nb: the batch's k-th segment start
+__device__ inline uint32_t l_seg(const MaintArgs& a, uint32_t b0, uint32_t nb) {
+  const uint32_t l = (uint32_t)lane_id();
+  return l < nb ? a.seg[b0 + l] : 0u;
+}
+
 template <int G>
 __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, const PoolLds& p, uint32_t t,
-                                       SlabCursor& cur) {
+                                       const RepairHead& hd, int k, SlabCursor& cur) {
   const int l = lane_id();
   const uint32_t R = ix.R;
-  const uint32_t an = (uint32_t)(a.pairs[t] >> 32);
+  const uint64_t pair0 = bcast_lane64(hd.pair, k);
+  const uint32_t an = (uint32_t)(pair0 >> 32);
   const uint4 wf = load_frag<G>(ix.x + (size_t)an * ix.dim);
   const uint32_t ww = group_sum<G>(dot16(wf, wf, 0u));
   // a's list and the first N(u), read side by side; the list lives in slots
   // 0..n-1 and in registers (lane x: slot and id of list entry x)
-  uint32_t u = (uint32_t)a.pairs[t];
-  const uint64_t ra = bcast64(load_ref(ix, an));
-  uint64_t ru = bcast64(load_ref(ix, u));
+  uint32_t u = (uint32_t)pair0;
+  const uint64_t ra = bcast_lane64(hd.ra, k);
+  uint64_t ru = bcast_lane64(hd.ru, k);
+  const uint64_t pair1 = bcast_lane64(hd.next, k);
   uint32_t n = ref_slab(ra) == NONE ? 0u : ref_deg(ra);
   uint32_t du = ref_slab(ru) == NONE ? 0u : ref_deg(ru);
   uint32_t lid = NONE, b = NONE;
@@ -2110,9 +2139,11 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
   }
   uint64_t used = n == 64 ? ~0ull : ((1ull << n) - 1ull);
   bool first = true;
-  for (uint32_t q = t; q < a.npairs && a.pairs[q] != KEY_NONE && (uint32_t)(a.pairs[q] >> 32) == an; ++q) {
+  for (uint32_t q = t; q < a.npairs; ++q) {
     if (!first) {
-      u = (uint32_t)a.pairs[q];
+      const uint64_t pq = q == t + 1 ? pair1 : a.pairs[q];
+      if (pq == KEY_NONE || (uint32_t)(pq >> 32) != an) break;
+      u = (uint32_t)pq;
       ru = bcast64(load_ref(ix, u));
       du = ref_slab(ru) == NONE ? 0u : ref_deg(ru);
       b = NONE;
@@ -2214,9 +2245,11 @@ __global__ void __launch_bounds__(256) k_repair_pool(Index ix, MaintArgs a) {
     if (b0 >= nseg) break;
     const uint32_t nb = min(BATCH, nseg - b0);
     SlabCursor cur = reserve_slabs(ix, nb, nb);
-    for (uint32_t si = b0; si < b0 + nb; ++si) {
+    const RepairHead hd = repair_heads(ix, a, b0, nb);
+    const uint32_t ts = l_seg(a, b0, nb);
+    for (uint32_t k = 0; k < nb; ++k) {
       wave_sync();
-      repair_chain_u8<G>(ix, a, p, a.seg[si], cur);
+      repair_chain_u8<G>(ix, a, p, (uint32_t)__builtin_amdgcn_readlane((int)ts, (int)k), hd, (int)k, cur);
     }
     finish_slabs(ix, cur, C_PUB_REPAIR);
   }
