@@ -403,7 +403,7 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     if (ix->cfg.metric == ETALE_METRIC_L2_U8 && R <= 32 && !ix->no_chain &&
         pool_lds_per_wave(pa.vstride) <= 65536u) {
       pa.chain = 1;
-      pa.lds_per_wave = std::max(pa.lds_per_wave, pool_lds_per_wave(pa.vstride));
+      pa.lds_per_wave = pool_lds_per_wave(pa.vstride);  // the pool kernel carves only the pool
     }
     pa.np_ctr = C_DEL_OK;
     pa.np_mult = R;
@@ -429,7 +429,7 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     MaintArgs ra = maint_args(ix, R + 1);
     if (ix->cfg.metric == ETALE_METRIC_L2_U8 && R <= 32 && !ix->no_chain) {
       ra.chain = 1;
-      ra.lds_per_wave = std::max(ra.lds_per_wave, chain_lds_per_wave(R, ra.vstride));
+      ra.lds_per_wave = chain_lds_per_wave(R, ra.vstride);  // the chain kernel carves only the chain state
     }
     ra.n = p.max_i;
     ra.pairs = sorted;
