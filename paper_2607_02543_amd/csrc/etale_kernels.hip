@@ -1321,10 +1321,18 @@ __device__ inline void reverse_one(const Index& ix, const MaintArgs& a, MaintLds
 // distances between the slots' rows. An offer then costs one row load and at
 // most R distances from LDS instead of a full RobustPrune. The distances are
 // exact integers, so the result is the one RobustPrune gives.
+// Index of the pair {x, y} of distinct slots in a triangular distance cache
+// of S slots (S (S - 1) / 2 + 1 words: x = y lands inside, on a word that is
+// never read for a decision).
+__device__ inline uint32_t tri(uint32_t x, uint32_t y) {
+  const uint32_t hi = max(x, y), lo = min(x, y);
+  return hi * (hi - 1u) / 2u + lo;
+}
+
 struct ChainLds {
   uint8_t* rows;    // [S][vstride]
   uint32_t* norm;   // [S]
-  uint32_t* M;      // [S][S]
+  uint32_t* M;      // [S (S - 1) / 2 + 1] squared distances between slots, by tri()
   uint32_t* id;     // [S]
   uint32_t* dw;     // [S] squared distance to the target
   uint32_t* dead;   // [S] deletion flag of the candidate
@@ -1336,7 +1344,7 @@ struct ChainLds {
 
 __host__ __device__ inline uint32_t chain_lds_bytes(uint32_t R, uint32_t vstride) {
   const uint32_t S = R + 1;
-  const uint32_t b = S * vstride + S * 4 + S * S * 4 + 7 * S * 4;
+  const uint32_t b = S * vstride + S * 4 + ((S * (S - 1u) / 2u + 1u + 3u) & ~3u) * 4 + 7 * S * 4;
   return (b + 15u) & ~15u;
 }
 
@@ -1349,7 +1357,7 @@ __device__ inline ChainLds carve_chain(char* base, uint32_t R, uint32_t vstride)
   c.norm = p;
   p += c.S;
   c.M = p;
-  p += c.S * c.S;
+  p += (c.S * (c.S - 1u) / 2u + 1u + 3u) & ~3u;
   c.id = p;
   p += c.S;
   c.dw = p;
@@ -1405,10 +1413,9 @@ __device__ inline void chain_fill_row(const ChainLds& c, uint32_t a, const uint3
     const uint32_t b = k < cnt ? slots[k] : a;
     const uint4 bv = *reinterpret_cast<const uint4*>(c.rows + (size_t)b * c.vstride + ch * 16);
     const uint32_t dot = group_sum<G>(dot16(av, bv, 0u));
-    if (k < cnt && ch == 0) {
+    if (k < cnt && ch == 0 && b != a) {  // the diagonal's word belongs to another pair
       const uint32_t d = na + c.norm[b] - 2u * dot;
-      c.M[a * c.S + b] = d;
-      c.M[b * c.S + a] = d;
+      c.M[tri(a, b)] = d;
     }
   }
   wave_sync();
@@ -1464,8 +1471,7 @@ __device__ inline void chain_fill_mfma(const Index& ix, const ChainLds& c, uint3
         const uint32_t row = ta * 16u + rb + (uint32_t)i;
         if (row < S) {
           const uint32_t d = nrm[row] + nc - 2u * (uint32_t)acc[i];
-          c.M[row * S + col] = d;
-          c.M[col * S + row] = d;
+          if (row != col) c.M[tri(row, col)] = d;
         }
       }
     }
@@ -1574,7 +1580,7 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        d[k] = j[k] >= 0 ? c.M[(uint32_t)__builtin_amdgcn_readlane((int)cs, j[k]) * c.S + cs] : 0u;
+        d[k] = j[k] >= 0 ? c.M[tri((uint32_t)__builtin_amdgcn_readlane((int)cs, j[k]), cs)] : 0u;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (j[k] < 0 || cnt >= R) break;
@@ -1625,7 +1631,7 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
 // the same with the cached candidate state (uint8 rows, R <= 32): a kernel of
 // its own so that its registers are not those of the generic path
 template <int G>
-__global__ void __launch_bounds__(256) k_reverse_chain(Index ix, MaintArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_reverse_chain(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, a.d)) return;
   resolve(ix, a);
@@ -1902,10 +1908,6 @@ __device__ inline PoolLds carve_pool(char* base, uint32_t) {
   return p;
 }
 
-__device__ inline uint32_t tri(uint32_t x, uint32_t y) {
-  const uint32_t hi = max(x, y), lo = min(x, y);
-  return hi * (hi - 1u) / 2u + lo;  // hi = lo = 0 gives 0, hi = lo = 63 gives POOL_M - 1
-}
 
 // shifted squared norms, deletion flags and distances to the target (fragment
 // wf, norm ww) of slots[0..cnt), all loads issued before any is used
