@@ -2387,48 +2387,79 @@ __global__ void k_del_bitmap(Index ix, uint64_t n_ids, Dyn d, uint64_t* bitmap) 
 __device__ inline bool bit_set(const uint64_t* bm, uint32_t id) { return (bm[id >> 6] >> (id & 63u)) & 1ull; }
 
 // live nodes with an edge into a tombstone ("dirty"), and the count of such
-// edges. One thread per node: reference words are read coalesced, each slab's
-// id half as whole 16-byte words, neighbors tested against the deletion bitmap.
+// edges; neighbors are tested against the deletion bitmap.
+constexpr uint32_t DIRTY_CHUNK = 1024;  // nodes per workgroup and step
+
 __global__ void __launch_bounds__(256) k_dirty(Index ix, uint64_t n_ids, Dyn d, const uint64_t* bitmap,
                                                uint32_t* dirty) {
+  __shared__ uint32_t buf[DIRTY_CHUNK];
+  __shared__ uint32_t cnt_s, dead_s, base_s;
   if (gated(ix, d)) return;
   const uint32_t n = dyn_count(ix, d, (uint32_t)n_ids);
   const uint32_t R = ix.R;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  const uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
-  // every lane runs the same number of iterations, so the wave-wide ballot
-  // and the one atomic per wave see all lanes
-  for (uint32_t base = first - lane_id(); base < n; base += stride) {
-    const uint32_t u = base + (uint32_t)lane_id();
-    uint32_t dead = 0;
-    if (u < n) {
-      const uint64_t r = load_ref(ix, u);
-      const uint32_t deg = ref_deg(r), s = ref_slab(r);
-      if (!ref_del(r) && s != NONE) {
-        const uint32_t* ids = ix.slabs + (size_t)s * 2u * R;
-        if ((R & 3u) == 0) {
-          for (uint32_t j = 0; j < deg; j += 4) {
-            const uint4 v = *reinterpret_cast<const uint4*>(ids + j);
-            dead += bit_set(bitmap, v.x);
-            if (j + 1 < deg) dead += bit_set(bitmap, v.y);
-            if (j + 2 < deg) dead += bit_set(bitmap, v.z);
-            if (j + 3 < deg) dead += bit_set(bitmap, v.w);
+  // A workgroup takes 1,024 nodes per step: each wave four runs of 64, lane l
+  // owning node base + l. The slabs are read by eight lanes per node, eight
+  // nodes at a time (lane c of a group reads ids 4c.. 4c+3, then 32 further
+  // on), so a node's id half is one contiguous run; each group's count goes
+  // to its node's lane. Dirty ids gather in LDS and take their place in the
+  // list with one atomic per workgroup and step.
+  const int l = lane_id();
+  const uint32_t c = (uint32_t)(l & 7), wv = threadIdx.x >> 6;
+  for (uint32_t chunk = blockIdx.x; chunk * DIRTY_CHUNK < n; chunk += gridDim.x) {
+    if (threadIdx.x == 0) {
+      cnt_s = 0;
+      dead_s = 0;
+    }
+    __syncthreads();
+    for (uint32_t run = 0; run < DIRTY_CHUNK / 256u; ++run) {
+      const uint32_t base = chunk * DIRTY_CHUNK + (run * 4u + wv) * 64u;
+      uint32_t dead = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k) {
+        const uint32_t v = base + 8u * k + (uint32_t)(l >> 3);
+        uint32_t cn = 0;
+        if (v < n) {
+          const uint64_t r = load_ref(ix, v);
+          const uint32_t deg = ref_deg(r), s = ref_slab(r);
+          if (!ref_del(r) && s != NONE) {
+            const uint32_t* ids = ix.slabs + (size_t)s * 2u * R;
+            if ((R & 3u) == 0) {
+              for (uint32_t j = 4u * c; j < deg; j += 32u) {
+                const uint4 w = *reinterpret_cast<const uint4*>(ids + j);
+                cn += bit_set(bitmap, w.x);
+                if (j + 1 < deg) cn += bit_set(bitmap, w.y);
+                if (j + 2 < deg) cn += bit_set(bitmap, w.z);
+                if (j + 3 < deg) cn += bit_set(bitmap, w.w);
+              }
+            } else {
+              for (uint32_t j = c; j < deg; j += 8u) cn += bit_set(bitmap, ids[j]);
+            }
           }
-        } else {
-          for (uint32_t j = 0; j < deg; ++j) dead += bit_set(bitmap, ids[j]);
         }
+        cn = group_sum<8>(cn);
+        // lane 8k + g takes the count of group g (node base + 8k + g)
+        const uint32_t got = (uint32_t)__shfl((int)cn, (int)((l & 7) * 8), 64);
+        if ((uint32_t)(l >> 3) == k) dead = got;
       }
+      const uint64_t m = ballot(dead != 0);
+      uint32_t total = dead;
+      for (int o = 32; o > 0; o >>= 1) total += (uint32_t)__shfl_xor((int)total, o, 64);
+      uint32_t at = 0;
+      if (l == 0 && m) {
+        at = atomicAdd(&cnt_s, (uint32_t)__popcll(m));
+        atomicAdd(&dead_s, total);
+      }
+      at = (uint32_t)__shfl((int)at, 0, 64);
+      if (dead) buf[at + lanes_below(m)] = base + (uint32_t)l;
     }
-    const uint64_t m = ballot(dead != 0);
-    uint32_t total = dead;
-    for (int o = 32; o > 0; o >>= 1) total += (uint32_t)__shfl_xor((int)total, o, 64);
-    uint32_t at = 0;
-    if (lane_id() == 0 && m) {
-      at = (uint32_t)atomicAdd(&ix.ctr[C_DIRTY], (unsigned long long)__popcll(m));
-      atomicAdd(&ix.ctr[C_DEAD], (unsigned long long)total);
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt_s) {
+      base_s = (uint32_t)atomicAdd(&ix.ctr[C_DIRTY], (unsigned long long)cnt_s);
+      atomicAdd(&ix.ctr[C_DEAD], (unsigned long long)dead_s);
     }
-    at = (uint32_t)__shfl((int)at, 0, 64);
-    if (dead) dirty[at + lanes_below(m)] = u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt_s; i += blockDim.x) dirty[base_s + i] = buf[i];
+    __syncthreads();
   }
 }
 
@@ -3032,7 +3063,7 @@ hipError_t launch_del_bitmap(const Index& ix, uint64_t n_ids, Dyn d, uint64_t* b
 hipError_t launch_dirty(const Index& ix, uint64_t n_ids, Dyn d, const uint64_t* bitmap, uint32_t* dirty,
                         hipStream_t s) {
   if (n_ids == 0) return hipSuccess;
-  const unsigned blocks = blocks_for(n_ids, 256);
+  const unsigned blocks = blocks_for(n_ids, DIRTY_CHUNK);
   hipLaunchKernelGGL(k_dirty, dim3(blocks < 4 * PERSIST_BLOCKS ? blocks : 4 * PERSIST_BLOCKS), dim3(256), 0, s, ix,
                      n_ids, d, bitmap, dirty);
   return hipGetLastError();
