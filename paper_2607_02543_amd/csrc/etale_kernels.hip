@@ -676,6 +676,12 @@ __device__ inline bool drop_crowded_twins(uint32_t nid, uint32_t vr, bool fresh,
   return keep;
 }
 
+// a wave's running totals of expansions and distance evaluations over its
+// queries (added to the index's counters once per workgroup)
+struct SearchTally {
+  uint32_t exp = 0, dist = 0;  // a wave's share of one launch stays below 2^32
+};
+
 // The search's results from its final list (keys lk, reference words lr, n
 // entries): a query's k nearest non-deleted listed nodes (re-ranked from the
 // FP32 rows for a bf16 / FP8 traversal), or an insert search's visit count;
@@ -683,7 +689,7 @@ __device__ inline bool drop_crowded_twins(uint32_t nid, uint32_t vr, bool fresh,
 template <class TP>
 __device__ inline void search_finish(const Index& ix, const SearchArgs& a, uint32_t qi, const void* qrow,
                                      const uint64_t* lk, const uint64_t* lr, int n, uint32_t* ci, uint64_t* ck,
-                                     uint32_t nexp, uint32_t ndist) {
+                                     uint32_t nexp, uint32_t ndist, SearchTally& tally) {
   const int l = lane_id();
   if (a.mode == MODE_QUERY) {
     // the first `want` listed nodes whose reference has flag 0: k of them, or
@@ -737,11 +743,11 @@ __device__ inline void search_finish(const Index& ix, const SearchArgs& a, uint3
   } else if (l == 0) {
     a.vis_cnt[qi] = nexp;
   }
+  if (a.mode == MODE_QUERY) {
+    tally.exp += nexp;
+    tally.dist += ndist;
+  }
   if (l == 0) {
-    if (a.mode == MODE_QUERY) {
-      atomicAdd(&ix.ctr[C_SEARCH_EXP], (unsigned long long)nexp);
-      atomicAdd(&ix.ctr[C_SEARCH_DIST], (unsigned long long)ndist);
-    }
     if (a.counts) {
       a.counts[2 * (size_t)qi] = nexp;
       a.counts[2 * (size_t)qi + 1] = ndist;
@@ -768,7 +774,7 @@ __device__ inline uint32_t expansion_ids(const Index& ix, uint64_t r0, uint64_t 
 // reference words, expanded flags), one batch of candidates, the merge
 // scratch and the visited table.
 template <class TP>
-__device__ inline void search_one(const Index& ix, const SearchArgs& a, char* base, uint32_t qi) {
+__device__ inline void search_one(const Index& ix, const SearchArgs& a, char* base, uint32_t qi, SearchTally& tally) {
   const int l = lane_id();
   CandList cl;
   uint64_t* p64 = reinterpret_cast<uint64_t*>(base);
@@ -856,7 +862,7 @@ __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* ba
     }
   }
 
-  search_finish<TP>(ix, a, qi, qrow, cl.keys(), cl.refs(), cl.n, ci, ck, nexp, ndist);
+  search_finish<TP>(ix, a, qi, qrow, cl.keys(), cl.refs(), cl.n, ci, ck, nexp, ndist, tally);
 }
 
 // Crowded-table twins of a step with H halves of 64 slab entries (half h
@@ -901,7 +907,8 @@ __device__ inline void drop_crowded_twins_h(const uint32_t (&nid)[H], const uint
 // all their fresh neighbors in one batch and merges them. Per-wave LDS: one
 // batch of candidates (64H) and the visited table.
 template <class TP, int H>
-__device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char* base, uint32_t qi) {
+__device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char* base, uint32_t qi,
+                                     SearchTally& tally) {
   constexpr int WMAX = 2 * H;
   const int l = lane_id();
   uint64_t* ck = reinterpret_cast<uint64_t*>(base);
@@ -1045,34 +1052,48 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
   ck[l] = lk;
   cr[l] = lr;
   wave_sync();
-  search_finish<TP>(ix, a, qi, qrow, ck, cr, n, ci, ck, nexp, ndist);
+  search_finish<TP>(ix, a, qi, qrow, ck, cr, n, ci, ck, nexp, ndist, tally);
 }
 
 template <class TP, bool RL, int H>
 __device__ inline void search_kernel(const Index& ix, SearchArgs& a, char* smem) {
+  __shared__ unsigned long long tsum[2];
   if (gated(ix, a.d)) return;
+  if (threadIdx.x == 0) tsum[0] = tsum[1] = 0;
+  __syncthreads();
   a.nq = dyn_count(ix, a.d, a.nq);
   a.first = dyn_first(ix, a.d, a.first);
   char* base = smem + (size_t)(threadIdx.x >> 6) * a.lds_per_wave;
+  const int l = lane_id();
+  SearchTally tally;
   if (!a.persistent) {  // one wave per query
     const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (qi < a.nq) {
-      if constexpr (RL) search_one_rl<TP, H>(ix, a, base, qi);
-      else search_one<TP>(ix, a, base, qi);
+      if constexpr (RL) search_one_rl<TP, H>(ix, a, base, qi, tally);
+      else search_one<TP>(ix, a, base, qi, tally);
     }
-    return;
+  } else {
+    unsigned long long* queue = &ix.ctr[C_QUEUE];
+    for (uint32_t qi = wave_ticket(queue); qi < a.nq; qi = wave_ticket(queue)) {
+      wave_sync();
+      if constexpr (RL) search_one_rl<TP, H>(ix, a, base, qi, tally);
+      else search_one<TP>(ix, a, base, qi, tally);
+    }
+    const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
+    if (l == 0 && done + 1 == total_waves()) {
+      atomicExch(queue, 0ull);
+      atomicExch(&ix.ctr[C_QDONE], 0ull);
+    }
   }
-  const int l = lane_id();
-  unsigned long long* queue = &ix.ctr[C_QUEUE];
-  for (uint32_t qi = wave_ticket(queue); qi < a.nq; qi = wave_ticket(queue)) {
-    wave_sync();
-    if constexpr (RL) search_one_rl<TP, H>(ix, a, base, qi);
-    else search_one<TP>(ix, a, base, qi);
+  // the workgroup's totals, one pair of atomics
+  if (l == 0 && (tally.exp | tally.dist)) {
+    atomicAdd(&tsum[0], (unsigned long long)tally.exp);
+    atomicAdd(&tsum[1], (unsigned long long)tally.dist);
   }
-  const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
-  if (l == 0 && done + 1 == total_waves()) {
-    atomicExch(queue, 0ull);
-    atomicExch(&ix.ctr[C_QDONE], 0ull);
+  __syncthreads();
+  if (threadIdx.x == 0 && (tsum[0] | tsum[1])) {
+    atomicAdd(&ix.ctr[C_SEARCH_EXP], tsum[0]);
+    atomicAdd(&ix.ctr[C_SEARCH_DIST], tsum[1]);
   }
 }
 
