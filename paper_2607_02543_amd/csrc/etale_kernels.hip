@@ -29,19 +29,25 @@ __global__ void k_init(Index ix) {
 }
 
 // End of a launch epoch: the retired stack joins the free stack (Lemma 1).
-__global__ void k_recycle(Index ix) {
+// The epoch's end (Lemma 1): retired slabs rejoin the free stack. Many
+// workgroups copy; a one-thread launch after them moves the counters.
+__global__ void __launch_bounds__(256) k_recycle(Index ix) {
+  const uint64_t n = ix.ctr[C_RETIRED_TOP];
+  const uint64_t f = ix.ctr[C_FREE_TOP];
+  if (f + n > ix.P) return;  // reported by k_recycle_commit
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    ix.free_stack[f + i] = ix.retired_stack[i];
+}
+
+__global__ void k_recycle_commit(Index ix) {
   const uint64_t n = ix.ctr[C_RETIRED_TOP];
   const uint64_t f = ix.ctr[C_FREE_TOP];
   if (f + n > ix.P) {
-    if (threadIdx.x == 0) atomicOr(&ix.ctr[C_ERROR], (unsigned long long)ERR_POOL_OVERFLOW);
+    atomicOr(&ix.ctr[C_ERROR], (unsigned long long)ERR_POOL_OVERFLOW);
     return;
   }
-  for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) ix.free_stack[f + i] = ix.retired_stack[i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    ix.ctr[C_FREE_TOP] = f + n;
-    ix.ctr[C_RETIRED_TOP] = 0;
-  }
+  ix.ctr[C_FREE_TOP] = f + n;
+  ix.ctr[C_RETIRED_TOP] = 0;
 }
 
 // ---- round control --------------------------------------------------------------------
@@ -1272,20 +1278,36 @@ __global__ void k_reverse_pairs(Index ix, MaintArgs a) {
 // Runs of one target in the sorted pair list: the start index of each run is
 // appended to seg (in no particular order; each run is applied by one wave,
 // and runs touch distinct targets).
-__global__ void k_segments(Index ix, const uint64_t* pairs, uint32_t n, Dyn d, uint32_t* seg) {
+constexpr uint32_t SEG_CHUNK = 2048;  // sorted pairs per workgroup
+
+__global__ void __launch_bounds__(256) k_segments(Index ix, const uint64_t* pairs, uint32_t n, Dyn d, uint32_t* seg) {
+  __shared__ uint32_t buf[SEG_CHUNK];
+  __shared__ uint32_t cnt_s, base_s;
   if (gated(ix, d)) return;
   n = dyn_count(ix, d, n);
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  bool start = false;
-  if (t < n) {
-    const uint64_t k = pairs[t];
-    start = k != KEY_NONE && (t == 0 || (uint32_t)(pairs[t - 1] >> 32) != (uint32_t)(k >> 32));
+  const uint32_t c0 = blockIdx.x * SEG_CHUNK;
+  if (c0 >= n) return;
+  if (threadIdx.x == 0) cnt_s = 0;
+  __syncthreads();
+  // run starts of the workgroup's pairs gather in LDS, then take their place
+  // in the list with one atomic per workgroup
+  for (uint32_t step = 0; step < SEG_CHUNK / 256u; ++step) {
+    const uint32_t t = c0 + step * 256u + threadIdx.x;
+    bool start = false;
+    if (t < n) {
+      const uint64_t k = pairs[t];
+      start = k != KEY_NONE && (t == 0 || (uint32_t)(pairs[t - 1] >> 32) != (uint32_t)(k >> 32));
+    }
+    const uint64_t m = ballot(start);
+    uint32_t at = 0;
+    if (lane_id() == 0 && m) at = atomicAdd(&cnt_s, (uint32_t)__popcll(m));
+    at = bcast(at);
+    if (start) buf[at + lanes_below(m)] = t;
   }
-  const uint64_t m = ballot(start);
-  uint32_t base = 0;
-  if (lane_id() == 0 && m) base = (uint32_t)atomicAdd(&ix.ctr[C_NSEG], (unsigned long long)__popcll(m));
-  base = bcast(base);
-  if (start) seg[base + lanes_below(m)] = t;
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt_s) base_s = (uint32_t)atomicAdd(&ix.ctr[C_NSEG], (unsigned long long)cnt_s);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < cnt_s; i += blockDim.x) seg[base_s + i] = buf[i];
 }
 
 // ---- insert: reverse edges in (target, source) order, one publication per target ------
@@ -1721,17 +1743,27 @@ __global__ void __launch_bounds__(256) k_refine_publish(Index ix, MaintArgs a) {
   uint32_t* ids = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * 512u);
   uint32_t* d = ids + 64;
   const int l = lane_id();
-  FOR_EACH_WAVE_ITEM(qi, a.n) {
-    const uint32_t cnt = a.vis_cnt[qi];
-    if (cnt == NONE) continue;
-    wave_sync();
-    if ((uint32_t)l < cnt) {
-      const uint64_t k = a.vis_keys[(size_t)qi * a.vcap + l];
-      ids[l] = key_id(k);
-      d[l] = key_dist(k);
+  const uint32_t w = wave_index(), W = total_waves();
+  // the wave's items in runs of 64: the changed lists of a run are counted
+  // first, so its slabs are reserved with one atomic per stack
+  for (uint32_t r0 = w; r0 < a.n; r0 += 64u * W) {
+    const uint32_t my = r0 + (uint32_t)l * W;
+    const bool changed = my < a.n && a.vis_cnt[my] != NONE;
+    const uint32_t np = (uint32_t)__popcll(ballot(changed));
+    SlabCursor cur = reserve_slabs(ix, np, np);
+    for (uint32_t qi = r0; qi < a.n && qi < r0 + 64u * W; qi += W) {
+      const uint32_t cnt = a.vis_cnt[qi];
+      if (cnt == NONE) continue;
+      wave_sync();
+      if ((uint32_t)l < cnt) {
+        const uint64_t k = a.vis_keys[(size_t)qi * a.vcap + l];
+        ids[l] = key_id(k);
+        d[l] = key_dist(k);
+      }
+      wave_sync();
+      publish(ix, a.first + qi, ids, d, cnt, C_PUB_REFINE, &cur);
     }
-    wave_sync();
-    publish(ix, a.first + qi, ids, d, cnt, C_PUB_REFINE);
+    finish_slabs(ix, cur, C_PUB_REFINE);
   }
 }
 
@@ -1790,24 +1822,29 @@ __global__ void k_del_classify(Index ix, const uint64_t* sorted, uint32_t n, Dyn
   n = dyn_count(ix, d, n);
   const uint64_t next_id = ix.ctr[C_NEXT_ID];
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const uint64_t k = sorted[t];
-  const uint32_t id = (uint32_t)(k >> 32), pos = (uint32_t)k;
-  const bool first = t == 0 || (uint32_t)(sorted[t - 1] >> 32) != id;
-  uint8_t st;
-  if (!first)
-    st = DEL_DUPLICATE;
-  else if ((uint64_t)id >= next_id)
-    st = DEL_OUT_OF_RANGE;
-  else if (ref_del(load_ref(ix, id)))
-    st = DEL_NOT_LIVE;
-  else
-    st = DEL_OK;
-  if (status) status[pos] = st;
-  if (st == DEL_OK) {
-    const unsigned long long i = atomicAdd(&ix.ctr[C_DEL_OK], 1ull);
-    dlist[i] = id;
+  uint8_t st = DEL_DUPLICATE;
+  uint32_t id = 0;
+  if (t < n) {
+    const uint64_t k = sorted[t];
+    id = (uint32_t)(k >> 32);
+    const uint32_t pos = (uint32_t)k;
+    const bool first = t == 0 || (uint32_t)(sorted[t - 1] >> 32) != id;
+    if (!first)
+      st = DEL_DUPLICATE;
+    else if ((uint64_t)id >= next_id)
+      st = DEL_OUT_OF_RANGE;
+    else if (ref_del(load_ref(ix, id)))
+      st = DEL_NOT_LIVE;
+    else
+      st = DEL_OK;
+    if (status) status[pos] = st;
   }
+  // the accepted ids of the wave take consecutive places, one atomic per wave
+  const bool ok = t < n && st == DEL_OK;
+  const uint64_t m = ballot(ok);
+  if (!m) return;
+  const uint32_t base = (uint32_t)wave_atomic_add(&ix.ctr[C_DEL_OK], (unsigned long long)__popcll(m));
+  if (ok) dlist[base + lanes_below(m)] = id;
 }
 
 // <0,d,s> -> <1,d,s>: the flag is set, degree and slab are kept
@@ -1815,17 +1852,21 @@ __global__ void k_tombstone(Index ix, const uint32_t* dlist, uint32_t n, Dyn d) 
   if (gated(ix, d)) return;
   n = dyn_count(ix, d, n);
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const uint32_t u = dlist[t];
-  uint64_t r = load_ref(ix, u);
-  for (int attempt = 0; attempt < 1024 && !ref_del(r); ++attempt) {
-    const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)r, (unsigned long long)(r | (1ull << 63)));
-    if (prev == r) {
-      atomicAdd(&ix.ctr[C_TOMBSTONED], 1ull);
-      break;
+  bool done = false;
+  if (t < n) {
+    const uint32_t u = dlist[t];
+    uint64_t r = load_ref(ix, u);
+    for (int attempt = 0; attempt < 1024 && !ref_del(r); ++attempt) {
+      const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)r, (unsigned long long)(r | (1ull << 63)));
+      if (prev == r) {
+        done = true;
+        break;
+      }
+      r = prev;
     }
-    r = prev;
   }
+  const uint64_t m = ballot(done);  // one count per wave
+  if (m) wave_atomic_add(&ix.ctr[C_TOMBSTONED], (unsigned long long)__popcll(m));
 }
 
 __global__ void k_repair_pairs(Index ix, MaintArgs a) {
@@ -2519,22 +2560,56 @@ __global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty
   finish_slabs(ix, cur, C_PUB_COMPACT);
 }
 
-// phase 2: <1,d,s> -> <1,0,none> and the slab is retired
-__global__ void k_free_tombstones(Index ix, uint64_t n_ids, Dyn d) {
+// phase 2: <1,d,s> -> <1,0,none> and the slab is retired. A workgroup takes
+// 1,024 ids per step; the slabs it frees gather in LDS and take consecutive
+// retired-stack slots with one atomic per workgroup and step.
+constexpr uint32_t FREE_CHUNK = 1024;
+
+__global__ void __launch_bounds__(256) k_free_tombstones(Index ix, uint64_t n_ids, Dyn d) {
+  __shared__ uint32_t buf[FREE_CHUNK];
+  __shared__ uint32_t cnt_s;
+  __shared__ unsigned long long base_s;
   if (gated(ix, d)) return;
   n_ids = dyn_count(ix, d, (uint32_t)n_ids);
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_ids) return;
-  const uint32_t u = (uint32_t)t;
-  uint64_t r = load_ref(ix, u);
-  for (int attempt = 0; attempt < 1024 && ref_del(r) && ref_slab(r) != NONE; ++attempt) {
-    const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)r, (unsigned long long)make_ref(1, 0, NONE));
-    if (prev == r) {
-      retire_slab(ix, ref_slab(r));
-      atomicAdd(&ix.ctr[C_FREED], 1ull);
-      break;
+  for (uint64_t c0 = (uint64_t)blockIdx.x * FREE_CHUNK; c0 < n_ids; c0 += (uint64_t)gridDim.x * FREE_CHUNK) {
+    if (threadIdx.x == 0) cnt_s = 0;
+    __syncthreads();
+    for (uint32_t step = 0; step < FREE_CHUNK / 256u; ++step) {
+      const uint64_t t = c0 + step * 256u + threadIdx.x;
+      uint32_t freed = NONE;
+      if (t < n_ids) {
+        const uint32_t u = (uint32_t)t;
+        uint64_t r = load_ref(ix, u);
+        for (int attempt = 0; attempt < 1024 && ref_del(r) && ref_slab(r) != NONE; ++attempt) {
+          const uint64_t prev =
+              atomicCAS(&ix.refs[u], (unsigned long long)r, (unsigned long long)make_ref(1, 0, NONE));
+          if (prev == r) {
+            freed = ref_slab(r);
+            break;
+          }
+          r = prev;
+        }
+      }
+      const uint64_t m = ballot(freed != NONE);
+      uint32_t at = 0;
+      if (lane_id() == 0 && m) at = atomicAdd(&cnt_s, (uint32_t)__popcll(m));
+      at = bcast(at);
+      if (freed != NONE) buf[at + lanes_below(m)] = freed;
     }
-    r = prev;
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt_s) {
+      base_s = atomicAdd(&ix.ctr[C_RETIRED_TOP], (unsigned long long)cnt_s);
+      atomicAdd(&ix.ctr[C_FREED], (unsigned long long)cnt_s);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt_s; i += blockDim.x) {
+      const unsigned long long idx = base_s + i;
+      if (idx < ix.P)
+        ix.retired_stack[idx] = buf[i];
+      else
+        atomicOr(&ix.ctr[C_ERROR], (unsigned long long)ERR_POOL_OVERFLOW);
+    }
+    __syncthreads();
   }
 }
 
@@ -2702,7 +2777,8 @@ hipError_t launch_init(const Index& ix, hipStream_t s) {
 }
 
 hipError_t launch_recycle(const Index& ix, hipStream_t s) {
-  hipLaunchKernelGGL(k_recycle, dim3(1), dim3(1024), 0, s, ix);
+  hipLaunchKernelGGL(k_recycle, dim3(256), dim3(256), 0, s, ix);
+  hipLaunchKernelGGL(k_recycle_commit, dim3(1), dim3(1), 0, s, ix);
   return hipGetLastError();
 }
 
@@ -2757,7 +2833,7 @@ hipError_t launch_refresh_entries(const Index& ix, uint32_t bound, uint32_t S, D
 hipError_t launch_segments(const Index& ix, const uint64_t* pairs, uint32_t nmax, Dyn d, uint32_t* seg,
                            hipStream_t s) {
   if (nmax == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_segments, dim3(blocks_for(nmax, 256)), dim3(256), 0, s, ix, pairs, nmax, d, seg);
+  hipLaunchKernelGGL(k_segments, dim3(blocks_for(nmax, SEG_CHUNK)), dim3(256), 0, s, ix, pairs, nmax, d, seg);
   return hipGetLastError();
 }
 
@@ -3101,7 +3177,9 @@ hipError_t launch_compact(const Index& ix, const uint32_t* dirty, uint64_t n, Dy
 
 hipError_t launch_free_tombstones(const Index& ix, uint64_t n_ids, Dyn d, hipStream_t s) {
   if (n_ids == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_free_tombstones, dim3(blocks_for(n_ids, 256)), dim3(256), 0, s, ix, n_ids, d);
+  const unsigned blocks = blocks_for(n_ids, FREE_CHUNK);
+  hipLaunchKernelGGL(k_free_tombstones, dim3(blocks < 4 * PERSIST_BLOCKS ? blocks : 4 * PERSIST_BLOCKS), dim3(256), 0,
+                     s, ix, n_ids, d);
   return hipGetLastError();
 }
 
