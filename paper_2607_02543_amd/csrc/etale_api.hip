@@ -51,6 +51,9 @@ struct etale_index {
   uint64_t dist_cap = 0;
   uint32_t* scan_gmin = nullptr;  // [gmin_cap] per-query group minima of those distances
   uint64_t gmin_cap = 0;
+  uint32_t* scan_bound = nullptr;  // [scan_chunk] per-query bounds (uint8 rows)
+  uint32_t* scan_ncand = nullptr;  // [scan_chunk x 64 spans] keys at or below them per span
+  uint64_t* scan_cand = nullptr;   // [scan_chunk x SCAN_KEYS_Q] those keys
   uint32_t scan_chunk = 0;
   uint64_t live = 0;
   int32_t qtrav = 0;              // query-side traversal copy
@@ -193,6 +196,9 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
     sc.ns_ctr = C_N_ENTRIES;
     sc.dist = ix->scan_dist;
     sc.gmin = ix->scan_gmin;
+    sc.bound = ix->scan_bound;
+    sc.ncand = ix->scan_ncand;
+    sc.cand = ix->scan_cand;
     sc.out_keys = ix->scan_keys;
     sc.out_n = ix->scan_n;
     sc.out_stride = L;
@@ -263,6 +269,9 @@ etale_status run_bootstrap(etale_index* ix, uint32_t nmax, uint32_t vcap, Dyn ba
     sc.ns_ctr = C_R_NINS;
     sc.dist = ix->scan_dist;
     sc.gmin = ix->scan_gmin;
+    sc.bound = ix->scan_bound;
+    sc.ncand = ix->scan_ncand;
+    sc.cand = ix->scan_cand;
     sc.out_keys = ix->vis_keys + (size_t)c * vcap;
     sc.out_n = ix->vis_cnt + c;
     sc.out_stride = vcap;
@@ -562,6 +571,9 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   // a chunk of n queries over ns start rows has at most n (ns / 32 + 8) group slots
   ix->gmin_cap = ix->dist_cap / 32 + 8ull * ix->scan_chunk;
   ALLOC(ix->scan_gmin, ix->gmin_cap * 4);
+  ALLOC(ix->scan_bound, (uint64_t)ix->scan_chunk * 4);
+  ALLOC(ix->scan_ncand, (uint64_t)ix->scan_chunk * 64 * 4);
+  ALLOC(ix->scan_cand, (uint64_t)ix->scan_chunk * SCAN_KEYS_Q * 8);
   ALLOC(ix->seg, B * R * 4);
   ALLOC(ix->hist, (uint64_t)sort_hist_words((uint32_t)(B * R)) * 4);
   ALLOC(ix->status, 16);

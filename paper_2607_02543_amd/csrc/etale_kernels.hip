@@ -188,11 +188,13 @@ __global__ void __launch_bounds__(1024) k_refresh_entries(Index ix, uint32_t nex
 // ---- start-set scoring: the L best start nodes of every query --------------------------
 // The start set (the entry set, or the batch itself for a bootstrap) is the
 // same for every query of a launch, so scoring it is one dense block of
-// distances: k_scan_dist (uint8 rows, on the matrix cores) and k_scan_dist_f
-// (float rows, 64 queries x 256 start rows per workgroup staged through LDS)
-// write the distance matrix; k_scan_select then takes, with one wave per
-// query, the exact L smallest (distance, id) keys. Start rows are in ascending
-// id order, so the row index breaks distance ties exactly as the id does.
+// distances. Float rows: k_scan_dist_f (64 queries x 256 start rows per
+// workgroup, staged through LDS) writes the distance matrix and k_scan_select
+// takes, with one wave per query, the exact L smallest (distance, id) keys.
+// Uint8 rows are scored on the matrix cores twice instead (first for bounds,
+// then for the few keys under them), so the matrix never reaches memory.
+// Start rows are in ascending id order, so the row index breaks distance ties
+// exactly as the id does.
 constexpr int SD_Q = 64, SD_E = 256, SD_KW = 4, SD_STRIDE = SD_KW + 1;  // in 16-byte words
 constexpr uint32_t D_INVALID = 0xFFFFFFFFu;
 
@@ -238,97 +240,193 @@ __device__ inline int frag_sq(v4i32 f) {
   return __builtin_amdgcn_sdot4(f.w, f.w, s, false);
 }
 
-__device__ inline void scan_dist_wave_tile(const Index& ix, const ScanArgs& a, uint32_t e0, uint32_t q0) {
+// One wave scores 64 queries against a span of SCAN_SPAN start rows, as
+// SCAN_SPAN / 64 tiles of 64 x 64. SCAN_MIN writes each query's group minima
+// (32 start rows per group); SCAN_DENSE writes them and the distances too
+// (each lane 16 contiguous bytes of its query's row). SCAN_FILTER writes the
+// (distance, row) key of every row at or below the query's bound to the
+// query's slots for this span and the number of such rows; rows beyond the
+// slots are left to the dense fallback. No atomics: each (query, span) pair
+// belongs to one wave.
+enum ScanPass { SCAN_MIN = 0, SCAN_FILTER = 1, SCAN_DENSE = 2 };
+
+// key slots per (query, span): the per-query key buffer split over the spans
+__device__ inline uint32_t scan_slots(uint32_t n_span) { return SCAN_KEYS_Q / max(1u, n_span); }
+
+template <int PASS>
+__device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, uint32_t span, uint32_t q0) {
   const int l = lane_id();
   const uint32_t ns = a.ns, dim = ix.dim, r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u;
-  const uint8_t* erow[4];
-  const uint8_t* qrow[4];
+  const uint32_t rb = (uint32_t)(l >> 4) * 4u;  // first of this lane's four start rows within a 16-row tile
+  const uint32_t n_span = (ns + SCAN_SPAN - 1) / SCAN_SPAN, slots = scan_slots(n_span);
+  // query rows q0 + 16n + r: row 16n of the base below
+  const uint8_t* qb = (a.mode == MODE_QUERY ? (const uint8_t*)a.q : ix.x + (size_t)(a.first + a.qoff) * dim) +
+                      (size_t)(q0 + r) * dim;
+  const uint32_t q_left = a.nq > q0 + r ? a.nq - (q0 + r) : 0u;  // queries n with 16n < q_left exist
+  uint32_t cnt[4] = {0, 0, 0, 0};
+  // the ids of a tile's start rows are read one tile ahead
+  constexpr bool AHEAD = PASS != SCAN_FILTER;  // the filter pass is short of registers
+  const uint32_t e_end = min(ns, (span + 1) * SCAN_SPAN);
+  uint32_t nid[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const uint32_t e = e0 + (uint32_t)m * 16u + r;
-    erow[m] = e < ns ? ix.x + (size_t)start_id(ix, a, e) * dim : nullptr;
-    const uint32_t q = q0 + (uint32_t)m * 16u + r;
-    qrow[m] = q >= a.nq ? nullptr
-              : a.mode == MODE_QUERY ? (const uint8_t*)a.q + (size_t)q * dim
-                                     : ix.x + (size_t)(a.first + a.qoff + q) * dim;
+    const uint32_t e = span * SCAN_SPAN + (uint32_t)m * 16u + r;
+    nid[m] = AHEAD && e < e_end ? start_id(ix, a, e) : NONE;
   }
-  v4i32 acc[4][4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int n = 0; n < 4; ++n) acc[m][n] = v4i32{0, 0, 0, 0};
-  int en[4] = {0, 0, 0, 0}, qn[4] = {0, 0, 0, 0};
-  for (uint32_t k0 = 0; k0 < dim; k0 += 64) {
-    v4i32 ef[4], qf[4];
+  for (uint32_t e0 = span * SCAN_SPAN; e0 < e_end; e0 += SD_WT) {
+    const uint8_t* erow[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      ef[m] = signed_frag(erow[m], k0 + kc, dim);
-      qf[m] = signed_frag(qrow[m], k0 + kc, dim);
+      if constexpr (AHEAD) {
+        erow[m] = nid[m] != NONE ? ix.x + (size_t)nid[m] * dim : nullptr;
+        const uint32_t e = e0 + SD_WT + (uint32_t)m * 16u + r;
+        nid[m] = e < e_end ? start_id(ix, a, e) : NONE;
+      } else {
+        const uint32_t e = e0 + (uint32_t)m * 16u + r;
+        erow[m] = e < e_end ? ix.x + (size_t)start_id(ix, a, e) * dim : nullptr;
+      }
     }
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      en[m] += frag_sq(ef[m]);
-      qn[m] += frag_sq(qf[m]);
-    }
+    v4i32 acc[4][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int n = 0; n < 4; ++n) acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ef[m], qf[n], acc[m][n], 0, 0, 0);
-  }
-  // full squared norms: lane l then holds start row m*16 + l%16 and query n*16 + l%16
+      for (int n = 0; n < 4; ++n) acc[m][n] = v4i32{0, 0, 0, 0};
+    int en[4] = {0, 0, 0, 0}, qn[4] = {0, 0, 0, 0};
+    for (uint32_t k0 = 0; k0 < dim; k0 += 64) {
+      v4i32 ef[4], qf[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    en[m] += __shfl_xor(en[m], 16, 64);
-    en[m] += __shfl_xor(en[m], 32, 64);
-    qn[m] += __shfl_xor(qn[m], 16, 64);
-    qn[m] += __shfl_xor(qn[m], 32, 64);
-  }
-  const uint32_t rb = (uint32_t)(l >> 4) * 4u;  // first of this lane's four start rows within a 16-row tile
-  const bool vec = (ns & 3u) == 0;
+      for (int m = 0; m < 4; ++m) {
+        ef[m] = signed_frag(erow[m], k0 + kc, dim);
+        qf[m] = signed_frag((uint32_t)m * 16u < q_left ? qb + (size_t)m * 16u * dim : nullptr, k0 + kc, dim);
+      }
 #pragma unroll
-  for (int n = 0; n < 4; ++n) {
-    const uint32_t qi = q0 + (uint32_t)n * 16u + r;
-    const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;  // a bootstrap row never scores itself
-    uint32_t g[2] = {D_INVALID, D_INVALID};  // minima of start rows [e0, e0 + 32) and [e0 + 32, e0 + 64)
+      for (int m = 0; m < 4; ++m) {
+        en[m] += frag_sq(ef[m]);
+        qn[m] += frag_sq(qf[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ef[m], qf[n], acc[m][n], 0, 0, 0);
+    }
+    // full squared norms: lane l then holds start row m*16 + l%16 and query n*16 + l%16
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      uint32_t d[4];
+      en[m] += __shfl_xor(en[m], 16, 64);
+      en[m] += __shfl_xor(en[m], 32, 64);
+      qn[m] += __shfl_xor(qn[m], 16, 64);
+      qn[m] += __shfl_xor(qn[m], 32, 64);
+    }
+    int er[4][4];  // norms of this lane's start rows m*16 + rb + i
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int e_n = __shfl(en[m], (int)rb + i, 64);
-        const uint32_t e = e0 + (uint32_t)m * 16u + rb + (uint32_t)i;
-        d[i] = e == self || e >= ns ? D_INVALID : (uint32_t)(qn[n] + e_n - 2 * acc[m][n][i]);
-        g[m >> 1] = min(g[m >> 1], d[i]);
-      }
-      if (qi >= a.nq) continue;
-      const uint32_t e = e0 + (uint32_t)m * 16u + rb;
-      uint32_t* out = a.dist + (size_t)qi * ns + e;
-      if (vec && e + 3 < ns) {
-        *reinterpret_cast<uint4*>(out) = make_uint4(d[0], d[1], d[2], d[3]);
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) er[m][i] = __shfl(en[m], (int)rb + i, 64);
+    const bool check = a.mode == MODE_BOOT || e0 + SD_WT > ns;  // some row of the tile may be invalid
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const uint32_t qi = q0 + (uint32_t)n * 16u + r;
+      if constexpr (PASS != SCAN_FILTER) {
+        uint32_t d[4][4];
+        if (check) {
+          const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;  // a bootstrap row never scores itself
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint32_t e = e0 + (uint32_t)m * 16u + rb + (uint32_t)i;
+              d[m][i] = e == self || e >= ns ? D_INVALID : (uint32_t)(qn[n] + er[m][i] - 2 * acc[m][n][i]);
+            }
+        } else {
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) d[m][i] = (uint32_t)(qn[n] + er[m][i] - 2 * acc[m][n][i]);
+        }
+        if constexpr (PASS == SCAN_DENSE) {
+          if (qi < a.nq) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              const uint32_t e = e0 + (uint32_t)m * 16u + rb;
+              uint32_t* out = a.dist + (size_t)qi * ns + e;
+              if ((ns & 3u) == 0 && e + 3 < ns) {
+                *reinterpret_cast<uint4*>(out) = make_uint4(d[m][0], d[m][1], d[m][2], d[m][3]);
+              } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                  if (e + (uint32_t)i < ns) out[i] = d[m][i];
+              }
+            }
+          }
+        }
+        uint32_t g[2] = {D_INVALID, D_INVALID};  // minima of start rows [e0, e0 + 32) and [e0 + 32, e0 + 64)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) g[m >> 1] = min(g[m >> 1], d[m][i]);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          g[h] = min(g[h], (uint32_t)__shfl_xor((int)g[h], 16, 64));
+          g[h] = min(g[h], (uint32_t)__shfl_xor((int)g[h], 32, 64));
+        }
+        // lanes 0-15 write group 0, lanes 16-31 group 1 (group slots 2 per 64-row tile)
+        if (qi < a.nq && l < 32)
+          a.gmin[(size_t)qi * a.g_stride + (e0 >> 5) + (uint32_t)(l >> 4)] = l < 16 ? g[0] : g[1];
       } else {
+        const uint32_t bnd = qi < a.nq ? a.bound[qi] : 0u;
+        const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;  // a bootstrap row never scores itself
+        uint32_t d[4][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (e + (uint32_t)i < ns) out[i] = d[i];
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t e = e0 + (uint32_t)m * 16u + rb + (uint32_t)i;
+            d[m][i] = e == self || e >= ns ? D_INVALID : (uint32_t)(qn[n] + er[m][i] - 2 * acc[m][n][i]);
+          }
+        uint32_t mine = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) mine += d[m][i] <= bnd ? 1u : 0u;
+        // the four lanes of query r (l = r + 16k) take consecutive slots
+        const uint32_t c0 = (uint32_t)__shfl((int)mine, (int)r, 64), c1 = (uint32_t)__shfl((int)mine, (int)r + 16, 64);
+        const uint32_t c2 = (uint32_t)__shfl((int)mine, (int)r + 32, 64),
+                       c3 = (uint32_t)__shfl((int)mine, (int)r + 48, 64);
+        const uint32_t k = (uint32_t)(l >> 4);
+        uint32_t pos = cnt[n] + (k > 0 ? c0 : 0u) + (k > 1 ? c1 : 0u) + (k > 2 ? c2 : 0u);
+        cnt[n] += c0 + c1 + c2 + c3;
+        if (mine && qi < a.nq) {
+          uint64_t* out = a.cand + (size_t)qi * SCAN_KEYS_Q + span * slots;
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (d[m][i] <= bnd) {
+                if (pos < slots) out[pos] = make_key(d[m][i], e0 + (uint32_t)m * 16u + rb + (uint32_t)i);
+                ++pos;
+              }
+        }
       }
     }
+  }
+  if constexpr (PASS == SCAN_FILTER) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      g[h] = min(g[h], (uint32_t)__shfl_xor((int)g[h], 16, 64));
-      g[h] = min(g[h], (uint32_t)__shfl_xor((int)g[h], 32, 64));
+    for (int n = 0; n < 4; ++n) {
+      const uint32_t qi = q0 + (uint32_t)n * 16u + r;
+      if (l < 16 && qi < a.nq) a.ncand[(size_t)qi * n_span + span] = cnt[n];
     }
-    // lanes 0-15 write group 0, lanes 16-31 group 1 (group slots 2 per 64-row tile)
-    if (qi < a.nq && l < 32) a.gmin[(size_t)qi * a.g_stride + (e0 >> 5) + (uint32_t)(l >> 4)] = l < 16 ? g[0] : g[1];
   }
 }
 
-__global__ void __launch_bounds__(256) k_scan_dist(Index ix, ScanArgs a) {
+template <int PASS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_scan_dist(Index ix, ScanArgs a) {
   if (gated(ix, a.d)) return;
   resolve(ix, a);
-  const uint32_t n_et = (a.ns + SD_WT - 1) / SD_WT, n_tiles = n_et * ((a.nq + SD_WT - 1) / SD_WT);
+  const uint32_t n_span = (a.ns + SCAN_SPAN - 1) / SCAN_SPAN, n_tasks = n_span * ((a.nq + SD_WT - 1) / SD_WT);
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  // consecutive waves take consecutive start tiles of one query tile
-  for (uint32_t tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); tile < n_tiles; tile += waves)
-    scan_dist_wave_tile(ix, a, (tile % n_et) * SD_WT, (tile / n_et) * SD_WT);
+  // consecutive waves take consecutive spans of one query tile
+  for (uint32_t t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < n_tasks; t += waves)
+    scan_dist_wave_span<PASS>(ix, a, t % n_span, (t / n_span) * SD_WT);
 }
 
 // Float rows: the same 64 x 256 tiling over 16-element slices, in FP32; start
@@ -508,47 +606,57 @@ __device__ inline uint32_t sel_compact(const uint32_t* D, uint32_t ns, uint32_t 
   return n;
 }
 
+// rows a query selects: L, or every valid start row if fewer
+__device__ inline uint32_t scan_need(const ScanArgs& a, uint32_t qi) {
+  const bool self_in = a.mode == MODE_BOOT && a.qoff + qi < a.ns;  // the one row scored D_INVALID
+  return min(a.L, a.ns - (self_in ? 1u : 0u));
+}
+
+// The need_all-th smallest group minimum of query qi: at least need_all
+// groups, and so at least need_all rows, lie at or below it. With fewer valid
+// groups than that, every valid row (D_INVALID - 1).
+__device__ inline uint32_t scan_bound_one(const ScanArgs& a, uint32_t qi, uint32_t need_all) {
+  const int l = lane_id();
+  const uint32_t ng = (a.ns + a.g_rows - 1) / a.g_rows * (a.g_rows / 32);
+  const uint32_t* G = a.gmin + (size_t)qi * a.g_stride;
+  uint32_t gv[SEL_GPL];
+  uint32_t glo = D_INVALID, ghi = 0, gvalid = 0;
+#pragma unroll
+  for (int t = 0; t < SEL_GPL; ++t) {
+    const uint32_t i = (uint32_t)(t * 64 + l);
+    gv[t] = i < ng ? G[i] : D_INVALID;
+    if (gv[t] != D_INVALID) {
+      glo = min(glo, gv[t]);
+      ghi = max(ghi, gv[t]);
+      ++gvalid;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    glo = min(glo, (uint32_t)__shfl_xor((int)glo, o, 64));
+    ghi = max(ghi, (uint32_t)__shfl_xor((int)ghi, o, 64));
+    gvalid += (uint32_t)__shfl_xor((int)gvalid, o, 64);
+  }
+  if (bcast(gvalid) < need_all) return D_INVALID - 1;
+  uint32_t lo = bcast(glo), hi = bcast(ghi);
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    uint32_t c = 0;
+#pragma unroll
+    for (int t = 0; t < SEL_GPL; ++t) c += (uint32_t)__popcll(ballot(gv[t] <= mid));
+    if (c >= need_all) hi = mid;
+    else lo = mid + 1;
+  }
+  return hi;
+}
+
 __device__ inline void scan_select_one(const Index& ix, const ScanArgs& a, uint32_t qi, uint64_t* sel, uint32_t cap) {
   const int l = lane_id();
   const uint32_t ns = a.ns;
   const uint32_t* D = a.dist + (size_t)qi * ns;
-  const bool self_in = a.mode == MODE_BOOT && a.qoff + qi < ns;  // the one row scored D_INVALID
-  const uint32_t need_all = min(a.L, ns - (self_in ? 1u : 0u));
+  const uint32_t need_all = scan_need(a, qi);
   uint32_t cnt = 0;
   if (need_all > 0) {
-    // the bound from the group minima
-    const uint32_t ng = (ns + a.g_rows - 1) / a.g_rows * (a.g_rows / 32);
-    const uint32_t* G = a.gmin + (size_t)qi * a.g_stride;
-    uint32_t gv[SEL_GPL];
-    uint32_t glo = D_INVALID, ghi = 0, gvalid = 0;
-#pragma unroll
-    for (int t = 0; t < SEL_GPL; ++t) {
-      const uint32_t i = (uint32_t)(t * 64 + l);
-      gv[t] = i < ng ? G[i] : D_INVALID;
-      if (gv[t] != D_INVALID) {
-        glo = min(glo, gv[t]);
-        ghi = max(ghi, gv[t]);
-        ++gvalid;
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      glo = min(glo, (uint32_t)__shfl_xor((int)glo, o, 64));
-      ghi = max(ghi, (uint32_t)__shfl_xor((int)ghi, o, 64));
-      gvalid += (uint32_t)__shfl_xor((int)gvalid, o, 64);
-    }
-    uint32_t hi = D_INVALID - 1;  // no bound: every valid row
-    if (bcast(gvalid) >= need_all) {
-      uint32_t lo = bcast(glo);
-      hi = bcast(ghi);
-      while (lo < hi) {  // the need_all-th smallest group minimum
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        uint32_t c = 0;
-#pragma unroll
-        for (int t = 0; t < SEL_GPL; ++t) c += (uint32_t)__popcll(ballot(gv[t] <= mid));
-        if (c >= need_all) hi = mid;
-        else lo = mid + 1;
-      }
-    }
+    uint32_t hi = scan_bound_one(a, qi, need_all);
     uint32_t lmin;
     cnt = sel_compact(D, ns, hi, sel, cap, &lmin);
     if (cnt > cap) {
@@ -606,6 +714,84 @@ __global__ void __launch_bounds__(256) k_scan_select(Index ix, ScanArgs a, uint3
   const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (qi >= a.nq) return;
   scan_select_one(ix, a, qi, reinterpret_cast<uint64_t*>(smem + (size_t)(threadIdx.x >> 6) * 8 * sel_cap), sel_cap);
+}
+
+// uint8 rows, in four launches that never write the distance matrix: group
+// minima (k_scan_dist<SCAN_MIN>), each query's bound (k_scan_bound), the keys
+// at or below it (k_scan_dist<SCAN_FILTER>), and their sort (k_scan_final).
+// A query whose keys overflow its list (heavy ties at the bound) has its
+// distance row written out and takes the general selection above.
+__global__ void __launch_bounds__(256) k_scan_bound(Index ix, ScanArgs a) {
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (qi >= a.nq) return;
+  const uint32_t need_all = scan_need(a, qi);
+  const uint32_t b = need_all ? scan_bound_one(a, qi, need_all) : 0u;
+  if (lane_id() == 0) a.bound[qi] = b;
+}
+
+// query qi's distances to every start row (exact in int32, as on the matrix cores)
+__device__ inline void scan_dense_row_u8(const Index& ix, const ScanArgs& a, uint32_t qi) {
+  const uint32_t dim = ix.dim, ns = a.ns;
+  const uint8_t* q = a.mode == MODE_QUERY ? (const uint8_t*)a.q + (size_t)qi * dim
+                                          : ix.x + (size_t)(a.first + a.qoff + qi) * dim;
+  const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;
+  uint32_t* D = a.dist + (size_t)qi * ns;
+  for (uint32_t e = (uint32_t)lane_id(); e < ns; e += 64) {
+    const uint8_t* row = ix.x + (size_t)start_id(ix, a, e) * dim;
+    int s = 0;
+    for (uint32_t k = 0; k < dim; k += 16) {
+      const uint4 qa = *reinterpret_cast<const uint4*>(q + k), ea = *reinterpret_cast<const uint4*>(row + k);
+      const uint32_t qw[4] = {qa.x, qa.y, qa.z, qa.w}, ew[4] = {ea.x, ea.y, ea.z, ea.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int qs = (int)(qw[j] ^ 0x80808080u), es = (int)(ew[j] ^ 0x80808080u);
+        s = __builtin_amdgcn_sdot4(qs, qs, s, false);
+        s = __builtin_amdgcn_sdot4(es, es, s, false);
+        s -= 2 * __builtin_amdgcn_sdot4(qs, es, 0, false);
+      }
+    }
+    D[e] = e == self ? D_INVALID : (uint32_t)s;
+  }
+  __threadfence_block();
+  wave_sync();
+}
+
+__global__ void __launch_bounds__(256) k_scan_final(Index ix, ScanArgs a, uint32_t sel_cap) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (qi >= a.nq) return;
+  uint64_t* sel = reinterpret_cast<uint64_t*>(smem + (size_t)(threadIdx.x >> 6) * 8 * sel_cap);
+  const int l = lane_id();
+  const uint32_t n_span = (a.ns + SCAN_SPAN - 1) / SCAN_SPAN, slots = scan_slots(n_span);  // one span per lane
+  const uint32_t c = (uint32_t)l < n_span ? a.ncand[(size_t)qi * n_span + (uint32_t)l] : 0u;
+  uint32_t off = c;  // inclusive prefix over the spans
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = (uint32_t)__shfl_up((int)off, (unsigned)o, 64);
+    if (l >= o) off += v;
+  }
+  const uint32_t n = (uint32_t)__shfl((int)off, 63, 64);
+  if (ballot(c > slots) || n > sel_cap) {
+    scan_dense_row_u8(ix, a, qi);
+    scan_select_one(ix, a, qi, sel, sel_cap);
+    return;
+  }
+  off -= c;
+  const uint64_t* src = a.cand + (size_t)qi * SCAN_KEYS_Q + (uint32_t)l * slots;
+  for (uint32_t j = 0; j < c; ++j) sel[off + j] = src[j];
+  const int np = next_pow2_ge64((int)n);
+  for (int i = (int)n + l; i < np; i += 64) sel[i] = KEY_NONE;
+  wave_sync();
+  wave_bitonic_sort(sel, np);
+  const uint32_t cnt = min(n, scan_need(a, qi));
+  for (uint32_t i = (uint32_t)l; i < cnt; i += 64) {
+    const uint64_t k = sel[i];
+    a.out_keys[(size_t)qi * a.out_stride + i] = make_key(key_dist(k), start_id(ix, a, key_id(k)));
+  }
+  if (l == 0) a.out_n[qi] = cnt;
 }
 
 // keys per wave: the compacted rows, or the L selected ones
@@ -2890,12 +3076,39 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
   // shapes from the upper bounds; the kernels resolve the launch-time counts
   const uint64_t tiles = (uint64_t)blocks_for(a.ns ? a.ns : 1u, SD_E) * blocks_for(a.nq, SD_Q);
   const dim3 dgrid(tiles < 2 * PERSIST_BLOCKS ? (unsigned)tiles : 2 * PERSIST_BLOCKS);
+  const uint32_t cap = scan_select_keys(a.L);
+  const dim3 grid(blocks_for(a.nq, 4)), blk(256);
+  const size_t lds = 4 * scan_select_lds_per_wave(a.L);
+  if (a.ns > SEL_GPL * 64 * 32) return hipErrorInvalidValue;
   if (ix.metric == 0) {
-    // one 64 x 64 tile per wave, four waves per workgroup
-    const uint64_t wt = (uint64_t)blocks_for(a.ns ? a.ns : 1u, SD_WT) * blocks_for(a.nq, SD_WT);
+    // one 64-query x SCAN_SPAN-row span per wave, four waves per workgroup
+    if (a.ns > SCAN_SPAN * 64) return hipErrorInvalidValue;
+    const uint64_t wt = (uint64_t)blocks_for(a.ns ? a.ns : 1u, SCAN_SPAN) * blocks_for(a.nq, SD_WT);
     const uint64_t wg = (wt + 3) / 4;
-    hipLaunchKernelGGL(k_scan_dist, dim3(wg < 4 * PERSIST_BLOCKS ? (unsigned)wg : 4 * PERSIST_BLOCKS), dim3(256), 0, s,
-                       ix, a);
+    const dim3 tgrid(wg < 4 * PERSIST_BLOCKS ? (unsigned)wg : 4 * PERSIST_BLOCKS);
+    if (a.L > SCAN_FILTER_L_MAX) {
+      // long lists: the bound admits a large share of the rows, so the matrix is written
+      hipLaunchKernelGGL(k_scan_dist<SCAN_DENSE>, tgrid, dim3(256), 0, s, ix, a);
+      if (after_dist) {
+        const hipError_t e = hipEventRecord(after_dist, s);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(k_scan_select, grid, blk, lds, s, ix, a, cap);
+      return hipGetLastError();
+    }
+    if (!a.bound || !a.ncand || !a.cand) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan_dist<SCAN_MIN>, tgrid, dim3(256), 0, s, ix, a);
+    hipLaunchKernelGGL(k_scan_bound, grid, blk, 0, s, ix, a);
+    hipLaunchKernelGGL(k_scan_dist<SCAN_FILTER>, tgrid, dim3(256), 0, s, ix, a);
+    if (after_dist) {
+      const hipError_t e = hipEventRecord(after_dist, s);
+      if (e != hipSuccess) return e;
+    }
+    // key capacity in LDS: lists up to 64 see about a hundred keys, so a
+    // smaller capacity keeps more waves resident
+    const uint32_t fcap = max(a.L <= 64 ? SCAN_CAND_CAP / 2 : SCAN_CAND_CAP, cap);
+    hipLaunchKernelGGL(k_scan_final, grid, blk, (size_t)4 * 8 * fcap, s, ix, a, fcap);
+    return hipGetLastError();
   } else {
     const int trav = a.mode == MODE_BOOT ? TRAV_NATIVE : a.trav;
     if (trav == TRAV_NATIVE)
@@ -2909,10 +3122,6 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
     const hipError_t e = hipEventRecord(after_dist, s);
     if (e != hipSuccess) return e;
   }
-  const uint32_t cap = scan_select_keys(a.L);
-  const dim3 grid(blocks_for(a.nq, 4)), blk(256);
-  const size_t lds = 4 * scan_select_lds_per_wave(a.L);
-  if (a.ns > SEL_GPL * 64 * 32) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_scan_select, grid, blk, lds, s, ix, a, cap);
   return hipGetLastError();
 }

@@ -35,6 +35,12 @@ struct SearchArgs {
 
 // k_scan: the L best start nodes (entry set, or the batch for a bootstrap,
 // excluding the query itself) of every query, in (distance, id) order
+// uint8 start-set selection: start rows per span (a start set holds at most
+// 64 spans), key slots per query (split evenly over the spans), keys sorted
+// per query before the dense fallback, and the longest list selected from
+// those keys (longer lists write the distance matrix)
+constexpr uint32_t SCAN_SPAN = 256, SCAN_KEYS_Q = 1024, SCAN_CAND_CAP = 1024, SCAN_FILTER_L_MAX = 128;
+
 struct ScanArgs {
   int mode;
   const void* q;       // MODE_QUERY rows; otherwise query i is stored vector first + qoff + i
@@ -45,6 +51,9 @@ struct ScanArgs {
   uint32_t* gmin;      // [nq x g_stride] smallest distance of each group of start rows
   uint32_t g_stride;   // group slots per query (upper bound over the launch-time ns)
   uint32_t g_rows;     // start rows per scoring tile; each tile has g_rows / 32 group slots
+  uint32_t* bound;     // uint8 rows: [nq] bound on the L-th smallest distance
+  uint32_t* ncand;     // uint8 rows: [nq x spans] rows at or below the bound in each span of start rows
+  uint64_t* cand;      // uint8 rows: [nq x SCAN_KEYS_Q] their (distance, row) keys, by span
   uint64_t* out_keys;  // [nq x out_stride]
   uint32_t* out_n;     // [nq]
   uint32_t out_stride;

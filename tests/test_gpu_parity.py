@@ -73,7 +73,14 @@ def test_parity_small_default():
 
 
 def test_parity_small_no_refine_two_L():
-    run_parity(small_workload(seed=2), refine=False, search_L=(16, 32, 100))
+    # L = 200 takes the start-set path that writes the distance matrix
+    run_parity(small_workload(seed=2), refine=False, search_L=(16, 32, 100, 200))
+
+
+def test_parity_many_entries_filtered_start_set():
+    # 1,000 entries: four spans of start rows, so the bounded keys of a query
+    # come from several spans and are merged before the sort
+    run_parity(small_workload(seed=12, rounds=1), n_entry=1000, search_L=(10, 64, 128))
 
 
 def test_parity_tombstone_only():
