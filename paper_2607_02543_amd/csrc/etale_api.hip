@@ -31,6 +31,8 @@ struct etale_index {
   uint32_t* retired_stack = nullptr;
   unsigned long long* ctr = nullptr;
   uint32_t* entries = nullptr;
+  uint8_t* ent_x = nullptr;     // uint8 rows: shifted copy of the entry set's rows
+  int32_t* ent_norm = nullptr;  // and their squared norms
   // call scratch
   uint64_t* vis_keys = nullptr;
   uint32_t* vis_cnt = nullptr;
@@ -555,6 +557,10 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   ALLOC(ix->retired_stack, P * 4);
   ALLOC(ix->ctr, C_NCOUNTERS * 8);
   ALLOC(ix->entries, (uint64_t)c.n_entry * 4);
+  if (c.metric == ETALE_METRIC_L2_U8) {
+    ALLOC(ix->ent_x, (uint64_t)c.n_entry * c.dim);
+    ALLOC(ix->ent_norm, ((uint64_t)c.n_entry + 63) / 64 * 64 * 4);
+  }
   ALLOC(ix->vis_keys, B * std::max<uint64_t>(ix->vcap_build, R) * 8);  // also the refined lists (R per node)
   ALLOC(ix->vis_cnt, B * 4);
   ALLOC(ix->F, B * R * 4);
@@ -604,6 +610,8 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   d.retired_stack = ix->retired_stack;
   d.ctr = ix->ctr;
   d.entries = ix->entries;
+  d.ent_x = ix->ent_x;
+  d.ent_norm = ix->ent_norm;
   ix->pair_bits = 1;
   while ((1ull << ix->pair_bits) <= C) ++ix->pair_bits;  // every id < 2^bits - 1: a KEY_NONE target sorts last
   if (launch_init(d, ix->stream) != hipSuccess || hipStreamSynchronize(ix->stream) != hipSuccess)

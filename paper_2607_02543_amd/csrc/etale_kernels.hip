@@ -155,6 +155,30 @@ __device__ inline uint32_t block_prefix(bool keep, uint32_t* wcnt, uint32_t* tot
   return before + lanes_below(m);
 }
 
+// The uint8 entry set's shifted copy: entry e's row XOR 0x80 (each byte as a
+// signed value, as the matrix cores take it) at row e, its squared norm at e.
+__global__ void __launch_bounds__(256) k_entry_rows(Index ix, uint32_t S, Dyn d) {
+  if (gated(ix, d)) return;
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= min<uint64_t>(S, ix.ctr[C_N_ENTRIES])) return;
+  const uint4* src = reinterpret_cast<const uint4*>(ix.x + (size_t)ix.entries[e] * ix.dim);
+  uint4* dst = reinterpret_cast<uint4*>(ix.ent_x + (size_t)e * ix.dim);
+  int sq = 0;
+  for (uint32_t c = 0; c < ix.dim / 16; ++c) {
+    uint4 w = src[c];
+    w.x ^= 0x80808080u;
+    w.y ^= 0x80808080u;
+    w.z ^= 0x80808080u;
+    w.w ^= 0x80808080u;
+    dst[c] = w;
+    sq = __builtin_amdgcn_sdot4((int)w.x, (int)w.x, sq, false);
+    sq = __builtin_amdgcn_sdot4((int)w.y, (int)w.y, sq, false);
+    sq = __builtin_amdgcn_sdot4((int)w.z, (int)w.z, sq, false);
+    sq = __builtin_amdgcn_sdot4((int)w.w, (int)w.w, sq, false);
+  }
+  ix.ent_norm[e] = sq;
+}
+
 __global__ void __launch_bounds__(1024) k_refresh_entries(Index ix, uint32_t next_id, uint32_t S, Dyn d) {
   __shared__ uint32_t wcnt[16];
   if (gated(ix, d)) return;
@@ -233,6 +257,16 @@ __device__ inline v4i32 signed_frag(const uint8_t* row, uint32_t off, uint32_t d
   return f;
 }
 
+// a fragment of a row stored already shifted
+__device__ inline v4i32 shifted_frag(const uint8_t* row, uint32_t off, uint32_t dim) {
+  v4i32 f = {0, 0, 0, 0};
+  if (row && off < dim) {
+    const uint4 w = *reinterpret_cast<const uint4*>(row + off);
+    f = v4i32{(int)w.x, (int)w.y, (int)w.z, (int)w.w};
+  }
+  return f;
+}
+
 __device__ inline int frag_sq(v4i32 f) {
   int s = __builtin_amdgcn_sdot4(f.x, f.x, 0, false);
   s = __builtin_amdgcn_sdot4(f.y, f.y, s, false);
@@ -253,7 +287,9 @@ enum ScanPass { SCAN_MIN = 0, SCAN_FILTER = 1, SCAN_DENSE = 2 };
 // key slots per (query, span): the per-query key buffer split over the spans
 __device__ inline uint32_t scan_slots(uint32_t n_span) { return SCAN_KEYS_Q / max(1u, n_span); }
 
-template <int PASS>
+// PRE: the start set is the entry set, read from its shifted copy (rows in
+// entry order, norms beside them) instead of through the id list.
+template <int PASS, bool PRE>
 __device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, uint32_t span, uint32_t q0) {
   const int l = lane_id();
   const uint32_t ns = a.ns, dim = ix.dim, r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u;
@@ -265,7 +301,7 @@ __device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, u
   const uint32_t q_left = a.nq > q0 + r ? a.nq - (q0 + r) : 0u;  // queries n with 16n < q_left exist
   uint32_t cnt[4] = {0, 0, 0, 0};
   // the ids of a tile's start rows are read one tile ahead
-  constexpr bool AHEAD = PASS != SCAN_FILTER;  // the filter pass is short of registers
+  constexpr bool AHEAD = !PRE && PASS != SCAN_FILTER;  // the filter pass is short of registers
   const uint32_t e_end = min(ns, (span + 1) * SCAN_SPAN);
   uint32_t nid[4];
 #pragma unroll
@@ -277,7 +313,10 @@ __device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, u
     const uint8_t* erow[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      if constexpr (AHEAD) {
+      if constexpr (PRE) {
+        const uint32_t e = e0 + (uint32_t)m * 16u + r;
+        erow[m] = e < e_end ? ix.ent_x + (size_t)e * dim : nullptr;
+      } else if constexpr (AHEAD) {
         erow[m] = nid[m] != NONE ? ix.x + (size_t)nid[m] * dim : nullptr;
         const uint32_t e = e0 + SD_WT + (uint32_t)m * 16u + r;
         nid[m] = e < e_end ? start_id(ix, a, e) : NONE;
@@ -296,12 +335,12 @@ __device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, u
       v4i32 ef[4], qf[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        ef[m] = signed_frag(erow[m], k0 + kc, dim);
+        ef[m] = PRE ? shifted_frag(erow[m], k0 + kc, dim) : signed_frag(erow[m], k0 + kc, dim);
         qf[m] = signed_frag((uint32_t)m * 16u < q_left ? qb + (size_t)m * 16u * dim : nullptr, k0 + kc, dim);
       }
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        en[m] += frag_sq(ef[m]);
+        if constexpr (!PRE) en[m] += frag_sq(ef[m]);
         qn[m] += frag_sq(qf[m]);
       }
 #pragma unroll
@@ -312,16 +351,28 @@ __device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, u
     // full squared norms: lane l then holds start row m*16 + l%16 and query n*16 + l%16
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      en[m] += __shfl_xor(en[m], 16, 64);
-      en[m] += __shfl_xor(en[m], 32, 64);
+      if constexpr (!PRE) {
+        en[m] += __shfl_xor(en[m], 16, 64);
+        en[m] += __shfl_xor(en[m], 32, 64);
+      }
       qn[m] += __shfl_xor(qn[m], 16, 64);
       qn[m] += __shfl_xor(qn[m], 32, 64);
     }
     int er[4][4];  // norms of this lane's start rows m*16 + rb + i
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 4; ++m) {
+      if constexpr (PRE) {
+        // the norm array is padded to whole 64-row tiles
+        const int4 v = *reinterpret_cast<const int4*>(ix.ent_norm + e0 + (uint32_t)m * 16u + rb);
+        er[m][0] = v.x;
+        er[m][1] = v.y;
+        er[m][2] = v.z;
+        er[m][3] = v.w;
+      } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) er[m][i] = __shfl(en[m], (int)rb + i, 64);
+        for (int i = 0; i < 4; ++i) er[m][i] = __shfl(en[m], (int)rb + i, 64);
+      }
+    }
     const bool check = a.mode == MODE_BOOT || e0 + SD_WT > ns;  // some row of the tile may be invalid
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
@@ -418,7 +469,7 @@ __device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, u
   }
 }
 
-template <int PASS>
+template <int PASS, bool PRE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_scan_dist(Index ix, ScanArgs a) {
   if (gated(ix, a.d)) return;
   resolve(ix, a);
@@ -426,7 +477,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   // consecutive waves take consecutive spans of one query tile
   for (uint32_t t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < n_tasks; t += waves)
-    scan_dist_wave_span<PASS>(ix, a, t % n_span, (t / n_span) * SD_WT);
+    scan_dist_wave_span<PASS, PRE>(ix, a, t % n_span, (t / n_span) * SD_WT);
 }
 
 // Float rows: the same 64 x 256 tiling over 16-element slices, in FP32; start
@@ -3013,6 +3064,8 @@ hipError_t launch_gather_rows(const void* rows, const uint32_t* idx, uint32_t n,
 
 hipError_t launch_refresh_entries(const Index& ix, uint32_t bound, uint32_t S, Dyn d, hipStream_t s) {
   hipLaunchKernelGGL(k_refresh_entries, dim3(1), dim3(1024), 0, s, ix, bound, S, d);
+  if (ix.metric == 0 && ix.ent_x && ix.ent_norm)
+    hipLaunchKernelGGL(k_entry_rows, dim3(blocks_for(S ? S : 1u, 256)), dim3(256), 0, s, ix, S, d);
   return hipGetLastError();
 }
 
@@ -3086,9 +3139,13 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
     const uint64_t wt = (uint64_t)blocks_for(a.ns ? a.ns : 1u, SCAN_SPAN) * blocks_for(a.nq, SD_WT);
     const uint64_t wg = (wt + 3) / 4;
     const dim3 tgrid(wg < 4 * PERSIST_BLOCKS ? (unsigned)wg : 4 * PERSIST_BLOCKS);
+    const bool pre = a.mode != MODE_BOOT && ix.ent_x && ix.ent_norm;
     if (a.L > SCAN_FILTER_L_MAX) {
       // long lists: the bound admits a large share of the rows, so the matrix is written
-      hipLaunchKernelGGL(k_scan_dist<SCAN_DENSE>, tgrid, dim3(256), 0, s, ix, a);
+      if (pre)
+        hipLaunchKernelGGL((k_scan_dist<SCAN_DENSE, true>), tgrid, dim3(256), 0, s, ix, a);
+      else
+        hipLaunchKernelGGL((k_scan_dist<SCAN_DENSE, false>), tgrid, dim3(256), 0, s, ix, a);
       if (after_dist) {
         const hipError_t e = hipEventRecord(after_dist, s);
         if (e != hipSuccess) return e;
@@ -3097,9 +3154,15 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
       return hipGetLastError();
     }
     if (!a.bound || !a.ncand || !a.cand) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_scan_dist<SCAN_MIN>, tgrid, dim3(256), 0, s, ix, a);
-    hipLaunchKernelGGL(k_scan_bound, grid, blk, 0, s, ix, a);
-    hipLaunchKernelGGL(k_scan_dist<SCAN_FILTER>, tgrid, dim3(256), 0, s, ix, a);
+    if (pre) {
+      hipLaunchKernelGGL((k_scan_dist<SCAN_MIN, true>), tgrid, dim3(256), 0, s, ix, a);
+      hipLaunchKernelGGL(k_scan_bound, grid, blk, 0, s, ix, a);
+      hipLaunchKernelGGL((k_scan_dist<SCAN_FILTER, true>), tgrid, dim3(256), 0, s, ix, a);
+    } else {
+      hipLaunchKernelGGL((k_scan_dist<SCAN_MIN, false>), tgrid, dim3(256), 0, s, ix, a);
+      hipLaunchKernelGGL(k_scan_bound, grid, blk, 0, s, ix, a);
+      hipLaunchKernelGGL((k_scan_dist<SCAN_FILTER, false>), tgrid, dim3(256), 0, s, ix, a);
+    }
     if (after_dist) {
       const hipError_t e = hipEventRecord(after_dist, s);
       if (e != hipSuccess) return e;
