@@ -477,8 +477,8 @@ def run_serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              f"(multi-GPU sharding is a design note, not an implemented path).", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported: the index is "
+              f"single-GPU (how it would shard is documented, not implemented).", file=sys.stderr)
         sys.exit(2)
     if args.workload == "precision_f32":
         print(json.dumps(run_precision(args)), flush=True)
