@@ -77,6 +77,15 @@ def test_parity_small_no_refine_two_L():
     run_parity(small_workload(seed=2), refine=False, search_L=(16, 32, 100, 200))
 
 
+def test_parity_short_build_list_filtered_bootstrap():
+    # L_build = 32: the bootstrap's candidate lists (4 L_build = 128) take the
+    # filtered start-set path with the batch itself as the start set, where each
+    # row skips itself
+    wl = dg.Workload("small_lb32", dg.Mixture(128, 8, 18.0, dg.METRIC_L2_U8), 1500, 32, 32, 6, 5,
+                     1, 0.05, 200, 10, (32,), 13, 700, 700)
+    run_parity(wl, search_L=(16, 32))
+
+
 def test_parity_many_entries_filtered_start_set():
     # 1,000 entries: four spans of start rows, so the bounded keys of a query
     # come from several spans and are merged before the sort
