@@ -818,6 +818,13 @@ __global__ void __launch_bounds__(256) k_scan_final(Index ix, ScanArgs a, uint32
   uint64_t* sel = reinterpret_cast<uint64_t*>(smem + (size_t)(threadIdx.x >> 6) * 8 * sel_cap);
   const int l = lane_id();
   const uint32_t n_span = (a.ns + SCAN_SPAN - 1) / SCAN_SPAN, slots = scan_slots(n_span);  // one span per lane
+  // the first keys of each span (at least 16 slots each) are read together with
+  // the counts; slots past a count hold stale keys that are never used
+  constexpr uint32_t EARLY = 8;
+  const uint64_t* src = a.cand + (size_t)qi * SCAN_KEYS_Q + (uint32_t)l * slots;
+  uint64_t early[EARLY];
+#pragma unroll
+  for (uint32_t j = 0; j < EARLY; ++j) early[j] = (uint32_t)l < n_span ? src[j] : KEY_NONE;
   const uint32_t c = (uint32_t)l < n_span ? a.ncand[(size_t)qi * n_span + (uint32_t)l] : 0u;
   uint32_t off = c;  // inclusive prefix over the spans
   for (int o = 1; o < 64; o <<= 1) {
@@ -831,8 +838,10 @@ __global__ void __launch_bounds__(256) k_scan_final(Index ix, ScanArgs a, uint32
     return;
   }
   off -= c;
-  const uint64_t* src = a.cand + (size_t)qi * SCAN_KEYS_Q + (uint32_t)l * slots;
-  for (uint32_t j = 0; j < c; ++j) sel[off + j] = src[j];
+#pragma unroll
+  for (uint32_t j = 0; j < EARLY; ++j)
+    if (j < c) sel[off + j] = early[j];
+  for (uint32_t j = EARLY; j < c; ++j) sel[off + j] = src[j];
   const int np = next_pow2_ge64((int)n);
   for (int i = (int)n + l; i < np; i += 64) sel[i] = KEY_NONE;
   wave_sync();
