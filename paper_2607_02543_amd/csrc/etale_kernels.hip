@@ -1267,38 +1267,64 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     TP::dist_batch(ix, qv, ci, cnt, ck, cr);
     wave_sync();
     ndist += (uint32_t)cnt;
-    // merge: the candidates below the current worst entry, each at its rank
-    uint64_t worst = n == L ? bcast_lane64(lk, L - 1) : KEY_NONE;
+    // merge: the list becomes the L smallest of itself and the candidates
+    // below its current worst entry (no other candidate can enter). Every
+    // entry's place is its rank in that union: one broadcast per accepted
+    // candidate counts, for each list entry and each candidate, the accepted
+    // candidates below it, and for each candidate the list entries below it.
+    // The wave then scatters the union's first L entries to the candidate
+    // scratch (free after the distances) and reads them back in order.
+    const uint64_t worst = n == L ? bcast_lane64(lk, L - 1) : KEY_NONE;
+    uint64_t cand[H], accm[H];
+    int na = 0;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-      uint64_t cand = KEY_NONE, cref = 0;
-      if (64 * h + l < cnt) {
-        cand = ck[64 * h + l];
-        cref = cr[64 * h + l];
+      cand[h] = 64 * h + l < cnt ? ck[64 * h + l] : KEY_NONE;
+      accm[h] = ballot(cand[h] < worst);
+      na += __popcll(accm[h]);
+    }
+    if (!na) continue;
+    uint32_t below_l = 0, below_c[H], list_c[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) below_c[h] = list_c[h] = 0;
+#pragma unroll
+    for (int hh = 0; hh < H; ++hh)
+      for (uint64_t m = accm[hh]; m; m &= m - 1) {
+        const int c = (int)__builtin_ctzll(m);
+        const uint64_t kc = bcast_lane64(cand[hh], c);
+        below_l += l < n && kc < lk ? 1u : 0u;
+#pragma unroll
+        for (int h = 0; h < H; ++h) below_c[h] += kc < cand[h] ? 1u : 0u;
+        const uint32_t nl = (uint32_t)__popcll(ballot(l < n && lk < kc));
+        if (l == c) list_c[hh] = nl;
       }
-      for (uint64_t acc = ballot(64 * h + l < cnt && cand < worst); acc; acc &= acc - 1) {
-        const int c = (int)__builtin_ctzll(acc);
-        const uint64_t kc = bcast_lane64(cand, c);
-        if (kc >= worst) continue;  // the list filled up or improved meanwhile
-        const uint64_t rf = bcast_lane64(cref, c);
-        const int pos = __popcll(ballot(lk < kc));
-        // shift lanes above pos up by one, then place the candidate at pos
-        const uint64_t sk = lane_shr1_64(lk), sr = lane_shr1_64(lr);
-        const uint32_t sx = lane_shr1(lx);
-        if (l > pos) {
-          lk = sk;
-          lr = sr;
-          lx = sx;
-        } else if (l == pos) {
-          lk = kc;
-          lr = rf;
-          lx = 0;
-        }
-        if (l >= L) lk = KEY_NONE;
-        n = min(n + 1, L);
-        worst = n == L ? bcast_lane64(lk, L - 1) : KEY_NONE;
+    uint64_t cref[H];  // read before the scatter overwrites the scratch
+#pragma unroll
+    for (int h = 0; h < H; ++h) cref[h] = ((accm[h] >> l) & 1ull) ? cr[64 * h + l] : 0ull;
+    wave_sync();
+    if (l < n && (uint32_t)l + below_l < (uint32_t)L) {
+      ck[l + below_l] = lk;
+      cr[l + below_l] = lr;
+      ci[l + below_l] = lx;
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const uint32_t p = list_c[h] + below_c[h];
+      if (((accm[h] >> l) & 1ull) && p < (uint32_t)L) {
+        ck[p] = cand[h];
+        cr[p] = cref[h];
+        ci[p] = 0;
       }
     }
+    wave_sync();
+    n = min(n + na, L);
+    lk = KEY_NONE;
+    if (l < n) {
+      lk = ck[l];
+      lr = cr[l];
+      lx = ci[l];
+    }
+    wave_sync();
   }
   // the list to LDS for the shared result stage (the candidate scratch is free)
   ck[l] = lk;
