@@ -63,6 +63,8 @@ def _load():
         lib.oracle_get_entries.argtypes = [vp, vp]
         lib.oracle_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_get_codes.argtypes = [vp, u32, vp, vp, vp]
+        lib.oracle_near_ties.restype = i64
+        lib.oracle_near_ties.argtypes = [vp, vp, vp, u64, i32]
         lib.oracle_bf16_encode.argtypes = [vp, u64, vp]
         lib.oracle_fp8_encode.argtypes = [vp, u64, vp]
         lib.oracle_fp8_decode.argtypes = [vp, u64, vp]
@@ -228,6 +230,19 @@ class Oracle:
         self.lib.oracle_export(self.h, _p(nbr), _p(rho), _p(deg), _p(de), _p(hs), _p(m))
         return dict(meta=meta, nbr=nbr[:n], rho=rho[:n], deg=deg[:n], deleted=de[:n].astype(bool),
                     has_slab=hs[:n].astype(bool))
+
+    def near_ties(self, clear: bool = True) -> dict:
+        """{node: smallest relative margin} of the float comparisons within the
+        tie margin (1e-5 relative) that decided a node's list since the last
+        clear (see the C source)."""
+        n = int(self.lib.oracle_near_ties(self.h, None, None, 0, 0))
+        own = np.zeros(max(n, 1), np.uint32)
+        mar = np.zeros(max(n, 1), np.float64)
+        self.lib.oracle_near_ties(self.h, _p(own), _p(mar), n, int(clear))
+        out = {}
+        for u, m in zip(own[:n].tolist(), mar[:n].tolist()):
+            out[u] = min(m, out.get(u, m))
+        return out
 
     def codes(self, u: int):
         bf = np.zeros(self.dim, np.uint16)

@@ -149,6 +149,43 @@ struct Oracle {
   std::vector<uint32_t> stamp;
   uint32_t cur = 0;
 
+  // ---- near-tie log (float metric) ------------------------------------------
+  // The GPU decides float comparisons in FP32, this model in FP64. Where two
+  // compared quantities lie within TIE_RTOL of each other (relative to the
+  // larger of them, and at least to `scale`, the magnitude of the terms the
+  // dot products sum), the two can decide the comparison differently. Each
+  // such comparison is logged with the node whose list it decides: the node
+  // being inserted (its search and its forward prune), or the owner of a
+  // repair, reverse or refine prune. Searches for queries log nothing (their
+  // results are checked against exact distances instead).
+  static constexpr double TIE_RTOL = 1e-5;
+  uint32_t tie_owner = NONE;
+  struct Tie {
+    uint32_t owner;
+    double margin;  // the smallest relative margin logged for it in a row
+  };
+  mutable std::vector<Tie> ties;  // logging does not change the index
+  // relative margin of a comparison between a and b (terms of magnitude scale)
+  double margin(double a, double b, double scale = 1.0) const {
+    const double m = std::max(std::max(std::fabs(a), std::fabs(b)), scale);
+    return std::fabs(a - b) / m;
+  }
+  void tie_log(double a, double b, double scale = 1.0) const {
+    if (metric != M_IP_F32 || tie_owner == NONE) return;
+    const double r = margin(a, b, scale);
+    if (r > TIE_RTOL) return;
+    if (!ties.empty() && ties.back().owner == tie_owner)
+      ties.back().margin = std::min(ties.back().margin, r);
+    else
+      ties.push_back({tie_owner, r});
+  }
+  // adjacent pairs among the first `upto` (+1) entries of a sorted list
+  template <class V, class F>
+  void tie_scan(const V& v, size_t upto, F dist) const {
+    if (metric != M_IP_F32 || tie_owner == NONE) return;
+    for (size_t i = 1; i < v.size() && i <= upto; ++i) tie_log(dist(v[i - 1]), dist(v[i]));
+  }
+
   uint32_t visit_cap(uint32_t L) const { return visit_mult * L; }
 
   // exact distance between a query vector and a stored id (fp64 for floats)
@@ -229,6 +266,7 @@ struct Oracle {
     std::vector<Entry> u;
     for (const Entry& e : c)
       if (u.empty() || u.back().id != e.id) u.push_back(e);
+    tie_scan(u, prune_cap, [](const Entry& e) { return e.d; });  // order and the cap
     if (u.size() > prune_cap) u.resize(prune_cap);
     const double a2 = (double)alpha_num * alpha_num, b2 = (double)alpha_den * alpha_den;
     std::vector<char> alive(u.size(), 1);
@@ -236,8 +274,12 @@ struct Oracle {
     for (size_t i = 0; i < u.size() && out.size() < R; ++i) {
       if (!alive[i]) continue;
       out.push_back(u[i]);
-      for (size_t j = i + 1; j < u.size(); ++j)
-        if (alive[j] && a2 * D(u[i].id, u[j].id) <= b2 * u[j].d) alive[j] = 0;
+      for (size_t j = i + 1; j < u.size(); ++j) {
+        if (!alive[j]) continue;
+        const double lhs = a2 * D(u[i].id, u[j].id), rhs = b2 * u[j].d;
+        tie_log(lhs, rhs, b2);
+        if (lhs <= rhs) alive[j] = 0;
+      }
     }
     return out;
   }
@@ -264,6 +306,7 @@ struct Oracle {
     }
     s.distances = entries.size();
     std::sort(s.list.begin(), s.list.end(), [](const Slot& a, const Slot& b) { return key_less(a.e, b.e); });
+    tie_scan(s.list, L, [](const Slot& x) { return x.e.d; });
     if (s.list.size() > L) s.list.resize(L);
     while (s.visited.size() < vcap) {
       std::vector<uint32_t> pick;  // up to W best unexpanded
@@ -284,9 +327,14 @@ struct Oracle {
           stamp[n] = cur;
           Entry c{dtrav(q, n), n};
           ++s.distances;
-          if (s.list.size() == L && !key_less(c, s.list.back().e)) continue;
+          if (s.list.size() == L && !key_less(c, s.list.back().e)) {
+            tie_log(c.d, s.list.back().e.d);  // rejected at the worst entry
+            continue;
+          }
           auto it = std::upper_bound(s.list.begin(), s.list.end(), c,
                                      [](const Entry& a, const Slot& b) { return key_less(a, b.e); });
+          if (it != s.list.begin()) tie_log(c.d, (it - 1)->e.d);  // its rank
+          if (it != s.list.end()) tie_log(c.d, it->e.d);
           s.list.insert(it, Slot{c, false});
           if (s.list.size() > L) s.list.pop_back();
         }
@@ -368,6 +416,7 @@ struct Oracle {
     std::vector<std::vector<uint32_t>> cand(n);
     for (uint64_t i = 0; i < n; ++i) {
       uint32_t v = first + (uint32_t)i;
+      tie_owner = v;
       if (!bootstrap) {
         Search s = beam_search(vec(v), L_build, vcap);
         for (const Entry& e : s.visited) cand[i].push_back(e.id);
@@ -376,10 +425,12 @@ struct Oracle {
         for (uint64_t j = 0; j < n; ++j)
           if (j != i) all.push_back({D(v, first + (uint32_t)j), first + (uint32_t)j});
         std::sort(all.begin(), all.end(), key_less);
+        tie_scan(all, vcap, [](const Entry& e) { return e.d; });
         if (all.size() > vcap) all.resize(vcap);
         for (const Entry& e : all) cand[i].push_back(e.id);
       }
     }
+    tie_owner = NONE;
     return cand;
   }
   // P2: forward neighbors, own slab (uncontended)
@@ -387,10 +438,12 @@ struct Oracle {
     std::vector<std::vector<Entry>> F(n);
     for (uint64_t i = 0; i < n; ++i) {
       uint32_t v = first + (uint32_t)i;
+      tie_owner = v;
       F[i] = robust_prune(v, cand[i]);
       publish(v, F[i]);
       ++pub_forward;
     }
+    tie_owner = NONE;
     return F;
   }
   // P3: repair every live out-neighbor a of each deleted u, pairs sorted by
@@ -403,6 +456,7 @@ struct Oracle {
     std::sort(pairs.begin(), pairs.end());
     for (size_t i = 0; i < pairs.size();) {
       uint32_t a = pairs[i].first;
+      tie_owner = a;
       std::vector<Entry> N = adj[a];
       size_t j = i;
       for (; j < pairs.size() && pairs[j].first == a; ++j) {
@@ -421,6 +475,7 @@ struct Oracle {
       ++pub_repair;
       i = j;
     }
+    tie_owner = NONE;
   }
   // P4: reverse edges, sorted by (target, source), one publish per target
   void reverse(uint32_t first, uint64_t n, const std::vector<std::vector<Entry>>& F) {
@@ -432,6 +487,7 @@ struct Oracle {
     for (size_t a = 0; a < pairs.size();) {
       size_t b = a;
       uint32_t w = pairs[a].first;
+      tie_owner = w;
       std::vector<Entry> N = adj[w];
       for (; b < pairs.size() && pairs[b].first == w; ++b) {
         uint32_t v = pairs[b].second;
@@ -452,6 +508,7 @@ struct Oracle {
       ++pub_reverse;
       a = b;
     }
+    tie_owner = NONE;
   }
   // P5: refine -- offer each new node the same-batch nodes two hops away.
   // Every new node reads the lists as they stand when the pass starts; the
@@ -475,7 +532,9 @@ struct Oracle {
         extra = !in;
       }
       if (!extra) continue;
+      tie_owner = v;
       out[i] = robust_prune(v, c);
+      tie_owner = NONE;
       bool same = out[i].size() == adj[v].size();
       for (size_t t = 0; same && t < out[i].size(); ++t) same = out[i][t].id == adj[v][t].id;
       changed[i] = !same;
@@ -586,7 +645,7 @@ struct Oracle {
     if (exp_out) *exp_out = (uint32_t)s.visited.size();
     if (dist_out) *dist_out = (uint32_t)s.distances;
     std::vector<Entry> res;
-    const bool rr = metric == M_IP_F32 && trav != T_NATIVE;
+    const bool rr = metric == M_IP_F32 && trav != T_NATIVE && rerank_mult > 0;  // 0: no re-rank
     const size_t want = rr ? (size_t)rerank_mult * k : k;
     for (const Slot& sl : s.list)
       if (res.size() < want && !del[sl.e.id]) res.push_back(sl.e);
@@ -810,6 +869,21 @@ int oracle_export(void* h, uint32_t* nbr, double* rho, uint8_t* deg, uint8_t* de
     std::memcpy(meta, m, sizeof(m));
   }
   return OK;
+}
+
+// Near-tie log (float metric): the nodes whose lists a comparison within the
+// tie margin decided, since the last clear, in logging order (consecutive
+// entries of one node folded, keeping the smallest relative margin). Writes up
+// to cap (node, margin) pairs; returns the count; clear != 0 empties the log.
+int64_t oracle_near_ties(void* h, uint32_t* owners, double* margins, uint64_t cap, int clear) {
+  Oracle* o = (Oracle*)h;
+  const uint64_t n = o->ties.size();
+  for (uint64_t i = 0; i < n && i < cap; ++i) {
+    owners[i] = o->ties[i].owner;
+    margins[i] = o->ties[i].margin;
+  }
+  if (clear) o->ties.clear();
+  return (int64_t)n;
 }
 
 // Stored low-precision copies of one vector (float metric only).

@@ -108,48 +108,106 @@ def test_search_parity_on_identical_graph(trav):
     g.close()
 
 
-@pytest.mark.parametrize("trav", [0, 2])
+def _hops(sources, nbr_a, deg_a, nbr_b, deg_b, depth):
+    """Nodes within `depth` hops of `sources` in the union of two graphs, edges
+    taken in both directions."""
+    n = nbr_a.shape[0]
+    adj = [set() for _ in range(n)]
+    for nbr, deg in ((nbr_a, deg_a), (nbr_b, deg_b)):
+        for u in range(n):
+            for v in nbr[u, :deg[u]].tolist():
+                adj[u].add(v)
+                adj[v].add(u)
+    seen = set(int(s) for s in sources)
+    frontier = set(seen)
+    for _ in range(depth):
+        frontier = {v for u in frontier for v in adj[u]} - seen
+        seen |= frontier
+    return seen
+
+
+@pytest.mark.parametrize("trav", [0, 1, 2])
 def test_float_maintenance_matches_oracle(trav):
+    """End-to-end protocol on the float path. After every call the maintained
+    lists are compared as neighbor sets. Until they first differ, they must be
+    identical, with the same flags, pool counts and publications; at the call
+    where they first differ, the oracle must have logged near-ties (float
+    comparisons decided by less than 1e-5 relative) in that call, and every
+    differing list must lie within three hops of a logged node in the union of
+    the two graphs (a tie in node v's search or prune changes v's list, then
+    the reverse offers v makes, then the same-batch refine of nodes two hops
+    from v). From then on the two runs are different graphs, and only flags,
+    stored distances against FP64 and the degree bound are compared."""
     torch = _torch()
     wl = float_workload(n_base=1500, batch=500, rounds=2, seed=11)
     p = index_params(wl, n_entry=32)
     o = make_oracle_f(p, traversal=trav)
     g = make_gpu_f(p, traversal=trav)
     st = dg.Stream(wl)
-    for b in wl.build_batches():
-        xb = st.base(b)
+    xs = np.zeros((p["id_capacity"], wl.dim), np.float32)
+    state = {"diverged": None, "n": 0}
+
+    def compare(where):
+        tie_margin = o.near_ties(clear=True)
+        ties = set(tie_margin)
+        eo, eg = o.export(), g.export()
+        n = eo["meta"]["next_id"]
+        assert np.array_equal(eo["deleted"], eg["deleted"]), where
+        differ = [u for u in range(n) if set(eo["nbr"][u, :eo["deg"][u]].tolist()) !=
+                  set(eg["nbr"][u, :eg["deg"][u]].tolist())]
+        # the GPU's lists are valid whatever happened before: degree bound, no
+        # self loop or repeat, stored distances within 1e-5 of FP64
+        for u in range(n):
+            d = int(eg["deg"][u])
+            ids = eg["nbr"][u, :d].astype(np.int64)
+            assert d <= wl.R and u not in ids and len(set(ids.tolist())) == d, f"{where}: list of {u}"
+            if d:
+                ex = 1.0 - xs[ids].astype(np.float64) @ xs[u].astype(np.float64)
+                rel = np.abs(eg["rho"][u, :d] - ex) / np.maximum(np.abs(ex), 1e-3)
+                assert rel.max() <= RTOL, f"{where}: stored distance of {u}"
+        if state["diverged"] is None:
+            if differ:
+                assert ties, f"{where}: {len(differ)} lists differ and the oracle logged no near-tie"
+                near = _hops(ties, eo["nbr"], eo["deg"], eg["nbr"], eg["deg"], 3)
+                far = [u for u in differ if u not in near]
+                assert not far, f"{where}: lists of {far[:10]} differ, none within 3 hops of a near-tie {sorted(ties)[:10]}"
+                state["diverged"] = where
+                tight = {u for u, m in tie_margin.items() if m < 1e-6}
+                near_t = _hops(tight, eo["nbr"], eo["deg"], eg["nbr"], eg["deg"], 3) if tight else set()
+                print(f"[float maint] trav={trav} {where}: first divergence, {len(differ)} lists; "
+                      f"{sum(u in ties for u in differ)} of them own a near-tie, "
+                      f"{sum(u in near_t for u in differ)} lie within 3 hops of a tie below 1e-6 "
+                      f"({len(tight)} such nodes)", flush=True)
+            else:
+                sg, mo = g.stats(), eo["meta"]
+                assert sg["resident_slabs"] == mo["resident"] and sg["free_slabs"] == mo["free"], where
+                for k in ("pub_forward", "pub_repair", "pub_reverse", "pub_refine", "pub_compact", "freed"):
+                    assert mo[k] == sg[k], f"{where}: {k}"
+        print(f"[float maint] trav={trav} {where}: {len(differ)} lists differ, {len(ties)} nodes with near-ties, "
+              f"first divergence: {state['diverged']}", flush=True)
+
+    def insert(xb):
+        n0 = state["n"]
+        xs[n0:n0 + xb.shape[0]] = xb
+        state["n"] += xb.shape[0]
         o.insert(xb)
         g.insert(torch.from_numpy(xb).cuda())
 
-    def compare(where):
-        eo, eg = o.export(), g.export()
-        same = np.array([set(eo["nbr"][u, :eo["deg"][u]].tolist()) == set(eg["nbr"][u, :eg["deg"][u]].tolist())
-                         for u in range(eo["meta"]["next_id"])])
-        frac = same.mean()
-        assert frac >= 0.98, f"{where}: only {frac:.4f} of lists agree"
-        assert np.array_equal(eo["deleted"], eg["deleted"]), where
-        # stored distances of agreeing lists, per neighbor id
-        for u in np.nonzero(same)[0][:300]:
-            d = int(eo["deg"][u])
-            mo = dict(zip(eo["nbr"][u, :d].tolist(), eo["rho"][u, :d].tolist()))
-            for v, r in zip(eg["nbr"][u, :d].tolist(), eg["rho"][u, :d].tolist()):
-                assert abs(r - mo[v]) <= RTOL * max(abs(mo[v]), 1e-3), where
-        return frac
-
-    compare("build")
+    for bi, b in enumerate(wl.build_batches()):
+        insert(st.base(b))
+        compare(f"build batch {bi}")
     for r in range(wl.churn_rounds):
         live = np.nonzero(~o.export()["deleted"])[0].astype(np.uint32)
         dl = st.deletes(live, wl.churn_count())
         o.delete(dl)
         g.delete(torch.from_numpy(dl.astype(np.int32)).cuda())
-        xb = st.inserts(wl.churn_count())
-        o.insert(xb)
-        g.insert(torch.from_numpy(xb).cuda())
+        compare(f"round {r} delete")
+        insert(st.inserts(wl.churn_count()))
+        compare(f"round {r} insert")
         o.reclaim()
         g.reclaim()
-        frac = compare(f"round {r}")
-        sg = g.stats()
-        mo = o.meta()
-        assert sg["resident_slabs"] == mo["resident"] and sg["free_slabs"] == mo["free"]
-        print(f"[float maint] trav={trav} round {r}: {frac:.4f} of lists identical as sets", flush=True)
+        compare(f"round {r} reclaim")
+        if state["diverged"] is None:
+            sg, mo = g.stats(), o.meta()
+            assert sg["resident_slabs"] == mo["resident"] and sg["free_slabs"] == mo["free"]
     g.close()
