@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--vt-slots", type=int, default=1024)
     ap.add_argument("--waves-per-block", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=5000)
+    ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--workload", default="scale_u8_1m", choices=["scale_u8_1m", "precision_f32", "batching_f32",
                                                                    "serving_u8"])
@@ -92,16 +92,32 @@ def recall(ids, gt, k=10):
     return hits / (k * ids.shape[0])
 
 
-def cpu_baseline(wl, L, n_sample, n_q=300):
-    """The oracle, single-threaded, on a bounded sample of the same workload."""
+def host_cpu():
+    """Model name and logical CPU count of this host."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def cpu_baseline(wl, L, n_sample, n_entry, W, n_q=1000):
+    """The oracle, single-threaded, on a bounded sample of the same workload
+    with the benchmark's own search settings (entry set, W, L): the entry set
+    is scored for every query as on the GPU, so the per-query cost is that of
+    the full-size workload up to the (logarithmic) depth of the walk."""
     import oracle
     from paper_2607_02543_amd import datagen as dg
 
     st = dg.Stream(wl)
-    cap = n_sample + 2 * max(1, n_sample // 100) + 16
-    n_entry = max(64, min(4096, n_sample // 16))
+    churn = max(1, n_sample // 100)
+    cap = n_sample + churn + 16
     o = oracle.Oracle(oracle.METRIC_L2_U8, wl.dim, wl.R, wl.L_build, cap, 3 * cap + (wl.R + 2) * 10000,
-                      alpha=(wl.alpha_num, wl.alpha_den), n_entry=n_entry)
+                      alpha=(wl.alpha_num, wl.alpha_den), n_entry=n_entry, W=W)
     b, done = 1000, 0
     t0 = time.perf_counter()
     while done < n_sample:
@@ -111,7 +127,6 @@ def cpu_baseline(wl, L, n_sample, n_q=300):
         b = min(10000, max(b, done))
     t_build = time.perf_counter() - t0
     live = np.arange(n_sample, dtype=np.uint32)
-    churn = max(1, n_sample // 100)
     t0 = time.perf_counter()
     o.delete(st.deletes(live, churn))
     o.insert(st.inserts(churn))
@@ -121,11 +136,14 @@ def cpu_baseline(wl, L, n_sample, n_q=300):
     t0 = time.perf_counter()
     o.search(q, 10, L)
     t_q = time.perf_counter() - t0
-    return {"value": n_q / t_q, "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle (g++ -O2, single thread) on the first {n_sample} vectors of the same mixture "
-                       f"(entry set {n_entry}); {n_q} queries at L={L}; one 1% churn round of that sample took "
-                       f"{t_round * 1e3:.1f} ms; build {t_build:.1f} s"),
-            "ms_per_churn_round_sample": t_round * 1e3}
+    model, ncpu = host_cpu()
+    return {"value": round(n_q / t_q, 1), "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle (g++ -O2, one thread) on the first {n_sample} vectors of the same mixture with the "
+                       f"benchmark's search settings (entry set {min(n_entry, n_sample)}, W={W}); {n_q} queries "
+                       f"at L={L}; one 1% churn round of that sample ({churn} + {churn}) took {t_round * 1e3:.1f} ms; "
+                       f"build {t_build:.1f} s"),
+            "host_cpu": model, "host_logical_cpus": ncpu,
+            "ms_per_churn_round_sample": round(t_round * 1e3, 1)}
 
 
 def run_precision(args):
@@ -646,7 +664,7 @@ def main():
                      "launch_ms": best["stage_ms"]["search_ms"]},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, L_star, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(wl, L_star, args.cpu_sample, args.n_entry, args.W)
     ix.close()
     print(json.dumps(out), flush=True)
 

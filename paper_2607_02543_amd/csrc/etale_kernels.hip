@@ -1377,16 +1377,20 @@ __device__ inline void search_kernel(const Index& ix, SearchArgs& a, char* smem)
 
 // list in registers; uint8 rows hold their registers to 7 waves per SIMD (the
 // LDS of 7 four-wave blocks fits a CU at the default visited-table size),
-// float rows keep theirs (they would spill)
-template <class TP, unsigned WPE, int H>
+// float rows keep theirs (they would spill). Q: query searches (results out)
+// or insert searches (expanded sets out), compiled apart so that each keeps
+// only its own output code and each has a kernel name of its own.
+template <class TP, unsigned WPE, int H, bool Q>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) k_search_rl(Index ix, SearchArgs a) {
   extern __shared__ __align__(16) char smem[];
+  a.mode = Q ? MODE_QUERY : MODE_INSERT;
   search_kernel<TP, true, H>(ix, a, smem);
 }
 
-template <class TP>
+template <class TP, bool Q>
 __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
   extern __shared__ __align__(16) char smem[];
+  a.mode = Q ? MODE_QUERY : MODE_INSERT;
   search_kernel<TP, false, 1>(ix, a, smem);
 }
 
@@ -3225,17 +3229,24 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
 }
 
 // the list lives in registers for L <= 64
-#define LS(TP)                                                                                   \
-  do {                                                                                           \
-    if (a.L <= 64)                                                                               \
-      if (a.W > 2)                                                                                \
-        hipLaunchKernelGGL((k_search_rl<TP, TP::FLOAT ? 1u : 6u, 2>), dim3(grid), dim3(64 * waves_per_block), lds, s, \
-                           ix, a);                                                                \
-      else                                                                                        \
-        hipLaunchKernelGGL((k_search_rl<TP, TP::FLOAT ? 1u : 7u, 1>), dim3(grid), dim3(64 * waves_per_block), lds, s, \
-                           ix, a);                                                                \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_search<TP>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a); \
+#define LSQ(TP, Q)                                                                                              \
+  do {                                                                                                          \
+    if (a.L <= 64)                                                                                              \
+      if (a.W > 2)                                                                                              \
+        hipLaunchKernelGGL((k_search_rl<TP, TP::FLOAT ? 1u : 6u, 2, Q>), dim3(grid), dim3(64 * waves_per_block), lds, \
+                           s, ix, a);                                                                           \
+      else                                                                                                      \
+        hipLaunchKernelGGL((k_search_rl<TP, TP::FLOAT ? 1u : 7u, 1, Q>), dim3(grid), dim3(64 * waves_per_block), lds, \
+                           s, ix, a);                                                                           \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_search<TP, Q>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a);             \
+  } while (0)
+#define LS(TP)                           \
+  do {                                   \
+    if (a.mode == MODE_QUERY)            \
+      LSQ(TP, true);                     \
+    else                                 \
+      LSQ(TP, false);                    \
   } while (0)
 
 hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_per_block, hipStream_t s) {
@@ -3281,6 +3292,7 @@ hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_pe
   return hipGetLastError();
 }
 #undef LS
+#undef LSQ
 
 uint32_t chain_lds_per_wave(uint32_t R, uint32_t vstride) { return chain_lds_bytes(R, vstride); }
 uint32_t pool_lds_per_wave(uint32_t vstride) { return pool_lds_bytes(vstride); }
