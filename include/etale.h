@@ -162,6 +162,23 @@ etale_status etale_delete_batch(etale_t ix, const uint32_t* ids_dev, uint64_t n,
 etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
                                 uint32_t* ids_out_dev, void* dists_out_dev, uint32_t* counts_out_dev);
 
+/* etale_search_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops that must not call hipMalloc,
+ * harnesses that forbid it): the same search, same arguments, same results
+ * bit for bit, but the start-set scan's scratch (initial lists, distance
+ * rows, group minima, bounds and bounded keys) lives in one static device
+ * array of 64 MiB per GPU, held from library load until the process ends,
+ * instead of the buffers etale_create allocates. The call makes no
+ * allocation of any kind; queries run in chunks of as many as fit that array
+ * (about 1,500 at n_entry = 8,192). Every call on one GPU, from any index,
+ * shares the array and leaves its contents behind (nothing in it needs to
+ * start cleared: each chunk writes what it later reads), so calls that
+ * overlap on one GPU (other streams, other threads) race: serialize them.
+ * Errors: as etale_search_batch, plus EINVAL when the scratch of a single
+ * query (n_entry and L) exceeds the array. */
+etale_status etale_search_batch_noalloc(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
+                                        uint32_t* ids_out_dev, void* dists_out_dev, uint32_t* counts_out_dev);
+
 /* Compaction, then release of every tombstone's slab (Algorithm 4). The
  * number of dirty nodes must be covered by free slabs, else ETALE_EPOOL with
  * nothing changed. A no-op in tombstone-only mode. */

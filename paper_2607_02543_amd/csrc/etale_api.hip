@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,6 +74,7 @@ struct etale_index {
   bool poisoned = false;
   std::string err;
   std::vector<void*> allocs;
+  unsigned char* noalloc = nullptr;  // device address of the static search scratch on the index's device
 };
 
 namespace {
@@ -92,6 +94,36 @@ etale_status fail(etale_index* ix, etale_status code, const std::string& what) {
   } while (0)
 
 bool pow2(uint64_t v) { return v && !(v & (v - 1)); }
+
+// ---- scratch of the allocation-free search (etale_search_batch_noalloc) -------
+// A file-scope device array: every device the library runs on holds its own
+// copy until the process ends. Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): the address
+// is resolved once per device with hipGetSymbolAddress and kept.
+constexpr uint64_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_addr;  // device ordinal -> address of `scratch` there
+
+// address of `scratch` on the current device
+hipError_t noalloc_scratch_address(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = g_scratch_addr.emplace(dev, static_cast<unsigned char*>(p)).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
+uint64_t round256(uint64_t b) { return (b + 255) & ~255ull; }
 
 uint32_t pow2_ge64(uint32_t n) {
   uint32_t p = 64;
@@ -172,6 +204,64 @@ uint32_t scan_chunk_for(const etale_index* ix, uint32_t ns) {
 
 constexpr uint32_t BOOT_MAX = 16384;  // a bootstrap batch is scored as one start set
 
+// Scratch of the start-set scan of one launch chunk: initial lists (out_stride
+// L), the query x start-set distance rows, their group minima, bounds, span
+// counts and bounded keys. `chunk` queries fit.
+struct ScanScratch {
+  uint64_t* keys = nullptr;
+  uint32_t* n = nullptr;
+  uint32_t* dist = nullptr;
+  uint32_t* gmin = nullptr;
+  uint32_t* bound = nullptr;
+  uint32_t* ncand = nullptr;
+  uint64_t* cand = nullptr;
+  uint32_t chunk = 0;
+};
+
+// the library's own scratch, allocated at create
+ScanScratch library_scratch(const etale_index* ix, uint32_t ns) {
+  ScanScratch s;
+  s.keys = ix->scan_keys;
+  s.n = ix->scan_n;
+  s.dist = ix->scan_dist;
+  s.gmin = ix->scan_gmin;
+  s.bound = ix->scan_bound;
+  s.ncand = ix->scan_ncand;
+  s.cand = ix->scan_cand;
+  s.chunk = scan_chunk_for(ix, ns);
+  return s;
+}
+
+// bytes of `scratch` that a chunk of c queries over ns start rows at list
+// length L uses (every region 256-byte aligned)
+uint64_t noalloc_bytes(uint64_t c, uint64_t ns, uint64_t L) {
+  return round256(c * L * 8) + round256(c * 4) + round256(c * ns * 4) + round256(c * (ns / 32 + 8) * 4) +
+         round256(c * 4) + round256(c * 64 * 4) + round256(c * SCAN_KEYS_Q * 8);
+}
+
+// the largest chunk of queries that fits `scratch`, carved at base (0 if none fits)
+ScanScratch noalloc_scratch(unsigned char* base, uint32_t ns, uint32_t L) {
+  ScanScratch s;
+  uint64_t c = std::min<uint64_t>(16384, NOALLOC_SCRATCH_BYTES / std::max<uint64_t>(1, noalloc_bytes(1, ns, L)));
+  while (c > 0 && noalloc_bytes(c, ns, L) > NOALLOC_SCRATCH_BYTES) --c;
+  if (c == 0) return s;
+  unsigned char* p = base;
+  auto take = [&](uint64_t bytes) {
+    unsigned char* r = p;
+    p += round256(bytes);
+    return r;
+  };
+  s.keys = reinterpret_cast<uint64_t*>(take(c * L * 8));
+  s.n = reinterpret_cast<uint32_t*>(take(c * 4));
+  s.dist = reinterpret_cast<uint32_t*>(take(c * ns * 4));
+  s.gmin = reinterpret_cast<uint32_t*>(take(c * (ns / 32 + 8) * 4));
+  s.bound = reinterpret_cast<uint32_t*>(take(c * 4));
+  s.ncand = reinterpret_cast<uint32_t*>(take(c * 64 * 4));
+  s.cand = reinterpret_cast<uint64_t*>(take(c * SCAN_KEYS_Q * 8));
+  s.chunk = (uint32_t)c;
+  return s;
+}
+
 // Start-set scoring, then the beam search, over up to nmax queries in chunks.
 // `base` gives the launch-time count of the queries (and, for insert
 // searches, the counter with the first new id) and the gate bits. With
@@ -180,9 +270,10 @@ constexpr uint32_t BOOT_MAX = 16384;  // a bootstrap batch is scored as one star
 // per possible query.
 etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t nmax, uint32_t k, uint32_t L,
                           uint32_t vcap, uint32_t* out_ids, uint32_t* out_d, uint32_t* counts, Dyn base,
-                          bool persistent = false) {
+                          bool persistent = false, const ScanScratch* given = nullptr) {
   const uint32_t ns = ix->cfg.n_entry;  // upper bound; the kernels read the entry count
-  const uint32_t chunk = scan_chunk_for(ix, ns);
+  const ScanScratch scr = given ? *given : library_scratch(ix, ns);
+  const uint32_t chunk = scr.chunk;
   const size_t qbytes = (size_t)ix->cfg.dim * (ix->cfg.metric == ETALE_METRIC_L2_U8 ? 1 : 4);
   for (uint64_t c = 0; c < nmax; c += chunk) {
     const uint32_t cn = (uint32_t)std::min<uint64_t>(chunk, nmax - c);
@@ -196,18 +287,18 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
     sc.L = L;
     sc.ns = ns;
     sc.ns_ctr = C_N_ENTRIES;
-    sc.dist = ix->scan_dist;
-    sc.gmin = ix->scan_gmin;
-    sc.bound = ix->scan_bound;
-    sc.ncand = ix->scan_ncand;
-    sc.cand = ix->scan_cand;
-    sc.out_keys = ix->scan_keys;
-    sc.out_n = ix->scan_n;
+    sc.dist = scr.dist;
+    sc.gmin = scr.gmin;
+    sc.bound = scr.bound;
+    sc.ncand = scr.ncand;
+    sc.cand = scr.cand;
+    sc.out_keys = scr.keys;
+    sc.out_n = scr.n;
     sc.out_stride = L;
     sc.trav = mode == MODE_QUERY ? ix->qtrav : ix->dev.trav;
     sc.d = d;
     std::array<hipEvent_t, 4> ev{};
-    const bool timed = ix->timing && mode == MODE_QUERY;
+    const bool timed = ix->timing && mode == MODE_QUERY && !given;
     if (timed) {
       for (auto& e : ev) {
         if (ix->ev_pool.empty()) {
@@ -234,8 +325,8 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
     sa.vt_mask = ix->cfg.vt_slots - 1;
     sa.W = ix->cfg.W;
     sa.lds_per_wave = search_lds_per_wave(L, ix->cfg.vt_slots, ix->cfg.W);
-    sa.init_keys = ix->scan_keys;
-    sa.init_n = ix->scan_n;
+    sa.init_keys = scr.keys;
+    sa.init_n = scr.n;
     sa.init_stride = L;
     sa.trav = sc.trav;
     sa.rerank = mode == MODE_QUERY ? ix->qrerank : 0;
@@ -616,6 +707,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   while ((1ull << ix->pair_bits) <= C) ++ix->pair_bits;  // every id < 2^bits - 1: a KEY_NONE target sorts last
   if (launch_init(d, ix->stream) != hipSuccess || hipStreamSynchronize(ix->stream) != hipSuccess)
     return cleanup(ETALE_EDEVICE, "init");
+  if (noalloc_scratch_address(&ix->noalloc) != hipSuccess) return cleanup(ETALE_EDEVICE, "scratch symbol");
   *out = ix;
   return ETALE_OK;
 }
@@ -687,6 +779,24 @@ etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint
     return fail(ix, ETALE_EINVAL, "search: rerank_mult * k must not exceed 64");
   return run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(q_dev), nq, k, L, ix->cfg.visit_mult * L,
                       ids_out_dev, reinterpret_cast<uint32_t*>(dists_out_dev), counts_out_dev, Dyn{});
+}
+
+etale_status etale_search_batch_noalloc(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
+                                        uint32_t* ids_out_dev, void* dists_out_dev, uint32_t* counts_out_dev) {
+  CHECK_HANDLE();
+  if (k < 1 || k > L || L > 256) return fail(ix, ETALE_EINVAL, "search_noalloc: need 1 <= k <= L <= 256");
+  if (nq == 0) return ETALE_OK;
+  if (!q_dev || !ids_out_dev || !dists_out_dev || nq > 0xFFFFFFFFull)
+    return fail(ix, ETALE_EINVAL, "search_noalloc: null buffer");
+  if (ix->cfg.metric == ETALE_METRIC_IP_F32 && ix->qtrav != ETALE_TRAV_NATIVE && (uint64_t)ix->qrerank * k > 64)
+    return fail(ix, ETALE_EINVAL, "search_noalloc: rerank_mult * k must not exceed 64");
+  if (!ix->noalloc) return fail(ix, ETALE_ESTATE, "search_noalloc: static scratch not resolved");
+  const ScanScratch scr = noalloc_scratch(ix->noalloc, ix->cfg.n_entry, L);
+  if (scr.chunk == 0)
+    return fail(ix, ETALE_EINVAL, "search_noalloc: one query's start-set scratch (n_entry, L) exceeds the " +
+                                      std::to_string(NOALLOC_SCRATCH_BYTES >> 20) + " MiB static scratch");
+  return run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(q_dev), nq, k, L, ix->cfg.visit_mult * L,
+                      ids_out_dev, reinterpret_cast<uint32_t*>(dists_out_dev), counts_out_dev, Dyn{}, false, &scr);
 }
 
 etale_status etale_reclaim(etale_t ix) {

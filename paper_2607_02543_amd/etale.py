@@ -111,6 +111,7 @@ def load() -> C.CDLL:
         "etale_insert_batch": ([vp, vp, u64, vp], i32),
         "etale_delete_batch": ([vp, vp, u64, vp], i32),
         "etale_search_batch": ([vp, vp, u64, u32, u32, vp, vp, vp], i32),
+        "etale_search_batch_noalloc": ([vp, vp, u64, u32, u32, vp, vp, vp], i32),
         "etale_reclaim": ([vp], i32),
         "etale_round": ([vp, C.POINTER(RoundDesc)], i32),
         "etale_bruteforce": ([vp, vp, u64, u32, vp, vp], i32),
@@ -225,6 +226,19 @@ class Index:
         cnt = torch.empty((nq, 2), dtype=torch.int32, device=q.device) if counts else None
         self._check(self.lib.etale_search_batch(self.h, _ptr(q), nq, k, L, _ptr(ids), _ptr(d), _ptr(cnt)),
                     "search_batch")
+        return (ids, d, cnt) if counts else (ids, d)
+
+    def search_noalloc(self, q, k: int, L: int, counts: bool = False):
+        """search() through the allocation-free entry point (static scratch);
+        the output tensors are the caller's, allocated here by torch."""
+        torch = self.torch
+        q = self._dev(q, self._vdtype)
+        nq = q.shape[0]
+        ids = torch.empty((nq, k), dtype=torch.int32, device=q.device)
+        d = torch.empty((nq, k), dtype=self._ddtype, device=q.device)
+        cnt = torch.empty((nq, 2), dtype=torch.int32, device=q.device) if counts else None
+        self._check(self.lib.etale_search_batch_noalloc(self.h, _ptr(q), nq, k, L, _ptr(ids), _ptr(d), _ptr(cnt)),
+                    "search_batch_noalloc")
         return (ids, d, cnt) if counts else (ids, d)
 
     def reclaim(self):
