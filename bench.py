@@ -39,13 +39,20 @@ def parse():
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--vt-slots", type=int, default=1024)
     ap.add_argument("--waves-per-block", type=int, default=4)
+    ap.add_argument("--row-lanes", type=int, default=0, help="uint8: lanes per row in distance batches (0: dim/16)")
+    ap.add_argument("--autotune", type=int, default=1, help="pick the result-invariant search knobs before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--workload", default="scale_u8_1m", choices=["scale_u8_1m", "precision_f32", "batching_f32",
-                                                                   "serving_u8"])
+                                                                   "serving_u8", "concurrent_u8", "sweeps_u8"])
     ap.add_argument("--rates", default="20000,50000,100000", help="serving: request rates per second")
-    ap.add_argument("--seconds", type=float, default=5.0, help="serving: trace length per rate")
+    ap.add_argument("--seconds", type=float, default=10.0, help="serving: real-time window per rate")
+    ap.add_argument("--equiv-rounds", type=float, default=100.0, help="serving: equivalent 1%% churn rounds")
+    ap.add_argument("--reclaim-every", type=int, default=100, help="serving: ticks between reclaims")
+    ap.add_argument("--max-tick", type=int, default=8192, help="serving: requests per tick at most")
+    ap.add_argument("--no-tombstone-twin", action="store_true", help="serving: skip the tombstone-only index")
+    ap.add_argument("--batches", type=int, default=2000, help="concurrent: query batches per phase")
     ap.add_argument("--rounds", type=int, default=0, help="batching workload: timed rounds (default 50)")
     ap.add_argument("--prune-cap", type=int, default=0)
     ap.add_argument("--W", type=int, default=2, help="expansions per search iteration (1 or 2)")
@@ -396,10 +403,20 @@ def run_batching(args):
 
 
 def run_serving(args):
-    """Open-loop serving: Poisson request traces (90% search, 5% insert, 5%
-    delete of a live base id) against a 10M x 128-d uint8 index, continuously
-    batched into rounds by the library's serving loop (etale_serve), one trace
-    per rate on the same index."""
+    """Serving a 10M x 128-d uint8 index (4,096-cluster mixture) through the
+    library's continuous-batching loop: each tick's searches (on a snapshot)
+    and its deletes and inserts (one round) overlap on two streams.
+
+    1. Real-time windows: Poisson arrivals at each rate (90% searches k=10
+       L=64, 5% inserts, 5% deletes of live base ids) replayed on the wall
+       clock for --seconds each: p50 / p99 latency from arrival to completion
+       and sustained throughput.
+    2. Churn: --equiv-rounds equivalent 1% rounds (that many times 1% of the
+       index inserted, as many base ids deleted, with the 90% searches around
+       them) pushed through the same loop saturated (arrival times ignored),
+       reclaiming every --reclaim-every ticks; then Recall@10 against brute
+       force over the live set, and the peak resident slabs against the same
+       stream on a tombstone-only index (flags only, no repair or reclaim)."""
     import torch
 
     from paper_2607_02543_amd import datagen as dg
@@ -410,85 +427,412 @@ def run_serving(args):
     rates = [float(v) for v in args.rates.split(",")]
     wl = dg.serving_u8(n_base=n_base)
     st = dg.Stream(wl)
-    traces, t0 = [], 0.0
-    for rate in rates:
-        tr = st.trace(rate, args.seconds, t0)
-        traces.append(tr)
-        t0 = float(tr["t"][-1]) + 1.0 if tr["t"].size else t0 + 1.0
-    n_ins = int(sum((tr["kind"] == 1).sum() for tr in traces))
-    n_del = int(sum((tr["kind"] == 2).sum() for tr in traces))
-    n_srch = int(sum((tr["kind"] == 0).sum() for tr in traces))
-    max_tick = 8192
+    max_tick = args.max_tick
+    traces = [st.trace(rate, args.seconds) for rate in rates]
+    n_sat_ins = int(round(args.equiv_rounds * 0.01 * n_base))
+    sat_kind = st.kinds(int(round(n_sat_ins / 0.05 * 1.02)))
+    rt_ins = int(sum((tr["kind"] == 1).sum() for tr in traces))
+    rt_del = int(sum((tr["kind"] == 2).sum() for tr in traces))
+    n_ins = rt_ins + int((sat_kind == 1).sum())
+    n_del = rt_del + int((sat_kind == 2).sum())
+    if n_del > n_base:  # more deletes than base ids: trim the churn stream
+        cut = np.nonzero(np.cumsum(sat_kind == 2) > n_base - rt_del)[0][0]
+        sat_kind = sat_kind[:cut]
+        n_ins = rt_ins + int((sat_kind == 1).sum())
+        n_del = rt_del + int((sat_kind == 2).sum())
     cap = n_base + n_ins + 16
     max_b = max(wl.build_batch_max, max_tick)
-    slab_cap = 2 * cap + max_b * (wl.R + 2)
-    t_b = time.perf_counter()
-    ix = etale.Index(wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den), n_entry=args.n_entry,
-                     id_capacity=cap, slab_capacity=slab_cap, max_batch=max_b, W=args.W)
-    done = 0
-    for b in wl.build_batches():
-        ix.insert(torch.from_numpy(st.base(b)).to(dev))
-        done += b
-        if done % 1_000_000 < b:
-            log(args, f"built {done}")
-    torch.cuda.synchronize()
-    t_build = time.perf_counter() - t_b
-    # request payloads: a pool of query rows (reused), one fresh row per insert,
-    # and distinct live base ids for the deletes
-    q_pool = min(max(n_srch, 1), 65536)
-    rows = torch.from_numpy(np.concatenate([st.queries(q_pool), st.inserts(n_ins)])).to(dev)
-    del_ids = st.deletes(np.arange(n_base, dtype=np.uint32), n_del)
-    st.rng["deletes"].shuffle(del_ids)
-    qi = ii = di = 0
-    out = {"metric": "serving: request latency p50 / p99 (ms) and sustained requests/s under Poisson load, 1 GPU",
-           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "u8", "data": "synthetic",
-           "config": {"workload": "serving_u8_10m", "n_base": n_base, "dim": wl.dim, "R": wl.R, "k": 10, "L": 64,
-                      "mix": "90% search / 5% insert / 5% delete", "rates": rates, "seconds_per_rate": args.seconds,
-                      "max_tick": max_tick, "hbm_budget_gb": 64, "n_entry": args.n_entry, "W": args.W,
-                      "parallelism": "single GPU"},
-           "build_s": round(t_build, 2), "per_rate": []}
-    for rate, tr in zip(rates, traces):
-        kind = tr["kind"]
+    slab_cap = 2 * n_base + 4 * max_b * (wl.R + 2)
+    q_pool = 65536
+    ins_rows_host = st.inserts(n_ins)
+    rows = torch.from_numpy(np.concatenate([st.queries(q_pool), ins_rows_host])).to(dev)
+    del_ids = st.rng["deletes"].permutation(n_base)[:n_del].astype(np.uint32)  # each base id at most once
+    qs = torch.from_numpy(st.queries(1000)).to(dev)
+    pct = lambda a, q: round(float(np.percentile(a, q)), 3) if a.size else None  # noqa: E731
+
+    def build(tombstone_only):
+        t_b = time.perf_counter()
+        ix = etale.Index(wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den), n_entry=args.n_entry,
+                         id_capacity=cap, slab_capacity=slab_cap, max_batch=max_b, W=args.W,
+                         tombstone_only=tombstone_only)
+        bst = dg.Stream(wl)
+        done = 0
+        for b in wl.build_batches():
+            ix.insert(torch.from_numpy(bst.base(b)).to(dev))
+            done += b
+            if done % 2_000_000 < b:
+                log(args, f"built {done}")
+        torch.cuda.synchronize()
+        return ix, time.perf_counter() - t_b
+
+    def args_of(kind, ii, di):
         arg = np.zeros(kind.size, np.uint32)
-        s_idx = np.nonzero(kind == 0)[0]
-        i_idx = np.nonzero(kind == 1)[0]
-        d_idx = np.nonzero(kind == 2)[0]
+        s_idx, i_idx, d_idx = (np.nonzero(kind == v)[0] for v in (0, 1, 2))
         arg[s_idx] = st.rng["arrivals"].integers(0, q_pool, size=s_idx.size)
         arg[i_idx] = q_pool + ii + np.arange(i_idx.size)
         arg[d_idx] = del_ids[di:di + d_idx.size]
-        ii += i_idx.size
-        di += d_idx.size
-        lat, sst = ix.serve(tr["t"], kind, arg, rows, k=10, L=64, max_tick=max_tick, reclaim_every=200,
-                            hbm_budget_bytes=64 << 30, graph=True)
+        return arg, ii + i_idx.size, di + d_idx.size
+
+    def recall_at_end(ix):
+        gt, _ = ix.bruteforce(qs, 10)
+        gt = gt.cpu().numpy()
+        return {f"L{L}": round(recall(ix.search(qs, 10, L)[0].cpu().numpy(), gt), 4) for L in (64, 128, 256)}
+
+    ix, t_build = build(False)
+    out = {"metric": "serving: search latency p50 / p99 (ms) under Poisson load with overlapped updates, and churn "
+                     "throughput, 1 GPU",
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "serving_u8_10m", "n_base": n_base, "dim": wl.dim, "clusters": 4096, "R": wl.R,
+                      "k": 10, "L": 64, "mix": "90% search / 5% insert / 5% delete", "rates": rates,
+                      "seconds_per_rate": args.seconds, "max_tick": max_tick, "hbm_budget_gb": 64,
+                      "n_entry": args.n_entry, "W": args.W, "equivalent_rounds": args.equiv_rounds,
+                      "reclaim_every_ticks": args.reclaim_every, "parallelism": "single GPU"},
+           "build_s": round(t_build, 2), "per_rate": []}
+    ii = di = 0
+    for rate, tr in zip(rates, traces):
+        kind = tr["kind"]
+        arg, ii, di = args_of(kind, ii, di)
+        lat, ticks, sst = ix.serve(tr["t"], kind, arg, rows, k=10, L=64, max_tick=max_tick,
+                                   reclaim_every=args.reclaim_every, hbm_budget_bytes=64 << 30, graph=True,
+                                   realtime=True)
         ok = lat >= 0
-        srch = lat[(kind == 0) & ok]
-        upd = lat[(kind != 0) & ok]
-        pct = lambda a, q: round(float(np.percentile(a, q)), 3) if a.size else None  # noqa: E731
+        srch, upd = lat[(kind == 0) & ok], lat[(kind != 0) & ok]
         row = {"rate": rate, "requests": int(kind.size), "completed": int(ok.sum()),
-               "throughput_rps": round(float(ok.sum()) / max(sst["trace_seconds"], 1e-9), 1),
+               "throughput_rps": round(float(ok.sum()) / max(sst["wall_seconds"], 1e-9), 1),
                "search_p50_ms": pct(srch, 50), "search_p99_ms": pct(srch, 99), "search_p999_ms": pct(srch, 99.9),
                "update_p50_ms": pct(upd, 50), "update_p99_ms": pct(upd, 99), "max_ms": pct(lat[ok], 100),
                "ticks": int(sst["ticks"]), "mean_tick_requests": round(float(ok.sum()) / max(sst["ticks"], 1), 1),
-               "busy_fraction": round(sst["busy_seconds"] / max(sst["trace_seconds"], 1e-9), 3),
-               "rejected_inserts": int(sst["rejected_inserts"]), "failed_ticks": int(sst["failed_ticks"]),
-               "reclaims": int(sst["reclaims"]), "graphs": int(sst["graphs"]),
-               "peak_resident_slabs": int(sst["peak_resident_slabs"]),
-               "final_resident_slabs": int(sst["final_resident_slabs"]),
-               "tombstone_only_resident_slabs": int(sst["ids_handed_out"])}
+               "device_busy_fraction": round(sst["device_busy_seconds"] / max(sst["wall_seconds"], 1e-9), 3),
+               "deferred": int(sst["deferred"]), "rejected_inserts": int(sst["rejected_inserts"]),
+               "failed_ticks": int(sst["failed_ticks"]), "reclaims": int(sst["reclaims"])}
         out["per_rate"].append(row)
         log(args, f"rate {rate}: {row}")
-    qs = torch.from_numpy(st.queries(1000)).to(dev)
-    gt, _ = ix.bruteforce(qs, 10)
-    gt = gt.cpu().numpy()
-    for L in (64, 128, 256):
-        ids_s, _ = ix.search(qs, 10, L)
-        out[f"recall_at_10_L{L}_end"] = round(recall(ids_s.cpu().numpy(), gt), 4)
-    last = out["per_rate"][-1]
-    out["value"] = last["search_p99_ms"]
-    out["slab_bytes_peak"] = max(r["peak_resident_slabs"] for r in out["per_rate"]) * wl.R * 8
-    out["slab_bytes_tombstone_only"] = out["per_rate"][-1]["tombstone_only_resident_slabs"] * wl.R * 8
+    rt_state = (ii, di)
+
+    def churn(ix_):
+        ii_, di_ = rt_state
+        arg, _, _ = args_of(sat_kind, ii_, di_)
+        t_s = time.perf_counter()
+        lat, ticks, sst = ix_.serve(np.zeros(sat_kind.size), sat_kind, arg, rows, k=10, L=64, max_tick=max_tick,
+                                    reclaim_every=args.reclaim_every, graph=True, realtime=False)
+        wall = time.perf_counter() - t_s
+        srch = lat[(sat_kind == 0) & (lat >= 0)]
+        return {"requests": int(sat_kind.size), "inserts": int(sst["inserts"]), "deletes": int(sst["deletes"]),
+                "equivalent_rounds": round(sst["inserts"] / (0.01 * n_base), 2), "ticks": int(sst["ticks"]),
+                "requests_per_s": round(sat_kind.size / max(sst["wall_seconds"], 1e-9), 1),
+                "host_wall_s": round(wall, 2), "tick_search_p50_ms": pct(srch, 50), "tick_search_p99_ms": pct(srch, 99),
+                "reclaims": int(sst["reclaims"]), "failed_ticks": int(sst["failed_ticks"]),
+                "deferred": int(sst["deferred"]),
+                "peak_resident_slabs": int(sst["peak_resident_slabs"]),
+                "final_resident_slabs": int(sst["final_resident_slabs"]), "live_at_end": ix_.stats()["live"]}
+
+    out["churn"] = churn(ix)
+    log(args, f"churn: {out['churn']}")
+    out["recall_at_10_end"] = recall_at_end(ix)
     out["device_bytes"] = ix.stats()["device_bytes"]
     ix.close()
+    del ix
+    torch.cuda.empty_cache()
+    if not args.no_tombstone_twin:
+        tw, _ = build(True)
+        ii = di = 0
+        for tr in traces:  # the same requests as the served index saw, then the churn stream
+            arg, ii, di = args_of(tr["kind"], ii, di)
+            tw.serve(tr["t"], tr["kind"], arg, rows, k=10, L=64, max_tick=max_tick, graph=True, realtime=False)
+        tw_churn = churn(tw)
+        out["tombstone_only"] = {"peak_resident_slabs": tw_churn["peak_resident_slabs"],
+                                 "final_resident_slabs": tw_churn["final_resident_slabs"],
+                                 "requests_per_s": tw_churn["requests_per_s"],
+                                 "recall_at_10_end": recall_at_end(tw)}
+        tw.close()
+    out["slab_bytes_peak"] = out["churn"]["peak_resident_slabs"] * wl.R * 8
+    if "tombstone_only" in out:
+        out["slab_bytes_peak_tombstone_only"] = out["tombstone_only"]["peak_resident_slabs"] * wl.R * 8
+    out["value"] = out["per_rate"][-1]["search_p99_ms"]
+    return out
+
+
+def run_concurrent(args):
+    """Queries while the index changes (the paper's concurrent experiment,
+    Section 5.6): batches of 1,000 queries back to back on one stream, and on
+    another stream, never synchronized with it, churn rounds (1% deletes and
+    1% inserts each) whose reverse edges race by CAS. Queries and updates are
+    kept apart in the data so the ground truth cannot move under the churn:
+    the queries come from a quarter of the clusters (anchors), and every delete
+    and insert from the other clusters. Reports per-batch latency p50 / p99 and
+    Recall@10 against the anchor ground truth, with and without rounds in
+    flight, and the publication counters of the contended rounds."""
+    import torch
+
+    from paper_2607_02543_amd import datagen as dg
+    from paper_2607_02543_amd import etale
+
+    dev = torch.device("cuda:0")
+    n_base = args.n_base
+    rounds = args.rounds or 20
+    wl = dg.scale_u8(n_base=n_base, rounds=rounds)
+    st = dg.Stream(wl)
+    churn = wl.churn_count()
+    clusters = wl.mixture.n_clusters
+    anchor = np.arange(0, clusters, 4)
+    other = np.setdiff1d(np.arange(clusters), anchor)
+    cap = n_base + rounds * churn + 16
+    max_b = max(wl.build_batch_max, churn)
+    # retired slabs are not recycled while the mode lasts: room for all of them
+    slab_cap = 2 * cap + rounds * churn * 40 * (wl.R + 2) + max_b * (wl.R + 2)
+    ix = etale.Index(wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den), n_entry=args.n_entry,
+                     id_capacity=cap, slab_capacity=slab_cap, max_batch=max_b, W=args.W)
+    labels = np.zeros(n_base, np.int64)
+    done = 0
+    for b in wl.build_batches():
+        x, lab = st.base_labeled(b)
+        labels[done:done + b] = lab
+        ix.insert(torch.from_numpy(x).to(dev))
+        done += b
+    torch.cuda.synchronize()
+    q = torch.from_numpy(st.queries(1000, clusters=anchor)).to(dev)
+    gt0, _ = ix.bruteforce(q, 10)
+    gt0 = gt0.cpu().numpy()
+    deletable = np.nonzero(np.isin(labels, other))[0].astype(np.uint32)
+    rng = st.rng["deletes"]
+    order = rng.permutation(deletable.size)
+    del_rounds = [np.sort(deletable[order[r * churn:(r + 1) * churn]]) for r in range(rounds)]
+    ins_rounds = [torch.from_numpy(st.inserts(churn, clusters=other)).to(dev) for _ in range(rounds)]
+    del_t = [torch.from_numpy(d.astype(np.int32)).to(dev) for d in del_rounds]
+    S = torch.cuda.Stream()
+    U = torch.cuda.current_stream()
+    ix.set_concurrent(True, S)
+
+    def batches(nb):
+        ev, res = [], []
+        with torch.cuda.stream(S):
+            for _ in range(nb):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(S)
+                res.append(ix.search(q, 10, 64)[0])
+                e1.record(S)
+                ev.append((e0, e1))
+        return ev, res
+
+    def summarize(ev, res):
+        torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        rec = [recall(r.cpu().numpy(), gt0) for r in res]
+        return {"batches": len(ms), "p50_ms": round(float(np.percentile(ms, 50)), 4),
+                "p99_ms": round(float(np.percentile(ms, 99)), 4), "mean_ms": round(float(ms.mean()), 4),
+                "recall_at_10": round(float(np.mean(rec)), 4), "recall_min": round(float(np.min(rec)), 4)}
+
+    for _ in range(args.warmup):
+        summarize(*batches(20))
+    quiet = summarize(*batches(args.batches))
+    s0 = ix.stats()
+    # the concurrent phase: all batches enqueued on S at once, the rounds on U
+    u0 = torch.cuda.Event(enable_timing=True)
+    u1 = torch.cuda.Event(enable_timing=True)
+    ev, res = batches(args.batches)
+    u0.record(U)
+    for r in range(rounds):
+        ix.delete(del_t[r])
+        ix.insert(ins_rounds[r])
+    u1.record(U)
+    conc = summarize(ev, res)
+    rounds_ms = u0.elapsed_time(u1)
+    # which batches overlapped the rounds: those that ended after the first round began
+    t_first = ev[0][0].elapsed_time(u0)
+    overl = [i for i, (a, b) in enumerate(ev) if ev[0][0].elapsed_time(b) > t_first]
+    ix.set_concurrent(False)
+    s1 = ix.stats()
+    ix.reclaim()
+    s2 = ix.stats()
+    gt1, _ = ix.bruteforce(q, 10)
+    stable = float(np.mean([set(a.tolist()) == set(b.tolist()) for a, b in zip(gt0, gt1.cpu().numpy())]))
+    out = {"metric": "query batch latency p50 / p99 (ms, 1,000 queries) quiescent vs under concurrent churn rounds, "
+                     "Recall@10 on a fixed anchor set, 1 GPU",
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "concurrent_u8", "n_base": n_base, "clusters": clusters,
+                      "anchor_clusters": int(anchor.size), "rounds": rounds, "churn_per_round": churn, "k": 10,
+                      "L": 64, "batch": 1000, "batches": args.batches, "n_entry": args.n_entry, "W": args.W},
+           "quiescent": quiet, "concurrent": conc, "batches_overlapping_rounds": len(overl),
+           "rounds_wall_ms": round(rounds_ms, 2), "ms_per_round_concurrent": round(rounds_ms / rounds, 3),
+           "cas_failures": int(s1["cas_failures"] - s0["cas_failures"]),
+           "publish_dropped": int(s1["publish_dropped"] - s0["publish_dropped"]),
+           "pub_reverse": int(s1["pub_reverse"] - s0["pub_reverse"]),
+           "anchor_ground_truth_stable": round(stable, 4),
+           "after_reclaim": {"resident_slabs": s2["resident_slabs"], "live": s2["live"],
+                             "free_plus_resident_equals_pool": s2["free_slabs"] + s2["resident_slabs"] == slab_cap},
+           "value": conc["p99_ms"]}
+    ix.close()
+    return out
+
+
+def run_sweeps(args):
+    """The paper's parameter studies (Sections 4.5, 5.5, 5.7, 5.9, 5.10) on a
+    synthetic stand-in of its setup: 200,000 active 128-d uint8 vectors
+    (1,024-cluster mixture), R = 32, churn rounds of 1% = 2,000 deletes of random
+    live ids + 2,000 inserts.
+    - reclaim: for intervals I = 1, 2, 4, ..., 64 rounds, let I rounds of
+      tombstones accumulate and time one reclaim; dirty nodes, dead edges and
+      reclaim time against accumulated tombstones t, with the saturating fit
+      M (1 - exp(-t / tau)) of Proposition 4 and the model's tau = L / mean
+      in-degree beside it;
+    - pure deletion: 10% of the index deleted per round (with reclaim), 5 rounds;
+    - search list length (EF_SEARCH) 16 .. 128: Recall@10 and queries/s;
+    - churn rate 1% .. 5%: maintenance and reclaim time per round, recall;
+    - reclaim ablation: 5 rounds at 1% with a reclaim after each round vs none:
+      maintenance time, resident slabs, recall."""
+    import torch
+
+    from paper_2607_02543_amd import datagen as dg
+    from paper_2607_02543_amd import etale
+
+    dev = torch.device("cuda:0")
+    n_base = args.n_base if args.n_base != 1_000_000 else 200_000
+    wl = dg.scale_u8(n_base=n_base)
+    base_churn = wl.churn_count()
+    q_host = dg.Stream(wl).queries(10_000)
+    q = torch.from_numpy(q_host).to(dev)
+    qs = q[:1000]
+
+    class Run:
+        def __init__(self, max_frac=0.1, rounds=200):
+            self.st = dg.Stream(wl)
+            cap = n_base + int(rounds * max_frac * n_base) + 16
+            mb = max(wl.build_batch_max, int(max_frac * n_base) + 1)
+            self.ix = etale.Index(wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den),
+                                  n_entry=min(args.n_entry, n_base // 4), id_capacity=cap,
+                                  slab_capacity=3 * cap + 2 * mb * (wl.R + 2), max_batch=mb, W=args.W,
+                                  vt_slots=args.vt_slots)
+            self.live = np.zeros(cap, bool)
+            self.next = 0
+            for b in wl.build_batches():
+                self.ix.insert(torch.from_numpy(self.st.base(b)).to(dev))
+                self.live[self.next:self.next + b] = True
+                self.next += b
+            torch.cuda.synchronize()
+
+        def round(self, n_del, n_ins, reclaim):
+            lids = np.nonzero(self.live[:self.next])[0].astype(np.uint32)
+            dl = self.st.deletes(lids, n_del)
+            x = torch.from_numpy(self.st.inserts(n_ins)).to(dev) if n_ins else None
+            dlt = torch.from_numpy(dl.astype(np.int32)).to(dev)
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            s = torch.cuda.current_stream()
+            e[0].record(s)
+            self.ix.delete(dlt)
+            if x is not None:
+                self.ix.insert(x)
+            e[1].record(s)
+            if reclaim:
+                self.ix.reclaim()
+            e[2].record(s)
+            torch.cuda.synchronize()
+            self.live[dl] = False
+            self.live[self.next:self.next + n_ins] = True
+            self.next += n_ins
+            return e[0].elapsed_time(e[1]), (e[1].elapsed_time(e[2]) if reclaim else 0.0)
+
+        def recall(self, L=64):
+            gt, _ = self.ix.bruteforce(qs, 10)
+            return round(recall(self.ix.search(qs, 10, L)[0].cpu().numpy(), gt.cpu().numpy()), 4)
+
+        def close(self):
+            self.ix.close()
+
+    def fit(t, y):
+        from scipy.optimize import curve_fit
+        t, y = np.asarray(t, float), np.asarray(y, float)
+        f = lambda x, M, tau: M * (1.0 - np.exp(-x / tau))  # noqa: E731
+        (M, tau), _ = curve_fit(f, t, y, p0=(max(y) * 1.2, float(np.median(t))), maxfev=20000)
+        res = y - f(t, M, tau)
+        r2 = 1.0 - float((res ** 2).sum()) / float(((y - y.mean()) ** 2).sum())
+        return {"M": round(float(M), 4), "tau": round(float(tau), 1), "r2": round(r2, 4)}
+
+    out = {"metric": "paper-shaped sweeps on a 200k-active stand-in: reclaim cost vs accumulated tombstones, "
+                     "pure deletion, search list length, churn rate, reclaim ablation; 1 GPU",
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "sweeps_u8_200k", "n_base": n_base, "dim": wl.dim, "clusters": 1024, "R": wl.R,
+                      "L_build": wl.L_build, "churn_1pct": base_churn, "n_entry": min(args.n_entry, n_base // 4),
+                      "W": args.W}}
+    # -- reclaim cost against accumulated tombstones (Proposition 4, Section 5.7)
+    r = Run()
+    e = r.ix.export()
+    live_n = int((~e["deleted"]).sum())
+    dbar = float(e["deg"][~e["deleted"]].astype(np.int64).sum()) / live_n
+    pts = []
+    for I in (1, 2, 4, 8, 16, 32, 64):
+        maint = [r.round(base_churn, base_churn, False)[0] for _ in range(I)]
+        s0 = r.ix.stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r.ix.reclaim()
+        e1.record()
+        torch.cuda.synchronize()
+        s1 = r.ix.stats()
+        pts.append({"interval_rounds": I, "tombstones": I * base_churn, "dirty": s1["dirty_last"],
+                    "dead_edges": s1["dead_edges_last"], "reclaim_ms": round(e0.elapsed_time(e1), 4),
+                    "freed": s1["freed"] - s0["freed"], "maintenance_ms_mean": round(float(np.mean(maint)), 3)})
+        log(args, f"reclaim I={I}: {pts[-1]}")
+    t = [p_["tombstones"] for p_ in pts]
+    out["reclaim"] = {"points": pts, "live": live_n, "mean_in_degree": round(dbar, 2),
+                      "tau_model_L_over_dbar": round(live_n / dbar, 1),
+                      "dirty_fit": fit(t, [p_["dirty"] for p_ in pts]),
+                      "reclaim_ms_fit": fit(t, [p_["reclaim_ms"] for p_ in pts]),
+                      "dead_edges_per_tombstone": [round(p_["dead_edges"] / p_["tombstones"], 2) for p_ in pts],
+                      "recall_at_10_end": r.recall()}
+    r.close()
+    # -- pure deletion stress (Section 5.5)
+    r = Run()
+    rows = [{"round": 0, "live": int(r.live.sum()), "recall_at_10": r.recall()}]
+    for i in range(5):
+        m_ms, r_ms = r.round(n_base // 10, 0, True)
+        rows.append({"round": i + 1, "live": int(r.live.sum()), "delete_ms": round(m_ms, 3),
+                     "reclaim_ms": round(r_ms, 3), "recall_at_10": r.recall()})
+    out["pure_deletion"] = rows
+    r.close()
+    # -- search list length (EF_SEARCH, Section 5.9), after 5 churn rounds
+    r = Run()
+    maint = [r.round(base_churn, base_churn, True) for _ in range(5)]
+    gt, _ = r.ix.bruteforce(qs, 10)
+    gt = gt.cpu().numpy()
+    ef = []
+    for L in (16, 32, 48, 64, 96, 128):
+        r.ix.search(q, 10, L)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            r.ix.search(q, 10, L)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        ef.append({"L": L, "recall_at_10": round(recall(r.ix.search(qs, 10, L)[0].cpu().numpy(), gt), 4),
+                   "qps": round(q.shape[0] / (ms * 1e-3), 1), "search_ms": round(ms, 4)})
+    out["ef_search"] = {"points": ef, "maintenance_ms_mean": round(float(np.mean([m[0] for m in maint])), 3),
+                        "reclaim_ms_mean": round(float(np.mean([m[1] for m in maint])), 3)}
+    r.close()
+    # -- churn rate (Section 5.9)
+    cr = []
+    for frac in (0.01, 0.02, 0.03, 0.04, 0.05):
+        r = Run(max_frac=0.05, rounds=4)
+        n = int(round(frac * n_base))
+        ms = [r.round(n, n, True) for _ in range(3)]
+        cr.append({"churn": frac, "per_round": n, "maintenance_ms": round(float(np.mean([m[0] for m in ms])), 3),
+                   "reclaim_ms": round(float(np.mean([m[1] for m in ms])), 3), "recall_at_10": r.recall()})
+        r.close()
+    out["churn_rate"] = cr
+    # -- reclaim ablation (Section 5.10)
+    ab = {}
+    for name, rec in (("reclaim_each_round", True), ("no_reclaim", False)):
+        r = Run(rounds=6)
+        ms = [r.round(base_churn, base_churn, rec) for _ in range(5)]
+        s_ = r.ix.stats()
+        ab[name] = {"maintenance_ms": round(float(np.mean([m[0] for m in ms])), 3),
+                    "reclaim_ms": round(float(np.mean([m[1] for m in ms])), 3),
+                    "resident_slabs": s_["resident_slabs"], "live": s_["live"], "recall_at_10": r.recall()}
+        r.close()
+    out["ablation"] = ab
+    out["value"] = out["ef_search"]["maintenance_ms_mean"]
     return out
 
 
@@ -506,6 +850,12 @@ def main():
         return
     if args.workload == "serving_u8":
         print(json.dumps(run_serving(args)), flush=True)
+        return
+    if args.workload == "concurrent_u8":
+        print(json.dumps(run_concurrent(args)), flush=True)
+        return
+    if args.workload == "sweeps_u8":
+        print(json.dumps(run_sweeps(args)), flush=True)
         return
     import torch
 
@@ -526,7 +876,8 @@ def main():
     t0 = time.perf_counter()
     ix = etale.Index(wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den),
                      n_entry=args.n_entry, id_capacity=cap, slab_capacity=slab_cap, max_batch=max_batch,
-                     vt_slots=args.vt_slots, waves_per_block=args.waves_per_block, W=args.W)
+                     vt_slots=args.vt_slots, waves_per_block=args.waves_per_block, W=args.W,
+                     row_lanes=args.row_lanes)
     live = np.zeros(cap, bool)
     done = 0
     for b in wl.build_batches():
@@ -571,12 +922,17 @@ def main():
         for L in Ls:
             ix.search(q, 10, L)
     torch.cuda.synchronize()
+    # result-invariant launch knobs (waves per workgroup, visited slots, lanes
+    # per row) picked by the library's autotuner on the query batch
+    tune = ix.autotune(q, 10, 64) if args.autotune else None
+    log(args, f"autotune: {tune}")
 
     # timed steps: one churn round, then the query batch at every L of the sweep
     inputs = [churn_round() for _ in range(args.steps)]
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2 + len(Ls))] for _ in range(args.steps)]
     counts = {L: [] for L in Ls}
     stage = {L: [] for L in Ls}
+    last_ids = {}
     ix.set_search_timing(True)
     ix.search_timing()
     torch.cuda.synchronize()
@@ -586,9 +942,10 @@ def main():
         apply_round(*inputs[s_])
         ev[s_][1].record(stream)
         for j, L in enumerate(Ls):
-            _, _, cnt = ix.search(q, 10, L, counts=True)
+            ids_L, _, cnt = ix.search(q, 10, L, counts=True)
             ev[s_][2 + j].record(stream)
             counts[L].append(cnt)
+            last_ids[L] = ids_L  # the final step's results give the recall (no search launch after timing)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # per-stage kernel durations of every timed search launch (HIP events on the index's stream)
@@ -609,16 +966,16 @@ def main():
     S = stats["n_entries"]
     sweep = {}
     for L in Ls:
-        ids_s, _ = ix.search(qs, 10, L)
+        ids_s = last_ids[L][: args.recall_sample]
         c = torch.stack(counts[L]).cpu().numpy().astype(np.int64)
         E, U = c[..., 0].sum(1).mean(), c[..., 1].sum(1).mean()
         t = float(np.mean(search_ms[L])) * 1e-3
-        # k_search's algorithmic bytes per launch: per expansion the slab's 4R-byte
-        # id half; per traversal distance one vector row plus its 8-byte reference
-        # (fetched with the row); per query its row, its initial list (L keys in,
-        # L references gathered) and k results out.
+        # the beam search's algorithmic bytes per launch, B_q = E (8 + 4R) + U m +
+        # m + 8k per query: per expansion the node's 8-byte reference word and
+        # its slab's 4R-byte id half, per traversal distance one m-byte row (its
+        # norm is computed from the row), per query its row and k results out
         U_trav = U - S * args.queries
-        nbytes = E * 4 * wl.R + U_trav * (wl.dim + 8) + args.queries * (wl.dim + 16 * L + 8 * 10)
+        nbytes = E * (8 + 4 * wl.R) + U_trav * wl.dim + args.queries * (wl.dim + 8 * 10)
         t_k = stage[L]["search_ms"] * 1e-3  # one k_search launch
         sweep[L] = {"recall_at_10": round(recall(ids_s.cpu().numpy(), gt), 4),
                     "qps": round(args.queries / t, 1), "search_ms": round(t * 1e3, 4),
@@ -653,6 +1010,7 @@ def main():
                    "queries": args.queries, "k": 10, "search_L": Ls, "n_entry": args.n_entry, "W": args.W,
                    "parallelism": "single GPU"},
         "sweep": {str(k): v for k, v in sweep.items()},
+        "autotune": tune,
         "build_s": round(t_build, 2),
         "slabs_resident": stats["resident_slabs"],
         "live": stats["live"],

@@ -284,19 +284,40 @@ etale_status etale_export_rows(etale_t ix, uint64_t first, uint64_t n, int32_t w
  * synchronizes, writes up to cap launches as (scan, select, search)
  * millisecond triples in launch order into ms_host (cap x 3), the number of
  * recorded launches into *launches, and forgets them. */
-/* ---- serving: continuous batching of a request trace ----------------------
- * Requests arrive at given times; each tick admits every request that has
- * arrived (up to max_tick) and runs them as one round (etale_round):
- * deletes, inserts and searches of a tick see the state left by the previous
- * tick (the tick's own tombstones applied first, as in every round). Ticks
- * run back to back; a tick that finds no pending request waits for the next
- * arrival. Time is the trace's clock: a tick starts at max(end of the
- * previous tick, first pending arrival) and lasts the measured wall time of
- * its host work and device work (one synchronization per tick); a request's
- * latency is its tick's end minus its arrival. With graph != 0 each tick
- * replays a captured round for the power-of-two size bucket of its counts.
- * Retired slabs return to the pool at the end of each tick (the epoch of
- * Lemma 1 is the tick). */
+/* ---- serving: continuous batching of a request stream ---------------------
+ * The problem statement of Section 3.1 has readers (searches) and writers
+ * (inserts, deletes) running against one graph at the same time. Here the
+ * requests are admitted in ticks, and every tick's work runs on two streams:
+ *   - its searches on the index's stream, against a snapshot taken when the
+ *     tick starts (reference words, counters, entry set and its rows: the state
+ *     the previous tick's updates left), and
+ *   - its deletes and inserts as one round (etale_round without queries, plus
+ *     the reclaim every reclaim_every ticks) on a second stream,
+ * so a tick's searches and its updates overlap on the device. The next tick's
+ * snapshot waits for both. Two sets of tick buffers alternate, so the host
+ * admits and enqueues tick t+1 while tick t runs. A slab that tick t's round
+ * retires is reused only by tick t+1's round, which starts after tick t's
+ * searches end: the epoch separation of Lemma 1, kept across the two streams.
+ * A search therefore returns exactly what the same query returns alone on the
+ * tick's snapshot (etale_search_batch on the state after the previous tick).
+ *
+ * Admission: a tick takes pending requests in arrival order, up to max_tick.
+ * A search is always admitted. An insert or delete is admitted only if the
+ * free slab pool, less the worst-case demand of the tick still in flight,
+ * covers the tick's worst-case demand n_ins*(R+2) + n_del*R; otherwise it
+ * waits for a later tick while the requests behind it go ahead (counted in
+ * `deferred`, once per skip). An insert that would take rows +
+ * resident slabs + the library's fixed buffers past hbm_budget_bytes (if
+ * nonzero), or the ids past the id space, is rejected (latency -1).
+ *
+ * Clock: realtime != 0 replays the arrival times on the wall clock from the
+ * first request (a request is admitted no earlier than it arrives; latency =
+ * completion - arrival, completions read from device events). realtime == 0
+ * ignores the arrival times and admits the next max_tick requests per tick
+ * (saturated throughput; the tick composition then depends only on the trace
+ * and the pool); latency is then completion - the tick's start.
+ * With graph != 0 each tick's round replays a captured round for the
+ * power-of-two size bucket of its counts. */
 enum { ETALE_REQ_SEARCH = 0, ETALE_REQ_INSERT = 1, ETALE_REQ_DELETE = 2 };
 
 typedef struct {
@@ -306,32 +327,35 @@ typedef struct {
 } etale_request;
 
 typedef struct {
-  uint32_t k, L;            /* every search: top k from a list of L */
-  uint32_t max_tick;        /* requests admitted per tick, at most max_batch */
-  uint32_t reclaim_every;   /* ticks between reclaims (0: never) */
-  uint64_t hbm_budget_bytes; /* 0, or: an insert is rejected (latency -1) when
-                                rows + resident slabs + the library's fixed
-                                buffers would exceed it after the tick */
-  int32_t graph;            /* replay size-bucketed captured rounds */
-  uint32_t reserved;
+  uint32_t k, L;             /* every search: top k from a list of L */
+  uint32_t max_tick;         /* requests admitted per tick, at most max_batch */
+  uint32_t reclaim_every;    /* ticks between reclaims (0: never) */
+  uint64_t hbm_budget_bytes; /* 0, or the budget inserts are admitted against */
+  int32_t graph;             /* replay size-bucketed captured rounds */
+  int32_t realtime;          /* 1: arrivals on the wall clock; 0: saturated */
 } etale_serve_config;
 
 typedef struct {
-  uint64_t ticks, searches, inserts, deletes, rejected_inserts, reclaims, failed_ticks;
+  uint64_t ticks, searches, inserts, deletes, rejected_inserts, deferred, reclaims, failed_ticks;
   uint64_t peak_resident_slabs, final_resident_slabs, ids_handed_out, graphs;
-  double trace_seconds; /* first arrival to the end of the last tick */
-  double busy_seconds;  /* sum of tick durations */
+  double wall_seconds;        /* from the loop's start to the last completion */
+  double device_busy_seconds; /* sum over ticks of snapshot -> last of its two streams */
 } etale_serve_stats;
 
 /* Serve reqs_host[0..n) against the index. rows_dev holds n_rows vectors
  * (dim elements each, uint8 or FP32 as the index) that search and insert
- * requests name by row. latency_ms_host (n floats, may be NULL) receives each
- * request's latency in ms (-1 for a rejected insert). Synchronizes. Errors:
- * EINVAL (bad arguments, a row or kind out of range), and those of
+ * requests name by row. Optional outputs (NULL to skip): latency_ms_host (n
+ * floats; -1 for a rejected insert or a failed tick), tick_host (n uint32:
+ * the tick that served each request, 0xFFFFFFFF if none), and res_ids_dev /
+ * res_dists_dev (device, n x k each, row j for request j; written for search
+ * requests only, padded as etale_search_batch). Synchronizes. Errors: EINVAL
+ * (bad arguments, a row or kind out of range), ENOMEM (tick buffers), EPOOL
+ * (pending updates that no slab pool state can cover), and those of
  * etale_round; a tick whose round fails on the device is counted in
  * failed_ticks and its requests get latency -1. */
 etale_status etale_serve(etale_t ix, const etale_serve_config* cfg, const etale_request* reqs_host, uint64_t n,
-                         const void* rows_dev, uint64_t n_rows, float* latency_ms_host, etale_serve_stats* out_host);
+                         const void* rows_dev, uint64_t n_rows, float* latency_ms_host, uint32_t* tick_host,
+                         uint32_t* res_ids_dev, void* res_dists_dev, etale_serve_stats* out_host);
 
 /* Result-invariant launch knobs of the beam search: waves per workgroup (1,
  * 2 or 4; halved further while a workgroup's LDS would exceed 64 KiB) and
@@ -340,21 +364,48 @@ etale_status etale_serve(etale_t ix, const etale_serve_config* cfg, const etale_
  * keyed by these values, so a change never alters a captured round. */
 etale_status etale_set_search_knobs(etale_t ix, uint32_t waves_per_block, uint32_t vt_slots);
 
+/* Result-invariant: lanes of a wave that share one uint8 row in a distance
+ * batch, dim/16 (16 bytes each, the default; 0 means the same) or, for 128-
+ * and 256-byte rows, dim/32 (32 bytes each: twice the rows per pass, shorter
+ * group sums). EINVAL otherwise. */
+etale_status etale_set_search_lanes(etale_t ix, uint32_t lanes_per_row);
+
 typedef struct {
   uint32_t waves_per_block;
   uint32_t vt_slots;
-  float ms;          /* mean search time of the chosen setting on the batch */
-  float ms_default;  /* the same for the setting in force before the call */
+  uint32_t row_lanes;  /* lanes per uint8 row (0 for float rows) */
+  float ms;            /* mean search time of the chosen setting on the batch */
+  float ms_default;    /* the same for the setting in force before the call */
 } etale_tune_result;
 
 /* Autotuner: times the query search on the caller's batch (q_dev [nq x dim],
- * k, L) for every knob setting above (waves 1/2/4 x slots 256..4096) and
- * keeps the fastest. Allocates its own output scratch; synchronizes. */
+ * k, L) for every setting of the result-invariant knobs above (waves 1/2/4 x
+ * visited slots 256..4096 x lanes per row) and keeps the fastest; results do
+ * not depend on the choice. Allocates its own output scratch; synchronizes. */
 etale_status etale_autotune(etale_t ix, const void* q_dev, uint64_t nq, uint32_t k, uint32_t L,
                             etale_tune_result* out_host);
 
 etale_status etale_set_search_timing(etale_t ix, int32_t enable);
 etale_status etale_get_search_timing(etale_t ix, float* ms_host, uint64_t cap, uint64_t* launches);
+
+/* Concurrent mode (the experiment of Section 5.6: readers and writers on two
+ * streams that do not synchronize with each other). enable != 0: searches
+ * (etale_search_batch) run on search_stream (a hipStream_t other than the
+ * index's) with their own scratch, read the live reference words and slabs
+ * while rounds on the index's stream publish, and return for each node the
+ * list either before or after any publication that overlaps them (one
+ * atomic reference load names an immutable slab). Meanwhile every publication
+ * takes the release fence before its CAS; reverse edges are applied offer by
+ * offer, racing by CAS with retries (Algorithm 1's loop; the list is rebuilt
+ * from a fresh snapshot after a lost CAS; an offer whose attempt budget runs
+ * out is counted in publish_dropped), so their order, and the lists, are not
+ * deterministic; the entry set is frozen; and slabs retired by the rounds
+ * are not recycled (a search may still hold them), so the pool must cover
+ * every publication of the mode. enable == 0: both streams drain, the retired
+ * slabs rejoin the free pool and the entry set is brought up to date
+ * (synchronizes). Not with tombstone_only. The no-alloc search and serving
+ * are not for this mode. */
+etale_status etale_set_concurrent(etale_t ix, int32_t enable, void* search_stream);
 
 /* Wait for the index's stream. */
 etale_status etale_sync(etale_t ix);

@@ -9,6 +9,8 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "etale.h"
@@ -75,6 +77,16 @@ struct etale_index {
   std::string err;
   std::vector<void*> allocs;
   unsigned char* noalloc = nullptr;  // device address of the static search scratch on the index's device
+  uint32_t row_lanes = 0;            // uint8 rows: lanes per row in distance batches (0: dim / 16)
+  // concurrent mode: searches on their own stream and scratch while rounds run
+  bool concurrent = false;
+  hipStream_t search_stream = nullptr;
+  std::vector<void*> conc_bufs;
+  struct {
+    uint64_t* keys = nullptr;
+    uint32_t *n = nullptr, *dist = nullptr, *gmin = nullptr, *bound = nullptr, *ncand = nullptr;
+    uint64_t* cand = nullptr;
+  } cs;
 };
 
 namespace {
@@ -268,12 +280,17 @@ ScanScratch noalloc_scratch(unsigned char* base, uint32_t ns, uint32_t L) {
 // counts known only on the device (a replayed graph sized for its maximum),
 // persistent search waves take queries from a work queue instead of one wave
 // per possible query.
+// `view` (default: the index itself) is the state the searches read, e.g. a
+// serving snapshot; `stream` (default: the index's) is where they run.
 etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t nmax, uint32_t k, uint32_t L,
                           uint32_t vcap, uint32_t* out_ids, uint32_t* out_d, uint32_t* counts, Dyn base,
-                          bool persistent = false, const ScanScratch* given = nullptr) {
+                          bool persistent = false, const ScanScratch* given = nullptr, const Index* view = nullptr,
+                          hipStream_t stream = nullptr) {
   const uint32_t ns = ix->cfg.n_entry;  // upper bound; the kernels read the entry count
   const ScanScratch scr = given ? *given : library_scratch(ix, ns);
   const uint32_t chunk = scr.chunk;
+  const Index& dev = view ? *view : ix->dev;
+  const hipStream_t st = view ? stream : ix->stream;
   const size_t qbytes = (size_t)ix->cfg.dim * (ix->cfg.metric == ETALE_METRIC_L2_U8 ? 1 : 4);
   for (uint64_t c = 0; c < nmax; c += chunk) {
     const uint32_t cn = (uint32_t)std::min<uint64_t>(chunk, nmax - c);
@@ -295,7 +312,7 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
     sc.out_keys = scr.keys;
     sc.out_n = scr.n;
     sc.out_stride = L;
-    sc.trav = mode == MODE_QUERY ? ix->qtrav : ix->dev.trav;
+    sc.trav = mode == MODE_QUERY ? ix->qtrav : dev.trav;
     sc.d = d;
     std::array<hipEvent_t, 4> ev{};
     const bool timed = ix->timing && mode == MODE_QUERY && !given;
@@ -310,10 +327,10 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
         ix->ev_pool.pop_back();
       }
       ix->ev_used.push_back(ev);
-      HIP_TRY(hipEventRecord(ev[0], ix->stream));
+      HIP_TRY(hipEventRecord(ev[0], st));
     }
-    HIP_TRY(launch_scan(ix->dev, sc, ix->stream, timed ? ev[1] : nullptr));
-    if (timed) HIP_TRY(hipEventRecord(ev[2], ix->stream));
+    HIP_TRY(launch_scan(dev, sc, st, timed ? ev[1] : nullptr));
+    if (timed) HIP_TRY(hipEventRecord(ev[2], st));
     SearchArgs sa{};
     sa.mode = mode;
     sa.q = sc.q;
@@ -332,6 +349,7 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
     sa.rerank = mode == MODE_QUERY ? ix->qrerank : 0;
     sa.d = d;
     sa.persistent = persistent ? 1u : 0u;
+    sa.row_lanes = ix->row_lanes;
     if (mode == MODE_QUERY) {
       sa.out_ids = out_ids + c * k;
       sa.out_d = out_d + c * k;
@@ -340,8 +358,8 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
       sa.vis_keys = ix->vis_keys + c * vcap;
       sa.vis_cnt = ix->vis_cnt + c;
     }
-    HIP_TRY(launch_search(ix->dev, sa, search_waves_per_block(ix, sa.lds_per_wave), ix->stream));
-    if (timed) HIP_TRY(hipEventRecord(ev[3], ix->stream));
+    HIP_TRY(launch_search(dev, sa, search_waves_per_block(ix, sa.lds_per_wave), st));
+    if (timed) HIP_TRY(hipEventRecord(ev[3], st));
   }
   return ETALE_OK;
 }
@@ -410,7 +428,7 @@ etale_status enqueue_reclaim(etale_index* ix, uint64_t n_ids_max, int32_t* statu
   df.skip = G_FAIL | G_RFAIL;
   df.n_ctr = C_NEXT_ID;
   HIP_TRY(launch_free_tombstones(d, n_ids_max, df, ix->stream));
-  HIP_TRY(launch_recycle(d, ix->stream));
+  if (!ix->concurrent) HIP_TRY(launch_recycle(d, ix->stream));
   return ETALE_OK;
 }
 
@@ -439,7 +457,7 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     Dyn dr;
     dr.skip = G_FAIL;
     dr.first_ctr = C_R_FIRST;  // this round's new ids are not live yet
-    HIP_TRY(launch_refresh_entries(d, 0, ix->cfg.n_entry, dr, s));
+    if (!ix->concurrent) HIP_TRY(launch_refresh_entries(d, 0, ix->cfg.n_entry, dr, s));
   }
   Dyn di;
   di.skip = G_FAIL;
@@ -448,6 +466,7 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
   const uint32_t vcap = ix->vcap_build;
   if (p.max_i) {
     HIP_TRY(launch_store_rows(d, p.vecs, p.ids_out, 0, p.max_i, di, s));
+    if (ix->cfg.metric == ETALE_METRIC_L2_U8 && ix->cfg.dim <= 256) HIP_TRY(launch_row_norms(d, 0, p.max_i, di, s));
     if (ix->cfg.metric == ETALE_METRIC_IP_F32) HIP_TRY(launch_encode(d, 0, p.max_i, di, ix->xs, ix->xb, ix->x8, s));
     // P1: the insert searches on the state the tombstones left, or the bootstrap
     if (p.boot != 0) {
@@ -520,6 +539,14 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     fa.pairs = ix->pairs_a;
     fa.d = di;
     HIP_TRY(launch_reverse_pairs(d, fa, s));
+    if (ix->concurrent) {
+      // concurrent mode: every offer applied on its own, racing by CAS
+      MaintArgs ra = maint_args(ix, R + 1);
+      ra.n = p.max_i;
+      ra.pairs = ix->pairs_a;
+      ra.d = di;
+      HIP_TRY(launch_maint(MK_REVERSE_FAST, d, ra, p.max_i * R, maint_waves_per_block(ra), s));
+    } else {
     Dyn dp;
     dp.skip = G_FAIL;
     dp.n_ctr = C_R_NINS;
@@ -541,6 +568,7 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     ra.seg = ix->seg;
     ra.d = di;
     HIP_TRY(launch_maint(MK_REVERSE, d, ra, ra.npairs, maint_waves_per_block(ra), s));
+    }
     // P5: refine (not after a bootstrap)
     if (ix->cfg.refine && p.boot != 1) {
       MaintArgs ga = maint_args(ix, R + R * R);
@@ -555,9 +583,11 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     Dyn de;
     de.skip = G_FAIL;
     de.first_ctr = C_NEXT_ID;
-    HIP_TRY(launch_refresh_entries(d, 0, ix->cfg.n_entry, de, s));
+    if (!ix->concurrent) HIP_TRY(launch_refresh_entries(d, 0, ix->cfg.n_entry, de, s));
   }
-  HIP_TRY(launch_recycle(d, s));  // end of the epoch (Lemma 1)
+  // end of the epoch (Lemma 1); in the concurrent mode searches may still read
+  // what this round retired, so the recycle waits for the mode's end
+  if (!ix->concurrent) HIP_TRY(launch_recycle(d, s));
   if (p.reclaim) return enqueue_reclaim(ix, p.n_ids_max, p.status);
   return ETALE_OK;
 }
@@ -682,6 +712,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   d.b2 = c.alpha_den * c.alpha_den;
   d.publish_attempts = c.publish_attempts;
   d.fence = 0;  // every call is a round-synchronous launch sequence
+  d.concurrent = 0;
   d.prune_cap = c.prune_cap;
   d.metric = c.metric;
   d.trav = c.metric == ETALE_METRIC_IP_F32 ? c.traversal : 0;
@@ -721,6 +752,7 @@ etale_status etale_destroy(etale_t ix) {
     for (hipEvent_t e : q) (void)hipEventDestroy(e);
   for (hipEvent_t e : ix->ev_pool) (void)hipEventDestroy(e);
   for (void* p : ix->allocs) (void)hipFree(p);
+  for (void* p : ix->conc_bufs) (void)hipFree(p);
   delete ix;
   return ETALE_OK;
 }
@@ -737,7 +769,7 @@ etale_status etale_insert_batch(etale_t ix, const void* vecs_dev, uint64_t n, ui
   if (!vecs_dev || n > ix->cfg.max_batch) return fail(ix, ETALE_EINVAL, "insert: null vectors or n > max_batch");
   unsigned long long h[C_NCOUNTERS];
   if (etale_status st = read_counters(ix, h)) return st;
-  if (h[C_N_ENTRIES] != std::min<uint64_t>(ix->cfg.n_entry, h[C_LIVE])) {
+  if (!ix->concurrent && h[C_N_ENTRIES] != std::min<uint64_t>(ix->cfg.n_entry, h[C_LIVE])) {  // frozen in that mode
     ix->poisoned = true;
     return fail(ix, ETALE_ESTATE, "entry-set size on the device disagrees with the live count");
   }
@@ -777,6 +809,20 @@ etale_status etale_search_batch(etale_t ix, const void* q_dev, uint64_t nq, uint
     return fail(ix, ETALE_EINVAL, "search: null buffer");
   if (ix->cfg.metric == ETALE_METRIC_IP_F32 && ix->qtrav != ETALE_TRAV_NATIVE && (uint64_t)ix->qrerank * k > 64)
     return fail(ix, ETALE_EINVAL, "search: rerank_mult * k must not exceed 64");
+  if (ix->concurrent) {  // alongside the rounds: own stream, own scratch, the live state
+    ScanScratch cs;
+    cs.keys = ix->cs.keys;
+    cs.n = ix->cs.n;
+    cs.dist = ix->cs.dist;
+    cs.gmin = ix->cs.gmin;
+    cs.bound = ix->cs.bound;
+    cs.ncand = ix->cs.ncand;
+    cs.cand = ix->cs.cand;
+    cs.chunk = scan_chunk_for(ix, ix->cfg.n_entry);
+    return run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(q_dev), nq, k, L, ix->cfg.visit_mult * L,
+                        ids_out_dev, reinterpret_cast<uint32_t*>(dists_out_dev), counts_out_dev, Dyn{}, false, &cs,
+                        &ix->dev, ix->search_stream);
+  }
   return run_searches(ix, MODE_QUERY, reinterpret_cast<const uint8_t*>(q_dev), nq, k, L, ix->cfg.visit_mult * L,
                       ids_out_dev, reinterpret_cast<uint32_t*>(dists_out_dev), counts_out_dev, Dyn{});
 }
@@ -840,7 +886,7 @@ etale_status etale_round(etale_t ix, const etale_round_desc* r) {
   if (!d.graph) return enqueue_round(ix, p);
   // capture once per descriptor, replay afterwards
   const std::string key = graph_key(d, ix->qtrav, ix->qrerank) + "/" + std::to_string(ix->cfg.waves_per_block) +
-                          "/" + std::to_string(ix->cfg.vt_slots);
+                          "/" + std::to_string(ix->cfg.vt_slots) + "/" + std::to_string(ix->row_lanes);
   auto it = ix->graphs.find(key);
   if (it == ix->graphs.end()) {
     if (!ix->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ix->cap_stream, hipStreamNonBlocking));
@@ -875,8 +921,16 @@ etale_status etale_bruteforce(etale_t ix, const void* q_dev, uint64_t nq, uint32
   if (nq == 0) return ETALE_OK;
   if (etale_status st = refresh_mirror(ix)) return st;
   if (!q_dev || !ids_out_dev || !dists_out_dev) return fail(ix, ETALE_EINVAL, "bruteforce: null buffer");
-  HIP_TRY(launch_bruteforce(ix->dev, q_dev, (uint32_t)nq, ix->next_id, k, ids_out_dev,
-                            reinterpret_cast<uint32_t*>(dists_out_dev), ix->stream));
+  const uint64_t sb = bruteforce_scratch_bytes(ix->dev, (uint32_t)nq, ix->next_id);
+  unsigned char* scr = nullptr;
+  if (sb && hipMallocAsync(reinterpret_cast<void**>(&scr), sb, ix->stream) != hipSuccess) {
+    scr = nullptr;  // no scratch: the one-wave-per-query kernel
+    (void)hipGetLastError();
+  }
+  const hipError_t e = launch_bruteforce(ix->dev, q_dev, (uint32_t)nq, ix->next_id, k, ids_out_dev,
+                                         reinterpret_cast<uint32_t*>(dists_out_dev), ix->stream, scr);
+  if (scr) (void)hipFreeAsync(scr, ix->stream);
+  HIP_TRY(e);
   return ETALE_OK;
 }
 
@@ -1042,190 +1096,413 @@ uint32_t size_bucket(uint32_t n, uint32_t floor, uint32_t cap) {
   while (b < n) b <<= 1;
   return b < cap ? b : cap;
 }
+
+// One of the two tick slots of the serving loop: device inputs and outputs,
+// pinned host staging, the events that mark the tick's stages, and what the
+// host needs to finish the tick when they have passed.
+struct TickSlot {
+  uint32_t *d_idx = nullptr, *d_qids = nullptr, *d_qd = nullptr, *d_counts = nullptr, *d_ids = nullptr;
+  uint32_t* d_pos = nullptr;  // request index of each search of the tick
+  uint8_t *d_vecs = nullptr, *d_q = nullptr, *d_dst = nullptr;
+  int32_t* d_status = nullptr;
+  uint32_t* h_idx = nullptr;  // [3T + 4]: delete ids, insert rows, query rows, counts
+  uint32_t* h_pos = nullptr;  // [T]
+  int32_t* h_status = nullptr;
+  unsigned long long* h_ctr = nullptr;  // free and retired stack tops after the tick's round
+  hipEvent_t e_snap = nullptr, e_srch = nullptr, e_upd = nullptr;
+  bool busy = false;
+  uint64_t tick = 0;
+  uint64_t demand = 0;  // worst-case slabs the tick's round may take
+  uint32_t nd = 0, ni = 0, nq = 0;
+  bool reclaim = false;
+  double t_enqueue = 0.0;  // wall seconds since the loop's start
+  std::vector<uint64_t> members;
+};
 }  // namespace
 
 etale_status etale_serve(etale_t ix, const etale_serve_config* cfg, const etale_request* reqs, uint64_t n,
-                         const void* rows_dev, uint64_t n_rows, float* latency_ms, etale_serve_stats* out) {
+                         const void* rows_dev, uint64_t n_rows, float* latency_ms, uint32_t* tick_host,
+                         uint32_t* res_ids_dev, void* res_dists_dev, etale_serve_stats* out) {
   CHECK_HANDLE();
   if (!cfg || !out || (n && !reqs)) return fail(ix, ETALE_EINVAL, "serve: null argument");
   const etale_serve_config c = *cfg;
   if (c.max_tick < 1 || c.max_tick > ix->cfg.max_batch || c.k < 1 || c.k > c.L || c.L > 256)
     return fail(ix, ETALE_EINVAL, "serve: need 1 <= max_tick <= max_batch and 1 <= k <= L <= 256");
+  if ((res_ids_dev == nullptr) != (res_dists_dev == nullptr))
+    return fail(ix, ETALE_EINVAL, "serve: result ids and distances go together");
+  if (ix->cfg.metric == ETALE_METRIC_IP_F32 && ix->qtrav != ETALE_TRAV_NATIVE && (uint64_t)ix->qrerank * c.k > 64)
+    return fail(ix, ETALE_EINVAL, "serve: rerank_mult * k must not exceed 64");
   for (uint64_t i = 0; i < n; ++i) {
     if (reqs[i].kind > ETALE_REQ_DELETE || (i && reqs[i].t_arrive < reqs[i - 1].t_arrive))
       return fail(ix, ETALE_EINVAL, "serve: bad kind or arrival order");
     if (reqs[i].kind != ETALE_REQ_DELETE && (!rows_dev || reqs[i].arg >= n_rows))
       return fail(ix, ETALE_EINVAL, "serve: row out of range");
   }
-  if (etale_status st = refresh_mirror(ix)) return st;
-  const uint32_t T = c.max_tick, k = c.k;
-  const uint64_t row_bytes = (uint64_t)ix->cfg.dim * (ix->cfg.metric == ETALE_METRIC_L2_U8 ? 1 : 4);
-  const uint64_t slab_bytes = 8ull * ix->cfg.R;
+  unsigned long long h0[C_NCOUNTERS];
+  if (etale_status st = read_counters(ix, h0)) return st;
+  const uint32_t T = c.max_tick, k = c.k, R = ix->cfg.R;
+  const uint32_t ns = ix->cfg.n_entry, dim = ix->cfg.dim;
+  const uint64_t row_bytes = (uint64_t)dim * (ix->cfg.metric == ETALE_METRIC_L2_U8 ? 1 : 4);
+  const uint64_t slab_bytes = 8ull * R;
   const uint64_t fixed = ix->bytes - ix->cfg.id_capacity * row_bytes - ix->cfg.slab_capacity * slab_bytes;
-  // tick buffers: device, and pinned host staging (reused after each tick's synchronization)
-  uint32_t *d_idx = nullptr, *d_qids = nullptr, *d_qd = nullptr, *d_counts = nullptr, *d_ids = nullptr;
-  uint8_t *d_vecs = nullptr, *d_q = nullptr, *d_dst = nullptr;
-  int32_t* d_status = nullptr;
-  uint32_t* h_idx = nullptr;
-  int32_t* h_status = nullptr;
-  unsigned long long* h_ctr = nullptr;
+
+  // ---- resources: the update stream, the snapshot, the search scratch, two tick slots
   std::vector<void*> dev_bufs, host_bufs;
-  auto dev = [&](auto** p, size_t bytes) {
-    hipError_t e = hipMalloc((void**)p, bytes ? bytes : 16);
-    if (e == hipSuccess) dev_bufs.push_back(*p);
-    return e;
-  };
-  auto host = [&](auto** p, size_t bytes) {
-    hipError_t e = hipHostMalloc((void**)p, bytes, hipHostMallocDefault);
-    if (e == hipSuccess) host_bufs.push_back(*p);
-    return e;
-  };
+  std::vector<hipEvent_t> events;
+  hipStream_t U = nullptr;
   auto release = [&]() {
+    if (U) (void)hipStreamSynchronize(U);
+    (void)hipStreamSynchronize(ix->stream);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (U) (void)hipStreamDestroy(U);
     for (void* p : dev_bufs) (void)hipFree(p);
     for (void* p : host_bufs) (void)hipHostFree(p);
   };
-  hipError_t e = dev(&d_idx, (size_t)3 * T * 4);
-  if (e == hipSuccess) e = dev(&d_vecs, (size_t)T * row_bytes);
-  if (e == hipSuccess) e = dev(&d_q, (size_t)T * row_bytes);
-  if (e == hipSuccess) e = dev(&d_qids, (size_t)T * k * 4);
-  if (e == hipSuccess) e = dev(&d_qd, (size_t)T * k * 4);
-  if (e == hipSuccess) e = dev(&d_counts, 16);
-  if (e == hipSuccess) e = dev(&d_ids, (size_t)T * 4);
-  if (e == hipSuccess) e = dev(&d_dst, (size_t)T);
-  if (e == hipSuccess) e = dev(&d_status, 16);
-  if (e == hipSuccess) e = host(&h_idx, (size_t)3 * T * 4 + 16);
-  if (e == hipSuccess) e = host(&h_status, 16);
-  if (e == hipSuccess) e = host(&h_ctr, 16);
+  hipError_t e = hipStreamCreateWithFlags(&U, hipStreamNonBlocking);  // default priority
+  auto dev = [&](auto** p, size_t bytes) {
+    if (e != hipSuccess) return;
+    e = hipMalloc((void**)p, bytes ? bytes : 16);
+    if (e == hipSuccess) dev_bufs.push_back(*p);
+  };
+  auto host = [&](auto** p, size_t bytes) {
+    if (e != hipSuccess) return;
+    e = hipHostMalloc((void**)p, bytes ? bytes : 16, hipHostMallocDefault);
+    if (e == hipSuccess) host_bufs.push_back(*p);
+  };
+  auto event = [&](hipEvent_t* ev) {
+    if (e != hipSuccess) return;
+    e = hipEventCreate(ev);
+    if (e == hipSuccess) events.push_back(*ev);
+  };
+  // the snapshot a tick's searches read: reference words, counters, entry set and its rows
+  unsigned long long* snap_refs = nullptr;
+  unsigned long long* snap_ctr = nullptr;
+  uint32_t* snap_entries = nullptr;
+  uint8_t* snap_ent_x = nullptr;
+  int32_t* snap_ent_norm = nullptr;
+  const uint64_t norm_words = ((uint64_t)ns + 63) / 64 * 64;
+  dev(&snap_refs, ix->cfg.id_capacity * 8);
+  dev(&snap_ctr, C_NCOUNTERS * 8);
+  dev(&snap_entries, (uint64_t)ns * 4);
+  if (ix->ent_x) {
+    dev(&snap_ent_x, (uint64_t)ns * dim);
+    dev(&snap_ent_norm, norm_words * 4);
+  }
+  // start-set scratch of the searches, apart from the library's own (which the
+  // concurrent round's insert searches use)
+  ScanScratch ss;
+  ss.chunk = T;
+  dev(&ss.keys, (uint64_t)T * c.L * 8);
+  dev(&ss.n, (uint64_t)T * 4);
+  dev(&ss.dist, (uint64_t)T * ns * 4);
+  dev(&ss.gmin, (uint64_t)T * (ns / 32 + 8) * 4);
+  dev(&ss.bound, (uint64_t)T * 4);
+  dev(&ss.ncand, (uint64_t)T * 64 * 4);
+  dev(&ss.cand, (uint64_t)T * SCAN_KEYS_Q * 8);
+  TickSlot slot[2];
+  for (TickSlot& t : slot) {
+    dev(&t.d_idx, (size_t)3 * T * 4);
+    dev(&t.d_vecs, (size_t)T * row_bytes);
+    dev(&t.d_q, (size_t)T * row_bytes);
+    dev(&t.d_qids, (size_t)T * k * 4);
+    dev(&t.d_qd, (size_t)T * k * 4);
+    dev(&t.d_counts, 16);
+    dev(&t.d_ids, (size_t)T * 4);
+    dev(&t.d_pos, (size_t)T * 4);
+    dev(&t.d_dst, (size_t)T);
+    dev(&t.d_status, 16);
+    host(&t.h_idx, (size_t)(3 * T + 4) * 4);
+    host(&t.h_pos, (size_t)T * 4);
+    host(&t.h_status, 16);
+    host(&t.h_ctr, 16);
+    event(&t.e_snap);
+    event(&t.e_srch);
+    event(&t.e_upd);
+    t.members.reserve(T);
+  }
+  hipEvent_t e_ref = nullptr;
+  event(&e_ref);
   if (e != hipSuccess) {
     release();
-    return fail(ix, ETALE_ENOMEM, "serve: tick buffers");
+    return fail(ix, ETALE_ENOMEM, std::string("serve: resources: ") + hipGetErrorString(e));
   }
-  uint32_t* h_del = h_idx;
-  uint32_t* h_ins = h_idx + T;
-  uint32_t* h_qr = h_idx + 2 * T;
-  uint32_t* h_cnt = h_idx + 3 * T;
-  etale_serve_stats S{};
-  std::vector<std::string> keys_before;
+  Index view = ix->dev;  // the searches' state: the snapshot, and its own counters
+  view.refs = snap_refs;
+  view.ctr = snap_ctr;
+  view.entries = snap_entries;
+  view.ent_x = snap_ent_x;
+  view.ent_norm = snap_ent_norm;
+
+  // ---- the loop
+  using clk = std::chrono::steady_clock;
+  const hipStream_t S = ix->stream;
+  const hipStream_t user_stream = ix->stream;
+  const bool user_timing = ix->timing;
+  ix->timing = false;
+  e = hipStreamSynchronize(S);
+  if (e == hipSuccess) e = hipEventRecord(e_ref, S);
+  if (e == hipSuccess) e = hipEventSynchronize(e_ref);
+  const auto t0 = clk::now();  // the wall time of e_ref
+  auto wall = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
+  const double origin = n ? reqs[0].t_arrive : 0.0;  // the trace's clock at the loop's start
+  std::vector<std::string> keys_before;  // rounds captured here name this call's buffers
   for (auto& g : ix->graphs) keys_before.push_back(g.first);
-  uint64_t next_id = ix->next_id;
-  uint64_t resident = 0;
-  {
-    unsigned long long h[C_NCOUNTERS];
-    if (etale_status st = read_counters(ix, h)) {
-      release();
-      return st;
-    }
-    resident = ix->cfg.slab_capacity - h[C_FREE_TOP] - h[C_RETIRED_TOP];
-  }
-  S.peak_resident_slabs = resident;
-  std::vector<uint64_t> members;  // request indices of the current tick, in admission order
-  members.reserve(T);
-  double t = n ? reqs[0].t_arrive : 0.0;
-  uint64_t i = 0;
+  etale_serve_stats Sx{};
+  uint64_t next_id = h0[C_NEXT_ID];
+  uint64_t free_known = h0[C_FREE_TOP];
+  uint64_t resident = ix->cfg.slab_capacity - h0[C_FREE_TOP] - h0[C_RETIRED_TOP];
+  Sx.peak_resident_slabs = resident;
+  std::vector<uint64_t> pending;  // arrived, not yet admitted, in arrival order
+  pending.reserve(4 * (size_t)T);
+  uint64_t arrived = 0, tick_no = 0, done_reqs = 0;
+  int oldest = 0;  // slot of the oldest tick in flight
+  double last_done = 0.0;
   etale_status result = ETALE_OK;
-  while (i < n) {
-    if (reqs[i].t_arrive > t) t = reqs[i].t_arrive;  // idle until the next arrival
-    const auto w0 = std::chrono::steady_clock::now();
-    uint32_t nd = 0, ni = 0, nq = 0;
-    members.clear();
-    uint64_t j = i;
-    uint64_t used = next_id * row_bytes + resident * slab_bytes + fixed;
-    for (; j < n && reqs[j].t_arrive <= t && members.size() < T; ++j) {
-      const etale_request& r = reqs[j];
-      if (r.kind == ETALE_REQ_DELETE) {
-        h_del[nd++] = r.arg;
-      } else if (r.kind == ETALE_REQ_INSERT) {
-        if (c.hbm_budget_bytes && used + row_bytes + slab_bytes > c.hbm_budget_bytes) {
-          if (latency_ms) latency_ms[j] = -1.0f;
-          ++S.rejected_inserts;
-          continue;
-        }
-        used += row_bytes + slab_bytes;
-        h_ins[ni++] = r.arg;
-      } else {
-        h_qr[nq++] = r.arg;
-      }
-      members.push_back(j);
+  if (latency_ms)
+    for (uint64_t i = 0; i < n; ++i) latency_ms[i] = -1.0f;
+  if (tick_host)
+    for (uint64_t i = 0; i < n; ++i) tick_host[i] = 0xFFFFFFFFu;
+
+  // the tick in slot t has passed its events: finish it on the host
+  auto finish = [&](TickSlot& t) -> etale_status {
+    if (!t.busy) return ETALE_OK;
+    hipError_t er = hipEventSynchronize(t.e_upd);
+    if (er == hipSuccess) er = hipEventSynchronize(t.e_srch);
+    float ms_s = 0.f, ms_u = 0.f, ms_0 = 0.f;
+    if (er == hipSuccess) er = hipEventElapsedTime(&ms_s, e_ref, t.e_srch);
+    if (er == hipSuccess) er = hipEventElapsedTime(&ms_u, e_ref, t.e_upd);
+    if (er == hipSuccess) er = hipEventElapsedTime(&ms_0, e_ref, t.e_snap);
+    if (er != hipSuccess) return fail(ix, ETALE_EDEVICE, std::string("serve: ") + hipGetErrorString(er));
+    const bool ok = t.h_status[0] == 0;
+    const double done_s = ms_s * 1e-3, done_u = ms_u * 1e-3;
+    for (uint64_t m : t.members) {
+      const double done = reqs[m].kind == ETALE_REQ_SEARCH ? done_s : done_u;
+      const double start = c.realtime ? reqs[m].t_arrive - origin : t.t_enqueue;
+      if (latency_ms) latency_ms[m] = ok ? (float)((done - start) * 1e3) : -1.0f;
     }
-    h_cnt[0] = nd;
-    h_cnt[1] = ni;
-    h_cnt[2] = nq;
-    const bool reclaim = c.reclaim_every && (S.ticks + 1) % c.reclaim_every == 0;
-    hipStream_t s = ix->stream;
-    e = hipMemcpyAsync(d_idx, h_idx, (size_t)3 * T * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_counts, h_cnt, 12, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_gather_rows(rows_dev, d_idx + T, ni, (uint32_t)row_bytes, d_vecs, s);
-    if (e == hipSuccess) e = launch_gather_rows(rows_dev, d_idx + 2 * T, nq, (uint32_t)row_bytes, d_q, s);
-    if (e != hipSuccess) {
-      result = fail(ix, ETALE_EDEVICE, std::string("serve: ") + hipGetErrorString(e));
-      break;
-    }
-    etale_round_desc d{};
-    d.del_ids = d_idx;
-    d.del_status = d_dst;
-    d.ins_vecs = d_vecs;
-    d.ins_ids = d_ids;
-    d.queries = d_q;
-    d.q_ids = d_qids;
-    d.q_dists = d_qd;
-    d.k = c.k;
-    d.L = c.L;
-    d.counts = d_counts;
-    d.status = d_status;
-    d.reclaim = reclaim ? 1 : 0;
-    d.graph = c.graph;
-    d.max_del = c.graph ? size_bucket(nd, 256, T) : nd;
-    d.max_ins = c.graph ? size_bucket(ni, 256, T) : ni;
-    d.max_q = c.graph ? size_bucket(nq, 64, T) : nq;
-    if (etale_status st = etale_round(ix, &d)) {
-      result = st;
-      break;
-    }
-    e = hipMemcpyAsync(h_status, d_status, 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, ix->ctr + C_FREE_TOP, 16, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      result = fail(ix, ETALE_EDEVICE, std::string("serve: ") + hipGetErrorString(e));
-      break;
-    }
-    const double dur = std::chrono::duration<double>(std::chrono::steady_clock::now() - w0).count();
-    const double t_end = t + dur;
-    const bool ok = h_status[0] == 0;
-    for (uint64_t m : members)
-      if (latency_ms) latency_ms[m] = ok ? (float)((t_end - reqs[m].t_arrive) * 1e3) : -1.0f;
     if (ok) {
-      S.searches += nq;
-      S.inserts += ni;
-      S.deletes += nd;
-      next_id += ni;
-      if (reclaim) S.reclaims += h_status[1] == 0;
+      Sx.searches += t.nq;
+      Sx.inserts += t.ni;
+      Sx.deletes += t.nd;
+      if (t.reclaim) Sx.reclaims += t.h_status[1] == 0;
     } else {
-      ++S.failed_ticks;
+      ++Sx.failed_ticks;
     }
-    resident = ix->cfg.slab_capacity - h_ctr[0] - h_ctr[1];
-    if (resident > S.peak_resident_slabs) S.peak_resident_slabs = resident;
-    ++S.ticks;
-    S.busy_seconds += dur;
-    t = t_end;
-    i = j;
+    free_known = t.h_ctr[0];
+    resident = ix->cfg.slab_capacity - t.h_ctr[0] - t.h_ctr[1];
+    if (resident > Sx.peak_resident_slabs) Sx.peak_resident_slabs = resident;
+    Sx.device_busy_seconds += std::max(done_s, done_u) - ms_0 * 1e-3;
+    last_done = std::max(last_done, std::max(done_s, done_u));
+    done_reqs += t.members.size();
+    t.busy = false;
+    return ETALE_OK;
+  };
+
+  while (result == ETALE_OK) {
+    // arrivals
+    if (c.realtime) {
+      const double now = wall() + origin;
+      while (arrived < n && reqs[arrived].t_arrive <= now) pending.push_back(arrived++);
+    } else {
+      while (arrived < n && pending.size() < 4 * (size_t)T) pending.push_back(arrived++);
+    }
+    TickSlot& free_slot = slot[oldest].busy ? slot[oldest ^ 1] : slot[oldest];
+    const bool have_slot = !free_slot.busy;
+    if (!have_slot || pending.empty()) {
+      const bool any_busy = slot[0].busy || slot[1].busy;
+      if (!have_slot || (pending.empty() && arrived == n && any_busy)) {
+        // wait for the oldest tick in flight
+        if (etale_status st = finish(slot[oldest])) {
+          result = st;
+          break;
+        }
+        oldest ^= 1;
+        continue;
+      }
+      if (arrived == n && !any_busy) break;  // drained
+      if (c.realtime && arrived < n) {
+        // nothing pending: wait for the next arrival or a finished tick
+        const double dt = reqs[arrived].t_arrive - origin - wall();
+        if (any_busy && hipEventQuery(slot[oldest].e_upd) == hipSuccess && hipEventQuery(slot[oldest].e_srch) == hipSuccess) {
+          if (etale_status st = finish(slot[oldest])) {
+            result = st;
+            break;
+          }
+          oldest ^= 1;
+        } else if (dt > 2e-4) {
+          std::this_thread::sleep_for(std::chrono::microseconds(100));
+        }
+      }
+      continue;
+    }
+    // ---- form a tick from the pending requests, in arrival order
+    TickSlot& t = free_slot;
+    t.members.clear();
+    uint32_t nd = 0, ni = 0, nq = 0;
+    uint64_t inflight = 0;
+    for (const TickSlot& o : slot)
+      if (o.busy) inflight += o.demand;
+    const uint64_t avail = free_known > inflight ? free_known - inflight : 0;
+    uint64_t used = next_id * row_bytes + (resident + inflight) * slab_bytes + fixed;
+    size_t keep = 0;
+    for (size_t pi = 0; pi < pending.size(); ++pi) {
+      const uint64_t j = pending[pi];
+      bool admit = t.members.size() < T, reject = false;
+      if (admit && reqs[j].kind == ETALE_REQ_INSERT) {
+        // ids are never reused and rows never freed: past the id space or the
+        // budget an insert can never be admitted
+        if ((c.hbm_budget_bytes && used + row_bytes + slab_bytes > c.hbm_budget_bytes) ||
+            next_id + ni + 1 > ix->cfg.id_capacity)
+          reject = true;
+        else
+          admit = (uint64_t)(ni + 1) * (R + 2) + (uint64_t)nd * R <= avail;
+      } else if (admit && reqs[j].kind == ETALE_REQ_DELETE) {
+        admit = ix->cfg.tombstone_only || (uint64_t)ni * (R + 2) + (uint64_t)(nd + 1) * R <= avail;
+      }
+      if (reject) {
+        ++Sx.rejected_inserts;
+        ++done_reqs;
+        continue;
+      }
+      if (!admit) {
+        if (t.members.size() < T && reqs[j].kind != ETALE_REQ_SEARCH) ++Sx.deferred;
+        pending[keep++] = j;
+        continue;
+      }
+      if (reqs[j].kind == ETALE_REQ_DELETE) {
+        t.h_idx[nd++] = reqs[j].arg;
+      } else if (reqs[j].kind == ETALE_REQ_INSERT) {
+        t.h_idx[T + ni++] = reqs[j].arg;
+        used += row_bytes + slab_bytes;
+      } else {
+        t.h_pos[nq] = (uint32_t)j;
+        t.h_idx[2 * T + nq++] = reqs[j].arg;
+      }
+      t.members.push_back(j);
+      if (tick_host) tick_host[j] = (uint32_t)tick_no;
+    }
+    pending.resize(keep);
+    if (t.members.empty() && pending.empty()) continue;  // every pending request was rejected
+    if (t.members.empty()) {
+      // everything pending waits for slabs: let the oldest tick finish first
+      if (slot[oldest].busy) {
+        if (etale_status st = finish(slot[oldest])) {
+          result = st;
+          break;
+        }
+        oldest ^= 1;
+        continue;
+      }
+      result = fail(ix, ETALE_EPOOL, "serve: pending updates cannot be covered by the free slab pool");
+      break;
+    }
+    t.nd = nd;
+    t.ni = ni;
+    t.nq = nq;
+    t.h_idx[3 * T] = nd;  // the round's counts: its deletes and inserts, no queries
+    t.h_idx[3 * T + 1] = ni;
+    t.h_idx[3 * T + 2] = 0;
+    t.demand = ix->cfg.tombstone_only ? (uint64_t)ni * (R + 2) : (uint64_t)ni * (R + 2) + (uint64_t)nd * R;
+    t.reclaim = c.reclaim_every && (tick_no + 1) % c.reclaim_every == 0 && !ix->cfg.tombstone_only;
+    t.tick = tick_no++;
+    t.t_enqueue = wall();
+    t.busy = true;
+    // search stream: inputs, then (after the previous tick's round) the snapshot, then the searches
+    const TickSlot& prev = slot[&t == &slot[0] ? 1 : 0];
+    e = hipMemcpyAsync(t.d_idx, t.h_idx, (size_t)3 * T * 4, hipMemcpyHostToDevice, S);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.d_counts, t.h_idx + 3 * T, 12, hipMemcpyHostToDevice, S);
+    if (e == hipSuccess && nq) e = hipMemcpyAsync(t.d_pos, t.h_pos, (size_t)nq * 4, hipMemcpyHostToDevice, S);
+    if (e == hipSuccess) e = launch_gather_rows(rows_dev, t.d_idx + T, ni, (uint32_t)row_bytes, t.d_vecs, S);
+    if (e == hipSuccess) e = launch_gather_rows(rows_dev, t.d_idx + 2 * T, nq, (uint32_t)row_bytes, t.d_q, S);
+    if (e == hipSuccess && prev.busy) e = hipStreamWaitEvent(S, prev.e_upd, 0);
+    if (e == hipSuccess && next_id) e = hipMemcpyAsync(snap_refs, ix->refs, next_id * 8, hipMemcpyDeviceToDevice, S);
+    if (e == hipSuccess) e = hipMemcpyAsync(snap_ctr, ix->ctr, C_NCOUNTERS * 8, hipMemcpyDeviceToDevice, S);
+    if (e == hipSuccess) e = hipMemcpyAsync(snap_entries, ix->entries, (size_t)ns * 4, hipMemcpyDeviceToDevice, S);
+    if (e == hipSuccess && snap_ent_x) e = hipMemcpyAsync(snap_ent_x, ix->ent_x, (size_t)ns * dim, hipMemcpyDeviceToDevice, S);
+    if (e == hipSuccess && snap_ent_x)
+      e = hipMemcpyAsync(snap_ent_norm, ix->ent_norm, norm_words * 4, hipMemcpyDeviceToDevice, S);
+    if (e == hipSuccess) e = hipEventRecord(t.e_snap, S);
+    if (e != hipSuccess) {
+      result = fail(ix, ETALE_EDEVICE, std::string("serve: ") + hipGetErrorString(e));
+      break;
+    }
+    if (nq) {
+      if (etale_status st = run_searches(ix, MODE_QUERY, t.d_q, nq, k, c.L, ix->cfg.visit_mult * c.L, t.d_qids,
+                                         t.d_qd, nullptr, Dyn{}, false, &ss, &view, S)) {
+        result = st;
+        break;
+      }
+      if (res_ids_dev)
+        e = launch_scatter_results(t.d_qids, t.d_qd, t.d_pos, nq, k, res_ids_dev,
+                                   reinterpret_cast<uint32_t*>(res_dists_dev), S);
+    }
+    if (e == hipSuccess) e = hipEventRecord(t.e_srch, S);
+    // update stream: after the snapshot, the tick's deletes and inserts as one round
+    if (e == hipSuccess) e = hipStreamWaitEvent(U, t.e_snap, 0);
+    if (e != hipSuccess) {
+      result = fail(ix, ETALE_EDEVICE, std::string("serve: ") + hipGetErrorString(e));
+      break;
+    }
+    if (nd || ni || t.reclaim) {
+      etale_round_desc d{};
+      d.del_ids = t.d_idx;
+      d.del_status = t.d_dst;
+      d.ins_vecs = t.d_vecs;
+      d.ins_ids = t.d_ids;
+      d.status = t.d_status;
+      d.reclaim = t.reclaim ? 1 : 0;
+      d.graph = c.graph;
+      d.counts = c.graph ? t.d_counts : nullptr;
+      d.max_del = c.graph ? size_bucket(nd, 256, T) : nd;
+      d.max_ins = c.graph ? size_bucket(ni, 256, T) : ni;
+      ix->stream = U;
+      const etale_status st = etale_round(ix, &d);
+      ix->stream = user_stream;
+      if (st) {
+        result = st;
+        break;
+      }
+    } else {
+      t.h_status[0] = t.h_status[1] = 0;
+      e = hipMemsetAsync(t.d_status, 0, 8, U);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(t.h_status, t.d_status, 8, hipMemcpyDeviceToHost, U);
+    if (e == hipSuccess) e = hipMemcpyAsync(t.h_ctr, ix->ctr + C_FREE_TOP, 16, hipMemcpyDeviceToHost, U);
+    if (e == hipSuccess) e = hipEventRecord(t.e_upd, U);
+    if (e != hipSuccess) {
+      result = fail(ix, ETALE_EDEVICE, std::string("serve: ") + hipGetErrorString(e));
+      break;
+    }
+    next_id += ni;
+    ++Sx.ticks;
   }
-  S.final_resident_slabs = resident;
-  S.ids_handed_out = next_id;
-  S.trace_seconds = n ? t - reqs[0].t_arrive : 0.0;
-  S.graphs = ix->graphs.size() - keys_before.size();
-  // the rounds captured here name this call's buffers: drop them with the buffers
+  // finish whatever is still in flight (also after an error, so no buffer is freed under a kernel)
+  for (int r = 0; r < 2; ++r) {
+    TickSlot& t = slot[oldest];
+    if (t.busy) {
+      const etale_status st = finish(t);
+      if (!result) result = st;
+    }
+    oldest ^= 1;
+  }
+  ix->timing = user_timing;
+  ix->stream = user_stream;
+  Sx.final_resident_slabs = resident;
+  Sx.ids_handed_out = next_id;
+  Sx.wall_seconds = last_done;
+  release();
   for (auto it = ix->graphs.begin(); it != ix->graphs.end();) {
     if (std::find(keys_before.begin(), keys_before.end(), it->first) == keys_before.end()) {
+      ++Sx.graphs;
       (void)hipGraphExecDestroy(it->second);
       it = ix->graphs.erase(it);
     } else {
       ++it;
     }
   }
-  release();
   if (result) return result;
-  ix->next_id = next_id;
-  *out = S;
+  if (etale_status st = refresh_mirror(ix)) return st;
+  *out = Sx;
   return ETALE_OK;
 }
 
@@ -1237,6 +1514,17 @@ etale_status etale_set_search_knobs(etale_t ix, uint32_t waves_per_block, uint32
   if (search_lds_per_wave(SCAN_L_MAX, vt_slots, ix->cfg.W) > 65536u) return fail(ix, ETALE_EINVAL, "search knobs: LDS");
   ix->cfg.waves_per_block = waves_per_block;
   ix->cfg.vt_slots = vt_slots;
+  return ETALE_OK;
+}
+
+etale_status etale_set_search_lanes(etale_t ix, uint32_t lanes_per_row) {
+  CHECK_HANDLE();
+  const bool ok = lanes_per_row == 0 ||
+                  (ix->cfg.metric == ETALE_METRIC_L2_U8 && (lanes_per_row * 16u == ix->cfg.dim ||
+                                                           (lanes_per_row * 32u == ix->cfg.dim &&
+                                                            (ix->cfg.dim == 128 || ix->cfg.dim == 256))));
+  if (!ok) return fail(ix, ETALE_EINVAL, "search lanes: 0, dim/16, or dim/32 for 128- and 256-byte rows");
+  ix->row_lanes = lanes_per_row * 16u == ix->cfg.dim ? 0u : lanes_per_row;
   return ETALE_OK;
 }
 
@@ -1252,12 +1540,13 @@ etale_status etale_autotune(etale_t ix, const void* q_dev, uint64_t nq, uint32_t
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const uint32_t wpb0 = ix->cfg.waves_per_block, vt0 = ix->cfg.vt_slots;
+  const uint32_t wpb0 = ix->cfg.waves_per_block, vt0 = ix->cfg.vt_slots, rl0 = ix->row_lanes;
   const bool timing = ix->timing;
   ix->timing = false;
-  auto time_one = [&](uint32_t wpb, uint32_t vt, float* ms) -> etale_status {
+  auto time_one = [&](uint32_t wpb, uint32_t vt, uint32_t rl, float* ms) -> etale_status {
     ix->cfg.waves_per_block = wpb;
     ix->cfg.vt_slots = vt;
+    ix->row_lanes = rl;
     const uint32_t vcap = ix->cfg.visit_mult * L;
     if (etale_status st = run_searches(ix, MODE_QUERY, (const uint8_t*)q_dev, nq, k, L, vcap, ids, d, nullptr, Dyn{}))
       return st;  // warm-up
@@ -1274,25 +1563,30 @@ etale_status etale_autotune(etale_t ix, const void* q_dev, uint64_t nq, uint32_t
   };
   etale_status st = ETALE_OK;
   float best = 0.f, base = 0.f;
-  uint32_t bw = wpb0, bv = vt0;
-  st = time_one(wpb0, vt0, &base);
+  uint32_t bw = wpb0, bv = vt0, br = rl0;
+  st = time_one(wpb0, vt0, rl0, &base);
   best = base;
   const uint32_t waves[] = {1, 2, 4};
   const uint32_t slots[] = {256, 512, 1024, 2048, 4096};
-  for (uint32_t w : waves)
-    for (uint32_t v : slots) {
-      if (st) break;
-      if (search_lds_per_wave(L, v, ix->cfg.W) > 65536u) continue;
-      float ms = 0.f;
-      st = time_one(w, v, &ms);
-      if (!st && ms < best) {
-        best = ms;
-        bw = w;
-        bv = v;
+  std::vector<uint32_t> lanes = {0};
+  if (ix->cfg.metric == ETALE_METRIC_L2_U8 && (ix->cfg.dim == 128 || ix->cfg.dim == 256)) lanes.push_back(ix->cfg.dim / 32);
+  for (uint32_t rl : lanes)
+    for (uint32_t w : waves)
+      for (uint32_t v : slots) {
+        if (st) break;
+        if (search_lds_per_wave(L, v, ix->cfg.W) > 65536u) continue;
+        float ms = 0.f;
+        st = time_one(w, v, rl, &ms);
+        if (!st && ms < best) {
+          best = ms;
+          bw = w;
+          bv = v;
+          br = rl;
+        }
       }
-    }
   ix->cfg.waves_per_block = st ? wpb0 : bw;
   ix->cfg.vt_slots = st ? vt0 : bv;
+  ix->row_lanes = st ? rl0 : br;
   ix->timing = timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1301,6 +1595,7 @@ etale_status etale_autotune(etale_t ix, const void* q_dev, uint64_t nq, uint32_t
   if (st) return st;
   out->waves_per_block = bw;
   out->vt_slots = bv;
+  out->row_lanes = br ? br : (ix->cfg.metric == ETALE_METRIC_L2_U8 ? ix->cfg.dim / 16 : 0);
   out->ms = best;
   out->ms_default = base;
   return ETALE_OK;
@@ -1329,6 +1624,59 @@ etale_status etale_get_search_timing(etale_t ix, float* ms_host, uint64_t cap, u
   *launches = ix->ev_used.size();
   ix->ev_used.clear();
   return ETALE_OK;
+}
+
+etale_status etale_set_concurrent(etale_t ix, int32_t enable, void* search_stream) {
+  CHECK_HANDLE();
+  const bool on = enable != 0;
+  if (on == ix->concurrent) {
+    if (on) ix->search_stream = reinterpret_cast<hipStream_t>(search_stream);
+    return ETALE_OK;
+  }
+  if (ix->cfg.tombstone_only) return fail(ix, ETALE_EINVAL, "concurrent mode: not with tombstone_only");
+  if (on) {
+    if (!search_stream || search_stream == (void*)ix->stream)
+      return fail(ix, ETALE_EINVAL, "concurrent mode: searches need a stream of their own");
+    HIP_TRY(hipStreamSynchronize(ix->stream));
+    if (ix->conc_bufs.empty()) {
+      const uint64_t C = ix->scan_chunk;
+      auto al = [&](auto** p, uint64_t bytes) -> hipError_t {
+        void* q = nullptr;
+        const hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+        if (e == hipSuccess) {
+          ix->conc_bufs.push_back(q);
+          *p = reinterpret_cast<std::remove_reference_t<decltype(*p)>>(q);
+        }
+        return e;
+      };
+      HIP_TRY(al(&ix->cs.keys, C * SCAN_L_MAX * 8));
+      HIP_TRY(al(&ix->cs.n, C * 4));
+      HIP_TRY(al(&ix->cs.dist, ix->dist_cap * 4));
+      HIP_TRY(al(&ix->cs.gmin, ix->gmin_cap * 4));
+      HIP_TRY(al(&ix->cs.bound, C * 4));
+      HIP_TRY(al(&ix->cs.ncand, C * 64 * 4));
+      HIP_TRY(al(&ix->cs.cand, C * SCAN_KEYS_Q * 8));
+    }
+    ix->search_stream = reinterpret_cast<hipStream_t>(search_stream);
+    ix->dev.fence = 1;
+    ix->dev.concurrent = 1;
+    ix->concurrent = true;
+    return ETALE_OK;
+  }
+  // leaving: both streams drain, then the slabs retired meanwhile rejoin the
+  // free pool and the entry set catches up with the deletes and inserts
+  HIP_TRY(hipStreamSynchronize(ix->search_stream));
+  HIP_TRY(hipStreamSynchronize(ix->stream));
+  ix->concurrent = false;
+  ix->dev.fence = 0;
+  ix->dev.concurrent = 0;
+  ix->search_stream = nullptr;
+  HIP_TRY(launch_recycle(ix->dev, ix->stream));
+  Dyn de;
+  de.first_ctr = C_NEXT_ID;
+  HIP_TRY(launch_refresh_entries(ix->dev, 0, ix->cfg.n_entry, de, ix->stream));
+  HIP_TRY(hipStreamSynchronize(ix->stream));
+  return refresh_mirror(ix);
 }
 
 etale_status etale_sync(etale_t ix) {

@@ -5,6 +5,11 @@
 //   refs   : one 64-bit reference word per id (Definition 1):
 //              bit 63 deletion flag, bits 62..56 degree, bits 31..0 slab id,
 //              slab id 0xFFFFFFFF = no slab. Unborn ids hold <0,0,none>.
+//              Bits 55..32 hold the squared norm of the id's uint8 row when
+//              dim <= 256 (at most 256 * 255^2 < 2^24), written when the row
+//              is stored and carried unchanged by every later change of the
+//              word, so a distance needs no second pass over the row; zero
+//              for wider or float rows.
 //   slabs  : pool of P slabs of 2R words each: R neighbor ids, then R
 //            distances (structure of arrays, so a search reads only the ids).
 //   free / retired stacks of slab ids with one counter each (Section 3.3).
@@ -23,7 +28,12 @@ constexpr uint64_t REF_UNBORN = 0x00000000FFFFFFFFull;
 __host__ __device__ inline uint64_t make_ref(uint32_t del, uint32_t deg, uint32_t slab) {
   return ((uint64_t)(del & 1u) << 63) | ((uint64_t)(deg & 0x7Fu) << 56) | (uint64_t)slab;
 }
+constexpr uint64_t REF_NORM_MASK = 0x00FFFFFF00000000ull;
 __host__ __device__ inline uint32_t ref_del(uint64_t r) { return (uint32_t)(r >> 63); }
+__host__ __device__ inline uint32_t ref_norm(uint64_t r) { return (uint32_t)(r >> 32) & 0xFFFFFFu; }
+// uint8 rows of at most 256 bytes (G = dim / 16 <= 16 lanes) keep their norm in the word
+template <int G>
+constexpr bool norm_in_ref() { return G <= 16; }
 __host__ __device__ inline uint32_t ref_deg(uint64_t r) { return (uint32_t)(r >> 56) & 0x7Fu; }
 __host__ __device__ inline uint32_t ref_slab(uint64_t r) { return (uint32_t)r; }
 
@@ -76,6 +86,7 @@ struct Index {
   uint32_t a2, b2;  // alpha = a/b, applied squared: a^2 * D1 <= b^2 * D2
   uint32_t publish_attempts;
   uint32_t fence;   // 1: a release fence orders a slab's contents before its reference (concurrent readers)
+  uint32_t concurrent;  // 1: searches may run alongside writers: slab ids are read with agent-coherent loads
   uint32_t prune_cap;
   int32_t metric;   // 0: uint8 squared L2, 1: FP32 inner product (d = 1 - <a,b>)
   int32_t trav;     // traversal copy for the float metric: 0 FP32, 1 bf16, 2 FP8 e4m3 + scale
@@ -261,8 +272,11 @@ __device__ inline uint32_t vt_insert(uint32_t* vt, uint32_t mask, uint32_t id) {
 #pragma unroll 1
     for (int tries = 0; tries < 4; ++tries) {
       const uint4 w = *reinterpret_cast<const uint4*>(slot);
-      if (w.x == id || w.y == id || w.z == id || w.w == id) return VT_SEEN;
-      const int e = w.x == NONE ? 0 : w.y == NONE ? 1 : w.z == NONE ? 2 : w.w == NONE ? 3 : -1;
+      // one of the four equals id exactly when the smallest XOR is zero
+      if (min(min(w.x ^ id, w.y ^ id), min(w.z ^ id, w.w ^ id)) == 0u) return VT_SEEN;
+      // slots fill in order (a miss always takes the first empty one), so the
+      // first empty slot is the count of filled ones
+      const int e = w.y == NONE ? (w.x == NONE ? 0 : 1) : (w.w == NONE ? (w.z == NONE ? 2 : 3) : -1);
       if (e < 0) break;  // full: the next bucket
       const uint32_t prev = atomicCAS(&slot[e], NONE, id);
       if (prev == NONE) return VT_NEW;
@@ -382,10 +396,13 @@ __device__ inline int list_first_open(const CandList& cl, int from = 0) {
 // G lanes share one vector (16 bytes each); 64/G vectors per pass. qf is this
 // lane's 16-byte chunk of the query, qq the query's squared norm.
 // Writes ck[i] = (D, id) for ids[0..cnt).
-template <int G>
+// REFS: read each row's reference word with it (for cr, and for the row's
+// norm where the word carries it); without, the norm comes from the row
+template <int G, bool REFS = true>
 __device__ inline void dist_batch_u8(const Index& ix, uint4 qf, uint32_t qq, const uint32_t* ids, int cnt,
                                      uint64_t* ck, uint64_t* cr = nullptr) {
   constexpr int VPP = 64 / G;
+  constexpr bool NR = REFS && norm_in_ref<G>();  // the row's norm comes with its reference word
   const int l = lane_id();
   const int c = l % G, grp = l / G;
   for (int base = 0; base < cnt; base += 4 * VPP) {
@@ -405,7 +422,7 @@ __device__ inline void dist_batch_u8(const Index& ix, uint4 qf, uint32_t qq, con
         id[u] = vi < cnt ? ids[vi] : NONE;
         if (id[u] != NONE) {
           v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim)[c];
-          if (cr && c == 0) r[u] = load_ref(ix, id[u]);
+          if (REFS && (cr || NR) && c == 0) r[u] = load_ref(ix, id[u]);
         }
       }
     }
@@ -413,11 +430,73 @@ __device__ inline void dist_batch_u8(const Index& ix, uint4 qf, uint32_t qq, con
     for (int u = 0; u < 4; ++u) {
       if (u >= used) break;
       uint32_t qx = group_sum<G>(dot16(qf, v[u], 0u));
-      uint32_t xx = group_sum<G>(dot16(v[u], v[u], 0u));
+      uint32_t xx;
+      if constexpr (NR)
+        xx = ref_norm(r[u]);  // lane c == 0 holds the word
+      else
+        xx = group_sum<G>(dot16(v[u], v[u], 0u));
       int vi = base + u * VPP + grp;
       if (c == 0 && vi < cnt) {
         ck[vi] = make_key(qq + xx - 2u * qx, id[u]);
-        if (cr) cr[vi] = r[u];
+        if (REFS && cr) cr[vi] = r[u];
+      }
+    }
+  }
+}
+
+// The same batch with C 16-byte chunks per lane (G lanes per row, G * C * 16 =
+// dim): fewer lanes per row, so more rows per pass and shorter group sums.
+// 4 / C sub-batches are in flight at a time.
+template <int G, int C, bool REFS>
+__device__ inline void dist_batch_u8c(const Index& ix, const uint4 (&qf)[C], uint32_t qq, const uint32_t* ids,
+                                      int cnt, uint64_t* ck, uint64_t* cr) {
+  constexpr int VPP = 64 / G;
+  constexpr int U = 4 / C;
+  constexpr bool NR = REFS && norm_in_ref<G * C>();
+  const int l = lane_id();
+  const int c = l % G, grp = l / G;
+  for (int base = 0; base < cnt; base += U * VPP) {
+    const int used = min(U, (cnt - base + VPP - 1) / VPP);
+    uint4 v[U][C];
+    uint32_t id[U];
+    uint64_t r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int vi = base + u * VPP + grp;
+      id[u] = NONE;
+      r[u] = 0;
+#pragma unroll
+      for (int t = 0; t < C; ++t) v[u][t] = make_uint4(0, 0, 0, 0);
+      if (u < used) {
+        id[u] = vi < cnt ? ids[vi] : NONE;
+        if (id[u] != NONE) {
+          const uint4* row = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim);
+#pragma unroll
+          for (int t = 0; t < C; ++t) v[u][t] = row[t * G + c];
+          if (REFS && (cr || NR) && c == 0) r[u] = load_ref(ix, id[u]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (u >= used) break;
+      uint32_t qx = 0;
+#pragma unroll
+      for (int t = 0; t < C; ++t) qx = dot16(qf[t], v[u][t], qx);
+      qx = group_sum<G>(qx);
+      uint32_t xx;
+      if constexpr (NR) {
+        xx = ref_norm(r[u]);
+      } else {
+        xx = 0;
+#pragma unroll
+        for (int t = 0; t < C; ++t) xx = dot16(v[u][t], v[u][t], xx);
+        xx = group_sum<G>(xx);
+      }
+      const int vi = base + u * VPP + grp;
+      if (c == 0 && vi < cnt) {
+        ck[vi] = make_key(qq + xx - 2u * qx, id[u]);
+        if (REFS && cr) cr[vi] = r[u];
       }
     }
   }
@@ -562,7 +641,7 @@ __device__ inline bool publish(const Index& ix, uint32_t u, const uint32_t* ids,
     uint32_t won = 0;
     const bool reserved_retire = cur && cur->ret_left && ref_slab(snap) != NONE;
     if (l == 0) {
-      const uint64_t want = make_ref(ref_del(snap), n, s);
+      const uint64_t want = make_ref(ref_del(snap), n, s) | (snap & REF_NORM_MASK);  // flag and norm carried
       const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)snap, (unsigned long long)want);
       if (prev == snap) {
         won = 1;
@@ -589,6 +668,42 @@ __device__ inline bool publish(const Index& ix, uint32_t u, const uint32_t* ids,
   }
   if (l == 0) atomicAdd(&ix.ctr[C_PUB_DROPPED], 1ull);
   return false;
+}
+
+// One attempt of Algorithm 1 against an explicit snapshot `snap` of u's
+// reference (the list was built from the slab that snapshot names): fresh
+// slab, contents, release fence, CAS snap -> <flag of snap, n, fresh>. On
+// success the displaced slab is retired; on failure the fresh one is, the
+// failure is counted, and the caller rebuilds its list from a new snapshot.
+// Whole wave; returns true when installed.
+__device__ inline bool publish_once(const Index& ix, uint32_t u, uint64_t snap, const uint32_t* ids, const uint32_t* d,
+                                    uint32_t n, Counter which) {
+  const int l = lane_id();
+  const uint32_t R = ix.R;
+  uint32_t s = 0;
+  if (l == 0) s = alloc_slab(ix);
+  s = bcast(s);
+  if (s == NONE) return false;
+  uint32_t* slab = ix.slabs + (size_t)s * 2u * R;
+  for (uint32_t j = (uint32_t)l; j < R; j += 64) {
+    slab[j] = j < n ? ids[j] : NONE;
+    slab[R + j] = j < n ? d[j] : 0u;
+  }
+  __threadfence();  // contents before the reference that names them
+  uint32_t won = 0;
+  if (l == 0) {
+    const uint64_t want = make_ref(ref_del(snap), n, s) | (snap & REF_NORM_MASK);
+    const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)snap, (unsigned long long)want);
+    if (prev == snap) {
+      won = 1;
+      if (ref_slab(snap) != NONE) retire_slab(ix, ref_slab(snap));
+      atomicAdd(&ix.ctr[which], 1ull);
+    } else {
+      retire_slab(ix, s);
+      atomicAdd(&ix.ctr[C_CAS_FAIL], 1ull);
+    }
+  }
+  return bcast(won) != 0;
 }
 
 // ---- RobustPrune (slack alpha), one wave -----------------------------------------

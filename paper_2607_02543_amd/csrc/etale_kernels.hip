@@ -138,6 +138,24 @@ __global__ void k_store_rows(Index ix, const uint4* src, uint32_t* ids_out, uint
   }
 }
 
+// uint8 rows of at most 256 bytes: the squared norm of each new row goes into
+// its (still unborn) reference word, where every later publication carries it
+__global__ void __launch_bounds__(256) k_row_norms(Index ix, uint32_t first, uint32_t n, Dyn d) {
+  if (gated(ix, d)) return;
+  n = dyn_count(ix, d, n);
+  first = dyn_first(ix, d, first);
+  const uint32_t words = ix.dim / 16u;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint4* row = reinterpret_cast<const uint4*>(ix.x + (size_t)(first + i) * ix.dim);
+    uint32_t nn = 0;
+    for (uint32_t w = 0; w < words; ++w) {
+      const uint4 v = row[w];
+      nn = dot16(v, v, nn);
+    }
+    ix.refs[first + i] = REF_UNBORN | ((uint64_t)nn << 32);
+  }
+}
+
 // ---- entry set: the S smallest live ids ---------------------------------------------
 // Old members stay unless deleted; the gap is filled with the next live ids
 // above the old largest member (every live id below it is already a member).
@@ -859,25 +877,42 @@ uint32_t scan_select_keys(uint32_t L) { return (uint32_t)max((int)SEL_COMPACT, n
 uint32_t scan_select_lds_per_wave(uint32_t L) { return 8u * scan_select_keys(L); }
 
 // ---- traversal policies ------------------------------------------------------------
-// uint8 rows: G = dim/16 lanes per row, one 16-byte chunk each
-template <int G>
+// uint8 rows: G lanes per row, C 16-byte chunks each (G * C * 16 = dim)
+template <int G, int C = 1>
 struct TravU8 {
   static constexpr bool FLOAT = false;
   struct Q {
-    uint4 f;
+    uint4 f[C];
     uint32_t qq;
   };
   __device__ static Q load_query(const void* row) {
     Q q;
-    q.f = load_frag<G>(reinterpret_cast<const uint8_t*>(row));
-    q.qq = group_sum<G>(dot16(q.f, q.f, 0u));
+    const uint4* r = reinterpret_cast<const uint4*>(row);
+    const int c = lane_id() % G;
+    uint32_t qq = 0;
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+      q.f[t] = r[t * G + c];
+      qq = dot16(q.f[t], q.f[t], qq);
+    }
+    q.qq = group_sum<G>(qq);
     return q;
   }
   __device__ static const void* stored_row(const Index& ix, uint32_t id) { return ix.x + (size_t)id * ix.dim; }
   __device__ static size_t query_bytes(const Index& ix) { return ix.dim; }
   __device__ static void dist_batch(const Index& ix, const Q& q, const uint32_t* ids, int cnt, uint64_t* ck,
                                     uint64_t* cr) {
-    dist_batch_u8<G>(ix, q.f, q.qq, ids, cnt, ck, cr);
+    if constexpr (C == 1)
+      dist_batch_u8<G>(ix, q.f[0], q.qq, ids, cnt, ck, cr);
+    else
+      dist_batch_u8c<G, C, true>(ix, q.f, q.qq, ids, cnt, ck, cr);
+  }
+  // distances only: no reference words read (one line request per row)
+  __device__ static void dist_only(const Index& ix, const Q& q, const uint32_t* ids, int cnt, uint64_t* ck) {
+    if constexpr (C == 1)
+      dist_batch_u8<G, false>(ix, q.f[0], q.qq, ids, cnt, ck, nullptr);
+    else
+      dist_batch_u8c<G, C, false>(ix, q.f, q.qq, ids, cnt, ck, nullptr);
   }
   __device__ static uint32_t out_bits(uint32_t kd) { return kd; }            // int32 distance
   __device__ static uint32_t pad_bits() { return 0x7FFFFFFFu; }              // INT32_MAX
@@ -898,6 +933,9 @@ struct TravFloat {
   __device__ static void dist_batch(const Index& ix, const Q& q, const uint32_t* ids, int cnt, uint64_t* ck,
                                     uint64_t* cr) {
     T::dist_batch(ix, q, ids, cnt, ck, cr);
+  }
+  __device__ static void dist_only(const Index& ix, const Q& q, const uint32_t* ids, int cnt, uint64_t* ck) {
+    T::dist_batch(ix, q, ids, cnt, ck, nullptr);
   }
   __device__ static uint32_t out_bits(uint32_t kd) { return __builtin_bit_cast(uint32_t, fkey_inv(kd)); }
   __device__ static uint32_t pad_bits() { return 0x7F800000u; }              // +inf
@@ -1016,7 +1054,12 @@ __device__ inline uint32_t expansion_ids(const Index& ix, uint64_t r0, uint64_t 
   const uint32_t slot = second ? l - R : l;
   const uint32_t deg = (second && !two) ? 0u : ref_deg(r), s = ref_slab(r);
   uint32_t nid = NONE;
-  if (slot < deg && s < ix.P) nid = ix.slabs[(size_t)s * 2u * R + slot];
+  if (slot < deg && s < ix.P) {
+    const uint32_t* w = ix.slabs + (size_t)s * 2u * R + slot;
+    // with writers running alongside, the slab may have been written on
+    // another XCD after this one cached its previous use: read it coherently
+    nid = ix.concurrent ? __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *w;
+  }
   return nid < ix.cap ? nid : NONE;
 }
 
@@ -1150,6 +1193,13 @@ __device__ inline void drop_crowded_twins_h(const uint32_t (&nid)[H], const uint
   }
 }
 
+// A list entry's reference word is read when the entry is expanded (or read
+// ahead for expansion), not when its distance is computed: most scored nodes
+// never reach expansion, and a reference word read costs a line request of its
+// own. Entries not read yet hold REF_LAZY (degree 127, impossible for a real
+// word); the output stage reads the words of the entries that still have none.
+constexpr uint64_t REF_LAZY = ~0ull;
+
 // The same search for L <= 64 with the list in registers: lane i holds entry
 // i (key, reference word, expanded flag), entries at or past n hold KEY_NONE.
 // The next entries to expand are the lowest lanes of one ballot, and each
@@ -1178,7 +1228,7 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
   uint32_t lx = 0;
   if (l < n) {
     lk = a.init_keys[(size_t)qi * a.init_stride + l];
-    lr = load_ref(ix, key_id(lk));
+    lr = REF_LAZY;
   }
   wave_sync();
   if (l < n) (void)vt_insert(vt, a.vt_mask, key_id(lk));
@@ -1221,6 +1271,11 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     bool hit = true;
 #pragma unroll
     for (int k = 0; k < WMAX; ++k) hit = hit && key[k] == pre_k[k];
+    if (!hit) {  // the slabs were not read ahead: the reference words first, where not read yet
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k)
+        if (key[k] != KEY_NONE && ref[k] == REF_LAZY) ref[k] = load_ref(ix, key_id(key[k]));
+    }
 #pragma unroll
     for (int h = 0; h < H; ++h)
       nid[h] = hit ? pre_nid[h] : expansion_ids(ix, ref[2 * h], ref[2 * h + 1], key[2 * h + 1] != KEY_NONE);
@@ -1239,6 +1294,10 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
           o &= o - 1;
           pre_k[k] = bcast_lane64(lk, j);
           pref[k] = bcast_lane64(lr, j);
+          if (pref[k] == REF_LAZY) {
+            pref[k] = load_ref(ix, key_id(pre_k[k]));
+            if (l == j) lr = pref[k];  // travels with the entry through the merge
+          }
         }
       }
 #pragma unroll
@@ -1264,7 +1323,7 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     }
     wave_sync();
     if (!cnt) continue;
-    TP::dist_batch(ix, qv, ci, cnt, ck, cr);
+    TP::dist_only(ix, qv, ci, cnt, ck);  // reference words are read when an entry is expanded
     wave_sync();
     ndist += (uint32_t)cnt;
     // merge: the list becomes the L smallest of itself and the candidates
@@ -1284,6 +1343,11 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
       na += __popcll(accm[h]);
     }
     if (!na) continue;
+    // Per accepted candidate: one compare against the list lanes gives both
+    // each list entry's count of candidates below it and (its ballot, as list
+    // keys and candidates are distinct) the candidate's count of list entries
+    // below it; lanes at or past n hold KEY_NONE and are never written back.
+    const uint64_t nmask = ballot(l < n);
     uint32_t below_l = 0, below_c[H], list_c[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) below_c[h] = list_c[h] = 0;
@@ -1292,15 +1356,13 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
       for (uint64_t m = accm[hh]; m; m &= m - 1) {
         const int c = (int)__builtin_ctzll(m);
         const uint64_t kc = bcast_lane64(cand[hh], c);
-        below_l += l < n && kc < lk ? 1u : 0u;
+        const bool above = kc < lk;
+        below_l += above ? 1u : 0u;
 #pragma unroll
         for (int h = 0; h < H; ++h) below_c[h] += kc < cand[h] ? 1u : 0u;
-        const uint32_t nl = (uint32_t)__popcll(ballot(l < n && lk < kc));
+        const uint32_t nl = (uint32_t)__popcll(nmask & ~ballot(above));
         if (l == c) list_c[hh] = nl;
       }
-    uint64_t cref[H];  // read before the scatter overwrites the scratch
-#pragma unroll
-    for (int h = 0; h < H; ++h) cref[h] = ((accm[h] >> l) & 1ull) ? cr[64 * h + l] : 0ull;
     wave_sync();
     if (l < n && (uint32_t)l + below_l < (uint32_t)L) {
       ck[l + below_l] = lk;
@@ -1312,7 +1374,7 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
       const uint32_t p = list_c[h] + below_c[h];
       if (((accm[h] >> l) & 1ull) && p < (uint32_t)L) {
         ck[p] = cand[h];
-        cr[p] = cref[h];
+        cr[p] = REF_LAZY;
         ci[p] = 0;
       }
     }
@@ -1326,7 +1388,9 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     }
     wave_sync();
   }
-  // the list to LDS for the shared result stage (the candidate scratch is free)
+  // the list to LDS for the shared result stage (the candidate scratch is
+  // free), every entry with its reference word: the output keeps flag-0 nodes
+  if (l < n && lr == REF_LAZY) lr = load_ref(ix, key_id(lk));
   ck[l] = lk;
   cr[l] = lr;
   wave_sync();
@@ -1949,6 +2013,75 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
 
 // the same with the cached candidate state (uint8 rows, R <= 32): a kernel of
 // its own so that its registers are not those of the generic path
+// Reverse edges in the concurrent mode (Algorithm 2's loop as the paper runs
+// it): the (target, source) offers are not sorted or grouped; each wave takes
+// single offers and applies each to the target's list as it stands, with a
+// compare-and-swap against the snapshot it read. Offers to one target from
+// different waves race; a lost CAS rebuilds the list from a fresh snapshot
+// and tries again, up to the attempt budget (then the offer is dropped and
+// counted). The order in which a target's offers land is not fixed.
+template <class P>
+__global__ void __launch_bounds__(256) k_reverse_fast(Index ix, MaintArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  if (gated(ix, a.d)) return;
+  resolve(ix, a);
+  MaintLds m = carve(wave_lds(smem, a), a, ix.R);
+  const int l = lane_id();
+  const uint32_t R = ix.R;
+  uint64_t* ck = m.pr.keys;
+  const uint32_t np = a.n * R;
+  FOR_EACH_WAVE_ITEM(t, np) {
+    const uint64_t key = a.pairs[t];
+    if (key == KEY_NONE) continue;
+    const uint32_t w = (uint32_t)(key >> 32), v = (uint32_t)key;
+    bool done = false;
+    for (uint32_t attempt = 0; attempt < ix.publish_attempts && !done; ++attempt) {
+      const uint64_t snap = bcast64(load_ref(ix, w));
+      const uint32_t s = ref_slab(snap);
+      uint32_t n = s == NONE ? 0u : ref_deg(snap);
+      if ((uint32_t)l < n) {
+        m.nl_id[l] = __hip_atomic_load(ix.slabs + (size_t)s * 2u * R + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        m.nl_d[l] = __hip_atomic_load(ix.slabs + (size_t)s * 2u * R + R + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      wave_sync();
+      if (ballot((uint32_t)l < n && m.nl_id[l] == v) != 0ull) {
+        done = true;  // already listed: a set union changes nothing
+        break;
+      }
+      if (n < R) {
+        const uint32_t rho = P::dist1(ix, w, v, m.tmp, ck);
+        const uint64_t kv = make_key(P::kd(rho), v);
+        const bool before = (uint32_t)l < n && make_key(P::kd(m.nl_d[l]), m.nl_id[l]) < kv;
+        const uint32_t pos = (uint32_t)__popcll(ballot(before));
+        uint32_t id_l = 0, d_l = 0;
+        if ((uint32_t)l < n) {
+          id_l = m.nl_id[l];
+          d_l = m.nl_d[l];
+        }
+        wave_sync();
+        if ((uint32_t)l < n && (uint32_t)l >= pos) {
+          m.nl_id[l + 1] = id_l;
+          m.nl_d[l + 1] = d_l;
+        }
+        if (l == 0) {
+          m.nl_id[pos] = v;
+          m.nl_d[pos] = rho;
+        }
+        wave_sync();
+        ++n;
+      } else {
+        if ((uint32_t)l < n) m.cand[l] = m.nl_id[l];
+        if (l == 0) m.cand[n] = v;
+        wave_sync();
+        n = (uint32_t)P::prune(ix, w, m.cand, (int)n + 1, m.pr);
+        copy_out(m, n);
+      }
+      done = publish_once(ix, w, snap, m.nl_id, m.nl_d, n, C_PUB_REVERSE);
+    }
+    if (!done && l == 0) atomicAdd(&ix.ctr[C_PUB_DROPPED], 1ull);
+  }
+}
+
 template <int G>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_reverse_chain(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
@@ -2857,8 +2990,8 @@ __global__ void __launch_bounds__(256) k_free_tombstones(Index ix, uint64_t n_id
         const uint32_t u = (uint32_t)t;
         uint64_t r = load_ref(ix, u);
         for (int attempt = 0; attempt < 1024 && ref_del(r) && ref_slab(r) != NONE; ++attempt) {
-          const uint64_t prev =
-              atomicCAS(&ix.refs[u], (unsigned long long)r, (unsigned long long)make_ref(1, 0, NONE));
+          const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)r,
+                                          (unsigned long long)(make_ref(1, 0, NONE) | (r & REF_NORM_MASK)));
           if (prev == r) {
             freed = ref_slab(r);
             break;
@@ -2934,6 +3067,141 @@ __global__ void __launch_bounds__(64) k_bruteforce_u8(Index ix, const uint8_t* q
       xx = dot16(v, v, xx);
     }
     uint64_t key = make_key(qq + xx - 2u * qx, (uint32_t)u);
+    if (key < best[K - 1]) {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const uint64_t lo = key < best[i] ? key : best[i];
+        const uint64_t hi = key < best[i] ? best[i] : key;
+        best[i] = lo;
+        key = hi;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) all[l * K + i] = best[i];
+  __syncthreads();
+  wave_bitonic_sort(all, 64 * K);
+  for (uint32_t i = (uint32_t)l; i < k; i += 64) {
+    const uint64_t kk = all[i];
+    out_ids[(size_t)qi * k + i] = kk == KEY_NONE ? NONE : key_id(kk);
+    out_d[(size_t)qi * k + i] = kk == KEY_NONE ? 0x7FFFFFFF : (int32_t)key_dist(kk);
+  }
+}
+
+// ---- brute-force ground truth on the matrix cores (uint8 rows, dim <= 256) -----------
+// The exact k nearest live rows of each query by (distance, id), in three passes.
+// Rows are shifted to signed bytes (x - 128), which leaves every squared
+// difference unchanged, so d = |q'|^2 + |x'|^2 - 2 q'.x' is exact in int32.
+//   k_bf_norms:  |x'|^2 of every id, or -1 where the id is not live;
+//   k_bf_mfma:   a wave holds 16 queries as the N operand of
+//                v_mfma_i32_16x16x64_i8 (their shifted fragments stay in
+//                registers) and streams one chunk of rows through the M operand,
+//                16 rows per tile; lane l then holds query l % 16 against rows
+//                4 (l / 16) + i of the tile and keeps the K best keys of the rows
+//                it sees, so a query's K best over the chunk are among its four
+//                lanes' lists, which are written out;
+//   k_bf_merge:  one wave per query selects the k best of all its candidates.
+__global__ void __launch_bounds__(256) k_bf_norms(Index ix, uint64_t n_ids, int32_t* xn) {
+  const uint32_t words = ix.dim / 16u;
+  for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n_ids; u += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t r = load_ref(ix, (uint32_t)u);
+    int32_t v = -1;
+    if (!ref_del(r) && ref_slab(r) != NONE) {
+      const uint8_t* row = ix.x + u * ix.dim;
+      int sq = 0;
+      for (uint32_t w = 0; w < words; ++w) {
+        const v4i32 f = signed_frag(row, w * 16u, ix.dim);
+        sq += frag_sq(f);
+      }
+      v = sq;
+    }
+    xn[u] = v;
+  }
+}
+
+template <int S, int K>
+__global__ void __launch_bounds__(256) k_bf_mfma(Index ix, const uint8_t* q, uint32_t nq, uint64_t n_ids,
+                                                 const int32_t* xn, uint32_t n_chunks, uint64_t chunk, uint64_t* cand) {
+  const uint32_t wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t qt = wv / n_chunks, c = wv % n_chunks;
+  if (qt * 16u >= nq) return;  // whole waves only
+  const int l = lane_id();
+  const uint32_t r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u, rb = (uint32_t)(l >> 4) * 4u;
+  const uint32_t dim = ix.dim, qi = qt * 16u + r;
+  const bool qok = qi < nq;
+  const uint8_t* qrow = qok ? q + (size_t)qi * dim : nullptr;
+  v4i32 qf[S];
+  int qn = 0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    qf[s] = signed_frag(qrow, (uint32_t)s * 64u + kc, dim);
+    qn += frag_sq(qf[s]);
+  }
+  qn += (int)lane_xor<16>((uint32_t)qn);  // the four lanes of query r hold its four 16-byte pieces
+  qn += (int)lane_xor<32>((uint32_t)qn);
+  uint64_t best[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) best[i] = KEY_NONE;
+  const uint64_t e_beg = (uint64_t)c * chunk;
+  const uint64_t e_end = min(n_ids, e_beg + chunk);
+  // fragments of the first tile, then each tile's while the previous one is scored
+  v4i32 xf[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+    xf[s] = signed_frag(e_beg + r < e_end ? ix.x + (e_beg + r) * dim : nullptr, (uint32_t)s * 64u + kc, dim);
+  for (uint64_t e0 = e_beg; e0 < e_end; e0 += 16) {
+    v4i32 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < S; ++s) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(xf[s], qf[s], acc, 0, 0, 0);
+    const uint64_t nx = e0 + 16 + r;
+#pragma unroll
+    for (int s = 0; s < S; ++s) xf[s] = signed_frag(nx < e_end ? ix.x + nx * dim : nullptr, (uint32_t)s * 64u + kc, dim);
+    // the norms of this lane's four rows (e0 is a multiple of 16: one aligned 16-byte load)
+    int4 nn = make_int4(-1, -1, -1, -1);
+    if (e0 + rb < e_end) {
+      if (e0 + rb + 4 <= e_end) {
+        nn = *reinterpret_cast<const int4*>(xn + e0 + rb);
+      } else {
+        nn.x = xn[e0 + rb];
+        if (e0 + rb + 1 < e_end) nn.y = xn[e0 + rb + 1];
+        if (e0 + rb + 2 < e_end) nn.z = xn[e0 + rb + 2];
+      }
+    }
+    const int nv[4] = {nn.x, nn.y, nn.z, nn.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (!qok || nv[i] < 0) continue;
+      uint64_t key = make_key((uint32_t)(qn + nv[i] - 2 * acc[i]), (uint32_t)(e0 + rb + (uint32_t)i));
+      if (key < best[K - 1]) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const uint64_t lo = key < best[j] ? key : best[j];
+          const uint64_t hi = key < best[j] ? best[j] : key;
+          best[j] = lo;
+          key = hi;
+        }
+      }
+    }
+  }
+  if (qok) {
+    uint64_t* out = cand + (((uint64_t)qi * n_chunks + c) * 4u + (uint32_t)(l >> 4)) * K;
+#pragma unroll
+    for (int i = 0; i < K; ++i) out[i] = best[i];
+  }
+}
+
+template <int K>
+__global__ void __launch_bounds__(64) k_bf_merge(const uint64_t* cand, uint32_t n_cand, uint32_t k, uint32_t* out_ids,
+                                                 int32_t* out_d) {
+  __shared__ uint64_t all[64 * K];
+  const uint32_t qi = blockIdx.x;
+  const int l = lane_id();
+  uint64_t best[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) best[i] = KEY_NONE;
+  const uint64_t* c = cand + (uint64_t)qi * n_cand;
+  for (uint32_t j = (uint32_t)l; j < n_cand; j += 64) {
+    uint64_t key = c[j];
     if (key < best[K - 1]) {
 #pragma unroll
       for (int i = 0; i < K; ++i) {
@@ -3075,6 +3343,13 @@ hipError_t launch_reclaim_gate(const Index& ix, int32_t* status, hipStream_t s) 
   return hipGetLastError();
 }
 
+hipError_t launch_row_norms(const Index& ix, uint32_t first, uint32_t n, Dyn d, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_norms, dim3(blocks_for(n, 256) < 1024u ? blocks_for(n, 256) : 1024u), dim3(256), 0, s, ix,
+                     first, n, d);
+  return hipGetLastError();
+}
+
 hipError_t launch_store_rows(const Index& ix, const void* src, uint32_t* ids_out, uint32_t first, uint32_t n, Dyn d,
                              hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -3098,6 +3373,25 @@ hipError_t launch_gather_rows(const void* rows, const uint32_t* idx, uint32_t n,
   const uint32_t words = row_bytes / 16u;
   hipLaunchKernelGGL(k_gather_rows, dim3(persist_grid((uint64_t)n * words, 256)), dim3(256), 0, s,
                      (const uint4*)rows, idx, n, words, (uint4*)out);
+  return hipGetLastError();
+}
+
+// serving: a tick's search results (nq x k) to the rows of the requests they answer
+__global__ void k_scatter_results(const uint32_t* ids, const uint32_t* d, const uint32_t* pos, uint32_t nq, uint32_t k,
+                                  uint32_t* out_ids, uint32_t* out_d) {
+  const uint64_t n = (uint64_t)nq * k;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t r = (uint64_t)pos[i / k] * k + i % k;
+    out_ids[r] = ids[i];
+    out_d[r] = d[i];
+  }
+}
+
+hipError_t launch_scatter_results(const uint32_t* ids, const uint32_t* d, const uint32_t* pos, uint32_t nq, uint32_t k,
+                                  uint32_t* out_ids, uint32_t* out_d, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  const unsigned b = blocks_for((uint64_t)nq * k, 256);
+  hipLaunchKernelGGL(k_scatter_results, dim3(b < 1024u ? b : 1024u), dim3(256), 0, s, ids, d, pos, nq, k, out_ids, out_d);
   return hipGetLastError();
 }
 
@@ -3254,12 +3548,18 @@ hipError_t launch_search(const Index& ix, const SearchArgs& a, uint32_t waves_pe
   const unsigned grid = a.persistent ? persist_grid(a.nq, waves_per_block) : blocks_for(a.nq, waves_per_block);
   const size_t lds = (size_t)a.lds_per_wave * waves_per_block;
   if (ix.metric == 0) {
+    // lanes per row: dim / 16 (one chunk each), or half that with two chunks each
+    const bool half = a.row_lanes != 0 && a.row_lanes * 32u == ix.dim;
     switch (ix.dim / 16) {
       case 1: { using TP = TravU8<1>; LS(TP); break; }
       case 2: { using TP = TravU8<2>; LS(TP); break; }
       case 4: { using TP = TravU8<4>; LS(TP); break; }
-      case 8: { using TP = TravU8<8>; LS(TP); break; }
-      case 16: { using TP = TravU8<16>; LS(TP); break; }
+      case 8:
+        if (half) { using TP = TravU8<4, 2>; LS(TP); } else { using TP = TravU8<8>; LS(TP); }
+        break;
+      case 16:
+        if (half) { using TP = TravU8<8, 2>; LS(TP); } else { using TP = TravU8<16>; LS(TP); }
+        break;
       case 32: { using TP = TravU8<32>; LS(TP); break; }
       case 64: { using TP = TravU8<64>; LS(TP); break; }
       default: return hipErrorInvalidValue;
@@ -3334,42 +3634,53 @@ static unsigned resident_blocks(F f, unsigned threads, size_t lds) {
   return r;
 }
 
+// share > 1: only that fraction of the resident blocks (the concurrent mode
+// leaves room on every CU for the searches of the other stream)
+template <class F>
+static dim3 resident_grid(F f, unsigned grid, dim3 blk, size_t lds, unsigned share) {
+  unsigned r = resident_blocks(f, blk.x, lds);
+  if (r && share > 1) r = r / share ? r / share : 1u;
+  return dim3(r && grid > r ? r : grid);
+}
 template <class F>
 static dim3 resident_grid(F f, unsigned grid, dim3 blk, size_t lds) {
-  const unsigned r = resident_blocks(f, blk.x, lds);
-  return dim3(r && grid > r ? r : grid);
+  return resident_grid(f, grid, blk, lds, 1u);
 }
 
 template <class P>
 static void launch_maint_p(MaintKernel which, const Index& ix, const MaintArgs& a, unsigned grid, dim3 blk,
                            size_t lds, hipStream_t s) {
+  const unsigned sh = ix.concurrent ? 2u : 1u;  // searches of the other stream need CUs too
   switch (which) {
     case MK_FORWARD:
-      hipLaunchKernelGGL(k_forward<P>, resident_grid(k_forward<P>, grid, blk, lds), blk, lds, s, ix, a);
+      hipLaunchKernelGGL(k_forward<P>, resident_grid(k_forward<P>, grid, blk, lds, sh), blk, lds, s, ix, a);
       break;
     case MK_REVERSE:
       if constexpr (P::CHAIN) {
         if (a.chain) {
-          hipLaunchKernelGGL(k_reverse_chain<P::GL>, resident_grid(k_reverse_chain<P::GL>, grid, blk, lds), blk, lds,
+          hipLaunchKernelGGL(k_reverse_chain<P::GL>, resident_grid(k_reverse_chain<P::GL>, grid, blk, lds, sh), blk, lds,
                              s, ix, a);
           break;
         }
       }
-      hipLaunchKernelGGL(k_reverse_apply<P>, resident_grid(k_reverse_apply<P>, grid, blk, lds), blk, lds, s, ix, a);
+      hipLaunchKernelGGL(k_reverse_apply<P>, resident_grid(k_reverse_apply<P>, grid, blk, lds, sh), blk, lds, s, ix, a);
+      break;
+    case MK_REVERSE_FAST:
+      hipLaunchKernelGGL(k_reverse_fast<P>, resident_grid(k_reverse_fast<P>, grid, blk, lds, sh), blk, lds, s, ix, a);
       break;
     case MK_REFINE:
-      hipLaunchKernelGGL(k_refine<P>, resident_grid(k_refine<P>, grid, blk, lds), blk, lds, s, ix, a);
+      hipLaunchKernelGGL(k_refine<P>, resident_grid(k_refine<P>, grid, blk, lds, sh), blk, lds, s, ix, a);
       hipLaunchKernelGGL(k_refine_publish, dim3(grid), blk, 512u * (blk.x / 64u), s, ix, a);
       break;
     case MK_REPAIR:
       if constexpr (P::CHAIN) {
         if (a.chain) {
-          hipLaunchKernelGGL(k_repair_pool<P::GL>, resident_grid(k_repair_pool<P::GL>, grid, blk, lds), blk, lds, s,
+          hipLaunchKernelGGL(k_repair_pool<P::GL>, resident_grid(k_repair_pool<P::GL>, grid, blk, lds, sh), blk, lds, s,
                              ix, a);
           break;
         }
       }
-      hipLaunchKernelGGL(k_repair_apply<P>, resident_grid(k_repair_apply<P>, grid, blk, lds), blk, lds, s, ix, a);
+      hipLaunchKernelGGL(k_repair_apply<P>, resident_grid(k_repair_apply<P>, grid, blk, lds, sh), blk, lds, s, ix, a);
       break;
   }
 }
@@ -3510,11 +3821,41 @@ hipError_t launch_export(const Index& ix, uint64_t n_ids, uint32_t* nbr, uint32_
   return hipGetLastError();
 }
 
+uint64_t bruteforce_norm_bytes(uint64_t n_ids) { return (n_ids * 4 + 255) / 256 * 256; }
+
+uint64_t bruteforce_scratch_bytes(const Index& ix, uint32_t nq, uint64_t n_ids) {
+  if (ix.metric != 0 || ix.dim < 64 || ix.dim > 256) return 0;
+  const uint32_t q_tiles = (nq + 15) / 16;
+  const uint64_t n_chunks = std::min<uint64_t>(std::max<uint64_t>(1, (n_ids + 1023) / 1024),
+                                               std::max<uint32_t>(1, (4096 + q_tiles - 1) / q_tiles));
+  return bruteforce_norm_bytes(n_ids) + (uint64_t)nq * n_chunks * 4 * 16 * 8;
+}
+
 hipError_t launch_bruteforce(const Index& ix, const void* q, uint32_t nq, uint64_t n_ids, uint32_t k,
-                             uint32_t* out_ids, uint32_t* out_d, hipStream_t s) {
+                             uint32_t* out_ids, uint32_t* out_d, hipStream_t s, unsigned char* scratch) {
   if (nq == 0) return hipSuccess;
   if (k > 16) return hipErrorInvalidValue;
-  if (ix.metric == 0) {
+  if (ix.metric == 0 && scratch && ix.dim >= 64 && ix.dim <= 256) {
+    // on the matrix cores: chunks of rows so that about 4,096 waves run
+    const uint32_t q_tiles = blocks_for(nq, 16);
+    uint32_t n_chunks = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, (n_ids + 1023) / 1024),
+                                                     std::max<uint32_t>(1, blocks_for(4096, q_tiles)));
+    const uint64_t chunk = ((n_ids + n_chunks - 1) / n_chunks + 15) / 16 * 16;
+    n_chunks = (uint32_t)std::max<uint64_t>(1, (n_ids + chunk - 1) / chunk);
+    int32_t* xn = reinterpret_cast<int32_t*>(scratch);
+    uint64_t* cand = reinterpret_cast<uint64_t*>(scratch + bruteforce_norm_bytes(n_ids));
+    hipLaunchKernelGGL(k_bf_norms, dim3(std::min<uint64_t>(4096, blocks_for(n_ids ? n_ids : 1, 256))), dim3(256), 0, s,
+                       ix, n_ids, xn);
+    const uint64_t waves = (uint64_t)q_tiles * n_chunks;
+    const dim3 grid((unsigned)((waves + 3) / 4)), blk(256);
+    switch (ix.dim / 64) {
+      case 1: hipLaunchKernelGGL((k_bf_mfma<1, 16>), grid, blk, 0, s, ix, (const uint8_t*)q, nq, n_ids, xn, n_chunks, chunk, cand); break;
+      case 2: hipLaunchKernelGGL((k_bf_mfma<2, 16>), grid, blk, 0, s, ix, (const uint8_t*)q, nq, n_ids, xn, n_chunks, chunk, cand); break;
+      case 4: hipLaunchKernelGGL((k_bf_mfma<4, 16>), grid, blk, 0, s, ix, (const uint8_t*)q, nq, n_ids, xn, n_chunks, chunk, cand); break;
+      default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_bf_merge<16>, dim3(nq), dim3(64), 0, s, cand, n_chunks * 4u * 16u, k, out_ids, (int32_t*)out_d);
+  } else if (ix.metric == 0) {
     hipLaunchKernelGGL(k_bruteforce_u8<16>, dim3(nq), dim3(64), 0, s, ix, (const uint8_t*)q, nq, n_ids, k, out_ids,
                        (int32_t*)out_d);
   } else {

@@ -31,6 +31,7 @@ struct SearchArgs {
   uint32_t* counts;    // optional [nq x 2]: expansions, distance evaluations
   Dyn d;               // launch-time count (nq) and first id
   uint32_t persistent; // 1: waves take queries from a work queue (count known only on the device)
+  uint32_t row_lanes;  // uint8 rows: lanes per row in distance batches (0: dim / 16); result-invariant
 };
 
 // k_scan: the L best start nodes (entry set, or the batch for a bootstrap,
@@ -81,7 +82,7 @@ struct MaintArgs {
   Dyn d;                   // launch-time count (n) and first id
 };
 
-enum MaintKernel { MK_FORWARD = 0, MK_REVERSE = 1, MK_REFINE = 2, MK_REPAIR = 3 };
+enum MaintKernel { MK_FORWARD = 0, MK_REVERSE = 1, MK_REFINE = 2, MK_REPAIR = 3, MK_REVERSE_FAST = 4 };
 
 hipError_t launch_init(const Index& ix, hipStream_t s);
 hipError_t launch_recycle(const Index& ix, hipStream_t s);
@@ -93,7 +94,12 @@ hipError_t launch_round_gate(const Index& ix, uint32_t tombstone_only, uint32_t 
 hipError_t launch_reclaim_gate(const Index& ix, int32_t* status, hipStream_t s);
 hipError_t launch_store_rows(const Index& ix, const void* src, uint32_t* ids_out, uint32_t first, uint32_t n, Dyn d,
                              hipStream_t s);
+// uint8 rows with dim <= 256: their squared norms into the new ids' reference words
+hipError_t launch_row_norms(const Index& ix, uint32_t first, uint32_t n, Dyn d, hipStream_t s);
 hipError_t launch_refresh_entries(const Index& ix, uint32_t bound, uint32_t S, Dyn d, hipStream_t s);
+// serving: results (nq x k) to rows pos[i] of the caller's (n_requests x k) arrays
+hipError_t launch_scatter_results(const uint32_t* ids, const uint32_t* d, const uint32_t* pos, uint32_t nq, uint32_t k,
+                                  uint32_t* out_ids, uint32_t* out_d, hipStream_t s);
 hipError_t launch_gather_rows(const void* rows, const uint32_t* idx, uint32_t n, uint32_t row_bytes, void* out,
                               hipStream_t s);
 uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots, uint32_t W);
@@ -127,8 +133,11 @@ hipError_t launch_compact(const Index& ix, const uint32_t* dirty, uint64_t n, Dy
 hipError_t launch_free_tombstones(const Index& ix, uint64_t n_ids, Dyn d, hipStream_t s);
 hipError_t launch_export(const Index& ix, uint64_t n_ids, uint32_t* nbr, uint32_t* rho, uint8_t* deg, uint8_t* del,
                          uint8_t* has_slab, hipStream_t s);
+// exact k nearest live rows; uint8 rows of 64..256 bytes run on the matrix
+// cores with `scratch` of bruteforce_scratch_bytes() (0: no scratch needed)
+uint64_t bruteforce_scratch_bytes(const Index& ix, uint32_t nq, uint64_t n_ids);
 hipError_t launch_bruteforce(const Index& ix, const void* q, uint32_t nq, uint64_t n_ids, uint32_t k,
-                             uint32_t* out_ids, uint32_t* out_d, hipStream_t s);
+                             uint32_t* out_ids, uint32_t* out_d, hipStream_t s, unsigned char* scratch = nullptr);
 hipError_t launch_encode(const Index& ix, uint32_t first, uint32_t n, Dyn d, float* xs, uint16_t* xb, uint8_t* x8,
                          hipStream_t s);
 hipError_t launch_set_lists(const Index& ix, const MaintArgs& a, const uint32_t* ids, const uint32_t* nbr,

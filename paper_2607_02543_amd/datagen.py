@@ -62,8 +62,17 @@ class Mixture:
         c /= np.linalg.norm(c, axis=1, keepdims=True)
         return c
 
-    def draw(self, rng: np.random.Generator, centers: np.ndarray, n: int) -> np.ndarray:
-        labels = rng.integers(0, self.n_clusters, size=n)
+    def draw(self, rng: np.random.Generator, centers: np.ndarray, n: int, with_labels: bool = False,
+             allowed: Optional[np.ndarray] = None):
+        """n points; with_labels also returns each point's cluster. With
+        `allowed` (cluster ids) the labels are drawn uniformly from those
+        clusters only; without it the draws are exactly those of the plain
+        call (the same stream consumption)."""
+        if allowed is None:
+            labels = rng.integers(0, self.n_clusters, size=n)
+        else:
+            allowed = np.asarray(allowed)
+            labels = allowed[rng.integers(0, allowed.size, size=n)]
         out = np.empty((n, self.dim), dtype=np.uint8 if self.metric == METRIC_L2_U8 else np.float32)
         chunk = 1 << 16
         for s in range(0, n, chunk):
@@ -75,7 +84,7 @@ class Mixture:
             else:
                 pts /= np.linalg.norm(pts, axis=1, keepdims=True)
                 out[s:e] = pts.astype(np.float32)
-        return out
+        return (out, labels) if with_labels else out
 
 
 @dataclasses.dataclass
@@ -143,9 +152,9 @@ def precision_f32(n_base: int = 1_000_000, rounds: int = 20, n_queries: int = 10
 
 
 def serving_u8(n_base: int = 10_000_000, seed: int = 0) -> Workload:
-    """The scale mixture (128-d uint8, 1,024 clusters, sigma 18) at 10M
-    vectors, served as a request stream (see Stream.trace)."""
-    return Workload("serving_u8_10m", Mixture(128, 1024, 18.0, METRIC_L2_U8), n_base, 32, 64, 6, 5,
+    """128-d uint8 from a 4,096-cluster mixture (sigma 18) at 10M vectors,
+    served as a request stream (see Stream.trace and Stream.kinds)."""
+    return Workload("serving_u8_10m", Mixture(128, 4096, 18.0, METRIC_L2_U8), n_base, 32, 64, 6, 5,
                     0, 0.0, 0, 10, (64,), seed, 1000, 100_000)
 
 
@@ -167,11 +176,15 @@ class Stream:
     def base(self, n: int) -> np.ndarray:
         return self.wl.mixture.draw(self.rng["base"], self.centers, n)
 
-    def inserts(self, n: int) -> np.ndarray:
-        return self.wl.mixture.draw(self.rng["inserts"], self.centers, n)
+    def base_labeled(self, n: int):
+        """base(n) and the cluster of each point (the same draws as base(n))."""
+        return self.wl.mixture.draw(self.rng["base"], self.centers, n, with_labels=True)
 
-    def queries(self, n: int) -> np.ndarray:
-        return self.wl.mixture.draw(self.rng["queries"], self.centers, n)
+    def inserts(self, n: int, clusters: Optional[np.ndarray] = None) -> np.ndarray:
+        return self.wl.mixture.draw(self.rng["inserts"], self.centers, n, allowed=clusters)
+
+    def queries(self, n: int, clusters: Optional[np.ndarray] = None) -> np.ndarray:
+        return self.wl.mixture.draw(self.rng["queries"], self.centers, n, allowed=clusters)
 
     def deletes(self, live_ids: np.ndarray, n: int) -> np.ndarray:
         """n distinct ids drawn uniformly without replacement from live_ids, sorted."""
@@ -193,6 +206,12 @@ class Stream:
         u = r.random(t.size)
         kind = np.where(u < p_insert, 1, np.where(u < p_insert + p_delete, 2, 0)).astype(np.uint32)
         return {"t": t, "kind": kind}
+
+    def kinds(self, n: int, p_insert: float = 0.05, p_delete: float = 0.05) -> np.ndarray:
+        """Request kinds only (0 search, 1 insert, 2 delete), for streams whose
+        arrival times do not matter (saturated serving)."""
+        u = self.rng["arrivals"].random(n)
+        return np.where(u < p_insert, 1, np.where(u < p_insert + p_delete, 2, 0)).astype(np.uint32)
 
     def round_params(self, live: int) -> dict:
         """One uneven round: churn fraction drawn from {0.1%, 1%, 5%} of the

@@ -55,8 +55,8 @@ class Stats(C.Structure):
 
 
 class TuneResult(C.Structure):
-    _fields_ = [("waves_per_block", C.c_uint32), ("vt_slots", C.c_uint32), ("ms", C.c_float),
-                ("ms_default", C.c_float)]
+    _fields_ = [("waves_per_block", C.c_uint32), ("vt_slots", C.c_uint32), ("row_lanes", C.c_uint32),
+                ("ms", C.c_float), ("ms_default", C.c_float)]
 
 
 class Request(C.Structure):
@@ -65,14 +65,14 @@ class Request(C.Structure):
 
 class ServeConfig(C.Structure):
     _fields_ = [("k", C.c_uint32), ("L", C.c_uint32), ("max_tick", C.c_uint32), ("reclaim_every", C.c_uint32),
-                ("hbm_budget_bytes", C.c_uint64), ("graph", C.c_int32), ("reserved", C.c_uint32)]
+                ("hbm_budget_bytes", C.c_uint64), ("graph", C.c_int32), ("realtime", C.c_int32)]
 
 
 class ServeStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
-        "ticks", "searches", "inserts", "deletes", "rejected_inserts", "reclaims", "failed_ticks",
+        "ticks", "searches", "inserts", "deletes", "rejected_inserts", "deferred", "reclaims", "failed_ticks",
         "peak_resident_slabs", "final_resident_slabs", "ids_handed_out", "graphs")] + \
-        [("trace_seconds", C.c_double), ("busy_seconds", C.c_double)]
+        [("wall_seconds", C.c_double), ("device_busy_seconds", C.c_double)]
 
 
 REQ_SEARCH, REQ_INSERT, REQ_DELETE = 0, 1, 2
@@ -122,10 +122,12 @@ def load() -> C.CDLL:
         "etale_set_query_traversal": ([vp, i32, u32], i32),
         "etale_export_rows": ([vp, u64, u64, i32, vp], i32),
         "etale_set_search_knobs": ([vp, u32, u32], i32),
-        "etale_serve": ([vp, C.POINTER(ServeConfig), vp, u64, vp, u64, vp, C.POINTER(ServeStats)], i32),
+        "etale_serve": ([vp, C.POINTER(ServeConfig), vp, u64, vp, u64, vp, vp, vp, vp, C.POINTER(ServeStats)], i32),
         "etale_autotune": ([vp, vp, u64, u32, u32, C.POINTER(TuneResult)], i32),
+        "etale_set_search_lanes": ([vp, u32], i32),
         "etale_set_search_timing": ([vp, i32], i32),
         "etale_get_search_timing": ([vp, vp, u64, C.POINTER(u64)], i32),
+        "etale_set_concurrent": ([vp, i32, vp], i32),
         "etale_sync": ([vp], i32),
         "etale_last_error": ([vp], C.c_char_p),
     }
@@ -149,7 +151,7 @@ class Index:
                  tombstone_only: bool = False, publish_attempts: int = 8, max_batch: int = 10000,
                  vt_slots: int = 1024, waves_per_block: int = 4, id_capacity: int = 100000,
                  slab_capacity: Optional[int] = None, metric: int = METRIC_L2_U8, traversal: int = TRAV_NATIVE,
-                 rerank_mult: int = 4, copies: int = 0, W: int = 1, stream=None):
+                 rerank_mult: int = 4, copies: int = 0, W: int = 1, stream=None, row_lanes: int = 0):
         import torch
 
         self.torch = torch
@@ -171,6 +173,8 @@ class Index:
         if rc != OK:
             raise EtaleError(rc, "etale_create", "configuration rejected or allocation failed")
         self.h = h
+        if row_lanes:
+            self.set_search_lanes(row_lanes)
 
     def close(self):
         if getattr(self, "h", None):
@@ -279,6 +283,12 @@ class Index:
     def sync(self):
         self._check(self.lib.etale_sync(self.h), "sync")
 
+    def set_concurrent(self, enable: bool, search_stream=None):
+        """Concurrent mode: searches on `search_stream` (a torch.cuda.Stream)
+        alongside rounds on the index's stream; leaving it drains both."""
+        ptr = search_stream.cuda_stream if search_stream is not None else None
+        self._check(self.lib.etale_set_concurrent(self.h, int(enable), ptr), "set_concurrent")
+
     def stats(self) -> dict:
         s = Stats()
         self._check(self.lib.etale_get_stats(self.h, C.byref(s)), "get_stats")
@@ -331,21 +341,33 @@ class Index:
         return out
 
     def serve(self, t_arrive: np.ndarray, kind: np.ndarray, arg: np.ndarray, rows, k: int = 10, L: int = 64,
-              max_tick: int = 4096, reclaim_every: int = 0, hbm_budget_bytes: int = 0, graph: bool = True):
-        """Run a request trace through the library's serving loop (continuous
-        batching into rounds). Returns (per-request latency in ms, stats)."""
+              max_tick: int = 4096, reclaim_every: int = 0, hbm_budget_bytes: int = 0, graph: bool = True,
+              realtime: bool = False, results: bool = False):
+        """Run a request stream through the library's serving loop (continuous
+        batching into ticks whose searches and updates overlap on the device).
+        Returns (per-request latency in ms, per-request tick, stats) and, with
+        results=True, the device tensors (ids, distances), n x k, written for
+        the search requests."""
+        torch = self.torch
         n = int(t_arrive.size)
         reqs = np.zeros(n, dtype=np.dtype([("t", np.float64), ("kind", np.uint32), ("arg", np.uint32)]))
         reqs["t"], reqs["kind"], reqs["arg"] = t_arrive, kind, arg
         rows = self._dev(rows, self._vdtype)
         lat = np.zeros(n, np.float32)
-        cfg = ServeConfig(k, L, max_tick, reclaim_every, hbm_budget_bytes, int(graph), 0)
+        ticks = np.zeros(n, np.uint32)
+        res_i = res_d = None
+        if results:
+            res_i = torch.full((n, k), -1, dtype=torch.int32, device=rows.device)
+            res_d = torch.zeros((n, k), dtype=self._ddtype, device=rows.device)
+        cfg = ServeConfig(k, L, max_tick, reclaim_every, hbm_budget_bytes, int(graph), int(realtime))
         st = ServeStats()
         p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
-        self._check(self.lib.etale_serve(self.h, C.byref(cfg), p(reqs), n, _ptr(rows), rows.shape[0], p(lat),
-                                         C.byref(st)), "serve")
+        self._check(self.lib.etale_serve(self.h, C.byref(cfg), p(reqs), n, _ptr(rows), rows.shape[0], p(lat), p(ticks),
+                                         _ptr(res_i), _ptr(res_d), C.byref(st)), "serve")
         stats = {name: getattr(st, name) for name, _ in ServeStats._fields_}
-        return lat, stats
+        if results:
+            return lat, ticks, stats, (res_i, res_d)
+        return lat, ticks, stats
 
     def set_search_knobs(self, waves_per_block: int, vt_slots: int):
         self._check(self.lib.etale_set_search_knobs(self.h, waves_per_block, vt_slots), "set_search_knobs")
@@ -355,7 +377,11 @@ class Index:
         q = self._dev(q, self._vdtype)
         r = TuneResult()
         self._check(self.lib.etale_autotune(self.h, _ptr(q), q.shape[0], k, L, C.byref(r)), "autotune")
-        return {"waves_per_block": r.waves_per_block, "vt_slots": r.vt_slots, "ms": r.ms, "ms_default": r.ms_default}
+        return {"waves_per_block": r.waves_per_block, "vt_slots": r.vt_slots, "row_lanes": r.row_lanes, "ms": r.ms,
+                "ms_default": r.ms_default}
+
+    def set_search_lanes(self, lanes_per_row: int):
+        self._check(self.lib.etale_set_search_lanes(self.h, lanes_per_row), "set_search_lanes")
 
     def set_search_timing(self, enable: bool = True):
         self._check(self.lib.etale_set_search_timing(self.h, int(enable)), "set_search_timing")

@@ -43,7 +43,7 @@ int main(void) {
          sizeof(etale_round_desc), offsetof(etale_round_desc, max_q), offsetof(etale_round_desc, counts),
          offsetof(etale_round_desc, graph));
   printf("%zu %zu %zu %zu\n", sizeof(etale_request), sizeof(etale_serve_config), sizeof(etale_serve_stats),
-         offsetof(etale_serve_stats, trace_seconds));
+         offsetof(etale_serve_stats, wall_seconds));
   return 0;
 }
 """
@@ -71,7 +71,8 @@ def test_struct_layout_matches_header():
     assert C.sizeof(etale.Request) == qsize
     assert C.sizeof(etale.ServeConfig) == scsize
     assert C.sizeof(etale.ServeStats) == sssize
-    assert etale.ServeStats.trace_seconds.offset == off_ts
+    assert etale.ServeStats.wall_seconds.offset == off_ts
+    assert etale.ServeConfig.realtime.offset == 28
 
 
 def test_create_rejects_bad_configs_without_touching_a_device():

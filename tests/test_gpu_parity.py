@@ -103,10 +103,37 @@ def test_parity_ragged_batches():
 
 
 def test_parity_knob_invariance():
-    # visited-table size and waves per block must not change any result
+    # visited-table size, waves per block and lanes per row must not change any result
     wl = small_workload(seed=5, n_base=1500, rounds=1)
     run_parity(wl, vt_slots=64, waves_per_block=1)
     run_parity(wl, vt_slots=4096, waves_per_block=2)
+    run_parity(wl, row_lanes=4, W=2, search_L=(32, 64, 100))
+
+
+def test_autotune_choice_leaves_results_unchanged():
+    # the autotuner only picks result-invariant knobs: results before and after
+    # are identical, and identical to the oracle's
+    torch = _torch()
+    wl = small_workload(seed=14, n_base=6000, clusters=16, batch=2000, rounds=0)
+    p = index_params(wl, n_entry=512, W=2)
+    o, g = make_oracle(p), make_gpu(p)
+    st = dg.Stream(wl)
+    for b in wl.build_batches():
+        x = st.base(b)
+        o.insert(x)
+        g.insert(torch.from_numpy(x).cuda())
+    q = st.queries(3000)
+    qd = torch.from_numpy(q).cuda()
+    before = [g.search(qd, 10, L) for L in (32, 64, 128)]
+    tune = g.autotune(qd, 10, 64)
+    print(f"[autotune] {tune}", flush=True)
+    assert tune["row_lanes"] in (4, 8) and tune["ms"] <= tune["ms_default"] * 1.05
+    for L, (i0, d0) in zip((32, 64, 128), before):
+        i1, d1 = g.search(qd, 10, L)
+        assert torch.equal(i0, i1) and torch.equal(d0, d1), f"L={L}: results changed with the tuned knobs"
+        io, do = o.search(q, 10, L)
+        assert np.array_equal(io, i1.cpu().numpy().astype(np.uint32)) and np.array_equal(do, d1.cpu().numpy())
+    g.close()
 
 
 def test_parity_two_expansions_per_iteration():
