@@ -50,6 +50,7 @@ struct etale_index {
   int32_t* status = nullptr;      // round status words of the calls that do not take one
   uint32_t pair_bits = 0;         // bits of an id (the sort range of pair targets)
   bool no_chain = false;          // reverse edges without the cached candidate state
+  bool no_mx = false;             // prunes select from staged rows even where the matrix cores could
   uint64_t* scan_keys = nullptr;  // [scan_chunk x 256] initial lists
   uint32_t* scan_n = nullptr;
   uint32_t* scan_dist = nullptr;  // [dist_cap] query x start-set distances
@@ -192,6 +193,16 @@ MaintArgs maint_args(const etale_index* ix, uint32_t nmax) {
   a.vstride = ix->cfg.metric == ETALE_METRIC_L2_U8 ? ix->cfg.dim + 16 : 0;  // uint8 rows are staged in LDS
   a.lds_per_wave = maint_lds_per_wave(a, ix->cfg.R);
   return a;
+}
+
+// The prunes of a launch select on the matrix cores (no staged rows) where
+// the rows allow it: uint8, at most 128 bytes (the tile's operands stay in
+// registers), R <= 32.
+void use_mx_prune(const etale_index* ix, MaintArgs& a) {
+  if (ix->cfg.metric == ETALE_METRIC_L2_U8 && ix->cfg.dim <= 128 && ix->cfg.R <= 32 && !ix->no_mx) {
+    a.mx = 1;
+    a.lds_per_wave = maint_lds_per_wave(a, ix->cfg.R);
+  }
 }
 
 // waves per search workgroup: the configured count, halved until the
@@ -499,6 +510,7 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     fa.vis_cnt = ix->vis_cnt;
     fa.F = ix->F;
     fa.d = di;
+    use_mx_prune(ix, fa);
     HIP_TRY(launch_maint(MK_FORWARD, d, fa, p.max_i, maint_waves_per_block(fa), s));
   }
   // P3: repair of the live out-neighbors of the deleted nodes, (a, u) order
@@ -578,6 +590,7 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
       ga.vcap = std::max(ga.vcap, R);
       ga.d = di;
       ga.d.skip = G_FAIL | G_BOOT;
+      use_mx_prune(ix, ga);
       HIP_TRY(launch_maint(MK_REFINE, d, ga, p.max_i, maint_waves_per_block(ga), s));
     }
     Dyn de;
@@ -710,6 +723,11 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   d.R = c.R;
   d.a2 = c.alpha_num * c.alpha_num;
   d.b2 = c.alpha_den * c.alpha_den;
+  {
+    const uint64_t dmax = (uint64_t)c.dim * 255u * 255u;  // largest uint8 squared distance
+    d.cmp32 = c.metric == ETALE_METRIC_L2_U8 && dmax < (1ull << 24) && d.a2 < (1u << 24) && d.b2 < (1u << 24) &&
+              (uint64_t)std::max(d.a2, d.b2) * dmax < (1ull << 32);
+  }
   d.publish_attempts = c.publish_attempts;
   d.fence = 0;  // every call is a round-synchronous launch sequence
   d.concurrent = 0;

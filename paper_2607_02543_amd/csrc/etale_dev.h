@@ -84,6 +84,7 @@ enum ErrorBits : uint64_t { ERR_POOL_EMPTY = 1, ERR_POOL_OVERFLOW = 2, ERR_BAD_L
 struct Index {
   uint32_t dim, R;
   uint32_t a2, b2;  // alpha = a/b, applied squared: a^2 * D1 <= b^2 * D2
+  uint32_t cmp32;   // 1: uint8 distances and both products stay below 2^32 (24-bit multiplies suffice)
   uint32_t publish_attempts;
   uint32_t fence;   // 1: a release fence orders a slab's contents before its reference (concurrent readers)
   uint32_t concurrent;  // 1: searches may run alongside writers: slab ids are read with agent-coherent loads
@@ -716,8 +717,12 @@ struct PruneLds {
   uint8_t* kill;    // [rows] per-candidate prune flags (FP32 rows)
   uint32_t* out_ids;  // [R]
   uint32_t* out_d;    // [R] stored distances (uint32 for uint8 rows, FP32 bits for float)
+  // matrix-core selection (uint8 rows; vec, norm and idx are then not carved):
+  uint32_t* M;   // [64 * 63 / 2 + 1] distances between the candidates of one tile; null: staged rows
+  uint32_t* tn;  // [64] shifted squared norms of the tile's candidates
+  uint32_t* kn;  // [R] shifted squared norms of the kept candidates
   int nsort;
-  int rows;  // staging rows: keys2, vec and norm hold this many candidates
+  int rows;  // keys2 (and, when staged, vec and norm) hold this many candidates
   int vstride;
 };
 
@@ -756,8 +761,11 @@ __device__ inline void wave_bitonic_sort(uint64_t* keys, int np) {
 // registers (up to 128 candidates; more take the one-at-a-time selection)
 constexpr int PRUNE_TILES = 2;
 
+// Steps 1-2 of RobustPrune on uint8 rows: the admissible candidates (not p,
+// not flagged) by (D(p,c), id), duplicates dropped, at most prune_cap, into
+// s.keys2; returns their count.
 template <int G>
-__device__ inline int robust_prune_u8(const Index& ix, uint32_t p, const uint32_t* cand, int n, PruneLds& s) {
+__device__ inline int prune_rank_u8(const Index& ix, uint32_t p, const uint32_t* cand, int n, PruneLds& s) {
   constexpr int VPP = 64 / G;
   const int l = lane_id();
   const int c = l % G, grp = l / G;
@@ -765,21 +773,22 @@ __device__ inline int robust_prune_u8(const Index& ix, uint32_t p, const uint32_
   const uint4 pf = load_frag<G>(prow);
   const uint32_t pp = group_sum<G>(dot16(pf, pf, 0u));
   const int np = next_pow2_ge64(n);
-  // 1. keys (D(p,c), c) for admissible candidates
+  // 1. keys (D(p,c), c) for admissible candidates; a candidate's row and its
+  // reference word (for the flag) are read together
   for (int base = 0; base < np; base += 4 * VPP) {
     uint4 v[4];
     uint32_t id[4];
+    uint64_t rf[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       int vi = base + u * VPP + grp;
       id[u] = vi < n ? cand[vi] : NONE;
       if (id[u] == p) id[u] = NONE;
       v[u] = make_uint4(0, 0, 0, 0);
+      rf[u] = 0;
       if (id[u] != NONE) {
-        if (ref_del(load_ref(ix, id[u])))
-          id[u] = NONE;
-        else
-          v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim)[c];
+        rf[u] = load_ref(ix, id[u]);
+        v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)id[u] * ix.dim)[c];
       }
     }
 #pragma unroll
@@ -787,7 +796,8 @@ __device__ inline int robust_prune_u8(const Index& ix, uint32_t p, const uint32_
       uint32_t px = group_sum<G>(dot16(pf, v[u], 0u));
       uint32_t xx = group_sum<G>(dot16(v[u], v[u], 0u));
       int vi = base + u * VPP + grp;
-      if (c == 0 && vi < np) s.keys[vi] = id[u] == NONE ? KEY_NONE : make_key(pp + xx - 2u * px, id[u]);
+      const bool none = id[u] == NONE || ref_del(rf[u]);
+      if (c == 0 && vi < np) s.keys[vi] = none ? KEY_NONE : make_key(pp + xx - 2u * px, id[u]);
     }
   }
   wave_sync();
@@ -806,6 +816,15 @@ __device__ inline int robust_prune_u8(const Index& ix, uint32_t p, const uint32_
   wave_sync();
   if (m > (int)ix.prune_cap) m = (int)ix.prune_cap;
   if (m > s.rows) m = s.rows;
+  return m;
+}
+
+template <int G>
+__device__ inline int robust_prune_u8(const Index& ix, uint32_t p, const uint32_t* cand, int n, PruneLds& s) {
+  constexpr int VPP = 64 / G;
+  const int l = lane_id();
+  const int c = l % G, grp = l / G;
+  const int m = prune_rank_u8<G>(ix, p, cand, n, s);
   // 3. stage the survivors' vectors (and norms) in LDS
   for (int base = 0; base < m; base += VPP) {
     int vi = base + grp;

@@ -10,6 +10,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 namespace etale {
 
@@ -1459,6 +1460,10 @@ __global__ void __launch_bounds__(256) k_search(Index ix, SearchArgs a) {
 }
 
 // ---- LDS carving for the maintenance kernels ------------------------------------------
+// words of the matrix-core prune's distance table (64 x 63 / 2 pairs, plus the
+// diagonal's index one past them), rounded up to 16 bytes
+constexpr uint32_t MX_M_WORDS = (64u * 63u / 2u + 1u + 3u) & ~3u;
+
 struct MaintLds {
   PruneLds pr;
   uint32_t* cand;   // [nmax]
@@ -1477,12 +1482,25 @@ __device__ inline MaintLds carve(char* base, const MaintArgs& a, uint32_t R) {
   p += (size_t)a.nsort * 8;
   m.pr.keys2 = reinterpret_cast<uint64_t*>(p);
   p += (size_t)a.prune_cap * 8;
-  m.pr.vec = reinterpret_cast<uint8_t*>(p);
-  p += (size_t)a.prune_cap * a.vstride;
-  m.pr.norm = reinterpret_cast<uint32_t*>(p);
-  p += (size_t)a.prune_cap * 4;
-  m.pr.idx = reinterpret_cast<uint32_t*>(p);
-  p += (size_t)a.prune_cap * 4;
+  m.pr.M = m.pr.tn = m.pr.kn = nullptr;
+  m.pr.vec = nullptr;
+  m.pr.norm = m.pr.idx = nullptr;
+  if (a.mx) {  // the matrix-core selection: a distance table instead of staged rows
+    p = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + 15u) & ~(uintptr_t)15u);
+    m.pr.M = reinterpret_cast<uint32_t*>(p);
+    p += (size_t)MX_M_WORDS * 4;
+    m.pr.tn = reinterpret_cast<uint32_t*>(p);
+    p += 64 * 4;
+    m.pr.kn = reinterpret_cast<uint32_t*>(p);
+    p += 64 * 4;
+  } else {
+    m.pr.vec = reinterpret_cast<uint8_t*>(p);
+    p += (size_t)a.prune_cap * a.vstride;
+    m.pr.norm = reinterpret_cast<uint32_t*>(p);
+    p += (size_t)a.prune_cap * 4;
+    m.pr.idx = reinterpret_cast<uint32_t*>(p);
+    p += (size_t)a.prune_cap * 4;
+  }
   m.pr.out_ids = reinterpret_cast<uint32_t*>(p);
   p += (size_t)(R + 1) * 4;
   m.pr.out_d = reinterpret_cast<uint32_t*>(p);
@@ -1526,6 +1544,216 @@ __device__ inline void copy_out(const MaintLds& m, uint32_t n) {
   wave_sync();
 }
 
+// ---- RobustPrune's ordered selection over cached distances ----------------------------
+// The alpha test a^2 D(kept, x) <= b^2 D(p, x) on exact integer distances:
+// 24-bit multiplies into 32 bits where every uint8 distance and both
+// products fit (Index::cmp32, checked at create), 64-bit products otherwise.
+template <bool C32>
+struct AlphaT {
+  using T = typename std::conditional<C32, uint32_t, uint64_t>::type;
+  __device__ static T scale(uint32_t c, uint32_t d) {
+    if constexpr (C32)
+      return __umul24(c, d);
+    else
+      return (uint64_t)c * (uint64_t)d;
+  }
+};
+
+// Lane x holds candidate x (candidates in rank order) with thr = b^2 D(p, x).
+// The candidates of `rest` are decided in order, four at a time: dist(j)
+// gives this lane's cached D(j, x) (read for the four together), and a
+// candidate covered by an earlier one of the four is skipped; a kept j
+// (keep(j, rank)) drops every later candidate it covers. Returns the kept
+// count, at most R: the result of the one-at-a-time selection.
+template <bool C32, class Dist, class Keep>
+__device__ inline uint32_t select_in_order(uint64_t rest, uint32_t R, uint32_t a2, typename AlphaT<C32>::T thr,
+                                           Dist dist, Keep keep) {
+  uint32_t cnt = 0;
+  while (cnt < R && rest) {
+    int j[4];
+    uint32_t d[4];
+    uint64_t m = rest;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      j[k] = m ? (int)__builtin_ctzll(m) : -1;
+      if (m) m &= m - 1ull;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) d[k] = j[k] >= 0 ? dist(j[k]) : 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (j[k] < 0 || cnt >= R) break;
+      if (!((rest >> j[k]) & 1ull)) continue;  // covered by an earlier one of the four
+      keep(j[k], cnt);
+      ++cnt;
+      const uint64_t above = j[k] == 63 ? 0ull : (~0ull << (j[k] + 1));
+      const uint64_t kill = ballot(AlphaT<C32>::scale(a2, d[k]) <= thr) & rest & above;
+      rest &= ~kill & ~(1ull << j[k]);
+    }
+    // every candidate up to the last of the four is decided
+    const int last = j[3] >= 0 ? j[3] : 63;
+    rest &= last == 63 ? 0ull : (~0ull << (last + 1));
+  }
+  return cnt;
+}
+
+// ---- RobustPrune on the matrix cores (uint8 rows, dim <= 128, R <= 32) ------------------
+// The ranked candidates (prune_rank_u8) are decided in tiles of 64, in rank
+// order, without staging their rows in LDS:
+//   - the distances between the tile's candidates come from
+//     v_mfma_i32_16x16x64_i8 tiles over the rows shifted to signed bytes
+//     (exact int32, as everywhere: the shift leaves every difference
+//     unchanged), the diagonal tiles giving the shifted norms; they go to a
+//     triangular table in LDS;
+//   - the candidates already kept (all ranked before the tile) are tested
+//     against the whole tile at once, from the same kind of tiles (kept rows x
+//     tile rows): a candidate that one of them covers is dropped;
+//   - the survivors are then decided in order as in the staged selection
+//     (four at a time, reading the table), the kept ones appended.
+// The kept set, its order and the stored distances are exactly those of the
+// one-at-a-time selection.
+__device__ inline v4i32 mx_frag(const Index& ix, uint32_t id, uint32_t off) {
+  v4i32 f = {0, 0, 0, 0};
+  if (id != NONE && off < ix.dim) {
+    const uint4 w = *reinterpret_cast<const uint4*>(ix.x + (size_t)id * ix.dim + off);
+    f = v4i32{(int)(w.x ^ 0x80808080u), (int)(w.y ^ 0x80808080u), (int)(w.z ^ 0x80808080u),
+              (int)(w.w ^ 0x80808080u)};
+  }
+  return f;
+}
+
+// index of the pair (x, y), x < y, in a triangular table
+__device__ inline uint32_t tri_lt(uint32_t x, uint32_t y) { return y * (y - 1u) / 2u + x; }
+
+template <int G>
+__device__ inline int prune_select_mx(const Index& ix, int m, PruneLds& s) {
+  constexpr uint32_t KS = (16u * G + 63u) / 64u;  // 64-byte steps of a row
+  const int l = lane_id();
+  const uint32_t r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u, rb = (uint32_t)(l >> 4) * 4u;
+  const uint64_t a2 = ix.a2, b2 = ix.b2;
+  const int R = (int)ix.R;  // at most 32: two blocks of kept rows
+  int cnt = 0;
+  for (int t0 = 0; t0 < m && cnt < R; t0 += 64) {
+    const int tm = min(64, m - t0);
+    // lane l's candidate (selection), and the tile's rows as matrix operands:
+    // block h, row 16h + l % 16, bytes 64 ks + 16 (l / 16) .. + 15
+    const uint64_t lk = l < tm ? s.keys2[t0 + l] : KEY_NONE;
+    const uint64_t dpl = (uint64_t)key_dist(lk);
+    v4i32 f[4][KS];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int i = h * 16 + (int)r;
+      const uint32_t id = i < tm ? key_id(s.keys2[t0 + i]) : NONE;
+#pragma unroll
+      for (uint32_t ks = 0; ks < KS; ++ks) f[h][ks] = mx_frag(ix, id, ks * 64u + kc);
+    }
+    // 1. the tile against itself. Lane l holds rows 16g + 4 (l / 16) + i
+    // against column 16h + l % 16; the diagonal blocks' diagonals are the
+    // shifted squared norms, stored first
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      v4i32 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (uint32_t ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[g][ks], f[g][ks], acc, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (rb + (uint32_t)i == r) s.tn[g * 16 + (int)r] = (uint32_t)acc[i];
+    }
+    wave_sync();
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const uint4 nr = *reinterpret_cast<const uint4*>(s.tn + g * 16 + (int)rb);
+      const uint32_t nrow[4] = {nr.x, nr.y, nr.z, nr.w};
+#pragma unroll
+      for (int h = g; h < 4; ++h) {
+        v4i32 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (uint32_t ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[g][ks], f[h][ks], acc, 0, 0, 0);
+        const uint32_t col = (uint32_t)h * 16u + r;
+        if ((int)col >= tm) continue;
+        const uint32_t nc = s.tn[col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t row = (uint32_t)g * 16u + rb + (uint32_t)i;
+          if (row < col) s.M[tri_lt(row, col)] = nrow[i] + nc - 2u * (uint32_t)acc[i];
+        }
+      }
+    }
+    uint64_t rest = tm == 64 ? ~0ull : ((1ull << tm) - 1ull);
+    // 2. the kept candidates (blocks of 16 rows) against the tile
+    if (cnt) {
+      const int KB = (cnt + 15) / 16;
+      v4i32 kf[2][KS];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const int k = g * 16 + (int)r;
+        const uint32_t id = g < KB && k < cnt ? s.out_ids[k] : NONE;
+#pragma unroll
+        for (uint32_t ks = 0; ks < KS; ++ks) kf[g][ks] = mx_frag(ix, id, ks * 64u + kc);
+      }
+      uint32_t nkv[2][4];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const uint4 nk = *reinterpret_cast<const uint4*>(s.kn + g * 16 + (int)rb);
+        nkv[g][0] = nk.x;
+        nkv[g][1] = nk.y;
+        nkv[g][2] = nk.z;
+        nkv[g][3] = nk.w;
+      }
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        v4i32 ka[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          if (g >= KB) break;
+#pragma unroll
+          for (uint32_t ks = 0; ks < KS; ++ks) ka[g] = __builtin_amdgcn_mfma_i32_16x16x64_i8(kf[g][ks], f[h][ks], ka[g], 0, 0, 0);
+        }
+        const uint32_t col = (uint32_t)h * 16u + r;
+        bool cov = false;
+        if ((int)col < tm) {
+          const uint32_t nc = s.tn[col];
+          const uint64_t dpc = (uint64_t)key_dist(s.keys2[t0 + (int)col]);
+#pragma unroll
+          for (int g = 0; g < 2; ++g) {
+            if (g >= KB) break;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int k = g * 16 + (int)rb + i;
+              if (k < cnt && a2 * (uint64_t)(nkv[g][i] + nc - 2u * (uint32_t)ka[g][i]) <= b2 * dpc) cov = true;
+            }
+          }
+        }
+        // the four row groups of a column: bits r, r + 16, r + 32, r + 48
+        uint64_t cm = ballot(cov);
+        cm |= cm >> 32;
+        cm |= cm >> 16;
+        rest &= ~((cm & 0xFFFFull) << (16 * h));
+      }
+    }
+    wave_sync();
+    // 3. the survivors in order, four at a time
+    const uint32_t tnl = l < tm ? s.tn[l] : 0u;
+    auto dist = [&](int j) { return l > j ? s.M[tri_lt((uint32_t)j, (uint32_t)l)] : 0u; };
+    auto keep = [&](int j, uint32_t rank) {
+      const uint64_t kj = bcast_lane64(lk, j);
+      const uint32_t nj = (uint32_t)__builtin_amdgcn_readlane((int)tnl, j);
+      if (l == 0) {
+        s.out_ids[cnt + (int)rank] = key_id(kj);
+        s.out_d[cnt + (int)rank] = key_dist(kj);
+        s.kn[cnt + (int)rank] = nj;
+      }
+    };
+    const uint32_t left = (uint32_t)(R - cnt);
+    if (ix.cmp32)
+      cnt += (int)select_in_order<true>(rest, left, ix.a2, AlphaT<true>::scale(ix.b2, (uint32_t)dpl), dist, keep);
+    else
+      cnt += (int)select_in_order<false>(rest, left, ix.a2, AlphaT<false>::scale(ix.b2, (uint32_t)dpl), dist, keep);
+    wave_sync();
+  }
+  return cnt;
+}
+
 // ---- per-metric maintenance policy --------------------------------------------------------
 // prune: RobustPrune; dist1: the exact stored distance between two rows (the
 // bit pattern kept in a slab); kd: a stored distance as the distance half of a
@@ -1533,6 +1761,9 @@ __device__ inline void copy_out(const MaintLds& m, uint32_t n) {
 template <int G>
 struct MaintU8 {
   __device__ static int prune(const Index& ix, uint32_t p, const uint32_t* cand, int n, PruneLds& s) {
+    if constexpr (G <= 8) {
+      if (s.M) return prune_select_mx<G>(ix, prune_rank_u8<G>(ix, p, cand, n, s), s);
+    }
     return robust_prune_u8<G>(ix, p, cand, n, s);
   }
   __device__ static uint32_t dist1(const Index& ix, uint32_t w, uint32_t v, uint32_t* tmp, uint64_t* ck) {
@@ -1591,7 +1822,7 @@ __device__ inline void forward_one(const Index& ix, const MaintArgs& a, MaintLds
 }
 
 template <class P>
-__global__ void __launch_bounds__(256) k_forward(Index ix, MaintArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_forward(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, a.d)) return;
   resolve(ix, a);
@@ -1949,34 +2180,18 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
     // the selection in order, four live candidates per step (their distances
     // read together, then decided in order; one killed by an earlier one of
     // the four is skipped)
-    uint32_t cnt = 0, ns = 0;
-    const uint64_t thr = (uint64_t)ix.b2 * (uint64_t)cdw;
-    uint64_t rest = alive;
-    while (cnt < R && rest) {
-      int j[4];
-      uint32_t d[4];
-      uint64_t m = rest;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        j[k] = m ? (int)__builtin_ctzll(m) : -1;
-        if (m) m &= m - 1ull;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        d[k] = j[k] >= 0 ? c.M[tri((uint32_t)__builtin_amdgcn_readlane((int)cs, j[k]), cs)] : 0u;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (j[k] < 0 || cnt >= R) break;
-        if (!((rest >> j[k]) & 1ull)) continue;
-        if ((uint32_t)l == cnt) ns = (uint32_t)__builtin_amdgcn_readlane((int)cs, j[k]);
-        ++cnt;
-        const uint64_t above = j[k] == 63 ? 0ull : (~0ull << (j[k] + 1));
-        const uint64_t kill = ballot((uint64_t)ix.a2 * d[k] <= thr) & rest & above;
-        rest &= ~kill & ~(1ull << j[k]);
-      }
-      const int last = j[3] >= 0 ? j[3] : 63;
-      rest &= last == 63 ? 0ull : (~0ull << (last + 1));
-    }
+    uint32_t ns = 0;
+    const uint32_t tb = cs * (cs - 1u) / 2u;  // this lane's row of the triangular table
+    auto dist = [&](int j) {
+      const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)cs, j);
+      return c.M[sj < cs ? tb + sj : sj * (sj - 1u) / 2u + cs];
+    };
+    auto keep = [&](int j, uint32_t rank) {
+      const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)cs, j);
+      if ((uint32_t)l == rank) ns = sj;
+    };
+    const uint32_t cnt = ix.cmp32 ? select_in_order<true>(alive, R, ix.a2, AlphaT<true>::scale(ix.b2, cdw), dist, keep)
+                                  : select_in_order<false>(alive, R, ix.a2, AlphaT<false>::scale(ix.b2, cdw), dist, keep);
     // the kept candidates, in order, are the new list
     wave_sync();
     if ((uint32_t)l < cnt) c.order[l] = ns;
@@ -2106,16 +2321,46 @@ __device__ inline void refine_one(const Index& ix, const MaintArgs& a, MaintLds&
   const uint32_t own = load_list(ix, v, m.nl_id, m.nl_d);
   if ((uint32_t)l < own) m.cand[l] = m.nl_id[l];
   uint32_t nc = own;
-  for (uint32_t j = 0; j < own; ++j) {
-    const uint32_t w = m.nl_id[j];
-    const uint64_t r = bcast64(load_ref(ix, w));
-    const uint32_t dw = ref_deg(r), s = ref_slab(r);
-    uint32_t b = NONE;
-    if ((uint32_t)l < dw && s != NONE) b = ix.slabs[(size_t)s * 2u * ix.R + (uint32_t)l];
-    const bool extra = b >= a.first && b < end && b != v;
-    const uint64_t bm = ballot(extra);
-    if (extra) m.cand[nc + lanes_below(bm)] = b;
-    nc += (uint32_t)__popcll(bm);
+  const uint32_t R = ix.R;
+  if (2u * R <= 64u) {
+    // every entry's reference word at once (lane j: entry j), then all their
+    // slabs' ids, two entries per load (lanes [0, R): entry 2i, [R, 2R):
+    // entry 2i + 1), before any is used; same-batch ids appended in entry order
+    const uint64_t rj = (uint32_t)l < own ? load_ref(ix, m.nl_id[l]) : 0ull;
+    const bool hi = (uint32_t)l >= R;
+    const uint32_t slot = hi ? (uint32_t)l - R : (uint32_t)l;
+    uint32_t b[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      b[i] = NONE;
+      if (2u * (uint32_t)i >= own) continue;
+      const uint64_t r0 = bcast_lane64(rj, 2 * i), r1 = bcast_lane64(rj, 2 * i + 1);
+      const uint64_t r = hi ? r1 : r0;
+      const uint32_t dw = 2u * (uint32_t)i + (hi ? 1u : 0u) < own ? ref_deg(r) : 0u, s = ref_slab(r);
+      if ((uint32_t)l < 2u * R && slot < dw && s != NONE) b[i] = ix.slabs[(size_t)s * 2u * R + slot];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (2u * (uint32_t)i >= own) break;
+      const bool extra = b[i] >= a.first && b[i] < end && b[i] != v;
+      const uint64_t e0 = ballot(extra && !hi), e1 = ballot(extra && hi);
+      if (extra && !hi) m.cand[nc + lanes_below(e0)] = b[i];
+      nc += (uint32_t)__popcll(e0);
+      if (extra && hi) m.cand[nc + lanes_below(e1)] = b[i];
+      nc += (uint32_t)__popcll(e1);
+    }
+  } else {
+    for (uint32_t j = 0; j < own; ++j) {
+      const uint32_t w = m.nl_id[j];
+      const uint64_t r = bcast64(load_ref(ix, w));
+      const uint32_t dw = ref_deg(r), s = ref_slab(r);
+      uint32_t b = NONE;
+      if ((uint32_t)l < dw && s != NONE) b = ix.slabs[(size_t)s * 2u * R + (uint32_t)l];
+      const bool extra = b >= a.first && b < end && b != v;
+      const uint64_t bm = ballot(extra);
+      if (extra) m.cand[nc + lanes_below(bm)] = b;
+      nc += (uint32_t)__popcll(bm);
+    }
   }
   wave_sync();
   uint32_t cnt = NONE;  // unchanged
@@ -2134,7 +2379,7 @@ __device__ inline void refine_one(const Index& ix, const MaintArgs& a, MaintLds&
 // are computed into the insert searches' scratch first (k_refine), then
 // published (k_refine_publish).
 template <class P>
-__global__ void __launch_bounds__(256) k_refine(Index ix, MaintArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_refine(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, a.d)) return;
   resolve(ix, a);
@@ -2386,24 +2631,26 @@ template <int G>
 __device__ inline void pool_stage(const Index& ix, const PoolLds& p, const uint32_t* slots, int cnt, uint4 wf,
                                   uint32_t ww) {
   constexpr int VPP = 64 / G;
+  // rows per lane in flight together
+  constexpr int U = G < 4 ? G : 4;
   const int l = lane_id();
   const int ch = l % G, grp = l / G;
   const uint4 ones = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
   uint64_t ref = 0;
   const uint32_t my = l < cnt ? slots[l] : 0u;
   if (l < cnt) ref = load_ref(ix, p.id[my]);
-  for (int base = 0; base < cnt; base += 4 * VPP) {
-    uint4 v[4];
-    int sl[4];
+  for (int base = 0; base < cnt; base += U * VPP) {
+    uint4 v[U];
+    int sl[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int k = base + u * VPP + grp;
       sl[u] = k < cnt ? (int)slots[k] : -1;
       v[u] = make_uint4(0, 0, 0, 0);
       if (sl[u] >= 0) v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)p.id[sl[u]] * ix.dim)[ch];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const uint32_t nn = group_sum<G>(dot16(v[u], v[u], 0u));
       const uint32_t sm = group_sum<G>(dot16(v[u], ones, 0u));
       const uint32_t dt = group_sum<G>(dot16(wf, v[u], 0u));
@@ -2433,37 +2680,81 @@ __device__ inline v4i32 pool_frag(const Index& ix, const PoolLds& p, uint32_t sl
   return f;
 }
 
-__device__ inline void pool_fill(const Index& ix, const PoolLds& p, const uint32_t* fresh, uint32_t nf, uint64_t occ) {
+// lane l holds fresh rows f0 + 4 (l / 16) + i against slot 16 st + l % 16
+__device__ inline void pool_store(const PoolLds& p, const uint32_t* fresh, uint32_t nf, uint64_t occ, uint32_t f0,
+                                  const v4i32 (&acc)[4]) {
   const int l = lane_id();
-  const uint32_t r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u, rb = (uint32_t)(l >> 4) * 4u;
-  for (uint32_t f0 = 0; f0 < nf; f0 += 16) {
-    const uint32_t fa = f0 + r < nf ? fresh[f0 + r] : 0u;
-    v4i32 acc[4];
+  const uint32_t r = (uint32_t)(l & 15), rb = (uint32_t)(l >> 4) * 4u;
 #pragma unroll
-    for (int st = 0; st < 4; ++st) acc[st] = v4i32{0, 0, 0, 0};
-    for (uint32_t k0 = 0; k0 < ix.dim; k0 += 64) {
-      const v4i32 fa_frag = pool_frag(ix, p, fa, f0 + r < nf, k0 + kc);
+  for (int st = 0; st < 4; ++st) {
+    const uint32_t sb = (uint32_t)st * 16u + r;
+    if (!((occ >> sb) & 1ull)) continue;
+    const uint32_t nb = p.norm[sb];
 #pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const uint32_t sb = (uint32_t)st * 16u + r;
-        acc[st] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa_frag, pool_frag(ix, p, sb, (occ >> sb) & 1ull, k0 + kc),
-                                                        acc[st], 0, 0, 0);
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t fi = f0 + rb + (uint32_t)i;
+      if (fi < nf) {
+        const uint32_t fs = fresh[fi];
+        if (fs != sb) p.M[tri(fs, sb)] = p.norm[fs] + nb - 2u * (uint32_t)acc[st][i];
       }
     }
-    // lane l holds fresh rows f0 + rb + i against slot 16 st + r
+  }
+}
+
+template <int G>
+__device__ inline void pool_fill(const Index& ix, const PoolLds& p, const uint32_t* fresh, uint32_t nf, uint64_t occ) {
+  const int l = lane_id();
+  const uint32_t r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u;
+  constexpr uint32_t KS = (16u * G + 63u) / 64u;  // 64-byte steps of a row
+  if constexpr (KS <= 2) {
+    // rows up to 128 bytes: the slot operands are the same for every block of
+    // 16 fresh rows, so they are read once, all at once, and each block's
+    // fresh operands are read while the previous block's results are stored
+    v4i32 sf[4][KS], ff[KS];
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
       const uint32_t sb = (uint32_t)st * 16u + r;
-      if (!((occ >> sb) & 1ull)) continue;
-      const uint32_t nb = p.norm[sb];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t fi = f0 + rb + (uint32_t)i;
-        if (fi < nf) {
-          const uint32_t fs = fresh[fi];
-          if (fs != sb) p.M[tri(fs, sb)] = p.norm[fs] + nb - 2u * (uint32_t)acc[st][i];
+      for (uint32_t ks = 0; ks < KS; ++ks) sf[st][ks] = pool_frag(ix, p, sb, (occ >> sb) & 1ull, ks * 64u + kc);
+    }
+    {
+      const uint32_t fa = r < nf ? fresh[r] : 0u;
+#pragma unroll
+      for (uint32_t ks = 0; ks < KS; ++ks) ff[ks] = pool_frag(ix, p, fa, r < nf, ks * 64u + kc);
+    }
+    for (uint32_t f0 = 0; f0 < nf; f0 += 16) {
+      v4i32 acc[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        acc[st] = v4i32{0, 0, 0, 0};
+#pragma unroll
+        for (uint32_t ks = 0; ks < KS; ++ks)
+          acc[st] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ff[ks], sf[st][ks], acc[st], 0, 0, 0);
+      }
+      if (f0 + 16u < nf) {  // the next block's operands travel while this block's results are stored
+        const uint32_t nx = f0 + 16u + r;
+        const uint32_t fa = nx < nf ? fresh[nx] : 0u;
+#pragma unroll
+        for (uint32_t ks = 0; ks < KS; ++ks) ff[ks] = pool_frag(ix, p, fa, nx < nf, ks * 64u + kc);
+      }
+      pool_store(p, fresh, nf, occ, f0, acc);
+    }
+  } else {
+    for (uint32_t f0 = 0; f0 < nf; f0 += 16) {
+      const uint32_t fa = f0 + r < nf ? fresh[f0 + r] : 0u;
+      v4i32 acc[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) acc[st] = v4i32{0, 0, 0, 0};
+      for (uint32_t k0 = 0; k0 < ix.dim; k0 += 64) {
+        const v4i32 fa_frag = pool_frag(ix, p, fa, f0 + r < nf, k0 + kc);
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const uint32_t sb = (uint32_t)st * 16u + r;
+          acc[st] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa_frag, pool_frag(ix, p, sb, (occ >> sb) & 1ull, k0 + kc),
+                                                          acc[st], 0, 0, 0);
         }
       }
+      pool_store(p, fresh, nf, occ, f0, acc);
     }
   }
   wave_sync();
@@ -2519,39 +2810,21 @@ __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const u
   if (mm > cap) mm = cap;
   const uint32_t csl = (uint32_t)l < mm ? p.sorted[l] : 0u;
   const uint32_t cdw = (uint32_t)l < mm ? p.dw[csl] : 0u;
-  uint64_t alive = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
-  uint32_t cnt = 0, keep_slot = 0;
-  // the selection in order of rank; the distances from the next four live
-  // candidates are read together and the four are then decided in order
-  // (one killed by an earlier one of the four is skipped)
-  const uint64_t thr = (uint64_t)ix.b2 * (uint64_t)cdw;
-  uint64_t rest = alive;  // live candidates not yet decided
-  while (cnt < ix.R && rest) {
-    int j[4];
-    uint32_t d[4];
-    uint64_t m = rest;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      j[k] = m ? (int)__builtin_ctzll(m) : -1;
-      if (m) m &= m - 1ull;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      d[k] = j[k] >= 0 ? p.M[tri((uint32_t)__builtin_amdgcn_readlane((int)csl, j[k]), csl)] : 0u;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (j[k] < 0 || cnt >= ix.R) break;
-      if (!((rest >> j[k]) & 1ull)) continue;  // killed by an earlier one of the four
-      if ((uint32_t)l == cnt) keep_slot = (uint32_t)__builtin_amdgcn_readlane((int)csl, j[k]);
-      ++cnt;
-      const uint64_t above = j[k] == 63 ? 0ull : (~0ull << (j[k] + 1));
-      const uint64_t kill = ballot((uint64_t)ix.a2 * d[k] <= thr) & rest & above;
-      rest &= ~kill & ~(1ull << j[k]);
-    }
-    // every candidate up to the last of the four is decided
-    const int last = j[3] >= 0 ? j[3] : 63;
-    rest &= last == 63 ? 0ull : (~0ull << (last + 1));
-  }
+  const uint64_t alive = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
+  uint32_t keep_slot = 0;
+  // the selection in order of rank over the cached distances (the slot of
+  // the k-th kept candidate lands in lane k)
+  const uint32_t tb = csl * (csl - 1u) / 2u;  // this lane's row of the triangular table
+  auto dist = [&](int j) {
+    const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)csl, j);
+    return p.M[sj < csl ? tb + sj : sj * (sj - 1u) / 2u + csl];
+  };
+  auto take = [&](int j, uint32_t rank) {
+    const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)csl, j);
+    if ((uint32_t)l == rank) keep_slot = sj;
+  };
+  const uint32_t cnt = ix.cmp32 ? select_in_order<true>(alive, ix.R, ix.a2, AlphaT<true>::scale(ix.b2, cdw), dist, take)
+                                : select_in_order<false>(alive, ix.R, ix.a2, AlphaT<false>::scale(ix.b2, cdw), dist, take);
   wave_sync();
   if ((uint32_t)l < cnt) out[l] = keep_slot;
   wave_sync();
@@ -2653,7 +2926,7 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
       occ |= 1ull << (uint32_t)__builtin_amdgcn_readlane(at, (int)__builtin_ctzll(m2));
     if (nf) {
       pool_stage<G>(ix, p, fs, (int)nf, wf, ww);
-      pool_fill(ix, p, fs, nf, occ);
+      pool_fill<G>(ix, p, fs, nf, occ);
     }
     first = false;
     // K = RobustPrune(a, B)
@@ -2705,7 +2978,7 @@ __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
 // so waves take them from a queue in batches, each batch with its own slab
 // reservation (one fresh and one retired slab per target).
 template <int G>
-__global__ void __launch_bounds__(256) k_repair_pool(Index ix, MaintArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_repair_pool(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, a.d)) return;
   resolve(ix, a);
@@ -3598,8 +3871,10 @@ uint32_t chain_lds_per_wave(uint32_t R, uint32_t vstride) { return chain_lds_byt
 uint32_t pool_lds_per_wave(uint32_t vstride) { return pool_lds_bytes(vstride); }
 
 uint32_t maint_lds_per_wave(const MaintArgs& a, uint32_t R) {
-  size_t b = (size_t)a.nsort * 8 + (size_t)a.prune_cap * 8 + (size_t)a.prune_cap * a.vstride + (size_t)a.prune_cap * 8 +
-             (size_t)(R + 1) * 8 + (size_t)a.nmax * 4 + (size_t)(R + 1) * 12 + (size_t)a.prune_cap;
+  const size_t sel = a.mx ? 16 + (size_t)MX_M_WORDS * 4 + 2 * 64 * 4  // alignment, table, tile and kept norms
+                          : (size_t)a.prune_cap * a.vstride + (size_t)a.prune_cap * 8;  // staged rows, norms
+  size_t b = (size_t)a.nsort * 8 + (size_t)a.prune_cap * 8 + sel + (size_t)(R + 1) * 8 + (size_t)a.nmax * 4 +
+             (size_t)(R + 1) * 12 + (size_t)a.prune_cap;
   return (uint32_t)((b + 15) & ~(size_t)15);
 }
 

@@ -79,6 +79,7 @@ struct MaintArgs {
   const uint32_t* seg;     // starts of the runs of one target in the sorted pairs
   uint32_t np_ctr = NO_CTR, np_mult = 1;  // launch-time pair count
   uint32_t chain = 0;      // reverse edges: cached candidate state (uint8 rows, R <= 32)
+  uint32_t mx = 0;         // RobustPrune selection on the matrix cores (uint8 rows, dim <= 128, R <= 32)
   Dyn d;                   // launch-time count (n) and first id
 };
 
