@@ -2760,6 +2760,83 @@ __device__ inline void pool_fill(const Index& ix, const PoolLds& p, const uint32
   wave_sync();
 }
 
+// The first (target, deleted neighbor) pair of a chain fills the whole pool
+// at once: slots 0..n-1 hold the target's list (lane x: entry x, whose stored
+// distance to the target is rho), slots n..nf-1 the new members of B. All
+// slots' rows are read once as matrix operands (with the target's row), and
+// the matrix cores give every slot's shifted norm (diagonal tiles), its
+// distance to the target where no stored one exists (target row x slot
+// tiles), and each pair's distance once (tiles g <= h), for the same table
+// the general fill writes.
+template <int G>
+__device__ inline void pool_first(const Index& ix, const PoolLds& p, uint32_t n, uint32_t nf, uint32_t an,
+                                  uint32_t rho) {
+  constexpr uint32_t KS = (16u * G + 63u) / 64u;
+  const int l = lane_id();
+  const uint32_t r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u, rb = (uint32_t)(l >> 4) * 4u;
+  const uint64_t ref = (uint32_t)l < nf ? load_ref(ix, p.id[l]) : 0ull;
+  v4i32 f[4][KS], fa[KS];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const uint32_t sl = (uint32_t)h * 16u + r;
+    const uint32_t id = sl < nf ? p.id[sl] : NONE;
+#pragma unroll
+    for (uint32_t ks = 0; ks < KS; ++ks) f[h][ks] = mx_frag(ix, id, ks * 64u + kc);
+  }
+#pragma unroll
+  for (uint32_t ks = 0; ks < KS; ++ks) fa[ks] = mx_frag(ix, an, ks * 64u + kc);
+  // shifted norms of the slots and of the target
+  v4i32 aa = {0, 0, 0, 0};
+#pragma unroll
+  for (uint32_t ks = 0; ks < KS; ++ks) aa = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[ks], fa[ks], aa, 0, 0, 0);
+  const uint32_t na = (uint32_t)aa[0];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    v4i32 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (uint32_t ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[g][ks], f[g][ks], acc, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (rb + (uint32_t)i == r) p.norm[g * 16 + (int)r] = (uint32_t)acc[i];
+  }
+  wave_sync();
+  // distances to the target: stored for the list, from the tiles for the rest
+  // (every row of the target's tile is the target: lanes 0..15 hold column r)
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    v4i32 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (uint32_t ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[ks], f[h][ks], acc, 0, 0, 0);
+    const uint32_t sl = (uint32_t)h * 16u + r;
+    if (l < 16 && sl >= n && sl < nf) p.dw[sl] = na + p.norm[sl] - 2u * (uint32_t)acc[0];
+  }
+  if ((uint32_t)l < n) p.dw[l] = rho;
+  // every pair once
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const uint4 nr = *reinterpret_cast<const uint4*>(p.norm + g * 16 + (int)rb);
+    const uint32_t nrow[4] = {nr.x, nr.y, nr.z, nr.w};
+#pragma unroll
+    for (int h = g; h < 4; ++h) {
+      if ((uint32_t)h * 16u >= nf) break;
+      v4i32 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (uint32_t ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[g][ks], f[h][ks], acc, 0, 0, 0);
+      const uint32_t col = (uint32_t)h * 16u + r;
+      if (col >= nf) continue;
+      const uint32_t nc = p.norm[col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t row = (uint32_t)g * 16u + rb + (uint32_t)i;
+        if (row < col) p.M[tri_lt(row, col)] = nrow[i] + nc - 2u * (uint32_t)acc[i];
+      }
+    }
+  }
+  wave_sync();
+  if ((uint32_t)l < nf && ref_del(ref)) p.dw[l] |= DW_DEAD;
+  wave_sync();
+}
+
 // 64-lane bitonic sort of (key, value) pairs held one per lane, ascending
 template <int K, int J>
 __device__ inline void lane_bitonic_step(uint64_t& key, uint32_t& val) {
@@ -2783,24 +2860,58 @@ __device__ inline void lane_bitonic_stage(uint64_t& key, uint32_t& val) {
 
 __device__ inline void lane_bitonic_sort(uint64_t& key, uint32_t& val) { lane_bitonic_stage<2>(key, val); }
 
-// RobustPrune(self, candidate slots cs[0..m)) into out[0..return); m <= 64.
+// stages 2 .. KMAX only: each run of KMAX lanes sorted (the first ascending)
+template <int K, int KMAX>
+__device__ inline void lane_bitonic_stages(uint64_t& key, uint32_t& val) {
+  lane_bitonic_step<K, K / 2>(key, val);
+  if constexpr (K < KMAX) lane_bitonic_stages<K * 2, KMAX>(key, val);
+}
+
+// How pool_prune ranks its candidates: any order (a full sort), at most 32
+// candidates (a sort of 32 lanes), or two runs each already in (distance, id)
+// order (one bitonic merge: the first run ascending from lane 0, the second
+// descending into the top lanes).
+enum PoolRank { RANK_SORT = 0, RANK_SORT32 = 1, RANK_MERGE = 2 };
+constexpr uint32_t DROP = 0x80000000u;  // a ranked slot that takes no part (itself or flagged)
+
+// RobustPrune(self, candidate slots cs[0..m)) into out[0..return); m <= 64;
+// with RANK_MERGE, cs[0..m1) and cs[m1..m) are the two ordered runs.
 // Candidates are ranked in registers (one per lane); during the selection each
 // lane reads the distance from the kept candidate to its own from the cache.
-__device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const uint32_t* cs, uint32_t m,
+template <int MODE>
+__device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const uint32_t* cs, uint32_t m, uint32_t m1,
                                       uint32_t self, uint32_t* out) {
   const int l = lane_id();
-  uint32_t slot = (uint32_t)l < m ? cs[l] : 0u;
+  uint32_t slot = 0;
   uint64_t key = KEY_NONE;
-  if ((uint32_t)l < m) {
-    const uint32_t id = p.id[slot];
-    const uint32_t w = p.dw[slot];
-    if (id != self && !(w & DW_DEAD)) key = make_key(w, id);
+  if constexpr (MODE == RANK_MERGE) {
+    // the runs keep their order whatever is dropped: a dropped candidate keeps
+    // its key for the merge and carries DROP in its slot word
+    const int src = (uint32_t)l < m1 ? l : (int)m1 + (63 - l);
+    if ((uint32_t)l < m1 || (l >= 64 - (int)(m - m1) && src < (int)m)) {
+      slot = cs[src];
+      const uint32_t id = p.id[slot];
+      const uint32_t w = p.dw[slot];
+      key = make_key(w & ~DW_DEAD, id);
+      if (id == self || (w & DW_DEAD)) slot |= DROP;
+    }
+    lane_bitonic_stages<64, 64>(key, slot);
+  } else {
+    if ((uint32_t)l < m) {
+      slot = cs[l];
+      const uint32_t id = p.id[slot];
+      const uint32_t w = p.dw[slot];
+      if (id != self && !(w & DW_DEAD)) key = make_key(w, id);
+    }
+    if constexpr (MODE == RANK_SORT32)
+      lane_bitonic_stages<2, 32>(key, slot);
+    else
+      lane_bitonic_sort(key, slot);
   }
-  lane_bitonic_sort(key, slot);
   // repeated ids are adjacent with equal keys: one copy stays
   const uint64_t prev_lo = (uint32_t)__shfl_up((int)(uint32_t)key, 1, 64);
   const uint64_t prev_hi = (uint32_t)__shfl_up((int)(uint32_t)(key >> 32), 1, 64);
-  const bool keep = key != KEY_NONE && (l == 0 || ((prev_hi << 32) | prev_lo) != key);
+  const bool keep = key != KEY_NONE && !(slot & DROP) && (l == 0 || ((prev_hi << 32) | prev_lo) != key);
   const uint64_t km = ballot(keep);
   wave_sync();
   if (keep) p.sorted[lanes_below(km)] = slot;
@@ -2875,8 +2986,11 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
   const uint64_t pair1 = bcast_lane64(hd.next, k);
   uint32_t n = ref_slab(ra) == NONE ? 0u : ref_deg(ra);
   uint32_t du = ref_slab(ru) == NONE ? 0u : ref_deg(ru);
-  uint32_t lid = NONE, b = NONE;
-  if ((uint32_t)l < n) lid = ix.slabs[(size_t)ref_slab(ra) * 2u * R + (uint32_t)l];
+  uint32_t lid = NONE, b = NONE, rho = 0;
+  if ((uint32_t)l < n) {
+    lid = ix.slabs[(size_t)ref_slab(ra) * 2u * R + (uint32_t)l];
+    rho = ix.slabs[(size_t)ref_slab(ra) * 2u * R + R + (uint32_t)l];
+  }
   if ((uint32_t)l < du) b = ix.slabs[(size_t)ref_slab(ru) * 2u * R + (uint32_t)l];
   uint32_t lslot = (uint32_t)l;
   if ((uint32_t)l < n) {
@@ -2924,13 +3038,20 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
     uint64_t occ = used;
     for (uint64_t m2 = fm; m2; m2 &= m2 - 1ull)
       occ |= 1ull << (uint32_t)__builtin_amdgcn_readlane(at, (int)__builtin_ctzll(m2));
-    if (nf) {
+    bool filled = false;
+    if constexpr (G <= 8) {  // rows up to 128 bytes: operands in registers
+      if (first) {  // slots 0..nf-1 in order: the list, then B's new members
+        pool_first<G>(ix, p, n, nf, an, rho);
+        filled = true;
+      }
+    }
+    if (!filled && nf) {
       pool_stage<G>(ix, p, fs, (int)nf, wf, ww);
       pool_fill<G>(ix, p, fs, nf, occ);
     }
     first = false;
-    // K = RobustPrune(a, B)
-    const uint32_t kc = pool_prune(ix, p, p.cand, (uint32_t)__popcll(om), an, p.kept);
+    // K = RobustPrune(a, B): at most R <= 32 candidates
+    const uint32_t kc = pool_prune<RANK_SORT32>(ix, p, p.cand, (uint32_t)__popcll(om), 0u, an, p.kept);
     // N = RobustPrune(a, (N \ {u}) U K)
     const uint32_t ks = (uint32_t)l < kc ? p.kept[l] : 0u;
     const bool stay = (uint32_t)l < n && lid != u;
@@ -2940,7 +3061,8 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
     if (stay) p.cand[lanes_below(sm)] = lslot;
     if ((uint32_t)l < kc) p.cand[ns + (uint32_t)l] = ks;
     wave_sync();
-    n = pool_prune(ix, p, p.cand, ns + kc, an, p.list);
+    // the list (without u) and K are each in (distance, id) order already
+    n = pool_prune<RANK_MERGE>(ix, p, p.cand, ns + kc, ns, an, p.list);
     lslot = (uint32_t)l < n ? p.list[l] : 0u;
     lid = (uint32_t)l < n ? p.id[lslot] : NONE;
     // slots not on the new list become free
