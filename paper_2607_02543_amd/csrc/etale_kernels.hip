@@ -1284,12 +1284,21 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     for (int k = 0; k < WMAX; ++k) pre_k[k] = KEY_NONE;
 #pragma unroll
     for (int h = 0; h < H; ++h) pre_nid[h] = NONE;
-    if (nexp < a.vcap && open) {
-      uint64_t pref[WMAX];
+    // read-ahead, first half: the entries the next step should expand and the
+    // reference words they still lack; the words are consumed only after the
+    // visited-table pass, so their latency overlaps it
+    const bool ahead = nexp < a.vcap && open;
+    uint64_t pref[WMAX];
+    int pj[WMAX];
+#pragma unroll
+    for (int k = 0; k < WMAX; ++k) {
+      pref[k] = 0;
+      pj[k] = -1;
+    }
+    if (ahead) {
       uint64_t o = open;
 #pragma unroll
       for (int k = 0; k < WMAX; ++k) {
-        pref[k] = 0;
         if (o && (k == 0 || ((uint32_t)k < a.W && nexp + (uint32_t)k < a.vcap))) {
           const int j = (int)__builtin_ctzll(o);
           o &= o - 1;
@@ -1297,13 +1306,10 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
           pref[k] = bcast_lane64(lr, j);
           if (pref[k] == REF_LAZY) {
             pref[k] = load_ref(ix, key_id(pre_k[k]));
-            if (l == j) lr = pref[k];  // travels with the entry through the merge
+            pj[k] = j;
           }
         }
       }
-#pragma unroll
-      for (int h = 0; h < H; ++h)
-        pre_nid[h] = expansion_ids(ix, pref[2 * h], pref[2 * h + 1], pre_k[2 * h + 1] != KEY_NONE);
     }
     uint32_t vr[H];
     bool fresh[H];
@@ -1321,6 +1327,15 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
       const uint64_t m = ballot(fresh[h]);
       if (fresh[h]) ci[cnt + (int)lanes_below(m)] = nid[h];
       cnt += __popcll(m);
+    }
+    // read-ahead, second half: the slabs' ids, in flight with this step's rows
+    if (ahead) {
+#pragma unroll
+      for (int k = 0; k < WMAX; ++k)
+        if (l == pj[k]) lr = pref[k];  // the word travels with its entry through the merge
+#pragma unroll
+      for (int h = 0; h < H; ++h)
+        pre_nid[h] = expansion_ids(ix, pref[2 * h], pref[2 * h + 1], pre_k[2 * h + 1] != KEY_NONE);
     }
     wave_sync();
     if (!cnt) continue;
@@ -2092,9 +2107,104 @@ __device__ inline void chain_fill_mfma(const Index& ix, const ChainLds& c, uint3
   wave_sync();
 }
 
+// OR of a 64-bit word over the wave, in every lane
+__device__ inline uint64_t wave_or64(uint64_t v) {
+  v |= lane_xor<1>(v);
+  v |= lane_xor<2>(v);
+  v |= lane_xor<4>(v);
+  v |= lane_xor<8>(v);
+  v |= lane_xor<16>(v);
+  v |= lane_xor<32>(v);
+  return v;
+}
+
+// M entries of slot a (row fragment av in the G-lane layout, squared norm na)
+// against slots[0..cnt), their rows read from memory
+template <int G>
+__device__ inline void chain_fill_row_g(const Index& ix, const ChainLds& c, uint32_t a, uint4 av, uint32_t na,
+                                        const uint32_t* slots, int cnt) {
+  constexpr int VPP = 64 / G;
+  const int l = lane_id();
+  const int ch = l % G, grp = l / G;
+  for (int base = 0; base < cnt; base += 4 * VPP) {
+    uint4 v[4];
+    uint32_t sl[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = base + u * VPP + grp;
+      sl[u] = k < cnt ? slots[k] : a;
+      v[u] = make_uint4(0, 0, 0, 0);
+      if (sl[u] != a) v[u] = reinterpret_cast<const uint4*>(ix.x + (size_t)c.id[sl[u]] * ix.dim)[ch];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t dot = group_sum<G>(dot16(av, v[u], 0u));
+      const uint32_t nb = group_sum<G>(dot16(v[u], v[u], 0u));
+      if (ch == 0 && sl[u] != a) c.M[tri(a, sl[u])] = na + nb - 2u * dot;  // the diagonal's word is another pair's
+    }
+  }
+  wave_sync();
+}
+
+// A target's first prune with rows up to 128 bytes: slots 0..S-1 (the list,
+// then the offer) are read once as matrix operands and every pair's distance
+// is computed and stored once (tiles g <= h; shifted bytes, the diagonal
+// tiles giving the norms); the flags of the list entries not known yet
+// (`known`: slots of this launch's offers, all live) are read alongside.
+template <int G>
+__device__ inline void chain_first_mx(const Index& ix, const ChainLds& c, uint32_t S, uint64_t known) {
+  constexpr uint32_t KS = (16u * G + 63u) / 64u;
+  const int l = lane_id();
+  const uint32_t r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u, rb = (uint32_t)(l >> 4) * 4u;
+  const bool need = (uint32_t)l < S && !((known >> l) & 1ull);
+  const uint64_t ref = need ? load_ref(ix, c.id[l]) : 0ull;
+  v4i32 f[3][KS];
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    const uint32_t sl = (uint32_t)h * 16u + r;
+    const uint32_t id = sl < S ? c.id[sl] : NONE;
+#pragma unroll
+    for (uint32_t ks = 0; ks < KS; ++ks) f[h][ks] = mx_frag(ix, id, ks * 64u + kc);
+  }
+  uint32_t* nrm = c.out_d;  // S words of scratch
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    v4i32 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (uint32_t ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[g][ks], f[g][ks], acc, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (rb + (uint32_t)i == r && (uint32_t)g * 16u + r < S) nrm[g * 16 + (int)r] = (uint32_t)acc[i];
+  }
+  wave_sync();
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+#pragma unroll
+    for (int h = g; h < 3; ++h) {
+      if ((uint32_t)h * 16u >= S) break;
+      v4i32 acc = {0, 0, 0, 0};
+#pragma unroll
+      for (uint32_t ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(f[g][ks], f[h][ks], acc, 0, 0, 0);
+      const uint32_t col = (uint32_t)h * 16u + r;
+      if (col >= S) continue;
+      const uint32_t nc = nrm[col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t row = (uint32_t)g * 16u + rb + (uint32_t)i;
+        if (row < col) c.M[tri_lt(row, col)] = nrm[row] + nc - 2u * (uint32_t)acc[i];
+      }
+    }
+  }
+  if (need) c.dead[l] = ref_del(ref);
+  wave_sync();
+}
+
 template <int G>
 __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, const ChainLds& c, uint32_t t,
                                         SlabCursor& cur) {
+  // rows up to 128 bytes: distances from matrix operands and rows in memory,
+  // no row staged in LDS
+  constexpr bool MX = G <= 8;
   const int l = lane_id();
   const int ch = l % G;
   const uint32_t R = ix.R;
@@ -2120,11 +2230,11 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
     if (ballot((uint32_t)l < n && c.id[c.order[l]] == v) != 0ull) continue;  // a set union
     // the offer takes a free slot: its row, norm, flag and distance to w
     const uint32_t f = (uint32_t)__builtin_ctzll(~used);
+    const uint4 vv = reinterpret_cast<const uint4*>(ix.x + (size_t)v * ix.dim)[ch];
+    const uint32_t vn = group_sum<G>(dot16(vv, vv, 0u));
     {
-      const uint4 vv = reinterpret_cast<const uint4*>(ix.x + (size_t)v * ix.dim)[ch];
-      const uint32_t vn = group_sum<G>(dot16(vv, vv, 0u));
       const uint32_t dot = group_sum<G>(dot16(wf, vv, 0u));
-      if (l < G) *reinterpret_cast<uint4*>(c.rows + (size_t)f * c.vstride + ch * 16) = vv;
+      if (!MX && l < G) *reinterpret_cast<uint4*>(c.rows + (size_t)f * c.vstride + ch * 16) = vv;
       if (l == 0) {
         c.id[f] = v;
         c.dead[f] = 0u;  // the round's new nodes are live
@@ -2143,27 +2253,41 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
       if ((uint32_t)l < n && (uint32_t)l >= pos) c.order[l + 1] = sl;
       if (l == 0) c.order[pos] = f;
       wave_sync();
-      if (cached) chain_fill_row<G>(c, f, c.order, (int)n + 1);  // M stays complete
+      if (cached) {  // M stays complete
+        if constexpr (MX)
+          chain_fill_row_g<G>(ix, c, f, vv, vn, c.order, (int)n + 1);
+        else
+          chain_fill_row<G>(c, f, c.order, (int)n + 1);
+      }
       used |= 1ull << f;
       ++n;
       continue;
     }
     // at R: RobustPrune(w, list + v) over the cached state
     if (!cached) {
-      // first prune of this target: rows and flags of the list entries, then all of M
-      const bool need = (uint32_t)l < n && !((staged >> sl) & 1ull);
-      const uint64_t nm = ballot(need);
-      if (need) {
-        c.out_id[lanes_below(nm)] = sl;
-        c.dead[sl] = ref_del(load_ref(ix, c.id[sl]));
+      if constexpr (MX) {
+        // slots 0..n: the list entries and offers kept so far fill slots in
+        // order until the first prune, and the offer takes slot n
+        chain_first_mx<G>(ix, c, n + 1u, staged);
+      } else {
+        // first prune of this target: rows and flags of the list entries, then all of M
+        const bool need = (uint32_t)l < n && !((staged >> sl) & 1ull);
+        const uint64_t nm = ballot(need);
+        if (need) {
+          c.out_id[lanes_below(nm)] = sl;
+          c.dead[sl] = ref_del(load_ref(ix, c.id[sl]));
+        }
+        wave_sync();
+        chain_stage_rows<G>(ix, c, c.out_id, __popcll(nm));
+        staged |= used;
+        chain_fill_mfma(ix, c, c.out_d);  // every staged pair, v's row included
       }
-      wave_sync();
-      chain_stage_rows<G>(ix, c, c.out_id, __popcll(nm));
-      staged |= used;
-      chain_fill_mfma(ix, c, c.out_d);  // every staged pair, v's row included
       cached = true;
     } else {
-      chain_fill_row<G>(c, f, c.order, (int)n);
+      if constexpr (MX)
+        chain_fill_row_g<G>(ix, c, f, vv, vn, c.order, (int)n);
+      else
+        chain_fill_row<G>(c, f, c.order, (int)n);
     }
     // candidates in (distance, id) order: the list with v at position pos
     uint32_t cs = f;
@@ -2195,8 +2319,7 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
     // the kept candidates, in order, are the new list
     wave_sync();
     if ((uint32_t)l < cnt) c.order[l] = ns;
-    used = 0;
-    for (uint32_t i = 0; i < cnt; ++i) used |= 1ull << (uint32_t)__shfl((int)ns, (int)i, 64);
+    used = wave_or64((uint32_t)l < cnt ? 1ull << ns : 0ull);
     n = cnt;
     wave_sync();
   }
@@ -2912,16 +3035,17 @@ __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const u
   const uint64_t prev_lo = (uint32_t)__shfl_up((int)(uint32_t)key, 1, 64);
   const uint64_t prev_hi = (uint32_t)__shfl_up((int)(uint32_t)(key >> 32), 1, 64);
   const bool keep = key != KEY_NONE && !(slot & DROP) && (l == 0 || ((prev_hi << 32) | prev_lo) != key);
-  const uint64_t km = ballot(keep);
-  wave_sync();
-  if (keep) p.sorted[lanes_below(km)] = slot;
-  wave_sync();
-  uint32_t mm = (uint32_t)__popcll(km);
+  // the candidates stay in their ranked lanes (the lanes of the others are
+  // skipped); at most prune_cap of them, the first in rank order
+  uint64_t alive = ballot(keep);
   const uint32_t cap = ix.prune_cap < POOL ? ix.prune_cap : POOL;
-  if (mm > cap) mm = cap;
-  const uint32_t csl = (uint32_t)l < mm ? p.sorted[l] : 0u;
-  const uint32_t cdw = (uint32_t)l < mm ? p.dw[csl] : 0u;
-  const uint64_t alive = mm == 64 ? ~0ull : ((1ull << mm) - 1ull);
+  if ((uint32_t)__popcll(alive) > cap) {
+    uint64_t rest = alive;
+    for (uint32_t k = 0; k < cap; ++k) rest &= rest - 1ull;
+    alive &= ~rest;
+  }
+  const uint32_t csl = slot & ~DROP;
+  const uint32_t cdw = keep ? key_dist(key) : 0u;
   uint32_t keep_slot = 0;
   // the selection in order of rank over the cached distances (the slot of
   // the k-th kept candidate lands in lane k)
@@ -3018,7 +3142,11 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
     if (!ok) at = -1;
     const bool fresh = ok && at < 0;
     const uint64_t fm = ballot(fresh);
-    {  // the k-th fresh member takes the k-th free slot
+    // the k-th fresh member takes the k-th free slot (for the first pair the
+    // free slots are n, n + 1, ...)
+    if (first) {
+      if (fresh) at = (int)(n + lanes_below(fm));
+    } else {
       uint64_t fr = ~used;
       for (uint64_t m2 = fm; m2; m2 &= m2 - 1ull) {
         if (l == (int)__builtin_ctzll(m2)) at = (int)__builtin_ctzll(fr);
@@ -3036,8 +3164,11 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
     wave_sync();
     const uint32_t nf = nl + (uint32_t)__popcll(fm);
     uint64_t occ = used;
-    for (uint64_t m2 = fm; m2; m2 &= m2 - 1ull)
-      occ |= 1ull << (uint32_t)__builtin_amdgcn_readlane(at, (int)__builtin_ctzll(m2));
+    if (first)
+      occ = nf == 64 ? ~0ull : ((1ull << nf) - 1ull);
+    else
+      for (uint64_t m2 = fm; m2; m2 &= m2 - 1ull)
+        occ |= 1ull << (uint32_t)__builtin_amdgcn_readlane(at, (int)__builtin_ctzll(m2));
     bool filled = false;
     if constexpr (G <= 8) {  // rows up to 128 bytes: operands in registers
       if (first) {  // slots 0..nf-1 in order: the list, then B's new members
