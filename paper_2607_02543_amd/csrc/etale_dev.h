@@ -612,12 +612,17 @@ __device__ inline void finish_slabs(const Index& ix, SlabCursor& c, Counter whic
 // reference from the snapshot to <flag of snapshot, n, fresh slab>; on
 // success retire the displaced slab, on failure retire the fresh one and
 // retry, up to the attempt budget. Returns true when installed.
+// A reference word no node can hold (degree 127): "not read yet".
+constexpr uint64_t REF_UNREAD = ~0ull;
+
+// snap0: u's reference word as the caller read it (REF_UNREAD: read it here);
+// a failed compare-and-swap reads it afresh for the next attempt.
 __device__ inline bool publish(const Index& ix, uint32_t u, const uint32_t* ids, const uint32_t* d, uint32_t n,
-                               Counter which, SlabCursor* cur = nullptr) {
+                               Counter which, SlabCursor* cur = nullptr, uint64_t snap0 = REF_UNREAD) {
   const int l = lane_id();
   const uint32_t R = ix.R;
   for (uint32_t attempt = 0; attempt < ix.publish_attempts; ++attempt) {
-    const uint64_t snap = bcast64(load_ref(ix, u));
+    const uint64_t snap = attempt == 0 && snap0 != REF_UNREAD ? snap0 : bcast64(load_ref(ix, u));
     uint32_t s = 0;
     if (cur && cur->free_left) {
       s = ix.free_stack[cur->free_hi - 1];

@@ -1579,7 +1579,9 @@ struct AlphaT {
 // gives this lane's cached D(j, x) (read for the four together), and a
 // candidate covered by an earlier one of the four is skipped; a kept j
 // (keep(j, rank)) drops every later candidate it covers. Returns the kept
-// count, at most R: the result of the one-at-a-time selection.
+// count, at most R: the result of the one-at-a-time selection. (Reading
+// eight rows at a time, decided or not, was slower: most candidates are
+// covered early, and their rows need not be read.)
 template <bool C32, class Dist, class Keep>
 __device__ inline uint32_t select_in_order(uint64_t rest, uint32_t R, uint32_t a2, typename AlphaT<C32>::T thr,
                                            Dist dist, Keep keep) {
@@ -2329,7 +2331,7 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
     c.out_d[l] = c.dw[sl];
   }
   wave_sync();
-  publish(ix, w, c.out_id, c.out_d, n, C_PUB_REVERSE, &cur);
+  publish(ix, w, c.out_id, c.out_d, n, C_PUB_REVERSE, &cur, r);  // only this wave writes w
 }
 
 // one wave per run of the sorted (target, source) pairs
@@ -3208,7 +3210,7 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
     p.sorted[l] = od;
   }
   wave_sync();
-  publish(ix, an, p.cand, p.sorted, n, C_PUB_REPAIR, &cur);
+  publish(ix, an, p.cand, p.sorted, n, C_PUB_REPAIR, &cur, ra);  // only this wave writes a
 }
 
 template <class P>
@@ -3461,36 +3463,57 @@ __global__ void __launch_bounds__(256) k_dirty(Index ix, uint64_t n_ids, Dyn d, 
 }
 
 // phase 1, compaction: republish each dirty node without its tombstoned entries
-__device__ inline void compact_one(const Index& ix, const uint64_t* bitmap, uint32_t* ids, uint32_t* d, uint32_t u,
-                                   SlabCursor& cur) {
+// the list of a dirty node (reference word r) as lane l's entry
+__device__ inline void compact_read(const Index& ix, uint64_t r, uint32_t& id, uint32_t& dd) {
   const int l = lane_id();
-  const uint64_t r = bcast64(load_ref(ix, u));
   const uint32_t deg = ref_deg(r), s = ref_slab(r);
-  uint32_t id = NONE, dd = 0;
-  if ((uint32_t)l < deg) {
+  id = NONE;
+  dd = 0;
+  if ((uint32_t)l < deg && s != NONE) {
     id = ix.slabs[(size_t)s * 2u * ix.R + (uint32_t)l];
     dd = ix.slabs[(size_t)s * 2u * ix.R + ix.R + (uint32_t)l];
   }
-  const bool keep = id != NONE && !bit_set(bitmap, id);
-  const uint64_t m = ballot(keep);
-  if (keep) {
-    ids[lanes_below(m)] = id;
-    d[lanes_below(m)] = dd;
-  }
-  wave_sync();
-  publish(ix, u, ids, d, (uint32_t)__popcll(m), C_PUB_COMPACT, &cur);
 }
 
+// A wave's dirty nodes (every total_waves()-th from its index) in batches of
+// 64: the batch's ids and reference words are read together (lane k: the
+// k-th), each node's list is read while the previous node is published, and
+// the publication starts from the word already read (no other wave touches
+// a dirty node in this phase).
 __global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty, uint64_t n, Dyn dn,
                                                  const uint64_t* bitmap, uint32_t lds_per_wave) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, dn)) return;
   const uint32_t cnt = dyn_count(ix, dn, (uint32_t)n);
   uint32_t* ids = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * lds_per_wave);
+  uint32_t* d = ids + 64;
   SlabCursor cur = reserve_slabs(ix, wave_items(cnt), wave_items(cnt));
-  FOR_EACH_WAVE_ITEM(i, cnt) {
-    wave_sync();
-    compact_one(ix, bitmap, ids, ids + 64, dirty[i], cur);
+  const int l = lane_id();
+  const uint32_t w = wave_index(), W = total_waves();
+  for (uint32_t base = w; base < cnt; base += 64u * W) {
+    const uint32_t my = base + (uint32_t)l * W;
+    const uint32_t ul = my < cnt ? dirty[my] : NONE;
+    const uint64_t rl = my < cnt ? load_ref(ix, ul) : 0ull;
+    const uint32_t nb = (uint32_t)__popcll(ballot(my < cnt));
+    uint32_t id, dd;
+    compact_read(ix, bcast_lane64(rl, 0), id, dd);
+    for (uint32_t k = 0; k < nb; ++k) {
+      const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)ul, (int)k);
+      const uint64_t r = bcast_lane64(rl, (int)k);
+      uint32_t nid = NONE, ndd = 0;
+      if (k + 1 < nb) compact_read(ix, bcast_lane64(rl, (int)k + 1), nid, ndd);
+      const bool keep = id != NONE && !bit_set(bitmap, id);
+      const uint64_t m = ballot(keep);
+      wave_sync();
+      if (keep) {
+        ids[lanes_below(m)] = id;
+        d[lanes_below(m)] = dd;
+      }
+      wave_sync();
+      publish(ix, u, ids, d, (uint32_t)__popcll(m), C_PUB_COMPACT, &cur, r);
+      id = nid;
+      dd = ndd;
+    }
   }
   finish_slabs(ix, cur, C_PUB_COMPACT);
 }
