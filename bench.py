@@ -402,8 +402,7 @@ def run_batching(args):
         "capture_all_s": round(t_cap, 3),
         "per_op_ms_all_rounds": round(float(np.mean([x["per_op_ms"] for x in rows_all])), 3),
         "recall_at_10_L64": round(rec, 4), "recall_at_10_L128": rec_l[128], "recall_at_10_L256": rec_l[256],
-        "autotune": tune,
-        "search_knobs": knobs, "build_s": round(t_build, 2),
+        "autotune": tune, "build_s": round(t_build, 2),
         "device_bytes_per_index": B.stats()["device_bytes"],
     }
     A.close()

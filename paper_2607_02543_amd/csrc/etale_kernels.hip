@@ -1578,10 +1578,12 @@ struct AlphaT {
 // The candidates of `rest` are decided in order, four at a time: dist(j)
 // gives this lane's cached D(j, x) (read for the four together), and a
 // candidate covered by an earlier one of the four is skipped; a kept j
-// (keep(j, rank)) drops every later candidate it covers. Returns the kept
-// count, at most R: the result of the one-at-a-time selection. (Reading
-// eight rows at a time, decided or not, was slower: most candidates are
-// covered early, and their rows need not be read.)
+// (keep(j, rank, true); keep(.., false) for one that is not) drops every
+// later candidate it covers. Returns the kept count, at most R: the result of
+// the one-at-a-time selection. The four decisions are made without branches
+// (scalar selects), and reading eight rows at a time, decided or not,
+// measured slower: most candidates are covered early and their rows need not
+// be read.
 template <bool C32, class Dist, class Keep>
 __device__ inline uint32_t select_in_order(uint64_t rest, uint32_t R, uint32_t a2, typename AlphaT<C32>::T thr,
                                            Dist dist, Keep keep) {
@@ -1592,24 +1594,23 @@ __device__ inline uint32_t select_in_order(uint64_t rest, uint32_t R, uint32_t a
     uint64_t m = rest;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      j[k] = m ? (int)__builtin_ctzll(m) : -1;
-      if (m) m &= m - 1ull;
+      j[k] = m ? (int)__builtin_ctzll(m) : 64;
+      m &= m - 1ull;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) d[k] = j[k] >= 0 ? dist(j[k]) : 0u;
+    for (int k = 0; k < 4; ++k) d[k] = dist(j[k] < 64 ? j[k] : j[0]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (j[k] < 0 || cnt >= R) break;
-      if (!((rest >> j[k]) & 1ull)) continue;  // covered by an earlier one of the four
-      keep(j[k], cnt);
-      ++cnt;
-      const uint64_t above = j[k] == 63 ? 0ull : (~0ull << (j[k] + 1));
-      const uint64_t kill = ballot(AlphaT<C32>::scale(a2, d[k]) <= thr) & rest & above;
-      rest &= ~kill & ~(1ull << j[k]);
+      const uint64_t bit = j[k] < 64 ? 1ull << j[k] : 0ull;
+      const bool take = (rest & bit) != 0 && cnt < R;  // live, not covered by an earlier one of the four
+      keep(j[k] < 64 ? j[k] : 0, cnt, take);
+      const uint64_t above = j[k] >= 63 ? 0ull : (~0ull << (j[k] + 1));
+      const uint64_t kill = ballot(AlphaT<C32>::scale(a2, d[k]) <= thr) & above;
+      rest &= take ? ~(kill | bit) : ~0ull;
+      cnt += take ? 1u : 0u;
     }
     // every candidate up to the last of the four is decided
-    const int last = j[3] >= 0 ? j[3] : 63;
-    rest &= last == 63 ? 0ull : (~0ull << (last + 1));
+    rest &= j[3] >= 63 ? 0ull : (~0ull << (j[3] + 1));
   }
   return cnt;
 }
@@ -1752,10 +1753,10 @@ __device__ inline int prune_select_mx(const Index& ix, int m, PruneLds& s) {
     // 3. the survivors in order, four at a time
     const uint32_t tnl = l < tm ? s.tn[l] : 0u;
     auto dist = [&](int j) { return l > j ? s.M[tri_lt((uint32_t)j, (uint32_t)l)] : 0u; };
-    auto keep = [&](int j, uint32_t rank) {
+    auto keep = [&](int j, uint32_t rank, bool take) {
       const uint64_t kj = bcast_lane64(lk, j);
       const uint32_t nj = (uint32_t)__builtin_amdgcn_readlane((int)tnl, j);
-      if (l == 0) {
+      if (take && l == 0) {
         s.out_ids[cnt + (int)rank] = key_id(kj);
         s.out_d[cnt + (int)rank] = key_dist(kj);
         s.kn[cnt + (int)rank] = nj;
@@ -2312,9 +2313,9 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
       const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)cs, j);
       return c.M[sj < cs ? tb + sj : sj * (sj - 1u) / 2u + cs];
     };
-    auto keep = [&](int j, uint32_t rank) {
+    auto keep = [&](int j, uint32_t rank, bool take) {
       const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)cs, j);
-      if ((uint32_t)l == rank) ns = sj;
+      if (take && (uint32_t)l == rank) ns = sj;
     };
     const uint32_t cnt = ix.cmp32 ? select_in_order<true>(alive, R, ix.a2, AlphaT<true>::scale(ix.b2, cdw), dist, keep)
                                   : select_in_order<false>(alive, R, ix.a2, AlphaT<false>::scale(ix.b2, cdw), dist, keep);
@@ -3056,9 +3057,9 @@ __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const u
     const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)csl, j);
     return p.M[sj < csl ? tb + sj : sj * (sj - 1u) / 2u + csl];
   };
-  auto take = [&](int j, uint32_t rank) {
+  auto take = [&](int j, uint32_t rank, bool kept) {
     const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)csl, j);
-    if ((uint32_t)l == rank) keep_slot = sj;
+    if (kept && (uint32_t)l == rank) keep_slot = sj;
   };
   const uint32_t cnt = ix.cmp32 ? select_in_order<true>(alive, ix.R, ix.a2, AlphaT<true>::scale(ix.b2, cdw), dist, take)
                                 : select_in_order<false>(alive, ix.R, ix.a2, AlphaT<false>::scale(ix.b2, cdw), dist, take);
@@ -3199,8 +3200,7 @@ __device__ inline void repair_chain_u8(const Index& ix, const MaintArgs& a, cons
     lslot = (uint32_t)l < n ? p.list[l] : 0u;
     lid = (uint32_t)l < n ? p.id[lslot] : NONE;
     // slots not on the new list become free
-    used = 0;
-    for (uint32_t k = 0; k < n; ++k) used |= 1ull << (uint32_t)__builtin_amdgcn_readlane((int)lslot, (int)k);
+    used = wave_or64((uint32_t)l < n ? 1ull << lslot : 0ull);
   }
   // publish (ids and distances in list order)
   const uint32_t od = (uint32_t)l < n ? p.dw[lslot] : 0u;
