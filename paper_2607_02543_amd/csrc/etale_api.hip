@@ -570,7 +570,10 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     MaintArgs ra = maint_args(ix, R + 1);
     if (ix->cfg.metric == ETALE_METRIC_L2_U8 && R <= 32 && !ix->no_chain) {
       ra.chain = 1;
-      ra.lds_per_wave = chain_lds_per_wave(R, ra.vstride);  // the chain kernel carves only the chain state
+      // the chain kernel carves only the chain state; up to 128-byte rows it
+      // reads rows from memory and stages none
+      if (ix->cfg.dim <= 128) ra.vstride = 0;
+      ra.lds_per_wave = chain_lds_per_wave(R, ra.vstride);
     }
     ra.n = p.max_i;
     ra.pairs = sorted;
