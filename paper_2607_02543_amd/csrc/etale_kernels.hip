@@ -1202,13 +1202,14 @@ __device__ inline void drop_crowded_twins_h(const uint32_t (&nid)[H], const uint
 constexpr uint64_t REF_LAZY = ~0ull;
 
 // The same search for L <= 64 with the list in registers: lane i holds entry
-// i (key, reference word, expanded flag), entries at or past n hold KEY_NONE.
-// The next entries to expand are the lowest lanes of one ballot, and each
-// accepted candidate is inserted at its rank (a ballot count) by shifting the
-// lanes above it up one, so the list never leaves the registers. A step
-// expands up to W entries (H = 2 halves of 64 slab entries when W = 4), scores
-// all their fresh neighbors in one batch and merges them. Per-wave LDS: one
-// batch of candidates (64H) and the visited table.
+// i (key, reference word or REF_LAZY, expanded flag), entries at or past n
+// hold KEY_NONE. The next entries to expand are the lowest lanes of one
+// ballot. A step expands up to W entries (H = 2 halves of 64 slab entries when
+// W = 4), scores all their fresh neighbors in one batch and merges them by
+// rank: every list entry and accepted candidate counts the keys of the other
+// side below it (one broadcast per accepted candidate), the first L of the
+// union are scattered to LDS at their ranks and read back in order. Per-wave
+// LDS: one batch of candidates (64H) and the visited table.
 template <class TP, int H>
 __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char* base, uint32_t qi,
                                      SearchTally& tally) {
