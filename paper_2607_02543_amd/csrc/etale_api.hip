@@ -463,7 +463,7 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
   if (p.max_d) {
     Dyn dt;
     dt.skip = G_FAIL;
-    dt.n_ctr = C_DEL_OK;
+    dt.n_ctr = C_R_NDEL;  // dlist: the sorted deletes, NONE where not accepted
     HIP_TRY(launch_tombstone(d, ix->dlist, p.max_d, dt, s));
     Dyn dr;
     dr.skip = G_FAIL;
@@ -520,16 +520,16 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
     pa.dlist = ix->dlist;
     pa.pairs = ix->pairs_a;
     pa.d.skip = G_FAIL;
-    pa.d.n_ctr = C_DEL_OK;
+    pa.d.n_ctr = C_R_NDEL;
     HIP_TRY(launch_repair_pairs(d, pa, s));
     Dyn dp;
     dp.skip = G_FAIL;
-    dp.n_ctr = C_DEL_OK;
+    dp.n_ctr = C_R_NDEL;
     dp.n_mult = R;
     uint64_t* sorted = nullptr;
-    // the deleted ids come in no particular order: sort on (target, source)
-    HIP_TRY(launch_sort(d, ix->pairs_a, ix->pairs_b, p.max_d * R, dp, 32, (int)ix->pair_bits, ix->hist, s, &sorted,
-                        (int)ix->pair_bits));
+    // pairs are written in ascending source order (dlist keeps the sorted
+    // deletes): the target half alone gives (target, source) order
+    HIP_TRY(launch_sort(d, ix->pairs_a, ix->pairs_b, p.max_d * R, dp, 32, (int)ix->pair_bits, ix->hist, s, &sorted));
     HIP_TRY(launch_segments(d, sorted, p.max_d * R, dp, ix->seg, s));
     pa.pairs = sorted;
     pa.npairs = p.max_d * R;
@@ -538,7 +538,7 @@ etale_status enqueue_round(etale_index* ix, const RoundPlan& p) {
       pa.chain = 1;
       pa.lds_per_wave = pool_lds_per_wave(pa.vstride);  // the pool kernel carves only the pool
     }
-    pa.np_ctr = C_DEL_OK;
+    pa.np_ctr = C_R_NDEL;
     pa.np_mult = R;
     pa.seg = ix->seg;
     HIP_TRY(launch_maint(MK_REPAIR, d, pa, pa.npairs, maint_waves_per_block(pa), s));

@@ -2620,12 +2620,14 @@ __global__ void k_del_classify(Index ix, const uint64_t* sorted, uint32_t n, Dyn
       st = DEL_OK;
     if (status) status[pos] = st;
   }
-  // the accepted ids of the wave take consecutive places, one atomic per wave
+  // dlist keeps the sorted order: position t holds the id when it is
+  // accepted and NONE otherwise, so the deleted ids appear in ascending order
+  // (pairs generated from them come out in source order); the accepted count,
+  // one atomic per wave
   const bool ok = t < n && st == DEL_OK;
+  if (t < n) dlist[t] = ok ? id : NONE;
   const uint64_t m = ballot(ok);
-  if (!m) return;
-  const uint32_t base = (uint32_t)wave_atomic_add(&ix.ctr[C_DEL_OK], (unsigned long long)__popcll(m));
-  if (ok) dlist[base + lanes_below(m)] = id;
+  if (m) wave_atomic_add(&ix.ctr[C_DEL_OK], (unsigned long long)__popcll(m));
 }
 
 // <0,d,s> -> <1,d,s>: the flag is set, degree and slab are kept
@@ -2634,8 +2636,8 @@ __global__ void k_tombstone(Index ix, const uint32_t* dlist, uint32_t n, Dyn d) 
   n = dyn_count(ix, d, n);
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   bool done = false;
-  if (t < n) {
-    const uint32_t u = dlist[t];
+  const uint32_t u = t < n ? dlist[t] : NONE;
+  if (u != NONE) {
     uint64_t r = load_ref(ix, u);
     for (int attempt = 0; attempt < 1024 && !ref_del(r); ++attempt) {
       const uint64_t prev = atomicCAS(&ix.refs[u], (unsigned long long)r, (unsigned long long)(r | (1ull << 63)));
@@ -2657,9 +2659,9 @@ __global__ void k_repair_pairs(Index ix, MaintArgs a) {
   if (i == 0 && lane_id() == 0) ix.ctr[C_NSEG] = 0;
   if (i >= a.n) return;
   const int l = lane_id();
-  const uint32_t u = a.dlist[i];
-  const uint64_t r = bcast64(load_ref(ix, u));
-  const uint32_t deg = ref_deg(r), s = ref_slab(r);
+  const uint32_t u = a.dlist[i];  // NONE where the delete was not accepted
+  const uint64_t r = u != NONE ? bcast64(load_ref(ix, u)) : 0ull;
+  const uint32_t deg = u != NONE ? ref_deg(r) : 0u, s = ref_slab(r);
   if ((uint32_t)l >= ix.R) return;
   uint64_t key = KEY_NONE;
   if ((uint32_t)l < deg && s != NONE) {
