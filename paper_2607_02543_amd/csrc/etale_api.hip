@@ -34,8 +34,8 @@ struct etale_index {
   uint32_t* retired_stack = nullptr;
   unsigned long long* ctr = nullptr;
   uint32_t* entries = nullptr;
-  uint8_t* ent_x = nullptr;     // uint8 rows: shifted copy of the entry set's rows
-  int32_t* ent_norm = nullptr;  // and their squared norms
+  uint8_t* ent_x = nullptr;     // uint8 rows: shifted copy of the entry set's rows, in operand order
+  int32_t* ent_norm = nullptr;  // and minus their squared norms
   // call scratch
   uint64_t* vis_keys = nullptr;
   uint32_t* vis_cnt = nullptr;
@@ -695,7 +695,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   ALLOC(ix->ctr, C_NCOUNTERS * 8);
   ALLOC(ix->entries, (uint64_t)c.n_entry * 4);
   if (c.metric == ETALE_METRIC_L2_U8) {
-    ALLOC(ix->ent_x, (uint64_t)c.n_entry * c.dim);
+    ALLOC(ix->ent_x, ent_copy_bytes(c.n_entry, c.dim));
     ALLOC(ix->ent_norm, ((uint64_t)c.n_entry + 63) / 64 * 64 * 4);
   }
   ALLOC(ix->vis_keys, B * std::max<uint64_t>(ix->vcap_build, R) * 8);  // also the refined lists (R per node)
@@ -1206,7 +1206,7 @@ etale_status etale_serve(etale_t ix, const etale_serve_config* cfg, const etale_
   dev(&snap_ctr, C_NCOUNTERS * 8);
   dev(&snap_entries, (uint64_t)ns * 4);
   if (ix->ent_x) {
-    dev(&snap_ent_x, (uint64_t)ns * dim);
+    dev(&snap_ent_x, ent_copy_bytes(ns, dim));
     dev(&snap_ent_norm, norm_words * 4);
   }
   // start-set scratch of the searches, apart from the library's own (which the
@@ -1439,7 +1439,8 @@ etale_status etale_serve(etale_t ix, const etale_serve_config* cfg, const etale_
     if (e == hipSuccess && next_id) e = hipMemcpyAsync(snap_refs, ix->refs, next_id * 8, hipMemcpyDeviceToDevice, S);
     if (e == hipSuccess) e = hipMemcpyAsync(snap_ctr, ix->ctr, C_NCOUNTERS * 8, hipMemcpyDeviceToDevice, S);
     if (e == hipSuccess) e = hipMemcpyAsync(snap_entries, ix->entries, (size_t)ns * 4, hipMemcpyDeviceToDevice, S);
-    if (e == hipSuccess && snap_ent_x) e = hipMemcpyAsync(snap_ent_x, ix->ent_x, (size_t)ns * dim, hipMemcpyDeviceToDevice, S);
+    if (e == hipSuccess && snap_ent_x)
+      e = hipMemcpyAsync(snap_ent_x, ix->ent_x, ent_copy_bytes(ns, dim), hipMemcpyDeviceToDevice, S);
     if (e == hipSuccess && snap_ent_x)
       e = hipMemcpyAsync(snap_ent_norm, ix->ent_norm, norm_words * 4, hipMemcpyDeviceToDevice, S);
     if (e == hipSuccess) e = hipEventRecord(t.e_snap, S);

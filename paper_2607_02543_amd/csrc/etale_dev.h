@@ -104,8 +104,8 @@ struct Index {
   uint32_t* retired_stack;
   unsigned long long* ctr;
   uint32_t* entries;
-  uint8_t* ent_x;     // uint8 rows: the entry set's rows, each byte XOR 0x80, in entry order
-  int32_t* ent_norm;  // their squared norms (as signed bytes), padded to a multiple of 64
+  uint8_t* ent_x;     // uint8 rows: the entry set's rows, each byte XOR 0x80, in matrix-operand order
+  int32_t* ent_norm;  // minus their squared norms (as signed bytes), padded to a multiple of 64
 };
 
 // ---- counts read at launch time --------------------------------------------------

@@ -174,28 +174,38 @@ __device__ inline uint32_t block_prefix(bool keep, uint32_t* wcnt, uint32_t* tot
   return before + lanes_below(m);
 }
 
-// The uint8 entry set's shifted copy: entry e's row XOR 0x80 (each byte as a
-// signed value, as the matrix cores take it) at row e, its squared norm at e.
+// The uint8 entry set's shifted copy, each byte XOR 0x80 (a signed value, as
+// the matrix cores take it), stored in the order the scoring kernel's lanes
+// take their operands: for each block of 16 entries and each 64-byte slice of
+// the rows, 1 KiB holding lane l's 16 bytes at 16 l (entry 16 b + l % 16,
+// bytes 64 s + 16 (l / 16) .. + 15), so that one operand load of a wave reads
+// 1 KiB of consecutive bytes. Slices past dim are zero; entry e's negated
+// squared norm (the form the scoring epilogue adds) is at e.
 __global__ void __launch_bounds__(256) k_entry_rows(Index ix, uint32_t S, Dyn d) {
   if (gated(ix, d)) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= min<uint64_t>(S, ix.ctr[C_N_ENTRIES])) return;
   const uint4* src = reinterpret_cast<const uint4*>(ix.x + (size_t)ix.entries[e] * ix.dim);
-  uint4* dst = reinterpret_cast<uint4*>(ix.ent_x + (size_t)e * ix.dim);
+  const uint32_t nsl = (ix.dim + 63) / 64, nc = ix.dim / 16;
+  uint8_t* blk = ix.ent_x + (size_t)(e >> 4) * nsl * 1024u + (e & 15u) * 16u;
   int sq = 0;
-  for (uint32_t c = 0; c < ix.dim / 16; ++c) {
-    uint4 w = src[c];
-    w.x ^= 0x80808080u;
-    w.y ^= 0x80808080u;
-    w.z ^= 0x80808080u;
-    w.w ^= 0x80808080u;
-    dst[c] = w;
-    sq = __builtin_amdgcn_sdot4((int)w.x, (int)w.x, sq, false);
-    sq = __builtin_amdgcn_sdot4((int)w.y, (int)w.y, sq, false);
-    sq = __builtin_amdgcn_sdot4((int)w.z, (int)w.z, sq, false);
-    sq = __builtin_amdgcn_sdot4((int)w.w, (int)w.w, sq, false);
+  for (uint32_t c = 0; c < nsl * 4u; ++c) {
+    uint4 w = make_uint4(0u, 0u, 0u, 0u);
+    if (c < nc) {
+      w = src[c];
+      w.x ^= 0x80808080u;
+      w.y ^= 0x80808080u;
+      w.z ^= 0x80808080u;
+      w.w ^= 0x80808080u;
+      sq = __builtin_amdgcn_sdot4((int)w.x, (int)w.x, sq, false);
+      sq = __builtin_amdgcn_sdot4((int)w.y, (int)w.y, sq, false);
+      sq = __builtin_amdgcn_sdot4((int)w.z, (int)w.z, sq, false);
+      sq = __builtin_amdgcn_sdot4((int)w.w, (int)w.w, sq, false);
+    }
+    // slice c / 4, lane (c % 4) * 16 + e % 16
+    *reinterpret_cast<uint4*>(blk + (c >> 2) * 1024u + (c & 3u) * 256u) = w;
   }
-  ix.ent_norm[e] = sq;
+  ix.ent_norm[e] = -sq;
 }
 
 __global__ void __launch_bounds__(1024) k_refresh_entries(Index ix, uint32_t next_id, uint32_t S, Dyn d) {
@@ -257,14 +267,14 @@ __device__ inline void resolve(const Index& ix, ScanArgs& a) {
 // uint8 rows on the matrix cores: every byte is shifted to a signed value
 // (x - 128, an XOR with 0x80), which leaves every difference and so every
 // squared distance unchanged, and d = |q'|^2 + |e'|^2 - 2 q'.e' is exact in
-// int32. One wave scores 64 start rows x 64 queries as 4 x 4 tiles of
-// v_mfma_i32_16x16x64_i8 (start rows as the M operand, queries as N), one
+// int32. One wave scores 32 start rows x 64 queries at a time as 2 x 4 tiles
+// of v_mfma_i32_16x16x64_i8 (start rows as the M operand, queries as N), one
 // 64-byte slice of the rows per step; the operands are read straight from
 // memory (the start rows stay in L2 across the query tiles). In the result
 // tile lane l holds query l % 16 and the four start rows 4 (l / 16) + i, so
 // each lane stores 16 contiguous bytes of its query's distance row.
 typedef int v4i32 __attribute__((ext_vector_type(4)));
-constexpr int SD_WT = 64;  // start rows and queries per wave tile
+constexpr int SD_WT = 64;  // queries per wave task (and start rows per group-count tile)
 
 __device__ inline v4i32 signed_frag(const uint8_t* row, uint32_t off, uint32_t dim) {
   v4i32 f = {0, 0, 0, 0};
@@ -293,210 +303,279 @@ __device__ inline int frag_sq(v4i32 f) {
   return __builtin_amdgcn_sdot4(f.w, f.w, s, false);
 }
 
-// One wave scores 64 queries against a span of SCAN_SPAN start rows, as
-// SCAN_SPAN / 64 tiles of 64 x 64. SCAN_MIN writes each query's group minima
-// (32 start rows per group); SCAN_DENSE writes them and the distances too
-// (each lane 16 contiguous bytes of its query's row). SCAN_FILTER writes the
-// (distance, row) key of every row at or below the query's bound to the
-// query's slots for this span and the number of such rows; rows beyond the
-// slots are left to the dense fallback. No atomics: each (query, span) pair
-// belongs to one wave.
+// One wave scores 64 queries against a span of SCAN_SPAN start rows, 32 rows
+// (one group) at a time, in KS 64-byte slices (KS * 64 >= dim). The query
+// tile's operands and squared norms are loaded once per span and stay in
+// registers; query slices past dim are zero, so whatever a start row's slice
+// holds there adds nothing. In the result tile lane l holds query 16n + l % 16
+// against start rows 16m + 4k + i (k = l / 16), and each value is kept as
+// u = 2 q'.e' - |e'|^2, one shift-add from the accumulator, so that the
+// distance is |q'|^2 - u and the smallest distance is the largest u.
+// SCAN_MIN writes each query's group minima; SCAN_DENSE writes them and the
+// distances (each lane 16 contiguous bytes of its query's row). SCAN_FILTER
+// writes the (distance, row) key of every row at or below the query's bound:
+// the four lanes that hold one query fill interleaved slots of the query's span
+// region (lane k takes slots k, k + 4, ...), so no lane needs another's count,
+// and the four counts go to one word, a byte each; keys past a lane's slots are
+// left to the dense fallback. No atomics: each (query, span) pair belongs to
+// one wave.
 enum ScanPass { SCAN_MIN = 0, SCAN_FILTER = 1, SCAN_DENSE = 2 };
 
 // key slots per (query, span): the per-query key buffer split over the spans
 __device__ inline uint32_t scan_slots(uint32_t n_span) { return SCAN_KEYS_Q / max(1u, n_span); }
+// slots of one lane of a (query, span) region: below 255, where the byte count saturates
+__device__ inline uint32_t scan_lane_slots(uint32_t n_span) { return min(scan_slots(n_span) / 4u, 254u); }
 
-// PRE: the start set is the entry set, read from its shifted copy (rows in
-// entry order, norms beside them) instead of through the id list.
-template <int PASS, bool PRE>
+// the two values a lane and its partner l ^ 16 (SWAP16) or l ^ 32 hold in a
+// and b: after the swap a lane of an even 16-lane row holds its own a and its
+// partner's a, a lane of an odd row its partner's b and its own b
+template <bool SWAP16>
+__device__ inline void swap_rows(uint32_t& a, uint32_t& b) {
+  const auto p = SWAP16 ? __builtin_amdgcn_permlane16_swap(a, b, false, false)
+                        : __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  a = p[0];
+  b = p[1];
+}
+__device__ inline uint32_t quad_sum(uint32_t v) {
+  uint32_t w = v;
+  swap_rows<true>(v, w);
+  v += w;
+  w = v;
+  swap_rows<false>(v, w);
+  return v + w;
+}
+// the largest of v[n] over the four lanes l % 16 + 16k, left in lane
+// l % 16 + 16n (a reduce-scatter: three swaps for four values)
+__device__ inline int quad_max_scatter(const int v[4]) {
+  uint32_t a = (uint32_t)v[0], b = (uint32_t)v[1], c = (uint32_t)v[2], d = (uint32_t)v[3];
+  swap_rows<true>(a, b);  // even rows: (own v0, partner v0); odd rows: (partner v1, own v1)
+  swap_rows<true>(c, d);
+  uint32_t x = (uint32_t)max((int)a, (int)b), y = (uint32_t)max((int)c, (int)d);
+  swap_rows<false>(x, y);  // rows 0, 1: (own, partner) of v0 / v1; rows 2, 3: of v2 / v3
+  return max((int)x, (int)y);
+}
+
+constexpr int U_INVALID = (int)0x80000000;  // u of a row that is not scored
+
+// PRE: the start set is the entry set, read from its shifted, operand-ordered
+// copy (16-entry blocks in entry order, zero past dim, the blocks padded to a
+// multiple of two; norms beside them) instead of through the id list. CHUNKED (rows longer than
+// 64 KS bytes, a whole number of KS-slice chunks): the query operands are
+// reloaded per chunk instead of staying in registers.
+template <int PASS, bool PRE, int KS, bool CHUNKED>
 __device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, uint32_t span, uint32_t q0) {
+  constexpr uint32_t CW = 64u * KS;  // bytes of a row per chunk
   const int l = lane_id();
-  const uint32_t ns = a.ns, dim = ix.dim, r = (uint32_t)(l & 15), kc = (uint32_t)(l >> 4) * 16u;
-  const uint32_t rb = (uint32_t)(l >> 4) * 4u;  // first of this lane's four start rows within a 16-row tile
-  const uint32_t n_span = (ns + SCAN_SPAN - 1) / SCAN_SPAN, slots = scan_slots(n_span);
-  // query rows q0 + 16n + r: row 16n of the base below
-  const uint8_t* qb = (a.mode == MODE_QUERY ? (const uint8_t*)a.q : ix.x + (size_t)(a.first + a.qoff) * dim) +
-                      (size_t)(q0 + r) * dim;
-  const uint32_t q_left = a.nq > q0 + r ? a.nq - (q0 + r) : 0u;  // queries n with 16n < q_left exist
-  uint32_t cnt[4] = {0, 0, 0, 0};
-  // the ids of a tile's start rows are read one tile ahead
-  constexpr bool AHEAD = !PRE && PASS != SCAN_FILTER;  // the filter pass is short of registers
-  const uint32_t e_end = min(ns, (span + 1) * SCAN_SPAN);
-  uint32_t nid[4];
+  const uint32_t ns = a.ns, dim = ix.dim, r = (uint32_t)(l & 15), k4 = (uint32_t)(l >> 4), kc = k4 * 16u;
+  const uint32_t rb = k4 * 4u;  // first of this lane's four start rows within a 16-row block
+  const uint32_t n_span = (ns + SCAN_SPAN - 1) / SCAN_SPAN;
+  const uint32_t e_begin = span * SCAN_SPAN, e_end = min(ns, e_begin + SCAN_SPAN);
+  const uint32_t nsl = (dim + 63) / 64;  // 64-byte slices per row of the entry copy
+  // the query tile: rows q0 + 16n + r; a row past the launch's queries reads
+  // the last query, and its results are not written
+  const uint8_t* qbase = a.mode == MODE_QUERY ? (const uint8_t*)a.q : ix.x + (size_t)(a.first + a.qoff) * dim;
+  const uint8_t* qrow[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const uint32_t e = span * SCAN_SPAN + (uint32_t)m * 16u + r;
-    nid[m] = AHEAD && e < e_end ? start_id(ix, a, e) : NONE;
+  for (int n = 0; n < 4; ++n) qrow[n] = qbase + (size_t)min(q0 + (uint32_t)n * 16u + r, a.nq - 1u) * dim;
+  v4i32 qf[KS][4];
+  auto load_q = [&](uint32_t c0) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) qf[ks][n] = signed_frag(qrow[n], c0 + (uint32_t)ks * 64u + kc, dim);
+  };
+  int qn[4] = {0, 0, 0, 0};
+  for (uint32_t c0 = 0; c0 < (CHUNKED ? dim : 1u); c0 += CW) {
+    load_q(c0);
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) qn[n] += frag_sq(qf[ks][n]);
   }
-  for (uint32_t e0 = span * SCAN_SPAN; e0 < e_end; e0 += SD_WT) {
-    const uint8_t* erow[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+  for (int n = 0; n < 4; ++n) qn[n] = (int)quad_sum((uint32_t)qn[n]);
+  // this lane's own query after a reduce-scatter: q0 + 16k + r
+  const uint32_t q_own = q0 + k4 * 16u + r;
+  const int qn_own = k4 == 0 ? qn[0] : k4 == 1 ? qn[1] : k4 == 2 ? qn[2] : qn[3];
+  // a bootstrap row never scores itself: row qoff + q0 + 16n + r of the start
+  // set (elsewhere a value no row offset takes)
+  const int self_base = a.mode == MODE_BOOT ? (int)(a.qoff + q0 + r) : -0x40000000;
+  int nthr[4];      // SCAN_FILTER: a row is kept when u >= nthr
+  uint32_t cnt[4];  // SCAN_FILTER: this lane's keys per query
+  uint64_t* outp = nullptr;
+  uint32_t lane_cap = 0;
+  if constexpr (PASS == SCAN_FILTER) {
+    lane_cap = scan_lane_slots(n_span);
+    outp = a.cand + (size_t)span * scan_slots(n_span) + k4;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const uint32_t qi = q0 + (uint32_t)n * 16u + r;
+      const uint32_t b = qi < a.nq ? a.bound[qi] : 0u;
+      // distances stay below 2^25: a bound of 2^31 or more admits every row
+      nthr[n] = qi >= a.nq ? 0x7FFFFFFF : b >= 0x80000000u ? U_INVALID + 1 : qn[n] - (int)b;
+      cnt[n] = 0;
+    }
+  }
+  uint32_t gprev = D_INVALID;  // SCAN_MIN / SCAN_DENSE: the previous (even) group's minimum
+  for (uint32_t e0 = e_begin; e0 < e_end; e0 += 32u) {
+    // this lane's rows of the two 16-row blocks: 16m + r, and 16m + rb + i in the result
+    const uint8_t* erow[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
       if constexpr (PRE) {
-        const uint32_t e = e0 + (uint32_t)m * 16u + r;
-        erow[m] = e < e_end ? ix.ent_x + (size_t)e * dim : nullptr;
-      } else if constexpr (AHEAD) {
-        erow[m] = nid[m] != NONE ? ix.x + (size_t)nid[m] * dim : nullptr;
-        const uint32_t e = e0 + SD_WT + (uint32_t)m * 16u + r;
-        nid[m] = e < e_end ? start_id(ix, a, e) : NONE;
+        // block (e0 + 16m) / 16 of the operand-ordered copy, this lane's 16 bytes
+        erow[m] = ix.ent_x + (size_t)((e0 >> 4) + (uint32_t)m) * nsl * 1024u + (uint32_t)l * 16u;
       } else {
         const uint32_t e = e0 + (uint32_t)m * 16u + r;
         erow[m] = e < e_end ? ix.x + (size_t)start_id(ix, a, e) * dim : nullptr;
       }
     }
-    v4i32 acc[4][4];
+    v4i32 acc[2][4];
+    int es[2] = {0, 0};  // !PRE: partial squared norms of rows 16m + r
+    for (uint32_t c0 = 0; c0 < (CHUNKED ? dim : 1u); c0 += CW) {
+      if constexpr (CHUNKED) load_q(c0);
+      v4i32 ef[KS][2];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int n = 0; n < 4; ++n) acc[m][n] = v4i32{0, 0, 0, 0};
-    int en[4] = {0, 0, 0, 0}, qn[4] = {0, 0, 0, 0};
-    for (uint32_t k0 = 0; k0 < dim; k0 += 64) {
-      v4i32 ef[4], qf[4];
+        for (int ks = 0; ks < KS; ++ks) {
+          if constexpr (PRE) {
+            const uint4 w = *reinterpret_cast<const uint4*>(erow[m] + ((c0 >> 6) + (uint32_t)ks) * 1024u);
+            ef[ks][m] = v4i32{(int)w.x, (int)w.y, (int)w.z, (int)w.w};
+          } else {
+            ef[ks][m] = signed_frag(erow[m], c0 + (uint32_t)ks * 64u + kc, dim);
+            es[m] += frag_sq(ef[ks][m]);
+          }
+        }
+      const bool first = !CHUNKED || c0 == 0;
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        ef[m] = PRE ? shifted_frag(erow[m], k0 + kc, dim) : signed_frag(erow[m], k0 + kc, dim);
-        qf[m] = signed_frag((uint32_t)m * 16u < q_left ? qb + (size_t)m * 16u * dim : nullptr, k0 + kc, dim);
-      }
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        if constexpr (!PRE) en[m] += frag_sq(ef[m]);
-        qn[m] += frag_sq(qf[m]);
-      }
+        for (int n = 0; n < 4; ++n)
+          acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ef[0][m], qf[0][n], first ? v4i32{0, 0, 0, 0} : acc[m][n],
+                                                            0, 0, 0);
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int ks = 1; ks < KS; ++ks)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ef[m], qf[n], acc[m][n], 0, 0, 0);
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int n = 0; n < 4; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ef[ks][m], qf[ks][n], acc[m][n], 0, 0, 0);
     }
-    // full squared norms: lane l then holds start row m*16 + l%16 and query n*16 + l%16
+    int ner[2][4];  // minus the squared norms of this lane's start rows 16m + rb + i
+    if constexpr (PRE) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      if constexpr (!PRE) {
-        en[m] += __shfl_xor(en[m], 16, 64);
-        en[m] += __shfl_xor(en[m], 32, 64);
-      }
-      qn[m] += __shfl_xor(qn[m], 16, 64);
-      qn[m] += __shfl_xor(qn[m], 32, 64);
-    }
-    int er[4][4];  // norms of this lane's start rows m*16 + rb + i
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      if constexpr (PRE) {
-        // the norm array is padded to whole 64-row tiles
+      for (int m = 0; m < 2; ++m) {
+        // the (negated) norm array is padded to whole 64-row tiles
         const int4 v = *reinterpret_cast<const int4*>(ix.ent_norm + e0 + (uint32_t)m * 16u + rb);
-        er[m][0] = v.x;
-        er[m][1] = v.y;
-        er[m][2] = v.z;
-        er[m][3] = v.w;
-      } else {
+        ner[m][0] = v.x;
+        ner[m][1] = v.y;
+        ner[m][2] = v.z;
+        ner[m][3] = v.w;
+      }
+    } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) er[m][i] = __shfl(en[m], (int)rb + i, 64);
+      for (int m = 0; m < 2; ++m) {
+        const int en = (int)quad_sum((uint32_t)es[m]);  // lane l: row 16m + l % 16
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ner[m][i] = -__shfl(en, (int)rb + i, 64);
       }
     }
-    const bool check = a.mode == MODE_BOOT || e0 + SD_WT > ns;  // some row of the tile may be invalid
+    // rows of the group past the start set, and a bootstrap row itself, are not scored
+    const bool check = a.mode == MODE_BOOT || e0 + 32u > ns;
+    const int lim = (int)ns - (int)e0;  // rows 16m + rb + i below lim exist
+    int gmax[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
       const uint32_t qi = q0 + (uint32_t)n * 16u + r;
+      int u[2][4];
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) u[m][i] = (acc[m][n][i] << 1) + ner[m][i];
+      if (check) {
+        const int self = self_base + n * 16 - (int)e0;
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int o = m * 16 + (int)rb + i;
+            if (o >= lim || o == self) u[m][i] = U_INVALID;
+          }
+      }
       if constexpr (PASS != SCAN_FILTER) {
-        uint32_t d[4][4];
-        if (check) {
-          const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;  // a bootstrap row never scores itself
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const uint32_t e = e0 + (uint32_t)m * 16u + rb + (uint32_t)i;
-              d[m][i] = e == self || e >= ns ? D_INVALID : (uint32_t)(qn[n] + er[m][i] - 2 * acc[m][n][i]);
-            }
-        } else {
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) d[m][i] = (uint32_t)(qn[n] + er[m][i] - 2 * acc[m][n][i]);
-        }
         if constexpr (PASS == SCAN_DENSE) {
           if (qi < a.nq) {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
+            for (int m = 0; m < 2; ++m) {
+              uint32_t d[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) d[i] = u[m][i] == U_INVALID ? D_INVALID : (uint32_t)(qn[n] - u[m][i]);
               const uint32_t e = e0 + (uint32_t)m * 16u + rb;
               uint32_t* out = a.dist + (size_t)qi * ns + e;
               if ((ns & 3u) == 0 && e + 3 < ns) {
-                *reinterpret_cast<uint4*>(out) = make_uint4(d[m][0], d[m][1], d[m][2], d[m][3]);
+                *reinterpret_cast<uint4*>(out) = make_uint4(d[0], d[1], d[2], d[3]);
               } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                  if (e + (uint32_t)i < ns) out[i] = d[m][i];
+                  if (e + (uint32_t)i < ns) out[i] = d[i];
               }
             }
           }
         }
-        uint32_t g[2] = {D_INVALID, D_INVALID};  // minima of start rows [e0, e0 + 32) and [e0 + 32, e0 + 64)
+        int v = u[0][0];
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) g[m >> 1] = min(g[m >> 1], d[m][i]);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          g[h] = min(g[h], (uint32_t)__shfl_xor((int)g[h], 16, 64));
-          g[h] = min(g[h], (uint32_t)__shfl_xor((int)g[h], 32, 64));
-        }
-        // lanes 0-15 write group 0, lanes 16-31 group 1 (group slots 2 per 64-row tile)
-        if (qi < a.nq && l < 32)
-          a.gmin[(size_t)qi * a.g_stride + (e0 >> 5) + (uint32_t)(l >> 4)] = l < 16 ? g[0] : g[1];
+        for (int j = 1; j < 8; ++j) v = max(v, u[j >> 2][j & 3]);
+        gmax[n] = v;
       } else {
-        const uint32_t bnd = qi < a.nq ? a.bound[qi] : 0u;
-        const uint32_t self = a.mode == MODE_BOOT ? a.qoff + qi : NONE;  // a bootstrap row never scores itself
-        uint32_t d[4][4];
+        uint64_t* out = outp + (size_t)qi * SCAN_KEYS_Q;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 2; ++m)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const uint32_t e = e0 + (uint32_t)m * 16u + rb + (uint32_t)i;
-            d[m][i] = e == self || e >= ns ? D_INVALID : (uint32_t)(qn[n] + er[m][i] - 2 * acc[m][n][i]);
-          }
-        uint32_t mine = 0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) mine += d[m][i] <= bnd ? 1u : 0u;
-        // the four lanes of query r (l = r + 16k) take consecutive slots
-        const uint32_t c0 = (uint32_t)__shfl((int)mine, (int)r, 64), c1 = (uint32_t)__shfl((int)mine, (int)r + 16, 64);
-        const uint32_t c2 = (uint32_t)__shfl((int)mine, (int)r + 32, 64),
-                       c3 = (uint32_t)__shfl((int)mine, (int)r + 48, 64);
-        const uint32_t k = (uint32_t)(l >> 4);
-        uint32_t pos = cnt[n] + (k > 0 ? c0 : 0u) + (k > 1 ? c1 : 0u) + (k > 2 ? c2 : 0u);
-        cnt[n] += c0 + c1 + c2 + c3;
-        if (mine && qi < a.nq) {
-          uint64_t* out = a.cand + (size_t)qi * SCAN_KEYS_Q + span * slots;
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (d[m][i] <= bnd) {
-                if (pos < slots) out[pos] = make_key(d[m][i], e0 + (uint32_t)m * 16u + rb + (uint32_t)i);
-                ++pos;
-              }
-        }
+          for (int i = 0; i < 4; ++i)
+            if (u[m][i] >= nthr[n]) {
+              out[4u * min(cnt[n], lane_cap - 1u)] =
+                  make_key((uint32_t)(qn[n] - u[m][i]), e0 + (uint32_t)m * 16u + rb + (uint32_t)i);
+              ++cnt[n];
+            }
       }
+    }
+    if constexpr (PASS != SCAN_FILTER) {
+      // the group's minimum for each query, one query per lane; groups are
+      // written in pairs (even, odd), an unpaired last group alone
+      const int g = quad_max_scatter(gmax);
+      const uint32_t gv = g == U_INVALID ? D_INVALID : (uint32_t)(qn_own - g);
+      uint32_t* gp = a.gmin + (size_t)q_own * a.g_stride + (e0 >> 5);
+      if (q_own < a.nq) {
+        if ((e0 >> 5) & 1u)
+          *reinterpret_cast<uint2*>(gp - 1) = make_uint2(gprev, gv);
+        else if (e0 + 32u >= e_end)
+          *gp = gv;
+      }
+      gprev = gv;
     }
   }
   if constexpr (PASS == SCAN_FILTER) {
+    // the four lanes' counts of query r, a byte each (lane k's in byte k)
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
       const uint32_t qi = q0 + (uint32_t)n * 16u + r;
-      if (l < 16 && qi < a.nq) a.ncand[(size_t)qi * n_span + span] = cnt[n];
+      const uint32_t packed = quad_sum(min(cnt[n], 255u) << (8u * k4));
+      if (l < 16 && qi < a.nq) a.ncand[(size_t)qi * n_span + span] = packed;
     }
   }
 }
 
-template <int PASS, bool PRE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_scan_dist(Index ix, ScanArgs a) {
+template <int PASS, bool PRE, int KS, bool CHUNKED>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(KS <= 2 ? (PASS == SCAN_MIN ? 4 : 3) : 2))) k_scan_dist(Index ix, ScanArgs a) {
   if (gated(ix, a.d)) return;
   resolve(ix, a);
   const uint32_t n_span = (a.ns + SCAN_SPAN - 1) / SCAN_SPAN, n_tasks = n_span * ((a.nq + SD_WT - 1) / SD_WT);
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   // consecutive waves take consecutive spans of one query tile
   for (uint32_t t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < n_tasks; t += waves)
-    scan_dist_wave_span<PASS, PRE>(ix, a, t % n_span, (t / n_span) * SD_WT);
+    scan_dist_wave_span<PASS, PRE, KS, CHUNKED>(ix, a, t % n_span, (t / n_span) * SD_WT);
 }
 
 // Float rows: the same 64 x 256 tiling over 16-element slices, in FP32; start
@@ -687,7 +766,10 @@ __device__ inline uint32_t scan_need(const ScanArgs& a, uint32_t qi) {
 // groups than that, every valid row (D_INVALID - 1).
 __device__ inline uint32_t scan_bound_one(const ScanArgs& a, uint32_t qi, uint32_t need_all) {
   const int l = lane_id();
-  const uint32_t ng = (a.ns + a.g_rows - 1) / a.g_rows * (a.g_rows / 32);
+  // uint8 rows (64-row tiles) write groups of 32 consecutive rows up to the
+  // last row; float rows (256-row tiles) interleave rows over a tile's eight
+  // groups and write all of them
+  const uint32_t ng = a.g_rows == (uint32_t)SD_WT ? (a.ns + 31) / 32 : (a.ns + a.g_rows - 1) / a.g_rows * (a.g_rows / 32);
   const uint32_t* G = a.gmin + (size_t)qi * a.g_stride;
   uint32_t gv[SEL_GPL];
   uint32_t glo = D_INVALID, ghi = 0, gvalid = 0;
@@ -836,31 +918,47 @@ __global__ void __launch_bounds__(256) k_scan_final(Index ix, ScanArgs a, uint32
   if (qi >= a.nq) return;
   uint64_t* sel = reinterpret_cast<uint64_t*>(smem + (size_t)(threadIdx.x >> 6) * 8 * sel_cap);
   const int l = lane_id();
-  const uint32_t n_span = (a.ns + SCAN_SPAN - 1) / SCAN_SPAN, slots = scan_slots(n_span);  // one span per lane
-  // the first keys of each span (at least 16 slots each) are read together with
-  // the counts; slots past a count hold stale keys that are never used
+  const uint32_t n_span = (a.ns + SCAN_SPAN - 1) / SCAN_SPAN;  // one span per lane
+  const uint32_t lane_cap = scan_lane_slots(n_span);
+  // a span's region interleaves the keys of its four scoring lanes (lane k's
+  // j-th key in slot 4j + k, at least 4 slots per lane) and its count word
+  // holds their counts, a byte each. The first two keys of every scoring lane
+  // are read together with the counts; slots past a count hold stale keys
+  // that are never used
   constexpr uint32_t EARLY = 8;
-  const uint64_t* src = a.cand + (size_t)qi * SCAN_KEYS_Q + (uint32_t)l * slots;
+  const uint64_t* src = a.cand + (size_t)qi * SCAN_KEYS_Q + (uint32_t)l * scan_slots(n_span);
   uint64_t early[EARLY];
 #pragma unroll
   for (uint32_t j = 0; j < EARLY; ++j) early[j] = (uint32_t)l < n_span ? src[j] : KEY_NONE;
-  const uint32_t c = (uint32_t)l < n_span ? a.ncand[(size_t)qi * n_span + (uint32_t)l] : 0u;
+  const uint32_t packed = (uint32_t)l < n_span ? a.ncand[(size_t)qi * n_span + (uint32_t)l] : 0u;
+  uint32_t ck[4], c = 0;
+  bool over = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    ck[k] = (packed >> (8 * k)) & 0xFFu;
+    over |= ck[k] > lane_cap;
+    c += ck[k];
+  }
   uint32_t off = c;  // inclusive prefix over the spans
   for (int o = 1; o < 64; o <<= 1) {
     const uint32_t v = (uint32_t)__shfl_up((int)off, (unsigned)o, 64);
     if (l >= o) off += v;
   }
   const uint32_t n = (uint32_t)__shfl((int)off, 63, 64);
-  if (ballot(c > slots) || n > sel_cap) {
+  if (ballot(over) || n > sel_cap) {
     scan_dense_row_u8(ix, a, qi);
     scan_select_one(ix, a, qi, sel, sel_cap);
     return;
   }
   off -= c;
 #pragma unroll
-  for (uint32_t j = 0; j < EARLY; ++j)
-    if (j < c) sel[off + j] = early[j];
-  for (uint32_t j = EARLY; j < c; ++j) sel[off + j] = src[j];
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (uint32_t j = 0; j < EARLY / 4; ++j)
+      if (j < ck[k]) sel[off + j] = early[4 * j + (uint32_t)k];
+    for (uint32_t j = EARLY / 4; j < ck[k]; ++j) sel[off + j] = src[4 * j + (uint32_t)k];
+    off += ck[k];
+  }
   const int np = next_pow2_ge64((int)n);
   for (int i = (int)n + l; i < np; i += 64) sel[i] = KEY_NONE;
   wave_sync();
@@ -4006,6 +4104,18 @@ uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots, uint32_t W) {
 // lanes per row of a float copy: 3 chunks of 16 bytes per lane
 static inline int float_lanes(uint32_t dim, int elem_bytes) { return (int)(dim * (uint32_t)elem_bytes / 16u / 3u); }
 
+// uint8 start-set scoring: 64-byte slices per row fixed at compile time (two
+// up to 128 bytes, four up to 256, then chunks of four)
+template <int PASS, bool PRE>
+static void launch_scan_dist(const Index& ix, const ScanArgs& a, dim3 grid, hipStream_t s) {
+  if (ix.dim <= 128)
+    hipLaunchKernelGGL((k_scan_dist<PASS, PRE, 2, false>), grid, dim3(256), 0, s, ix, a);
+  else if (ix.dim <= 256)
+    hipLaunchKernelGGL((k_scan_dist<PASS, PRE, 4, false>), grid, dim3(256), 0, s, ix, a);
+  else
+    hipLaunchKernelGGL((k_scan_dist<PASS, PRE, 4, true>), grid, dim3(256), 0, s, ix, a);
+}
+
 hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hipEvent_t after_dist) {
   if (args.nq == 0) return hipSuccess;
   ScanArgs a = args;
@@ -4028,9 +4138,9 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
     if (a.L > SCAN_FILTER_L_MAX) {
       // long lists: the bound admits a large share of the rows, so the matrix is written
       if (pre)
-        hipLaunchKernelGGL((k_scan_dist<SCAN_DENSE, true>), tgrid, dim3(256), 0, s, ix, a);
+        launch_scan_dist<SCAN_DENSE, true>(ix, a, tgrid, s);
       else
-        hipLaunchKernelGGL((k_scan_dist<SCAN_DENSE, false>), tgrid, dim3(256), 0, s, ix, a);
+        launch_scan_dist<SCAN_DENSE, false>(ix, a, tgrid, s);
       if (after_dist) {
         const hipError_t e = hipEventRecord(after_dist, s);
         if (e != hipSuccess) return e;
@@ -4040,13 +4150,13 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
     }
     if (!a.bound || !a.ncand || !a.cand) return hipErrorInvalidValue;
     if (pre) {
-      hipLaunchKernelGGL((k_scan_dist<SCAN_MIN, true>), tgrid, dim3(256), 0, s, ix, a);
+      launch_scan_dist<SCAN_MIN, true>(ix, a, tgrid, s);
       hipLaunchKernelGGL(k_scan_bound, grid, blk, 0, s, ix, a);
-      hipLaunchKernelGGL((k_scan_dist<SCAN_FILTER, true>), tgrid, dim3(256), 0, s, ix, a);
+      launch_scan_dist<SCAN_FILTER, true>(ix, a, tgrid, s);
     } else {
-      hipLaunchKernelGGL((k_scan_dist<SCAN_MIN, false>), tgrid, dim3(256), 0, s, ix, a);
+      launch_scan_dist<SCAN_MIN, false>(ix, a, tgrid, s);
       hipLaunchKernelGGL(k_scan_bound, grid, blk, 0, s, ix, a);
-      hipLaunchKernelGGL((k_scan_dist<SCAN_FILTER, false>), tgrid, dim3(256), 0, s, ix, a);
+      launch_scan_dist<SCAN_FILTER, false>(ix, a, tgrid, s);
     }
     if (after_dist) {
       const hipError_t e = hipEventRecord(after_dist, s);

@@ -40,7 +40,10 @@ struct SearchArgs {
 // 64 spans), key slots per query (split evenly over the spans), keys sorted
 // per query before the dense fallback, and the longest list selected from
 // those keys (longer lists write the distance matrix)
-constexpr uint32_t SCAN_SPAN = 256, SCAN_KEYS_Q = 1024, SCAN_CAND_CAP = 1024, SCAN_FILTER_L_MAX = 128;
+constexpr uint32_t SCAN_SPAN = 256, SCAN_KEYS_Q = 2048, SCAN_CAND_CAP = 1024, SCAN_FILTER_L_MAX = 128;
+// bytes of the uint8 entry set's operand-ordered copy: n entries padded to a
+// multiple of 32, rows padded to whole 64-byte slices
+inline uint64_t ent_copy_bytes(uint64_t n, uint32_t dim) { return (n + 31) / 32 * 32 * ((dim + 63) / 64 * 64); }
 
 struct ScanArgs {
   int mode;
@@ -53,7 +56,8 @@ struct ScanArgs {
   uint32_t g_stride;   // group slots per query (upper bound over the launch-time ns)
   uint32_t g_rows;     // start rows per scoring tile; each tile has g_rows / 32 group slots
   uint32_t* bound;     // uint8 rows: [nq] bound on the L-th smallest distance
-  uint32_t* ncand;     // uint8 rows: [nq x spans] rows at or below the bound in each span of start rows
+  uint32_t* ncand;     // uint8 rows: [nq x spans] rows at or below the bound in each span of start rows,
+                       // one byte per scoring lane
   uint64_t* cand;      // uint8 rows: [nq x SCAN_KEYS_Q] their (distance, row) keys, by span
   uint64_t* out_keys;  // [nq x out_stride]
   uint32_t* out_n;     // [nq]
