@@ -220,10 +220,16 @@ uint32_t maint_waves_per_block(const MaintArgs& a) {
   return w >= 4 ? 4 : (w >= 2 ? 2 : 1);
 }
 
-// queries per launch so that the distance matrix fits its scratch
+// queries per launch so that the distance matrix fits its scratch; a whole
+// number of 64-query tiles (the uint8 group minima are stored by tile)
 uint32_t scan_chunk_for(const etale_index* ix, uint32_t ns) {
-  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ix->scan_chunk, ix->dist_cap / std::max(1u, ns)));
+  const uint64_t c = std::min<uint64_t>(ix->scan_chunk, ix->dist_cap / std::max(1u, ns));
+  return (uint32_t)std::max<uint64_t>(1, c >= 64 ? c / 64 * 64 : c);
 }
+
+// group-minimum slots of a chunk of c queries over ns start rows: whole
+// 64-query tiles of at most ns / 32 + 8 slots per query
+uint64_t gmin_slots(uint64_t c, uint64_t ns) { return (c + 63) / 64 * 64 * (ns / 32 + 8); }
 
 constexpr uint32_t BOOT_MAX = 16384;  // a bootstrap batch is scored as one start set
 
@@ -258,7 +264,7 @@ ScanScratch library_scratch(const etale_index* ix, uint32_t ns) {
 // bytes of `scratch` that a chunk of c queries over ns start rows at list
 // length L uses (every region 256-byte aligned)
 uint64_t noalloc_bytes(uint64_t c, uint64_t ns, uint64_t L) {
-  return round256(c * L * 8) + round256(c * 4) + round256(c * ns * 4) + round256(c * (ns / 32 + 8) * 4) +
+  return round256(c * L * 8) + round256(c * 4) + round256(c * ns * 4) + round256(gmin_slots(c, ns) * 4) +
          round256(c * 4) + round256(c * 64 * 4) + round256(c * SCAN_KEYS_Q * 8);
 }
 
@@ -277,7 +283,7 @@ ScanScratch noalloc_scratch(unsigned char* base, uint32_t ns, uint32_t L) {
   s.keys = reinterpret_cast<uint64_t*>(take(c * L * 8));
   s.n = reinterpret_cast<uint32_t*>(take(c * 4));
   s.dist = reinterpret_cast<uint32_t*>(take(c * ns * 4));
-  s.gmin = reinterpret_cast<uint32_t*>(take(c * (ns / 32 + 8) * 4));
+  s.gmin = reinterpret_cast<uint32_t*>(take(gmin_slots(c, ns) * 4));
   s.bound = reinterpret_cast<uint32_t*>(take(c * 4));
   s.ncand = reinterpret_cast<uint32_t*>(take(c * 64 * 4));
   s.cand = reinterpret_cast<uint64_t*>(take(c * SCAN_KEYS_Q * 8));
@@ -711,7 +717,8 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   ALLOC(ix->scan_n, (uint64_t)ix->scan_chunk * 4);
   ix->dist_cap = std::min<uint64_t>(1ull << 27, std::max<uint64_t>((uint64_t)ix->scan_chunk * c.n_entry, B * 4096));
   ALLOC(ix->scan_dist, ix->dist_cap * 4);
-  // a chunk of n queries over ns start rows has at most n (ns / 32 + 8) group slots
+  // a chunk of n queries (a multiple of 64) over ns start rows has at most
+  // n (ns / 32 + 8) group slots
   ix->gmin_cap = ix->dist_cap / 32 + 8ull * ix->scan_chunk;
   ALLOC(ix->scan_gmin, ix->gmin_cap * 4);
   ALLOC(ix->scan_bound, (uint64_t)ix->scan_chunk * 4);
@@ -1216,7 +1223,7 @@ etale_status etale_serve(etale_t ix, const etale_serve_config* cfg, const etale_
   dev(&ss.keys, (uint64_t)T * c.L * 8);
   dev(&ss.n, (uint64_t)T * 4);
   dev(&ss.dist, (uint64_t)T * ns * 4);
-  dev(&ss.gmin, (uint64_t)T * (ns / 32 + 8) * 4);
+  dev(&ss.gmin, gmin_slots(T, ns) * 4);
   dev(&ss.bound, (uint64_t)T * 4);
   dev(&ss.ncand, (uint64_t)T * 64 * 4);
   dev(&ss.cand, (uint64_t)T * SCAN_KEYS_Q * 8);

@@ -326,6 +326,13 @@ __device__ inline uint32_t scan_slots(uint32_t n_span) { return SCAN_KEYS_Q / ma
 // slots of one lane of a (query, span) region: below 255, where the byte count saturates
 __device__ inline uint32_t scan_lane_slots(uint32_t n_span) { return min(scan_slots(n_span) / 4u, 254u); }
 
+// uint8 group minima, tiled: for each 64-query tile and span of start rows, the
+// eight groups of each of the tile's queries side by side (64 x 8 words); the
+// first slot of query qi in span s
+__device__ inline size_t gmin_tile_slot(uint32_t qi, uint32_t s, uint32_t n_span) {
+  return (((size_t)(qi >> 6) * n_span + s) * 64u + (qi & 63u)) * 8u;
+}
+
 // the two values a lane and its partner l ^ 16 (SWAP16) or l ^ 32 hold in a
 // and b: after the swap a lane of an even 16-lane row holds its own a and its
 // partner's a, a lane of an odd row its partner's b and its own b
@@ -416,8 +423,12 @@ __device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, u
       cnt[n] = 0;
     }
   }
-  uint32_t gprev = D_INVALID;  // SCAN_MIN / SCAN_DENSE: the previous (even) group's minimum
-  for (uint32_t e0 = e_begin; e0 < e_end; e0 += 32u) {
+  uint32_t gb[8];  // SCAN_MIN / SCAN_DENSE: the span's group minima of this lane's own query
+#pragma unroll
+  for (int j = 0; j < 8; ++j) gb[j] = D_INVALID;
+  // one group of 32 start rows: its products and results; the group's minimum
+  // for each query, one query per lane (SCAN_MIN / SCAN_DENSE)
+  auto group = [&](uint32_t e0) -> uint32_t {
     // this lane's rows of the two 16-row blocks: 16m + r, and 16m + rb + i in the result
     const uint8_t* erow[2];
 #pragma unroll
@@ -541,18 +552,29 @@ __device__ inline void scan_dist_wave_span(const Index& ix, const ScanArgs& a, u
       }
     }
     if constexpr (PASS != SCAN_FILTER) {
-      // the group's minimum for each query, one query per lane; groups are
-      // written in pairs (even, odd), an unpaired last group alone
       const int g = quad_max_scatter(gmax);
-      const uint32_t gv = g == U_INVALID ? D_INVALID : (uint32_t)(qn_own - g);
-      uint32_t* gp = a.gmin + (size_t)q_own * a.g_stride + (e0 >> 5);
-      if (q_own < a.nq) {
-        if ((e0 >> 5) & 1u)
-          *reinterpret_cast<uint2*>(gp - 1) = make_uint2(gprev, gv);
-        else if (e0 + 32u >= e_end)
-          *gp = gv;
-      }
-      gprev = gv;
+      return g == U_INVALID ? D_INVALID : (uint32_t)(qn_own - g);
+    }
+    return D_INVALID;
+  };
+  if constexpr (PASS == SCAN_FILTER) {
+    for (uint32_t e0 = e_begin; e0 < e_end; e0 += 32u) group(e0);
+  } else {
+    // unrolled, so that each minimum has a register of its own
+#pragma unroll
+    for (int j = 0; j < SCAN_SPAN / 32; ++j) {
+      const uint32_t e0 = e_begin + (uint32_t)j * 32u;
+      if (e0 >= e_end) break;
+      gb[j] = group(e0);
+    }
+  }
+  if constexpr (PASS != SCAN_FILTER) {
+    // the span's eight minima of each query side by side: the wave's two
+    // stores fill 2 KiB of whole lines (groups past the start set stay invalid)
+    if (q_own < a.nq) {
+      uint4* gp = reinterpret_cast<uint4*>(a.gmin + gmin_tile_slot(q_own, span, n_span));
+      gp[0] = make_uint4(gb[0], gb[1], gb[2], gb[3]);
+      gp[1] = make_uint4(gb[4], gb[5], gb[6], gb[7]);
     }
   }
   if constexpr (PASS == SCAN_FILTER) {
@@ -766,17 +788,34 @@ __device__ inline uint32_t scan_need(const ScanArgs& a, uint32_t qi) {
 // groups than that, every valid row (D_INVALID - 1).
 __device__ inline uint32_t scan_bound_one(const ScanArgs& a, uint32_t qi, uint32_t need_all) {
   const int l = lane_id();
-  // uint8 rows (64-row tiles) write groups of 32 consecutive rows up to the
-  // last row; float rows (256-row tiles) interleave rows over a tile's eight
-  // groups and write all of them
-  const uint32_t ng = a.g_rows == (uint32_t)SD_WT ? (a.ns + 31) / 32 : (a.ns + a.g_rows - 1) / a.g_rows * (a.g_rows / 32);
-  const uint32_t* G = a.gmin + (size_t)qi * a.g_stride;
   uint32_t gv[SEL_GPL];
+  if (a.g_rows == (uint32_t)SD_WT) {
+    // uint8 rows: the tiled layout, eight slots per span (all written); lane l
+    // takes groups 4 (64 u + l) .. + 3, one 16-byte load each
+    const uint32_t n_span = (a.ns + SCAN_SPAN - 1) / SCAN_SPAN, ng = n_span * 8u;
+#pragma unroll
+    for (int u = 0; u < SEL_GPL / 4; ++u) {
+      const uint32_t i = (uint32_t)(u * 64 + l) * 4u;
+      uint4 v = make_uint4(D_INVALID, D_INVALID, D_INVALID, D_INVALID);
+      if (i < ng) v = *reinterpret_cast<const uint4*>(a.gmin + gmin_tile_slot(qi, i >> 3, n_span) + (i & 7u));
+      gv[4 * u] = v.x;
+      gv[4 * u + 1] = v.y;
+      gv[4 * u + 2] = v.z;
+      gv[4 * u + 3] = v.w;
+    }
+  } else {
+    // float rows: each query's row of g_stride slots (a 256-row tile's eight groups interleave its rows)
+    const uint32_t ng = (a.ns + a.g_rows - 1) / a.g_rows * (a.g_rows / 32);
+    const uint32_t* G = a.gmin + (size_t)qi * a.g_stride;
+#pragma unroll
+    for (int t = 0; t < SEL_GPL; ++t) {
+      const uint32_t i = (uint32_t)(t * 64 + l);
+      gv[t] = i < ng ? G[i] : D_INVALID;
+    }
+  }
   uint32_t glo = D_INVALID, ghi = 0, gvalid = 0;
 #pragma unroll
   for (int t = 0; t < SEL_GPL; ++t) {
-    const uint32_t i = (uint32_t)(t * 64 + l);
-    gv[t] = i < ng ? G[i] : D_INVALID;
     if (gv[t] != D_INVALID) {
       glo = min(glo, gv[t]);
       ghi = max(ghi, gv[t]);
