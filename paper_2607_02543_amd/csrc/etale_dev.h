@@ -232,6 +232,41 @@ __device__ inline uint64_t lane_xor(uint64_t v) {
   return ((uint64_t)lane_xor<J>((uint32_t)(v >> 32)) << 32) | lane_xor<J>((uint32_t)v);
 }
 
+// Bitonic sort of 64 NK keys in registers, ascending: key s * 64 + l in v[s]
+// of lane l. Partners within 64 lanes move by lane_xor, distance 64 is the
+// lane's own pair.
+template <int J, int K, int NK>
+__device__ inline void bitonic_step_regs(uint64_t (&v)[NK]) {
+  const int l = lane_id();
+  if constexpr (J == 64) {
+    const uint64_t lo = min(v[0], v[1]), hi = max(v[0], v[1]);
+    v[0] = lo;
+    v[1] = hi;
+  } else {
+    const bool lower = (l & J) == 0;
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      const uint64_t p = lane_xor<J>(v[s]);
+      const bool up = ((s * 64 + l) & K) == 0;  // direction of this element's run
+      v[s] = lower == up ? min(v[s], p) : max(v[s], p);
+    }
+  }
+}
+template <int K, int J, int NK>
+__device__ inline void bitonic_pass_regs(uint64_t (&v)[NK]) {
+  if constexpr (J > 0) {
+    bitonic_step_regs<J, K, NK>(v);
+    bitonic_pass_regs<K, J / 2, NK>(v);
+  }
+}
+template <int NK, int K = 2>
+__device__ inline void wave_sort_regs(uint64_t (&v)[NK]) {
+  if constexpr (K <= 64 * NK) {
+    bitonic_pass_regs<K, K / 2, NK>(v);
+    wave_sort_regs<NK, K * 2>(v);
+  }
+}
+
 // sum over the G consecutive lanes of a group (G a power of two), every lane
 // of the group ending with the same value
 template <int G, class T>

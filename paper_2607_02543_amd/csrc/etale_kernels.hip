@@ -1001,11 +1001,26 @@ __global__ void __launch_bounds__(256) k_scan_final(Index ix, ScanArgs a, uint32
   const int np = next_pow2_ge64((int)n);
   for (int i = (int)n + l; i < np; i += 64) sel[i] = KEY_NONE;
   wave_sync();
-  wave_bitonic_sort(sel, np);
   const uint32_t cnt = min(n, scan_need(a, qi));
-  for (uint32_t i = (uint32_t)l; i < cnt; i += 64) {
-    const uint64_t k = sel[i];
-    a.out_keys[(size_t)qi * a.out_stride + i] = make_key(key_dist(k), start_id(ix, a, key_id(k)));
+  uint64_t* out = a.out_keys + (size_t)qi * a.out_stride;
+  if (np <= 128) {
+    // up to 128 keys: sorted in registers, two per lane
+    uint64_t v[2] = {sel[l], np > 64 ? sel[64 + l] : KEY_NONE};
+    if (np > 64) {
+      wave_sort_regs<2>(v);
+    } else {
+      uint64_t (&v1)[1] = *reinterpret_cast<uint64_t(*)[1]>(&v[0]);
+      wave_sort_regs<1>(v1);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if ((uint32_t)(s * 64 + l) < cnt) out[s * 64 + l] = make_key(key_dist(v[s]), start_id(ix, a, key_id(v[s])));
+  } else {
+    wave_bitonic_sort(sel, np);
+    for (uint32_t i = (uint32_t)l; i < cnt; i += 64) {
+      const uint64_t k = sel[i];
+      out[i] = make_key(key_dist(k), start_id(ix, a, key_id(k)));
+    }
   }
   if (l == 0) a.out_n[qi] = cnt;
 }
