@@ -783,39 +783,14 @@ __device__ inline uint32_t scan_need(const ScanArgs& a, uint32_t qi) {
   return min(a.L, a.ns - (self_in ? 1u : 0u));
 }
 
-// The need_all-th smallest group minimum of query qi: at least need_all
-// groups, and so at least need_all rows, lie at or below it. With fewer valid
-// groups than that, every valid row (D_INVALID - 1).
-__device__ inline uint32_t scan_bound_one(const ScanArgs& a, uint32_t qi, uint32_t need_all) {
-  const int l = lane_id();
-  uint32_t gv[SEL_GPL];
-  if (a.g_rows == (uint32_t)SD_WT) {
-    // uint8 rows: the tiled layout, eight slots per span (all written); lane l
-    // takes groups 4 (64 u + l) .. + 3, one 16-byte load each
-    const uint32_t n_span = (a.ns + SCAN_SPAN - 1) / SCAN_SPAN, ng = n_span * 8u;
-#pragma unroll
-    for (int u = 0; u < SEL_GPL / 4; ++u) {
-      const uint32_t i = (uint32_t)(u * 64 + l) * 4u;
-      uint4 v = make_uint4(D_INVALID, D_INVALID, D_INVALID, D_INVALID);
-      if (i < ng) v = *reinterpret_cast<const uint4*>(a.gmin + gmin_tile_slot(qi, i >> 3, n_span) + (i & 7u));
-      gv[4 * u] = v.x;
-      gv[4 * u + 1] = v.y;
-      gv[4 * u + 2] = v.z;
-      gv[4 * u + 3] = v.w;
-    }
-  } else {
-    // float rows: each query's row of g_stride slots (a 256-row tile's eight groups interleave its rows)
-    const uint32_t ng = (a.ns + a.g_rows - 1) / a.g_rows * (a.g_rows / 32);
-    const uint32_t* G = a.gmin + (size_t)qi * a.g_stride;
-#pragma unroll
-    for (int t = 0; t < SEL_GPL; ++t) {
-      const uint32_t i = (uint32_t)(t * 64 + l);
-      gv[t] = i < ng ? G[i] : D_INVALID;
-    }
-  }
+// The need_all-th smallest of the group minima held GPL per lane (the rest
+// unused): at least need_all groups, and so at least need_all rows, lie at or
+// below it. With fewer valid groups than that, every valid row (D_INVALID - 1).
+template <int GPL>
+__device__ inline uint32_t bound_bisect(const uint32_t (&gv)[SEL_GPL], uint32_t need_all) {
   uint32_t glo = D_INVALID, ghi = 0, gvalid = 0;
 #pragma unroll
-  for (int t = 0; t < SEL_GPL; ++t) {
+  for (int t = 0; t < GPL; ++t) {
     if (gv[t] != D_INVALID) {
       glo = min(glo, gv[t]);
       ghi = max(ghi, gv[t]);
@@ -833,11 +808,45 @@ __device__ inline uint32_t scan_bound_one(const ScanArgs& a, uint32_t qi, uint32
     const uint32_t mid = lo + ((hi - lo) >> 1);
     uint32_t c = 0;
 #pragma unroll
-    for (int t = 0; t < SEL_GPL; ++t) c += (uint32_t)__popcll(ballot(gv[t] <= mid));
+    for (int t = 0; t < GPL; ++t) c += (uint32_t)__popcll(ballot(gv[t] <= mid));
     if (c >= need_all) hi = mid;
     else lo = mid + 1;
   }
   return hi;
+}
+
+// query qi's bound from its group minima
+__device__ inline uint32_t scan_bound_one(const ScanArgs& a, uint32_t qi, uint32_t need_all) {
+  const int l = lane_id();
+  uint32_t gv[SEL_GPL];
+  uint32_t ng;
+  if (a.g_rows == (uint32_t)SD_WT) {
+    // uint8 rows: the tiled layout, eight slots per span (all written); lane l
+    // takes groups 4 (64 u + l) .. + 3, one 16-byte load each
+    const uint32_t n_span = (a.ns + SCAN_SPAN - 1) / SCAN_SPAN;
+    ng = n_span * 8u;
+#pragma unroll
+    for (int u = 0; u < SEL_GPL / 4; ++u) {
+      const uint32_t i = (uint32_t)(u * 64 + l) * 4u;
+      uint4 v = make_uint4(D_INVALID, D_INVALID, D_INVALID, D_INVALID);
+      if (i < ng) v = *reinterpret_cast<const uint4*>(a.gmin + gmin_tile_slot(qi, i >> 3, n_span) + (i & 7u));
+      gv[4 * u] = v.x;
+      gv[4 * u + 1] = v.y;
+      gv[4 * u + 2] = v.z;
+      gv[4 * u + 3] = v.w;
+    }
+  } else {
+    // float rows: each query's row of g_stride slots (a 256-row tile's eight groups interleave its rows)
+    ng = (a.ns + a.g_rows - 1) / a.g_rows * (a.g_rows / 32);
+    const uint32_t* G = a.gmin + (size_t)qi * a.g_stride;
+#pragma unroll
+    for (int t = 0; t < SEL_GPL; ++t) {
+      const uint32_t i = (uint32_t)(t * 64 + l);
+      gv[t] = i < ng ? G[i] : D_INVALID;
+    }
+  }
+  // up to 256 groups fill four values per lane in both layouts
+  return ng <= 256 ? bound_bisect<4>(gv, need_all) : bound_bisect<SEL_GPL>(gv, need_all);
 }
 
 __device__ inline void scan_select_one(const Index& ix, const ScanArgs& a, uint32_t qi, uint64_t* sel, uint32_t cap) {
