@@ -92,6 +92,17 @@ def test_parity_many_entries_filtered_start_set():
     run_parity(small_workload(seed=12, rounds=1), n_entry=1000, search_L=(10, 64, 128))
 
 
+def test_parity_row_lengths():
+    # 64-, 256- and 512-byte rows: start-set scoring with slices past the row,
+    # four slices held in registers, and rows scored in two chunks (smaller R
+    # and L_build keep the longer rows' staged prunes within one workgroup's LDS,
+    # which index creation checks)
+    for dim, R, L_build in ((64, 16, 32), (256, 16, 32), (512, 8, 16)):
+        wl = dg.Workload(f"rows{dim}", dg.Mixture(dim, 8, 18.0, dg.METRIC_L2_U8), 1200, R, L_build, 6, 5,
+                         1, 0.05, 200, 10, (32,), 30 + dim, 400, 400)
+        run_parity(wl, n_entry=300, search_L=(16, 48))
+
+
 def test_parity_tombstone_only():
     run_parity(small_workload(seed=3), tombstone_only=True)
 
