@@ -698,7 +698,7 @@ etale_status etale_create(const etale_config* cfg, etale_t* out) {
   ALLOC(ix->slabs, P * 2 * R * 4);
   ALLOC(ix->free_stack, P * 4);
   ALLOC(ix->retired_stack, P * 4);
-  ALLOC(ix->ctr, C_NCOUNTERS * 8);
+  ALLOC(ix->ctr, CTR_WORDS * 8);
   ALLOC(ix->entries, (uint64_t)c.n_entry * 4);
   if (c.metric == ETALE_METRIC_L2_U8) {
     ALLOC(ix->ent_x, ent_copy_bytes(c.n_entry, c.dim));

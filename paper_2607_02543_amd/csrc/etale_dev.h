@@ -72,8 +72,15 @@ enum Counter {
   C_NSEG,      // segments (runs of one target) of the last sorted pair list
   C_QUEUE,     // work queue of the running search launch
   C_QDONE,     // waves of that launch that have left the queue
+  C_RES_FREE,  // a launch's slab reservation: free-stack top before it (~0: none)
+  C_RES_RET,   // and its first retired-stack slot (~0: none)
   C_NCOUNTERS = 32
 };
+// the repair launch's work queues, each on a line of its own after the
+// counters (atomics on one line serialize, whichever word they touch)
+constexpr uint32_t N_RQ = 8, RQ_STRIDE = 32;
+constexpr uint32_t CTR_WORDS = C_NCOUNTERS + N_RQ * RQ_STRIDE;
+__host__ __device__ inline uint32_t rq_word(uint32_t q) { return C_NCOUNTERS + q * RQ_STRIDE; }
 
 // Round gate: set before any mutation of a round; kernels whose skip mask
 // meets it do nothing.
@@ -609,9 +616,64 @@ __device__ inline SlabCursor reserve_slabs(const Index& ix, uint32_t n_alloc, ui
   return c;
 }
 
+// reserve_slabs for every wave of a workgroup (all of them call it, with
+// their own counts) with one pair of atomics for the workgroup: waves take
+// consecutive ranges of the workgroup's reservation. Same-address atomics from
+// thousands of waves serialize at the cache, so kernels with many short waves
+// reserve this way.
+__device__ inline SlabCursor reserve_slabs_block(const Index& ix, uint32_t n_alloc, uint32_t n_retire) {
+  __shared__ uint32_t s_na[16], s_nr[16];
+  __shared__ unsigned long long s_free, s_ret;
+  const uint32_t wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane_id() == 0) {
+    s_na[wv] = n_alloc;
+    s_nr[wv] = n_retire;
+  }
+  __syncthreads();
+  uint32_t pa = 0, pr = 0, ta = 0, tr = 0;
+  for (uint32_t k = 0; k < nw; ++k) {
+    if (k < wv) {
+      pa += s_na[k];
+      pr += s_nr[k];
+    }
+    ta += s_na[k];
+    tr += s_nr[k];
+  }
+  if (threadIdx.x == 0) {
+    unsigned long long f = ~0ull, r = ~0ull;
+    if (ta) {
+      const unsigned long long top = atomicAdd(&ix.ctr[C_FREE_TOP], (unsigned long long)(-(long long)ta));
+      if (top >= ta && top <= ix.P)
+        f = top;
+      else
+        atomicAdd(&ix.ctr[C_FREE_TOP], (unsigned long long)ta);  // give back; single allocs report the shortage
+    }
+    if (tr) {
+      const unsigned long long at = atomicAdd(&ix.ctr[C_RETIRED_TOP], (unsigned long long)tr);
+      if (at + tr <= ix.P)
+        r = at;
+      else
+        atomicAdd(&ix.ctr[C_RETIRED_TOP], (unsigned long long)(-(long long)tr));
+    }
+    s_free = f;
+    s_ret = r;
+  }
+  __syncthreads();
+  SlabCursor c;
+  if (n_alloc && s_free != ~0ull) {
+    c.free_hi = s_free - pa;
+    c.free_left = n_alloc;
+  }
+  if (n_retire && s_ret != ~0ull) {
+    c.ret_next = s_ret + pr;
+    c.ret_left = n_retire;
+  }
+  return c;
+}
+
 // after a wave's last item: reserved slots left unused go back to the pool
 // (every reserved retired slot must name a slab), then the phase counter
-__device__ inline void finish_slabs(const Index& ix, SlabCursor& c, Counter which) {
+__device__ inline void return_slabs(const Index& ix, SlabCursor& c) {
   const int l = lane_id();
   while (c.ret_left) {  // fill with an unused reserved slab, else a freshly popped one
     uint32_t s = NONE;
@@ -638,8 +700,24 @@ __device__ inline void finish_slabs(const Index& ix, SlabCursor& c, Counter whic
     --c.free_left;
     if (l == 0) retire_slab(ix, s);
   }
+}
+__device__ inline void finish_slabs(const Index& ix, SlabCursor& c, Counter which) {
+  return_slabs(ix, c);
   if (c.pubs) wave_atomic_add(&ix.ctr[which], (unsigned long long)c.pubs);
   c.pubs = 0;
+}
+
+// finish_slabs for every wave of a workgroup (all of them call it): the
+// publication count goes to the counter with one atomic per workgroup
+__device__ inline void finish_slabs_block(const Index& ix, SlabCursor& c, Counter which) {
+  __shared__ unsigned int s_pubs;
+  return_slabs(ix, c);
+  if (threadIdx.x == 0) s_pubs = 0;
+  __syncthreads();
+  if (lane_id() == 0 && c.pubs) atomicAdd(&s_pubs, c.pubs);
+  c.pubs = 0;
+  __syncthreads();
+  if (threadIdx.x == 0 && s_pubs) atomicAdd(&ix.ctr[which], (unsigned long long)s_pubs);
 }
 
 // Copy-on-write publication of list (ids, d)[0..n) for node u by the whole

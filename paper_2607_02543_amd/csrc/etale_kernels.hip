@@ -26,7 +26,8 @@ __global__ void k_init(Index ix) {
     ix.refs[i] = REF_UNBORN;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ix.P; i += stride)
     ix.free_stack[i] = (uint32_t)(ix.P - 1 - i);
-  if (blockIdx.x == 0 && threadIdx.x < C_NCOUNTERS) ix.ctr[threadIdx.x] = threadIdx.x == C_FREE_TOP ? ix.P : 0ull;
+  if (blockIdx.x == 0)
+    for (uint32_t i = threadIdx.x; i < CTR_WORDS; i += blockDim.x) ix.ctr[i] = i == C_FREE_TOP ? ix.P : 0ull;
 }
 
 // End of a launch epoch: the retired stack joins the free stack (Lemma 1).
@@ -2007,12 +2008,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   if (gated(ix, a.d)) return;
   resolve(ix, a);
   MaintLds m = carve(wave_lds(smem, a), a, ix.R);
-  SlabCursor cur = reserve_slabs(ix, wave_items(a.n), 0);  // new nodes hold no slab yet
+  SlabCursor cur = reserve_slabs_block(ix, wave_items(a.n), 0);  // new nodes hold no slab yet
   FOR_EACH_WAVE_ITEM(qi, a.n) {
     wave_sync();
     forward_one<P>(ix, a, m, qi, cur);
   }
-  finish_slabs(ix, cur, C_PUB_FORWARD);
+  finish_slabs_block(ix, cur, C_PUB_FORWARD);
 }
 
 __global__ void k_reverse_pairs(Index ix, MaintArgs a) {
@@ -2505,13 +2506,13 @@ __global__ void __launch_bounds__(256) k_reverse_apply(Index ix, MaintArgs a) {
   resolve(ix, a);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
   // every target is a live node with a slab: one fresh slab and one retired slab each
-  SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
+  SlabCursor cur = reserve_slabs_block(ix, wave_items(nseg), wave_items(nseg));
   MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   FOR_EACH_WAVE_ITEM(si, nseg) {
     wave_sync();
     reverse_one<P>(ix, a, m, a.seg[si], cur);
   }
-  finish_slabs(ix, cur, C_PUB_REVERSE);
+  finish_slabs_block(ix, cur, C_PUB_REVERSE);
 }
 
 // the same with the cached candidate state (uint8 rows, R <= 32): a kernel of
@@ -2591,13 +2592,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
   if (gated(ix, a.d)) return;
   resolve(ix, a);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
-  SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
+  SlabCursor cur = reserve_slabs_block(ix, wave_items(nseg), wave_items(nseg));
   const ChainLds c = carve_chain(wave_lds(smem, a), ix.R, a.vstride);
   FOR_EACH_WAVE_ITEM(si, nseg) {
     wave_sync();
     reverse_chain_u8<G>(ix, a, c, a.seg[si], cur);
   }
-  finish_slabs(ix, cur, C_PUB_REVERSE);
+  finish_slabs_block(ix, cur, C_PUB_REVERSE);
 }
 
 // ---- insert: refine -- same-batch nodes two hops away are offered ----------------------
@@ -3383,46 +3384,96 @@ __global__ void __launch_bounds__(256) k_repair_apply(Index ix, MaintArgs a) {
   if (gated(ix, a.d)) return;
   resolve(ix, a);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
-  SlabCursor cur = reserve_slabs(ix, wave_items(nseg), wave_items(nseg));
+  SlabCursor cur = reserve_slabs_block(ix, wave_items(nseg), wave_items(nseg));
   MaintLds m = carve(wave_lds(smem, a), a, ix.R);
   FOR_EACH_WAVE_ITEM(si, nseg) {
     wave_sync();
     repair_one<P>(ix, a, m, a.seg[si], cur);
   }
-  finish_slabs(ix, cur, C_PUB_REPAIR);
+  finish_slabs_block(ix, cur, C_PUB_REPAIR);
 }
 
 // the same with the wave-local candidate pool (uint8 rows, R <= 32), a kernel
 // of its own. Targets differ in cost (one to a dozen deleted out-neighbors),
-// so waves take them from a queue in batches, each batch with its own slab
-// reservation (one fresh and one retired slab per target).
+// so waves take them from queues in batches of four. Every target publishes
+// once, so the launch's slabs (one fresh and one retired slot per target) are
+// reserved beforehand by one thread (k_reserve_launch) and batch b takes the
+// b-th four of each: no per-batch atomics. The batches are split over N_RQ
+// queues on lines of their own, a workgroup starting at its own queue and
+// moving on when it is empty, and the publication count is summed per
+// workgroup: same-address atomics from thousands of waves serialize.
+__global__ void k_reserve_launch(Index ix, Dyn d) {
+  if (gated(ix, d)) return;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint64_t n = ix.ctr[C_NSEG];
+  unsigned long long f = ~0ull, r = ~0ull;
+  if (n) {
+    const unsigned long long top = atomicAdd(&ix.ctr[C_FREE_TOP], (unsigned long long)(-(long long)n));
+    if (top >= n && top <= ix.P)
+      f = top;
+    else
+      atomicAdd(&ix.ctr[C_FREE_TOP], (unsigned long long)n);  // a shortage: each publication allocates alone
+    const unsigned long long at = atomicAdd(&ix.ctr[C_RETIRED_TOP], (unsigned long long)n);
+    if (at + n <= ix.P)
+      r = at;
+    else
+      atomicAdd(&ix.ctr[C_RETIRED_TOP], (unsigned long long)(-(long long)n));
+  }
+  ix.ctr[C_RES_FREE] = f;
+  ix.ctr[C_RES_RET] = r;
+}
+
 template <int G>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_repair_pool(Index ix, MaintArgs a) {
   extern __shared__ __align__(16) char smem[];
   if (gated(ix, a.d)) return;
   resolve(ix, a);
   const uint32_t nseg = (uint32_t)ix.ctr[C_NSEG];
+  const uint64_t fbase = ix.ctr[C_RES_FREE], rbase = ix.ctr[C_RES_RET];
   constexpr uint32_t BATCH = 4;
+  const uint32_t nbat = (nseg + BATCH - 1) / BATCH;
   const PoolLds p = carve_pool(wave_lds(smem, a), a.vstride);
-  unsigned long long* queue = &ix.ctr[C_QUEUE];
-  for (;;) {
-    const uint32_t b0 = (uint32_t)wave_atomic_add(queue, BATCH);
-    if (b0 >= nseg) break;
-    const uint32_t nb = min(BATCH, nseg - b0);
-    SlabCursor cur = reserve_slabs(ix, nb, nb);
-    const RepairHead hd = repair_heads(ix, a, b0, nb);
-    const uint32_t ts = l_seg(a, b0, nb);
-    for (uint32_t k = 0; k < nb; ++k) {
-      wave_sync();
-      repair_chain_u8<G>(ix, a, p, (uint32_t)__builtin_amdgcn_readlane((int)ts, (int)k), hd, (int)k, cur);
+  uint32_t pubs = 0;
+  for (uint32_t qq = 0; qq < N_RQ; ++qq) {
+    const uint32_t q = (blockIdx.x + qq) % N_RQ;
+    unsigned long long* queue = &ix.ctr[rq_word(q)];
+    const uint32_t lo = (uint32_t)((uint64_t)nbat * q / N_RQ), hi = (uint32_t)((uint64_t)nbat * (q + 1) / N_RQ);
+    // an empty queue is passed over with a plain read
+    if (lo + (uint32_t)__hip_atomic_load(queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi) continue;
+    for (;;) {
+      const uint32_t bi = lo + (uint32_t)wave_atomic_add(queue, 1ull);
+      if (bi >= hi) break;
+      const uint32_t b0 = bi * BATCH;
+      const uint32_t nb = min(BATCH, nseg - b0);
+      SlabCursor cur;
+      if (fbase != ~0ull) {
+        cur.free_hi = fbase - b0;
+        cur.free_left = nb;
+      }
+      if (rbase != ~0ull) {
+        cur.ret_next = rbase + b0;
+        cur.ret_left = nb;
+      }
+      const RepairHead hd = repair_heads(ix, a, b0, nb);
+      const uint32_t ts = l_seg(a, b0, nb);
+      for (uint32_t k = 0; k < nb; ++k) {
+        wave_sync();
+        repair_chain_u8<G>(ix, a, p, (uint32_t)__builtin_amdgcn_readlane((int)ts, (int)k), hd, (int)k, cur);
+      }
+      return_slabs(ix, cur);
+      pubs += cur.pubs;
     }
-    finish_slabs(ix, cur, C_PUB_REPAIR);
   }
-  // the last wave out resets the queue for the next launch
-  const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
-  if (lane_id() == 0 && done + 1 == total_waves()) {
-    atomicExch(queue, 0ull);
-    atomicExch(&ix.ctr[C_QDONE], 0ull);
+  SlabCursor tally;
+  tally.pubs = pubs;
+  finish_slabs_block(ix, tally, C_PUB_REPAIR);  // ends with a workgroup barrier
+  // the last workgroup out resets the queues for the next launch
+  if (threadIdx.x == 0) {
+    const unsigned long long done = atomicAdd(&ix.ctr[C_QDONE], 1ull);
+    if (done + 1 == gridDim.x) {
+      for (uint32_t q = 0; q < N_RQ; ++q) atomicExch(&ix.ctr[rq_word(q)], 0ull);
+      atomicExch(&ix.ctr[C_QDONE], 0ull);
+    }
   }
 }
 
@@ -3651,7 +3702,7 @@ __global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty
   const uint32_t cnt = dyn_count(ix, dn, (uint32_t)n);
   uint32_t* ids = reinterpret_cast<uint32_t*>(smem + (size_t)(threadIdx.x >> 6) * lds_per_wave);
   uint32_t* d = ids + 64;
-  SlabCursor cur = reserve_slabs(ix, wave_items(cnt), wave_items(cnt));
+  SlabCursor cur = reserve_slabs_block(ix, wave_items(cnt), wave_items(cnt));
   const int l = lane_id();
   const uint32_t w = wave_index(), W = total_waves();
   for (uint32_t base = w; base < cnt; base += 64u * W) {
@@ -3679,7 +3730,7 @@ __global__ void __launch_bounds__(256) k_compact(Index ix, const uint32_t* dirty
       dd = ndd;
     }
   }
-  finish_slabs(ix, cur, C_PUB_COMPACT);
+  finish_slabs_block(ix, cur, C_PUB_COMPACT);
 }
 
 // phase 2: <1,d,s> -> <1,0,none> and the slab is retired. A workgroup takes
@@ -4402,6 +4453,7 @@ static void launch_maint_p(MaintKernel which, const Index& ix, const MaintArgs& 
     case MK_REPAIR:
       if constexpr (P::CHAIN) {
         if (a.chain) {
+          hipLaunchKernelGGL(k_reserve_launch, dim3(1), dim3(64), 0, s, ix, a.d);
           hipLaunchKernelGGL(k_repair_pool<P::GL>, resident_grid(k_repair_pool<P::GL>, grid, blk, lds, sh), blk, lds, s,
                              ix, a);
           break;
