@@ -2687,13 +2687,15 @@ __global__ void __launch_bounds__(256) k_refine_publish(Index ix, MaintArgs a) {
   uint32_t* d = ids + 64;
   const int l = lane_id();
   const uint32_t w = wave_index(), W = total_waves();
-  // the wave's items in runs of 64: the changed lists of a run are counted
-  // first, so its slabs are reserved with one atomic per stack
+  // the wave's changed lists (items w, w + W, ...) are counted first, so the
+  // workgroup reserves their slabs with one atomic per stack
+  uint32_t np = 0;
   for (uint32_t r0 = w; r0 < a.n; r0 += 64u * W) {
     const uint32_t my = r0 + (uint32_t)l * W;
-    const bool changed = my < a.n && a.vis_cnt[my] != NONE;
-    const uint32_t np = (uint32_t)__popcll(ballot(changed));
-    SlabCursor cur = reserve_slabs(ix, np, np);
+    np += (uint32_t)__popcll(ballot(my < a.n && a.vis_cnt[my] != NONE));
+  }
+  SlabCursor cur = reserve_slabs_block(ix, np, np);
+  for (uint32_t r0 = w; r0 < a.n; r0 += 64u * W) {
     for (uint32_t qi = r0; qi < a.n && qi < r0 + 64u * W; qi += W) {
       const uint32_t cnt = a.vis_cnt[qi];
       if (cnt == NONE) continue;
@@ -2706,8 +2708,8 @@ __global__ void __launch_bounds__(256) k_refine_publish(Index ix, MaintArgs a) {
       wave_sync();
       publish(ix, a.first + qi, ids, d, cnt, C_PUB_REFINE, &cur);
     }
-    finish_slabs(ix, cur, C_PUB_REFINE);
   }
+  finish_slabs_block(ix, cur, C_PUB_REFINE);
 }
 
 // ---- install given neighbor lists (import / test hook) -----------------------------------
