@@ -3480,14 +3480,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 }
 
 // ---- stable LSD radix sort with a launch-time count --------------------------------------
-// 8-bit digits over a bit range. Per pass: digit counts per tile of 4,096
+// 8-bit digits over a bit range. Per pass: digit counts per tile of 1,024
 // keys, an exclusive scan of each digit's counts over the tiles (one block
-// per digit), then a stable scatter: a tile is read in 16 rounds of 256 keys
+// per digit), then a stable scatter: a tile is read in 4 rounds of 256 keys
 // in input order; a key's rank among equal digits is its rank within its wave
 // (ballots on the digit bits) plus the counts of the earlier waves and rounds.
 // Pair keys are produced in ascending source order, so sorting on the target
 // half alone gives (target, source) order.
-constexpr uint32_t RS_TILE = 4096;
+constexpr uint32_t RS_TILE = 1024;
 
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
   const int l = lane_id();
@@ -3621,6 +3621,7 @@ __global__ void __launch_bounds__(256) k_dirty(Index ix, uint64_t n_ids, Dyn d, 
   // list with one atomic per workgroup and step.
   const int l = lane_id();
   const uint32_t c = (uint32_t)(l & 7), wv = threadIdx.x >> 6;
+  const bool short_lists = R <= 32u && (R & 3u) == 0;
   for (uint32_t chunk = blockIdx.x; chunk * DIRTY_CHUNK < n; chunk += gridDim.x) {
     if (threadIdx.x == 0) {
       cnt_s = 0;
@@ -3630,6 +3631,37 @@ __global__ void __launch_bounds__(256) k_dirty(Index ix, uint64_t n_ids, Dyn d, 
     for (uint32_t run = 0; run < DIRTY_CHUNK / 256u; ++run) {
       const uint32_t base = chunk * DIRTY_CHUNK + (run * 4u + wv) * 64u;
       uint32_t dead = 0;
+      if (short_lists) {
+        // R <= 32: one 16-byte read per lane and node covers the list. The
+        // run's reference words are read in one coalesced load (lane l: node
+        // base + l) and the eight groups' slab reads are all issued before
+        // the first bitmap test, so the three dependent reads of a node
+        // overlap with those of the others.
+        const uint32_t vme = base + (uint32_t)l;
+        const uint64_t rme = vme < n ? load_ref(ix, vme) : ~0ull;
+        uint4 w[8];
+        uint32_t dg[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+          const uint64_t r = __shfl((unsigned long long)rme, (int)(8u * k + (uint32_t)(l >> 3)), 64);
+          const uint32_t deg = ref_deg(r), s = ref_slab(r);
+          const bool live = !ref_del(r) && s != NONE && 4u * c < deg;
+          dg[k] = live ? deg : 0u;
+          w[k] = live ? *reinterpret_cast<const uint4*>(ix.slabs + (size_t)s * 2u * R + 4u * c) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+          const uint32_t j = 4u * c;
+          uint32_t cn = 0;
+          if (j < dg[k]) cn += bit_set(bitmap, w[k].x);
+          if (j + 1 < dg[k]) cn += bit_set(bitmap, w[k].y);
+          if (j + 2 < dg[k]) cn += bit_set(bitmap, w[k].z);
+          if (j + 3 < dg[k]) cn += bit_set(bitmap, w[k].w);
+          cn = group_sum<8>(cn);
+          const uint32_t got = (uint32_t)__shfl((int)cn, (int)((l & 7) * 8), 64);
+          if ((uint32_t)(l >> 3) == k) dead = got;
+        }
+      } else
 #pragma unroll
       for (uint32_t k = 0; k < 8; ++k) {
         const uint32_t v = base + 8u * k + (uint32_t)(l >> 3);
