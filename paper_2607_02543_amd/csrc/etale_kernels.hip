@@ -1327,10 +1327,10 @@ __device__ inline void search_one(const Index& ix, const SearchArgs& a, char* ba
 // holds the slabs of the step's entries 2h and 2h + 1, in rank order). A
 // crowded lane drops its id when an earlier half, a lane of its own half that
 // stored it or a lower crowded lane of its own half offers it too, or when it
-// is listed (lanes below n hold the list's keys lk).
-template <int H>
+// is listed (list entry 64s + l, for entries below n, is lane l's lk[s]).
+template <int H, int NL>
 __device__ inline void drop_crowded_twins_h(const uint32_t (&nid)[H], const uint32_t (&vr)[H], bool (&fresh)[H],
-                                            uint64_t lk, int n) {
+                                            const uint64_t (&lk)[NL], int n) {
   const int l = lane_id();
   uint64_t crowded[H], fr[H];
   uint64_t any = 0;
@@ -1350,7 +1350,8 @@ __device__ inline void drop_crowded_twins_h(const uint32_t (&nid)[H], const uint
       bool drop = (others & ((1ull << c) - 1ull)) != 0 || (others & ~crowded[h]) != 0;
 #pragma unroll
       for (int e = 0; e < h; ++e) drop = drop || (ballot(nid[e] == id) & fr[e]) != 0;
-      drop = drop || ballot(l < n && key_id(lk) == id) != 0;
+#pragma unroll
+      for (int s = 0; s < NL; ++s) drop = drop || ballot(64 * s + l < n && key_id(lk[s]) == id) != 0;
       if (drop && l == c) fresh[h] = false;
     }
   }
@@ -1363,24 +1364,70 @@ __device__ inline void drop_crowded_twins_h(const uint32_t (&nid)[H], const uint
 // word); the output stage reads the words of the entries that still have none.
 constexpr uint64_t REF_LAZY = ~0ull;
 
-// The same search for L <= 64 with the list in registers: lane i holds entry
-// i (key, reference word or REF_LAZY, expanded flag), entries at or past n
-// hold KEY_NONE. The next entries to expand are the lowest lanes of one
-// ballot. A step expands up to W entries (H = 2 halves of 64 slab entries when
-// W = 4), scores all their fresh neighbors in one batch and merges them by
-// rank: every list entry and accepted candidate counts the keys of the other
-// side below it (one broadcast per accepted candidate), the first L of the
-// union are scattered to LDS at their ranks and read back in order. Per-wave
-// LDS: one batch of candidates (64H) and the visited table.
-template <class TP, int H>
+// List slots in registers: entry 64s + l of the list is lane l's slot s.
+// The open (unexpanded) entries are one ballot per slot; entries are taken
+// lowest first.
+template <int NL>
+__device__ inline bool open_any(const uint64_t (&o)[NL]) {
+  bool any = false;
+#pragma unroll
+  for (int s = 0; s < NL; ++s) any = any || o[s] != 0;
+  return any;
+}
+
+// the lowest entry of a non-empty open set (its list index), taken out of it
+template <int NL>
+__device__ inline int open_take(uint64_t (&o)[NL]) {
+  if constexpr (NL == 1) {
+    const int j = (int)__builtin_ctzll(o[0]);
+    o[0] &= o[0] - 1;
+    return j;
+  } else {
+    int e = -1;
+#pragma unroll
+    for (int s = 0; s < NL; ++s)
+      if (e < 0 && o[s]) {
+        e = 64 * s + (int)__builtin_ctzll(o[s]);
+        o[s] &= o[s] - 1;
+      }
+    return e;
+  }
+}
+
+// the value of list entry e (wave-uniform) held in slots v
+template <int NL>
+__device__ inline uint64_t list_at(const uint64_t (&v)[NL], int e) {
+  if constexpr (NL == 1) {
+    return bcast_lane64(v[0], e);
+  } else {
+    uint64_t r = 0;
+#pragma unroll
+    for (int s = 0; s < NL; ++s)
+      if ((e >> 6) == s) r = bcast_lane64(v[s], e & 63);
+    return r;
+  }
+}
+
+// The same search with the list in registers, for L <= 64 NL: lane l holds
+// entries l, 64 + l, ... (key, reference word or REF_LAZY, expanded flag),
+// entries at or past n hold KEY_NONE. The next entries to expand are the
+// lowest of one ballot per slot. A step expands up to W entries (H = 2 halves
+// of 64 slab entries when W = 4), scores all their fresh neighbors in one
+// batch and merges them by rank: every list entry and accepted candidate
+// counts the keys of the other side below it (one broadcast per accepted
+// candidate), the first L of the union are scattered to LDS at their ranks and
+// read back in order. Per-wave LDS: a scratch of 64 max(H, NL) entries (one
+// batch of candidates, the merged list) and the visited table.
+template <class TP, int H, int NL>
 __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char* base, uint32_t qi,
                                      SearchTally& tally) {
   constexpr int WMAX = 2 * H;
+  constexpr int CAP = 64 * (H > NL ? H : NL);
   const int l = lane_id();
   uint64_t* ck = reinterpret_cast<uint64_t*>(base);
-  uint64_t* cr = ck + 64 * H;
-  uint32_t* ci = reinterpret_cast<uint32_t*>(cr + 64 * H);
-  uint32_t* vt = ci + 64 * H;
+  uint64_t* cr = ck + CAP;
+  uint32_t* ci = reinterpret_cast<uint32_t*>(cr + CAP);
+  uint32_t* vt = ci + CAP;
   const int L = (int)a.L;
   const void* qrow = a.mode == MODE_QUERY ? (const void*)((const uint8_t*)a.q + (size_t)qi * TP::query_bytes(ix))
                                           : TP::stored_row(ix, a.first + qi);
@@ -1388,14 +1435,22 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
   for (uint32_t i = (uint32_t)l; i <= a.vt_mask; i += 64) vt[i] = NONE;
   // the initial list: the L best start nodes, with their reference words
   int n = (int)a.init_n[qi];
-  uint64_t lk = KEY_NONE, lr = 0;
-  uint32_t lx = 0;
-  if (l < n) {
-    lk = a.init_keys[(size_t)qi * a.init_stride + l];
-    lr = REF_LAZY;
+  uint64_t lk[NL], lr[NL];
+  uint32_t lx[NL];
+#pragma unroll
+  for (int s = 0; s < NL; ++s) {
+    lk[s] = KEY_NONE;
+    lr[s] = 0;
+    lx[s] = 0;
+    if (64 * s + l < n) {
+      lk[s] = a.init_keys[(size_t)qi * a.init_stride + 64 * s + l];
+      lr[s] = REF_LAZY;
+    }
   }
   wave_sync();
-  if (l < n) (void)vt_insert(vt, a.vt_mask, key_id(lk));
+#pragma unroll
+  for (int s = 0; s < NL; ++s)
+    if (64 * s + l < n) (void)vt_insert(vt, a.vt_mask, key_id(lk[s]));
   wave_sync();
   uint32_t ndist = (uint32_t)ix.ctr[C_N_ENTRIES];  // scored by the start-set scan
   uint32_t nexp = 0;
@@ -1410,20 +1465,23 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
   for (int k = 0; k < WMAX; ++k) pre_k[k] = KEY_NONE;
   while (nexp < a.vcap) {
     // up to W best unexpanded entries, within the visit cap
-    uint64_t open = ballot(l < n && lx == 0);
-    if (!open) break;
+    uint64_t open[NL];
+#pragma unroll
+    for (int s = 0; s < NL; ++s) open[s] = ballot(64 * s + l < n && lx[s] == 0);
+    if (!open_any(open)) break;
     uint64_t key[WMAX], ref[WMAX];
     uint32_t np = 0;
 #pragma unroll
     for (int k = 0; k < WMAX; ++k) {
       key[k] = KEY_NONE;
       ref[k] = 0;
-      if (open && (k == 0 || ((uint32_t)k < a.W && nexp + (uint32_t)k < a.vcap))) {
-        const int j = (int)__builtin_ctzll(open);
-        open &= open - 1;  // then the open entries after the picked ones
-        key[k] = bcast_lane64(lk, j);
-        ref[k] = bcast_lane64(lr, j);
-        if (l == j) lx = 1;
+      if (open_any(open) && (k == 0 || ((uint32_t)k < a.W && nexp + (uint32_t)k < a.vcap))) {
+        const int e = open_take(open);  // then the open entries after the picked ones
+        key[k] = list_at(lk, e);
+        ref[k] = list_at(lr, e);
+#pragma unroll
+        for (int s = 0; s < NL; ++s)
+          if (64 * s + l == e) lx[s] = 1;
         if (l == 0 && a.mode == MODE_INSERT) a.vis_keys[(size_t)qi * a.vcap + nexp + (uint32_t)k] = key[k];
         ++np;
       }
@@ -1450,7 +1508,7 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     // read-ahead, first half: the entries the next step should expand and the
     // reference words they still lack; the words are consumed only after the
     // visited-table pass, so their latency overlaps it
-    const bool ahead = nexp < a.vcap && open;
+    const bool ahead = nexp < a.vcap && open_any(open);
     uint64_t pref[WMAX];
     int pj[WMAX];
 #pragma unroll
@@ -1459,17 +1517,18 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
       pj[k] = -1;
     }
     if (ahead) {
-      uint64_t o = open;
+      uint64_t o[NL];
+#pragma unroll
+      for (int s = 0; s < NL; ++s) o[s] = open[s];
 #pragma unroll
       for (int k = 0; k < WMAX; ++k) {
-        if (o && (k == 0 || ((uint32_t)k < a.W && nexp + (uint32_t)k < a.vcap))) {
-          const int j = (int)__builtin_ctzll(o);
-          o &= o - 1;
-          pre_k[k] = bcast_lane64(lk, j);
-          pref[k] = bcast_lane64(lr, j);
+        if (open_any(o) && (k == 0 || ((uint32_t)k < a.W && nexp + (uint32_t)k < a.vcap))) {
+          const int e = open_take(o);
+          pre_k[k] = list_at(lk, e);
+          pref[k] = list_at(lr, e);
           if (pref[k] == REF_LAZY) {
             pref[k] = load_ref(ix, key_id(pre_k[k]));
-            pj[k] = j;
+            pj[k] = e;
           }
         }
       }
@@ -1483,7 +1542,7 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     }
     // a crowded table can pass an id twice (two slabs list it) or one already
     // listed; the insertion below needs distinct, unlisted candidates
-    drop_crowded_twins_h<H>(nid, vr, fresh, lk, n);
+    drop_crowded_twins_h<H, NL>(nid, vr, fresh, lk, n);
     int cnt = 0;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
@@ -1495,7 +1554,9 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     if (ahead) {
 #pragma unroll
       for (int k = 0; k < WMAX; ++k)
-        if (l == pj[k]) lr = pref[k];  // the word travels with its entry through the merge
+#pragma unroll
+        for (int s = 0; s < NL; ++s)
+          if (64 * s + l == pj[k]) lr[s] = pref[k];  // the word travels with its entry through the merge
 #pragma unroll
       for (int h = 0; h < H; ++h)
         pre_nid[h] = expansion_ids(ix, pref[2 * h], pref[2 * h + 1], pre_k[2 * h + 1] != KEY_NONE);
@@ -1510,9 +1571,9 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     // entry's place is its rank in that union: one broadcast per accepted
     // candidate counts, for each list entry and each candidate, the accepted
     // candidates below it, and for each candidate the list entries below it.
-    // The wave then scatters the union's first L entries to the candidate
-    // scratch (free after the distances) and reads them back in order.
-    const uint64_t worst = n == L ? bcast_lane64(lk, L - 1) : KEY_NONE;
+    // The wave then scatters the union's first L entries to the scratch (free
+    // after the distances) and reads them back in order.
+    const uint64_t worst = n == L ? list_at(lk, L - 1) : KEY_NONE;
     uint64_t cand[H], accm[H];
     int na = 0;
 #pragma unroll
@@ -1522,12 +1583,17 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
       na += __popcll(accm[h]);
     }
     if (!na) continue;
-    // Per accepted candidate: one compare against the list lanes gives both
+    // Per accepted candidate: one compare against each list slot gives both
     // each list entry's count of candidates below it and (its ballot, as list
     // keys and candidates are distinct) the candidate's count of list entries
-    // below it; lanes at or past n hold KEY_NONE and are never written back.
-    const uint64_t nmask = ballot(l < n);
-    uint32_t below_l = 0, below_c[H], list_c[H];
+    // below it; entries at or past n hold KEY_NONE and are never written back.
+    uint64_t nmask[NL];
+    uint32_t below_l[NL], below_c[H], list_c[H];
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+      nmask[s] = ballot(64 * s + l < n);
+      below_l[s] = 0;
+    }
 #pragma unroll
     for (int h = 0; h < H; ++h) below_c[h] = list_c[h] = 0;
 #pragma unroll
@@ -1535,18 +1601,26 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
       for (uint64_t m = accm[hh]; m; m &= m - 1) {
         const int c = (int)__builtin_ctzll(m);
         const uint64_t kc = bcast_lane64(cand[hh], c);
-        const bool above = kc < lk;
-        below_l += above ? 1u : 0u;
+        uint32_t nl = 0;
+#pragma unroll
+        for (int s = 0; s < NL; ++s) {
+          const bool above = kc < lk[s];
+          below_l[s] += above ? 1u : 0u;
+          nl += (uint32_t)__popcll(nmask[s] & ~ballot(above));
+        }
 #pragma unroll
         for (int h = 0; h < H; ++h) below_c[h] += kc < cand[h] ? 1u : 0u;
-        const uint32_t nl = (uint32_t)__popcll(nmask & ~ballot(above));
         if (l == c) list_c[hh] = nl;
       }
     wave_sync();
-    if (l < n && (uint32_t)l + below_l < (uint32_t)L) {
-      ck[l + below_l] = lk;
-      cr[l + below_l] = lr;
-      ci[l + below_l] = lx;
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+      const uint32_t e = 64u * (uint32_t)s + (uint32_t)l;
+      if ((int)e < n && e + below_l[s] < (uint32_t)L) {
+        ck[e + below_l[s]] = lk[s];
+        cr[e + below_l[s]] = lr[s];
+        ci[e + below_l[s]] = lx[s];
+      }
     }
 #pragma unroll
     for (int h = 0; h < H; ++h) {
@@ -1559,24 +1633,30 @@ __device__ inline void search_one_rl(const Index& ix, const SearchArgs& a, char*
     }
     wave_sync();
     n = min(n + na, L);
-    lk = KEY_NONE;
-    if (l < n) {
-      lk = ck[l];
-      lr = cr[l];
-      lx = ci[l];
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+      lk[s] = KEY_NONE;
+      if (64 * s + l < n) {
+        lk[s] = ck[64 * s + l];
+        lr[s] = cr[64 * s + l];
+        lx[s] = ci[64 * s + l];
+      }
     }
     wave_sync();
   }
   // the list to LDS for the shared result stage (the candidate scratch is
   // free), every entry with its reference word: the output keeps flag-0 nodes
-  if (l < n && lr == REF_LAZY) lr = load_ref(ix, key_id(lk));
-  ck[l] = lk;
-  cr[l] = lr;
+#pragma unroll
+  for (int s = 0; s < NL; ++s) {
+    if (64 * s + l < n && lr[s] == REF_LAZY) lr[s] = load_ref(ix, key_id(lk[s]));
+    ck[64 * s + l] = lk[s];
+    cr[64 * s + l] = lr[s];
+  }
   wave_sync();
   search_finish<TP>(ix, a, qi, qrow, ck, cr, n, ci, ck, nexp, ndist, tally);
 }
 
-template <class TP, bool RL, int H>
+template <class TP, bool RL, int H, int NL = 1>
 __device__ inline void search_kernel(const Index& ix, SearchArgs& a, char* smem) {
   __shared__ unsigned long long tsum[2];
   if (gated(ix, a.d)) return;
@@ -1590,14 +1670,14 @@ __device__ inline void search_kernel(const Index& ix, SearchArgs& a, char* smem)
   if (!a.persistent) {  // one wave per query
     const uint32_t qi = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (qi < a.nq) {
-      if constexpr (RL) search_one_rl<TP, H>(ix, a, base, qi, tally);
+      if constexpr (RL) search_one_rl<TP, H, NL>(ix, a, base, qi, tally);
       else search_one<TP>(ix, a, base, qi, tally);
     }
   } else {
     unsigned long long* queue = &ix.ctr[C_QUEUE];
     for (uint32_t qi = wave_ticket(queue); qi < a.nq; qi = wave_ticket(queue)) {
       wave_sync();
-      if constexpr (RL) search_one_rl<TP, H>(ix, a, base, qi, tally);
+      if constexpr (RL) search_one_rl<TP, H, NL>(ix, a, base, qi, tally);
       else search_one<TP>(ix, a, base, qi, tally);
     }
     const uint32_t done = wave_ticket(&ix.ctr[C_QDONE]);
@@ -1628,6 +1708,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE)))
   extern __shared__ __align__(16) char smem[];
   a.mode = Q ? MODE_QUERY : MODE_INSERT;
   search_kernel<TP, true, H>(ix, a, smem);
+}
+
+// two list slots per lane (64 < L <= 128, up to two expansions per step);
+// uint8 rows at 6 waves per SIMD
+template <class TP, unsigned WPE, bool Q>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) k_search_rl2(Index ix, SearchArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  a.mode = Q ? MODE_QUERY : MODE_INSERT;
+  search_kernel<TP, true, 1, 2>(ix, a, smem);
 }
 
 template <class TP, bool Q>
@@ -4244,6 +4333,8 @@ uint32_t search_lds_per_wave(uint32_t L, uint32_t vt_slots, uint32_t W) {
   // L <= 64 (list in registers): candidate keys/refs, ids (64 per two
   // expansions of a step), visited table
   if (L <= 64) return (W > 2 ? 2u : 1u) * (2u * 512u + 256u) + 4u * vt_slots;
+  // L <= 128 at W <= 2 (two list slots per lane): the same for 128 entries
+  if (L <= 128 && W <= 2) return 2u * (2u * 512u + 256u) + 4u * vt_slots;
   // keys + refs (double-buffered), candidate keys/refs, merge scratch, ids,
   // insertion points, visited table, expanded flags
   return 32u * L + 4u * 512u + 2u * 256u + 4u * vt_slots + ((2u * L + 15u) & ~15u);
@@ -4332,7 +4423,7 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
   return hipGetLastError();
 }
 
-// the list lives in registers for L <= 64
+// the list lives in registers for L <= 64, and for L <= 128 at W <= 2
 #define LSQ(TP, Q)                                                                                              \
   do {                                                                                                          \
     if (a.L <= 64)                                                                                              \
@@ -4342,6 +4433,9 @@ hipError_t launch_scan(const Index& ix, const ScanArgs& args, hipStream_t s, hip
       else                                                                                                      \
         hipLaunchKernelGGL((k_search_rl<TP, TP::FLOAT ? 1u : 7u, 1, Q>), dim3(grid), dim3(64 * waves_per_block), lds, \
                            s, ix, a);                                                                           \
+    else if (a.L <= 128 && a.W <= 2)                                                                            \
+      hipLaunchKernelGGL((k_search_rl2<TP, TP::FLOAT ? 1u : 6u, Q>), dim3(grid), dim3(64 * waves_per_block), lds, \
+                         s, ix, a);                                                                             \
     else                                                                                                        \
       hipLaunchKernelGGL((k_search<TP, Q>), dim3(grid), dim3(64 * waves_per_block), lds, s, ix, a);             \
   } while (0)
