@@ -336,8 +336,10 @@ etale_status run_searches(etale_index* ix, int mode, const uint8_t* q, uint64_t 
     if (timed) {
       for (auto& e : ev) {
         if (ix->ev_pool.empty()) {
+          // timing only: without the system-scope fence, whose cache
+          // write-back stalls the stream for microseconds at every stage
           hipEvent_t ne;
-          HIP_TRY(hipEventCreate(&ne));
+          HIP_TRY(hipEventCreateWithFlags(&ne, hipEventDisableSystemFence));
           ix->ev_pool.push_back(ne);
         }
         e = ix->ev_pool.back();

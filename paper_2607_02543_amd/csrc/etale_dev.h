@@ -240,15 +240,22 @@ __device__ inline uint64_t lane_xor(uint64_t v) {
 }
 
 // Bitonic sort of 64 NK keys in registers, ascending: key s * 64 + l in v[s]
-// of lane l. Partners within 64 lanes move by lane_xor, distance 64 is the
-// lane's own pair.
+// of lane l. Partners within 64 lanes move by lane_xor; at distances of 64
+// and more both keys are the lane's own (slots s and s + J / 64).
 template <int J, int K, int NK>
 __device__ inline void bitonic_step_regs(uint64_t (&v)[NK]) {
   const int l = lane_id();
-  if constexpr (J == 64) {
-    const uint64_t lo = min(v[0], v[1]), hi = max(v[0], v[1]);
-    v[0] = lo;
-    v[1] = hi;
+  if constexpr (J >= 64) {
+    constexpr int D = J / 64;
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      if ((s & D) == 0) {
+        const bool up = ((s * 64 + l) & K) == 0;  // direction of this pair's run
+        const uint64_t lo = min(v[s], v[s + D]), hi = max(v[s], v[s + D]);
+        v[s] = up ? lo : hi;
+        v[s + D] = up ? hi : lo;
+      }
+    }
   } else {
     const bool lower = (l & J) == 0;
 #pragma unroll

@@ -1025,6 +1025,20 @@ __global__ void __launch_bounds__(256) k_scan_final(Index ix, ScanArgs a, uint32
 #pragma unroll
     for (int s = 0; s < 2; ++s)
       if ((uint32_t)(s * 64 + l) < cnt) out[s * 64 + l] = make_key(key_dist(v[s]), start_id(ix, a, key_id(v[s])));
+  } else if (np <= 512) {
+    // up to 512 keys: sorted in registers, four or eight per lane
+    uint64_t v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = s * 64 < np ? sel[s * 64 + l] : KEY_NONE;
+    if (np <= 256) {
+      uint64_t (&v4)[4] = *reinterpret_cast<uint64_t(*)[4]>(&v[0]);
+      wave_sort_regs<4>(v4);
+    } else {
+      wave_sort_regs<8>(v);
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      if ((uint32_t)(s * 64 + l) < cnt) out[s * 64 + l] = make_key(key_dist(v[s]), start_id(ix, a, key_id(v[s])));
   } else {
     wave_bitonic_sort(sel, np);
     for (uint32_t i = (uint32_t)l; i < cnt; i += 64) {
