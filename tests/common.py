@@ -11,25 +11,26 @@ def small_workload(n_base=2000, clusters=8, seed=1, batch=500, rounds=2, churn=0
                        rounds, churn, 200, 10, (64,), seed, batch, batch)
 
 
-def index_params(wl, n_entry=64, refine=True, tombstone_only=False, max_batch=None, slack=2, W=1):
+def index_params(wl, n_entry=64, refine=True, tombstone_only=False, max_batch=None, slack=2, W=1, visit_mult=4):
     cap = wl.id_capacity()
     mb = max_batch or max(wl.build_batch_max, wl.churn_count(), 1)
     return dict(dim=wl.dim, R=wl.R, L_build=wl.L_build, alpha=(wl.alpha_num, wl.alpha_den), n_entry=n_entry,
                 refine=refine, tombstone_only=tombstone_only, id_capacity=cap,
-                slab_capacity=slack * cap + mb * (wl.R + 2), max_batch=mb, W=W)
+                slab_capacity=slack * cap + mb * (wl.R + 2), max_batch=mb, W=W, visit_mult=visit_mult)
 
 
 def make_oracle(p):
     return oracle.Oracle(oracle.METRIC_L2_U8, p["dim"], p["R"], p["L_build"], p["id_capacity"], p["slab_capacity"],
                          alpha=p["alpha"], n_entry=p["n_entry"], refine=p["refine"],
-                         tombstone_only=p["tombstone_only"], W=p["W"])
+                         tombstone_only=p["tombstone_only"], W=p["W"], visit_mult=p.get("visit_mult", 4))
 
 
 def make_gpu(p, **kw):
     from paper_2607_02543_amd import etale
     return etale.Index(p["dim"], R=p["R"], L_build=p["L_build"], alpha=p["alpha"], n_entry=p["n_entry"],
                        refine=p["refine"], tombstone_only=p["tombstone_only"], id_capacity=p["id_capacity"],
-                       slab_capacity=p["slab_capacity"], max_batch=p["max_batch"], W=p["W"], **kw)
+                       slab_capacity=p["slab_capacity"], max_batch=p["max_batch"], W=p["W"],
+                       visit_mult=p.get("visit_mult", 4), **kw)
 
 
 def assert_same_state(o, g, where=""):

@@ -21,9 +21,9 @@ def _torch():
 
 
 def run_parity(wl, n_entry=64, refine=True, tombstone_only=False, search_L=(64,), k=10, n_queries=200,
-               reclaim=True, W=1, **gpu_kw):
+               reclaim=True, W=1, visit_mult=4, **gpu_kw):
     torch = _torch()
-    p = index_params(wl, n_entry=n_entry, refine=refine, tombstone_only=tombstone_only, W=W)
+    p = index_params(wl, n_entry=n_entry, refine=refine, tombstone_only=tombstone_only, W=W, visit_mult=visit_mult)
     o = make_oracle(p)
     g = make_gpu(p, **gpu_kw)
     st = dg.Stream(wl)
@@ -145,6 +145,19 @@ def test_autotune_choice_leaves_results_unchanged():
         io, do = o.search(q, 10, L)
         assert np.array_equal(io, i1.cpu().numpy().astype(np.uint32)) and np.array_equal(do, d1.cpu().numpy())
     g.close()
+
+
+def test_parity_two_slot_register_list():
+    # lists of 65..128 entries held as two slots per lane: one entry in the
+    # second slot (L = 65), a full second slot (L = 128), an initial list
+    # shorter than one slot (37 entries), and a crowded visited table at W = 2
+    run_parity(small_workload(seed=15, rounds=1), n_entry=37, search_L=(65, 127))
+    run_parity(small_workload(seed=16, rounds=1), n_entry=200, W=2, search_L=(65, 128), vt_slots=64)
+    # insert searches on the two-slot list (L_build = 96; a visit cap of 2 L_build
+    # keeps the maintenance kernels' LDS within a workgroup's)
+    wl = dg.Workload("lbuild96", dg.Mixture(128, 8, 18.0, dg.METRIC_L2_U8), 1200, 32, 96, 6, 5,
+                     1, 0.05, 200, 10, (96,), 17, 400, 400)
+    run_parity(wl, search_L=(96,), visit_mult=2)
 
 
 def test_parity_two_expansions_per_iteration():
