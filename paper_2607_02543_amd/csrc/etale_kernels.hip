@@ -1849,34 +1849,36 @@ struct AlphaT {
 // the one-at-a-time selection. The four decisions are made without branches
 // (scalar selects), and reading eight rows at a time, decided or not,
 // measured slower: most candidates are covered early and their rows need not
-// be read.
+// be read. When a candidate is decided every candidate ranked before it has
+// left `rest` (kept, or covered), so a kept one's cover mask needs no
+// masking to the later ranks, and after the four nothing up to the last of
+// them remains.
 template <bool C32, class Dist, class Keep>
 __device__ inline uint32_t select_in_order(uint64_t rest, uint32_t R, uint32_t a2, typename AlphaT<C32>::T thr,
                                            Dist dist, Keep keep) {
   uint32_t cnt = 0;
   while (cnt < R && rest) {
     int j[4];
+    uint64_t bit[4];
     uint32_t d[4];
     uint64_t m = rest;
+    j[0] = (int)__builtin_ctzll(m);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      j[k] = m ? (int)__builtin_ctzll(m) : 64;
+      bit[k] = m & (0ull - m);  // 0 past the last candidate
+      if (k > 0) j[k] = m ? (int)__builtin_ctzll(m) : j[0];
       m &= m - 1ull;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) d[k] = dist(j[k] < 64 ? j[k] : j[0]);
+    for (int k = 0; k < 4; ++k) d[k] = dist(j[k]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const uint64_t bit = j[k] < 64 ? 1ull << j[k] : 0ull;
-      const bool take = (rest & bit) != 0 && cnt < R;  // live, not covered by an earlier one of the four
-      keep(j[k] < 64 ? j[k] : 0, cnt, take);
-      const uint64_t above = j[k] >= 63 ? 0ull : (~0ull << (j[k] + 1));
-      const uint64_t kill = ballot(AlphaT<C32>::scale(a2, d[k]) <= thr) & above;
-      rest &= take ? ~(kill | bit) : ~0ull;
+      const bool take = (rest & bit[k]) != 0 && cnt < R;  // live, not covered by an earlier one of the four
+      keep(j[k], cnt, take);
+      const uint64_t kill = ballot(AlphaT<C32>::scale(a2, d[k]) <= thr);
+      rest &= take ? ~(kill | bit[k]) : ~0ull;
       cnt += take ? 1u : 0u;
     }
-    // every candidate up to the last of the four is decided
-    rest &= j[3] >= 63 ? 0ull : (~0ull << (j[3] + 1));
   }
   return cnt;
 }
