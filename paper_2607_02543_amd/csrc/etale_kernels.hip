@@ -1861,24 +1861,36 @@ __device__ inline uint32_t select_in_order(uint64_t rest, uint32_t R, uint32_t a
     int j[4];
     uint64_t bit[4];
     uint32_t d[4];
+    // past the last candidate: bit 0 and index 63 (its distance is read and
+    // never used: every caller's table has a row for every lane)
     uint64_t m = rest;
-    j[0] = (int)__builtin_ctzll(m);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      bit[k] = m & (0ull - m);  // 0 past the last candidate
-      if (k > 0) j[k] = m ? (int)__builtin_ctzll(m) : j[0];
-      m &= m - 1ull;
+      j[k] = (int)__builtin_ctzll(m | (1ull << 63));
+      const uint64_t next = m & (m - 1ull);
+      bit[k] = m ^ next;
+      m = next;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) d[k] = dist(j[k]);
+    // the four in order; with room for all four kept, liveness alone decides
+    // (no count test per candidate)
+    auto decide = [&](auto check_count) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const bool take = (rest & bit[k]) != 0 && cnt < R;  // live, not covered by an earlier one of the four
-      keep(j[k], cnt, take);
-      const uint64_t kill = ballot(AlphaT<C32>::scale(a2, d[k]) <= thr);
-      rest &= take ? ~(kill | bit[k]) : ~0ull;
-      cnt += take ? 1u : 0u;
-    }
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t tk = rest & bit[k];  // live, not covered by an earlier one of the four
+        uint32_t t = (uint32_t)((tk | (0ull - tk)) >> 63);  // tk != 0, in scalar arithmetic
+        if constexpr (decltype(check_count)::value) t = cnt < R ? t : 0u;
+        keep(j[k], cnt, t != 0);
+        const uint64_t kill = ballot(AlphaT<C32>::scale(a2, d[k]) <= thr);
+        rest &= t ? ~(kill | tk) : ~0ull;
+        cnt += t;
+      }
+    };
+    if (cnt + 4u <= R)
+      decide(std::false_type{});
+    else
+      decide(std::true_type{});
   }
   return cnt;
 }
@@ -2576,10 +2588,12 @@ __device__ inline void reverse_chain_u8(const Index& ix, const MaintArgs& a, con
     // read together, then decided in order; one killed by an earlier one of
     // the four is skipped)
     uint32_t ns = 0;
-    const uint32_t tb = cs * (cs - 1u) / 2u;  // this lane's row of the triangular table
+    // the triangular table's entry for slots (sj, cs), the larger one's row:
+    // computed per lane without a branch (the selection is bound by scalar issue)
     auto dist = [&](int j) {
       const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)cs, j);
-      return c.M[sj < cs ? tb + sj : sj * (sj - 1u) / 2u + cs];
+      const uint32_t hi = max(sj, cs), lo = min(sj, cs);
+      return c.M[__umul24(hi, hi - 1u) / 2u + lo];
     };
     auto keep = [&](int j, uint32_t rank, bool take) {
       const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)cs, j);
@@ -3324,10 +3338,12 @@ __device__ inline uint32_t pool_prune(const Index& ix, const PoolLds& p, const u
   uint32_t keep_slot = 0;
   // the selection in order of rank over the cached distances (the slot of
   // the k-th kept candidate lands in lane k)
-  const uint32_t tb = csl * (csl - 1u) / 2u;  // this lane's row of the triangular table
+  // the triangular table's entry for slots (sj, csl), the larger one's row:
+  // computed per lane without a branch (the selection is bound by scalar issue)
   auto dist = [&](int j) {
     const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)csl, j);
-    return p.M[sj < csl ? tb + sj : sj * (sj - 1u) / 2u + csl];
+    const uint32_t hi = max(sj, csl), lo = min(sj, csl);
+    return p.M[__umul24(hi, hi - 1u) / 2u + lo];
   };
   auto take = [&](int j, uint32_t rank, bool kept) {
     const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)csl, j);
